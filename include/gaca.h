@@ -1,0 +1,188 @@
+/*
+ * gaca.h -- C ABI of the MI355X (gfx950) library for the generalised (3-D) adaptive cross
+ * approximation of Laplace-domain boundary element tensors.
+ *
+ * Operation (Haider, Rjasanow, Schanz, "Generalised adaptive cross approximation for
+ * convolution quadrature based boundary element formulation"):
+ *   - Sec. 3 (spatial discretisation, eq. bie_semi_diri / bie_semi_indirect): the single
+ *     layer V and double layer K matrices of flat triangles with piecewise-constant
+ *     functions, collocation at element centroids or Galerkin;
+ *   - Sec. 3 (temporal discretisation): their Laplace-domain kernels
+ *     exp(-s r)/(4 pi r) and its normal derivative at the L complex frequencies s_l,
+ *     i.e. the M x M x L array that the gCQ needs;
+ *   - Sec. 4, Algorithm 1 and eq. (norm): 3D-ACA of every admissible block of a
+ *     geometric cluster-tree partition (faces by ACA, pivot by dense expansion);
+ *   - Sec. 4, eq. (product): the reordered product sum_l C(s_l) X_l.
+ *
+ * Conventions
+ *   - every call returns a gaca_status; on failure gaca_last_error() (thread-local) holds
+ *     a message; no C++ exception crosses the ABI;
+ *   - complex numbers are interleaved (re, im) doubles (C128) or floats (C64);
+ *   - element numbering is the caller's original order unless a function says "tree order"
+ *     (the library renumbers elements so that every cluster is a contiguous range; the
+ *     permutation is returned by gaca_problem_perm);
+ *   - handles are owned by the library and freed by the matching *_destroy; all inputs are
+ *     copied; a handle is used by one host thread at a time.
+ */
+#ifndef GACA_H
+#define GACA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GACA_ABI_VERSION 1
+
+typedef enum {
+    GACA_OK = 0,
+    GACA_ERR_INVALID_ARG = -1,   /* bad argument (null pointer, size, degenerate mesh ...) */
+    GACA_ERR_OOM = -2,           /* device allocation failed or exceeded max_device_bytes */
+    GACA_ERR_HIP = -3,           /* a HIP runtime call failed */
+    GACA_ERR_STATE = -4,         /* handle in the wrong state (e.g. no GPU, not built) */
+    GACA_ERR_NOT_CONVERGED = -5, /* a rank cap was hit in at least one block (result kept) */
+    GACA_ERR_UNSUPPORTED = -6    /* combination not implemented */
+} gaca_status;
+
+typedef enum { GACA_COLLOCATION_P0 = 0, GACA_GALERKIN_P0 = 1 } gaca_scheme;
+typedef enum { GACA_SLP = 0, GACA_DLP = 1 } gaca_kernel;
+/* FP64: every step in FP64.  MIXED: far-field faces evaluated and stored in FP32 complex
+ * with a per-(block, frequency) scale, FP64 fibres, norms and pivot bookkeeping; near
+ * field computed in FP64 and stored in FP32. */
+typedef enum { GACA_FP64 = 0, GACA_MIXED = 1 } gaca_precision;
+/* SUM: Y[i][b] = sum_l sum_j C(i,j,l) X[l][j][b]  (eq. product);
+ * PER_FREQ: Y[l][i][b] = sum_j C(i,j,l) X[l][j][b]. */
+typedef enum { GACA_APPLY_SUM = 0, GACA_APPLY_PER_FREQ = 1 } gaca_apply_mode;
+typedef enum { GACA_C128 = 0, GACA_C64 = 1 } gaca_dtype;
+
+typedef struct {
+    int32_t leaf_size;        /* cluster-tree leaf size (default 32) */
+    double eta;               /* admissibility: min(diam) <= eta * dist (default 1) */
+    double eps3d;             /* 3-D ACA tolerance eps of Algorithm 1 (default 1e-6) */
+    double eps_aca;           /* face ACA tolerance (default eps3d / 100) */
+    gaca_precision precision; /* default GACA_FP64 */
+    int32_t n_duffy;          /* Duffy order of the collocation self term (default 16) */
+    int32_t n_galerkin;       /* Galerkin touching-pair order per direction (default 5) */
+    double tie;               /* relative tie window of every argmax (default 1e-9, FP64) */
+    double delta_zero;        /* zero-face threshold factor (default 1e-13) */
+    int32_t max_rank3d;       /* cap on crosses per block (default min(L, 64)) */
+    int32_t max_face_rank;    /* cap on a face's ACA rank (default min(m, n)) */
+    uint64_t max_device_bytes;/* 0 = no limit; otherwise total library device memory cap */
+    uint64_t batch_bytes;     /* far-field scratch per launch (default 24 GiB) */
+    int32_t threads_small;    /* workgroup size for blocks with m*n <= 4096 (64/128/256) */
+    int32_t threads_large;    /* workgroup size for larger blocks (default 256) */
+} gaca_options;
+
+typedef struct gaca_context gaca_context;
+typedef struct gaca_problem gaca_problem;
+typedef struct gaca_hmatrix gaca_hmatrix;
+
+typedef struct {
+    int64_t n_far, n_near;
+    int32_t rank_min, rank_max;   /* 3-D ranks over far blocks (number of crosses) */
+    double rank_mean;
+    int32_t face_rank_max;
+    double face_rank_mean;
+    int64_t n_capped;             /* blocks that hit max_rank3d or max_face_rank */
+    int64_t n_zero_blocks;        /* far blocks of rank 0 */
+    uint64_t bytes_far;           /* stored far-field factors (U, W, fibres) */
+    uint64_t bytes_near;          /* stored near field */
+    double dense_bytes;           /* M * M * L * (16 FP64 / 8 MIXED) */
+    double compression;           /* (bytes_far + bytes_near) / dense_bytes */
+    double entries_near;          /* near-field tensor entries computed (m n L per block) */
+    double entries_face;          /* entries read by the face ACAs (algorithmic count) */
+    double entries_fibre;         /* frequency-fibre entries (r L per block) */
+    double entries_face_kernel;   /* entries the face kernels evaluated (dense faces) */
+    double ms_near, ms_far, ms_total;  /* device time of the build phases */
+} gaca_stats;
+
+int gaca_abi_version(void);
+const char *gaca_last_error(void);
+void gaca_options_default(gaca_options *opt);
+
+/* Context on HIP device `device`, launching on `hip_stream` (a hipStream_t, may be NULL
+ * for the default stream; not owned).  GACA_ERR_STATE if no usable GPU. */
+gaca_status gaca_context_create(int device, void *hip_stream, gaca_context **out);
+gaca_status gaca_context_destroy(gaca_context *ctx);
+
+/* Problem: mesh + frequencies + scheme (Sec. 3).  xyz: nv x 3 doubles; tri: M x 3 int32
+ * vertex ids, counter-clockwise seen from outside; s_re, s_im: L frequencies.
+ * Validates (finite coordinates, ids in range, non-degenerate triangles, L >= 1),
+ * builds the cluster tree and block partition on the host and uploads the geometry.
+ * If s_{L-1-l} == conj(s_l) exactly for all l, kernels evaluate only half the
+ * frequencies and mirror the rest. */
+gaca_status gaca_problem_create(gaca_context *ctx, const double *xyz, int64_t nv,
+                                const int32_t *tri, int64_t M, const double *s_re,
+                                const double *s_im, int32_t L, gaca_scheme scheme,
+                                const gaca_options *opt, gaca_problem **out);
+gaca_status gaca_problem_destroy(gaca_problem *p);
+/* Tree permutation: perm[p] = original element id at tree position p (M entries). */
+gaca_status gaca_problem_perm(const gaca_problem *p, int64_t *perm);
+/* Block counts and lists (tree order): each block is (row_start, m, col_start, n). */
+gaca_status gaca_problem_block_counts(const gaca_problem *p, int64_t *n_far, int64_t *n_near);
+gaca_status gaca_problem_blocks(const gaca_problem *p, int64_t *far4, int64_t *near4);
+
+/* Host-only tree + partition (no device), for tests of the host logic.
+ * perm: M entries; far4 / near4: 4 * capacity entries; counts written to n_far, n_near;
+ * GACA_ERR_INVALID_ARG if the capacity is too small (counts still written). */
+gaca_status gaca_partition_host(const double *xyz, int64_t nv, const int32_t *tri, int64_t M,
+                                int32_t leaf_size, double eta, int64_t *perm,
+                                int64_t capacity, int64_t *far4, int64_t *n_far,
+                                int64_t *near4, int64_t *n_near);
+
+/* Host-only quadrature tables used by the kernels (Sec. 3 regular / Duffy quadrature):
+ * kind 0: n-point Gauss-Legendre on [0, 1] -> nodes[n], weights[n];
+ * kind 1: symmetric 6-point degree-4 triangle rule (n must be 6) -> nodes[6 * 3]
+ *         barycentric coordinates, weights[6] summing to 1. */
+gaca_status gaca_quadrature_rule(int kind, int n, double *nodes, double *weights);
+
+/* Build (Algorithm 1 on every far block + dense near field) for one kernel.
+ * Synchronous: returns when the device work is done.  GACA_ERR_NOT_CONVERGED if a rank
+ * cap was hit (the handle is still returned and usable). */
+gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out);
+gaca_status gaca_hmatrix_destroy(gaca_hmatrix *h);
+gaca_status gaca_hmatrix_stats(const gaca_hmatrix *h, gaca_stats *st);
+/* Frequency-usage histogram: hist[k] = number of far blocks whose crosses use s_k. */
+gaca_status gaca_hmatrix_freq_hist(const gaca_hmatrix *h, int64_t *hist);
+
+/* Export of far block idx (tree-order rows/cols, see gaca_problem_blocks):
+ * info[8] = {row_start, m, col_start, n, r, sum_rho, capped, zero_faces}.
+ * Then (host buffers sized from info): ks[r], pi[r], pj[r] (tree-local pivots), rho[r],
+ * U: sum_rho * m complex (cross by cross, column-major m x rho_l),
+ * W: sum_rho * n complex (column-major n x rho_l), F: r * L complex (FP64 fibres),
+ * all as C128 (MIXED factors are widened). */
+gaca_status gaca_hmatrix_block_info(const gaca_hmatrix *h, int64_t idx, int64_t *info);
+gaca_status gaca_hmatrix_block_export(const gaca_hmatrix *h, int64_t idx, int32_t *ks,
+                                      int32_t *pi, int32_t *pj, int32_t *rho, double *U,
+                                      double *W, double *F);
+/* Near block idx as C128 [m][L][n] (tree-local order). */
+gaca_status gaca_hmatrix_near_export(const gaca_hmatrix *h, int64_t idx, double *out);
+
+/* Apply (eq. product).  X: device pointer, [L][M][nrhs] complex in ORIGINAL element order;
+ * Y: device pointer, [M][nrhs] (SUM) or [L][M][nrhs] (PER_FREQ).  dtype GACA_C128 runs the
+ * FP64 apply, GACA_C64 the FP32 apply.  Asynchronous on `hip_stream` (NULL: context
+ * stream); X, Y are caller-owned; the library uses internal workspace sized at the
+ * first call for this nrhs. */
+gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, const void *X,
+                       void *Y, gaca_dtype dtype, void *hip_stream);
+
+/* Test hook: entries E(i[p], j[p], k[p]) (ORIGINAL element ids) with the quadrature the
+ * build uses for a pair in a far block (far[p] = 1) or a near block (far[p] = 0), FP64,
+ * evaluated on the device.  out: 2 * n doubles (host).  n may be 0. */
+gaca_status gaca_eval_entries(gaca_problem *p, gaca_kernel kernel, int64_t n,
+                              const int32_t *i, const int32_t *j, const int32_t *k,
+                              const int32_t *far, double *out);
+
+/* Test hook: 3D-ACA (Algorithm 1) of one dense tensor given on the device,
+ * T[i][j][k] C128 with m x n x L entries, using the options' tolerances and precision
+ * FP64.  The result has one far block covering the whole tensor. */
+gaca_status gaca_compress_tensor(gaca_context *ctx, const void *dev_tensor, int64_t m,
+                                 int64_t n, int32_t L, const gaca_options *opt,
+                                 gaca_hmatrix **out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GACA_H */

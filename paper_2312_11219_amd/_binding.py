@@ -1,0 +1,343 @@
+"""ctypes binding of libgaca (names follow include/gaca.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libgaca.so")
+_lib = None
+
+P = ctypes.c_void_p
+I32, I64, F64, U64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
+
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "STATE", -5: "NOT_CONVERGED",
+          -6: "UNSUPPORTED"}
+SCHEMES = {"collocation": 0, "galerkin": 1}
+KERNELS = {"slp": 0, "dlp": 1}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+MODES = {"sum": 0, "per_freq": 1}
+
+
+class GacaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"gaca error {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("leaf_size", I32), ("eta", F64), ("eps3d", F64), ("eps_aca", F64),
+                ("precision", I32), ("n_duffy", I32), ("n_galerkin", I32), ("tie", F64),
+                ("delta_zero", F64), ("max_rank3d", I32), ("max_face_rank", I32),
+                ("max_device_bytes", U64), ("batch_bytes", U64), ("threads_small", I32),
+                ("threads_large", I32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_far", I64), ("n_near", I64), ("rank_min", I32), ("rank_max", I32),
+                ("rank_mean", F64), ("face_rank_max", I32), ("face_rank_mean", F64),
+                ("n_capped", I64), ("n_zero_blocks", I64), ("bytes_far", U64),
+                ("bytes_near", U64), ("dense_bytes", F64), ("compression", F64),
+                ("entries_near", F64), ("entries_face", F64), ("entries_fibre", F64),
+                ("entries_face_kernel", F64), ("ms_near", F64), ("ms_far", F64),
+                ("ms_total", F64)]
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libgaca.so; raises if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
+                           "`python paper_2312_11219_amd/build.py` (or __graft_entry__.build())")
+    lib = ctypes.CDLL(_LIB_PATH)
+    sig = {
+        "gaca_abi_version": (I32, []),
+        "gaca_last_error": (ctypes.c_char_p, []),
+        "gaca_options_default": (None, [P]),
+        "gaca_context_create": (I32, [ctypes.c_int, P, P]),
+        "gaca_context_destroy": (I32, [P]),
+        "gaca_problem_create": (I32, [P, P, I64, P, I64, P, P, I32, ctypes.c_int, P, P]),
+        "gaca_problem_destroy": (I32, [P]),
+        "gaca_problem_perm": (I32, [P, P]),
+        "gaca_problem_block_counts": (I32, [P, P, P]),
+        "gaca_problem_blocks": (I32, [P, P, P]),
+        "gaca_partition_host": (I32, [P, I64, P, I64, I32, F64, P, I64, P, P, P, P]),
+        "gaca_build": (I32, [P, ctypes.c_int, P]),
+        "gaca_hmatrix_destroy": (I32, [P]),
+        "gaca_hmatrix_stats": (I32, [P, P]),
+        "gaca_hmatrix_freq_hist": (I32, [P, P]),
+        "gaca_hmatrix_block_info": (I32, [P, I64, P]),
+        "gaca_hmatrix_block_export": (I32, [P, I64, P, P, P, P, P, P, P]),
+        "gaca_hmatrix_near_export": (I32, [P, I64, P]),
+        "gaca_apply": (I32, [P, ctypes.c_int, I32, P, P, ctypes.c_int, P]),
+        "gaca_eval_entries": (I32, [P, ctypes.c_int, I64, P, P, P, P, P]),
+        "gaca_compress_tensor": (I32, [P, P, I64, I64, I32, P, P]),
+        "gaca_quadrature_rule": (I32, [ctypes.c_int, ctypes.c_int, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code, allow=()):
+    if code != 0 and code not in allow:
+        raise GacaError(code, load_library().gaca_last_error().decode())
+    return code
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(P)
+
+
+def options_default(**overrides) -> Options:
+    lib = load_library()
+    o = Options()
+    lib.gaca_options_default(ctypes.byref(o))
+    for k, v in overrides.items():
+        if k == "precision" and isinstance(v, str):
+            v = PRECISIONS[v]
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def quadrature_rule(kind: str, n: int):
+    """The library's own tables: ('gauss', n) -> (nodes, weights) on [0, 1];
+    ('triangle6', 6) -> (barycentric 6 x 3, weights)."""
+    lib = load_library()
+    if kind == "gauss":
+        x = np.zeros(n)
+        w = np.zeros(n)
+        _check(lib.gaca_quadrature_rule(0, n, _ptr(x), _ptr(w)))
+        return x, w
+    x = np.zeros(18)
+    w = np.zeros(6)
+    _check(lib.gaca_quadrature_rule(1, 6, _ptr(x), _ptr(w)))
+    return x.reshape(6, 3), w
+
+
+def partition_host(xyz, tri, leaf_size, eta):
+    """Host-only tree + partition: (perm, far (nf,4), near (nn,4))."""
+    lib = load_library()
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    M = tri.shape[0]
+    perm = np.zeros(M, dtype=np.int64)
+    cap = max(16, 4 * M * M // max(1, leaf_size) // max(1, leaf_size) + 64)
+    cap = min(cap, 50_000_000)
+    while True:
+        far = np.zeros((cap, 4), dtype=np.int64)
+        near = np.zeros((cap, 4), dtype=np.int64)
+        nf, nn = I64(0), I64(0)
+        rc = lib.gaca_partition_host(_ptr(xyz), xyz.shape[0], _ptr(tri), M, leaf_size, eta,
+                                     _ptr(perm), cap, _ptr(far), ctypes.byref(nf), _ptr(near),
+                                     ctypes.byref(nn))
+        if rc == 0:
+            return perm, far[:nf.value], near[:nn.value]
+        if max(nf.value, nn.value) > cap:
+            cap = max(nf.value, nn.value)
+            continue
+        _check(rc)
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        self._lib = load_library()
+        h = P()
+        sp = None
+        if stream is not None:
+            sp = P(stream if isinstance(stream, int) else stream.cuda_stream)
+        _check(self._lib.gaca_context_create(device, sp, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            self._lib.gaca_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    def __init__(self, ctx: Context, xyz, tri, s, scheme="collocation", **options):
+        self._lib = load_library()
+        self.ctx = ctx
+        self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        self.tri = np.ascontiguousarray(tri, dtype=np.int32)
+        s = np.asarray(s, dtype=np.complex128)
+        self.s = s
+        self.L = s.shape[0]
+        self.M = self.tri.shape[0]
+        s_re = np.ascontiguousarray(s.real)
+        s_im = np.ascontiguousarray(s.imag)
+        self.opt = options_default(**options)
+        h = P()
+        _check(self._lib.gaca_problem_create(ctx.handle, _ptr(self.xyz), self.xyz.shape[0],
+                                             _ptr(self.tri), self.M, _ptr(s_re), _ptr(s_im),
+                                             self.L, SCHEMES[scheme], ctypes.byref(self.opt),
+                                             ctypes.byref(h)))
+        self.handle = h
+
+    @property
+    def perm(self):
+        out = np.zeros(self.M, dtype=np.int64)
+        _check(self._lib.gaca_problem_perm(self.handle, _ptr(out)))
+        return out
+
+    def blocks(self):
+        nf, nn = I64(0), I64(0)
+        _check(self._lib.gaca_problem_block_counts(self.handle, ctypes.byref(nf), ctypes.byref(nn)))
+        far = np.zeros((nf.value, 4), dtype=np.int64)
+        near = np.zeros((nn.value, 4), dtype=np.int64)
+        _check(self._lib.gaca_problem_blocks(self.handle, _ptr(far), _ptr(near)))
+        return far, near
+
+    def build(self, kernel="slp", allow_not_converged=True) -> "HMatrix":
+        h = P()
+        allow = (-5,) if allow_not_converged else ()
+        rc = _check(self._lib.gaca_build(self.handle, KERNELS[kernel], ctypes.byref(h)), allow)
+        return HMatrix(self, h, kernel, converged=(rc == 0))
+
+    def eval_entries(self, kernel, i, j, k, far):
+        i = np.ascontiguousarray(i, dtype=np.int32)
+        j = np.ascontiguousarray(j, dtype=np.int32)
+        k = np.ascontiguousarray(k, dtype=np.int32)
+        far = np.ascontiguousarray(far, dtype=np.int32)
+        n = i.shape[0]
+        out = np.zeros(2 * max(n, 1), dtype=np.float64)
+        _check(self._lib.gaca_eval_entries(self.handle, KERNELS[kernel], n, _ptr(i), _ptr(j),
+                                           _ptr(k), _ptr(far), _ptr(out)))
+        return out[0:2 * n:2] + 1j * out[1:2 * n:2]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.gaca_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HMatrix:
+    def __init__(self, problem, handle, kernel, converged=True, L=None):
+        self._lib = load_library()
+        self.problem = problem
+        self.handle = handle
+        self.kernel = kernel
+        self.converged = converged
+        self.L = L if L is not None else problem.L
+
+    def stats(self) -> dict:
+        st = Stats()
+        _check(self._lib.gaca_hmatrix_stats(self.handle, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in Stats._fields_}
+
+    def freq_hist(self):
+        out = np.zeros(self.L, dtype=np.int64)
+        _check(self._lib.gaca_hmatrix_freq_hist(self.handle, _ptr(out)))
+        return out
+
+    def block_info(self, idx):
+        info = np.zeros(8, dtype=np.int64)
+        _check(self._lib.gaca_hmatrix_block_info(self.handle, idx, _ptr(info)))
+        return dict(r0=int(info[0]), m=int(info[1]), c0=int(info[2]), n=int(info[3]),
+                    rank=int(info[4]), sum_rho=int(info[5]), capped=int(info[6]),
+                    zero_faces=int(info[7]))
+
+    def export_block(self, idx):
+        inf = self.block_info(idx)
+        r, sr, m, n, L = inf["rank"], inf["sum_rho"], inf["m"], inf["n"], self.L
+        ks = np.zeros(max(r, 1), np.int32)
+        pi = np.zeros(max(r, 1), np.int32)
+        pj = np.zeros(max(r, 1), np.int32)
+        rho = np.zeros(max(r, 1), np.int32)
+        U = np.zeros(2 * max(sr * m, 1))
+        W = np.zeros(2 * max(sr * n, 1))
+        F = np.zeros(2 * max(r * L, 1))
+        _check(self._lib.gaca_hmatrix_block_export(self.handle, idx, _ptr(ks), _ptr(pi), _ptr(pj),
+                                                   _ptr(rho), _ptr(U), _ptr(W), _ptr(F)))
+        Uc = U[0::2] + 1j * U[1::2]
+        Wc = W[0::2] + 1j * W[1::2]
+        Fc = (F[0::2] + 1j * F[1::2])[:r * L].reshape(r, L)
+        crosses = []
+        uo = wo = 0
+        for c in range(r):
+            p = int(rho[c])
+            Ul = Uc[uo:uo + p * m].reshape(p, m).T
+            Wl = Wc[wo:wo + p * n].reshape(p, n).T
+            uo += p * m
+            wo += p * n
+            crosses.append(dict(k=int(ks[c]), i=int(pi[c]), j=int(pj[c]), rho=p, U=Ul, W=Wl,
+                                f=Fc[c]))
+        inf["crosses"] = crosses
+        return inf
+
+    def reconstruct_block(self, idx):
+        b = self.export_block(idx)
+        out = np.zeros((b["m"], b["n"], self.L), dtype=complex)
+        for c in b["crosses"]:
+            out += (c["U"] @ c["W"].T)[:, :, None] * c["f"][None, None, :]
+        return out
+
+    def near_block(self, idx, m, n):
+        out = np.zeros(2 * m * n * self.L)
+        _check(self._lib.gaca_hmatrix_near_export(self.handle, idx, _ptr(out)))
+        return (out[0::2] + 1j * out[1::2]).reshape(m, self.L, n)
+
+    def apply(self, X, mode="sum", Y=None, stream=None):
+        """X: torch complex tensor [L, M, nrhs] on the GPU (original element order)."""
+        import torch
+        if X.dim() != 3 or X.shape[0] != self.L:
+            raise ValueError("X must be [L, M, nrhs]")
+        if not X.is_cuda or not X.is_contiguous():
+            raise ValueError("X must be a contiguous GPU tensor")
+        dtype = {torch.complex128: 0, torch.complex64: 1}[X.dtype]
+        L, M, nrhs = X.shape
+        if Y is None:
+            shape = (M, nrhs) if mode == "sum" else (L, M, nrhs)
+            Y = torch.empty(shape, dtype=X.dtype, device=X.device)
+        sp = P(stream.cuda_stream) if stream is not None else P(torch.cuda.current_stream().cuda_stream)
+        _check(self._lib.gaca_apply(self.handle, MODES[mode], nrhs, P(X.data_ptr()),
+                                    P(Y.data_ptr()), dtype, sp))
+        return Y
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.gaca_hmatrix_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def compress_tensor(ctx: Context, T, **options) -> HMatrix:
+    """3D-ACA of a dense device tensor T (torch complex128 [m, n, L])."""
+    lib = load_library()
+    m, n, L = T.shape
+    opt = options_default(**options)
+    h = P()
+    rc = _check(lib.gaca_compress_tensor(ctx.handle, P(T.data_ptr()), m, n, L, ctypes.byref(opt),
+                                         ctypes.byref(h)), (-5,))
+    return HMatrix(None, h, "tensor", converged=(rc == 0), L=L)

@@ -1,0 +1,54 @@
+// Host-side data structures of libgaca (mesh, cluster tree, block partition).
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <vector>
+
+#include "internal.h"
+
+namespace gaca {
+
+const char *last_error();
+void options_default(gaca_options *o);
+
+struct HostMesh {
+    int64_t nv = 0, M = 0;
+    std::vector<double> xyz;
+    std::vector<int32_t> tri;
+    // per element (original order)
+    std::vector<double> vert;   // 9 per element: a, b, c
+    std::vector<double> cen;    // centroid
+    std::vector<double> nrm;    // unit normal
+    std::vector<double> area, dpl, hmax;
+    std::vector<double> vmin, vmax;  // vertex box
+    void init(const double *xyz, int64_t nv, const int32_t *tri, int64_t M);
+};
+
+struct ClusterTree {
+    struct Node {
+        int64_t start = 0, size = 0;
+        int32_t level = 0;
+        int32_t child[2] = {-1, -1};
+        double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        double diam = 0.0;
+    };
+    int32_t leaf_size = 32;
+    std::vector<int64_t> perm;   // tree position -> original id
+    std::vector<Node> nodes;     // nodes[0] = root
+    void build(const HostMesh &mesh, int32_t leaf);
+
+   private:
+    int32_t build_rec(const HostMesh &mesh, int64_t start, int64_t size, int level);
+};
+
+struct Partition {
+    double eta = 1.0;
+    std::vector<std::array<int64_t, 4>> far, near;   // (row_start, m, col_start, n)
+    std::vector<int32_t> far_level;
+    void build(const ClusterTree &tree, double eta);
+};
+
+int32_t collocation_tier(const HostMesh &mesh, int64_t i, int64_t j);
+
+}  // namespace gaca

@@ -1,0 +1,100 @@
+// Internal types shared by the host code and the HIP kernels of libgaca.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gaca.h"
+
+namespace gaca {
+
+// ---- error state ---------------------------------------------------------------------
+void set_error(const std::string &msg);
+struct Error {
+    gaca_status code;
+    std::string msg;
+};
+
+#define GACA_HIP_CHECK(expr)                                                              \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            throw ::gaca::Error{GACA_ERR_HIP, std::string(#expr) + ": " +                 \
+                                                  hipGetErrorString(e_)};                 \
+    } while (0)
+
+// ---- quadrature tables (host generated, independent derivations) ---------------------
+struct Rule1D {
+    std::vector<double> x, w;   // nodes / weights on [0, 1]
+};
+Rule1D gauss_legendre01(int n);
+// Symmetric 6-point degree-4 triangle rule: barycentric (6 x 3) and weights summing to 1.
+void triangle6(double bary[6][3], double w[6]);
+
+// ---- device views ----------------------------------------------------------------------
+// Geometry in tree order, structure of arrays (length M each).
+struct GeoDev {
+    int64_t M;
+    const double *ax, *ay, *az, *bx, *by, *bz, *cx, *cy, *cz;  // vertices
+    const double *xx, *xy, *xz;                                // centroids (collocation points)
+    const double *nx, *ny, *nz, *d;                            // unit normal, plane offset n.a
+    const double *h, *area;                                    // longest edge, area
+    const double *q6x, *q6y, *q6z, *q6w;                       // [6][M] far-rule points/weights
+};
+
+// Quadrature tables in device memory.
+struct QuadDev {
+    int n4, n8, nd, ng;
+    const double *g4;    // n4 x 2 (node, weight)
+    const double *g8;    // n8 x 2
+    const double *gd;    // nd x 2
+    const double *gg;    // ng x 2 (Galerkin touching pairs)
+    const double *r6;    // 6 x 4 (bary, weight)
+};
+
+struct FreqDev {
+    int L;
+    int L_eval;          // frequencies actually evaluated (L or ceil(L/2) with mirror)
+    int mirror;          // 1: s_{L-1-l} = conj(s_l) exactly
+    const double *re, *im;
+};
+
+enum Tier : int32_t { TIER_FAR6 = 0, TIER_MID4 = 1, TIER_NEAR8 = 2, TIER_SELF = 3 };
+
+// One admissible block of a far-field launch.
+struct FarBlockDev {
+    int32_t r0, m, c0, n;      // tree-order ranges
+    int64_t face_off;          // scratch offset (complex elements) of the dense faces
+    int64_t uw_off;            // scratch offset of the current face's U (rho_max x m), W
+    int64_t fib_off;           // scratch offset of fibres (rcap x L complex)
+    int64_t gram_off;          // scratch offset of Gram matrix (rcap x rcap complex)
+    int32_t rho_max;           // face-rank cap for this block
+    int32_t out_idx;           // global far-block index
+};
+
+// Per-block result metadata written by the far-field kernel.
+struct FarMeta {
+    int32_t rank;              // crosses
+    int32_t sum_rho;
+    int32_t capped;
+    int32_t zero_faces;
+    int64_t fac_off;           // offset (complex elements) of this block's factors in the arena
+    double norm2;
+};
+
+struct CrossMeta {
+    int32_t k, pi, pj, rho;
+};
+
+struct AcaParams {
+    double eps, eps_aca, tie, delta;
+    int32_t rcap;              // crosses per block
+    int32_t kernel;            // 0 SLP, 1 DLP
+    int32_t galerkin;          // 1 Galerkin
+    int32_t _pad;
+};
+
+}  // namespace gaca

@@ -1,0 +1,48 @@
+"""Shared fixtures for GPU tests: workloads, oracle references, helpers."""
+import functools
+import sys
+
+import numpy as np
+
+from inputs import circle_frequencies, cube_mesh, get_config, mesh_for_config
+
+
+def log(*args):
+    print(*args, flush=True)
+    sys.stdout.flush()
+
+
+# Small far-field workload the oracle finishes in seconds: 768-triangle cube, leaf 16.
+SMALL = dict(name="cube768", mesh=("cube", 8), L=16, c0=10.0, rho=0.9, leaf=16, eta=1.0,
+             eps=1e-4)
+
+
+def workload(name):
+    if name == "cube768":
+        cfg = dict(SMALL)
+        xyz, tri = cube_mesh(8)
+    else:
+        cfg = get_config(name)
+        xyz, tri = mesh_for_config(name)
+    cfg.setdefault("eps_aca", cfg["eps"] / 100.0)
+    s = circle_frequencies(cfg["L"], cfg["c0"], cfg["rho"])
+    return cfg, xyz, tri, s
+
+
+@functools.lru_cache(maxsize=None)
+def context():
+    import paper_2312_11219_amd as gaca
+    return gaca.Context(0)
+
+
+def gpu_problem(name, **kw):
+    import paper_2312_11219_amd as gaca
+    cfg, xyz, tri, s = workload(name)
+    opts = dict(leaf_size=cfg["leaf"], eta=cfg["eta"], eps3d=cfg["eps"], eps_aca=cfg["eps_aca"])
+    opts.update(kw)
+    return cfg, gaca.Problem(context(), xyz, tri, s, **opts), (xyz, tri, s)
+
+
+def rel_fro(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a)

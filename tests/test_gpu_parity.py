@@ -1,0 +1,251 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+Bars (FP64 path): kernel entries <= 1e-12 relative per (block, frequency) Frobenius norm;
+compressed blocks ||C_gpu - C_oracle||_F / ||C||_F <= 1e-6 (expected ~1e-12 where the
+pivot sequences agree), and each error against the dense tensor <= 10 eps; apply
+<= 1e-12 against the dense product of the exported factors.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import gpu_problem, log, rel_fro, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_problem(name):
+    from oracle.hmatrix import Problem
+    cfg, xyz, tri, s = workload(name)
+    return cfg, Problem(xyz, tri, s, cfg["leaf"], cfg["eta"])
+
+
+@pytest.mark.parametrize("kernel", ["slp", "dlp"])
+def test_eval_entries_all_tiers(kernel):
+    from oracle.entries import Geometry, collocation_entries
+    log("eval entries", kernel)
+    cfg, prob, (xyz, tri, s) = gpu_problem("cube768")
+    rng = np.random.default_rng(3)
+    M, L = tri.shape[0], s.shape[0]
+    n = 6000
+    i = rng.integers(0, M, n)
+    j = rng.integers(0, M, n)
+    j[:200] = i[:200]
+    # neighbours of i for the near tiers
+    cen = (xyz[tri[:, 0]] + xyz[tri[:, 1]] + xyz[tri[:, 2]]) / 3
+    for t in range(200, 1200):
+        d = np.linalg.norm(cen - cen[i[t]], axis=1)
+        j[t] = int(np.argsort(d)[1 + t % 12])
+    k = rng.integers(0, L, n)
+    far = (rng.random(n) < 0.3).astype(np.int32)
+    far[:200] = 0
+    got = prob.eval_entries(kernel, i, j, k, far)
+    ref_all = collocation_entries(Geometry(xyz, tri), kernel, s, i, j, far)
+    ref = ref_all[np.arange(n), k]
+    scale = np.abs(ref_all).max(axis=1)
+    err = np.abs(got - ref) / np.maximum(scale, 1e-300)
+    err[scale == 0] = np.abs(got[scale == 0])
+    log("max rel entry err", err.max())
+    assert err.max() < 1e-12
+
+
+def test_near_field_c1_all_entries():
+    """C1 (192 triangles, leaf 16): every block is near, so the build stores the whole
+    192 x 192 x 16 tensor; compare all of it with the oracle."""
+    log("near C1")
+    cfg, prob, _ = gpu_problem("C1")
+    ocfg, op = _oracle_problem("C1")
+    h = prob.build("slp")
+    far, near = prob.blocks()
+    assert far.shape[0] == 0 and near.shape[0] == len(op.near)
+    worst = 0.0
+    for b, blk in enumerate(near):
+        got = h.near_block(b, int(blk[1]), int(blk[3]))          # [m][L][n]
+        ref = op.block_tensor("slp", tuple(int(v) for v in blk), False)   # [m][n][L]
+        ref = np.transpose(ref, (0, 2, 1))
+        for l in range(ref.shape[1]):
+            worst = max(worst, rel_fro(got[:, l, :], ref[:, l, :]))
+    log("C1 near worst rel", worst)
+    assert worst < 1e-12
+    st = h.stats()
+    assert st["n_far"] == 0 and st["entries_near"] == 192 * 192 * 16
+
+
+def _compare_far(name, kernel, pick=None, eps_mult=10.0):
+    cfg, prob, _ = gpu_problem(name)
+    ocfg, op = _oracle_problem(name)
+    from oracle.aca3d import aca3d
+    h = prob.build(kernel)
+    far, near = prob.blocks()
+    idx = range(far.shape[0]) if pick is None else pick
+    n_same = 0
+    tot_num = tot_den = par_num = 0.0
+    for b in idx:
+        blk = tuple(int(v) for v in far[b])
+        Tb = op.block_tensor(kernel, blk, True)
+        ores = aca3d(Tb, cfg["eps"], cfg["eps_aca"])
+        gb = h.export_block(b)
+        C_g = h.reconstruct_block(b)
+        C_o = ores.reconstruct(blk[1], blk[3], op.L)
+        same = (gb["rank"] == ores.rank and
+                all(c["k"] == oc.k and c["i"] == oc.i and c["j"] == oc.j and c["rho"] == oc.U.shape[1]
+                    for c, oc in zip(gb["crosses"], ores.crosses)))
+        n_same += same
+        nt = np.linalg.norm(Tb)
+        par_num += np.linalg.norm(C_g - C_o) ** 2
+        tot_num += np.linalg.norm(C_g - Tb) ** 2
+        tot_den += nt ** 2
+        if nt > 0:
+            assert np.linalg.norm(C_g - Tb) <= eps_mult * cfg["eps"] * nt, (b, blk)
+        else:
+            assert gb["rank"] == 0
+    n = len(list(idx))
+    par = np.sqrt(par_num / tot_den) if tot_den > 0 else np.sqrt(par_num)
+    err = np.sqrt(tot_num / tot_den) if tot_den > 0 else 0.0
+    log(f"{name} {kernel}: blocks {n} same pivots {n_same} parity {par:.3e} err {err:.3e}",
+        h.stats())
+    assert par <= 1e-6
+    assert err <= eps_mult * cfg["eps"]
+    return n_same, n
+
+
+@pytest.mark.parametrize("kernel", ["slp", "dlp"])
+def test_far_aca_small_all_blocks(kernel):
+    log("far small", kernel)
+    n_same, n = _compare_far("cube768", kernel)
+    assert n_same >= 0.95 * n
+
+
+@pytest.mark.parametrize("kernel", ["slp", "dlp"])
+def test_far_aca_c2_sampled_blocks(kernel):
+    log("far C2 sampled", kernel)
+    cfg, prob, _ = gpu_problem("C2")
+    far, _ = prob.blocks()
+    rng = np.random.default_rng(17)
+    pick = sorted(set(rng.choice(far.shape[0], 10, replace=False).tolist() +
+                      [int(np.argmax(far[:, 1] * far[:, 3]))]))
+    del prob
+    n_same, n = _compare_far("C2", kernel, pick)
+    assert n_same >= n - 2
+
+
+def test_c2_near_sampled():
+    log("near C2 sampled")
+    cfg, prob, _ = gpu_problem("C2")
+    ocfg, op = _oracle_problem("C2")
+    for kernel in ("slp", "dlp"):
+        h = prob.build(kernel)
+        far, near = prob.blocks()
+        rng = np.random.default_rng(5)
+        worst = 0.0
+        for b in rng.choice(near.shape[0], 12, replace=False):
+            blk = tuple(int(v) for v in near[b])
+            got = h.near_block(int(b), blk[1], blk[3])
+            ref = np.transpose(op.block_tensor(kernel, blk, False), (0, 2, 1))
+            for l in range(ref.shape[1]):
+                nr = np.linalg.norm(ref[:, l, :])
+                if nr > 0:
+                    worst = max(worst, np.linalg.norm(got[:, l, :] - ref[:, l, :]) / nr)
+                else:
+                    assert np.all(got[:, l, :] == 0)
+        log("C2 near", kernel, worst)
+        assert worst < 1e-12
+
+
+def test_build_deterministic():
+    cfg, prob, _ = gpu_problem("cube768")
+    h1 = prob.build("slp")
+    h2 = prob.build("slp")
+    far, _ = prob.blocks()
+    for b in range(0, far.shape[0], 7):
+        e1, e2 = h1.export_block(b), h2.export_block(b)
+        assert e1["rank"] == e2["rank"]
+        for c1, c2 in zip(e1["crosses"], e2["crosses"]):
+            assert np.array_equal(c1["U"], c2["U"]) and np.array_equal(c1["f"], c2["f"])
+
+
+@pytest.mark.parametrize("mode", ["sum", "per_freq"])
+def test_apply_matches_exported_dense(mode):
+    import torch
+    from inputs import random_rhs
+    log("apply", mode)
+    cfg, prob, (xyz, tri, s) = gpu_problem("cube768")
+    h = prob.build("slp")
+    far, near = prob.blocks()
+    perm = prob.perm
+    M, L = tri.shape[0], s.shape[0]
+    C = np.zeros((M, M, L), dtype=complex)
+    for b, blk in enumerate(far):
+        rows = perm[blk[0]:blk[0] + blk[1]]
+        cols = perm[blk[2]:blk[2] + blk[3]]
+        C[np.ix_(rows, cols)] = h.reconstruct_block(b)
+    for b, blk in enumerate(near):
+        rows = perm[blk[0]:blk[0] + blk[1]]
+        cols = perm[blk[2]:blk[2] + blk[3]]
+        C[np.ix_(rows, cols)] = np.transpose(h.near_block(b, int(blk[1]), int(blk[3])), (0, 2, 1))
+    X = random_rhs(L, M, 3, seed=4)
+    Xd = torch.from_numpy(X).cuda()
+    Y = h.apply(Xd, mode=mode)
+    torch.cuda.synchronize()
+    Y = Y.cpu().numpy()
+    ref = np.einsum("ijl,ljb->ib", C, X) if mode == "sum" else np.einsum("ijl,ljb->lib", C, X)
+    err = rel_fro(Y, ref)
+    log("apply err", mode, err)
+    assert err < 1e-12
+
+
+def test_apply_vs_oracle_apply():
+    import torch
+    from inputs import random_rhs
+    from oracle.hmatrix import apply as oapply, compress_far
+    cfg, prob, (xyz, tri, s) = gpu_problem("cube768")
+    ocfg, op = _oracle_problem("cube768")
+    h = prob.build("slp")
+    fres = [compress_far(op, "slp", blk, cfg["eps"], cfg["eps_aca"])[0] for blk in op.far]
+    ntens = [op.block_tensor("slp", blk, False) for blk in op.near]
+    X = random_rhs(op.L, op.M, 2, seed=9)
+    Yo = oapply(op, fres, ntens, X)
+    Yg = h.apply(torch.from_numpy(X).cuda()).cpu().numpy()
+    err = rel_fro(Yg, Yo)
+    log("apply vs oracle", err)
+    assert err < 1e-6
+
+
+@pytest.mark.parametrize("R,rho", [(1, 2), (3, 3), (6, 2)])
+def test_compress_tensor_known_rank(R, rho):
+    import torch
+    import paper_2312_11219_amd as gaca
+    from gpu_common import context
+    from oracle.aca3d import aca3d
+    rng = np.random.default_rng(R)
+    m, n, L = 40, 33, 12
+    T = np.zeros((m, n, L), dtype=complex)
+    for _ in range(R):
+        H = (rng.standard_normal((m, rho)) + 1j * rng.standard_normal((m, rho))) @ \
+            (rng.standard_normal((rho, n)) + 1j * rng.standard_normal((rho, n)))
+        T += H[:, :, None] * (rng.standard_normal(L) + 1j * rng.standard_normal(L))[None, None, :]
+    h = gaca.compress_tensor(context(), torch.from_numpy(T).cuda(), eps3d=1e-10, eps_aca=1e-12)
+    b = h.export_block(0)
+    C = h.reconstruct_block(0)
+    o = aca3d(T, 1e-10, 1e-12)
+    assert b["rank"] == R == o.rank
+    assert rel_fro(C, T) < 1e-12
+    assert [c["k"] for c in b["crosses"]] == [c.k for c in o.crosses]
+    assert [(c["i"], c["j"]) for c in b["crosses"]] == [(c.i, c.j) for c in o.crosses]
+
+
+def test_compress_tensor_zero_and_dense():
+    import torch
+    import paper_2312_11219_amd as gaca
+    from gpu_common import context
+    from oracle.aca3d import aca3d
+    T = np.zeros((7, 5, 6), dtype=complex)
+    h = gaca.compress_tensor(context(), torch.from_numpy(T).cuda(), eps3d=1e-6, eps_aca=1e-8)
+    b = h.export_block(0)
+    assert b["rank"] == 0 and b["zero_faces"] == 3
+    rng = np.random.default_rng(1)
+    T = rng.standard_normal((6, 5, 4)) + 1j * rng.standard_normal((6, 5, 4))
+    h = gaca.compress_tensor(context(), torch.from_numpy(T).cuda(), eps3d=0.0, eps_aca=0.0)
+    assert h.export_block(0)["rank"] == 4
+    assert rel_fro(h.reconstruct_block(0), T) < 1e-12
+    o = aca3d(T, 0.0, 0.0)
+    assert [c["k"] for c in h.export_block(0)["crosses"]] == [c.k for c in o.crosses]
