@@ -1,0 +1,175 @@
+"""Benchmark: 3-way ACA build of Laplace-domain BEM tensors on one MI355X.
+
+One step = the whole hot path on the 3072-triangle cube workload (collocation, L = 64,
+s_l = 20 (1 + 0.95 e^{i 2 pi (l + 1/2)/64}), leaf 32, eta 1, eps 1e-6, FP64): the dense
+near field and the 3D-ACA of every far block for the single layer AND the double layer,
+plus one reordered product (eq. product, 2 right-hand sides per frequency) with each.
+The problem (mesh, tree, partition, device geometry) is created before the timed
+region; the right-hand sides are resident in HBM.
+
+Prints ONE JSON line.  value = kernel entries per second, where the entries are the
+tensor entries the method needs: the dense near field (m n L per near block), the rows
+and columns the face ACAs read (rho (m + n) per face) and the frequency fibres (r L).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="C2")
+    ap.add_argument("--nrhs", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, xyz, tri, s, budget_s):
+    """The oracle timed on a bounded sample of the same workload: seeded random far blocks
+    (dense assembly + serial 3D-ACA, as the oracle does it) and near blocks, until about
+    budget_s seconds of CPU work; reported in the same unit (entries per second)."""
+    import numpy as np
+    from oracle.aca3d import aca3d
+    from oracle.hmatrix import Problem
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    op = Problem(xyz, tri, s, cfg["leaf"], cfg["eta"])
+    rng = np.random.default_rng(0)
+    far_order = rng.permutation(len(op.far))
+    near_order = rng.permutation(len(op.near))
+    # the workload's mix: near entries vs far blocks in proportion to their counts
+    entries = 0.0
+    t0 = time.perf_counter()
+    nf = nn = 0
+    fi = ni = 0
+    while time.perf_counter() - t0 < budget_s and (fi < len(far_order) or ni < len(near_order)):
+        for kernel in cfg["kernels"]:
+            if fi < len(far_order):
+                blk = op.far[far_order[fi]]
+                T = op.block_tensor(kernel, blk, True)
+                res = aca3d(T, cfg["eps"], cfg["eps_aca"])
+                m, n = blk[1], blk[3]
+                entries += sum(c.U.shape[1] * (m + n) for c in res.crosses) + res.rank * op.L
+                nf += 1
+            if ni < len(near_order):
+                blk = op.near[near_order[ni]]
+                op.block_tensor(kernel, blk, False)
+                entries += blk[1] * blk[3] * op.L
+                nn += 1
+        fi += 1
+        ni += 1
+    dt = time.perf_counter() - t0
+    return {"value": entries / dt, "unit": "entries/s", "cores": threads, "kind": "oracle",
+            "sample": f"{fi} far + {ni} near blocks per kernel ({','.join(cfg['kernels'])}), "
+                      f"seeded random order, {dt:.1f} s, oracle dense block assembly "
+                      f"(C, OpenMP over pairs) + serial numpy 3D-ACA"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the far blocks would shard by LPT across GPUs, see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2312_11219_amd as gaca
+    from inputs import circle_frequencies, get_config, mesh_for_config, random_rhs
+
+    cfg = get_config(args.config)
+    xyz, tri = mesh_for_config(args.config)
+    s = circle_frequencies(cfg["L"], cfg["c0"], cfg["rho"])
+    M, L = tri.shape[0], cfg["L"]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    ctx = gaca.Context(0, stream=stream)
+    t_setup = time.perf_counter()
+    prob = gaca.Problem(ctx, xyz, tri, s, leaf_size=cfg["leaf"], eta=cfg["eta"],
+                        eps3d=cfg["eps"], eps_aca=cfg["eps_aca"])
+    t_setup = time.perf_counter() - t_setup
+    X = torch.from_numpy(random_rhs(L, M, args.nrhs, seed=0)).to(dev)
+    kernels = cfg["kernels"]
+
+    def step():
+        stats = []
+        for k in kernels:
+            h = prob.build(k)
+            h.apply(X, stream=stream)
+            stats.append(h.stats())
+            del h
+        return stats
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    all_stats = []
+    for _ in range(args.steps):
+        all_stats.append(step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    last = all_stats[-1]
+    entries_step = sum(st["entries_near"] + st["entries_face"] + st["entries_fibre"] for st in last)
+    value = entries_step * args.steps / elapsed
+    # dominant kernel: the far-field 3D-ACA kernel (HIP events around each launch)
+    far_ms = np.mean([sum(st["ms_far_kernel"] for st in stp) for stp in all_stats])
+    far_launches = sum(st["n_far_launches"] for st in last)
+    far_flops = sum(st["far_flops"] for st in last)
+    near_ms = np.mean([sum(st["ms_near_kernel"] for st in stp) for stp in all_stats])
+    achieved = far_flops / (far_ms * 1e-3) / 1e12
+    out = {
+        "metric": "3-way ACA build s + kernel entries/s, FP64 vs mixed-prec at stated rel err",
+        "value": value,
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"cube surface 16x16 squares per face ({M} triangles), "
+                               f"collocation P0, single+double layer, L={L} circle frequencies "
+                               f"c0={cfg['c0']} rho={cfg['rho']}, leaf {cfg['leaf']}, eta "
+                               f"{cfg['eta']}, eps {cfg['eps']}, eps_aca {cfg['eps_aca']}, "
+                               f"build + apply with {args.nrhs} rhs",
+                   "global_batch": 1, "parallelism": "single-gpu"},
+        "build_ms": {k: st["ms_total"] for k, st in zip(kernels, last)},
+        "near_kernel_ms": near_ms,
+        "far_kernel_ms": far_ms,
+        "entries_per_step": entries_step,
+        "ranks": {k: [st["rank_min"], st["rank_max"], round(st["rank_mean"], 2)]
+                  for k, st in zip(kernels, last)},
+        "compression": {k: st["compression"] for k, st in zip(kernels, last)},
+        "setup_s": t_setup,
+        "roofline": {"bound": "alu", "kernel": "far_fp64_kernel (3D-ACA, all launches of a step)",
+                     "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "launches_per_step": far_launches},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, xyz, tri, s, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -95,6 +95,13 @@ typedef struct {
     double entries_fibre;         /* frequency-fibre entries (r L per block) */
     double entries_face_kernel;   /* entries the face kernels evaluated (dense faces) */
     double ms_near, ms_far, ms_total;  /* device time of the build phases */
+    double ms_near_kernel;        /* sum of near-field kernel durations (HIP events) */
+    double ms_far_kernel;         /* sum of far-field 3D-ACA kernel durations (last attempt) */
+    int32_t n_far_launches;       /* far-field kernel launches in the last attempt */
+    int32_t far_attempts;         /* 1 + arena re-allocations */
+    double far_flops;             /* algorithmic FP64 flops of the far-field kernels */
+    double far_kernel_evals;      /* quadrature-point x frequency kernel evaluations (far) */
+    double near_kernel_evals;     /* quadrature-point x frequency kernel evaluations (near) */
 } gaca_stats;
 
 int gaca_abi_version(void);

@@ -42,7 +42,9 @@ class Stats(ctypes.Structure):
                 ("bytes_near", U64), ("dense_bytes", F64), ("compression", F64),
                 ("entries_near", F64), ("entries_face", F64), ("entries_fibre", F64),
                 ("entries_face_kernel", F64), ("ms_near", F64), ("ms_far", F64),
-                ("ms_total", F64)]
+                ("ms_total", F64), ("ms_near_kernel", F64), ("ms_far_kernel", F64),
+                ("n_far_launches", I32), ("far_attempts", I32), ("far_flops", F64),
+                ("far_kernel_evals", F64), ("near_kernel_evals", F64)]
 
 
 def lib_path() -> str:
@@ -57,6 +59,10 @@ def load_library():
     if not os.path.exists(_LIB_PATH):
         raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
                            "`python paper_2312_11219_amd/build.py` (or __graft_entry__.build())")
+    # One HIP runtime per process: torch ships its own libamdhip64.so.7 (same SONAME as the
+    # system one libgaca links against).  Loading torch first makes libgaca bind to the
+    # runtime torch uses, so device pointers and streams are shared with it.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(_LIB_PATH)
     sig = {
         "gaca_abi_version": (I32, []),

@@ -542,7 +542,11 @@ static void run_far(gaca_hmatrix *h, const double2 *dense) {
             }
         }
         d_items.upload(ctx, descs);
+        std::vector<hipEvent_t> evs(2 * batches.size());
+        for (auto &e : evs) GACA_HIP_CHECK(hipEventCreate(&e));
+        size_t bi = 0;
         for (auto &bt : batches) {
+            GACA_HIP_CHECK(hipEventRecord(evs[2 * bi], st));
             FarLaunch fl{};
             fl.blocks = d_items.as<FarBlockDev>() + bt.first;
             fl.nb = (int32_t)(bt.second - bt.first);
@@ -562,12 +566,24 @@ static void run_far(gaca_hmatrix *h, const double2 *dense) {
             fl.dense = dense;
             launch_far_fp64(h->kernel, p->g, p->f, P, fl, st);
             GACA_HIP_CHECK(hipGetLastError());
+            GACA_HIP_CHECK(hipEventRecord(evs[2 * bi + 1], st));
+            ++bi;
         }
         int32_t over = 0;
         unsigned long long ctrs[2];
         GACA_HIP_CHECK(hipMemcpyAsync(&over, d_over.ptr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         GACA_HIP_CHECK(hipMemcpyAsync(ctrs, d_ctr.ptr, sizeof(ctrs), hipMemcpyDeviceToHost, st));
         GACA_HIP_CHECK(hipStreamSynchronize(st));
+        double ms_k = 0.0;
+        for (size_t b2 = 0; b2 < batches.size(); ++b2) {
+            float ms = 0.0f;
+            GACA_HIP_CHECK(hipEventElapsedTime(&ms, evs[2 * b2], evs[2 * b2 + 1]));
+            ms_k += ms;
+        }
+        for (auto &e : evs) (void)hipEventDestroy(e);
+        h->st.ms_far_kernel = ms_k;
+        h->st.n_far_launches = (int32_t)batches.size();
+        h->st.far_attempts = attempt + 1;
         if (!over) break;
         arena_cap = std::max<uint64_t>(arena_cap * 2, ctrs[0] + 1024);
         fib_cap = std::max<uint64_t>(fib_cap * 2, ctrs[1] + 1024);
@@ -620,6 +636,28 @@ static void fill_stats(gaca_hmatrix *h) {
         fib_elems += (double)mt.rank * L;
         for (int k = 0; k < L; ++k) h->freq_hist[k] += used[k];
     }
+    // Algorithmic work model (FP64 flops; a complex multiply-add is 8 flops).  Per
+    // quadrature-point x frequency evaluation of the single layer: distance 8, sqrt 13
+    // (rsq + 2 Newton steps), exp 31 (reduction + degree-13 polynomial + scaling), sincos
+    // 36 (Cody-Waite reduction + two polynomials), 1/(4 pi r) 8, weight and complex
+    // accumulate 9 -> 105; the double layer adds (1 + s r), r^3 and the numerator: 113.
+    const double f_eval = h->kernel == 0 ? 105.0 : 113.0;
+    double macs = 0.0, evals = 0.0;
+    for (int64_t b = 0; b < h->nfar; ++b) {
+        const FarMeta &mt = h->meta[b];
+        const double m = (double)p->part.far[b][1], n = (double)p->part.far[b][3];
+        evals += (double)(mt.rank + mt.zero_faces) * m * n * 6.0 + (double)mt.rank * L * 6.0;
+        for (int c = 0; c < mt.rank; ++c) {
+            const double rho = h->cmeta[b * h->rcap + c].rho;
+            macs += c * m * n;                       // residual face: previous crosses
+            macs += (m + n) * rho * (rho - 1.0);     // face ACA row/column corrections + Gram
+            macs += m * n * rho;                     // dense expansion (pivot search)
+            macs += m * n * (c + 1.0);               // <H_l, H_p>
+            macs += 2.0 * L * c;                     // fibre correction and fibre dots
+        }
+    }
+    s.far_kernel_evals = evals;
+    s.far_flops = evals * f_eval + 8.0 * macs;
     s.rank_mean = h->nfar ? rsum / h->nfar : 0.0;
     s.face_rank_mean = nfaces > 0 ? frsum / nfaces : 0.0;
     const double eb = h->prec == GACA_FP64 ? 16.0 : 8.0;
@@ -649,9 +687,9 @@ gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out) 
         GACA_HIP_CHECK(hipEventCreate(&e0));
         GACA_HIP_CHECK(hipEventCreate(&e1));
         GACA_HIP_CHECK(hipEventCreate(&e2));
-        GACA_HIP_CHECK(hipEventRecord(e0, st));
         // near field
         h->d_near.alloc(ctx, std::max<int64_t>(1, p->near_elems) * sizeof(double2));
+        GACA_HIP_CHECK(hipEventRecord(e0, st));
         for (int t = 0; t < 4; ++t)
             launch_near(kernel, t, p->g, p->q, p->f, p->d_pairs[t].as<NearPair>(), p->npairs[t],
                         p->d_nblocks.as<NearBlockDev>(), h->d_near.as<double2>(), nullptr, st);
@@ -668,6 +706,14 @@ gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out) 
         (void)hipEventDestroy(e2);
         fill_stats(h.get());
         h->st.ms_near = ms_near;
+        h->st.ms_near_kernel = ms_near;
+        {
+            const double le = p->f.L_eval;
+            const double qp[4] = {6.0, 16.0, 64.0, kernel == 0 ? 3.0 * p->opt.n_duffy * p->opt.n_duffy : 0.0};
+            double ev = 0.0;
+            for (int t = 0; t < 4; ++t) ev += (double)p->npairs[t] * le * qp[t];
+            h->st.near_kernel_evals = ev;
+        }
         h->st.ms_far = ms_far;
         h->st.ms_total = ms_near + ms_far;
         capped = h->st.n_capped > 0;
