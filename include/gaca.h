@@ -96,12 +96,18 @@ typedef struct {
     double entries_face_kernel;   /* entries the face kernels evaluated (dense faces) */
     double ms_near, ms_far, ms_total;  /* device time of the build phases */
     double ms_near_kernel;        /* sum of near-field kernel durations (HIP events) */
-    double ms_far_kernel;         /* sum of far-field 3D-ACA kernel durations (last attempt) */
+    double ms_far_kernel;         /* device time span of the far-field 3D-ACA launches (the
+                                     launch classes run concurrently on three streams) */
     int32_t n_far_launches;       /* far-field kernel launches in the last attempt */
     int32_t far_attempts;         /* 1 + arena re-allocations */
     double far_flops;             /* algorithmic FP64 flops of the far-field kernels */
     double far_kernel_evals;      /* quadrature-point x frequency kernel evaluations (far) */
     double near_kernel_evals;     /* quadrature-point x frequency kernel evaluations (near) */
+    /* per far-field launch class (0: small blocks, residual face in LDS, 64 threads;
+     * 1: small blocks, 256 threads; 2: large blocks, HBM scratch, 512 threads) */
+    double ms_far_by_kind[3];     /* sum of launch durations (HIP events on the launch stream) */
+    int32_t launches_by_kind[3];
+    double far_flops_by_kind[3];  /* algorithmic FP64 flops of the class */
 } gaca_stats;
 
 int gaca_abi_version(void);

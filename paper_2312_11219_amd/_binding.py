@@ -44,7 +44,9 @@ class Stats(ctypes.Structure):
                 ("entries_face_kernel", F64), ("ms_near", F64), ("ms_far", F64),
                 ("ms_total", F64), ("ms_near_kernel", F64), ("ms_far_kernel", F64),
                 ("n_far_launches", I32), ("far_attempts", I32), ("far_flops", F64),
-                ("far_kernel_evals", F64), ("near_kernel_evals", F64)]
+                ("far_kernel_evals", F64), ("near_kernel_evals", F64),
+                ("ms_far_by_kind", F64 * 3), ("launches_by_kind", I32 * 3),
+                ("far_flops_by_kind", F64 * 3)]
 
 
 def lib_path() -> str:
@@ -255,7 +257,11 @@ class HMatrix:
     def stats(self) -> dict:
         st = Stats()
         _check(self._lib.gaca_hmatrix_stats(self.handle, ctypes.byref(st)))
-        return {name: getattr(st, name) for name, _ in Stats._fields_}
+        out = {}
+        for name, _ in Stats._fields_:
+            v = getattr(st, name)
+            out[name] = list(v) if hasattr(v, "__len__") else v
+        return out
 
     def freq_hist(self):
         out = np.zeros(self.L, dtype=np.int64)

@@ -1,0 +1,144 @@
+// Device helpers shared by the HIP kernels: double2 complex arithmetic and fixed-order
+// wave64 / workgroup reductions (deterministic: the same inputs give the same bits).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace gaca {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * conj(b)
+    return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
+    return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ double2 csub(double2 a, double2 b) {
+    return make_double2(a.x - b.x, a.y - b.y);
+}
+__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {  // c + a * b
+    return make_double2(c.x + a.x * b.x - a.y * b.y, c.y + a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+    double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Workgroup reductions; buf must hold >= 4 * NT / 64 doubles of shared memory.  Every
+// call starts with a barrier, so consecutive calls may reuse the same buffer.
+template <int NT>
+struct Red {
+    static constexpr int NW = NT / 64;
+    double *buf;
+    __device__ double sum(double v) {
+        v = wave_sum(v);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) buf[threadIdx.x >> 6] = v;
+        __syncthreads();
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += buf[w];
+        return t;
+    }
+    __device__ void sum3(double &a, double &b, double &c) {
+        a = wave_sum(a);
+        b = wave_sum(b);
+        c = wave_sum(c);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) {
+            buf[3 * (threadIdx.x >> 6)] = a;
+            buf[3 * (threadIdx.x >> 6) + 1] = b;
+            buf[3 * (threadIdx.x >> 6) + 2] = c;
+        }
+        __syncthreads();
+        a = b = c = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            a += buf[3 * w];
+            b += buf[3 * w + 1];
+            c += buf[3 * w + 2];
+        }
+    }
+    __device__ double max(double v) {
+        v = wave_max(v);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) buf[threadIdx.x >> 6] = v;
+        __syncthreads();
+        double t = buf[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) t = fmax(t, buf[w]);
+        return t;
+    }
+    // max of a and sum of b in one round
+    __device__ void maxsum(double &a, double &b) {
+        a = wave_max(a);
+        b = wave_sum(b);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) {
+            buf[2 * (threadIdx.x >> 6)] = a;
+            buf[2 * (threadIdx.x >> 6) + 1] = b;
+        }
+        __syncthreads();
+        a = buf[0];
+        b = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            a = fmax(a, buf[2 * w]);
+            b += buf[2 * w + 1];
+        }
+    }
+    __device__ int imin(int v) {
+        v = wave_min(v);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) reinterpret_cast<int *>(buf)[threadIdx.x >> 6] = v;
+        __syncthreads();
+        int t = reinterpret_cast<int *>(buf)[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) t = min(t, reinterpret_cast<int *>(buf)[w]);
+        return t;
+    }
+};
+
+// sum_{qq < q} a[qq * sa] * b[qq * sb] with eight independent partial sums, so that up to
+// sixteen loads are in flight per thread (the loops are latency-bound otherwise).
+__device__ __forceinline__ double2 dot_strided(const double2 *__restrict__ a, int64_t sa,
+                                               const double2 *__restrict__ b, int64_t sb,
+                                               int q0, int q1) {
+    double2 s[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) s[t] = make_double2(0.0, 0.0);
+    int qq = q0;
+    for (; qq + 8 <= q1; qq += 8) {
+        double2 av[8], bv[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            av[t] = a[(int64_t)(qq + t) * sa];
+            bv[t] = b[(int64_t)(qq + t) * sb];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) s[t] = cfma(av[t], bv[t], s[t]);
+    }
+    for (; qq < q1; ++qq) s[0] = cfma(a[(int64_t)qq * sa], b[(int64_t)qq * sb], s[0]);
+    return cadd(cadd(cadd(s[0], s[1]), cadd(s[2], s[3])), cadd(cadd(s[4], s[5]), cadd(s[6], s[7])));
+}
+
+}  // namespace gaca

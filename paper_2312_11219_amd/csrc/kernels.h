@@ -22,10 +22,14 @@ void launch_near(int kernel, int tier, const GeoDev &g, const QuadDev &q, const 
                  double2 *out64, float2 *out32, hipStream_t st);
 
 // Far field FP64 3D-ACA: one workgroup per block of `blocks` (nb blocks).
+// kind 0: small blocks (m n <= 1024, sides <= 64), residual face in LDS, 64 threads;
+// kind 1: small blocks (m n <= 2304, sides <= 96), residual face in LDS, 256 threads;
+// kind 2: large blocks, residual face and factors in HBM scratch, 512 threads.
+// Small kinds need rcap <= 64.
 struct FarLaunch {
     const FarBlockDev *blocks;
     int32_t nb;
-    int32_t threads;
+    int32_t kind;
     double2 *scratch;
     FarMeta *meta;
     CrossMeta *cmeta;     // [nfar][rcap]

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <functional>
 #include <numeric>
 
 #include "host.h"
@@ -115,6 +116,13 @@ struct gaca_problem {
     int64_t npairs[4] = {0, 0, 0, 0};
     // leaves for the apply
     std::vector<int32_t> leaf_r0, leaf_m;
+    // far-field launch classes run concurrently on these streams (default priority)
+    hipStream_t far_streams[3] = {nullptr, nullptr, nullptr};
+    bool far_streams_ready = false;
+    ~gaca_problem() {
+        if (far_streams_ready)
+            for (auto &s : far_streams) (void)hipStreamDestroy(s);
+    }
 };
 
 struct gaca_hmatrix {
@@ -422,7 +430,15 @@ gaca_status gaca_problem_blocks(const gaca_problem *p, int64_t *far4, int64_t *n
 
 // ---------------------------------------------------------------------------------------
 // far-field build
-static void run_far(gaca_hmatrix *h, const double2 *dense) {
+// Launch class of a far block: small blocks keep the residual face in LDS.
+static int far_kind(int m, int n, int rcap) {
+    const int64_t mn = (int64_t)m * n;
+    if (rcap <= 64 && mn <= 1024 && m <= 64 && n <= 64) return 0;
+    if (rcap <= 64 && mn <= 2304 && m <= 96 && n <= 96) return 1;
+    return 2;
+}
+
+static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<void()> &main_work) {
     gaca_problem *p = h->p;
     gaca_context *ctx = p->ctx;
     const auto &far = p->part.far;
@@ -439,7 +455,10 @@ static void run_far(gaca_hmatrix *h, const double2 *dense) {
     for (int64_t b = 0; b < nfar; ++b)
         for (int k = 0; k < 4; ++k) far4[4 * b + k] = (int32_t)far[b][k];
     h->d_far4.upload(ctx, far4);
-    if (nfar == 0) return;
+    if (nfar == 0) {
+        main_work();
+        return;
+    }
     h->d_meta.alloc(ctx, nfar * sizeof(FarMeta));
     h->d_cmeta.alloc(ctx, nfar * rcap * sizeof(CrossMeta));
     h->d_cross_off.alloc(ctx, nfar * rcap * sizeof(int64_t));
@@ -447,7 +466,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense) {
     // per-block scratch (complex elements) and launch classes
     struct Item {
         int64_t b, bytes;
-        int threads;
+        int kind;
         FarBlockDev d;
     };
     std::vector<Item> items;
@@ -470,21 +489,18 @@ static void run_far(gaca_hmatrix *h, const double2 *dense) {
         d.uw_off = faces;
         d.fib_off = faces + uw;
         d.gram_off = faces + uw + fibs;
-        int64_t elems = faces + uw + fibs + gram;
-        int thr = ((int64_t)m * n <= 4096) ? p->opt.threads_small : p->opt.threads_large;
-        thr = thr <= 64 ? 64 : 256;
-        items.push_back(Item{b, elems, thr, d});
+        items.push_back(Item{b, faces + uw + fibs + gram, far_kind(m, n, rcap), d});
         dense_far += (double)m * n * L;
     }
-    // biggest blocks first inside each class
+    // large blocks first, biggest first inside each class
     std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
-        if (a.threads != b.threads) return a.threads > b.threads;
+        if (a.kind != b.kind) return a.kind > b.kind;
         return a.bytes > b.bytes;
     });
-    // arenas: estimates, doubled on overflow
     uint64_t arena_cap = (uint64_t)std::max(1.0e6, 0.35 * dense_far);
     uint64_t fib_cap = (uint64_t)std::max<int64_t>(1 << 16, nfar * (int64_t)std::min(rcap, 24) * L);
-    const uint64_t budget_elems = std::max<uint64_t>(p->opt.batch_bytes / sizeof(double2), 1 << 20);
+    const uint64_t budget_elems =
+        std::max<uint64_t>(p->opt.batch_bytes / sizeof(double2) / 3, 1 << 20);
     AcaParams P{};
     P.eps = p->opt.eps3d;
     P.eps_aca = p->opt.eps_aca;
@@ -492,35 +508,50 @@ static void run_far(gaca_hmatrix *h, const double2 *dense) {
     P.delta = p->opt.delta_zero;
     P.rcap = rcap;
     P.kernel = h->kernel;
-    DevBuf d_ctr, d_items, d_scratch, d_over;
+    DevBuf d_ctr, d_items, d_over;
+    DevBuf d_scratch[3];
     d_ctr.alloc(ctx, 2 * sizeof(unsigned long long));
     d_over.alloc(ctx, sizeof(int32_t));
-    int64_t max_item = 0;
-    for (auto &it : items) max_item = std::max(max_item, it.bytes);
-    // batches
-    std::vector<std::pair<size_t, size_t>> batches;   // [begin, end) into items
-    {
-        size_t s = 0;
-        while (s < items.size()) {
-            size_t e = s;
-            uint64_t acc = 0;
-            while (e < items.size() && items[e].threads == items[s].threads &&
-                   (e == s || acc + items[e].bytes <= budget_elems)) {
-                acc += items[e].bytes;
-                ++e;
-            }
-            batches.push_back({s, e});
-            s = e;
+    // batches: consecutive items of one class within the memory budget
+    struct Batch {
+        size_t first, last;
+        int kind;
+        uint64_t elems;
+    };
+    std::vector<Batch> batches;
+    uint64_t kind_max[3] = {0, 0, 0};
+    for (size_t s = 0; s < items.size();) {
+        size_t e = s;
+        uint64_t acc = 0;
+        while (e < items.size() && items[e].kind == items[s].kind &&
+               (e == s || acc + items[e].bytes <= budget_elems)) {
+            acc += items[e].bytes;
+            ++e;
+        }
+        batches.push_back(Batch{s, e, items[s].kind, acc});
+        kind_max[items[s].kind] = std::max(kind_max[items[s].kind], acc);
+        s = e;
+    }
+    for (int k = 0; k < 3; ++k)
+        if (kind_max[k] > 0) d_scratch[k].alloc(ctx, kind_max[k] * sizeof(double2));
+    if (!p->far_streams_ready) {
+        for (int k = 0; k < 3; ++k) GACA_HIP_CHECK(hipStreamCreate(&p->far_streams[k]));
+        p->far_streams_ready = true;
+    }
+    std::vector<FarBlockDev> descs(items.size());
+    for (auto &bt : batches) {
+        int64_t acc = 0;
+        for (size_t k = bt.first; k < bt.last; ++k) {
+            FarBlockDev d = items[k].d;
+            d.face_off += acc;
+            d.uw_off += acc;
+            d.fib_off += acc;
+            d.gram_off += acc;
+            acc += items[k].bytes;
+            descs[k] = d;
         }
     }
-    uint64_t max_batch = 0;
-    for (auto &bt : batches) {
-        uint64_t acc = 0;
-        for (size_t k = bt.first; k < bt.second; ++k) acc += items[k].bytes;
-        max_batch = std::max(max_batch, acc);
-    }
-    d_scratch.alloc(ctx, max_batch * sizeof(double2));
-    std::vector<FarBlockDev> descs(items.size());
+    d_items.upload(ctx, descs);
     for (int attempt = 0; attempt < 6; ++attempt) {
         h->d_arena.release();
         h->d_fib.release();
@@ -528,30 +559,20 @@ static void run_far(gaca_hmatrix *h, const double2 *dense) {
         h->d_fib.alloc(ctx, fib_cap * sizeof(double2));
         GACA_HIP_CHECK(hipMemsetAsync(d_ctr.ptr, 0, 2 * sizeof(unsigned long long), st));
         GACA_HIP_CHECK(hipMemsetAsync(d_over.ptr, 0, sizeof(int32_t), st));
-        // descriptors with scratch offsets per batch
-        for (auto &bt : batches) {
-            int64_t acc = 0;
-            for (size_t k = bt.first; k < bt.second; ++k) {
-                FarBlockDev d = items[k].d;
-                d.face_off += acc;
-                d.uw_off += acc;
-                d.fib_off += acc;
-                d.gram_off += acc;
-                acc += items[k].bytes;
-                descs[k] = d;
-            }
-        }
-        d_items.upload(ctx, descs);
-        std::vector<hipEvent_t> evs(2 * batches.size());
+        std::vector<hipEvent_t> evs(2 * batches.size() + 4);
         for (auto &e : evs) GACA_HIP_CHECK(hipEventCreate(&e));
-        size_t bi = 0;
-        for (auto &bt : batches) {
-            GACA_HIP_CHECK(hipEventRecord(evs[2 * bi], st));
+        hipEvent_t ev_start = evs[2 * batches.size()];
+        GACA_HIP_CHECK(hipEventRecord(ev_start, st));
+        for (int k = 0; k < 3; ++k) GACA_HIP_CHECK(hipStreamWaitEvent(p->far_streams[k], ev_start, 0));
+        for (size_t bi = 0; bi < batches.size(); ++bi) {
+            const Batch &bt = batches[bi];
+            hipStream_t fs = p->far_streams[bt.kind];
+            GACA_HIP_CHECK(hipEventRecord(evs[2 * bi], fs));
             FarLaunch fl{};
             fl.blocks = d_items.as<FarBlockDev>() + bt.first;
-            fl.nb = (int32_t)(bt.second - bt.first);
-            fl.threads = items[bt.first].threads;
-            fl.scratch = d_scratch.as<double2>();
+            fl.nb = (int32_t)(bt.last - bt.first);
+            fl.kind = bt.kind;
+            fl.scratch = d_scratch[bt.kind].as<double2>();
             fl.meta = h->d_meta.as<FarMeta>();
             fl.cmeta = h->d_cmeta.as<CrossMeta>();
             fl.cross_off = h->d_cross_off.as<int64_t>();
@@ -564,24 +585,37 @@ static void run_far(gaca_hmatrix *h, const double2 *dense) {
             fl.fib_off = h->d_fib_off.as<int64_t>();
             fl.overflow = d_over.as<int32_t>();
             fl.dense = dense;
-            launch_far_fp64(h->kernel, p->g, p->f, P, fl, st);
+            launch_far_fp64(h->kernel, p->g, p->f, P, fl, fs);
             GACA_HIP_CHECK(hipGetLastError());
-            GACA_HIP_CHECK(hipEventRecord(evs[2 * bi + 1], st));
-            ++bi;
+            GACA_HIP_CHECK(hipEventRecord(evs[2 * bi + 1], fs));
+        }
+        if (attempt == 0) main_work();   // near field on the context stream, concurrently
+        for (int k = 0; k < 3; ++k) {
+            hipEvent_t done = evs[2 * batches.size() + 1 + k];
+            GACA_HIP_CHECK(hipEventRecord(done, p->far_streams[k]));
+            GACA_HIP_CHECK(hipStreamWaitEvent(st, done, 0));
         }
         int32_t over = 0;
         unsigned long long ctrs[2];
         GACA_HIP_CHECK(hipMemcpyAsync(&over, d_over.ptr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         GACA_HIP_CHECK(hipMemcpyAsync(ctrs, d_ctr.ptr, sizeof(ctrs), hipMemcpyDeviceToHost, st));
         GACA_HIP_CHECK(hipStreamSynchronize(st));
-        double ms_k = 0.0;
-        for (size_t b2 = 0; b2 < batches.size(); ++b2) {
-            float ms = 0.0f;
-            GACA_HIP_CHECK(hipEventElapsedTime(&ms, evs[2 * b2], evs[2 * b2 + 1]));
-            ms_k += ms;
+        double by_kind[3] = {0, 0, 0}, span = 0.0;
+        int nl[3] = {0, 0, 0};
+        for (size_t bi = 0; bi < batches.size(); ++bi) {
+            float ms = 0.0f, ms_end = 0.0f;
+            GACA_HIP_CHECK(hipEventElapsedTime(&ms, evs[2 * bi], evs[2 * bi + 1]));
+            GACA_HIP_CHECK(hipEventElapsedTime(&ms_end, ev_start, evs[2 * bi + 1]));
+            by_kind[batches[bi].kind] += ms;
+            nl[batches[bi].kind] += 1;
+            span = std::max(span, (double)ms_end);
         }
         for (auto &e : evs) (void)hipEventDestroy(e);
-        h->st.ms_far_kernel = ms_k;
+        for (int k = 0; k < 3; ++k) {
+            h->st.ms_far_by_kind[k] = by_kind[k];
+            h->st.launches_by_kind[k] = nl[k];
+        }
+        h->st.ms_far_kernel = span;
         h->st.n_far_launches = (int32_t)batches.size();
         h->st.far_attempts = attempt + 1;
         if (!over) break;
@@ -643,9 +677,12 @@ static void fill_stats(gaca_hmatrix *h) {
     // accumulate 9 -> 105; the double layer adds (1 + s r), r^3 and the numerator: 113.
     const double f_eval = h->kernel == 0 ? 105.0 : 113.0;
     double macs = 0.0, evals = 0.0;
+    double kmacs[3] = {0, 0, 0}, kevals[3] = {0, 0, 0};
     for (int64_t b = 0; b < h->nfar; ++b) {
         const FarMeta &mt = h->meta[b];
         const double m = (double)p->part.far[b][1], n = (double)p->part.far[b][3];
+        const int kind = far_kind((int)m, (int)n, h->rcap);
+        const double macs0 = macs, evals0 = evals;
         evals += (double)(mt.rank + mt.zero_faces) * m * n * 6.0 + (double)mt.rank * L * 6.0;
         for (int c = 0; c < mt.rank; ++c) {
             const double rho = h->cmeta[b * h->rcap + c].rho;
@@ -655,7 +692,10 @@ static void fill_stats(gaca_hmatrix *h) {
             macs += m * n * (c + 1.0);               // <H_l, H_p>
             macs += 2.0 * L * c;                     // fibre correction and fibre dots
         }
+        kmacs[kind] += macs - macs0;
+        kevals[kind] += evals - evals0;
     }
+    for (int k = 0; k < 3; ++k) s.far_flops_by_kind[k] = kevals[k] * f_eval + 8.0 * kmacs[k];
     s.far_kernel_evals = evals;
     s.far_flops = evals * f_eval + 8.0 * macs;
     s.rank_mean = h->nfar ? rsum / h->nfar : 0.0;
@@ -673,6 +713,7 @@ gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out) 
     gaca_status rc = guarded([&] {
         REQUIRE(p && out, "null argument");
         REQUIRE(kernel == GACA_SLP || kernel == GACA_DLP, "bad kernel");
+        REQUIRE(!p->synthetic, "build needs a mesh problem");
         if (p->opt.precision != GACA_FP64)
             throw Error{GACA_ERR_UNSUPPORTED, "mixed precision not available in this build"};
         gaca_context *ctx = p->ctx;
@@ -687,35 +728,38 @@ gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out) 
         GACA_HIP_CHECK(hipEventCreate(&e0));
         GACA_HIP_CHECK(hipEventCreate(&e1));
         GACA_HIP_CHECK(hipEventCreate(&e2));
-        // near field
         h->d_near.alloc(ctx, std::max<int64_t>(1, p->near_elems) * sizeof(double2));
-        GACA_HIP_CHECK(hipEventRecord(e0, st));
-        for (int t = 0; t < 4; ++t)
-            launch_near(kernel, t, p->g, p->q, p->f, p->d_pairs[t].as<NearPair>(), p->npairs[t],
-                        p->d_nblocks.as<NearBlockDev>(), h->d_near.as<double2>(), nullptr, st);
-        GACA_HIP_CHECK(hipGetLastError());
-        GACA_HIP_CHECK(hipEventRecord(e1, st));
-        run_far(h.get(), nullptr);
-        GACA_HIP_CHECK(hipEventRecord(e2, st));
-        GACA_HIP_CHECK(hipEventSynchronize(e2));
-        float ms_near = 0, ms_far = 0;
-        GACA_HIP_CHECK(hipEventElapsedTime(&ms_near, e0, e1));
-        GACA_HIP_CHECK(hipEventElapsedTime(&ms_far, e1, e2));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        (void)hipEventDestroy(e2);
+        hipEvent_t ev[4];
+        for (auto &e : ev) GACA_HIP_CHECK(hipEventCreate(&e));
+        GACA_HIP_CHECK(hipEventRecord(ev[0], st));
+        auto near_work = [&] {
+            GACA_HIP_CHECK(hipEventRecord(ev[1], st));
+            for (int t = 0; t < 4; ++t)
+                launch_near(kernel, t, p->g, p->q, p->f, p->d_pairs[t].as<NearPair>(),
+                            p->npairs[t], p->d_nblocks.as<NearBlockDev>(),
+                            h->d_near.as<double2>(), nullptr, st);
+            GACA_HIP_CHECK(hipGetLastError());
+            GACA_HIP_CHECK(hipEventRecord(ev[2], st));
+        };
+        run_far(h.get(), nullptr, near_work);
+        GACA_HIP_CHECK(hipEventRecord(ev[3], st));
+        GACA_HIP_CHECK(hipEventSynchronize(ev[3]));
+        float ms_near = 0, ms_total = 0;
+        GACA_HIP_CHECK(hipEventElapsedTime(&ms_near, ev[1], ev[2]));
+        GACA_HIP_CHECK(hipEventElapsedTime(&ms_total, ev[0], ev[3]));
+        for (auto &e : ev) (void)hipEventDestroy(e);
         fill_stats(h.get());
         h->st.ms_near = ms_near;
         h->st.ms_near_kernel = ms_near;
         {
             const double le = p->f.L_eval;
             const double qp[4] = {6.0, 16.0, 64.0, kernel == 0 ? 3.0 * p->opt.n_duffy * p->opt.n_duffy : 0.0};
-            double ev = 0.0;
-            for (int t = 0; t < 4; ++t) ev += (double)p->npairs[t] * le * qp[t];
-            h->st.near_kernel_evals = ev;
+            double evn = 0.0;
+            for (int t = 0; t < 4; ++t) evn += (double)p->npairs[t] * le * qp[t];
+            h->st.near_kernel_evals = evn;
         }
-        h->st.ms_far = ms_far;
-        h->st.ms_total = ms_near + ms_far;
+        h->st.ms_far = h->st.ms_far_kernel;
+        h->st.ms_total = ms_total;
         capped = h->st.n_capped > 0;
         *out = h.release();
     });
@@ -982,7 +1026,7 @@ gaca_status gaca_compress_tensor(gaca_context *ctx, const void *dev_tensor, int6
         h->prec = GACA_FP64;
         h->rcap = std::max(1, std::min({L, p->opt.max_rank3d > 0 ? p->opt.max_rank3d : L, 256}));
         GACA_HIP_CHECK(hipSetDevice(ctx->device));
-        run_far(h.get(), reinterpret_cast<const double2 *>(dev_tensor));
+        run_far(h.get(), reinterpret_cast<const double2 *>(dev_tensor), [] {});
         fill_stats(h.get());
         capped = h->st.n_capped > 0;
         h->owned_problem = std::move(p);
