@@ -27,6 +27,50 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
 }
 __device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
 
+// float2 overloads (mixed-precision faces); cabs2 of a float2 is evaluated in FP64
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 c) {
+    return make_float2(c.x + a.x * b.x - a.y * b.y, c.y + a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cdiv(float2 a, float2 b) {
+    float d = b.x * b.x + b.y * b.y;
+    return make_float2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__device__ __forceinline__ double cabs2(float2 a) {
+    return (double)a.x * a.x + (double)a.y * a.y;
+}
+__device__ __forceinline__ double2 to_d2(double2 a) { return a; }
+__device__ __forceinline__ double2 to_d2(float2 a) { return make_double2(a.x, a.y); }
+template <class T>
+__device__ __forceinline__ T from_d2(double2 a);
+template <>
+__device__ __forceinline__ double2 from_d2<double2>(double2 a) { return a; }
+template <>
+__device__ __forceinline__ float2 from_d2<float2>(double2 a) {
+    return make_float2((float)a.x, (float)a.y);
+}
+template <class T>
+__device__ __forceinline__ T cast_c(double2 a) { return from_d2<T>(a); }
+template <class T>
+__device__ __forceinline__ T cast_c(float2 a);
+template <>
+__device__ __forceinline__ float2 cast_c<float2>(float2 a) { return a; }
+template <>
+__device__ __forceinline__ double2 cast_c<double2>(float2 a) { return to_d2(a); }
+template <class T>
+__device__ __forceinline__ T czero();
+template <>
+__device__ __forceinline__ double2 czero<double2>() { return make_double2(0.0, 0.0); }
+template <>
+__device__ __forceinline__ float2 czero<float2>() { return make_float2(0.0f, 0.0f); }
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -120,15 +164,15 @@ struct Red {
 
 // sum_{qq < q} a[qq * sa] * b[qq * sb] with eight independent partial sums, so that up to
 // sixteen loads are in flight per thread (the loops are latency-bound otherwise).
-__device__ __forceinline__ double2 dot_strided(const double2 *__restrict__ a, int64_t sa,
-                                               const double2 *__restrict__ b, int64_t sb,
-                                               int q0, int q1) {
-    double2 s[8];
+template <class T>
+__device__ __forceinline__ T dot_strided(const T *__restrict__ a, int64_t sa,
+                                         const T *__restrict__ b, int64_t sb, int q0, int q1) {
+    T s[8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) s[t] = make_double2(0.0, 0.0);
+    for (int t = 0; t < 8; ++t) s[t] = czero<T>();
     int qq = q0;
     for (; qq + 8 <= q1; qq += 8) {
-        double2 av[8], bv[8];
+        T av[8], bv[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             av[t] = a[(int64_t)(qq + t) * sa];

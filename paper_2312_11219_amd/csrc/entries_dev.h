@@ -64,6 +64,52 @@ __device__ __forceinline__ void entry_far6(const GeoDev &g, double x, double y, 
     ei = ai;
 }
 
+// Mixed-precision far entry divided by the block scale c = exp(-s d0), FP32 arithmetic:
+//   sum_q w_q exp(-s (r_q - d0)) / (4 pi r_q)         (SLP)
+//   num * sum_q w_q exp(-s (r_q - d0)) (1 + s r_q) / (4 pi r_q^3)   (DLP)
+// with D = x_sigma - y_tau (box centres, d0 = |D|), a = (x_i - x_sigma) - (y_q - y_tau) and
+// r - d0 = (2 a.D + a.a) / (r + d0), free of cancellation; the exponent stays within
+// +-Re(s) (radius_sigma + radius_tau) so FP32 neither over- nor underflows.
+template <int KERNEL>
+__device__ __forceinline__ float2 entry_far6_scaled(const GeoDev &g, float ax, float ay,
+                                                    float az, float Dx, float Dy, float Dz,
+                                                    float d0, float kappa, int64_t j, float cjx,
+                                                    float cjy, float cjz, float sre, float sim,
+                                                    float num) {
+    float ar = 0.0f, ai = 0.0f;
+    const int64_t M = g.M;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        const float bx = cjx + g.q6dx[p * M + j], by = cjy + g.q6dy[p * M + j],
+                    bz = cjz + g.q6dz[p * M + j];
+        const float qx = ax - bx, qy = ay - by, qz = az - bz;
+        const float vx = qx + Dx, vy = qy + Dy, vz = qz + Dz;
+        const float r = sqrtf(vx * vx + vy * vy + vz * vz);
+        const float dr =
+            (2.0f * (qx * Dx + qy * Dy + qz * Dz) + (qx * qx + qy * qy + qz * qz) + kappa) / (r + d0);
+        const float mag = expf(-sre * dr);
+        float sn, cs;
+        sincosf(sim * dr, &sn, &cs);
+        const float er = mag * cs, ei = -mag * sn;
+        const float w = g.q6wf[p * M + j];
+        if (KERNEL == 0) {
+            const float c = w / (12.566370614359172f * r);
+            ar += c * er;
+            ai += c * ei;
+        } else {
+            const float fr = 1.0f + sre * r, fi = sim * r;
+            const float c = w / (12.566370614359172f * r * r * r);
+            ar += c * (er * fr - ei * fi);
+            ai += c * (er * fi + ei * fr);
+        }
+    }
+    if (KERNEL == 1) {
+        ar *= num;
+        ai *= num;
+    }
+    return make_float2(ar, ai);
+}
+
 // Tier of a collocation pair inside a near block (host computes the same with the same
 // operations; the device version is used only by the test hook).
 __device__ __forceinline__ int tier_of(const GeoDev &g, int64_t i, int64_t j) {

@@ -1,5 +1,5 @@
-// FP64 3D-ACA of far (admissible) blocks, Algorithm 1 of the paper with ACA faces and the
-// dense-expansion pivot, one workgroup per block.
+// 3D-ACA of far (admissible) blocks: Algorithm 1 of the paper with ACA faces and the
+// dense-expansion pivot, one workgroup per block, FP64 or mixed precision.
 //
 // Per face l (frequency k_l):
 //   residual face R = ENTRY(:, :, k) - sum_{p < l} f_p[k] H_p   (previous dense faces H_p)
@@ -9,6 +9,13 @@
 //   eq. (norm): |C^(l)|^2 += 2 Re sum_p <H_l, H_p><f_l, f_p> + |H_l|^2 |f_l|^2
 //   stop when |H_l| |f_l| <= eps |C^(l)|, else k_{l+1} = tie-argmax over unused k of |f_l|.
 //
+// Mixed precision: faces, residuals and face factors are FP32 (float2) and every face is
+// kept divided by the block scale c_k = exp(-s_k d0) (d0 = distance of the cluster
+// centres), so neither the e^{-Re(s) r} decay nor the phase Im(s) r leaves the FP32 range;
+// the crosses stay exact because the scale moves into the FP64 fibres:
+//   C ~ sum_p H~_p (x) f_p,  R~(:,:,k) = E(:,:,k)/c_k - sum_p (f_p[k]/c_k) H~_p.
+// Fibres, Gram values, norms, stop tests and pivot comparisons are FP64.
+//
 // Two variants share the per-cross tail:
 //   small blocks (m n <= MNMAX, m, n <= SIDE): the residual face R and its approximation
 //     S = sum_q u_q w_q^T live in LDS and are updated in place by rank-1 updates, so the
@@ -17,6 +24,8 @@
 //   large blocks: R, H_l and the factor history in HBM scratch (L2 resident), row and
 //     column corrections split over thread groups with pipelined loads.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "device_util.h"
 #include "entries_dev.h"
@@ -29,10 +38,36 @@ constexpr int kMaxLds = 1024;
 constexpr int kMaxRcap = 256;
 constexpr int kMaxRcapSmall = 64;
 
+// Face entry at (il, jl, kk): FP64 value (FT = double2), the dense test tensor, or the
+// scaled FP32 value (FT = float2).
+template <int KERNEL, bool DENSE, class FT>
+__device__ __forceinline__ FT face_entry(const GeoDev &g, const FreqDev &f, const FarLaunch &fl,
+                                         const FarBlockDev &B, int il, int jl, int kk) {
+    if (DENSE) return from_d2<FT>(fl.dense[((int64_t)il * B.n + jl) * f.L + kk]);
+    const int64_t gi = B.r0 + il, gj = B.c0 + jl;
+    if constexpr (sizeof(FT) == sizeof(double2)) {
+        double er, ei;
+        entry_far6<KERNEL>(g, g.xx[gi], g.xy[gi], g.xz[gi], gj, f.re[kk], f.im[kk], er, ei);
+        return from_d2<FT>(make_double2(er, ei));
+    } else {
+        const double xi = g.xx[gi], yi = g.xy[gi], zi = g.xz[gi];
+        const float ax = (float)(xi - B.xs_adj[0]), ay = (float)(yi - B.xs_adj[1]),
+                    az = (float)(zi - B.xs_adj[2]);
+        const float cx = (float)(g.xx[gj] - B.yt[0]), cy = (float)(g.xy[gj] - B.yt[1]),
+                    cz = (float)(g.xz[gj] - B.yt[2]);
+        float num = 0.0f;
+        if (KERNEL == 1) num = (float)(g.nx[gj] * xi + g.ny[gj] * yi + g.nz[gj] * zi - g.d[gj]);
+        return entry_far6_scaled<KERNEL>(g, ax, ay, az, B.Dh[0], B.Dh[1], B.Dh[2], B.d0f,
+                                         B.kappa, gj, cx, cy, cz, (float)f.re[kk],
+                                         (float)f.im[kk], num);
+    }
+}
+
+// Unscaled FP64 entry (fibres are always FP64).
 template <int KERNEL, bool DENSE>
-__device__ __forceinline__ double2 far_entry(const GeoDev &g, const FreqDev &f,
-                                             const FarLaunch &fl, const FarBlockDev &B, int il,
-                                             int jl, int kk) {
+__device__ __forceinline__ double2 fibre_entry(const GeoDev &g, const FreqDev &f,
+                                               const FarLaunch &fl, const FarBlockDev &B,
+                                               int il, int jl, int kk) {
     if (DENSE) return fl.dense[((int64_t)il * B.n + jl) * f.L + kk];
     const int64_t gi = B.r0 + il, gj = B.c0 + jl;
     double er, ei;
@@ -40,54 +75,55 @@ __device__ __forceinline__ double2 far_entry(const GeoDev &g, const FreqDev &f,
     return make_double2(er, ei);
 }
 
+// 1 / c_k = exp(s_k d0) (mixed scaling), FP64.
+__device__ __forceinline__ double2 inv_scale(const FreqDev &f, const FarBlockDev &B, int k) {
+    const double d0 = (double)B.d0f;
+    const double mag = exp(f.re[k] * d0);
+    double sn, cs;
+    sincos(f.im[k] * d0, &sn, &cs);
+    return make_double2(mag * cs, mag * sn);
+}
+
 struct FarState {
     int ell = 0, k = 0, zero_run = 0, zero_faces = 0, capped = 0, sum_rho = 0, nused_k = 0;
     double norm2 = 0.0, scale = 0.0;
 };
 
-// Residual face into dst (LDS or HBM) and ||C^(l-1)(:,:,k)||^2.
-template <int KERNEL, int NT, bool DENSE>
+// Residual face into dst (LDS or HBM); returns ||C^(l-1)(:,:,k)||^2 in the face's frame
+// and writes the face's zero threshold factor (1 or 1/|c_k|) to *zscale.
+template <int KERNEL, int NT, bool DENSE, bool MIXED, class FT>
 __device__ double residual_face(const GeoDev &g, const FreqDev &f, const FarLaunch &fl,
-                                const FarBlockDev &B, const FarState &S, const double2 *faces,
-                                const double2 *fib, const double2 *G, int rcap, double2 *coef,
-                                double2 *dst, double2 *zero_dst, Red<NT> &red) {
+                                const FarBlockDev &B, const FarState &S, const FT *faces,
+                                const double2 *fib, const double2 *G, int rcap,
+                                double2 *coefd, FT *dst, FT *zero_dst, double *zscale,
+                                Red<NT> &red) {
     const int tid = threadIdx.x, L = f.L, n = B.n;
     const int64_t mn = (int64_t)B.m * n;
-    for (int p = tid; p < S.ell; p += NT) coef[p] = fib[(int64_t)p * L + S.k];
+    double2 isc = make_double2(1.0, 0.0);
+    if (MIXED) isc = inv_scale(f, B, S.k);
+    for (int p = tid; p < S.ell; p += NT) {
+        coefd[p] = cmul(fib[(int64_t)p * L + S.k], isc);
+    }
+    *zscale = MIXED ? sqrt(cabs2(isc)) : 1.0;
     __syncthreads();
     for (int64_t idx = tid; idx < mn; idx += NT) {
         const int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
-        double2 e = far_entry<KERNEL, DENSE>(g, f, fl, B, i, j, S.k);
-        for (int p = 0; p < S.ell; ++p) e = csub(e, cmul(coef[p], faces[(int64_t)p * mn + idx]));
+        FT e = face_entry<KERNEL, DENSE, FT>(g, f, fl, B, i, j, S.k);
+        for (int p = 0; p < S.ell; ++p)
+            e = csub(e, cmul(from_d2<FT>(coefd[p]), faces[(int64_t)p * mn + idx]));
         dst[idx] = e;
-        if (zero_dst) zero_dst[idx] = make_double2(0.0, 0.0);
+        if (zero_dst) zero_dst[idx] = czero<FT>();
     }
     double part = 0.0;
     for (int a = tid; a < S.ell; a += NT)
         for (int b = 0; b < S.ell; ++b)
-            part += cmul(cmulc(coef[a], coef[b]), G[(int64_t)a * rcap + b]).x;
+            part += cmul(cmulc(coefd[a], coefd[b]), G[(int64_t)a * rcap + b]).x;
     return fmax(red.sum(part), 0.0);
 }
 
-// Tie-argmax helpers over a contiguous array (LDS or HBM), optionally masked.
-template <int NT>
-__device__ int tie_argmax(const double2 *v, int len, double tie2, Red<NT> &red) {
-    double mx = 0.0;
-    for (int t = threadIdx.x; t < len; t += NT) mx = fmax(mx, cabs2(v[t]));
-    mx = red.max(mx);
-    const double thr = tie2 * mx;
-    int c = 0x7fffffff;
-    for (int t = threadIdx.x; t < len; t += NT)
-        if (cabs2(v[t]) >= thr) {
-            c = t;
-            break;
-        }
-    return red.imin(c);
-}
-
-template <int NT>
-__device__ int tie_argmax_unused(const double2 *v, const unsigned char *used, int len,
-                                 double tie2, Red<NT> &red) {
+template <int NT, class T>
+__device__ int tie_argmax_unused(const T *v, const unsigned char *used, int len, double tie2,
+                                 Red<NT> &red) {
     double mx = -1.0;
     for (int t = threadIdx.x; t < len; t += NT)
         if (!used[t]) mx = fmax(mx, cabs2(v[t]));
@@ -113,16 +149,15 @@ __device__ int first_unused(const unsigned char *used, int len, Red<NT> &red) {
     return red.imin(c);
 }
 
-// Everything after the face ACA: H_l (at Hl, any address space; it is also copied to the
-// HBM slot `slot` when Hl is in LDS) -> pivot, Gram, fibre, eq. (norm), output, stop test,
-// next frequency.  Returns true when the block is finished.
-template <int KERNEL, int NT, bool DENSE>
+// Everything after the face ACA, given H_l at Hl (LDS or HBM) and its copy in the HBM slot
+// of face l: pivot, Gram, fibre, eq. (norm), output, stop test, next frequency.
+// Returns true when the block is finished.
+template <int KERNEL, int NT, bool DENSE, bool MIXED, class FT>
 __device__ bool far_cross_tail(const GeoDev &g, const FreqDev &f, const AcaParams &P,
                                const FarLaunch &fl, const FarBlockDev &B, FarState &S,
-                               double2 *faces, const double2 *Ub, const double2 *Wb,
-                               double2 *fib, double2 *G, const double2 *Hl, int rho,
-                               double mxh, double h2, unsigned char *used_k, Red<NT> &red,
-                               unsigned long long *sh_off) {
+                               FT *faces, const FT *Ub, const FT *Wb, double2 *fib, double2 *G,
+                               const FT *Hl, int rho, double mxh, double h2,
+                               unsigned char *used_k, Red<NT> &red, unsigned long long *sh_off) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     constexpr int NW = NT / 64;
     const int m = B.m, n = B.n, L = f.L, rcap = P.rcap;
@@ -138,18 +173,18 @@ __device__ bool far_cross_tail(const GeoDev &g, const FreqDev &f, const AcaParam
             break;
         }
     const int pidx = red.imin(pc);
-    const double2 hpiv = Hl[pidx];
+    const double2 hpiv = to_d2(Hl[pidx]);
     const int ip = pidx / n, jpv = pidx - ip * n;
-    // Gram <H_l, H_p>, p < l: four p per wave iteration so their loads overlap
+    // Gram <H_l, H_p>, p < l, accumulated in FP64: four p per wave iteration
     for (int p0 = wave * 4; p0 < ell; p0 += NW * 4) {
         double gr[4] = {0, 0, 0, 0}, gi[4] = {0, 0, 0, 0};
         const int np = min(4, ell - p0);
         for (int64_t idx = lane; idx < mn; idx += 64) {
-            const double2 h = Hl[idx];
+            const double2 h = to_d2(Hl[idx]);
 #pragma unroll
             for (int t = 0; t < 4; ++t)
                 if (t < np) {
-                    double2 v = cmulc(h, faces[(int64_t)(p0 + t) * mn + idx]);
+                    double2 v = cmulc(h, to_d2(faces[(int64_t)(p0 + t) * mn + idx]));
                     gr[t] += v.x;
                     gi[t] += v.y;
                 }
@@ -166,11 +201,11 @@ __device__ bool far_cross_tail(const GeoDev &g, const FreqDev &f, const AcaParam
             }
     }
     if (tid == 0) G[(int64_t)ell * rcap + ell] = make_double2(h2, 0.0);
-    // frequency fibre through the pivot
+    // frequency fibre through the pivot (FP64)
     for (int kk = tid; kk < L; kk += NT) {
-        double2 e = far_entry<KERNEL, DENSE>(g, f, fl, B, ip, jpv, kk);
+        double2 e = fibre_entry<KERNEL, DENSE>(g, f, fl, B, ip, jpv, kk);
         for (int p = 0; p < ell; ++p)
-            e = csub(e, cmul(faces[(int64_t)p * mn + pidx], fib[(int64_t)p * L + kk]));
+            e = csub(e, cmul(to_d2(faces[(int64_t)p * mn + pidx]), fib[(int64_t)p * L + kk]));
         fib[(int64_t)ell * L + kk] = cdiv(e, hpiv);
     }
     __syncthreads();
@@ -208,10 +243,10 @@ __device__ bool far_cross_tail(const GeoDev &g, const FreqDev &f, const AcaParam
     }
     __syncthreads();
     const unsigned long long off = *sh_off;
+    FT *arena = reinterpret_cast<FT *>(fl.arena);
     if (off + nfac <= fl.arena_cap) {
-        for (int64_t t = tid; t < (int64_t)rho * m; t += NT) fl.arena[off + t] = Ub[t];
-        for (int64_t t = tid; t < (int64_t)rho * n; t += NT)
-            fl.arena[off + (int64_t)rho * m + t] = Wb[t];
+        for (int64_t t = tid; t < (int64_t)rho * m; t += NT) arena[off + t] = Ub[t];
+        for (int64_t t = tid; t < (int64_t)rho * n; t += NT) arena[off + (int64_t)rho * m + t] = Wb[t];
         if (tid == 0) fl.cross_off[(int64_t)B.out_idx * rcap + ell] = (int64_t)off;
     } else if (tid == 0) {
         *fl.overflow = 1;
@@ -266,26 +301,37 @@ __device__ void far_finalize(const FarLaunch &fl, const FarBlockDev &B, const Fa
     }
 }
 
+template <class FT>
+struct Scratch {
+    FT *faces, *Ub, *Wb;
+    double2 *fib, *G;
+    __device__ Scratch(const FarLaunch &fl, const FarBlockDev &B) {
+        char *base = reinterpret_cast<char *>(fl.scratch);
+        faces = reinterpret_cast<FT *>(base + B.face_off);
+        Ub = reinterpret_cast<FT *>(base + B.uw_off);
+        Wb = Ub + (int64_t)B.rho_max * B.m;
+        fib = reinterpret_cast<double2 *>(base + B.fib_off);
+        G = reinterpret_cast<double2 *>(base + B.gram_off);
+    }
+};
+
 // ---------------------------------------------------------------------------------------
 // Small blocks: R and S in LDS.
-template <int KERNEL, int NT, bool DENSE, int MNMAX, int SIDE>
+template <int KERNEL, int NT, bool DENSE, bool MIXED, int MNMAX, int SIDE>
 __global__ void __launch_bounds__(NT)
     far_small_kernel(GeoDev g, FreqDev f, AcaParams P, FarLaunch fl) {
+    using FT = typename std::conditional<MIXED, float2, double2>::type;
     const FarBlockDev B = fl.blocks[blockIdx.x];
     const int m = B.m, n = B.n, L = f.L;
     const int mn = m * n;
     const int tid = threadIdx.x;
-    double2 *faces = fl.scratch + B.face_off;
-    double2 *Ub = fl.scratch + B.uw_off;
-    double2 *Wb = Ub + (int64_t)B.rho_max * m;
-    double2 *fib = fl.scratch + B.fib_off;
-    double2 *G = fl.scratch + B.gram_off;
+    Scratch<FT> sc(fl, B);
 
-    __shared__ double2 Rs[MNMAX];
-    __shared__ double2 Ss[MNMAX];
-    __shared__ double2 ucol[SIDE];
-    __shared__ double2 wrow[SIDE];
-    __shared__ double2 coef[kMaxRcapSmall];
+    __shared__ FT Rs[MNMAX];
+    __shared__ FT Ss[MNMAX];
+    __shared__ FT ucol[SIDE];
+    __shared__ FT wrow[SIDE];
+    __shared__ double2 coefd[kMaxRcapSmall];
     __shared__ unsigned char used_row[SIDE];
     __shared__ unsigned char used_k[kMaxLds];
     __shared__ double redbuf[4 * (NT / 64) + 4];
@@ -297,9 +343,10 @@ __global__ void __launch_bounds__(NT)
     FarState S;
     __syncthreads();
     while (true) {
-        const double ref2 = residual_face<KERNEL, NT, DENSE>(g, f, fl, B, S, faces, fib, G, P.rcap,
-                                                             coef, Rs, Ss, red);
-        const double zero_tol = P.delta * S.scale;
+        double zs = 1.0;
+        const double ref2 = residual_face<KERNEL, NT, DENSE, MIXED, FT>(
+            g, f, fl, B, S, sc.faces, sc.fib, sc.G, P.rcap, coefd, Rs, Ss, &zs, red);
+        const double zero_tol = P.delta * S.scale * zs;
         for (int r = tid; r < m; r += NT) used_row[r] = 0;
         __syncthreads();
         int q = 0, i = 0, nused = 0;
@@ -325,27 +372,27 @@ __global__ void __launch_bounds__(NT)
                     break;
                 }
             const int jp = red.imin(jc);
-            const double2 piv = Rs[i * n + jp];
+            const FT piv = Rs[i * n + jp];
             double nw2 = 0.0, nu2 = 0.0;
             for (int j = tid; j < n; j += NT) {
-                const double2 w = cdiv(Rs[i * n + j], piv);
+                const FT w = cdiv(Rs[i * n + j], piv);
                 wrow[j] = w;
-                Wb[(int64_t)q * n + j] = w;
+                sc.Wb[(int64_t)q * n + j] = w;
                 nw2 += cabs2(w);
             }
             for (int r = tid; r < m; r += NT) {
-                const double2 u = Rs[r * n + jp];
+                const FT u = Rs[r * n + jp];
                 ucol[r] = u;
-                Ub[(int64_t)q * m + r] = u;
+                sc.Ub[(int64_t)q * m + r] = u;
                 nu2 += cabs2(u);
             }
             __syncthreads();
             double sp = 0.0;
             for (int idx = tid; idx < mn; idx += NT) {
                 const int r = idx / n, j = idx - r * n;
-                const double2 t = cmul(ucol[r], wrow[j]);
+                const FT t = cmul(ucol[r], wrow[j]);
                 Rs[idx] = csub(Rs[idx], t);
-                const double2 sv = cadd(Ss[idx], t);
+                const FT sv = cadd(Ss[idx], t);
                 Ss[idx] = sv;
                 sp += cabs2(sv);
             }
@@ -366,46 +413,44 @@ __global__ void __launch_bounds__(NT)
         }
         S.zero_run = 0;
         // H_l = S: store to its HBM slot (needed by later residual faces)
-        double2 *Hslot = faces + (int64_t)S.ell * mn;
+        FT *Hslot = sc.faces + (int64_t)S.ell * mn;
         double mxh = 0.0, h2 = 0.0;
         for (int idx = tid; idx < mn; idx += NT) {
-            const double2 h = Ss[idx];
+            const FT h = Ss[idx];
             Hslot[idx] = h;
             const double a2 = cabs2(h);
             mxh = fmax(mxh, a2);
             h2 += a2;
         }
         red.maxsum(mxh, h2);
-        if (far_cross_tail<KERNEL, NT, DENSE>(g, f, P, fl, B, S, faces, Ub, Wb, fib, G, Ss, rho,
-                                              mxh, h2, used_k, red, &sh_off))
+        if (far_cross_tail<KERNEL, NT, DENSE, MIXED, FT>(g, f, P, fl, B, S, sc.faces, sc.Ub, sc.Wb,
+                                                         sc.fib, sc.G, Ss, rho, mxh, h2, used_k,
+                                                         red, &sh_off))
             break;
     }
-    far_finalize<NT>(fl, B, S, fib, L, &sh_off);
+    far_finalize<NT>(fl, B, S, sc.fib, L, &sh_off);
 }
 
 // ---------------------------------------------------------------------------------------
 // Large blocks: R / H_l and the factor history in HBM scratch.
-template <int KERNEL, int NT, bool DENSE>
+template <int KERNEL, int NT, bool DENSE, bool MIXED>
 __global__ void __launch_bounds__(NT)
     far_large_kernel(GeoDev g, FreqDev f, AcaParams P, FarLaunch fl) {
+    using FT = typename std::conditional<MIXED, float2, double2>::type;
     const FarBlockDev B = fl.blocks[blockIdx.x];
     const int m = B.m, n = B.n, L = f.L;
     const int64_t mn = (int64_t)m * n;
     const int tid = threadIdx.x;
     constexpr int NW = NT / 64;
     const int wave = tid >> 6, lane = tid & 63;
-    double2 *faces = fl.scratch + B.face_off;
-    double2 *Ub = fl.scratch + B.uw_off;
-    double2 *Wb = Ub + (int64_t)B.rho_max * m;
-    double2 *fib = fl.scratch + B.fib_off;
-    double2 *G = fl.scratch + B.gram_off;
+    Scratch<FT> sc(fl, B);
+    FT *faces = sc.faces, *Ub = sc.Ub, *Wb = sc.Wb;
 
-    __shared__ double2 coef[kMaxRcap];
-    __shared__ double2 part[NT];       // split-K partial sums of row / column corrections
+    __shared__ double2 coefd[kMaxRcap];
+    __shared__ FT part[NT];       // split-K partial sums of row / column corrections
     __shared__ unsigned char used_row[kMaxRowsLds];
     __shared__ unsigned char used_k[kMaxLds];
     __shared__ double redbuf[4 * NW + 4];
-    __shared__ double wpart[4 * NW];
     __shared__ unsigned long long sh_off;
     Red<NT> red{redbuf};
     const double tie2 = (1.0 - P.tie) * (1.0 - P.tie);
@@ -414,37 +459,37 @@ __global__ void __launch_bounds__(NT)
     FarState S;
     __syncthreads();
     while (true) {
-        double2 *R = faces + (int64_t)S.ell * mn;
-        const double ref2 = residual_face<KERNEL, NT, DENSE>(g, f, fl, B, S, faces, fib, G, P.rcap,
-                                                             coef, R, nullptr, red);
-        const double zero_tol = P.delta * S.scale;
+        FT *R = faces + (int64_t)S.ell * mn;
+        double zs = 1.0;
+        const double ref2 = residual_face<KERNEL, NT, DENSE, MIXED, FT>(
+            g, f, fl, B, S, faces, sc.fib, sc.G, P.rcap, coefd, R, (FT *)nullptr, &zs, red);
+        const double zero_tol = P.delta * S.scale * zs;
         for (int r = tid; r < m; r += NT) used_row[r] = 0;
         __syncthreads();
         int q = 0, i = 0, nused = 0;
         double s2 = 0.0;
-        // split-K factors: nsplit thread groups per element when the vector is short
         const int splitw = max(1, NT / n), splitu = max(1, NT / m);
         while (true) {
-            double2 *Wq = Wb + (int64_t)q * n;
-            double2 *Uq = Ub + (int64_t)q * m;
+            FT *Wq = Wb + (int64_t)q * n;
+            FT *Uq = Ub + (int64_t)q * m;
             // row i of R - sum_{q'<q} u_q'[i] w_q'
             double mx = 0.0;
             if (splitw > 1) {
                 const int s = tid / n, j = tid - s * n;
                 if (s < splitw) {
                     const int q0 = (int)((int64_t)q * s / splitw), q1 = (int)((int64_t)q * (s + 1) / splitw);
-                    part[tid] = dot_strided(Ub + i, m, Wb + j, n, q0, q1);
+                    part[tid] = dot_strided<FT>(Ub + i, m, Wb + j, n, q0, q1);
                 }
                 __syncthreads();
                 if (tid < n) {
-                    double2 v = R[(int64_t)i * n + tid];
+                    FT v = R[(int64_t)i * n + tid];
                     for (int t = 0; t < splitw; ++t) v = csub(v, part[t * n + tid]);
                     Wq[tid] = v;
                     mx = cabs2(v);
                 }
             } else {
                 for (int j = tid; j < n; j += NT) {
-                    double2 v = csub(R[(int64_t)i * n + j], dot_strided(Ub + i, m, Wb + j, n, 0, q));
+                    FT v = csub(R[(int64_t)i * n + j], dot_strided<FT>(Ub + i, m, Wb + j, n, 0, q));
                     Wq[j] = v;
                     mx = fmax(mx, cabs2(v));
                 }
@@ -467,11 +512,11 @@ __global__ void __launch_bounds__(NT)
                     break;
                 }
             const int jp = red.imin(jc);
-            const double2 piv = Wq[jp];
+            const FT piv = Wq[jp];
             __syncthreads();
             double nw2 = 0.0, nu2 = 0.0;
             for (int j = tid; j < n; j += NT) {
-                double2 w = cdiv(Wq[j], piv);
+                FT w = cdiv(Wq[j], piv);
                 Wq[j] = w;
                 nw2 += cabs2(w);
             }
@@ -480,45 +525,45 @@ __global__ void __launch_bounds__(NT)
                 const int s = tid / m, r = tid - s * m;
                 if (s < splitu) {
                     const int q0 = (int)((int64_t)q * s / splitu), q1 = (int)((int64_t)q * (s + 1) / splitu);
-                    part[tid] = dot_strided(Wb + jp, n, Ub + r, m, q0, q1);
+                    part[tid] = dot_strided<FT>(Wb + jp, n, Ub + r, m, q0, q1);
                 }
                 __syncthreads();
                 if (tid < m) {
-                    double2 u = R[(int64_t)tid * n + jp];
+                    FT u = R[(int64_t)tid * n + jp];
                     for (int t = 0; t < splitu; ++t) u = csub(u, part[t * m + tid]);
                     Uq[tid] = u;
                     nu2 += cabs2(u);
                 }
             } else {
                 for (int r = tid; r < m; r += NT) {
-                    double2 u = csub(R[(int64_t)r * n + jp], dot_strided(Wb + jp, n, Ub + r, m, 0, q));
+                    FT u = csub(R[(int64_t)r * n + jp], dot_strided<FT>(Wb + jp, n, Ub + r, m, 0, q));
                     Uq[r] = u;
                     nu2 += cabs2(u);
                 }
             }
             __syncthreads();
-            // sum_{q'<q} Re(<u_q, u_q'> <w_q, w_q'>): four q' per wave iteration
+            // sum_{q'<q} Re(<u_q, u_q'> <w_q, w_q'>) in FP64: four q' per wave iteration
             double cr = 0.0;
             for (int q0 = wave * 4; q0 < q; q0 += NW * 4) {
                 const int nq = min(4, q - q0);
                 double ur[4] = {0, 0, 0, 0}, ui[4] = {0, 0, 0, 0}, wr[4] = {0, 0, 0, 0},
                        wi[4] = {0, 0, 0, 0};
                 for (int r = lane; r < m; r += 64) {
-                    const double2 u = Uq[r];
+                    const double2 u = to_d2(Uq[r]);
 #pragma unroll
                     for (int t = 0; t < 4; ++t)
                         if (t < nq) {
-                            double2 v = cmulc(u, Ub[(int64_t)(q0 + t) * m + r]);
+                            double2 v = cmulc(u, to_d2(Ub[(int64_t)(q0 + t) * m + r]));
                             ur[t] += v.x;
                             ui[t] += v.y;
                         }
                 }
                 for (int j = lane; j < n; j += 64) {
-                    const double2 w = Wq[j];
+                    const double2 w = to_d2(Wq[j]);
 #pragma unroll
                     for (int t = 0; t < 4; ++t)
                         if (t < nq) {
-                            double2 v = cmulc(w, Wb[(int64_t)(q0 + t) * n + j]);
+                            double2 v = cmulc(w, to_d2(Wb[(int64_t)(q0 + t) * n + j]));
                             wr[t] += v.x;
                             wi[t] += v.y;
                         }
@@ -553,42 +598,46 @@ __global__ void __launch_bounds__(NT)
         double mxh = 0.0, h2 = 0.0;
         for (int64_t idx = tid; idx < mn; idx += NT) {
             const int ii = (int)(idx / n), jj = (int)(idx - (int64_t)ii * n);
-            const double2 h = dot_strided(Ub + ii, m, Wb + jj, n, 0, rho);
+            const FT h = dot_strided<FT>(Ub + ii, m, Wb + jj, n, 0, rho);
             R[idx] = h;
             const double a2 = cabs2(h);
             mxh = fmax(mxh, a2);
             h2 += a2;
         }
         red.maxsum(mxh, h2);
-        if (far_cross_tail<KERNEL, NT, DENSE>(g, f, P, fl, B, S, faces, Ub, Wb, fib, G, R, rho,
-                                              mxh, h2, used_k, red, &sh_off))
+        if (far_cross_tail<KERNEL, NT, DENSE, MIXED, FT>(g, f, P, fl, B, S, faces, Ub, Wb, sc.fib,
+                                                         sc.G, R, rho, mxh, h2, used_k, red,
+                                                         &sh_off))
             break;
     }
-    far_finalize<NT>(fl, B, S, fib, L, &sh_off);
+    far_finalize<NT>(fl, B, S, sc.fib, L, &sh_off);
 }
 
 // kind: 0 small-A (m n <= 1024, sides <= 64), 1 small-B (m n <= 2304, sides <= 96),
 // 2 large.
-void launch_far_fp64(int kernel, const GeoDev &g, const FreqDev &f, const AcaParams &P,
-                     const FarLaunch &fl, hipStream_t st) {
-    if (fl.nb <= 0) return;
+template <int K, bool D, bool MX>
+static void far_dispatch(const GeoDev &g, const FreqDev &f, const AcaParams &P,
+                         const FarLaunch &fl, hipStream_t st) {
     dim3 grid(fl.nb);
-#define GACA_SMALLA(K, D) far_small_kernel<K, 64, D, 1024, 64><<<grid, 64, 0, st>>>(g, f, P, fl)
-#define GACA_SMALLB(K, D) far_small_kernel<K, 256, D, 2304, 96><<<grid, 256, 0, st>>>(g, f, P, fl)
-#define GACA_LARGE(K, D) far_large_kernel<K, 512, D><<<grid, 512, 0, st>>>(g, f, P, fl)
-#define GACA_KIND(K, D)                        \
-    do {                                       \
-        if (fl.kind == 0) GACA_SMALLA(K, D);   \
-        else if (fl.kind == 1) GACA_SMALLB(K, D); \
-        else GACA_LARGE(K, D);                 \
-    } while (0)
-    if (fl.dense) GACA_KIND(0, true);
-    else if (kernel == 0) GACA_KIND(0, false);
-    else GACA_KIND(1, false);
-#undef GACA_KIND
-#undef GACA_LARGE
-#undef GACA_SMALLB
-#undef GACA_SMALLA
+    if (fl.kind == 0)
+        far_small_kernel<K, 64, D, MX, 1024, 64><<<grid, 64, 0, st>>>(g, f, P, fl);
+    else if (fl.kind == 1)
+        far_small_kernel<K, 256, D, MX, 2304, 96><<<grid, 256, 0, st>>>(g, f, P, fl);
+    else
+        far_large_kernel<K, 512, D, MX><<<grid, 512, 0, st>>>(g, f, P, fl);
+}
+
+void launch_far(int kernel, const GeoDev &g, const FreqDev &f, const AcaParams &P,
+                const FarLaunch &fl, hipStream_t st) {
+    if (fl.nb <= 0) return;
+    if (fl.dense) far_dispatch<0, true, false>(g, f, P, fl, st);
+    else if (!fl.mixed) {
+        if (kernel == 0) far_dispatch<0, false, false>(g, f, P, fl, st);
+        else far_dispatch<1, false, false>(g, f, P, fl, st);
+    } else {
+        if (kernel == 0) far_dispatch<0, false, true>(g, f, P, fl, st);
+        else far_dispatch<1, false, true>(g, f, P, fl, st);
+    }
 }
 
 }  // namespace gaca

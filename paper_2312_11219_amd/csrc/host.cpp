@@ -279,6 +279,7 @@ void Partition::build(const ClusterTree &tree, double eta_) {
     far.clear();
     near.clear();
     far_level.clear();
+    far_nodes.clear();
     struct Pair {
         int32_t s, t;
     };
@@ -293,6 +294,7 @@ void Partition::build(const ClusterTree &tree, double eta_) {
         if (admissible(s, t, eta)) {
             far.push_back({s.start, s.size, t.start, t.size});
             far_level.push_back(std::max(s.level, t.level));
+            far_nodes.push_back({pr.s, pr.t});
         } else if (s.child[0] < 0 || t.child[0] < 0) {
             near.push_back({s.start, s.size, t.start, t.size});
         } else {

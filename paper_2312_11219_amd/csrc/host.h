@@ -46,6 +46,7 @@ struct Partition {
     double eta = 1.0;
     std::vector<std::array<int64_t, 4>> far, near;   // (row_start, m, col_start, n)
     std::vector<int32_t> far_level;
+    std::vector<std::array<int32_t, 2>> far_nodes;   // (row cluster, column cluster) node ids
     void build(const ClusterTree &tree, double eta);
 };
 

@@ -43,6 +43,9 @@ struct GeoDev {
     const double *nx, *ny, *nz, *d;                            // unit normal, plane offset n.a
     const double *h, *area;                                    // longest edge, area
     const double *q6x, *q6y, *q6z, *q6w;                       // [6][M] far-rule points/weights
+    // FP32 copies for the mixed-precision far field: far-rule points relative to the
+    // element centroid (small, so FP32 keeps them to ~1e-7 of the element size) and weights
+    const float *q6dx, *q6dy, *q6dz, *q6wf;                    // [6][M]
 };
 
 // Quadrature tables in device memory.
@@ -64,15 +67,21 @@ struct FreqDev {
 
 enum Tier : int32_t { TIER_FAR6 = 0, TIER_MID4 = 1, TIER_NEAR8 = 2, TIER_SELF = 3 };
 
-// One admissible block of a far-field launch.
+// One admissible block of a far-field launch.  Scratch offsets are in BYTES (faces and
+// factors are double2 in FP64, float2 in the mixed path; fibres and Gram always double2).
 struct FarBlockDev {
     int32_t r0, m, c0, n;      // tree-order ranges
-    int64_t face_off;          // scratch offset (complex elements) of the dense faces
-    int64_t uw_off;            // scratch offset of the current face's U (rho_max x m), W
-    int64_t fib_off;           // scratch offset of fibres (rcap x L complex)
-    int64_t gram_off;          // scratch offset of Gram matrix (rcap x rcap complex)
+    int64_t face_off;          // dense faces (rcap x m x n)
+    int64_t uw_off;            // current face's U (rho_max x m) then W (rho_max x n)
+    int64_t fib_off;           // fibres (rcap x L, double2)
+    int64_t gram_off;          // Gram matrix (rcap x rcap, double2)
     int32_t rho_max;           // face-rank cap for this block
     int32_t out_idx;           // global far-block index
+    // mixed-precision scaling, c_k = exp(-s_k d0f): with D = x_sigma - y_tau (box centres),
+    // Dh = fl32(D), d0f = fl32(|D|), kappa = |Dh|^2 - d0f^2 (exact in FP64) and
+    // xs_adj = x_sigma - (D - Dh) (so row offsets absorb the rounding of D)
+    double xs_adj[3], yt[3];
+    float Dh[3], d0f, kappa, pad_[3];
 };
 
 // Per-block result metadata written by the far-field kernel.

@@ -30,11 +30,12 @@ struct FarLaunch {
     const FarBlockDev *blocks;
     int32_t nb;
     int32_t kind;
-    double2 *scratch;
+    int32_t mixed;        // 1: FP32 faces/factors (float2), FP64 bookkeeping
+    void *scratch;        // byte offsets in FarBlockDev
     FarMeta *meta;
     CrossMeta *cmeta;     // [nfar][rcap]
-    int64_t *cross_off;   // [nfar][rcap] arena offsets of U (then W follows)
-    double2 *arena;
+    int64_t *cross_off;   // [nfar][rcap] arena offsets (elements) of U (then W follows)
+    void *arena;          // double2 (FP64) or float2 (mixed) factors
     unsigned long long *arena_ctr;
     unsigned long long arena_cap;
     double2 *fib_arena;
@@ -44,7 +45,7 @@ struct FarLaunch {
     int32_t *overflow;
     const double2 *dense; // synthetic-entry mode: dense tensor [m][n][L] (block 0 only)
 };
-void launch_far_fp64(int kernel, const GeoDev &g, const FreqDev &f, const AcaParams &P,
+void launch_far(int kernel, const GeoDev &g, const FreqDev &f, const AcaParams &P,
                      const FarLaunch &fl, hipStream_t st);
 
 // Test hook: entries of (row, col) tree positions with given tiers at frequency k.
@@ -62,7 +63,8 @@ struct ApplyDev {
     const FarMeta *meta;
     const CrossMeta *cmeta;
     const int64_t *cross_off;
-    const double2 *arena;
+    const void *arena;            // double2 (FP64 build) or float2 (mixed build) factors
+    int32_t fac_fp32;
     const int64_t *fib_off;
     const double2 *fib_arena;
     const NearBlockDev *nblocks;
@@ -75,8 +77,10 @@ struct ApplyDev {
     const int32_t *leaf_near_ptr, *leaf_near_idx;
     const int64_t *z_off;         // [nfar] offset of the block's z (sum_rho x nrhs) or v
 };
-void launch_apply_fp64(const ApplyDev &a, int mode, const double2 *X, double2 *Y,
-                       double2 *Xp, double2 *Yp, double2 *zbuf, double2 *tbuf,
-                       const int64_t *t_off, hipStream_t st);
+// x_fp32: X, Y and the workspace are complex64 (FP32 arithmetic), else complex128.
+// Workspace pointers are in elements of that type.
+void launch_apply(const ApplyDev &a, int mode, int x_fp32, const void *X, void *Y, void *Xp,
+                  void *Yp, void *zbuf, void *tbuf, const int64_t *t_off, void *ybuf,
+                  const int64_t *y_off, hipStream_t st);
 
 }  // namespace gaca

@@ -104,7 +104,7 @@ struct gaca_problem {
     int64_t M = 0;
     std::vector<int64_t> inv_perm;
     // device geometry / tables
-    DevBuf d_geo, d_quad, d_freq, d_perm;
+    DevBuf d_geo, d_geo32, d_quad, d_freq, d_perm;
     GeoDev g{};
     QuadDev q{};
     FreqDev f{};
@@ -132,6 +132,7 @@ struct gaca_hmatrix {
     gaca_precision prec = GACA_FP64;
     int32_t rcap = 0;
     int64_t nfar = 0;
+    double eps_aca_used = 0.0;
     DevBuf d_near, d_arena, d_fib, d_meta, d_cmeta, d_cross_off, d_fib_off, d_far4;
     std::vector<FarMeta> meta;
     std::vector<CrossMeta> cmeta;
@@ -139,8 +140,8 @@ struct gaca_hmatrix {
     gaca_stats st{};
     std::vector<int64_t> freq_hist;
     // apply workspace
-    int32_t ws_nrhs = -1, ws_mode = -1;
-    DevBuf d_xp, d_yp, d_z, d_t, d_toff, d_zoff;
+    int32_t ws_nrhs = -1, ws_mode = -1, ws_dtype = -1;
+    DevBuf d_xp, d_yp, d_z, d_t, d_toff, d_zoff, d_yb, d_yoff;
     DevBuf d_leaf_r0, d_leaf_m, d_lfp, d_lfi, d_lnp, d_lni;
     bool leaf_ready = false;
 };
@@ -260,6 +261,21 @@ static void upload_problem(gaca_problem *p) {
     g.q6y = G + (size_t)24 * M;
     g.q6z = G + (size_t)30 * M;
     g.q6w = G + (size_t)36 * M;
+    // FP32 far-rule data for the mixed path: points relative to the centroid, weights
+    std::vector<float> geo32((size_t)24 * M);
+    for (int64_t t = 0; t < M; ++t)
+        for (int q = 0; q < 6; ++q) {
+            for (int k = 0; k < 3; ++k)
+                geo32[(size_t)(6 * k + q) * M + t] =
+                    (float)(geo[(size_t)(18 + 6 * k + q) * M + t] - geo[(size_t)(9 + k) * M + t]);
+            geo32[(size_t)(18 + q) * M + t] = (float)geo[(size_t)(36 + q) * M + t];
+        }
+    p->d_geo32.upload(ctx, geo32);
+    const float *G32 = p->d_geo32.as<float>();
+    g.q6dx = G32;
+    g.q6dy = G32 + (size_t)6 * M;
+    g.q6dz = G32 + (size_t)12 * M;
+    g.q6wf = G32 + (size_t)18 * M;
     // quadrature tables
     Rule1D r4 = gauss_legendre01(4), r8 = gauss_legendre01(8),
            rd = gauss_legendre01(p->opt.n_duffy), rg = gauss_legendre01(p->opt.n_galerkin);
@@ -483,12 +499,34 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
         d.n = n;
         d.rho_max = rho_max;
         d.out_idx = (int32_t)b;
-        int64_t faces = (int64_t)rcap * m * n, uw = (int64_t)rho_max * (m + n),
-                fibs = (int64_t)rcap * L, gram = (int64_t)rcap * rcap;
+        // scratch layout in bytes: faces and current-face factors in the face type, fibres
+        // and Gram values in double2 (16-byte aligned)
+        const int64_t es = h->prec == GACA_MIXED ? 8 : 16;
+        auto al16 = [](int64_t v) { return (v + 15) & ~(int64_t)15; };
+        int64_t faces = al16((int64_t)rcap * m * n * es), uw = al16((int64_t)rho_max * (m + n) * es),
+                fibs = (int64_t)rcap * L * 16, gram = (int64_t)rcap * rcap * 16;
         d.face_off = 0;
         d.uw_off = faces;
         d.fib_off = faces + uw;
         d.gram_off = faces + uw + fibs;
+        if (!p->synthetic && p->part.far_nodes.size() == far.size()) {
+            // mixed scaling geometry from the cluster boxes
+            const auto &ns = p->tree.nodes[p->part.far_nodes[b][0]];
+            const auto &nt = p->tree.nodes[p->part.far_nodes[b][1]];
+            double D[3], dd = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const double xs = 0.5 * (ns.lo[k] + ns.hi[k]), yt = 0.5 * (nt.lo[k] + nt.hi[k]);
+                D[k] = xs - yt;
+                dd += D[k] * D[k];
+                d.yt[k] = yt;
+                d.Dh[k] = (float)D[k];
+                d.xs_adj[k] = xs - (D[k] - (double)d.Dh[k]);
+            }
+            d.d0f = (float)std::sqrt(dd);
+            double kap = -(double)d.d0f * (double)d.d0f;
+            for (int k = 0; k < 3; ++k) kap += (double)d.Dh[k] * (double)d.Dh[k];
+            d.kappa = (float)kap;
+        }
         items.push_back(Item{b, faces + uw + fibs + gram, far_kind(m, n, rcap), d});
         dense_far += (double)m * n * L;
     }
@@ -499,13 +537,20 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
     });
     uint64_t arena_cap = (uint64_t)std::max(1.0e6, 0.35 * dense_far);
     uint64_t fib_cap = (uint64_t)std::max<int64_t>(1 << 16, nfar * (int64_t)std::min(rcap, 24) * L);
-    const uint64_t budget_elems =
-        std::max<uint64_t>(p->opt.batch_bytes / sizeof(double2) / 3, 1 << 20);
+    const uint64_t budget_elems = std::max<uint64_t>(p->opt.batch_bytes / 3, 16ull << 20);  // bytes
     AcaParams P{};
     P.eps = p->opt.eps3d;
     P.eps_aca = p->opt.eps_aca;
     P.tie = p->opt.tie;
     P.delta = p->opt.delta_zero;
+    if (h->prec == GACA_MIXED) {
+        // FP32 faces: the face tolerance, tie window and zero threshold cannot go below
+        // what FP32 resolves
+        P.eps_aca = std::max(P.eps_aca, 2e-6);
+        P.tie = std::max(P.tie, 1e-4);
+        P.delta = std::max(P.delta, 1e-6);
+    }
+    h->eps_aca_used = P.eps_aca;
     P.rcap = rcap;
     P.kernel = h->kernel;
     DevBuf d_ctr, d_items, d_over;
@@ -533,7 +578,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
         s = e;
     }
     for (int k = 0; k < 3; ++k)
-        if (kind_max[k] > 0) d_scratch[k].alloc(ctx, kind_max[k] * sizeof(double2));
+        if (kind_max[k] > 0) d_scratch[k].alloc(ctx, kind_max[k]);
     if (!p->far_streams_ready) {
         for (int k = 0; k < 3; ++k) GACA_HIP_CHECK(hipStreamCreate(&p->far_streams[k]));
         p->far_streams_ready = true;
@@ -555,7 +600,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
     for (int attempt = 0; attempt < 6; ++attempt) {
         h->d_arena.release();
         h->d_fib.release();
-        h->d_arena.alloc(ctx, arena_cap * sizeof(double2));
+        h->d_arena.alloc(ctx, arena_cap * (h->prec == GACA_MIXED ? sizeof(float2) : sizeof(double2)));
         h->d_fib.alloc(ctx, fib_cap * sizeof(double2));
         GACA_HIP_CHECK(hipMemsetAsync(d_ctr.ptr, 0, 2 * sizeof(unsigned long long), st));
         GACA_HIP_CHECK(hipMemsetAsync(d_over.ptr, 0, sizeof(int32_t), st));
@@ -572,11 +617,12 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             fl.blocks = d_items.as<FarBlockDev>() + bt.first;
             fl.nb = (int32_t)(bt.last - bt.first);
             fl.kind = bt.kind;
-            fl.scratch = d_scratch[bt.kind].as<double2>();
+            fl.scratch = d_scratch[bt.kind].ptr;
+            fl.mixed = h->prec == GACA_MIXED ? 1 : 0;
             fl.meta = h->d_meta.as<FarMeta>();
             fl.cmeta = h->d_cmeta.as<CrossMeta>();
             fl.cross_off = h->d_cross_off.as<int64_t>();
-            fl.arena = h->d_arena.as<double2>();
+            fl.arena = h->d_arena.ptr;
             fl.arena_ctr = d_ctr.as<unsigned long long>();
             fl.arena_cap = arena_cap;
             fl.fib_arena = h->d_fib.as<double2>();
@@ -585,7 +631,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             fl.fib_off = h->d_fib_off.as<int64_t>();
             fl.overflow = d_over.as<int32_t>();
             fl.dense = dense;
-            launch_far_fp64(h->kernel, p->g, p->f, P, fl, fs);
+            launch_far(h->kernel, p->g, p->f, P, fl, fs);
             GACA_HIP_CHECK(hipGetLastError());
             GACA_HIP_CHECK(hipEventRecord(evs[2 * bi + 1], fs));
         }
@@ -714,8 +760,7 @@ gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out) 
         REQUIRE(p && out, "null argument");
         REQUIRE(kernel == GACA_SLP || kernel == GACA_DLP, "bad kernel");
         REQUIRE(!p->synthetic, "build needs a mesh problem");
-        if (p->opt.precision != GACA_FP64)
-            throw Error{GACA_ERR_UNSUPPORTED, "mixed precision not available in this build"};
+        REQUIRE(p->opt.precision == GACA_FP64 || p->opt.precision == GACA_MIXED, "bad precision");
         gaca_context *ctx = p->ctx;
         GACA_HIP_CHECK(hipSetDevice(ctx->device));
         auto h = std::make_unique<gaca_hmatrix>();
@@ -724,11 +769,10 @@ gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out) 
         h->prec = p->opt.precision;
         h->rcap = std::max(1, std::min({p->L, p->opt.max_rank3d > 0 ? p->opt.max_rank3d : p->L, 256}));
         const hipStream_t st = ctx->stream;
-        hipEvent_t e0, e1, e2;
-        GACA_HIP_CHECK(hipEventCreate(&e0));
-        GACA_HIP_CHECK(hipEventCreate(&e1));
-        GACA_HIP_CHECK(hipEventCreate(&e2));
-        h->d_near.alloc(ctx, std::max<int64_t>(1, p->near_elems) * sizeof(double2));
+        const bool mixed = h->prec == GACA_MIXED;
+        // near field: FP64 quadrature, stored FP64 or (mixed) FP32
+        h->d_near.alloc(ctx, std::max<int64_t>(1, p->near_elems) *
+                                 (mixed ? sizeof(float2) : sizeof(double2)));
         hipEvent_t ev[4];
         for (auto &e : ev) GACA_HIP_CHECK(hipEventCreate(&e));
         GACA_HIP_CHECK(hipEventRecord(ev[0], st));
@@ -737,7 +781,8 @@ gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out) 
             for (int t = 0; t < 4; ++t)
                 launch_near(kernel, t, p->g, p->q, p->f, p->d_pairs[t].as<NearPair>(),
                             p->npairs[t], p->d_nblocks.as<NearBlockDev>(),
-                            h->d_near.as<double2>(), nullptr, st);
+                            mixed ? nullptr : h->d_near.as<double2>(),
+                            mixed ? h->d_near.as<float2>() : nullptr, st);
             GACA_HIP_CHECK(hipGetLastError());
             GACA_HIP_CHECK(hipEventRecord(ev[2], st));
         };
@@ -825,13 +870,20 @@ gaca_status gaca_hmatrix_block_export(const gaca_hmatrix *h, int64_t idx, int32_
             if (pj) pj[c] = cm.pj;
             if (rho) rho[c] = cm.rho;
             if (off < 0) throw Error{GACA_ERR_STATE, "factors missing (arena overflow)"};
-            const double2 *A = h->d_arena.as<double2>();
-            if (U)
-                GACA_HIP_CHECK(hipMemcpy(U + 2 * uo, A + off, (size_t)cm.rho * m * sizeof(double2),
-                                         hipMemcpyDeviceToHost));
-            if (W)
-                GACA_HIP_CHECK(hipMemcpy(W + 2 * wo, A + off + (int64_t)cm.rho * m,
-                                         (size_t)cm.rho * n * sizeof(double2), hipMemcpyDeviceToHost));
+            // factors are double2 (FP64) or float2 (mixed); exported widened to C128
+            auto fetch = [&](double *dst, int64_t eoff, int64_t cnt) {
+                if (h->prec == GACA_MIXED) {
+                    std::vector<float> tmp(2 * cnt);
+                    GACA_HIP_CHECK(hipMemcpy(tmp.data(), h->d_arena.as<float2>() + eoff,
+                                             cnt * sizeof(float2), hipMemcpyDeviceToHost));
+                    for (int64_t t = 0; t < 2 * cnt; ++t) dst[t] = tmp[t];
+                } else {
+                    GACA_HIP_CHECK(hipMemcpy(dst, h->d_arena.as<double2>() + eoff,
+                                             cnt * sizeof(double2), hipMemcpyDeviceToHost));
+                }
+            };
+            if (U) fetch(U + 2 * uo, off, (int64_t)cm.rho * m);
+            if (W) fetch(W + 2 * wo, off + (int64_t)cm.rho * m, (int64_t)cm.rho * n);
             uo += (int64_t)cm.rho * m;
             wo += (int64_t)cm.rho * n;
         }
@@ -898,7 +950,7 @@ gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, cons
         REQUIRE(h && X && Y, "null argument");
         REQUIRE(nrhs >= 1, "nrhs must be >= 1");
         REQUIRE(mode == GACA_APPLY_SUM || mode == GACA_APPLY_PER_FREQ, "bad mode");
-        if (dtype != GACA_C128) throw Error{GACA_ERR_UNSUPPORTED, "C64 apply not available in this build"};
+        REQUIRE(dtype == GACA_C128 || dtype == GACA_C64, "bad dtype");
         REQUIRE(!h->p->synthetic, "apply needs a mesh problem");
         gaca_problem *p = h->p;
         gaca_context *ctx = p->ctx;
@@ -906,25 +958,32 @@ gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, cons
         prepare_leaves(h);
         const int L = p->L;
         const int64_t M = p->M;
-        if (h->ws_nrhs != nrhs || h->ws_mode != (int)mode) {
-            std::vector<int64_t> zoff(std::max<int64_t>(h->nfar, 1)), toff(std::max<int64_t>(h->nfar, 1));
-            int64_t zacc = 0, tacc = 0;
+        const size_t xs = dtype == GACA_C64 ? sizeof(float2) : sizeof(double2);
+        if (h->ws_nrhs != nrhs || h->ws_mode != (int)mode || h->ws_dtype != (int)dtype) {
+            std::vector<int64_t> zoff(std::max<int64_t>(h->nfar, 1)), toff(std::max<int64_t>(h->nfar, 1)),
+                yoff(std::max<int64_t>(h->nfar, 1));
+            int64_t zacc = 0, tacc = 0, yacc = 0;
             for (int64_t b = 0; b < h->nfar; ++b) {
                 zoff[b] = zacc;
                 toff[b] = tacc;
+                yoff[b] = yacc;
+                yacc += p->part.far[b][1] * (int64_t)nrhs;
                 const int64_t sr = h->meta[b].sum_rho;
                 zacc += mode == GACA_APPLY_SUM ? sr * nrhs : sr * (int64_t)L * nrhs;
                 tacc += mode == GACA_APPLY_SUM ? p->part.far[b][3] * (int64_t)nrhs : 0;
             }
             h->d_zoff.upload(ctx, zoff);
             h->d_toff.upload(ctx, toff);
-            h->d_z.alloc(ctx, std::max<int64_t>(zacc, 1) * sizeof(double2));
-            h->d_t.alloc(ctx, std::max<int64_t>(tacc, 1) * sizeof(double2));
-            h->d_xp.alloc(ctx, (size_t)L * M * nrhs * sizeof(double2));
+            h->d_yoff.upload(ctx, yoff);
+            h->d_yb.alloc(ctx, std::max<int64_t>(yacc, 1) * xs);
+            h->d_z.alloc(ctx, std::max<int64_t>(zacc, 1) * xs);
+            h->d_t.alloc(ctx, std::max<int64_t>(tacc, 1) * xs);
+            h->d_xp.alloc(ctx, (size_t)L * M * nrhs * xs);
             const int nl = mode == GACA_APPLY_SUM ? 1 : L;
-            h->d_yp.alloc(ctx, (size_t)nl * M * nrhs * sizeof(double2));
+            h->d_yp.alloc(ctx, (size_t)nl * M * nrhs * xs);
             h->ws_nrhs = nrhs;
             h->ws_mode = (int)mode;
+            h->ws_dtype = (int)dtype;
         }
         ApplyDev a{};
         a.L = L;
@@ -938,12 +997,13 @@ gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, cons
         a.meta = h->d_meta.as<FarMeta>();
         a.cmeta = h->d_cmeta.as<CrossMeta>();
         a.cross_off = h->d_cross_off.as<int64_t>();
-        a.arena = h->d_arena.as<double2>();
+        a.arena = h->d_arena.ptr;
+        a.fac_fp32 = h->prec == GACA_MIXED ? 1 : 0;
         a.fib_off = h->d_fib_off.as<int64_t>();
         a.fib_arena = h->d_fib.as<double2>();
         a.nblocks = p->d_nblocks.as<NearBlockDev>();
-        a.near64 = h->d_near.as<double2>();
-        a.near32 = nullptr;
+        a.near64 = h->prec == GACA_MIXED ? nullptr : h->d_near.as<double2>();
+        a.near32 = h->prec == GACA_MIXED ? h->d_near.as<float2>() : nullptr;
         a.nleaf = (int32_t)p->leaf_r0.size();
         a.leaf_r0 = h->d_leaf_r0.as<int32_t>();
         a.leaf_m = h->d_leaf_m.as<int32_t>();
@@ -952,10 +1012,9 @@ gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, cons
         a.leaf_near_ptr = h->d_lnp.as<int32_t>();
         a.leaf_near_idx = h->d_lni.as<int32_t>();
         a.z_off = h->d_zoff.as<int64_t>();
-        launch_apply_fp64(a, (int)mode, reinterpret_cast<const double2 *>(X),
-                          reinterpret_cast<double2 *>(Y), h->d_xp.as<double2>(),
-                          h->d_yp.as<double2>(), h->d_z.as<double2>(), h->d_t.as<double2>(),
-                          h->d_toff.as<int64_t>(), st);
+        launch_apply(a, (int)mode, dtype == GACA_C64 ? 1 : 0, X, Y, h->d_xp.ptr, h->d_yp.ptr,
+                     h->d_z.ptr, h->d_t.ptr, h->d_toff.as<int64_t>(), h->d_yb.ptr,
+                     h->d_yoff.as<int64_t>(), st);
         GACA_HIP_CHECK(hipGetLastError());
     });
 }
