@@ -15,6 +15,7 @@ from . import quadrature as Q
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "entries.c")
+_SRCS = [_SRC, os.path.join(_HERE, "galerkin.c")]
 _LIB = os.path.join(_HERE, "_oracle_entries.so")
 _lib = None
 
@@ -24,10 +25,11 @@ N_DUFFY = 16  # Duffy order per sub-triangle of the self term
 
 
 def build(force: bool = False) -> str:
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(s) for s in _SRCS)
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off",
-                               "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+                               "-shared", "-fPIC", "-o", tmp] + _SRCS + ["-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -45,6 +47,10 @@ def _load():
         lib.oracle_collocation_entries_order.argtypes = [
             ctypes.c_int, P, ctypes.c_int, P, P, ctypes.c_int64, P, P, ctypes.c_int, P, P]
         lib.oracle_collocation_entries_order.restype = None
+        lib.oracle_galerkin_entries.argtypes = [
+            P, P, ctypes.c_int, P, P, ctypes.c_int64, P, P, P, P, ctypes.c_int, P,
+            ctypes.c_int, P, ctypes.c_int, P, P, P]
+        lib.oracle_galerkin_entries.restype = None
         _lib = lib
     return _lib
 
