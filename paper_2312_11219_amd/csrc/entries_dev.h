@@ -124,7 +124,8 @@ template <int KERNEL, int NF>
 __device__ __forceinline__ void collapsed_acc(double x, double y, double z, const double *a,
                                              const double *b, const double *c, int n,
                                              const double *gtab, const FreqDev &f, int l0,
-                                             int nl, double *ar, double *ai) {
+                                             int nl, double *ar, double *ai,
+                                             double wscale = 1.0) {
     double e1x = b[0] - a[0], e1y = b[1] - a[1], e1z = b[2] - a[2];
     double e2x = c[0] - b[0], e2y = c[1] - b[1], e2z = c[2] - b[2];
     double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
@@ -137,7 +138,7 @@ __device__ __forceinline__ void collapsed_acc(double x, double y, double z, cons
             double px = a[0] + u * e1x + uv * e2x;
             double py = a[1] + u * e1y + uv * e2y;
             double pz = a[2] + u * e1z + uv * e2z;
-            double w = wu * wv * u * two_area;
+            double w = wu * wv * u * two_area * wscale;
             double r = dist3(x, y, z, px, py, pz);
 #pragma unroll
             for (int t = 0; t < NF; ++t)

@@ -29,6 +29,7 @@
 
 #include "device_util.h"
 #include "entries_dev.h"
+#include "galerkin_dev.h"
 #include "kernels.h"
 
 namespace gaca {
@@ -45,7 +46,20 @@ __device__ __forceinline__ FT face_entry(const GeoDev &g, const FreqDev &f, cons
                                          const FarBlockDev &B, int il, int jl, int kk) {
     if (DENSE) return from_d2<FT>(fl.dense[((int64_t)il * B.n + jl) * f.L + kk]);
     const int64_t gi = B.r0 + il, gj = B.c0 + jl;
-    if constexpr (sizeof(FT) == sizeof(double2)) {
+    if constexpr (KERNEL == 2) {
+        if constexpr (sizeof(FT) == sizeof(double2)) {
+            double er, ei;
+            entry_gal36(g, gi, gj, f.re[kk], f.im[kk], er, ei);
+            return from_d2<FT>(make_double2(er, ei));
+        } else {
+            const float cix = (float)(g.xx[gi] - B.xs_adj[0]), ciy = (float)(g.xy[gi] - B.xs_adj[1]),
+                        ciz = (float)(g.xz[gi] - B.xs_adj[2]);
+            const float cjx = (float)(g.xx[gj] - B.yt[0]), cjy = (float)(g.xy[gj] - B.yt[1]),
+                        cjz = (float)(g.xz[gj] - B.yt[2]);
+            return entry_gal36_scaled(g, cix, ciy, ciz, gi, B.Dh[0], B.Dh[1], B.Dh[2], B.d0f,
+                                      B.kappa, gj, cjx, cjy, cjz, (float)f.re[kk], (float)f.im[kk]);
+        }
+    } else if constexpr (sizeof(FT) == sizeof(double2)) {
         double er, ei;
         entry_far6<KERNEL>(g, g.xx[gi], g.xy[gi], g.xz[gi], gj, f.re[kk], f.im[kk], er, ei);
         return from_d2<FT>(make_double2(er, ei));
@@ -71,7 +85,10 @@ __device__ __forceinline__ double2 fibre_entry(const GeoDev &g, const FreqDev &f
     if (DENSE) return fl.dense[((int64_t)il * B.n + jl) * f.L + kk];
     const int64_t gi = B.r0 + il, gj = B.c0 + jl;
     double er, ei;
-    entry_far6<KERNEL>(g, g.xx[gi], g.xy[gi], g.xz[gi], gj, f.re[kk], f.im[kk], er, ei);
+    if constexpr (KERNEL == 2)
+        entry_gal36(g, gi, gj, f.re[kk], f.im[kk], er, ei);
+    else
+        entry_far6<KERNEL>(g, g.xx[gi], g.xy[gi], g.xz[gi], gj, f.re[kk], f.im[kk], er, ei);
     return make_double2(er, ei);
 }
 
@@ -633,10 +650,12 @@ void launch_far(int kernel, const GeoDev &g, const FreqDev &f, const AcaParams &
     if (fl.dense) far_dispatch<0, true, false>(g, f, P, fl, st);
     else if (!fl.mixed) {
         if (kernel == 0) far_dispatch<0, false, false>(g, f, P, fl, st);
-        else far_dispatch<1, false, false>(g, f, P, fl, st);
+        else if (kernel == 1) far_dispatch<1, false, false>(g, f, P, fl, st);
+        else far_dispatch<2, false, false>(g, f, P, fl, st);
     } else {
         if (kernel == 0) far_dispatch<0, false, true>(g, f, P, fl, st);
-        else far_dispatch<1, false, true>(g, f, P, fl, st);
+        else if (kernel == 1) far_dispatch<1, false, true>(g, f, P, fl, st);
+        else far_dispatch<2, false, true>(g, f, P, fl, st);
     }
 }
 

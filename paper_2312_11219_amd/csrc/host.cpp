@@ -314,4 +314,21 @@ int32_t collocation_tier(const HostMesh &mesh, int64_t i, int64_t j) {
     return q >= 4.0 ? TIER_FAR6 : (q >= 2.0 ? TIER_MID4 : TIER_NEAR8);
 }
 
+// Galerkin pair class in ORIGINAL ids: 5 coincident, 3 common edge, 4 common vertex, else
+// by q = |x_i - x_j| / max(h_i, h_j): 0 (q >= 4), 1 (2 <= q < 4), 2 (q < 2).
+int32_t galerkin_tier(const HostMesh &mesh, int64_t i, int64_t j) {
+    if (i == j) return 5;
+    int shared = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            if (mesh.tri[3 * i + a] == mesh.tri[3 * j + b]) ++shared;
+    if (shared >= 2) return 3;
+    if (shared == 1) return 4;
+    double dv[3];
+    for (int k = 0; k < 3; ++k) dv[k] = mesh.cen[3 * i + k] - mesh.cen[3 * j + k];
+    const double hm = mesh.hmax[i] > mesh.hmax[j] ? mesh.hmax[i] : mesh.hmax[j];
+    const double q = std::sqrt(dot3(dv, dv)) / hm;
+    return q >= 4.0 ? 0 : (q >= 2.0 ? 1 : 2);
+}
+
 }  // namespace gaca

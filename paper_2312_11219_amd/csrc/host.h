@@ -51,5 +51,8 @@ struct Partition {
 };
 
 int32_t collocation_tier(const HostMesh &mesh, int64_t i, int64_t j);
+int32_t galerkin_tier(const HostMesh &mesh, int64_t i, int64_t j);
+constexpr int kNumTiers = 6;          // pair classes (collocation uses the first 4)
+constexpr int kGalerkinNTheta = 16;   // Gauss points per angular sector (coincident pairs)
 
 }  // namespace gaca

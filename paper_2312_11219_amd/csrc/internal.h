@@ -56,6 +56,8 @@ struct QuadDev {
     const double *gd;    // nd x 2
     const double *gg;    // ng x 2 (Galerkin touching pairs)
     const double *r6;    // 6 x 4 (bary, weight)
+    int nth;
+    const double *gth;   // nth x 2 (Galerkin coincident pairs, per angular sector)
 };
 
 struct FreqDev {

@@ -21,7 +21,14 @@ void launch_near(int kernel, int tier, const GeoDev &g, const QuadDev &q, const 
                  const NearPair *pairs, int64_t npairs, const NearBlockDev *blocks,
                  double2 *out64, float2 *out32, hipStream_t st);
 
-// Far field FP64 3D-ACA: one workgroup per block of `blocks` (nb blocks).
+// Galerkin single layer near field, one pair class (GalTier) per launch.
+void launch_near_galerkin(int tier, const GeoDev &g, const QuadDev &q, const FreqDev &f,
+                          const NearPair *pairs, int64_t npairs, const NearBlockDev *blocks,
+                          double2 *out64, float2 *out32, hipStream_t st);
+
+// Kernel ids used by the far-field and eval launches: 0 collocation single layer,
+// 1 collocation double layer, 2 Galerkin single layer.
+// Far field 3D-ACA: one workgroup per block of `blocks` (nb blocks).
 // kind 0: small blocks (m n <= 1024, sides <= 64), residual face in LDS, 64 threads;
 // kind 1: small blocks (m n <= 2304, sides <= 96), residual face in LDS, 256 threads;
 // kind 2: large blocks, residual face and factors in HBM scratch, 512 threads.

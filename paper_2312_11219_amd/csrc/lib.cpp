@@ -112,8 +112,9 @@ struct gaca_problem {
     std::vector<NearBlockDev> nblocks;
     int64_t near_elems = 0;
     DevBuf d_nblocks;
-    DevBuf d_pairs[4];
-    int64_t npairs[4] = {0, 0, 0, 0};
+    DevBuf d_pairs[kNumTiers];
+    int64_t npairs[kNumTiers] = {0, 0, 0, 0, 0, 0};
+    int kid(gaca_kernel k) const { return scheme == GACA_GALERKIN_P0 ? 2 : (int)k; }
     // leaves for the apply
     std::vector<int32_t> leaf_r0, leaf_m;
     // far-field launch classes run concurrently on these streams (default priority)
@@ -288,7 +289,9 @@ static void upload_problem(gaca_problem *p) {
         }
         return off;
     };
-    size_t o4 = push_rule(r4), o8 = push_rule(r8), od = push_rule(rd), og = push_rule(rg);
+    Rule1D rth = gauss_legendre01(kGalerkinNTheta);
+    size_t o4 = push_rule(r4), o8 = push_rule(r8), od = push_rule(rd), og = push_rule(rg),
+           oth = push_rule(rth);
     size_t o6 = qt.size();
     for (int q = 0; q < 6; ++q) {
         qt.push_back(bary[q][0]);
@@ -307,12 +310,15 @@ static void upload_problem(gaca_problem *p) {
     p->q.gd = Q + od;
     p->q.gg = Q + og;
     p->q.r6 = Q + o6;
+    p->q.nth = kGalerkinNTheta;
+    p->q.gth = Q + oth;
     // permutation
     p->d_perm.upload(ctx, p->tree.perm);
     // near blocks and tier pair lists
     p->nblocks.clear();
     int64_t off = 0;
-    std::vector<NearPair> pairs[4];
+    std::vector<NearPair> pairs[kNumTiers];
+    const bool gal = p->scheme == GACA_GALERKIN_P0;
     for (size_t b = 0; b < p->part.near.size(); ++b) {
         const auto &nb = p->part.near[b];
         NearBlockDev d{(int32_t)nb[0], (int32_t)nb[1], (int32_t)nb[2], (int32_t)nb[3], off};
@@ -323,13 +329,14 @@ static void upload_problem(gaca_problem *p) {
         for (int64_t i = 0; i < nb[1]; ++i)
             for (int64_t j = 0; j < nb[3]; ++j) {
                 const int64_t oi = p->tree.perm[nb[0] + i], oj = p->tree.perm[nb[2] + j];
-                const int32_t tier = collocation_tier(p->mesh, oi, oj);
+                const int32_t tier =
+                    gal ? galerkin_tier(p->mesh, oi, oj) : collocation_tier(p->mesh, oi, oj);
                 pairs[tier].push_back(NearPair{(int32_t)b, (int16_t)i, (int16_t)j});
             }
     }
     p->near_elems = off;
     p->d_nblocks.upload(ctx, p->nblocks);
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < kNumTiers; ++t) {
         p->npairs[t] = (int64_t)pairs[t].size();
         p->d_pairs[t].upload(ctx, pairs[t]);
     }
@@ -377,8 +384,6 @@ gaca_status gaca_problem_create(gaca_context *ctx, const double *xyz, int64_t nv
         REQUIRE(s_re && s_im, "null frequencies");
         REQUIRE(L >= 1 && L <= 1024, "L must be in [1, 1024]");
         REQUIRE(scheme == GACA_COLLOCATION_P0 || scheme == GACA_GALERKIN_P0, "bad scheme");
-        if (scheme == GACA_GALERKIN_P0)
-            throw Error{GACA_ERR_UNSUPPORTED, "Galerkin scheme not available in this build"};
         auto p = std::make_unique<gaca_problem>();
         p->ctx = ctx;
         if (opt) p->opt = *opt;
@@ -721,7 +726,8 @@ static void fill_stats(gaca_hmatrix *h) {
     // (rsq + 2 Newton steps), exp 31 (reduction + degree-13 polynomial + scaling), sincos
     // 36 (Cody-Waite reduction + two polynomials), 1/(4 pi r) 8, weight and complex
     // accumulate 9 -> 105; the double layer adds (1 + s r), r^3 and the numerator: 113.
-    const double f_eval = h->kernel == 0 ? 105.0 : 113.0;
+    const double f_eval = h->kernel == 1 ? 113.0 : 105.0;
+    const double qpe = h->kernel == 2 ? 36.0 : 6.0;   // far-rule points per entry
     double macs = 0.0, evals = 0.0;
     double kmacs[3] = {0, 0, 0}, kevals[3] = {0, 0, 0};
     for (int64_t b = 0; b < h->nfar; ++b) {
@@ -729,7 +735,7 @@ static void fill_stats(gaca_hmatrix *h) {
         const double m = (double)p->part.far[b][1], n = (double)p->part.far[b][3];
         const int kind = far_kind((int)m, (int)n, h->rcap);
         const double macs0 = macs, evals0 = evals;
-        evals += (double)(mt.rank + mt.zero_faces) * m * n * 6.0 + (double)mt.rank * L * 6.0;
+        evals += (double)(mt.rank + mt.zero_faces) * m * n * qpe + (double)mt.rank * L * qpe;
         for (int c = 0; c < mt.rank; ++c) {
             const double rho = h->cmeta[b * h->rcap + c].rho;
             macs += c * m * n;                       // residual face: previous crosses
@@ -761,11 +767,13 @@ gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out) 
         REQUIRE(kernel == GACA_SLP || kernel == GACA_DLP, "bad kernel");
         REQUIRE(!p->synthetic, "build needs a mesh problem");
         REQUIRE(p->opt.precision == GACA_FP64 || p->opt.precision == GACA_MIXED, "bad precision");
+        if (p->scheme == GACA_GALERKIN_P0 && kernel != GACA_SLP)
+            throw Error{GACA_ERR_UNSUPPORTED, "Galerkin is available for the single layer only"};
         gaca_context *ctx = p->ctx;
         GACA_HIP_CHECK(hipSetDevice(ctx->device));
         auto h = std::make_unique<gaca_hmatrix>();
         h->p = p;
-        h->kernel = kernel;
+        h->kernel = p->kid(kernel);
         h->prec = p->opt.precision;
         h->rcap = std::max(1, std::min({p->L, p->opt.max_rank3d > 0 ? p->opt.max_rank3d : p->L, 256}));
         const hipStream_t st = ctx->stream;
@@ -778,11 +786,16 @@ gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out) 
         GACA_HIP_CHECK(hipEventRecord(ev[0], st));
         auto near_work = [&] {
             GACA_HIP_CHECK(hipEventRecord(ev[1], st));
-            for (int t = 0; t < 4; ++t)
-                launch_near(kernel, t, p->g, p->q, p->f, p->d_pairs[t].as<NearPair>(),
-                            p->npairs[t], p->d_nblocks.as<NearBlockDev>(),
-                            mixed ? nullptr : h->d_near.as<double2>(),
-                            mixed ? h->d_near.as<float2>() : nullptr, st);
+            double2 *n64 = mixed ? nullptr : h->d_near.as<double2>();
+            float2 *n32 = mixed ? h->d_near.as<float2>() : nullptr;
+            for (int t = 0; t < kNumTiers; ++t) {
+                if (p->scheme == GACA_GALERKIN_P0)
+                    launch_near_galerkin(t, p->g, p->q, p->f, p->d_pairs[t].as<NearPair>(),
+                                         p->npairs[t], p->d_nblocks.as<NearBlockDev>(), n64, n32, st);
+                else if (t < 4)
+                    launch_near(kernel, t, p->g, p->q, p->f, p->d_pairs[t].as<NearPair>(),
+                                p->npairs[t], p->d_nblocks.as<NearBlockDev>(), n64, n32, st);
+            }
             GACA_HIP_CHECK(hipGetLastError());
             GACA_HIP_CHECK(hipEventRecord(ev[2], st));
         };
@@ -798,9 +811,15 @@ gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out) 
         h->st.ms_near_kernel = ms_near;
         {
             const double le = p->f.L_eval;
-            const double qp[4] = {6.0, 16.0, 64.0, kernel == 0 ? 3.0 * p->opt.n_duffy * p->opt.n_duffy : 0.0};
+            const double ng2 = (double)p->opt.n_galerkin * p->opt.n_galerkin;
+            double qp[kNumTiers] = {6.0, 16.0, 64.0, kernel == 0 ? 3.0 * p->opt.n_duffy * p->opt.n_duffy : 0.0, 0.0, 0.0};
+            if (p->scheme == GACA_GALERKIN_P0) {
+                const double g6[kNumTiers] = {36.0, 256.0, 3.0 * ng2 * ng2, 3.0 * ng2 * ng2,
+                                              3.0 * ng2 * ng2, 6.0 * kGalerkinNTheta};
+                for (int t = 0; t < kNumTiers; ++t) qp[t] = g6[t];
+            }
             double evn = 0.0;
-            for (int t = 0; t < 4; ++t) evn += (double)p->npairs[t] * le * qp[t];
+            for (int t = 0; t < kNumTiers; ++t) evn += (double)p->npairs[t] * le * qp[t];
             h->st.near_kernel_evals = evn;
         }
         h->st.ms_far = h->st.ms_far_kernel;
@@ -1037,8 +1056,14 @@ gaca_status gaca_eval_entries(gaca_problem *p, gaca_kernel kernel, int64_t n, co
             rows[t] = (int32_t)p->inv_perm[i[t]];
             cols[t] = (int32_t)p->inv_perm[j[t]];
             ks[t] = k[t];
-            tiers[t] = far[t] ? (i[t] == j[t] ? TIER_SELF : TIER_FAR6) : collocation_tier(p->mesh, i[t], j[t]);
+            if (p->scheme == GACA_GALERKIN_P0)
+                tiers[t] = i[t] == j[t] ? 5 : (far[t] ? 0 : galerkin_tier(p->mesh, i[t], j[t]));
+            else
+                tiers[t] = far[t] ? (i[t] == j[t] ? TIER_SELF : TIER_FAR6)
+                                  : collocation_tier(p->mesh, i[t], j[t]);
         }
+        if (p->scheme == GACA_GALERKIN_P0 && kernel != GACA_SLP)
+            throw Error{GACA_ERR_UNSUPPORTED, "Galerkin is available for the single layer only"};
         gaca_context *ctx = p->ctx;
         DevBuf dr, dc, dk, dt, dout;
         dr.upload(ctx, rows);
@@ -1046,7 +1071,7 @@ gaca_status gaca_eval_entries(gaca_problem *p, gaca_kernel kernel, int64_t n, co
         dk.upload(ctx, ks);
         dt.upload(ctx, tiers);
         dout.alloc(ctx, n * sizeof(double2));
-        launch_eval(kernel, p->g, p->q, p->f, n, dr.as<int32_t>(), dc.as<int32_t>(), dk.as<int32_t>(),
+        launch_eval(p->kid(kernel), p->g, p->q, p->f, n, dr.as<int32_t>(), dc.as<int32_t>(), dk.as<int32_t>(),
                     dt.as<int32_t>(), dout.as<double2>(), ctx->stream);
         GACA_HIP_CHECK(hipGetLastError());
         GACA_HIP_CHECK(hipStreamSynchronize(ctx->stream));

@@ -3,9 +3,77 @@
 
 #include "device_util.h"
 #include "entries_dev.h"
+#include "galerkin_dev.h"
 #include "kernels.h"
 
 namespace gaca {
+
+// Galerkin near field (single layer): one thread per (pair, NF frequencies), one class
+// per launch.
+template <int TIER, int NF>
+__global__ void __launch_bounds__(256)
+    near_gal_kernel(GeoDev g, QuadDev q, FreqDev f, const NearPair *__restrict__ pairs,
+                    int64_t npairs, const NearBlockDev *__restrict__ blocks, double2 *out64,
+                    float2 *out32) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npairs) return;
+    const int l0 = blockIdx.y * NF;
+    const int nl = min(NF, f.L_eval - l0);
+    NearPair pr = pairs[p];
+    NearBlockDev B = blocks[pr.blk];
+    const int64_t i = B.r0 + pr.i, j = B.c0 + pr.j;
+    double ar[NF], ai[NF];
+    gal_near_entry<NF>(g, q, f, i, j, TIER, l0, nl, ar, ai);
+    const int64_t base = B.off + (int64_t)pr.i * f.L * B.n + pr.j;
+#pragma unroll
+    for (int t = 0; t < NF; ++t) {
+        if (t < nl) {
+            const int l = l0 + t;
+            if (out64) {
+                out64[base + (int64_t)l * B.n] = make_double2(ar[t], ai[t]);
+                if (f.mirror && f.L - 1 - l != l)
+                    out64[base + (int64_t)(f.L - 1 - l) * B.n] = make_double2(ar[t], -ai[t]);
+            } else {
+                out32[base + (int64_t)l * B.n] = make_float2((float)ar[t], (float)ai[t]);
+                if (f.mirror && f.L - 1 - l != l)
+                    out32[base + (int64_t)(f.L - 1 - l) * B.n] =
+                        make_float2((float)ar[t], (float)-ai[t]);
+            }
+        }
+    }
+}
+
+template <int T, int NF>
+static void near_gal_launch(const GeoDev &g, const QuadDev &q, const FreqDev &f,
+                            const NearPair *pairs, int64_t npairs, const NearBlockDev *blocks,
+                            double2 *o64, float2 *o32, hipStream_t st) {
+    dim3 grid((unsigned)((npairs + 255) / 256), (unsigned)((f.L_eval + NF - 1) / NF));
+    near_gal_kernel<T, NF><<<grid, 256, 0, st>>>(g, q, f, pairs, npairs, blocks, o64, o32);
+}
+
+void launch_near_galerkin(int tier, const GeoDev &g, const QuadDev &q, const FreqDev &f,
+                          const NearPair *pairs, int64_t npairs, const NearBlockDev *blocks,
+                          double2 *out64, float2 *out32, hipStream_t st) {
+    if (npairs <= 0) return;
+    switch (tier) {
+        case GT_FAR36: near_gal_launch<GT_FAR36, 8>(g, q, f, pairs, npairs, blocks, out64, out32, st); break;
+        case GT_MID: near_gal_launch<GT_MID, 4>(g, q, f, pairs, npairs, blocks, out64, out32, st); break;
+        case GT_NEAR: near_gal_launch<GT_NEAR, 2>(g, q, f, pairs, npairs, blocks, out64, out32, st); break;
+        case GT_EDGE: near_gal_launch<GT_EDGE, 2>(g, q, f, pairs, npairs, blocks, out64, out32, st); break;
+        case GT_VERTEX: near_gal_launch<GT_VERTEX, 2>(g, q, f, pairs, npairs, blocks, out64, out32, st); break;
+        default: near_gal_launch<GT_COINC, 4>(g, q, f, pairs, npairs, blocks, out64, out32, st); break;
+    }
+}
+
+__global__ void eval_gal_kernel(GeoDev g, QuadDev q, FreqDev f, int64_t n, const int32_t *rows,
+                                const int32_t *cols, const int32_t *ks, const int32_t *tiers,
+                                double2 *out) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    double ar[1], ai[1];
+    gal_near_entry<1>(g, q, f, rows[p], cols[p], tiers[p], ks[p], 1, ar, ai);
+    out[p] = make_double2(ar[0], ai[0]);
+}
 
 // One thread per (pair, chunk of NF frequencies) of one quadrature tier: every wave runs
 // the same quadrature, so there is no divergence between tiers.  With mirrored
@@ -94,8 +162,10 @@ void launch_eval(int kernel, const GeoDev &g, const QuadDev &q, const FreqDev &f
     unsigned nb = (unsigned)((n + 127) / 128);
     if (kernel == 0)
         eval_kernel<0><<<nb, 128, 0, st>>>(g, q, f, n, rows, cols, ks, tiers, out);
-    else
+    else if (kernel == 1)
         eval_kernel<1><<<nb, 128, 0, st>>>(g, q, f, n, rows, cols, ks, tiers, out);
+    else
+        eval_gal_kernel<<<nb, 128, 0, st>>>(g, q, f, n, rows, cols, ks, tiers, out);
 }
 
 }  // namespace gaca

@@ -14,13 +14,20 @@ def log(*args):
 
 # Small far-field workload the oracle finishes in seconds: 768-triangle cube, leaf 16.
 SMALL = dict(name="cube768", mesh=("cube", 8), L=16, c0=10.0, rho=0.9, leaf=16, eta=1.0,
-             eps=1e-4)
+             eps=1e-4, scheme="collocation")
+SMALL_GAL = dict(name="lshape768", mesh=("lshape", 4), L=16, c0=10.0, rho=0.9, leaf=16,
+                 eta=1.0, eps=1e-4, scheme="galerkin")
 
 
 def workload(name):
     if name == "cube768":
         cfg = dict(SMALL)
         xyz, tri = cube_mesh(8)
+    elif name == "lshape768":
+        # small Galerkin workload: reentrant-corner cube, 1/8 grid (768 triangles)
+        cfg = dict(SMALL_GAL)
+        from inputs import lshape_mesh
+        xyz, tri = lshape_mesh(4)
     else:
         cfg = get_config(name)
         xyz, tri = mesh_for_config(name)
@@ -40,7 +47,14 @@ def gpu_problem(name, **kw):
     cfg, xyz, tri, s = workload(name)
     opts = dict(leaf_size=cfg["leaf"], eta=cfg["eta"], eps3d=cfg["eps"], eps_aca=cfg["eps_aca"])
     opts.update(kw)
-    return cfg, gaca.Problem(context(), xyz, tri, s, **opts), (xyz, tri, s)
+    scheme = cfg.get("scheme", "collocation")
+    return cfg, gaca.Problem(context(), xyz, tri, s, scheme=scheme, **opts), (xyz, tri, s)
+
+
+def oracle_problem(name):
+    from oracle.hmatrix import Problem
+    cfg, xyz, tri, s = workload(name)
+    return cfg, Problem(xyz, tri, s, cfg["leaf"], cfg["eta"], scheme=cfg.get("scheme", "collocation"))
 
 
 def rel_fro(a, b):
