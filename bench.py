@@ -34,6 +34,7 @@ def parse():
     ap.add_argument("--config", default="C2")
     ap.add_argument("--nrhs", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     return ap.parse_args()
 
@@ -166,9 +167,55 @@ def main():
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
                      "launches_per_step": far_launches},
     }
+    if not args.no_mixed:
+        out["mixed"] = mixed_leg(gaca, ctx, xyz, tri, s, cfg, X, kernels, stream, prob, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, xyz, tri, s, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def mixed_leg(gaca, ctx, xyz, tri, s, cfg, X, kernels, stream, prob64, args):
+    """The same step with the mixed-precision build (FP32 far-field faces and factors with
+    the per-(block, frequency) scale, FP64 fibres/norms; near field stored FP32) and the
+    relative difference of its apply from the FP64 build's apply (same X)."""
+    import numpy as np
+    import torch
+    pm = gaca.Problem(ctx, xyz, tri, s, leaf_size=cfg["leaf"], eta=cfg["eta"],
+                      eps3d=cfg["eps"], eps_aca=cfg["eps_aca"], precision="mixed")
+    X32 = X.to(torch.complex64)
+
+    def step():
+        res = []
+        for k in kernels:
+            h = pm.build(k)
+            y = h.apply(X32, stream=stream)
+            res.append((h.stats(), y))
+            del h
+        return res
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [step() for _ in range(max(1, args.steps))]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    last = runs[-1]
+    entries = sum(st["entries_near"] + st["entries_face"] + st["entries_fibre"] for st, _ in last)
+    errs = {}
+    for k, (st, y) in zip(kernels, last):
+        h64 = prob64.build(k)
+        y64 = h64.apply(X, stream=stream)
+        torch.cuda.synchronize()
+        d = (y.to(torch.complex128) - y64).norm().item() / y64.norm().item()
+        errs[k] = d
+        del h64
+    return {"value": entries * len(runs) / el, "unit": "entries/s",
+            "ms_per_step": el / len(runs) * 1e3,
+            "build_ms": {k: st["ms_total"] for k, (st, _) in zip(kernels, last)},
+            "far_kernel_ms": float(np.mean([sum(st["ms_far_kernel"] for st, _ in r) for r in runs])),
+            "apply_rel_diff_vs_fp64": errs,
+            "ranks": {k: [st["rank_min"], st["rank_max"], round(st["rank_mean"], 2)]
+                      for k, (st, _) in zip(kernels, last)}}
 
 
 if __name__ == "__main__":

@@ -459,6 +459,17 @@ static int far_kind(int m, int n, int rcap) {
     return 2;
 }
 
+// Replace buf by a copy holding its first `used` bytes when that frees a useful amount.
+static void compact(gaca_context *ctx, DevBuf &buf, size_t used, hipStream_t st) {
+    if (used == 0 || buf.bytes < (64u << 20) || used > buf.bytes / 4 * 3) return;
+    DevBuf tight;
+    tight.alloc(ctx, used);
+    GACA_HIP_CHECK(hipMemcpyAsync(tight.ptr, buf.ptr, used, hipMemcpyDeviceToDevice, st));
+    GACA_HIP_CHECK(hipStreamSynchronize(st));
+    std::swap(buf.ptr, tight.ptr);
+    std::swap(buf.bytes, tight.bytes);
+}
+
 static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<void()> &main_work) {
     gaca_problem *p = h->p;
     gaca_context *ctx = p->ctx;
@@ -491,7 +502,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
         FarBlockDev d;
     };
     std::vector<Item> items;
-    double dense_far = 0.0;
+    double factor_guess = 0.0;
     for (int64_t b = 0; b < nfar; ++b) {
         const int m = (int)far[b][1], n = (int)far[b][3];
         if (m > 8192) throw Error{GACA_ERR_UNSUPPORTED, "far block with more than 8192 rows"};
@@ -533,15 +544,25 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             d.kappa = (float)kap;
         }
         items.push_back(Item{b, faces + uw + fibs + gram, far_kind(m, n, rcap), d});
-        dense_far += (double)m * n * L;
+        // first guess of the factor storage: 16 crosses of face rank 16, never more than
+        // the dense block (the build retries with a larger arena when the guess is short)
+        factor_guess += std::min((double)m * n * L,
+                                 (double)std::min(rcap, 16) * std::min(rho_max, 16) * (m + n));
     }
     // large blocks first, biggest first inside each class
     std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
         if (a.kind != b.kind) return a.kind > b.kind;
         return a.bytes > b.bytes;
     });
-    uint64_t arena_cap = (uint64_t)std::max(1.0e6, 0.35 * dense_far);
-    uint64_t fib_cap = (uint64_t)std::max<int64_t>(1 << 16, nfar * (int64_t)std::min(rcap, 24) * L);
+    const size_t fac_bytes = h->prec == GACA_MIXED ? sizeof(float2) : sizeof(double2);
+    uint64_t arena_cap = (uint64_t)std::max(1.0e6, factor_guess);
+    uint64_t fib_cap = (uint64_t)std::max<int64_t>(1 << 16, nfar * (int64_t)std::min(rcap, 16) * L);
+    {
+        // keep the first guess within a third of the free device memory
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0)
+            arena_cap = std::min<uint64_t>(arena_cap, std::max<uint64_t>(1 << 20, free_b / 3 / fac_bytes));
+    }
     const uint64_t budget_elems = std::max<uint64_t>(p->opt.batch_bytes / 3, 16ull << 20);  // bytes
     AcaParams P{};
     P.eps = p->opt.eps3d;
@@ -605,7 +626,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
     for (int attempt = 0; attempt < 6; ++attempt) {
         h->d_arena.release();
         h->d_fib.release();
-        h->d_arena.alloc(ctx, arena_cap * (h->prec == GACA_MIXED ? sizeof(float2) : sizeof(double2)));
+        h->d_arena.alloc(ctx, arena_cap * fac_bytes);
         h->d_fib.alloc(ctx, fib_cap * sizeof(double2));
         GACA_HIP_CHECK(hipMemsetAsync(d_ctr.ptr, 0, 2 * sizeof(unsigned long long), st));
         GACA_HIP_CHECK(hipMemsetAsync(d_over.ptr, 0, sizeof(int32_t), st));
@@ -669,7 +690,12 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
         h->st.ms_far_kernel = span;
         h->st.n_far_launches = (int32_t)batches.size();
         h->st.far_attempts = attempt + 1;
-        if (!over) break;
+        if (!over) {
+            // shrink both arenas to what the build used (offsets are relative to the base)
+            compact(ctx, h->d_arena, ctrs[0] * fac_bytes, st);
+            compact(ctx, h->d_fib, ctrs[1] * sizeof(double2), st);
+            break;
+        }
         arena_cap = std::max<uint64_t>(arena_cap * 2, ctrs[0] + 1024);
         fib_cap = std::max<uint64_t>(fib_cap * 2, ctrs[1] + 1024);
         if (attempt == 5) throw Error{GACA_ERR_OOM, "factor arena overflow"};
