@@ -24,6 +24,11 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
+PHASES = ["face", "aca", "expand", "tail"]
+PHASE_KERNELS = ["far_face_kernel (residual faces, FP64 VALU)",
+                 "far_aca_small_kernel / far_aca_large_kernel (face ACA, 3 classes concurrent)",
+                 "far_expand_kernel (dense H_l, Gram partials)",
+                 "far_tail_kernel (fibre, norm, stop test)"]
 
 
 def parse():
@@ -129,12 +134,16 @@ def main():
     last = all_stats[-1]
     entries_step = sum(st["entries_near"] + st["entries_face"] + st["entries_fibre"] for st in last)
     value = entries_step * args.steps / elapsed
-    # dominant kernel: the far-field 3D-ACA kernel (HIP events around each launch)
+    # dominant kernel: the far-field phase with the largest device time over the step (each
+    # phase's launches are timed with HIP events on the stream they run on)
+    phase_ms = np.mean([[sum(st["ms_far_phase"][k] for st in stp) for k in range(4)]
+                        for stp in all_stats], axis=0)
+    phase_flops = [sum(st["far_flops_phase"][k] for st in last) for k in range(4)]
+    phase_launch = [sum(st["launches_phase"][k] for st in last) for k in range(4)]
+    dom = int(np.argmax(phase_ms))
     far_ms = np.mean([sum(st["ms_far_kernel"] for st in stp) for stp in all_stats])
-    far_launches = sum(st["n_far_launches"] for st in last)
-    far_flops = sum(st["far_flops"] for st in last)
     near_ms = np.mean([sum(st["ms_near_kernel"] for st in stp) for stp in all_stats])
-    achieved = far_flops / (far_ms * 1e-3) / 1e12
+    achieved = phase_flops[dom] / (phase_ms[dom] * 1e-3) / 1e12
     out = {
         "metric": "3-way ACA build s + kernel entries/s, FP64 vs mixed-prec at stated rel err",
         "value": value,
@@ -162,10 +171,14 @@ def main():
                   for k, st in zip(kernels, last)},
         "compression": {k: st["compression"] for k, st in zip(kernels, last)},
         "setup_s": t_setup,
-        "roofline": {"bound": "alu", "kernel": "far_fp64_kernel (3D-ACA, all launches of a step)",
+        "far_phases": {name: {"ms": float(phase_ms[k]), "tflops": phase_flops[k] / max(phase_ms[k], 1e-9) / 1e9,
+                              "launches": phase_launch[k]} for k, name in enumerate(PHASES)},
+        "far_iters": {k: st["far_iters"] for k, st in zip(kernels, last)},
+        "roofline": {"bound": "alu", "kernel": PHASE_KERNELS[dom],
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "launches_per_step": far_launches},
+                     "launches_per_step": phase_launch[dom],
+                     "ms_per_launch": float(phase_ms[dom] / max(1, phase_launch[dom]))},
     }
     if not args.no_mixed:
         out["mixed"] = mixed_leg(gaca, ctx, xyz, tri, s, cfg, X, kernels, stream, prob, args)
@@ -213,6 +226,8 @@ def mixed_leg(gaca, ctx, xyz, tri, s, cfg, X, kernels, stream, prob64, args):
             "ms_per_step": el / len(runs) * 1e3,
             "build_ms": {k: st["ms_total"] for k, (st, _) in zip(kernels, last)},
             "far_kernel_ms": float(np.mean([sum(st["ms_far_kernel"] for st, _ in r) for r in runs])),
+            "far_phase_ms": [float(np.mean([sum(st["ms_far_phase"][k] for st, _ in r) for r in runs]))
+                             for k in range(4)],
             "apply_rel_diff_vs_fp64": errs,
             "ranks": {k: [st["rank_min"], st["rank_max"], round(st["rank_mean"], 2)]
                       for k, (st, _) in zip(kernels, last)}}

@@ -69,7 +69,7 @@ typedef struct {
     int32_t max_rank3d;       /* cap on crosses per block (default min(L, 64)) */
     int32_t max_face_rank;    /* cap on a face's ACA rank (default min(m, n)) */
     uint64_t max_device_bytes;/* 0 = no limit; otherwise total library device memory cap */
-    uint64_t batch_bytes;     /* far-field scratch per launch (default 24 GiB) */
+    uint64_t batch_bytes;     /* far-field scratch per batch of blocks (default 24 GiB) */
     int32_t threads_small;    /* workgroup size for blocks with m*n <= 4096 (64/128/256) */
     int32_t threads_large;    /* workgroup size for larger blocks (default 256) */
 } gaca_options;
@@ -96,18 +96,23 @@ typedef struct {
     double entries_face_kernel;   /* entries the face kernels evaluated (dense faces) */
     double ms_near, ms_far, ms_total;  /* device time of the build phases */
     double ms_near_kernel;        /* sum of near-field kernel durations (HIP events) */
-    double ms_far_kernel;         /* device time span of the far-field 3D-ACA launches (the
-                                     launch classes run concurrently on three streams) */
-    int32_t n_far_launches;       /* far-field kernel launches in the last attempt */
-    int32_t far_attempts;         /* 1 + arena re-allocations */
-    double far_flops;             /* algorithmic FP64 flops of the far-field kernels */
+    double ms_far_kernel;         /* device time span of the far field (its iterations run
+                                     on their own streams, concurrently with the near field) */
+    int32_t n_far_launches;       /* far-field kernel launches */
+    int32_t far_iters;            /* far-field iterations (faces of the longest block) */
+    double far_flops;             /* algorithmic flops of the far field (FP64; faces in FP32
+                                     arithmetic in the mixed path) */
     double far_kernel_evals;      /* quadrature-point x frequency kernel evaluations (far) */
     double near_kernel_evals;     /* quadrature-point x frequency kernel evaluations (near) */
-    /* per far-field launch class (0: small blocks, residual face in LDS, 64 threads;
-     * 1: small blocks, 256 threads; 2: large blocks, HBM scratch, 512 threads) */
-    double ms_far_by_kind[3];     /* sum of launch durations (HIP events on the launch stream) */
-    int32_t launches_by_kind[3];
-    double far_flops_by_kind[3];  /* algorithmic FP64 flops of the class */
+    /* per far-field phase: 0 face (residual faces, every entry in parallel), 1 aca (face
+     * ACA, one workgroup per block), 2 expand (dense H_l, pivot data and Gram values of
+     * large faces), 3 tail (fibre, eq. (norm), stop test, next frequency) */
+    double ms_far_phase[4];       /* sum of launch durations (HIP events on the launch stream) */
+    int32_t launches_phase[4];
+    double far_flops_phase[4];    /* algorithmic flops of the phase */
+    /* aca phase by launch class: 0 m n <= 1024 and sides <= 64 (LDS, 64 threads), 1 m n <=
+     * 2304 and sides <= 96 (LDS, 256 threads), 2 larger (HBM, 512 threads) */
+    double ms_far_by_kind[3];
 } gaca_stats;
 
 int gaca_abi_version(void);

@@ -43,10 +43,10 @@ class Stats(ctypes.Structure):
                 ("entries_near", F64), ("entries_face", F64), ("entries_fibre", F64),
                 ("entries_face_kernel", F64), ("ms_near", F64), ("ms_far", F64),
                 ("ms_total", F64), ("ms_near_kernel", F64), ("ms_far_kernel", F64),
-                ("n_far_launches", I32), ("far_attempts", I32), ("far_flops", F64),
+                ("n_far_launches", I32), ("far_iters", I32), ("far_flops", F64),
                 ("far_kernel_evals", F64), ("near_kernel_evals", F64),
-                ("ms_far_by_kind", F64 * 3), ("launches_by_kind", I32 * 3),
-                ("far_flops_by_kind", F64 * 3)]
+                ("ms_far_phase", F64 * 4), ("launches_phase", I32 * 4),
+                ("far_flops_phase", F64 * 4), ("ms_far_by_kind", F64 * 3)]
 
 
 def lib_path() -> str:

@@ -26,6 +26,7 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
     return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
 }
 __device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ double2 conj_d2(double2 a) { return make_double2(a.x, -a.y); }
 
 // float2 overloads (mixed-precision faces); cabs2 of a float2 is evaluated in FP64
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {

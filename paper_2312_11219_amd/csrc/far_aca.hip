@@ -1,13 +1,23 @@
 // 3D-ACA of far (admissible) blocks: Algorithm 1 of the paper with ACA faces and the
-// dense-expansion pivot, one workgroup per block, FP64 or mixed precision.
+// dense-expansion pivot, FP64 or mixed precision, run as iterations over all unfinished
+// blocks of a batch.  One iteration adds one face to every active block:
 //
-// Per face l (frequency k_l):
-//   residual face R = ENTRY(:, :, k) - sum_{p < l} f_p[k] H_p   (previous dense faces H_p)
-//   partial-pivot ACA of R  -> u_q, w_q, stop when |u||w| <= eps_aca sqrt(|C(:,:,k)|^2 + |S|^2)
-//   H_l = sum_q u_q w_q^T, pivot (i_l, j_l) = tie-argmax |H_l|
-//   fibre f_l[k'] = (ENTRY(i_l, j_l, k') - sum_p H_p[i_l, j_l] f_p[k']) / H_l[i_l, j_l]
-//   eq. (norm): |C^(l)|^2 += 2 Re sum_p <H_l, H_p><f_l, f_p> + |H_l|^2 |f_l|^2
-//   stop when |H_l| |f_l| <= eps |C^(l)|, else k_{l+1} = tie-argmax over unused k of |f_l|.
+//   face    R = ENTRY(:, :, k) - sum_{p < l} f_p[k] H_p         (previous dense faces H_p)
+//   aca     partial-pivot ACA of R -> u_q, w_q; stop when |u||w| <= eps_aca sqrt(|C(:,:,k)|^2
+//           + |S|^2), at a zero face, when all rows are used or at the face-rank cap
+//   expand  H_l = sum_q u_q w_q^T (stored in the slot of R), max |H_l|^2, |H_l|_F^2 and the
+//           Gram values <H_l, H_p>
+//   tail    pivot (i_l, j_l) = tie-argmax |H_l|;
+//           fibre f_l[k'] = (ENTRY(i_l, j_l, k') - sum_p H_p[i_l, j_l] f_p[k']) / H_l[i_l, j_l];
+//           eq. (norm): |C^(l)|^2 += 2 Re sum_p <H_l, H_p><f_l, f_p> + |H_l|^2 |f_l|^2;
+//           stop when |H_l| |f_l| <= eps |C^(l)|, else k_{l+1} = tie-argmax over unused k of
+//           |f_l|; the residual coefficients and |C^(l)(:,:,k_{l+1})|^2 of the next face.
+//
+// The face phase evaluates every entry of every active face in parallel (the kernel
+// evaluations are most of the arithmetic); only the ACA of one face is sequential and runs
+// one workgroup per block.  Small faces (kinds 0/1) stay in LDS through the ACA, which
+// updates R and S = sum_q u_q w_q^T in place and so also produces H_l = S, its pivot and its
+// Gram row; larger faces keep R in HBM and are expanded by the tiled expand phase.
 //
 // Mixed precision: faces, residuals and face factors are FP32 (float2) and every face is
 // kept divided by the block scale c_k = exp(-s_k d0) (d0 = distance of the cluster
@@ -15,14 +25,6 @@
 // the crosses stay exact because the scale moves into the FP64 fibres:
 //   C ~ sum_p H~_p (x) f_p,  R~(:,:,k) = E(:,:,k)/c_k - sum_p (f_p[k]/c_k) H~_p.
 // Fibres, Gram values, norms, stop tests and pivot comparisons are FP64.
-//
-// Two variants share the per-cross tail:
-//   small blocks (m n <= MNMAX, m, n <= SIDE): the residual face R and its approximation
-//     S = sum_q u_q w_q^T live in LDS and are updated in place by rank-1 updates, so the
-//     ACA steps never re-read the factor history; |S|_F^2 is summed directly and
-//     H_l = S needs no separate expansion;
-//   large blocks: R, H_l and the factor history in HBM scratch (L2 resident), row and
-//     column corrections split over thread groups with pipelined loads.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -34,17 +36,16 @@
 
 namespace gaca {
 
-constexpr int kMaxRowsLds = 8192;
-constexpr int kMaxLds = 1024;
-constexpr int kMaxRcap = 256;
-constexpr int kMaxRcapSmall = 64;
+constexpr int kMaxRowsLds = 8192;   // rows of a block (used-row flags in LDS)
+constexpr int kMaxLds = 1024;       // frequencies
+constexpr int kMaxRcap = 256;       // crosses per block
 
 // Face entry at (il, jl, kk): FP64 value (FT = double2), the dense test tensor, or the
 // scaled FP32 value (FT = float2).
 template <int KERNEL, bool DENSE, class FT>
-__device__ __forceinline__ FT face_entry(const GeoDev &g, const FreqDev &f, const FarLaunch &fl,
+__device__ __forceinline__ FT face_entry(const GeoDev &g, const FreqDev &f, const double2 *dense,
                                          const FarBlockDev &B, int il, int jl, int kk) {
-    if (DENSE) return from_d2<FT>(fl.dense[((int64_t)il * B.n + jl) * f.L + kk]);
+    if (DENSE) return from_d2<FT>(dense[((int64_t)il * B.n + jl) * f.L + kk]);
     const int64_t gi = B.r0 + il, gj = B.c0 + jl;
     if constexpr (KERNEL == 2) {
         if constexpr (sizeof(FT) == sizeof(double2)) {
@@ -80,9 +81,9 @@ __device__ __forceinline__ FT face_entry(const GeoDev &g, const FreqDev &f, cons
 // Unscaled FP64 entry (fibres are always FP64).
 template <int KERNEL, bool DENSE>
 __device__ __forceinline__ double2 fibre_entry(const GeoDev &g, const FreqDev &f,
-                                               const FarLaunch &fl, const FarBlockDev &B,
+                                               const double2 *dense, const FarBlockDev &B,
                                                int il, int jl, int kk) {
-    if (DENSE) return fl.dense[((int64_t)il * B.n + jl) * f.L + kk];
+    if (DENSE) return dense[((int64_t)il * B.n + jl) * f.L + kk];
     const int64_t gi = B.r0 + il, gj = B.c0 + jl;
     double er, ei;
     if constexpr (KERNEL == 2)
@@ -101,43 +102,52 @@ __device__ __forceinline__ double2 inv_scale(const FreqDev &f, const FarBlockDev
     return make_double2(mag * cs, mag * sn);
 }
 
-struct FarState {
-    int ell = 0, k = 0, zero_run = 0, zero_faces = 0, capped = 0, sum_rho = 0, nused_k = 0;
-    double norm2 = 0.0, scale = 0.0;
-};
 
-// Residual face into dst (LDS or HBM); returns ||C^(l-1)(:,:,k)||^2 in the face's frame
-// and writes the face's zero threshold factor (1 or 1/|c_k|) to *zscale.
-template <int KERNEL, int NT, bool DENSE, bool MIXED, class FT>
-__device__ double residual_face(const GeoDev &g, const FreqDev &f, const FarLaunch &fl,
-                                const FarBlockDev &B, const FarState &S, const FT *faces,
-                                const double2 *fib, const double2 *G, int rcap,
-                                double2 *coefd, FT *dst, FT *zero_dst, double *zscale,
-                                Red<NT> &red) {
-    const int tid = threadIdx.x, L = f.L, n = B.n;
-    const int64_t mn = (int64_t)B.m * n;
-    double2 isc = make_double2(1.0, 0.0);
-    if (MIXED) isc = inv_scale(f, B, S.k);
-    for (int p = tid; p < S.ell; p += NT) {
-        coefd[p] = cmul(fib[(int64_t)p * L + S.k], isc);
-    }
-    *zscale = MIXED ? sqrt(cabs2(isc)) : 1.0;
-    __syncthreads();
-    for (int64_t idx = tid; idx < mn; idx += NT) {
-        const int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
-        FT e = face_entry<KERNEL, DENSE, FT>(g, f, fl, B, i, j, S.k);
-        for (int p = 0; p < S.ell; ++p)
-            e = csub(e, cmul(from_d2<FT>(coefd[p]), faces[(int64_t)p * mn + idx]));
-        dst[idx] = e;
-        if (zero_dst) zero_dst[idx] = czero<FT>();
-    }
-    double part = 0.0;
-    for (int a = tid; a < S.ell; a += NT)
-        for (int b = 0; b < S.ell; ++b)
-            part += cmul(cmulc(coefd[a], coefd[b]), G[(int64_t)a * rcap + b]).x;
-    return fmax(red.sum(part), 0.0);
+template <bool MIXED>
+using face_t = typename std::conditional<MIXED, float2, double2>::type;
+
+// ---------------------------------------------------------------------------------------
+// Work maps: face chunk -> active index, expand tile -> active index.
+__global__ void far_map_kernel(FarBatchDev bd, const FarActive *act, int nact, int nlarge) {
+    const int a = blockIdx.x;
+    if (a >= nact) return;
+    const FarActive A = act[a];
+    const FarBlockDev B = bd.blk[A.b];
+    const int64_t nch = ((int64_t)B.m * B.n + kFarChunk - 1) / kFarChunk;
+    for (int64_t c = threadIdx.x; c < nch; c += blockDim.x) bd.map_chunk[A.chunk0 + c] = a;
+    if (a < nlarge)
+        for (int64_t t = threadIdx.x; t < A.ntile; t += blockDim.x) bd.map_tile[A.tile0 + t] = a;
 }
 
+// ---------------------------------------------------------------------------------------
+// Face phase: R = ENTRY(:, :, k) - sum_p coef_p H_p into the face's H slot.
+template <int KERNEL, bool DENSE, bool MIXED>
+__global__ void __launch_bounds__(kFarChunk)
+    far_face_kernel(GeoDev g, FreqDev f, FarBatchDev bd, const FarActive *act) {
+    using FT = face_t<MIXED>;
+    const int64_t c = blockIdx.x;
+    const int a = bd.map_chunk[c];
+    const FarActive A = act[a];
+    const FarBlockDev B = bd.blk[A.b];
+    const int ell = bd.st[A.b].ell, k = bd.st[A.b].k;
+    __shared__ double2 coef[kMaxRcap];
+    __shared__ int64_t hsl[kMaxRcap];
+    for (int p = threadIdx.x; p < ell; p += kFarChunk) {
+        coef[p] = bd.coef[(int64_t)A.b * bd.rcap + p];
+        hsl[p] = bd.hs[(int64_t)A.b * bd.rcap + p];
+    }
+    __syncthreads();
+    const int64_t mn = (int64_t)B.m * B.n;
+    const int64_t idx = (c - A.chunk0) * kFarChunk + threadIdx.x;
+    if (idx >= mn) return;
+    const int i = (int)(idx / B.n), j = (int)(idx - (int64_t)i * B.n);
+    const FT *H = reinterpret_cast<const FT *>(bd.hpool);
+    FT e = face_entry<KERNEL, DENSE, FT>(g, f, bd.dense, B, i, j, k);
+    for (int p = 0; p < ell; ++p) e = csub(e, cmul(from_d2<FT>(coef[p]), H[hsl[p] + idx]));
+    reinterpret_cast<FT *>(bd.hpool)[A.hslot + idx] = e;
+}
+
+// ---------------------------------------------------------------------------------------
 template <int NT, class T>
 __device__ int tie_argmax_unused(const T *v, const unsigned char *used, int len, double tie2,
                                  Red<NT> &red) {
@@ -156,6 +166,19 @@ __device__ int tie_argmax_unused(const T *v, const unsigned char *used, int len,
 }
 
 template <int NT>
+__device__ int first_unused(const unsigned char *used, int len, Red<NT> &red);
+
+// As tie_argmax_unused, but never out of range: if no value compares (NaN), the first
+// unused index (callers guarantee that one exists).
+template <int NT, class T>
+__device__ int pick_unused(const T *v, const unsigned char *used, int len, double tie2,
+                           Red<NT> &red) {
+    int c = tie_argmax_unused<NT>(v, used, len, tie2, red);
+    if (c >= len) c = first_unused<NT>(used, len, red);
+    return min(c, len - 1);
+}
+
+template <int NT>
 __device__ int first_unused(const unsigned char *used, int len, Red<NT> &red) {
     int c = len;
     for (int t = threadIdx.x; t < len; t += NT)
@@ -166,42 +189,22 @@ __device__ int first_unused(const unsigned char *used, int len, Red<NT> &red) {
     return red.imin(c);
 }
 
-// Everything after the face ACA, given H_l at Hl (LDS or HBM) and its copy in the HBM slot
-// of face l: pivot, Gram, fibre, eq. (norm), output, stop test, next frequency.
-// Returns true when the block is finished.
-template <int KERNEL, int NT, bool DENSE, bool MIXED, class FT>
-__device__ bool far_cross_tail(const GeoDev &g, const FreqDev &f, const AcaParams &P,
-                               const FarLaunch &fl, const FarBlockDev &B, FarState &S,
-                               FT *faces, const FT *Ub, const FT *Wb, double2 *fib, double2 *G,
-                               const FT *Hl, int rho, double mxh, double h2,
-                               unsigned char *used_k, Red<NT> &red, unsigned long long *sh_off) {
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+// <H_l, H_p>_F for p < ell (FP64 sums, four p per wave iteration), H_l given by a
+// callable hl(idx); lane 0 of the owning wave writes G[p].
+template <int NT, class FT, class HL>
+__device__ void gram_row(const HL &hl, const FT *hpool, const int64_t *hs, int ell, int64_t mn,
+                         double2 *G) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     constexpr int NW = NT / 64;
-    const int m = B.m, n = B.n, L = f.L, rcap = P.rcap;
-    const int64_t mn = (int64_t)m * n;
-    const double tie2 = (1.0 - P.tie) * (1.0 - P.tie);
-    const int ell = S.ell;
-    // pivot: lowest row-major index with |H|^2 >= (1 - tie)^2 max |H|^2
-    const double thh = tie2 * mxh;
-    int pc = 0x7fffffff;
-    for (int64_t idx = tid; idx < mn; idx += NT)
-        if (cabs2(Hl[idx]) >= thh) {
-            pc = (int)idx;
-            break;
-        }
-    const int pidx = red.imin(pc);
-    const double2 hpiv = to_d2(Hl[pidx]);
-    const int ip = pidx / n, jpv = pidx - ip * n;
-    // Gram <H_l, H_p>, p < l, accumulated in FP64: four p per wave iteration
     for (int p0 = wave * 4; p0 < ell; p0 += NW * 4) {
         double gr[4] = {0, 0, 0, 0}, gi[4] = {0, 0, 0, 0};
         const int np = min(4, ell - p0);
         for (int64_t idx = lane; idx < mn; idx += 64) {
-            const double2 h = to_d2(Hl[idx]);
+            const double2 h = to_d2(hl(idx));
 #pragma unroll
             for (int t = 0; t < 4; ++t)
                 if (t < np) {
-                    double2 v = cmulc(h, to_d2(faces[(int64_t)(p0 + t) * mn + idx]));
+                    const double2 v = cmulc(h, to_d2(hpool[hs[p0 + t] + idx]));
                     gr[t] += v.x;
                     gi[t] += v.y;
                 }
@@ -212,451 +215,689 @@ __device__ bool far_cross_tail(const GeoDev &g, const FreqDev &f, const AcaParam
             gi[t] = wave_sum(gi[t]);
         }
         if (lane == 0)
-            for (int t = 0; t < np; ++t) {
-                G[(int64_t)ell * rcap + p0 + t] = make_double2(gr[t], gi[t]);
-                G[(int64_t)(p0 + t) * rcap + ell] = make_double2(gr[t], -gi[t]);
-            }
-    }
-    if (tid == 0) G[(int64_t)ell * rcap + ell] = make_double2(h2, 0.0);
-    // frequency fibre through the pivot (FP64)
-    for (int kk = tid; kk < L; kk += NT) {
-        double2 e = fibre_entry<KERNEL, DENSE>(g, f, fl, B, ip, jpv, kk);
-        for (int p = 0; p < ell; ++p)
-            e = csub(e, cmul(to_d2(faces[(int64_t)p * mn + pidx]), fib[(int64_t)p * L + kk]));
-        fib[(int64_t)ell * L + kk] = cdiv(e, hpiv);
-    }
-    __syncthreads();
-    // eq. (norm) update
-    const double2 *fl_ = fib + (int64_t)ell * L;
-    double c3 = 0.0, f2 = 0.0, fmx = 0.0;
-    for (int p = wave; p < ell; p += NW) {
-        double dr = 0.0, di = 0.0;
-        for (int kk = lane; kk < L; kk += 64) {
-            double2 t = cmulc(fl_[kk], fib[(int64_t)p * L + kk]);
-            dr += t.x;
-            di += t.y;
-        }
-        dr = wave_sum(dr);
-        di = wave_sum(di);
-        double2 gv = G[(int64_t)ell * rcap + p];
-        c3 += gv.x * dr - gv.y * di;
-    }
-    if (lane != 0) c3 = 0.0;
-    for (int kk = tid; kk < L; kk += NT) {
-        double a2 = cabs2(fl_[kk]);
-        f2 += a2;
-        fmx = fmax(fmx, a2);
-    }
-    fmx = red.max(fmx);
-    double unused0 = 0.0;
-    red.sum3(c3, f2, unused0);
-    S.norm2 = S.norm2 + 2.0 * c3 + h2 * f2;
-    S.scale = fmax(S.scale, sqrt(cabs2(hpiv)) * sqrt(fmx));
-    // output: this cross's factors to the arena
-    const int64_t nfac = (int64_t)rho * (m + n);
-    if (tid == 0) {
-        *sh_off = atomicAdd(fl.arena_ctr, (unsigned long long)nfac);
-        fl.cmeta[(int64_t)B.out_idx * rcap + ell] = CrossMeta{S.k, ip, jpv, rho};
-    }
-    __syncthreads();
-    const unsigned long long off = *sh_off;
-    FT *arena = reinterpret_cast<FT *>(fl.arena);
-    if (off + nfac <= fl.arena_cap) {
-        for (int64_t t = tid; t < (int64_t)rho * m; t += NT) arena[off + t] = Ub[t];
-        for (int64_t t = tid; t < (int64_t)rho * n; t += NT) arena[off + (int64_t)rho * m + t] = Wb[t];
-        if (tid == 0) fl.cross_off[(int64_t)B.out_idx * rcap + ell] = (int64_t)off;
-    } else if (tid == 0) {
-        *fl.overflow = 1;
-        fl.cross_off[(int64_t)B.out_idx * rcap + ell] = -1;
-    }
-    S.sum_rho += rho;
-    S.ell = ell + 1;
-    if (sqrt(h2 * f2) <= P.eps * sqrt(fmax(S.norm2, 0.0))) return true;
-    if (S.nused_k >= L) return true;
-    if (S.ell >= rcap) {
-        S.capped = 1;
-        return true;
-    }
-    S.k = tie_argmax_unused<NT>(fl_, used_k, L, tie2, red);
-    return false;
-}
-
-// Zero face bookkeeping; returns true when the block is finished.
-template <int NT>
-__device__ bool zero_face(FarState &S, const unsigned char *used_k, int L, Red<NT> &red) {
-    ++S.zero_faces;
-    ++S.zero_run;
-    if (S.zero_run >= 3 || S.nused_k >= L) return true;
-    S.k = first_unused<NT>(used_k, L, red);
-    return false;
-}
-
-template <int NT>
-__device__ void far_finalize(const FarLaunch &fl, const FarBlockDev &B, const FarState &S,
-                             const double2 *fib, int L, unsigned long long *sh_off) {
-    const int tid = threadIdx.x;
-    const int64_t nf = (int64_t)S.ell * L;
-    if (tid == 0) *sh_off = nf > 0 ? atomicAdd(fl.fib_ctr, (unsigned long long)nf) : 0ull;
-    __syncthreads();
-    const unsigned long long foff = *sh_off;
-    if (foff + nf <= fl.fib_cap) {
-        for (int64_t t = tid; t < nf; t += NT) fl.fib_arena[foff + t] = fib[t];
-        if (tid == 0) fl.fib_off[B.out_idx] = (int64_t)foff;
-    } else if (tid == 0) {
-        *fl.overflow = 1;
-        fl.fib_off[B.out_idx] = -1;
-    }
-    if (tid == 0) {
-        FarMeta mt;
-        mt.rank = S.ell;
-        mt.sum_rho = S.sum_rho;
-        mt.capped = S.capped;
-        mt.zero_faces = S.zero_faces;
-        mt.fac_off = 0;
-        mt.norm2 = S.norm2;
-        fl.meta[B.out_idx] = mt;
+            for (int t = 0; t < np; ++t) G[p0 + t] = make_double2(gr[t], gi[t]);
     }
 }
-
-template <class FT>
-struct Scratch {
-    FT *faces, *Ub, *Wb;
-    double2 *fib, *G;
-    __device__ Scratch(const FarLaunch &fl, const FarBlockDev &B) {
-        char *base = reinterpret_cast<char *>(fl.scratch);
-        faces = reinterpret_cast<FT *>(base + B.face_off);
-        Ub = reinterpret_cast<FT *>(base + B.uw_off);
-        Wb = Ub + (int64_t)B.rho_max * B.m;
-        fib = reinterpret_cast<double2 *>(base + B.fib_off);
-        G = reinterpret_cast<double2 *>(base + B.gram_off);
-    }
-};
 
 // ---------------------------------------------------------------------------------------
-// Small blocks: R and S in LDS.
-template <int KERNEL, int NT, bool DENSE, bool MIXED, int MNMAX, int SIDE>
+// ACA phase, small faces: R and S in LDS, updated in place by the rank-1 steps.  Also
+// stores H_l = S over R, finds its pivot and writes the Gram row of the new cross.
+template <int NT, bool MIXED, int MNMAX, int SIDE>
 __global__ void __launch_bounds__(NT)
-    far_small_kernel(GeoDev g, FreqDev f, AcaParams P, FarLaunch fl) {
-    using FT = typename std::conditional<MIXED, float2, double2>::type;
-    const FarBlockDev B = fl.blocks[blockIdx.x];
-    const int m = B.m, n = B.n, L = f.L;
-    const int mn = m * n;
+    far_aca_small_kernel(AcaParams P, FarBatchDev bd, const FarActive *act) {
+    using FT = face_t<MIXED>;
+    const FarActive A = act[blockIdx.x];
+    const int b = A.b;
+    const FarBlockDev B = bd.blk[b];
+    const int m = B.m, n = B.n, mn = m * n, L = bd.L;
     const int tid = threadIdx.x;
-    Scratch<FT> sc(fl, B);
+    const int ell = bd.st[b].ell;
+    const double zero_tol = bd.st[b].zero_tol, ref2 = bd.st[b].ref2;
+    FT *R = reinterpret_cast<FT *>(bd.hpool) + A.hslot;
+    FT *Ub = reinterpret_cast<FT *>(bd.uw) + B.uw_off;
+    FT *Wb = Ub + (int64_t)B.rho_max * m;
 
     __shared__ FT Rs[MNMAX];
     __shared__ FT Ss[MNMAX];
     __shared__ FT ucol[SIDE];
     __shared__ FT wrow[SIDE];
-    __shared__ double2 coefd[kMaxRcapSmall];
     __shared__ unsigned char used_row[SIDE];
-    __shared__ unsigned char used_k[kMaxLds];
+    __shared__ int64_t hsl[kMaxRcap];
     __shared__ double redbuf[4 * (NT / 64) + 4];
-    __shared__ unsigned long long sh_off;
     Red<NT> red{redbuf};
     const double tie2 = (1.0 - P.tie) * (1.0 - P.tie);
 
-    for (int kk = tid; kk < L; kk += NT) used_k[kk] = 0;
-    FarState S;
+    for (int idx = tid; idx < mn; idx += NT) {
+        Rs[idx] = R[idx];
+        Ss[idx] = czero<FT>();
+    }
+    for (int r = tid; r < m; r += NT) used_row[r] = 0;
+    for (int p = tid; p < ell; p += NT) hsl[p] = bd.hs[(int64_t)b * bd.rcap + p];
     __syncthreads();
+    int q = 0, i = 0, nused = 0;
+    double s2 = 0.0;
     while (true) {
-        double zs = 1.0;
-        const double ref2 = residual_face<KERNEL, NT, DENSE, MIXED, FT>(
-            g, f, fl, B, S, sc.faces, sc.fib, sc.G, P.rcap, coefd, Rs, Ss, &zs, red);
-        const double zero_tol = P.delta * S.scale * zs;
-        for (int r = tid; r < m; r += NT) used_row[r] = 0;
-        __syncthreads();
-        int q = 0, i = 0, nused = 0;
-        double s2 = 0.0;
-        while (true) {
-            double mx = 0.0;
-            for (int j = tid; j < n; j += NT) mx = fmax(mx, cabs2(Rs[i * n + j]));
-            mx = red.max(mx);
-            if (tid == 0) used_row[i] = 1;
-            ++nused;
-            if (sqrt(mx) <= zero_tol) {
-                __syncthreads();
-                const int cand = first_unused<NT>(used_row, m, red);
-                if (cand >= m) break;
-                i = cand;
-                continue;
-            }
-            const double thr = tie2 * mx;
-            int jc = n;
-            for (int j = tid; j < n; j += NT)
-                if (cabs2(Rs[i * n + j]) >= thr) {
-                    jc = j;
-                    break;
-                }
-            const int jp = red.imin(jc);
-            const FT piv = Rs[i * n + jp];
-            double nw2 = 0.0, nu2 = 0.0;
-            for (int j = tid; j < n; j += NT) {
-                const FT w = cdiv(Rs[i * n + j], piv);
-                wrow[j] = w;
-                sc.Wb[(int64_t)q * n + j] = w;
-                nw2 += cabs2(w);
-            }
-            for (int r = tid; r < m; r += NT) {
-                const FT u = Rs[r * n + jp];
-                ucol[r] = u;
-                sc.Ub[(int64_t)q * m + r] = u;
-                nu2 += cabs2(u);
-            }
+        double mx = 0.0;
+        for (int j = tid; j < n; j += NT) mx = fmax(mx, cabs2(Rs[i * n + j]));
+        mx = red.max(mx);
+        if (tid == 0) used_row[i] = 1;
+        ++nused;
+        if (sqrt(mx) <= zero_tol) {
             __syncthreads();
-            double sp = 0.0;
-            for (int idx = tid; idx < mn; idx += NT) {
-                const int r = idx / n, j = idx - r * n;
-                const FT t = cmul(ucol[r], wrow[j]);
-                Rs[idx] = csub(Rs[idx], t);
-                const FT sv = cadd(Ss[idx], t);
-                Ss[idx] = sv;
-                sp += cabs2(sv);
-            }
-            red.sum3(nu2, nw2, sp);
-            s2 = sp;
-            ++q;
-            if (sqrt(nu2 * nw2) <= P.eps_aca * sqrt(ref2 + s2) || nused >= m || q >= B.rho_max)
-                break;
-            i = tie_argmax_unused<NT>(ucol, used_row, m, tie2, red);
-        }
-        const int rho = q;
-        if (tid == 0) used_k[S.k] = 1;
-        ++S.nused_k;
-        __syncthreads();
-        if (rho == 0) {
-            if (zero_face<NT>(S, used_k, L, red)) break;
+            const int cand = first_unused<NT>(used_row, m, red);
+            if (cand >= m) break;
+            i = cand;
             continue;
         }
-        S.zero_run = 0;
-        // H_l = S: store to its HBM slot (needed by later residual faces)
-        FT *Hslot = sc.faces + (int64_t)S.ell * mn;
-        double mxh = 0.0, h2 = 0.0;
+        const double thr = tie2 * mx;
+        int jc = n;
+        for (int j = tid; j < n; j += NT)
+            if (cabs2(Rs[i * n + j]) >= thr) {
+                jc = j;
+                break;
+            }
+        const int jp = min(red.imin(jc), n - 1);   // in range even for NaN rows
+        const FT piv = Rs[i * n + jp];
+        double nw2 = 0.0, nu2 = 0.0;
+        for (int j = tid; j < n; j += NT) {
+            const FT w = cdiv(Rs[i * n + j], piv);
+            wrow[j] = w;
+            Wb[(int64_t)q * n + j] = w;
+            nw2 += cabs2(w);
+        }
+        for (int r = tid; r < m; r += NT) {
+            const FT u = Rs[r * n + jp];
+            ucol[r] = u;
+            Ub[(int64_t)q * m + r] = u;
+            nu2 += cabs2(u);
+        }
+        __syncthreads();
+        double sp = 0.0;
+        for (int idx = tid; idx < mn; idx += NT) {
+            const int r = idx / n, j = idx - r * n;
+            const FT t = cmul(ucol[r], wrow[j]);
+            Rs[idx] = csub(Rs[idx], t);
+            const FT sv = cadd(Ss[idx], t);
+            Ss[idx] = sv;
+            sp += cabs2(sv);
+        }
+        red.sum3(nu2, nw2, sp);
+        s2 = sp;
+        ++q;
+        if (sqrt(nu2 * nw2) <= P.eps_aca * sqrt(ref2 + s2) || nused >= m || q >= B.rho_max)
+            break;
+        i = pick_unused<NT>(ucol, used_row, m, tie2, red);
+    }
+    const int rho = q;
+    int pidx = 0;
+    double mxh = 0.0, h2 = 0.0;
+    if (rho > 0) {
         for (int idx = tid; idx < mn; idx += NT) {
             const FT h = Ss[idx];
-            Hslot[idx] = h;
-            const double a2 = cabs2(h);
-            mxh = fmax(mxh, a2);
-            h2 += a2;
-        }
-        red.maxsum(mxh, h2);
-        if (far_cross_tail<KERNEL, NT, DENSE, MIXED, FT>(g, f, P, fl, B, S, sc.faces, sc.Ub, sc.Wb,
-                                                         sc.fib, sc.G, Ss, rho, mxh, h2, used_k,
-                                                         red, &sh_off))
-            break;
-    }
-    far_finalize<NT>(fl, B, S, sc.fib, L, &sh_off);
-}
-
-// ---------------------------------------------------------------------------------------
-// Large blocks: R / H_l and the factor history in HBM scratch.
-template <int KERNEL, int NT, bool DENSE, bool MIXED>
-__global__ void __launch_bounds__(NT)
-    far_large_kernel(GeoDev g, FreqDev f, AcaParams P, FarLaunch fl) {
-    using FT = typename std::conditional<MIXED, float2, double2>::type;
-    const FarBlockDev B = fl.blocks[blockIdx.x];
-    const int m = B.m, n = B.n, L = f.L;
-    const int64_t mn = (int64_t)m * n;
-    const int tid = threadIdx.x;
-    constexpr int NW = NT / 64;
-    const int wave = tid >> 6, lane = tid & 63;
-    Scratch<FT> sc(fl, B);
-    FT *faces = sc.faces, *Ub = sc.Ub, *Wb = sc.Wb;
-
-    __shared__ double2 coefd[kMaxRcap];
-    __shared__ FT part[NT];       // split-K partial sums of row / column corrections
-    __shared__ unsigned char used_row[kMaxRowsLds];
-    __shared__ unsigned char used_k[kMaxLds];
-    __shared__ double redbuf[4 * NW + 4];
-    __shared__ unsigned long long sh_off;
-    Red<NT> red{redbuf};
-    const double tie2 = (1.0 - P.tie) * (1.0 - P.tie);
-
-    for (int kk = tid; kk < L; kk += NT) used_k[kk] = 0;
-    FarState S;
-    __syncthreads();
-    while (true) {
-        FT *R = faces + (int64_t)S.ell * mn;
-        double zs = 1.0;
-        const double ref2 = residual_face<KERNEL, NT, DENSE, MIXED, FT>(
-            g, f, fl, B, S, faces, sc.fib, sc.G, P.rcap, coefd, R, (FT *)nullptr, &zs, red);
-        const double zero_tol = P.delta * S.scale * zs;
-        for (int r = tid; r < m; r += NT) used_row[r] = 0;
-        __syncthreads();
-        int q = 0, i = 0, nused = 0;
-        double s2 = 0.0;
-        const int splitw = max(1, NT / n), splitu = max(1, NT / m);
-        while (true) {
-            FT *Wq = Wb + (int64_t)q * n;
-            FT *Uq = Ub + (int64_t)q * m;
-            // row i of R - sum_{q'<q} u_q'[i] w_q'
-            double mx = 0.0;
-            if (splitw > 1) {
-                const int s = tid / n, j = tid - s * n;
-                if (s < splitw) {
-                    const int q0 = (int)((int64_t)q * s / splitw), q1 = (int)((int64_t)q * (s + 1) / splitw);
-                    part[tid] = dot_strided<FT>(Ub + i, m, Wb + j, n, q0, q1);
-                }
-                __syncthreads();
-                if (tid < n) {
-                    FT v = R[(int64_t)i * n + tid];
-                    for (int t = 0; t < splitw; ++t) v = csub(v, part[t * n + tid]);
-                    Wq[tid] = v;
-                    mx = cabs2(v);
-                }
-            } else {
-                for (int j = tid; j < n; j += NT) {
-                    FT v = csub(R[(int64_t)i * n + j], dot_strided<FT>(Ub + i, m, Wb + j, n, 0, q));
-                    Wq[j] = v;
-                    mx = fmax(mx, cabs2(v));
-                }
-            }
-            mx = red.max(mx);
-            if (tid == 0) used_row[i] = 1;
-            ++nused;
-            if (sqrt(mx) <= zero_tol) {
-                __syncthreads();
-                const int cand = first_unused<NT>(used_row, m, red);
-                if (cand >= m) break;
-                i = cand;
-                continue;
-            }
-            const double thr = tie2 * mx;
-            int jc = n;
-            for (int j = tid; j < n; j += NT)
-                if (cabs2(Wq[j]) >= thr) {
-                    jc = j;
-                    break;
-                }
-            const int jp = red.imin(jc);
-            const FT piv = Wq[jp];
-            __syncthreads();
-            double nw2 = 0.0, nu2 = 0.0;
-            for (int j = tid; j < n; j += NT) {
-                FT w = cdiv(Wq[j], piv);
-                Wq[j] = w;
-                nw2 += cabs2(w);
-            }
-            // column jp of R - sum_{q'<q} w_q'[jp] u_q'
-            if (splitu > 1) {
-                const int s = tid / m, r = tid - s * m;
-                if (s < splitu) {
-                    const int q0 = (int)((int64_t)q * s / splitu), q1 = (int)((int64_t)q * (s + 1) / splitu);
-                    part[tid] = dot_strided<FT>(Wb + jp, n, Ub + r, m, q0, q1);
-                }
-                __syncthreads();
-                if (tid < m) {
-                    FT u = R[(int64_t)tid * n + jp];
-                    for (int t = 0; t < splitu; ++t) u = csub(u, part[t * m + tid]);
-                    Uq[tid] = u;
-                    nu2 += cabs2(u);
-                }
-            } else {
-                for (int r = tid; r < m; r += NT) {
-                    FT u = csub(R[(int64_t)r * n + jp], dot_strided<FT>(Wb + jp, n, Ub + r, m, 0, q));
-                    Uq[r] = u;
-                    nu2 += cabs2(u);
-                }
-            }
-            __syncthreads();
-            // sum_{q'<q} Re(<u_q, u_q'> <w_q, w_q'>) in FP64: four q' per wave iteration
-            double cr = 0.0;
-            for (int q0 = wave * 4; q0 < q; q0 += NW * 4) {
-                const int nq = min(4, q - q0);
-                double ur[4] = {0, 0, 0, 0}, ui[4] = {0, 0, 0, 0}, wr[4] = {0, 0, 0, 0},
-                       wi[4] = {0, 0, 0, 0};
-                for (int r = lane; r < m; r += 64) {
-                    const double2 u = to_d2(Uq[r]);
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        if (t < nq) {
-                            double2 v = cmulc(u, to_d2(Ub[(int64_t)(q0 + t) * m + r]));
-                            ur[t] += v.x;
-                            ui[t] += v.y;
-                        }
-                }
-                for (int j = lane; j < n; j += 64) {
-                    const double2 w = to_d2(Wq[j]);
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        if (t < nq) {
-                            double2 v = cmulc(w, to_d2(Wb[(int64_t)(q0 + t) * n + j]));
-                            wr[t] += v.x;
-                            wi[t] += v.y;
-                        }
-                }
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    ur[t] = wave_sum(ur[t]);
-                    ui[t] = wave_sum(ui[t]);
-                    wr[t] = wave_sum(wr[t]);
-                    wi[t] = wave_sum(wi[t]);
-                    if (t < nq) cr += ur[t] * wr[t] - ui[t] * wi[t];
-                }
-            }
-            if (lane != 0) cr = 0.0;
-            red.sum3(nu2, nw2, cr);
-            s2 = s2 + 2.0 * cr + nu2 * nw2;
-            ++q;
-            if (sqrt(nu2 * nw2) <= P.eps_aca * sqrt(ref2 + s2) || nused >= m || q >= B.rho_max)
-                break;
-            i = tie_argmax_unused<NT>(Uq, used_row, m, tie2, red);
-        }
-        const int rho = q;
-        if (tid == 0) used_k[S.k] = 1;
-        ++S.nused_k;
-        __syncthreads();
-        if (rho == 0) {
-            if (zero_face<NT>(S, used_k, L, red)) break;
-            continue;
-        }
-        S.zero_run = 0;
-        // dense expansion H_l = U W^T into the slot of R
-        double mxh = 0.0, h2 = 0.0;
-        for (int64_t idx = tid; idx < mn; idx += NT) {
-            const int ii = (int)(idx / n), jj = (int)(idx - (int64_t)ii * n);
-            const FT h = dot_strided<FT>(Ub + ii, m, Wb + jj, n, 0, rho);
             R[idx] = h;
             const double a2 = cabs2(h);
             mxh = fmax(mxh, a2);
             h2 += a2;
         }
         red.maxsum(mxh, h2);
-        if (far_cross_tail<KERNEL, NT, DENSE, MIXED, FT>(g, f, P, fl, B, S, faces, Ub, Wb, sc.fib,
-                                                         sc.G, R, rho, mxh, h2, used_k, red,
-                                                         &sh_off))
+        const double thh = tie2 * mxh;
+        int pc = 0x7fffffff;
+        for (int idx = tid; idx < mn; idx += NT)
+            if (cabs2(Ss[idx]) >= thh) {
+                pc = idx;
+                break;
+            }
+        pidx = min(red.imin(pc), mn - 1);
+        double2 *G = bd.fgpool + A.fgslot + L;
+        gram_row<NT, FT>([&](int64_t idx) { return Ss[idx]; },
+                         reinterpret_cast<const FT *>(bd.hpool), hsl, ell, (int64_t)mn, G);
+        if (tid == 0) G[ell] = make_double2(h2, 0.0);
+    }
+    if (tid == 0) {
+        FarStateDev *S = bd.st + b;
+        S->rho = rho;
+        S->pidx = pidx;
+        S->mxh = mxh;
+        S->h2 = h2;
+    }
+}
+
+// ACA phase, large faces: R and the factor history in HBM (L2 resident), row and column
+// corrections split over thread groups with pipelined loads.
+template <int NT, bool MIXED>
+__global__ void __launch_bounds__(NT)
+    far_aca_large_kernel(AcaParams P, FarBatchDev bd, const FarActive *act) {
+    using FT = face_t<MIXED>;
+    const FarActive A = act[blockIdx.x];
+    const int b = A.b;
+    const FarBlockDev B = bd.blk[b];
+    const int m = B.m, n = B.n;
+    const int tid = threadIdx.x;
+    constexpr int NW = NT / 64;
+    const int wave = tid >> 6, lane = tid & 63;
+    const double zero_tol = bd.st[b].zero_tol, ref2 = bd.st[b].ref2;
+    const FT *R = reinterpret_cast<const FT *>(bd.hpool) + A.hslot;
+    FT *Ub = reinterpret_cast<FT *>(bd.uw) + B.uw_off;
+    FT *Wb = Ub + (int64_t)B.rho_max * m;
+
+    __shared__ FT part[NT];       // split-K partial sums of row / column corrections
+    __shared__ unsigned char used_row[kMaxRowsLds];
+    __shared__ double redbuf[4 * NW + 4];
+    Red<NT> red{redbuf};
+    const double tie2 = (1.0 - P.tie) * (1.0 - P.tie);
+
+    for (int r = tid; r < m; r += NT) used_row[r] = 0;
+    __syncthreads();
+    int q = 0, i = 0, nused = 0;
+    double s2 = 0.0;
+    const int splitw = max(1, NT / n), splitu = max(1, NT / m);
+    while (true) {
+        FT *Wq = Wb + (int64_t)q * n;
+        FT *Uq = Ub + (int64_t)q * m;
+        // row i of R - sum_{q'<q} u_q'[i] w_q'
+        double mx = 0.0;
+        if (splitw > 1) {
+            const int s = tid / n, j = tid - s * n;
+            if (s < splitw) {
+                const int q0 = (int)((int64_t)q * s / splitw), q1 = (int)((int64_t)q * (s + 1) / splitw);
+                part[tid] = dot_strided<FT>(Ub + i, m, Wb + j, n, q0, q1);
+            }
+            __syncthreads();
+            if (tid < n) {
+                FT v = R[(int64_t)i * n + tid];
+                for (int t = 0; t < splitw; ++t) v = csub(v, part[t * n + tid]);
+                Wq[tid] = v;
+                mx = cabs2(v);
+            }
+        } else {
+            for (int j = tid; j < n; j += NT) {
+                FT v = csub(R[(int64_t)i * n + j], dot_strided<FT>(Ub + i, m, Wb + j, n, 0, q));
+                Wq[j] = v;
+                mx = fmax(mx, cabs2(v));
+            }
+        }
+        mx = red.max(mx);
+        if (tid == 0) used_row[i] = 1;
+        ++nused;
+        if (sqrt(mx) <= zero_tol) {
+            __syncthreads();
+            const int cand = first_unused<NT>(used_row, m, red);
+            if (cand >= m) break;
+            i = cand;
+            continue;
+        }
+        const double thr = tie2 * mx;
+        int jc = n;
+        for (int j = tid; j < n; j += NT)
+            if (cabs2(Wq[j]) >= thr) {
+                jc = j;
+                break;
+            }
+        const int jp = min(red.imin(jc), n - 1);   // in range even for NaN rows
+        const FT piv = Wq[jp];
+        __syncthreads();
+        double nw2 = 0.0, nu2 = 0.0;
+        for (int j = tid; j < n; j += NT) {
+            FT w = cdiv(Wq[j], piv);
+            Wq[j] = w;
+            nw2 += cabs2(w);
+        }
+        // column jp of R - sum_{q'<q} w_q'[jp] u_q'
+        if (splitu > 1) {
+            const int s = tid / m, r = tid - s * m;
+            if (s < splitu) {
+                const int q0 = (int)((int64_t)q * s / splitu), q1 = (int)((int64_t)q * (s + 1) / splitu);
+                part[tid] = dot_strided<FT>(Wb + jp, n, Ub + r, m, q0, q1);
+            }
+            __syncthreads();
+            if (tid < m) {
+                FT u = R[(int64_t)tid * n + jp];
+                for (int t = 0; t < splitu; ++t) u = csub(u, part[t * m + tid]);
+                Uq[tid] = u;
+                nu2 += cabs2(u);
+            }
+        } else {
+            for (int r = tid; r < m; r += NT) {
+                FT u = csub(R[(int64_t)r * n + jp], dot_strided<FT>(Wb + jp, n, Ub + r, m, 0, q));
+                Uq[r] = u;
+                nu2 += cabs2(u);
+            }
+        }
+        __syncthreads();
+        // sum_{q'<q} Re(<u_q, u_q'> <w_q, w_q'>) in FP64: four q' per wave iteration
+        double cr = 0.0;
+        for (int q0 = wave * 4; q0 < q; q0 += NW * 4) {
+            const int nq = min(4, q - q0);
+            double ur[4] = {0, 0, 0, 0}, ui[4] = {0, 0, 0, 0}, wr[4] = {0, 0, 0, 0},
+                   wi[4] = {0, 0, 0, 0};
+            for (int r = lane; r < m; r += 64) {
+                const double2 u = to_d2(Uq[r]);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (t < nq) {
+                        double2 v = cmulc(u, to_d2(Ub[(int64_t)(q0 + t) * m + r]));
+                        ur[t] += v.x;
+                        ui[t] += v.y;
+                    }
+            }
+            for (int j = lane; j < n; j += 64) {
+                const double2 w = to_d2(Wq[j]);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (t < nq) {
+                        double2 v = cmulc(w, to_d2(Wb[(int64_t)(q0 + t) * n + j]));
+                        wr[t] += v.x;
+                        wi[t] += v.y;
+                    }
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                ur[t] = wave_sum(ur[t]);
+                ui[t] = wave_sum(ui[t]);
+                wr[t] = wave_sum(wr[t]);
+                wi[t] = wave_sum(wi[t]);
+                if (t < nq) cr += ur[t] * wr[t] - ui[t] * wi[t];
+            }
+        }
+        if (lane != 0) cr = 0.0;
+        red.sum3(nu2, nw2, cr);
+        s2 = s2 + 2.0 * cr + nu2 * nw2;
+        ++q;
+        if (sqrt(nu2 * nw2) <= P.eps_aca * sqrt(ref2 + s2) || nused >= m || q >= B.rho_max)
             break;
+        i = pick_unused<NT>(Uq, used_row, m, tie2, red);
     }
-    far_finalize<NT>(fl, B, S, sc.fib, L, &sh_off);
+    if (tid == 0) bd.st[b].rho = q;
 }
 
-// kind: 0 small-A (m n <= 1024, sides <= 64), 1 small-B (m n <= 2304, sides <= 96),
-// 2 large.
-template <int K, bool D, bool MX>
-static void far_dispatch(const GeoDev &g, const FreqDev &f, const AcaParams &P,
-                         const FarLaunch &fl, hipStream_t st) {
-    dim3 grid(fl.nb);
-    if (fl.kind == 0)
-        far_small_kernel<K, 64, D, MX, 1024, 64><<<grid, 64, 0, st>>>(g, f, P, fl);
-    else if (fl.kind == 1)
-        far_small_kernel<K, 256, D, MX, 2304, 96><<<grid, 256, 0, st>>>(g, f, P, fl);
-    else
-        far_large_kernel<K, 512, D, MX><<<grid, 512, 0, st>>>(g, f, P, fl);
+// ---------------------------------------------------------------------------------------
+// Expand phase (kind 2): one 32 x 32 tile of H_l = U W^T per workgroup, written over R,
+// with the tile's max |H|^2, sum |H|^2 and Gram partials <H_l, H_p>.
+template <bool MIXED>
+__global__ void __launch_bounds__(256) far_expand_kernel(FarBatchDev bd, const FarActive *act) {
+    using FT = face_t<MIXED>;
+    constexpr int T = kFarTile;
+    const int64_t c = blockIdx.x;
+    const int a = bd.map_tile[c];
+    const FarActive A = act[a];
+    const int b = A.b;
+    const int rho = bd.st[b].rho, ell = bd.st[b].ell;
+    if (rho == 0) return;
+    const FarBlockDev B = bd.blk[b];
+    const int m = B.m, n = B.n;
+    const int t = (int)(c - A.tile0), ntj = (n + T - 1) / T;
+    const int i0 = (t / ntj) * T, j0 = (t % ntj) * T;
+    const int tid = threadIdx.x, r = tid >> 3, cg = (tid & 7) * 4;
+    const FT *Ub = reinterpret_cast<const FT *>(bd.uw) + B.uw_off;
+    const FT *Wb = Ub + (int64_t)B.rho_max * m;
+    FT *H = reinterpret_cast<FT *>(bd.hpool) + A.hslot;
+    const FT *hp = reinterpret_cast<const FT *>(bd.hpool);
+
+    __shared__ FT Us[T][T + 1];
+    __shared__ FT Ws[T][T + 1];
+    __shared__ int64_t hsl[kMaxRcap];
+    __shared__ double red8[8][4];
+    for (int p = tid; p < ell; p += 256) hsl[p] = bd.hs[(int64_t)b * bd.rcap + p];
+    FT acc[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[e] = czero<FT>();
+    for (int q0 = 0; q0 < rho; q0 += T) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int id = tid + 256 * e, qq = id >> 5, ii = id & 31;
+            const bool qv = q0 + qq < rho;
+            Us[qq][ii] = (qv && i0 + ii < m) ? Ub[(int64_t)(q0 + qq) * m + i0 + ii] : czero<FT>();
+            Ws[qq][ii] = (qv && j0 + ii < n) ? Wb[(int64_t)(q0 + qq) * n + j0 + ii] : czero<FT>();
+        }
+        __syncthreads();
+        const int nq = min(T, rho - q0);
+        for (int qq = 0; qq < nq; ++qq) {
+            const FT u = Us[qq][r];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] = cfma(u, Ws[qq][cg + e], acc[e]);
+        }
+    }
+    const int i = i0 + r;
+    double mx = 0.0, s = 0.0;
+    int64_t gidx[4];
+    bool ok[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int j = j0 + cg + e;
+        ok[e] = i < m && j < n;
+        gidx[e] = (int64_t)i * n + j;
+        if (ok[e]) {
+            H[gidx[e]] = acc[e];
+            const double a2 = cabs2(acc[e]);
+            mx = fmax(mx, a2);
+            s += a2;
+        }
+    }
+    double *out = bd.part + (A.tile0 + t) * (int64_t)far_part_stride(bd.rcap);
+    const int wave = tid >> 6, lane = tid & 63;
+    mx = wave_max(mx);
+    s = wave_sum(s);
+    if (lane == 0) {
+        red8[0][wave] = mx;
+        red8[1][wave] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        out[0] = fmax(fmax(red8[0][0], red8[0][1]), fmax(red8[0][2], red8[0][3]));
+        out[1] = (red8[1][0] + red8[1][1]) + (red8[1][2] + red8[1][3]);
+    }
+    for (int p0 = 0; p0 < ell; p0 += 4) {
+        const int np = min(4, ell - p0);
+        double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (ok[e]) {
+                const double2 h = to_d2(acc[e]);
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt)
+                    if (tt < np) {
+                        const double2 v = cmulc(h, to_d2(hp[hsl[p0 + tt] + gidx[e]]));
+                        g[2 * tt] += v.x;
+                        g[2 * tt + 1] += v.y;
+                    }
+            }
+#pragma unroll
+        for (int v = 0; v < 8; ++v) g[v] = wave_sum(g[v]);
+        __syncthreads();
+        if (lane == 0)
+#pragma unroll
+            for (int v = 0; v < 8; ++v) red8[v][wave] = g[v];
+        __syncthreads();
+        if (tid < 2 * np) out[2 + 2 * p0 + tid] = (red8[tid][0] + red8[tid][1]) + (red8[tid][2] + red8[tid][3]);
+    }
 }
 
-void launch_far(int kernel, const GeoDev &g, const FreqDev &f, const AcaParams &P,
-                const FarLaunch &fl, hipStream_t st) {
-    if (fl.nb <= 0) return;
-    if (fl.dense) far_dispatch<0, true, false>(g, f, P, fl, st);
-    else if (!fl.mixed) {
-        if (kernel == 0) far_dispatch<0, false, false>(g, f, P, fl, st);
-        else if (kernel == 1) far_dispatch<1, false, false>(g, f, P, fl, st);
-        else far_dispatch<2, false, false>(g, f, P, fl, st);
+// ---------------------------------------------------------------------------------------
+// Tail phase: one workgroup per active block.
+template <int KERNEL, bool DENSE, bool MIXED>
+__global__ void __launch_bounds__(256)
+    far_tail_kernel(GeoDev g, FreqDev f, AcaParams P, FarBatchDev bd, const FarActive *act,
+                    int nlarge) {
+    using FT = face_t<MIXED>;
+    constexpr int NT = 256, NW = NT / 64;
+    const int a = blockIdx.x;
+    const FarActive A = act[a];
+    const int b = A.b;
+    const FarBlockDev B = bd.blk[b];
+    FarStateDev S = bd.st[b];
+    const int L = f.L, rcap = bd.rcap, m = B.m, n = B.n;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const double tie2 = (1.0 - P.tie) * (1.0 - P.tie);
+    const FT *hp = reinterpret_cast<const FT *>(bd.hpool);
+    const FT *H = hp + A.hslot;
+    double2 *fg = bd.fgpool;
+
+    __shared__ unsigned char used_k[kMaxLds];
+    __shared__ int64_t fsl[kMaxRcap], hsl[kMaxRcap];
+    __shared__ double2 gsh[kMaxRcap], hpiv_p[kMaxRcap], coefs[kMaxRcap];
+    __shared__ double redbuf[4 * NW + 4];
+    Red<NT> red{redbuf};
+
+    for (int kk = tid; kk < L; kk += NT) used_k[kk] = bd.usedk[(int64_t)b * L + kk];
+    for (int p = tid; p < S.ell; p += NT) {
+        fsl[p] = bd.fs[(int64_t)b * rcap + p];
+        hsl[p] = bd.hs[(int64_t)b * rcap + p];
+    }
+    __syncthreads();
+    if (tid == 0) used_k[S.k] = 1;
+    S.nused_k += 1;
+    const int rho = S.rho;
+    bool done = false;
+    if (rho == 0) {
+        S.zero_faces += 1;
+        S.zero_run += 1;
+        __syncthreads();
+        if (S.zero_run >= 3 || S.nused_k >= L) done = true;
+        else S.k = first_unused<NT>(used_k, L, red);
     } else {
-        if (kernel == 0) far_dispatch<0, false, true>(g, f, P, fl, st);
-        else if (kernel == 1) far_dispatch<1, false, true>(g, f, P, fl, st);
-        else far_dispatch<2, false, true>(g, f, P, fl, st);
+        S.zero_run = 0;
+        const int ell = S.ell;
+        double mxh, h2;
+        int pidx;
+        if (a < nlarge) {
+            // reduce the expand partials (fixed order) and locate the pivot
+            const int PS = far_part_stride(rcap);
+            const double *pt = bd.part + A.tile0 * (int64_t)PS;
+            double mx = 0.0, s = 0.0;
+            for (int t = tid; t < A.ntile; t += NT) {
+                mx = fmax(mx, pt[(int64_t)t * PS]);
+                s += pt[(int64_t)t * PS + 1];
+            }
+            red.maxsum(mx, s);
+            mxh = mx;
+            h2 = s;
+            for (int p = tid; p < ell; p += NT) {
+                double gr = 0.0, gi = 0.0;
+                for (int t = 0; t < A.ntile; ++t) {
+                    gr += pt[(int64_t)t * PS + 2 + 2 * p];
+                    gi += pt[(int64_t)t * PS + 3 + 2 * p];
+                }
+                gsh[p] = make_double2(gr, gi);
+                fg[A.fgslot + L + p] = gsh[p];
+            }
+            if (tid == 0) fg[A.fgslot + L + ell] = make_double2(h2, 0.0);
+            const double thh = tie2 * mxh;
+            int tc = 0x7fffffff;
+            for (int t = tid; t < A.ntile; t += NT)
+                if (pt[(int64_t)t * PS] >= thh) {
+                    tc = t;
+                    break;
+                }
+            tc = red.imin(tc);
+            if (tc >= A.ntile) tc = 0;   // no tile compares (NaN)
+            const int ntj = (n + kFarTile - 1) / kFarTile;
+            const int64_t lo = (int64_t)(tc / ntj) * kFarTile * n;
+            const int64_t hi = min((int64_t)m, (int64_t)(tc / ntj + 1) * kFarTile) * n;
+            int pc = 0x7fffffff;
+            for (int64_t idx = lo + tid; idx < hi; idx += NT)
+                if (cabs2(H[idx]) >= thh) {
+                    pc = (int)idx;
+                    break;
+                }
+            pidx = (int)min((int64_t)red.imin(pc), hi - 1);
+        } else {
+            mxh = S.mxh;
+            h2 = S.h2;
+            pidx = S.pidx;
+            for (int p = tid; p < ell; p += NT) gsh[p] = fg[A.fgslot + L + p];
+        }
+        (void)mxh;
+        const double2 hpiv = to_d2(H[pidx]);
+        const int ip = pidx / n, jpv = pidx - ip * n;
+        for (int p = tid; p < ell; p += NT) hpiv_p[p] = to_d2(hp[hsl[p] + pidx]);
+        __syncthreads();
+        // frequency fibre through the pivot (FP64)
+        double2 *fl_ = fg + A.fgslot;
+        for (int kk = tid; kk < L; kk += NT) {
+            double2 e = fibre_entry<KERNEL, DENSE>(g, f, bd.dense, B, ip, jpv, kk);
+            for (int p = 0; p < ell; ++p) e = csub(e, cmul(hpiv_p[p], fg[fsl[p] + kk]));
+            fl_[kk] = cdiv(e, hpiv);
+        }
+        __syncthreads();
+        // eq. (norm) update
+        double c3 = 0.0, f2 = 0.0, fmx = 0.0;
+        for (int p = wave; p < ell; p += NW) {
+            double dr = 0.0, di = 0.0;
+            for (int kk = lane; kk < L; kk += 64) {
+                const double2 t = cmulc(fl_[kk], fg[fsl[p] + kk]);
+                dr += t.x;
+                di += t.y;
+            }
+            dr = wave_sum(dr);
+            di = wave_sum(di);
+            c3 += gsh[p].x * dr - gsh[p].y * di;
+        }
+        if (lane != 0) c3 = 0.0;
+        for (int kk = tid; kk < L; kk += NT) {
+            const double a2 = cabs2(fl_[kk]);
+            f2 += a2;
+            fmx = fmax(fmx, a2);
+        }
+        fmx = red.max(fmx);
+        double unused0 = 0.0;
+        red.sum3(c3, f2, unused0);
+        S.norm2 = S.norm2 + 2.0 * c3 + h2 * f2;
+        S.scale = fmax(S.scale, sqrt(cabs2(hpiv)) * sqrt(fmx));
+        if (tid == 0) {
+            bd.cmeta[(int64_t)B.out_idx * rcap + ell] = CrossMeta{S.k, ip, jpv, rho};
+            bd.hs[(int64_t)b * rcap + ell] = A.hslot;
+            bd.fs[(int64_t)b * rcap + ell] = A.fgslot;
+            fsl[ell] = A.fgslot;
+        }
+        S.sum_rho += rho;
+        S.ell = ell + 1;
+        if (sqrt(h2 * f2) <= P.eps * sqrt(fmax(S.norm2, 0.0))) done = true;
+        else if (S.nused_k >= L) done = true;
+        else if (S.ell >= rcap) {
+            S.capped = 1;
+            done = true;
+        } else {
+            S.k = pick_unused<NT>(fl_, used_k, L, tie2, red);
+        }
     }
+    if (!done) {
+        // residual coefficients and |C^(l)(:,:,k)|_F^2 of the next face
+        __syncthreads();
+        const int ell = S.ell;
+        double2 isc = make_double2(1.0, 0.0);
+        if (MIXED) isc = inv_scale(f, B, S.k);
+        for (int p = tid; p < ell; p += NT) {
+            coefs[p] = cmul(fg[fsl[p] + S.k], isc);
+            bd.coef[(int64_t)b * rcap + p] = coefs[p];
+        }
+        __syncthreads();
+        double part = 0.0;
+        for (int x = tid; x < ell; x += NT)
+            for (int y = 0; y < ell; ++y) {
+                const double2 gxy = x >= y ? fg[fsl[x] + L + y] : conj_d2(fg[fsl[y] + L + x]);
+                part += cmul(cmulc(coefs[x], coefs[y]), gxy).x;
+            }
+        S.ref2 = fmax(red.sum(part), 0.0);
+        S.zero_tol = P.delta * S.scale * (MIXED ? sqrt(cabs2(isc)) : 1.0);
+    }
+    S.done = done ? 1 : 0;
+    if (tid == 0) {
+        bd.st[b] = S;
+        bd.status[2 * a] = (rho > 0 ? 1 : 0) | (done ? 2 : 0);
+        bd.status[2 * a + 1] = rho;
+        if (done) {
+            FarMeta mt;
+            mt.rank = S.ell;
+            mt.sum_rho = S.sum_rho;
+            mt.capped = S.capped;
+            mt.zero_faces = S.zero_faces;
+            mt.fac_off = 0;
+            mt.norm2 = S.norm2;
+            bd.meta[B.out_idx] = mt;
+        }
+    }
+    __syncthreads();
+    for (int kk = tid; kk < L; kk += NT) bd.usedk[(int64_t)b * L + kk] = used_k[kk];
+}
+
+// ---------------------------------------------------------------------------------------
+// Factors of accepted crosses -> arena (U: rho x m, then W: rho x n).
+template <class FT>
+__global__ void __launch_bounds__(256) far_copy_kernel(FarBatchDev bd, const FarCopy *cp,
+                                                       FT *arena, int64_t *cross_off) {
+    const FarCopy C = cp[blockIdx.x];
+    const FarBlockDev B = bd.blk[C.b];
+    const FT *Ub = reinterpret_cast<const FT *>(bd.uw) + B.uw_off;
+    const FT *Wb = Ub + (int64_t)B.rho_max * B.m;
+    const int64_t nu = (int64_t)C.rho * B.m, nw = (int64_t)C.rho * B.n;
+    for (int64_t t = threadIdx.x; t < nu; t += 256) arena[C.off + t] = Ub[t];
+    for (int64_t t = threadIdx.x; t < nw; t += 256) arena[C.off + nu + t] = Wb[t];
+    if (threadIdx.x == 0) cross_off[(int64_t)B.out_idx * bd.rcap + C.p] = C.off;
+}
+
+// Fibres of finished blocks -> fibre arena (rank x L, contiguous per block).
+__global__ void __launch_bounds__(256) far_gather_kernel(FarBatchDev bd, const FarGather *gt,
+                                                         double2 *fib_arena, int64_t *fib_off) {
+    const FarGather G = gt[blockIdx.x];
+    const FarBlockDev B = bd.blk[G.b];
+    const int L = bd.L;
+    for (int p = 0; p < G.rank; ++p) {
+        const int64_t src = bd.fs[(int64_t)G.b * bd.rcap + p];
+        for (int kk = threadIdx.x; kk < L; kk += 256)
+            fib_arena[G.off + (int64_t)p * L + kk] = bd.fgpool[src + kk];
+    }
+    if (threadIdx.x == 0) fib_off[B.out_idx] = G.off;
+}
+
+// ---------------------------------------------------------------------------------------
+void launch_far_map(const FarBatchDev &bd, const FarActive *act, int nact, int nlarge,
+                    hipStream_t st) {
+    if (nact <= 0) return;
+    far_map_kernel<<<nact, 256, 0, st>>>(bd, act, nact, nlarge);
+}
+
+template <int K, bool D, bool MX>
+static void face_dispatch(const GeoDev &g, const FreqDev &f, const FarBatchDev &bd,
+                          const FarActive *act, int64_t nchunk, hipStream_t st) {
+    far_face_kernel<K, D, MX><<<(unsigned)nchunk, kFarChunk, 0, st>>>(g, f, bd, act);
+}
+
+void launch_far_face(int kernel, const GeoDev &g, const FreqDev &f, const FarBatchDev &bd,
+                     const FarActive *act, int64_t nchunk, hipStream_t st) {
+    if (nchunk <= 0) return;
+    if (bd.dense) face_dispatch<0, true, false>(g, f, bd, act, nchunk, st);
+    else if (!bd.mixed) {
+        if (kernel == 0) face_dispatch<0, false, false>(g, f, bd, act, nchunk, st);
+        else if (kernel == 1) face_dispatch<1, false, false>(g, f, bd, act, nchunk, st);
+        else face_dispatch<2, false, false>(g, f, bd, act, nchunk, st);
+    } else {
+        if (kernel == 0) face_dispatch<0, false, true>(g, f, bd, act, nchunk, st);
+        else if (kernel == 1) face_dispatch<1, false, true>(g, f, bd, act, nchunk, st);
+        else face_dispatch<2, false, true>(g, f, bd, act, nchunk, st);
+    }
+}
+
+template <bool MX>
+static void aca_dispatch(int kind, const AcaParams &P, const FarBatchDev &bd,
+                         const FarActive *act, int nact, hipStream_t st) {
+    if (kind == 0)
+        far_aca_small_kernel<64, MX, 1024, 64><<<nact, 64, 0, st>>>(P, bd, act);
+    else if (kind == 1)
+        far_aca_small_kernel<256, MX, 2304, 96><<<nact, 256, 0, st>>>(P, bd, act);
+    else
+        far_aca_large_kernel<512, MX><<<nact, 512, 0, st>>>(P, bd, act);
+}
+
+void launch_far_aca(int kind, const AcaParams &P, const FarBatchDev &bd, const FarActive *act,
+                    int nact, hipStream_t st) {
+    if (nact <= 0) return;
+    if (bd.mixed) aca_dispatch<true>(kind, P, bd, act, nact, st);
+    else aca_dispatch<false>(kind, P, bd, act, nact, st);
+}
+
+void launch_far_expand(const FarBatchDev &bd, const FarActive *act, int64_t ntile, hipStream_t st) {
+    if (ntile <= 0) return;
+    if (bd.mixed) far_expand_kernel<true><<<(unsigned)ntile, 256, 0, st>>>(bd, act);
+    else far_expand_kernel<false><<<(unsigned)ntile, 256, 0, st>>>(bd, act);
+}
+
+template <int K, bool D, bool MX>
+static void tail_dispatch(const GeoDev &g, const FreqDev &f, const AcaParams &P,
+                          const FarBatchDev &bd, const FarActive *act, int nact, int nlarge,
+                          hipStream_t st) {
+    far_tail_kernel<K, D, MX><<<nact, 256, 0, st>>>(g, f, P, bd, act, nlarge);
+}
+
+void launch_far_tail(int kernel, const GeoDev &g, const FreqDev &f, const AcaParams &P,
+                     const FarBatchDev &bd, const FarActive *act, int nact, int nlarge,
+                     hipStream_t st) {
+    if (nact <= 0) return;
+    if (bd.dense) tail_dispatch<0, true, false>(g, f, P, bd, act, nact, nlarge, st);
+    else if (!bd.mixed) {
+        if (kernel == 0) tail_dispatch<0, false, false>(g, f, P, bd, act, nact, nlarge, st);
+        else if (kernel == 1) tail_dispatch<1, false, false>(g, f, P, bd, act, nact, nlarge, st);
+        else tail_dispatch<2, false, false>(g, f, P, bd, act, nact, nlarge, st);
+    } else {
+        if (kernel == 0) tail_dispatch<0, false, true>(g, f, P, bd, act, nact, nlarge, st);
+        else if (kernel == 1) tail_dispatch<1, false, true>(g, f, P, bd, act, nact, nlarge, st);
+        else tail_dispatch<2, false, true>(g, f, P, bd, act, nact, nlarge, st);
+    }
+}
+
+void launch_far_copy(const FarBatchDev &bd, const FarCopy *c, int n, void *arena,
+                     int64_t *cross_off, hipStream_t st) {
+    if (n <= 0) return;
+    if (bd.mixed)
+        far_copy_kernel<float2><<<n, 256, 0, st>>>(bd, c, reinterpret_cast<float2 *>(arena), cross_off);
+    else
+        far_copy_kernel<double2><<<n, 256, 0, st>>>(bd, c, reinterpret_cast<double2 *>(arena), cross_off);
+}
+
+void launch_far_gather(const FarBatchDev &bd, const FarGather *gt, int n, double2 *fib_arena,
+                       int64_t *fib_off, hipStream_t st) {
+    if (n <= 0) return;
+    far_gather_kernel<<<n, 256, 0, st>>>(bd, gt, fib_arena, fib_off);
 }
 
 }  // namespace gaca

@@ -69,14 +69,10 @@ struct FreqDev {
 
 enum Tier : int32_t { TIER_FAR6 = 0, TIER_MID4 = 1, TIER_NEAR8 = 2, TIER_SELF = 3 };
 
-// One admissible block of a far-field launch.  Scratch offsets are in BYTES (faces and
-// factors are double2 in FP64, float2 in the mixed path; fibres and Gram always double2).
+// One admissible block of a far-field batch (constant during the build).
 struct FarBlockDev {
     int32_t r0, m, c0, n;      // tree-order ranges
-    int64_t face_off;          // dense faces (rcap x m x n)
-    int64_t uw_off;            // current face's U (rho_max x m) then W (rho_max x n)
-    int64_t fib_off;           // fibres (rcap x L, double2)
-    int64_t gram_off;          // Gram matrix (rcap x rcap, double2)
+    int64_t uw_off;            // face-type elements: this block's U (rho_max x m) then W (rho_max x n)
     int32_t rho_max;           // face-rank cap for this block
     int32_t out_idx;           // global far-block index
     // mixed-precision scaling, c_k = exp(-s_k d0f): with D = x_sigma - y_tau (box centres),
@@ -84,6 +80,16 @@ struct FarBlockDev {
     // xs_adj = x_sigma - (D - Dh) (so row offsets absorb the rounding of D)
     double xs_adj[3], yt[3];
     float Dh[3], d0f, kappa, pad_[3];
+};
+
+// Mutable 3D-ACA state of one far block between the phases of an iteration.
+struct FarStateDev {
+    int32_t ell, k, zero_run, zero_faces, capped, sum_rho, nused_k, done;
+    int32_t rho;               // rank of the current face (0: zero face)
+    int32_t pidx;              // pivot of the current face (row-major index), small blocks
+    double norm2, scale;       // ||C^(l)||_F^2 and max_p |H_p[i_p, j_p]| max_k |f_p[k]|
+    double ref2, zero_tol;     // current face: ||C^(l-1)(:,:,k)||^2 (face frame), zero threshold
+    double mxh, h2;            // current face: max |H_l|^2 and ||H_l||_F^2, small blocks
 };
 
 // Per-block result metadata written by the far-field kernel.

@@ -28,32 +28,72 @@ void launch_near_galerkin(int tier, const GeoDev &g, const QuadDev &q, const Fre
 
 // Kernel ids used by the far-field and eval launches: 0 collocation single layer,
 // 1 collocation double layer, 2 Galerkin single layer.
-// Far field 3D-ACA: one workgroup per block of `blocks` (nb blocks).
-// kind 0: small blocks (m n <= 1024, sides <= 64), residual face in LDS, 64 threads;
-// kind 1: small blocks (m n <= 2304, sides <= 96), residual face in LDS, 256 threads;
-// kind 2: large blocks, residual face and factors in HBM scratch, 512 threads.
-// Small kinds need rcap <= 64.
-struct FarLaunch {
-    const FarBlockDev *blocks;
-    int32_t nb;
-    int32_t kind;
-    int32_t mixed;        // 1: FP32 faces/factors (float2), FP64 bookkeeping
-    void *scratch;        // byte offsets in FarBlockDev
-    FarMeta *meta;
-    CrossMeta *cmeta;     // [nfar][rcap]
-    int64_t *cross_off;   // [nfar][rcap] arena offsets (elements) of U (then W follows)
-    void *arena;          // double2 (FP64) or float2 (mixed) factors
-    unsigned long long *arena_ctr;
-    unsigned long long arena_cap;
-    double2 *fib_arena;
-    unsigned long long *fib_ctr;
-    unsigned long long fib_cap;
-    int64_t *fib_off;     // [nfar]
-    int32_t *overflow;
-    const double2 *dense; // synthetic-entry mode: dense tensor [m][n][L] (block 0 only)
+//
+// Far field 3D-ACA, run as iterations over all unfinished blocks of a batch; one iteration
+// adds one face (one 3-D cross, or one zero face) to every active block in four phases:
+//   face    residual face R = ENTRY(:, :, k) - sum_p coef_p H_p, all entries in parallel
+//   aca     partial-pivot ACA of R, one workgroup per block (kinds 0/1: R in LDS, which also
+//           expand H_l, pick the pivot and form the Gram row; kind 2: R in HBM)
+//   expand  kind 2: H_l = U W^T in 32 x 32 tiles with per-tile max, norm and Gram partials
+//   tail    pivot (kind 2), fibre, eq. (norm), stop test, next frequency and coefficients
+constexpr int kFarChunk = 256;   // face entries per workgroup of the face phase
+constexpr int kFarTile = 32;     // expand tile side
+constexpr int kFarMaxRows = 8192; // rows / columns of a far block
+__host__ __device__ constexpr int far_part_stride(int rcap) { return 2 + 2 * rcap; }
+
+// One active block of an iteration (host-built, sorted kind 2, kind 1, kind 0).
+struct FarActive {
+    int32_t b;          // batch-local block index
+    int32_t ntile;      // expand tiles (kind 2)
+    int64_t hslot;      // face-type element offset of this face's slot in the H pool
+    int64_t fgslot;     // double2 offset of this cross's fibre (L) + Gram row (rcap) slot
+    int64_t chunk0;     // first face-phase chunk
+    int64_t tile0;      // first expand tile (kind 2)
 };
-void launch_far(int kernel, const GeoDev &g, const FreqDev &f, const AcaParams &P,
-                     const FarLaunch &fl, hipStream_t st);
+
+struct FarCopy {        // factors of an accepted cross -> arena
+    int32_t b, p, rho, pad;
+    int64_t off;
+};
+struct FarGather {      // fibres of a finished block -> fibre arena
+    int32_t b, rank;
+    int64_t off;
+};
+
+struct FarBatchDev {
+    const FarBlockDev *blk;   // [nb]
+    FarStateDev *st;          // [nb]
+    double2 *coef;            // [nb][rcap] residual coefficients of the current face
+    int64_t *hs, *fs;         // [nb][rcap] H slot / fibre slot of each accepted cross
+    unsigned char *usedk;     // [nb][L]
+    void *hpool;              // faces H_p (and the current residual), face type
+    double2 *fgpool;          // fibres and Gram rows
+    void *uw;                 // current face factors, face type
+    double *part;             // expand partials, far_part_stride(rcap) doubles per tile
+    int32_t *map_chunk;       // face chunk -> active index
+    int32_t *map_tile;        // expand tile -> active index
+    int32_t *status;          // [nact][2]: accepted | done << 1, rho
+    FarMeta *meta;            // [nfar] (global index)
+    CrossMeta *cmeta;         // [nfar][rcap]
+    const double2 *dense;     // synthetic-entry mode: dense tensor [m][n][L] of block 0
+    int32_t mixed, rcap, L, pad;
+};
+
+void launch_far_map(const FarBatchDev &bd, const FarActive *act, int nact, int nlarge,
+                    hipStream_t st);
+void launch_far_face(int kernel, const GeoDev &g, const FreqDev &f, const FarBatchDev &bd,
+                     const FarActive *act, int64_t nchunk, hipStream_t st);
+// kind 0/1/2 on act[0 .. nact)
+void launch_far_aca(int kind, const AcaParams &P, const FarBatchDev &bd, const FarActive *act,
+                    int nact, hipStream_t st);
+void launch_far_expand(const FarBatchDev &bd, const FarActive *act, int64_t ntile, hipStream_t st);
+void launch_far_tail(int kernel, const GeoDev &g, const FreqDev &f, const AcaParams &P,
+                     const FarBatchDev &bd, const FarActive *act, int nact, int nlarge,
+                     hipStream_t st);
+void launch_far_copy(const FarBatchDev &bd, const FarCopy *c, int n, void *arena,
+                     int64_t *cross_off, hipStream_t st);
+void launch_far_gather(const FarBatchDev &bd, const FarGather *gt, int n, double2 *fib_arena,
+                       int64_t *fib_off, hipStream_t st);
 
 // Test hook: entries of (row, col) tree positions with given tiers at frequency k.
 void launch_eval(int kernel, const GeoDev &g, const QuadDev &q, const FreqDev &f, int64_t n,

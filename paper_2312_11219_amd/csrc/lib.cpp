@@ -66,6 +66,36 @@ struct DevBuf {
     }
 };
 
+// Pinned host staging buffer (per-iteration uploads and status read-back).
+struct PinnedBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    PinnedBuf() = default;
+    PinnedBuf(const PinnedBuf &) = delete;
+    PinnedBuf &operator=(const PinnedBuf &) = delete;
+    ~PinnedBuf() {
+        if (ptr) (void)hipHostFree(ptr);
+    }
+    void ensure(size_t need) {
+        if (need <= bytes && ptr) return;
+        if (ptr) (void)hipHostFree(ptr);
+        ptr = nullptr;
+        const size_t want = std::max<size_t>({need, bytes + bytes / 2, 4096});
+        bytes = 0;
+        GACA_HIP_CHECK(hipHostMalloc(&ptr, want, 0));
+        bytes = want;
+    }
+    template <class T>
+    T *as() const { return reinterpret_cast<T *>(ptr); }
+};
+
+// Far-field working memory, kept by the problem across builds (it only grows).
+struct FarScratch {
+    DevBuf blk, state, coef, hs, fs, usedk, hpool, fgpool, uw, part, act, map_chunk, map_tile,
+        status, copies, gathers;
+    PinnedBuf h_act, h_status, h_copies, h_gathers;
+};
+
 template <class F>
 gaca_status guarded(F &&fn) {
     try {
@@ -120,6 +150,7 @@ struct gaca_problem {
     // far-field launch classes run concurrently on these streams (default priority)
     hipStream_t far_streams[3] = {nullptr, nullptr, nullptr};
     bool far_streams_ready = false;
+    FarScratch fsc;
     ~gaca_problem() {
         if (far_streams_ready)
             for (auto &s : far_streams) (void)hipStreamDestroy(s);
@@ -451,12 +482,31 @@ gaca_status gaca_problem_blocks(const gaca_problem *p, int64_t *far4, int64_t *n
 
 // ---------------------------------------------------------------------------------------
 // far-field build
-// Launch class of a far block: small blocks keep the residual face in LDS.
-static int far_kind(int m, int n, int rcap) {
+// Launch class of a far block in the aca phase: small faces stay in LDS.
+static int far_kind(int m, int n) {
     const int64_t mn = (int64_t)m * n;
-    if (rcap <= 64 && mn <= 1024 && m <= 64 && n <= 64) return 0;
-    if (rcap <= 64 && mn <= 2304 && m <= 96 && n <= 96) return 1;
+    if (mn <= 1024 && m <= 64 && n <= 64) return 0;
+    if (mn <= 2304 && m <= 96 && n <= 96) return 1;
     return 2;
+}
+
+// Grow buf to at least need bytes keeping its first `used` bytes (stream-ordered copy).
+static void grow_keep(gaca_context *ctx, DevBuf &buf, size_t need, size_t used, hipStream_t st) {
+    if (buf.bytes >= need && buf.ptr) return;
+    DevBuf nb;
+    nb.alloc(ctx, std::max(need, buf.bytes + buf.bytes / 2));
+    if (used > 0 && buf.ptr)
+        GACA_HIP_CHECK(hipMemcpyAsync(nb.ptr, buf.ptr, std::min(used, buf.bytes),
+                                      hipMemcpyDeviceToDevice, st));
+    GACA_HIP_CHECK(hipStreamSynchronize(st));
+    std::swap(buf.ptr, nb.ptr);
+    std::swap(buf.bytes, nb.bytes);
+}
+
+// Grow buf to at least need bytes; the contents are not kept.
+static void ensure(gaca_context *ctx, DevBuf &buf, size_t need) {
+    if (buf.bytes >= need && buf.ptr) return;
+    buf.alloc(ctx, std::max(need, buf.bytes + buf.bytes / 2));
 }
 
 // Replace buf by a copy holding its first `used` bytes when that frees a useful amount.
@@ -470,6 +520,10 @@ static void compact(gaca_context *ctx, DevBuf &buf, size_t used, hipStream_t st)
     std::swap(buf.bytes, tight.bytes);
 }
 
+// Far field: batches of blocks within the memory budget; in each batch, iterations of the
+// four phases over the unfinished blocks until every block has stopped.  The host assigns
+// the H / fibre slots of each face and the arena offsets of accepted factors, so storage
+// is exact and the layout does not depend on the order in which workgroups run.
 static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<void()> &main_work) {
     gaca_problem *p = h->p;
     gaca_context *ctx = p->ctx;
@@ -478,7 +532,9 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
     h->nfar = nfar;
     const int L = p->L;
     const int rcap = h->rcap;
-    const hipStream_t st = ctx->stream;
+    const bool mixed = h->prec == GACA_MIXED;
+    const size_t es = mixed ? sizeof(float2) : sizeof(double2);
+    const int PS = far_part_stride(rcap);
     h->meta.assign(nfar, FarMeta{});
     h->cmeta.assign(nfar * rcap, CrossMeta{});
     h->cross_off.assign(nfar * rcap, -1);
@@ -495,17 +551,36 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
     h->d_cmeta.alloc(ctx, nfar * rcap * sizeof(CrossMeta));
     h->d_cross_off.alloc(ctx, nfar * rcap * sizeof(int64_t));
     h->d_fib_off.alloc(ctx, nfar * sizeof(int64_t));
-    // per-block scratch (complex elements) and launch classes
-    struct Item {
-        int64_t b, bytes;
-        int kind;
-        FarBlockDev d;
-    };
-    std::vector<Item> items;
+    GACA_HIP_CHECK(hipMemset(h->d_meta.ptr, 0, nfar * sizeof(FarMeta)));
+    GACA_HIP_CHECK(hipMemset(h->d_cmeta.ptr, 0, nfar * rcap * sizeof(CrossMeta)));
+    GACA_HIP_CHECK(hipMemset(h->d_cross_off.ptr, 0xff, nfar * rcap * sizeof(int64_t)));
+    GACA_HIP_CHECK(hipMemset(h->d_fib_off.ptr, 0xff, nfar * sizeof(int64_t)));
+    AcaParams P{};
+    P.eps = p->opt.eps3d;
+    P.eps_aca = p->opt.eps_aca;
+    P.tie = p->opt.tie;
+    P.delta = p->opt.delta_zero;
+    if (mixed) {
+        // FP32 faces: the face tolerance, tie window and zero threshold cannot go below
+        // what FP32 resolves
+        P.eps_aca = std::max(P.eps_aca, 2e-6);
+        P.tie = std::max(P.tie, 1e-4);
+        P.delta = std::max(P.delta, 1e-6);
+    }
+    h->eps_aca_used = P.eps_aca;
+    P.rcap = rcap;
+    P.kernel = h->kernel;
+
+    // block descriptors, launch classes and memory estimates
+    std::vector<FarBlockDev> desc(nfar);
+    std::vector<int> kind(nfar);
+    std::vector<double> est(nfar);
+    const int rguess = std::min(rcap, 24);
     double factor_guess = 0.0;
     for (int64_t b = 0; b < nfar; ++b) {
         const int m = (int)far[b][1], n = (int)far[b][3];
-        if (m > 8192) throw Error{GACA_ERR_UNSUPPORTED, "far block with more than 8192 rows"};
+        if (m > kFarMaxRows || n > kFarMaxRows)
+            throw Error{GACA_ERR_UNSUPPORTED, "far block with more than 8192 rows or columns"};
         int rho_max = std::min(m, n);
         if (p->opt.max_face_rank > 0) rho_max = std::min(rho_max, p->opt.max_face_rank);
         FarBlockDev d{};
@@ -515,16 +590,6 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
         d.n = n;
         d.rho_max = rho_max;
         d.out_idx = (int32_t)b;
-        // scratch layout in bytes: faces and current-face factors in the face type, fibres
-        // and Gram values in double2 (16-byte aligned)
-        const int64_t es = h->prec == GACA_MIXED ? 8 : 16;
-        auto al16 = [](int64_t v) { return (v + 15) & ~(int64_t)15; };
-        int64_t faces = al16((int64_t)rcap * m * n * es), uw = al16((int64_t)rho_max * (m + n) * es),
-                fibs = (int64_t)rcap * L * 16, gram = (int64_t)rcap * rcap * 16;
-        d.face_off = 0;
-        d.uw_off = faces;
-        d.fib_off = faces + uw;
-        d.gram_off = faces + uw + fibs;
         if (!p->synthetic && p->part.far_nodes.size() == far.size()) {
             // mixed scaling geometry from the cluster boxes
             const auto &ns = p->tree.nodes[p->part.far_nodes[b][0]];
@@ -543,167 +608,324 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             for (int k = 0; k < 3; ++k) kap += (double)d.Dh[k] * (double)d.Dh[k];
             d.kappa = (float)kap;
         }
-        items.push_back(Item{b, faces + uw + fibs + gram, far_kind(m, n, rcap), d});
-        // first guess of the factor storage: 16 crosses of face rank 16, never more than
-        // the dense block (the build retries with a larger arena when the guess is short)
-        factor_guess += std::min((double)m * n * L,
-                                 (double)std::min(rcap, 16) * std::min(rho_max, 16) * (m + n));
+        desc[b] = d;
+        kind[b] = far_kind(m, n);
+        const double mn = (double)m * n;
+        const double tiles = kind[b] == 2 ? std::ceil(m / 32.0) * std::ceil(n / 32.0) : 0.0;
+        est[b] = (double)rho_max * (m + n) * es + (rguess + 1) * mn * es +
+                 rguess * (double)(L + rcap) * 16 + tiles * PS * 8 + sizeof(FarStateDev) +
+                 sizeof(FarBlockDev) + rcap * 32.0 + L + 64;
+        factor_guess += std::min(mn * L, (double)std::min(rcap, 16) * std::min(rho_max, 24) * (m + n));
     }
-    // large blocks first, biggest first inside each class
-    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
-        if (a.kind != b.kind) return a.kind > b.kind;
-        return a.bytes > b.bytes;
-    });
-    const size_t fac_bytes = h->prec == GACA_MIXED ? sizeof(float2) : sizeof(double2);
-    uint64_t arena_cap = (uint64_t)std::max(1.0e6, factor_guess);
-    uint64_t fib_cap = (uint64_t)std::max<int64_t>(1 << 16, nfar * (int64_t)std::min(rcap, 16) * L);
-    {
-        // keep the first guess within a third of the free device memory
-        size_t free_b = 0, total_b = 0;
-        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0)
-            arena_cap = std::min<uint64_t>(arena_cap, std::max<uint64_t>(1 << 20, free_b / 3 / fac_bytes));
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        free_b = (size_t)p->opt.batch_bytes;
     }
-    const uint64_t budget_elems = std::max<uint64_t>(p->opt.batch_bytes / 3, 16ull << 20);  // bytes
-    AcaParams P{};
-    P.eps = p->opt.eps3d;
-    P.eps_aca = p->opt.eps_aca;
-    P.tie = p->opt.tie;
-    P.delta = p->opt.delta_zero;
-    if (h->prec == GACA_MIXED) {
-        // FP32 faces: the face tolerance, tie window and zero threshold cannot go below
-        // what FP32 resolves
-        P.eps_aca = std::max(P.eps_aca, 2e-6);
-        P.tie = std::max(P.tie, 1e-4);
-        P.delta = std::max(P.delta, 1e-6);
+    const double budget = std::max(64.0 * (1 << 20), std::min((double)p->opt.batch_bytes, 0.5 * free_b));
+    std::vector<std::pair<int64_t, int64_t>> batches;
+    for (int64_t s0 = 0; s0 < nfar;) {
+        int64_t e = s0;
+        double acc = 0.0;
+        while (e < nfar && (e == s0 || acc + est[e] <= budget)) acc += est[e++];
+        batches.emplace_back(s0, e);
+        s0 = e;
     }
-    h->eps_aca_used = P.eps_aca;
-    P.rcap = rcap;
-    P.kernel = h->kernel;
-    DevBuf d_ctr, d_items, d_over;
-    DevBuf d_scratch[3];
-    d_ctr.alloc(ctx, 2 * sizeof(unsigned long long));
-    d_over.alloc(ctx, sizeof(int32_t));
-    // batches: consecutive items of one class within the memory budget
-    struct Batch {
-        size_t first, last;
-        int kind;
-        uint64_t elems;
-    };
-    std::vector<Batch> batches;
-    uint64_t kind_max[3] = {0, 0, 0};
-    for (size_t s = 0; s < items.size();) {
-        size_t e = s;
-        uint64_t acc = 0;
-        while (e < items.size() && items[e].kind == items[s].kind &&
-               (e == s || acc + items[e].bytes <= budget_elems)) {
-            acc += items[e].bytes;
-            ++e;
-        }
-        batches.push_back(Batch{s, e, items[s].kind, acc});
-        kind_max[items[s].kind] = std::max(kind_max[items[s].kind], acc);
-        s = e;
-    }
-    for (int k = 0; k < 3; ++k)
-        if (kind_max[k] > 0) d_scratch[k].alloc(ctx, kind_max[k]);
+
+    main_work();   // near field on the context stream, concurrently with the far field
     if (!p->far_streams_ready) {
-        for (int k = 0; k < 3; ++k) GACA_HIP_CHECK(hipStreamCreate(&p->far_streams[k]));
+        for (int k = 0; k < 3; ++k)
+            GACA_HIP_CHECK(hipStreamCreateWithFlags(&p->far_streams[k], hipStreamNonBlocking));
         p->far_streams_ready = true;
     }
-    std::vector<FarBlockDev> descs(items.size());
-    for (auto &bt : batches) {
-        int64_t acc = 0;
-        for (size_t k = bt.first; k < bt.last; ++k) {
-            FarBlockDev d = items[k].d;
-            d.face_off += acc;
-            d.uw_off += acc;
-            d.fib_off += acc;
-            d.gram_off += acc;
-            acc += items[k].bytes;
-            descs[k] = d;
+    hipStream_t s0 = p->far_streams[0], s1 = p->far_streams[1], s2 = p->far_streams[2];
+    enum { EV_BEGIN, EV_END, EV_F0, EV_F1, EV_K0, EV_K1, EV_K2, EV_J, EV_X, EV_T, EV_N };
+    hipEvent_t ev[EV_N];
+    for (auto &e : ev) GACA_HIP_CHECK(hipEventCreate(&e));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            for (int i = 0; i < EV_N; ++i) (void)hipEventDestroy(e[i]);
         }
-    }
-    d_items.upload(ctx, descs);
-    for (int attempt = 0; attempt < 6; ++attempt) {
-        h->d_arena.release();
-        h->d_fib.release();
-        h->d_arena.alloc(ctx, arena_cap * fac_bytes);
-        h->d_fib.alloc(ctx, fib_cap * sizeof(double2));
-        GACA_HIP_CHECK(hipMemsetAsync(d_ctr.ptr, 0, 2 * sizeof(unsigned long long), st));
-        GACA_HIP_CHECK(hipMemsetAsync(d_over.ptr, 0, sizeof(int32_t), st));
-        std::vector<hipEvent_t> evs(2 * batches.size() + 4);
-        for (auto &e : evs) GACA_HIP_CHECK(hipEventCreate(&e));
-        hipEvent_t ev_start = evs[2 * batches.size()];
-        GACA_HIP_CHECK(hipEventRecord(ev_start, st));
-        for (int k = 0; k < 3; ++k) GACA_HIP_CHECK(hipStreamWaitEvent(p->far_streams[k], ev_start, 0));
-        for (size_t bi = 0; bi < batches.size(); ++bi) {
-            const Batch &bt = batches[bi];
-            hipStream_t fs = p->far_streams[bt.kind];
-            GACA_HIP_CHECK(hipEventRecord(evs[2 * bi], fs));
-            FarLaunch fl{};
-            fl.blocks = d_items.as<FarBlockDev>() + bt.first;
-            fl.nb = (int32_t)(bt.last - bt.first);
-            fl.kind = bt.kind;
-            fl.scratch = d_scratch[bt.kind].ptr;
-            fl.mixed = h->prec == GACA_MIXED ? 1 : 0;
-            fl.meta = h->d_meta.as<FarMeta>();
-            fl.cmeta = h->d_cmeta.as<CrossMeta>();
-            fl.cross_off = h->d_cross_off.as<int64_t>();
-            fl.arena = h->d_arena.ptr;
-            fl.arena_ctr = d_ctr.as<unsigned long long>();
-            fl.arena_cap = arena_cap;
-            fl.fib_arena = h->d_fib.as<double2>();
-            fl.fib_ctr = d_ctr.as<unsigned long long>() + 1;
-            fl.fib_cap = fib_cap;
-            fl.fib_off = h->d_fib_off.as<int64_t>();
-            fl.overflow = d_over.as<int32_t>();
-            fl.dense = dense;
-            launch_far(h->kernel, p->g, p->f, P, fl, fs);
+    } ev_guard{ev};
+    GACA_HIP_CHECK(hipEventRecord(ev[EV_BEGIN], s0));
+
+    FarScratch &W = p->fsc;
+    size_t arena_used = 0, fib_used = 0;
+    h->d_arena.alloc(ctx, (size_t)std::max(1.0e5, factor_guess) * es);
+    h->d_fib.alloc(ctx, (size_t)std::max<int64_t>(1024, nfar * (int64_t)std::min(rcap, 16) * L) *
+                            sizeof(double2));
+    // algorithmic work model (flops; a complex multiply-add is 8): per quadrature point x
+    // frequency the single layer costs 105 (distance 8, sqrt 13, exp 31, sincos 36,
+    // 1/(4 pi r) 8, weight and accumulation 9), the double layer 113
+    const double f_eval = dense ? 0.0 : (h->kernel == 1 ? 113.0 : 105.0);
+    const double qpe = h->kernel == 2 ? 36.0 : 6.0;
+    double ms_phase[4] = {0, 0, 0, 0}, ms_kind[3] = {0, 0, 0}, fl_phase[4] = {0, 0, 0, 0};
+    int launches_phase[4] = {0, 0, 0, 0};
+    int iters_max = 0, n_launch = 0;
+    double evals = 0.0;
+
+    for (const auto &bt : batches) {
+        const int64_t base = bt.first;
+        const int nb = (int)(bt.second - bt.first);
+        std::vector<FarBlockDev> bdesc(desc.begin() + bt.first, desc.begin() + bt.second);
+        int64_t uw_total = 0;
+        for (auto &d : bdesc) {
+            d.uw_off = uw_total;
+            uw_total += (int64_t)d.rho_max * (d.m + d.n);
+        }
+        W.blk.upload(ctx, bdesc);
+        ensure(ctx, W.state, nb * sizeof(FarStateDev));
+        ensure(ctx, W.coef, (size_t)nb * rcap * sizeof(double2));
+        ensure(ctx, W.hs, (size_t)nb * rcap * sizeof(int64_t));
+        ensure(ctx, W.fs, (size_t)nb * rcap * sizeof(int64_t));
+        ensure(ctx, W.usedk, (size_t)nb * L);
+        ensure(ctx, W.uw, (size_t)std::max<int64_t>(uw_total, 1) * es);
+        ensure(ctx, W.act, nb * sizeof(FarActive));
+        ensure(ctx, W.status, nb * 2 * sizeof(int32_t));
+        ensure(ctx, W.copies, nb * sizeof(FarCopy));
+        ensure(ctx, W.gathers, nb * sizeof(FarGather));
+        W.h_act.ensure(nb * sizeof(FarActive));
+        W.h_status.ensure(nb * 2 * sizeof(int32_t));
+        W.h_copies.ensure(nb * sizeof(FarCopy));
+        W.h_gathers.ensure(nb * sizeof(FarGather));
+        GACA_HIP_CHECK(hipMemsetAsync(W.state.ptr, 0, nb * sizeof(FarStateDev), s0));
+        GACA_HIP_CHECK(hipMemsetAsync(W.usedk.ptr, 0, (size_t)nb * L, s0));
+        std::vector<int32_t> ell_h(nb, 0);
+        std::vector<int64_t> hcur(nb, -1), fcur(nb, -1);
+        std::vector<int> active(nb);
+        std::iota(active.begin(), active.end(), 0);
+        std::vector<FarCopy> pending;
+        int64_t hused = 0, fused = 0;
+        int iter = 0;
+
+        auto batch_dev = [&]() {
+            FarBatchDev bd{};
+            bd.blk = W.blk.as<FarBlockDev>();
+            bd.st = W.state.as<FarStateDev>();
+            bd.coef = W.coef.as<double2>();
+            bd.hs = W.hs.as<int64_t>();
+            bd.fs = W.fs.as<int64_t>();
+            bd.usedk = W.usedk.as<unsigned char>();
+            bd.hpool = W.hpool.ptr;
+            bd.fgpool = W.fgpool.as<double2>();
+            bd.uw = W.uw.ptr;
+            bd.part = W.part.as<double>();
+            bd.map_chunk = W.map_chunk.as<int32_t>();
+            bd.map_tile = W.map_tile.as<int32_t>();
+            bd.status = W.status.as<int32_t>();
+            bd.meta = h->d_meta.as<FarMeta>();
+            bd.cmeta = h->d_cmeta.as<CrossMeta>();
+            bd.dense = dense;
+            bd.mixed = mixed ? 1 : 0;
+            bd.rcap = rcap;
+            bd.L = L;
+            return bd;
+        };
+        auto flush_copies = [&]() {
+            if (pending.empty()) return;
+            std::memcpy(W.h_copies.ptr, pending.data(), pending.size() * sizeof(FarCopy));
+            GACA_HIP_CHECK(hipMemcpyAsync(W.copies.ptr, W.h_copies.ptr, pending.size() * sizeof(FarCopy),
+                                          hipMemcpyHostToDevice, s0));
+            launch_far_copy(batch_dev(), W.copies.as<FarCopy>(), (int)pending.size(), h->d_arena.ptr,
+                            h->d_cross_off.as<int64_t>(), s0);
             GACA_HIP_CHECK(hipGetLastError());
-            GACA_HIP_CHECK(hipEventRecord(evs[2 * bi + 1], fs));
+            ++n_launch;
+            pending.clear();
+        };
+
+        while (!active.empty()) {
+            // slots of this iteration's faces (a zero face keeps its slots for the next one)
+            const int64_t hprev = hused, fprev = fused;
+            for (int lb : active) {
+                const FarBlockDev &d = bdesc[lb];
+                if (hcur[lb] < 0) {
+                    hcur[lb] = hused;
+                    hused += (int64_t)d.m * d.n;
+                }
+                if (fcur[lb] < 0) {
+                    fcur[lb] = fused;
+                    fused += L + rcap;
+                }
+            }
+            if (iter == 0) {
+                // first guess of the pool sizes, kept by the problem across builds
+                double hg = 0.0;
+                for (int lb = 0; lb < nb; ++lb) hg += (double)bdesc[lb].m * bdesc[lb].n;
+                const double hcap = std::min((rguess + 1) * hg, std::max((double)hused, 0.25 * free_b / es));
+                grow_keep(ctx, W.hpool, (size_t)std::max((double)hused, hcap) * es, 0, s0);
+                grow_keep(ctx, W.fgpool, (size_t)nb * (rguess + 1) * (L + rcap) * sizeof(double2), 0, s0);
+            }
+            grow_keep(ctx, W.hpool, (size_t)hused * es, (size_t)hprev * es, s0);
+            grow_keep(ctx, W.fgpool, (size_t)fused * sizeof(double2), (size_t)fprev * sizeof(double2), s0);
+            std::stable_sort(active.begin(), active.end(), [&](int x, int y) {
+                if (kind[base + x] != kind[base + y]) return kind[base + x] > kind[base + y];
+                return (int64_t)bdesc[x].m * bdesc[x].n > (int64_t)bdesc[y].m * bdesc[y].n;
+            });
+            const int nact = (int)active.size();
+            FarActive *ha = W.h_act.as<FarActive>();
+            int64_t nchunk = 0, ntile = 0;
+            int cnt[3] = {0, 0, 0};
+            double fl_face = 0.0;
+            for (int a = 0; a < nact; ++a) {
+                const int lb = active[a];
+                const FarBlockDev &d = bdesc[lb];
+                const int kd = kind[base + lb];
+                const int64_t mn = (int64_t)d.m * d.n;
+                FarActive A{};
+                A.b = lb;
+                A.hslot = hcur[lb];
+                A.fgslot = fcur[lb];
+                A.chunk0 = nchunk;
+                nchunk += (mn + kFarChunk - 1) / kFarChunk;
+                A.tile0 = ntile;
+                A.ntile = kd == 2 ? ((d.m + kFarTile - 1) / kFarTile) * ((d.n + kFarTile - 1) / kFarTile) : 0;
+                ntile += A.ntile;
+                cnt[kd]++;
+                ha[a] = A;
+                evals += (double)mn * qpe;
+                fl_face += (double)mn * (qpe * f_eval + 8.0 * ell_h[lb]);
+            }
+            ensure(ctx, W.map_chunk, (size_t)std::max<int64_t>(nchunk, 1) * sizeof(int32_t));
+            ensure(ctx, W.map_tile, (size_t)std::max<int64_t>(ntile, 1) * sizeof(int32_t));
+            ensure(ctx, W.part, (size_t)std::max<int64_t>(ntile, 1) * PS * sizeof(double));
+            GACA_HIP_CHECK(hipMemcpyAsync(W.act.ptr, W.h_act.ptr, nact * sizeof(FarActive),
+                                          hipMemcpyHostToDevice, s0));
+            flush_copies();
+            const FarBatchDev bd = batch_dev();
+            const FarActive *dact = W.act.as<FarActive>();
+            const int nlarge = cnt[2], n1 = cnt[1], n0 = cnt[0];
+            launch_far_map(bd, dact, nact, nlarge, s0);
+            GACA_HIP_CHECK(hipEventRecord(ev[EV_F0], s0));
+            launch_far_face(h->kernel, p->g, p->f, bd, dact, nchunk, s0);
+            GACA_HIP_CHECK(hipEventRecord(ev[EV_F1], s0));
+            GACA_HIP_CHECK(hipStreamWaitEvent(s1, ev[EV_F1], 0));
+            GACA_HIP_CHECK(hipStreamWaitEvent(s2, ev[EV_F1], 0));
+            launch_far_aca(2, P, bd, dact, nlarge, s0);
+            launch_far_aca(1, P, bd, dact + nlarge, n1, s1);
+            launch_far_aca(0, P, bd, dact + nlarge + n1, n0, s2);
+            GACA_HIP_CHECK(hipGetLastError());
+            GACA_HIP_CHECK(hipEventRecord(ev[EV_K2], s0));
+            GACA_HIP_CHECK(hipEventRecord(ev[EV_K1], s1));
+            GACA_HIP_CHECK(hipEventRecord(ev[EV_K0], s2));
+            GACA_HIP_CHECK(hipStreamWaitEvent(s0, ev[EV_K1], 0));
+            GACA_HIP_CHECK(hipStreamWaitEvent(s0, ev[EV_K0], 0));
+            GACA_HIP_CHECK(hipEventRecord(ev[EV_J], s0));
+            launch_far_expand(bd, dact, ntile, s0);
+            GACA_HIP_CHECK(hipEventRecord(ev[EV_X], s0));
+            launch_far_tail(h->kernel, p->g, p->f, P, bd, dact, nact, nlarge, s0);
+            GACA_HIP_CHECK(hipGetLastError());
+            GACA_HIP_CHECK(hipEventRecord(ev[EV_T], s0));
+            GACA_HIP_CHECK(hipMemcpyAsync(W.h_status.ptr, W.status.ptr, nact * 2 * sizeof(int32_t),
+                                          hipMemcpyDeviceToHost, s0));
+            GACA_HIP_CHECK(hipStreamSynchronize(s0));
+            n_launch += 3 + (nlarge > 0) + (n1 > 0) + (n0 > 0) + (ntile > 0);
+            auto elapsed = [&](int x, int y) {
+                float ms = 0.0f;
+                GACA_HIP_CHECK(hipEventElapsedTime(&ms, ev[x], ev[y]));
+                return (double)ms;
+            };
+            ms_phase[0] += elapsed(EV_F0, EV_F1);
+            ms_phase[1] += elapsed(EV_F1, EV_J);
+            ms_phase[2] += elapsed(EV_J, EV_X);
+            ms_phase[3] += elapsed(EV_X, EV_T);
+            if (nlarge) ms_kind[2] += elapsed(EV_F1, EV_K2);
+            if (n1) ms_kind[1] += elapsed(EV_F1, EV_K1);
+            if (n0) ms_kind[0] += elapsed(EV_F1, EV_K0);
+            launches_phase[0] += 1;
+            launches_phase[1] += (nlarge > 0) + (n1 > 0) + (n0 > 0);
+            launches_phase[2] += ntile > 0;
+            launches_phase[3] += 1;
+            fl_phase[0] += fl_face;
+            // status: accepted crosses get arena space, finished blocks leave
+            const int32_t *hs_ = W.h_status.as<int32_t>();
+            std::vector<int> next;
+            next.reserve(nact);
+            const size_t arena_before = arena_used;
+            for (int a = 0; a < nact; ++a) {
+                const int lb = ha[a].b;
+                const FarBlockDev &d = bdesc[lb];
+                const int code = hs_[2 * a], rho = hs_[2 * a + 1];
+                const double mn = (double)d.m * d.n;
+                const int ell = ell_h[lb];
+                const int kd = kind[base + lb];
+                if (code & 1) {
+                    FarCopy c{};
+                    c.b = lb;
+                    c.p = ell;
+                    c.rho = rho;
+                    c.off = (int64_t)arena_used;
+                    arena_used += (size_t)rho * (d.m + d.n);
+                    pending.push_back(c);
+                    ell_h[lb] = ell + 1;
+                    hcur[lb] = -1;
+                    fcur[lb] = -1;
+                    if (kd == 2) {
+                        fl_phase[1] += 8.0 * (d.m + d.n) * (double)rho * (rho - 1.0);
+                        fl_phase[2] += 8.0 * mn * (rho + ell);
+                    } else {
+                        fl_phase[1] += 8.0 * mn * (2.0 * rho + ell);
+                    }
+                    fl_phase[3] += (double)L * qpe * f_eval + 16.0 * L * ell + 8.0 * (ell + 1.0) * (ell + 1.0);
+                    evals += (double)L * qpe;
+                } else {
+                    fl_phase[3] += 8.0 * (double)ell * ell;
+                }
+                if (!(code & 2)) next.push_back(lb);
+            }
+            if (arena_used > h->d_arena.bytes / es)
+                grow_keep(ctx, h->d_arena, arena_used * es, arena_before * es, s0);
+            active.swap(next);
+            ++iter;
         }
-        if (attempt == 0) main_work();   // near field on the context stream, concurrently
-        for (int k = 0; k < 3; ++k) {
-            hipEvent_t done = evs[2 * batches.size() + 1 + k];
-            GACA_HIP_CHECK(hipEventRecord(done, p->far_streams[k]));
-            GACA_HIP_CHECK(hipStreamWaitEvent(st, done, 0));
+        flush_copies();
+        // fibres of the batch -> fibre arena, contiguous per block
+        std::vector<FarGather> gth;
+        const size_t fib_before = fib_used;
+        for (int lb = 0; lb < nb; ++lb) {
+            FarGather g{};
+            g.b = lb;
+            g.rank = ell_h[lb];
+            g.off = (int64_t)fib_used;
+            fib_used += (size_t)ell_h[lb] * L;
+            gth.push_back(g);
         }
-        int32_t over = 0;
-        unsigned long long ctrs[2];
-        GACA_HIP_CHECK(hipMemcpyAsync(&over, d_over.ptr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        GACA_HIP_CHECK(hipMemcpyAsync(ctrs, d_ctr.ptr, sizeof(ctrs), hipMemcpyDeviceToHost, st));
-        GACA_HIP_CHECK(hipStreamSynchronize(st));
-        double by_kind[3] = {0, 0, 0}, span = 0.0;
-        int nl[3] = {0, 0, 0};
-        for (size_t bi = 0; bi < batches.size(); ++bi) {
-            float ms = 0.0f, ms_end = 0.0f;
-            GACA_HIP_CHECK(hipEventElapsedTime(&ms, evs[2 * bi], evs[2 * bi + 1]));
-            GACA_HIP_CHECK(hipEventElapsedTime(&ms_end, ev_start, evs[2 * bi + 1]));
-            by_kind[batches[bi].kind] += ms;
-            nl[batches[bi].kind] += 1;
-            span = std::max(span, (double)ms_end);
-        }
-        for (auto &e : evs) (void)hipEventDestroy(e);
-        for (int k = 0; k < 3; ++k) {
-            h->st.ms_far_by_kind[k] = by_kind[k];
-            h->st.launches_by_kind[k] = nl[k];
-        }
-        h->st.ms_far_kernel = span;
-        h->st.n_far_launches = (int32_t)batches.size();
-        h->st.far_attempts = attempt + 1;
-        if (!over) {
-            // shrink both arenas to what the build used (offsets are relative to the base)
-            compact(ctx, h->d_arena, ctrs[0] * fac_bytes, st);
-            compact(ctx, h->d_fib, ctrs[1] * sizeof(double2), st);
-            break;
-        }
-        arena_cap = std::max<uint64_t>(arena_cap * 2, ctrs[0] + 1024);
-        fib_cap = std::max<uint64_t>(fib_cap * 2, ctrs[1] + 1024);
-        if (attempt == 5) throw Error{GACA_ERR_OOM, "factor arena overflow"};
+        grow_keep(ctx, h->d_fib, std::max<size_t>(fib_used, 1) * sizeof(double2),
+                  fib_before * sizeof(double2), s0);
+        std::memcpy(W.h_gathers.ptr, gth.data(), gth.size() * sizeof(FarGather));
+        GACA_HIP_CHECK(hipMemcpyAsync(W.gathers.ptr, W.h_gathers.ptr, gth.size() * sizeof(FarGather),
+                                      hipMemcpyHostToDevice, s0));
+        launch_far_gather(batch_dev(), W.gathers.as<FarGather>(), nb, h->d_fib.as<double2>(),
+                          h->d_fib_off.as<int64_t>(), s0);
+        GACA_HIP_CHECK(hipGetLastError());
+        ++n_launch;
+        GACA_HIP_CHECK(hipStreamSynchronize(s0));
+        iters_max = std::max(iters_max, iter);
     }
+    GACA_HIP_CHECK(hipEventRecord(ev[EV_END], s0));
+    GACA_HIP_CHECK(hipStreamWaitEvent(ctx->stream, ev[EV_END], 0));
+    GACA_HIP_CHECK(hipEventSynchronize(ev[EV_END]));
+    float span = 0.0f;
+    GACA_HIP_CHECK(hipEventElapsedTime(&span, ev[EV_BEGIN], ev[EV_END]));
+    compact(ctx, h->d_arena, arena_used * es, s0);
+    compact(ctx, h->d_fib, fib_used * sizeof(double2), s0);
     GACA_HIP_CHECK(hipMemcpy(h->meta.data(), h->d_meta.ptr, nfar * sizeof(FarMeta), hipMemcpyDeviceToHost));
     GACA_HIP_CHECK(hipMemcpy(h->cmeta.data(), h->d_cmeta.ptr, nfar * rcap * sizeof(CrossMeta), hipMemcpyDeviceToHost));
     GACA_HIP_CHECK(hipMemcpy(h->cross_off.data(), h->d_cross_off.ptr, nfar * rcap * sizeof(int64_t), hipMemcpyDeviceToHost));
     GACA_HIP_CHECK(hipMemcpy(h->fib_off.data(), h->d_fib_off.ptr, nfar * sizeof(int64_t), hipMemcpyDeviceToHost));
+    gaca_stats &st = h->st;
+    st.ms_far_kernel = span;
+    st.n_far_launches = n_launch;
+    st.far_iters = iters_max;
+    st.far_kernel_evals = evals;
+    st.far_flops = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        st.ms_far_phase[k] = ms_phase[k];
+        st.launches_phase[k] = launches_phase[k];
+        st.far_flops_phase[k] = fl_phase[k];
+        st.far_flops += fl_phase[k];
+    }
+    for (int k = 0; k < 3; ++k) st.ms_far_by_kind[k] = ms_kind[k];
 }
 
 static void fill_stats(gaca_hmatrix *h) {
@@ -747,35 +969,6 @@ static void fill_stats(gaca_hmatrix *h) {
         fib_elems += (double)mt.rank * L;
         for (int k = 0; k < L; ++k) h->freq_hist[k] += used[k];
     }
-    // Algorithmic work model (FP64 flops; a complex multiply-add is 8 flops).  Per
-    // quadrature-point x frequency evaluation of the single layer: distance 8, sqrt 13
-    // (rsq + 2 Newton steps), exp 31 (reduction + degree-13 polynomial + scaling), sincos
-    // 36 (Cody-Waite reduction + two polynomials), 1/(4 pi r) 8, weight and complex
-    // accumulate 9 -> 105; the double layer adds (1 + s r), r^3 and the numerator: 113.
-    const double f_eval = h->kernel == 1 ? 113.0 : 105.0;
-    const double qpe = h->kernel == 2 ? 36.0 : 6.0;   // far-rule points per entry
-    double macs = 0.0, evals = 0.0;
-    double kmacs[3] = {0, 0, 0}, kevals[3] = {0, 0, 0};
-    for (int64_t b = 0; b < h->nfar; ++b) {
-        const FarMeta &mt = h->meta[b];
-        const double m = (double)p->part.far[b][1], n = (double)p->part.far[b][3];
-        const int kind = far_kind((int)m, (int)n, h->rcap);
-        const double macs0 = macs, evals0 = evals;
-        evals += (double)(mt.rank + mt.zero_faces) * m * n * qpe + (double)mt.rank * L * qpe;
-        for (int c = 0; c < mt.rank; ++c) {
-            const double rho = h->cmeta[b * h->rcap + c].rho;
-            macs += c * m * n;                       // residual face: previous crosses
-            macs += (m + n) * rho * (rho - 1.0);     // face ACA row/column corrections + Gram
-            macs += m * n * rho;                     // dense expansion (pivot search)
-            macs += m * n * (c + 1.0);               // <H_l, H_p>
-            macs += 2.0 * L * c;                     // fibre correction and fibre dots
-        }
-        kmacs[kind] += macs - macs0;
-        kevals[kind] += evals - evals0;
-    }
-    for (int k = 0; k < 3; ++k) s.far_flops_by_kind[k] = kevals[k] * f_eval + 8.0 * kmacs[k];
-    s.far_kernel_evals = evals;
-    s.far_flops = evals * f_eval + 8.0 * macs;
     s.rank_mean = h->nfar ? rsum / h->nfar : 0.0;
     s.face_rank_mean = nfaces > 0 ? frsum / nfaces : 0.0;
     const double eb = h->prec == GACA_FP64 ? 16.0 : 8.0;
