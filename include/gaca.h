@@ -70,8 +70,11 @@ typedef struct {
     int32_t max_face_rank;    /* cap on a face's ACA rank (default min(m, n)) */
     uint64_t max_device_bytes;/* 0 = no limit; otherwise total library device memory cap */
     uint64_t batch_bytes;     /* far-field scratch per batch of blocks (default 24 GiB) */
-    int32_t threads_small;    /* workgroup size for blocks with m*n <= 4096 (64/128/256) */
-    int32_t threads_large;    /* workgroup size for larger blocks (default 256) */
+    int32_t threads_small;    /* face-ACA workgroup size for faces with m n <= 1024 (64 or
+                                 128; default 64) */
+    int32_t threads_large;    /* face-ACA workgroup size for faces with m n > 2304 (256, 512
+                                 or 1024; default 0: 1024 while an iteration has at most two
+                                 such faces per compute unit, else 256) */
 } gaca_options;
 
 typedef struct gaca_context gaca_context;
@@ -111,8 +114,12 @@ typedef struct {
     int32_t launches_phase[4];
     double far_flops_phase[4];    /* algorithmic flops of the phase */
     /* aca phase by launch class: 0 m n <= 1024 and sides <= 64 (LDS, 64 threads), 1 m n <=
-     * 2304 and sides <= 96 (LDS, 256 threads), 2 larger (HBM, 512 threads) */
-    double ms_far_by_kind[3];
+     * 2304 and sides <= 96 (LDS, 256 threads), 2 m n <= 4096 (FP64) or 8192 (mixed) and
+     * sides <= 128 (LDS, 512 threads), 3 larger (HBM, 256 to 1024 threads) */
+    double ms_far_by_kind[4];
+    double ms_far_aca_block_max;  /* longest total face-ACA time of one block (device clock) */
+    double ms_host_setup;         /* host time of the build before the far-field launches */
+    double ms_host_finish;        /* host time of the build after the far field completed */
 } gaca_stats;
 
 int gaca_abi_version(void);

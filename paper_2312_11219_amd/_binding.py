@@ -46,7 +46,8 @@ class Stats(ctypes.Structure):
                 ("n_far_launches", I32), ("far_iters", I32), ("far_flops", F64),
                 ("far_kernel_evals", F64), ("near_kernel_evals", F64),
                 ("ms_far_phase", F64 * 4), ("launches_phase", I32 * 4),
-                ("far_flops_phase", F64 * 4), ("ms_far_by_kind", F64 * 3)]
+                ("far_flops_phase", F64 * 4), ("ms_far_by_kind", F64 * 4),
+                ("ms_far_aca_block_max", F64), ("ms_host_setup", F64), ("ms_host_finish", F64)]
 
 
 def lib_path() -> str:

@@ -163,27 +163,31 @@ struct Red {
     }
 };
 
-// sum_{qq < q} a[qq * sa] * b[qq * sb] with eight independent partial sums, so that up to
-// sixteen loads are in flight per thread (the loops are latency-bound otherwise).
-template <class T>
+// sum_{qq in [q0, q1)} a[qq * sa] * b[qq * sb] with NACC independent partial sums, so that
+// 2 NACC loads are in flight per thread (the loops are latency-bound otherwise).
+template <class T, int NACC = 8>
 __device__ __forceinline__ T dot_strided(const T *__restrict__ a, int64_t sa,
                                          const T *__restrict__ b, int64_t sb, int q0, int q1) {
-    T s[8];
+    T s[NACC];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) s[t] = czero<T>();
+    for (int t = 0; t < NACC; ++t) s[t] = czero<T>();
     int qq = q0;
-    for (; qq + 8 <= q1; qq += 8) {
-        T av[8], bv[8];
+    for (; qq + NACC <= q1; qq += NACC) {
+        T av[NACC], bv[NACC];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
+        for (int t = 0; t < NACC; ++t) {
             av[t] = a[(int64_t)(qq + t) * sa];
             bv[t] = b[(int64_t)(qq + t) * sb];
         }
 #pragma unroll
-        for (int t = 0; t < 8; ++t) s[t] = cfma(av[t], bv[t], s[t]);
+        for (int t = 0; t < NACC; ++t) s[t] = cfma(av[t], bv[t], s[t]);
     }
     for (; qq < q1; ++qq) s[0] = cfma(a[(int64_t)qq * sa], b[(int64_t)qq * sb], s[0]);
-    return cadd(cadd(cadd(s[0], s[1]), cadd(s[2], s[3])), cadd(cadd(s[4], s[5]), cadd(s[6], s[7])));
+#pragma unroll
+    for (int w = NACC / 2; w > 0; w /= 2)
+#pragma unroll
+        for (int t = 0; t < w; ++t) s[t] = cadd(s[t], s[t + w]);
+    return s[0];
 }
 
 }  // namespace gaca

@@ -189,39 +189,10 @@ __device__ int first_unused(const unsigned char *used, int len, Red<NT> &red) {
     return red.imin(c);
 }
 
-// <H_l, H_p>_F for p < ell (FP64 sums, four p per wave iteration), H_l given by a
-// callable hl(idx); lane 0 of the owning wave writes G[p].
-template <int NT, class FT, class HL>
-__device__ void gram_row(const HL &hl, const FT *hpool, const int64_t *hs, int ell, int64_t mn,
-                         double2 *G) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    constexpr int NW = NT / 64;
-    for (int p0 = wave * 4; p0 < ell; p0 += NW * 4) {
-        double gr[4] = {0, 0, 0, 0}, gi[4] = {0, 0, 0, 0};
-        const int np = min(4, ell - p0);
-        for (int64_t idx = lane; idx < mn; idx += 64) {
-            const double2 h = to_d2(hl(idx));
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                if (t < np) {
-                    const double2 v = cmulc(h, to_d2(hpool[hs[p0 + t] + idx]));
-                    gr[t] += v.x;
-                    gi[t] += v.y;
-                }
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            gr[t] = wave_sum(gr[t]);
-            gi[t] = wave_sum(gi[t]);
-        }
-        if (lane == 0)
-            for (int t = 0; t < np; ++t) G[p0 + t] = make_double2(gr[t], gi[t]);
-    }
-}
-
 // ---------------------------------------------------------------------------------------
 // ACA phase, small faces: R and S in LDS, updated in place by the rank-1 steps.  Also
-// stores H_l = S over R, finds its pivot and writes the Gram row of the new cross.
+// stores H_l = S over R, and finds its max, norm and pivot (the Gram row against the
+// previous faces follows in far_gram_small_kernel).
 template <int NT, bool MIXED, int MNMAX, int SIDE>
 __global__ void __launch_bounds__(NT)
     far_aca_small_kernel(AcaParams P, FarBatchDev bd, const FarActive *act) {
@@ -229,30 +200,29 @@ __global__ void __launch_bounds__(NT)
     const FarActive A = act[blockIdx.x];
     const int b = A.b;
     const FarBlockDev B = bd.blk[b];
-    const int m = B.m, n = B.n, mn = m * n, L = bd.L;
+    const int m = B.m, n = B.n, mn = m * n;
     const int tid = threadIdx.x;
-    const int ell = bd.st[b].ell;
     const double zero_tol = bd.st[b].zero_tol, ref2 = bd.st[b].ref2;
     FT *R = reinterpret_cast<FT *>(bd.hpool) + A.hslot;
     FT *Ub = reinterpret_cast<FT *>(bd.uw) + B.uw_off;
     FT *Wb = Ub + (int64_t)B.rho_max * m;
 
+    const int64_t t_start = wall_clock64();
     __shared__ FT Rs[MNMAX];
     __shared__ FT Ss[MNMAX];
     __shared__ FT ucol[SIDE];
     __shared__ FT wrow[SIDE];
     __shared__ unsigned char used_row[SIDE];
-    __shared__ int64_t hsl[kMaxRcap];
     __shared__ double redbuf[4 * (NT / 64) + 4];
     Red<NT> red{redbuf};
     const double tie2 = (1.0 - P.tie) * (1.0 - P.tie);
 
+#pragma unroll 8
     for (int idx = tid; idx < mn; idx += NT) {
         Rs[idx] = R[idx];
         Ss[idx] = czero<FT>();
     }
     for (int r = tid; r < m; r += NT) used_row[r] = 0;
-    for (int p = tid; p < ell; p += NT) hsl[p] = bd.hs[(int64_t)b * bd.rcap + p];
     __syncthreads();
     int q = 0, i = 0, nused = 0;
     double s2 = 0.0;
@@ -328,10 +298,6 @@ __global__ void __launch_bounds__(NT)
                 break;
             }
         pidx = min(red.imin(pc), mn - 1);
-        double2 *G = bd.fgpool + A.fgslot + L;
-        gram_row<NT, FT>([&](int64_t idx) { return Ss[idx]; },
-                         reinterpret_cast<const FT *>(bd.hpool), hsl, ell, (int64_t)mn, G);
-        if (tid == 0) G[ell] = make_double2(h2, 0.0);
     }
     if (tid == 0) {
         FarStateDev *S = bd.st + b;
@@ -339,15 +305,19 @@ __global__ void __launch_bounds__(NT)
         S->pidx = pidx;
         S->mxh = mxh;
         S->h2 = h2;
+        S->aca_ticks += wall_clock64() - t_start;
     }
 }
 
-// ACA phase, large faces: R and the factor history in HBM (L2 resident), row and column
-// corrections split over thread groups with pipelined loads.
-template <int NT, bool MIXED>
+// ACA phase, large faces: R in HBM; the factor history u_q', w_q' in LDS for the first qL
+// steps (as many as fit) and in HBM beyond, so the row / column corrections and the cross
+// terms of the stopping norm mostly read LDS.  Row and column corrections are split over
+// thread groups.
+template <int NT, bool MIXED, int HB>
 __global__ void __launch_bounds__(NT)
     far_aca_large_kernel(AcaParams P, FarBatchDev bd, const FarActive *act) {
     using FT = face_t<MIXED>;
+    const int64_t t_start = wall_clock64();
     const FarActive A = act[blockIdx.x];
     const int b = A.b;
     const FarBlockDev B = bd.blk[b];
@@ -360,11 +330,33 @@ __global__ void __launch_bounds__(NT)
     FT *Ub = reinterpret_cast<FT *>(bd.uw) + B.uw_off;
     FT *Wb = Ub + (int64_t)B.rho_max * m;
 
+    __shared__ double2 hist_raw[HB / sizeof(double2)];
     __shared__ FT part[NT];       // split-K partial sums of row / column corrections
     __shared__ unsigned char used_row[kMaxRowsLds];
     __shared__ double redbuf[4 * NW + 4];
     Red<NT> red{redbuf};
     const double tie2 = (1.0 - P.tie) * (1.0 - P.tie);
+    const int qL = min(B.rho_max, (int)(HB / ((int64_t)(m + n) * (int64_t)sizeof(FT))));
+    FT *Uh = reinterpret_cast<FT *>(hist_raw);       // [qL][m]
+    FT *Wh = Uh + (int64_t)qL * m;                    // [qL][n]
+
+    // sum_{q' in [q0, q1)} a_q'[ia] b_q'[ib] over the histories (LDS part, then HBM part)
+    auto hdot = [&](const FT *ah, const FT *ag, int la, int ia, const FT *bh, const FT *bg,
+                    int lb, int ib, int q0, int q1) {
+        FT acc0 = czero<FT>(), acc1 = czero<FT>();
+        const int qm = min(q1, qL);
+        int qq = q0;
+        for (; qq + 1 < qm; qq += 2) {
+            acc0 = cfma(ah[qq * la + ia], bh[qq * lb + ib], acc0);
+            acc1 = cfma(ah[(qq + 1) * la + ia], bh[(qq + 1) * lb + ib], acc1);
+        }
+        if (qq < qm) acc0 = cfma(ah[qq * la + ia], bh[qq * lb + ib], acc0);
+        FT acc = cadd(acc0, acc1);
+        if (q1 > qL)
+            acc = cadd(acc, dot_strided<FT, (NT >= 1024 ? 4 : 8)>(ag + ia, la, bg + ib, lb,
+                                                                    max(q0, qL), q1));
+        return acc;
+    };
 
     for (int r = tid; r < m; r += NT) used_row[r] = 0;
     __syncthreads();
@@ -380,7 +372,7 @@ __global__ void __launch_bounds__(NT)
             const int s = tid / n, j = tid - s * n;
             if (s < splitw) {
                 const int q0 = (int)((int64_t)q * s / splitw), q1 = (int)((int64_t)q * (s + 1) / splitw);
-                part[tid] = dot_strided<FT>(Ub + i, m, Wb + j, n, q0, q1);
+                part[tid] = hdot(Uh, Ub, m, i, Wh, Wb, n, j, q0, q1);
             }
             __syncthreads();
             if (tid < n) {
@@ -391,7 +383,7 @@ __global__ void __launch_bounds__(NT)
             }
         } else {
             for (int j = tid; j < n; j += NT) {
-                FT v = csub(R[(int64_t)i * n + j], dot_strided<FT>(Ub + i, m, Wb + j, n, 0, q));
+                FT v = csub(R[(int64_t)i * n + j], hdot(Uh, Ub, m, i, Wh, Wb, n, j, 0, q));
                 Wq[j] = v;
                 mx = fmax(mx, cabs2(v));
             }
@@ -418,66 +410,59 @@ __global__ void __launch_bounds__(NT)
         __syncthreads();
         double nw2 = 0.0, nu2 = 0.0;
         for (int j = tid; j < n; j += NT) {
-            FT w = cdiv(Wq[j], piv);
+            const FT w = cdiv(Wq[j], piv);
             Wq[j] = w;
+            if (q < qL) Wh[q * n + j] = w;
             nw2 += cabs2(w);
         }
+        __syncthreads();
         // column jp of R - sum_{q'<q} w_q'[jp] u_q'
         if (splitu > 1) {
             const int s = tid / m, r = tid - s * m;
             if (s < splitu) {
                 const int q0 = (int)((int64_t)q * s / splitu), q1 = (int)((int64_t)q * (s + 1) / splitu);
-                part[tid] = dot_strided<FT>(Wb + jp, n, Ub + r, m, q0, q1);
+                part[tid] = hdot(Wh, Wb, n, jp, Uh, Ub, m, r, q0, q1);
             }
             __syncthreads();
             if (tid < m) {
                 FT u = R[(int64_t)tid * n + jp];
                 for (int t = 0; t < splitu; ++t) u = csub(u, part[t * m + tid]);
                 Uq[tid] = u;
+                if (q < qL) Uh[q * m + tid] = u;
                 nu2 += cabs2(u);
             }
         } else {
             for (int r = tid; r < m; r += NT) {
-                FT u = csub(R[(int64_t)r * n + jp], dot_strided<FT>(Wb + jp, n, Ub + r, m, 0, q));
+                const FT u = csub(R[(int64_t)r * n + jp], hdot(Wh, Wb, n, jp, Uh, Ub, m, r, 0, q));
                 Uq[r] = u;
+                if (q < qL) Uh[q * m + r] = u;
                 nu2 += cabs2(u);
             }
         }
         __syncthreads();
-        // sum_{q'<q} Re(<u_q, u_q'> <w_q, w_q'>) in FP64: four q' per wave iteration
+        // sum_{q'<q} Re(<u_q, u_q'> <w_q, w_q'>) in FP64, one q' per wave iteration
+        const FT *uc = q < qL ? Uh + (int64_t)q * m : Uq;
+        const FT *wc = q < qL ? Wh + (int64_t)q * n : Wq;
         double cr = 0.0;
-        for (int q0 = wave * 4; q0 < q; q0 += NW * 4) {
-            const int nq = min(4, q - q0);
-            double ur[4] = {0, 0, 0, 0}, ui[4] = {0, 0, 0, 0}, wr[4] = {0, 0, 0, 0},
-                   wi[4] = {0, 0, 0, 0};
+        for (int qq = wave; qq < q; qq += NW) {
+            const FT *up = qq < qL ? Uh + (int64_t)qq * m : Ub + (int64_t)qq * m;
+            const FT *wp = qq < qL ? Wh + (int64_t)qq * n : Wb + (int64_t)qq * n;
+            double ur = 0.0, ui = 0.0, wr = 0.0, wi = 0.0;
             for (int r = lane; r < m; r += 64) {
-                const double2 u = to_d2(Uq[r]);
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    if (t < nq) {
-                        double2 v = cmulc(u, to_d2(Ub[(int64_t)(q0 + t) * m + r]));
-                        ur[t] += v.x;
-                        ui[t] += v.y;
-                    }
+                const double2 v = cmulc(to_d2(uc[r]), to_d2(up[r]));
+                ur += v.x;
+                ui += v.y;
             }
             for (int j = lane; j < n; j += 64) {
-                const double2 w = to_d2(Wq[j]);
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    if (t < nq) {
-                        double2 v = cmulc(w, to_d2(Wb[(int64_t)(q0 + t) * n + j]));
-                        wr[t] += v.x;
-                        wi[t] += v.y;
-                    }
+                const double2 v = cmulc(to_d2(wc[j]), to_d2(wp[j]));
+                wr += v.x;
+                wi += v.y;
             }
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                ur[t] = wave_sum(ur[t]);
-                ui[t] = wave_sum(ui[t]);
-                wr[t] = wave_sum(wr[t]);
-                wi[t] = wave_sum(wi[t]);
-                if (t < nq) cr += ur[t] * wr[t] - ui[t] * wi[t];
-            }
+            ur = wave_sum(ur);
+            ui = wave_sum(ui);
+            wr = wave_sum(wr);
+            wi = wave_sum(wi);
+            cr += ur * wr - ui * wi;
         }
         if (lane != 0) cr = 0.0;
         red.sum3(nu2, nw2, cr);
@@ -487,7 +472,10 @@ __global__ void __launch_bounds__(NT)
             break;
         i = pick_unused<NT>(Uq, used_row, m, tie2, red);
     }
-    if (tid == 0) bd.st[b].rho = q;
+    if (tid == 0) {
+        bd.st[b].rho = q;
+        bd.st[b].aca_ticks += wall_clock64() - t_start;
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -593,6 +581,52 @@ __global__ void __launch_bounds__(256) far_expand_kernel(FarBatchDev bd, const F
     }
 }
 
+// Gram row <H_l, H_p> (p < l) of a small face (kinds 0/1, H_l already stored by the ACA
+// phase), one workgroup per face, written as the face's single partial row.
+__global__ void __launch_bounds__(256) far_gram_small_kernel(FarBatchDev bd, const FarActive *act) {
+    const FarActive A = act[blockIdx.x];
+    const int b = A.b;
+    const int rho = bd.st[b].rho, ell = bd.st[b].ell;
+    if (rho == 0) return;
+    const FarBlockDev B = bd.blk[b];
+    const int mn = B.m * B.n, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    __shared__ int64_t hsl[kMaxRcap];
+    __shared__ double red8[8][4];
+    for (int p = tid; p < ell; p += 256) hsl[p] = bd.hs[(int64_t)b * bd.rcap + p];
+    __syncthreads();
+    double *out = bd.part + A.tile0 * (int64_t)far_part_stride(bd.rcap);
+    auto run = [&](auto tag) {
+        using FT = decltype(tag);
+        const FT *hp = reinterpret_cast<const FT *>(bd.hpool);
+        const FT *H = hp + A.hslot;
+        for (int p0 = 0; p0 < ell; p0 += 4) {
+            const int np = min(4, ell - p0);
+            double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int idx = tid; idx < mn; idx += 256) {
+                const double2 h = to_d2(H[idx]);
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt)
+                    if (tt < np) {
+                        const double2 v = cmulc(h, to_d2(hp[hsl[p0 + tt] + idx]));
+                        g[2 * tt] += v.x;
+                        g[2 * tt + 1] += v.y;
+                    }
+            }
+#pragma unroll
+            for (int v = 0; v < 8; ++v) g[v] = wave_sum(g[v]);
+            __syncthreads();
+            if (lane == 0)
+#pragma unroll
+                for (int v = 0; v < 8; ++v) red8[v][wave] = g[v];
+            __syncthreads();
+            if (tid < 2 * np)
+                out[2 + 2 * p0 + tid] = (red8[tid][0] + red8[tid][1]) + (red8[tid][2] + red8[tid][3]);
+        }
+    };
+    if (bd.mixed) run(float2{});
+    else run(double2{});
+}
+
 // ---------------------------------------------------------------------------------------
 // Tail phase: one workgroup per active block.
 template <int KERNEL, bool DENSE, bool MIXED>
@@ -685,7 +719,12 @@ __global__ void __launch_bounds__(256)
             mxh = S.mxh;
             h2 = S.h2;
             pidx = S.pidx;
-            for (int p = tid; p < ell; p += NT) gsh[p] = fg[A.fgslot + L + p];
+            const double *pt = bd.part + A.tile0 * (int64_t)far_part_stride(rcap);
+            for (int p = tid; p < ell; p += NT) {
+                gsh[p] = make_double2(pt[2 + 2 * p], pt[3 + 2 * p]);
+                fg[A.fgslot + L + p] = gsh[p];
+            }
+            if (tid == 0) fg[A.fgslot + L + ell] = make_double2(h2, 0.0);
         }
         (void)mxh;
         const double2 hpiv = to_d2(H[pidx]);
@@ -772,7 +811,7 @@ __global__ void __launch_bounds__(256)
             mt.sum_rho = S.sum_rho;
             mt.capped = S.capped;
             mt.zero_faces = S.zero_faces;
-            mt.fac_off = 0;
+            mt.aca_ticks = S.aca_ticks;
             mt.norm2 = S.norm2;
             bd.meta[B.out_idx] = mt;
         }
@@ -839,27 +878,44 @@ void launch_far_face(int kernel, const GeoDev &g, const FreqDev &f, const FarBat
 }
 
 template <bool MX>
-static void aca_dispatch(int kind, const AcaParams &P, const FarBatchDev &bd,
+static void aca_dispatch(int kind, int threads, const AcaParams &P, const FarBatchDev &bd,
                          const FarActive *act, int nact, hipStream_t st) {
-    if (kind == 0)
-        far_aca_small_kernel<64, MX, 1024, 64><<<nact, 64, 0, st>>>(P, bd, act);
-    else if (kind == 1)
+    if (kind == 0) {
+        if (threads >= 128) far_aca_small_kernel<128, MX, 1024, 64><<<nact, 128, 0, st>>>(P, bd, act);
+        else far_aca_small_kernel<64, MX, 1024, 64><<<nact, 64, 0, st>>>(P, bd, act);
+    } else if (kind == 1) {
         far_aca_small_kernel<256, MX, 2304, 96><<<nact, 256, 0, st>>>(P, bd, act);
-    else
-        far_aca_large_kernel<512, MX><<<nact, 512, 0, st>>>(P, bd, act);
+    } else if (kind == 2) {
+        // R and S in 128 KB of LDS: 4096 FP64 or 8192 FP32 complex entries each
+        far_aca_small_kernel<512, MX, (MX ? 8192 : 4096), 128><<<nact, 512, 0, st>>>(P, bd, act);
+    } else {
+        // latency shapes (few faces, one per CU): 1024 or 512 threads with ~110 KB of LDS
+        // history; throughput shape (many faces): 256 threads with 32 KB, several per CU
+        if (threads >= 1024)
+            far_aca_large_kernel<1024, MX, 106496><<<nact, 1024, 0, st>>>(P, bd, act);
+        else if (threads >= 512)
+            far_aca_large_kernel<512, MX, 114688><<<nact, 512, 0, st>>>(P, bd, act);
+        else
+            far_aca_large_kernel<256, MX, 32768><<<nact, 256, 0, st>>>(P, bd, act);
+    }
 }
 
-void launch_far_aca(int kind, const AcaParams &P, const FarBatchDev &bd, const FarActive *act,
-                    int nact, hipStream_t st) {
+void launch_far_aca(int kind, int threads, const AcaParams &P, const FarBatchDev &bd,
+                    const FarActive *act, int nact, hipStream_t st) {
     if (nact <= 0) return;
-    if (bd.mixed) aca_dispatch<true>(kind, P, bd, act, nact, st);
-    else aca_dispatch<false>(kind, P, bd, act, nact, st);
+    if (bd.mixed) aca_dispatch<true>(kind, threads, P, bd, act, nact, st);
+    else aca_dispatch<false>(kind, threads, P, bd, act, nact, st);
 }
 
 void launch_far_expand(const FarBatchDev &bd, const FarActive *act, int64_t ntile, hipStream_t st) {
     if (ntile <= 0) return;
     if (bd.mixed) far_expand_kernel<true><<<(unsigned)ntile, 256, 0, st>>>(bd, act);
     else far_expand_kernel<false><<<(unsigned)ntile, 256, 0, st>>>(bd, act);
+}
+
+void launch_far_gram_small(const FarBatchDev &bd, const FarActive *act, int nact, hipStream_t st) {
+    if (nact <= 0) return;
+    far_gram_small_kernel<<<nact, 256, 0, st>>>(bd, act);
 }
 
 template <int K, bool D, bool MX>

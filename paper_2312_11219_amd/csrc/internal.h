@@ -90,6 +90,7 @@ struct FarStateDev {
     double norm2, scale;       // ||C^(l)||_F^2 and max_p |H_p[i_p, j_p]| max_k |f_p[k]|
     double ref2, zero_tol;     // current face: ||C^(l-1)(:,:,k)||^2 (face frame), zero threshold
     double mxh, h2;            // current face: max |H_l|^2 and ||H_l||_F^2, small blocks
+    int64_t aca_ticks;         // device wall-clock ticks spent in the face ACAs so far
 };
 
 // Per-block result metadata written by the far-field kernel.
@@ -98,7 +99,7 @@ struct FarMeta {
     int32_t sum_rho;
     int32_t capped;
     int32_t zero_faces;
-    int64_t fac_off;           // offset (complex elements) of this block's factors in the arena
+    int64_t aca_ticks;         // device wall-clock ticks of the block's face ACAs (sum)
     double norm2;
 };
 

@@ -32,23 +32,24 @@ void launch_near_galerkin(int tier, const GeoDev &g, const QuadDev &q, const Fre
 // Far field 3D-ACA, run as iterations over all unfinished blocks of a batch; one iteration
 // adds one face (one 3-D cross, or one zero face) to every active block in four phases:
 //   face    residual face R = ENTRY(:, :, k) - sum_p coef_p H_p, all entries in parallel
-//   aca     partial-pivot ACA of R, one workgroup per block (kinds 0/1: R in LDS, which also
-//           expand H_l, pick the pivot and form the Gram row; kind 2: R in HBM)
-//   expand  kind 2: H_l = U W^T in 32 x 32 tiles with per-tile max, norm and Gram partials
+//   aca     partial-pivot ACA of R, one workgroup per block (kinds 0-2: R and S in LDS, which
+//           also expand H_l and pick the pivot; kind 3: R in HBM)
+//   expand  kind 3: H_l = U W^T in 32 x 32 tiles with per-tile max, norm and Gram partials;
+//           kinds 0-2: the Gram row of H_l (one partial row per face)
 //   tail    pivot (kind 2), fibre, eq. (norm), stop test, next frequency and coefficients
 constexpr int kFarChunk = 256;   // face entries per workgroup of the face phase
 constexpr int kFarTile = 32;     // expand tile side
 constexpr int kFarMaxRows = 8192; // rows / columns of a far block
 __host__ __device__ constexpr int far_part_stride(int rcap) { return 2 + 2 * rcap; }
 
-// One active block of an iteration (host-built, sorted kind 2, kind 1, kind 0).
+// One active block of an iteration (host-built, sorted kind 3, 2, 1, 0).
 struct FarActive {
     int32_t b;          // batch-local block index
-    int32_t ntile;      // expand tiles (kind 2)
+    int32_t ntile;      // expand tiles (kind 3)
     int64_t hslot;      // face-type element offset of this face's slot in the H pool
     int64_t fgslot;     // double2 offset of this cross's fibre (L) + Gram row (rcap) slot
     int64_t chunk0;     // first face-phase chunk
-    int64_t tile0;      // first expand tile (kind 2)
+    int64_t tile0;      // first expand tile (kind 3) or the face's partial row (kinds 0-2)
 };
 
 struct FarCopy {        // factors of an accepted cross -> arena
@@ -83,10 +84,14 @@ void launch_far_map(const FarBatchDev &bd, const FarActive *act, int nact, int n
                     hipStream_t st);
 void launch_far_face(int kernel, const GeoDev &g, const FreqDev &f, const FarBatchDev &bd,
                      const FarActive *act, int64_t nchunk, hipStream_t st);
-// kind 0/1/2 on act[0 .. nact)
-void launch_far_aca(int kind, const AcaParams &P, const FarBatchDev &bd, const FarActive *act,
-                    int nact, hipStream_t st);
+// Classes: kind 0 m n <= 1024, sides <= 64; kind 1 m n <= 2304, sides <= 96; kind 2 m n <=
+// 4096 (FP64) or 8192 (mixed), sides <= 128; kind 3 larger.  threads: workgroup size
+// (kind 0: 64 or 128; kind 3: 256, 512 or 1024; kind 1: 256; kind 2: 512).
+void launch_far_aca(int kind, int threads, const AcaParams &P, const FarBatchDev &bd,
+                    const FarActive *act, int nact, hipStream_t st);
 void launch_far_expand(const FarBatchDev &bd, const FarActive *act, int64_t ntile, hipStream_t st);
+// Gram rows of LDS-resident faces (kinds 0-2) into their single partial row (FarActive::tile0)
+void launch_far_gram_small(const FarBatchDev &bd, const FarActive *act, int nact, hipStream_t st);
 void launch_far_tail(int kernel, const GeoDev &g, const FreqDev &f, const AcaParams &P,
                      const FarBatchDev &bd, const FarActive *act, int nact, int nlarge,
                      hipStream_t st);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -18,6 +19,7 @@ using namespace gaca;
 // device buffers with accounting against max_device_bytes
 struct gaca_context {
     int device = 0;
+    int n_cu = 256;           // compute units of the device
     hipStream_t stream = nullptr;
     uint64_t limit = 0;       // 0: none
     uint64_t in_use = 0;
@@ -148,7 +150,7 @@ struct gaca_problem {
     // leaves for the apply
     std::vector<int32_t> leaf_r0, leaf_m;
     // far-field launch classes run concurrently on these streams (default priority)
-    hipStream_t far_streams[3] = {nullptr, nullptr, nullptr};
+    hipStream_t far_streams[4] = {nullptr, nullptr, nullptr, nullptr};
     bool far_streams_ready = false;
     FarScratch fsc;
     ~gaca_problem() {
@@ -200,6 +202,12 @@ gaca_status gaca_context_create(int device, void *hip_stream, gaca_context **out
         auto *c = new gaca_context;
         c->device = device;
         c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+            ncu > 0)
+            c->n_cu = ncu;
+        else
+            (void)hipGetLastError();
         *out = c;
     });
 }
@@ -482,12 +490,14 @@ gaca_status gaca_problem_blocks(const gaca_problem *p, int64_t *far4, int64_t *n
 
 // ---------------------------------------------------------------------------------------
 // far-field build
-// Launch class of a far block in the aca phase: small faces stay in LDS.
-static int far_kind(int m, int n) {
+// Launch class of a far block in the aca phase: faces of kinds 0-2 stay in LDS (R and S,
+// up to 128 KB), kind 3 keeps R in HBM.
+static int far_kind(int m, int n, bool mixed) {
     const int64_t mn = (int64_t)m * n;
     if (mn <= 1024 && m <= 64 && n <= 64) return 0;
     if (mn <= 2304 && m <= 96 && n <= 96) return 1;
-    return 2;
+    if (mn <= (mixed ? 8192 : 4096) && m <= 128 && n <= 128) return 2;
+    return 3;
 }
 
 // Grow buf to at least need bytes keeping its first `used` bytes (stream-ordered copy).
@@ -524,7 +534,12 @@ static void compact(gaca_context *ctx, DevBuf &buf, size_t used, hipStream_t st)
 // four phases over the unfinished blocks until every block has stopped.  The host assigns
 // the H / fibre slots of each face and the arena offsets of accepted factors, so storage
 // is exact and the layout does not depend on the order in which workgroups run.
+static double wall_ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
 static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<void()> &main_work) {
+    const auto t_entry = std::chrono::steady_clock::now();
     gaca_problem *p = h->p;
     gaca_context *ctx = p->ctx;
     const auto &far = p->part.far;
@@ -609,13 +624,14 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             d.kappa = (float)kap;
         }
         desc[b] = d;
-        kind[b] = far_kind(m, n);
+        kind[b] = far_kind(m, n, mixed);
         const double mn = (double)m * n;
-        const double tiles = kind[b] == 2 ? std::ceil(m / 32.0) * std::ceil(n / 32.0) : 0.0;
+        const double tiles = kind[b] == 3 ? std::ceil(m / 32.0) * std::ceil(n / 32.0) : 1.0;
         est[b] = (double)rho_max * (m + n) * es + (rguess + 1) * mn * es +
                  rguess * (double)(L + rcap) * 16 + tiles * PS * 8 + sizeof(FarStateDev) +
                  sizeof(FarBlockDev) + rcap * 32.0 + L + 64;
-        factor_guess += std::min(mn * L, (double)std::min(rcap, 16) * std::min(rho_max, 24) * (m + n));
+        // first guess of the factor storage (the arena grows by half when it runs short)
+        factor_guess += std::min(mn * L, (double)std::min(rcap, 8) * std::min(rho_max, 16) * (m + n));
     }
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
@@ -634,12 +650,14 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
 
     main_work();   // near field on the context stream, concurrently with the far field
     if (!p->far_streams_ready) {
-        for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < 4; ++k)
             GACA_HIP_CHECK(hipStreamCreateWithFlags(&p->far_streams[k], hipStreamNonBlocking));
         p->far_streams_ready = true;
     }
-    hipStream_t s0 = p->far_streams[0], s1 = p->far_streams[1], s2 = p->far_streams[2];
-    enum { EV_BEGIN, EV_END, EV_F0, EV_F1, EV_K0, EV_K1, EV_K2, EV_J, EV_X, EV_T, EV_N };
+    hipStream_t s0 = p->far_streams[0];
+    // the aca phase of kind k runs on ks[k] (kind 3, the large faces, on the main far stream)
+    const hipStream_t ks[4] = {p->far_streams[3], p->far_streams[2], p->far_streams[1], s0};
+    enum { EV_BEGIN, EV_END, EV_F0, EV_F1, EV_K0, EV_K1, EV_K2, EV_K3, EV_J, EV_X, EV_T, EV_N };
     hipEvent_t ev[EV_N];
     for (auto &e : ev) GACA_HIP_CHECK(hipEventCreate(&e));
     struct EvGuard {
@@ -649,6 +667,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
         }
     } ev_guard{ev};
     GACA_HIP_CHECK(hipEventRecord(ev[EV_BEGIN], s0));
+    const double ms_setup = wall_ms_since(t_entry);
 
     FarScratch &W = p->fsc;
     size_t arena_used = 0, fib_used = 0;
@@ -660,7 +679,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
     // 1/(4 pi r) 8, weight and accumulation 9), the double layer 113
     const double f_eval = dense ? 0.0 : (h->kernel == 1 ? 113.0 : 105.0);
     const double qpe = h->kernel == 2 ? 36.0 : 6.0;
-    double ms_phase[4] = {0, 0, 0, 0}, ms_kind[3] = {0, 0, 0}, fl_phase[4] = {0, 0, 0, 0};
+    double ms_phase[4] = {0, 0, 0, 0}, ms_kind[4] = {0, 0, 0, 0}, fl_phase[4] = {0, 0, 0, 0};
     int launches_phase[4] = {0, 0, 0, 0};
     int iters_max = 0, n_launch = 0;
     double evals = 0.0;
@@ -749,12 +768,13 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
                 }
             }
             if (iter == 0) {
-                // first guess of the pool sizes, kept by the problem across builds
+                // first guess of the pool sizes (12 faces per block), kept by the problem
+                // across builds; both grow by half when they run short
                 double hg = 0.0;
                 for (int lb = 0; lb < nb; ++lb) hg += (double)bdesc[lb].m * bdesc[lb].n;
-                const double hcap = std::min((rguess + 1) * hg, std::max((double)hused, 0.25 * free_b / es));
+                const double hcap = std::min(13.0 * hg, std::max((double)hused, 0.3 * free_b / es));
                 grow_keep(ctx, W.hpool, (size_t)std::max((double)hused, hcap) * es, 0, s0);
-                grow_keep(ctx, W.fgpool, (size_t)nb * (rguess + 1) * (L + rcap) * sizeof(double2), 0, s0);
+                grow_keep(ctx, W.fgpool, (size_t)nb * 13 * (L + rcap) * sizeof(double2), 0, s0);
             }
             grow_keep(ctx, W.hpool, (size_t)hused * es, (size_t)hprev * es, s0);
             grow_keep(ctx, W.fgpool, (size_t)fused * sizeof(double2), (size_t)fprev * sizeof(double2), s0);
@@ -765,7 +785,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             const int nact = (int)active.size();
             FarActive *ha = W.h_act.as<FarActive>();
             int64_t nchunk = 0, ntile = 0;
-            int cnt[3] = {0, 0, 0};
+            int cnt[4] = {0, 0, 0, 0};
             double fl_face = 0.0;
             for (int a = 0; a < nact; ++a) {
                 const int lb = active[a];
@@ -779,37 +799,50 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
                 A.chunk0 = nchunk;
                 nchunk += (mn + kFarChunk - 1) / kFarChunk;
                 A.tile0 = ntile;
-                A.ntile = kd == 2 ? ((d.m + kFarTile - 1) / kFarTile) * ((d.n + kFarTile - 1) / kFarTile) : 0;
+                A.ntile = kd == 3 ? ((d.m + kFarTile - 1) / kFarTile) * ((d.n + kFarTile - 1) / kFarTile) : 0;
                 ntile += A.ntile;
                 cnt[kd]++;
                 ha[a] = A;
                 evals += (double)mn * qpe;
                 fl_face += (double)mn * (qpe * f_eval + 8.0 * ell_h[lb]);
             }
+            // small faces: one partial row each (their Gram row), after the expand tiles
+            for (int a = cnt[3]; a < nact; ++a) ha[a].tile0 = ntile + (a - cnt[3]);
+            const int64_t nparts = ntile + (nact - cnt[3]);
             ensure(ctx, W.map_chunk, (size_t)std::max<int64_t>(nchunk, 1) * sizeof(int32_t));
             ensure(ctx, W.map_tile, (size_t)std::max<int64_t>(ntile, 1) * sizeof(int32_t));
-            ensure(ctx, W.part, (size_t)std::max<int64_t>(ntile, 1) * PS * sizeof(double));
+            ensure(ctx, W.part, (size_t)std::max<int64_t>(nparts, 1) * PS * sizeof(double));
             GACA_HIP_CHECK(hipMemcpyAsync(W.act.ptr, W.h_act.ptr, nact * sizeof(FarActive),
                                           hipMemcpyHostToDevice, s0));
             flush_copies();
             const FarBatchDev bd = batch_dev();
             const FarActive *dact = W.act.as<FarActive>();
-            const int nlarge = cnt[2], n1 = cnt[1], n0 = cnt[0];
+            const int nlarge = cnt[3];
+            // act is ordered kind 3, 2, 1, 0
+            const int first[4] = {cnt[3] + cnt[2] + cnt[1], cnt[3] + cnt[2], cnt[3], 0};
             launch_far_map(bd, dact, nact, nlarge, s0);
             GACA_HIP_CHECK(hipEventRecord(ev[EV_F0], s0));
             launch_far_face(h->kernel, p->g, p->f, bd, dact, nchunk, s0);
             GACA_HIP_CHECK(hipEventRecord(ev[EV_F1], s0));
-            GACA_HIP_CHECK(hipStreamWaitEvent(s1, ev[EV_F1], 0));
-            GACA_HIP_CHECK(hipStreamWaitEvent(s2, ev[EV_F1], 0));
-            launch_far_aca(2, P, bd, dact, nlarge, s0);
-            launch_far_aca(1, P, bd, dact + nlarge, n1, s1);
-            launch_far_aca(0, P, bd, dact + nlarge + n1, n0, s2);
+            for (int k = 0; k < 3; ++k) GACA_HIP_CHECK(hipStreamWaitEvent(ks[k], ev[EV_F1], 0));
+            // large faces: one big workgroup per face while they fit the chip at once (the
+            // aca phase is then bound by the longest face), else smaller, several per CU
+            int tl = p->opt.threads_large;
+            if (tl <= 0) tl = nlarge <= 2 * ctx->n_cu ? 1024 : 256;
+            const int threads[4] = {p->opt.threads_small, 256, 512, tl};
+            int nl = 0;
+            for (int k = 3; k >= 0; --k) {
+                if (cnt[k] == 0) continue;
+                launch_far_aca(k, threads[k], P, bd, dact + first[k], cnt[k], ks[k]);
+                ++nl;
+                if (k < 3) {
+                    launch_far_gram_small(bd, dact + first[k], cnt[k], ks[k]);
+                    ++nl;
+                }
+            }
             GACA_HIP_CHECK(hipGetLastError());
-            GACA_HIP_CHECK(hipEventRecord(ev[EV_K2], s0));
-            GACA_HIP_CHECK(hipEventRecord(ev[EV_K1], s1));
-            GACA_HIP_CHECK(hipEventRecord(ev[EV_K0], s2));
-            GACA_HIP_CHECK(hipStreamWaitEvent(s0, ev[EV_K1], 0));
-            GACA_HIP_CHECK(hipStreamWaitEvent(s0, ev[EV_K0], 0));
+            for (int k = 0; k < 4; ++k) GACA_HIP_CHECK(hipEventRecord(ev[EV_K0 + k], ks[k]));
+            for (int k = 0; k < 3; ++k) GACA_HIP_CHECK(hipStreamWaitEvent(s0, ev[EV_K0 + k], 0));
             GACA_HIP_CHECK(hipEventRecord(ev[EV_J], s0));
             launch_far_expand(bd, dact, ntile, s0);
             GACA_HIP_CHECK(hipEventRecord(ev[EV_X], s0));
@@ -819,7 +852,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             GACA_HIP_CHECK(hipMemcpyAsync(W.h_status.ptr, W.status.ptr, nact * 2 * sizeof(int32_t),
                                           hipMemcpyDeviceToHost, s0));
             GACA_HIP_CHECK(hipStreamSynchronize(s0));
-            n_launch += 3 + (nlarge > 0) + (n1 > 0) + (n0 > 0) + (ntile > 0);
+            n_launch += 3 + nl + (ntile > 0);
             auto elapsed = [&](int x, int y) {
                 float ms = 0.0f;
                 GACA_HIP_CHECK(hipEventElapsedTime(&ms, ev[x], ev[y]));
@@ -829,11 +862,10 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             ms_phase[1] += elapsed(EV_F1, EV_J);
             ms_phase[2] += elapsed(EV_J, EV_X);
             ms_phase[3] += elapsed(EV_X, EV_T);
-            if (nlarge) ms_kind[2] += elapsed(EV_F1, EV_K2);
-            if (n1) ms_kind[1] += elapsed(EV_F1, EV_K1);
-            if (n0) ms_kind[0] += elapsed(EV_F1, EV_K0);
+            for (int k = 0; k < 4; ++k)
+                if (cnt[k]) ms_kind[k] += elapsed(EV_F1, EV_K0 + k);
             launches_phase[0] += 1;
-            launches_phase[1] += (nlarge > 0) + (n1 > 0) + (n0 > 0);
+            launches_phase[1] += nl;
             launches_phase[2] += ntile > 0;
             launches_phase[3] += 1;
             fl_phase[0] += fl_face;
@@ -860,7 +892,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
                     ell_h[lb] = ell + 1;
                     hcur[lb] = -1;
                     fcur[lb] = -1;
-                    if (kd == 2) {
+                    if (kd == 3) {
                         fl_phase[1] += 8.0 * (d.m + d.n) * (double)rho * (rho - 1.0);
                         fl_phase[2] += 8.0 * mn * (rho + ell);
                     } else {
@@ -907,6 +939,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
     GACA_HIP_CHECK(hipEventSynchronize(ev[EV_END]));
     float span = 0.0f;
     GACA_HIP_CHECK(hipEventElapsedTime(&span, ev[EV_BEGIN], ev[EV_END]));
+    const auto t_fin = std::chrono::steady_clock::now();
     compact(ctx, h->d_arena, arena_used * es, s0);
     compact(ctx, h->d_fib, fib_used * sizeof(double2), s0);
     GACA_HIP_CHECK(hipMemcpy(h->meta.data(), h->d_meta.ptr, nfar * sizeof(FarMeta), hipMemcpyDeviceToHost));
@@ -925,7 +958,18 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
         st.far_flops_phase[k] = fl_phase[k];
         st.far_flops += fl_phase[k];
     }
-    for (int k = 0; k < 3; ++k) st.ms_far_by_kind[k] = ms_kind[k];
+    for (int k = 0; k < 4; ++k) st.ms_far_by_kind[k] = ms_kind[k];
+    int wclk_khz = 0;
+    if (hipDeviceGetAttribute(&wclk_khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess ||
+        wclk_khz <= 0) {
+        (void)hipGetLastError();
+        wclk_khz = 100000;
+    }
+    int64_t tmax = 0;
+    for (const auto &mt : h->meta) tmax = std::max<int64_t>(tmax, mt.aca_ticks);
+    st.ms_far_aca_block_max = (double)tmax / wclk_khz;
+    st.ms_host_setup = ms_setup;
+    st.ms_host_finish = wall_ms_since(t_fin);
 }
 
 static void fill_stats(gaca_hmatrix *h) {
