@@ -25,10 +25,35 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 PHASES = ["face", "aca", "expand", "tail"]
-PHASE_KERNELS = ["far_face_kernel (residual faces, FP64 VALU)",
-                 "far_aca_small_kernel / far_aca_large_kernel (face ACA, 3 classes concurrent)",
-                 "far_expand_kernel (dense H_l, Gram partials)",
-                 "far_tail_kernel (fibre, norm, stop test)"]
+KID = {"slp": 0, "dlp": 1}
+
+
+def dominant_kernels(kernels, all_stats):
+    """Per-kernel device time (mean over steps), launches and algorithmic flops of one step,
+    keyed by the kernel's name as the profiler lists it (FP64 build).  The face-ACA classes
+    0-2 share their stream with the Gram-row kernel, so only class 3 (one kernel per launch
+    window) is listed as a single kernel."""
+    out = {}
+    nsteps = len(all_stats)
+    for stp in all_stats:
+        for k, st in zip(kernels, stp):
+            kid = KID[k]
+            rows = [(f"far_face_kernel<{kid}, false, false>", st["ms_far_phase"][0],
+                     st["launches_phase"][0], st["far_flops_phase"][0]),
+                    ("far_expand_kernel<false>", st["ms_far_phase"][2], st["launches_phase"][2],
+                     st["far_flops_phase"][2]),
+                    (f"far_tail_kernel<{kid}, false, false>", st["ms_far_phase"][3],
+                     st["launches_phase"][3], st["far_flops_phase"][3]),
+                    ("far_aca_large_kernel<*, false, *> (faces with m n > 4096)",
+                     st["ms_far_by_kind"][3], st["launches_by_kind"][3], st["far_flops_by_kind"][3])]
+            for name, ms, nl, fl in rows:
+                e = out.setdefault(name, {"ms": 0.0, "launches": 0, "flops": 0.0})
+                e["ms"] += ms / nsteps
+                e["launches"] += nl / nsteps
+                e["flops"] += fl / nsteps
+    for e in out.values():
+        e["launches"] = int(round(e["launches"]))
+    return out
 
 
 def parse():
@@ -134,16 +159,16 @@ def main():
     last = all_stats[-1]
     entries_step = sum(st["entries_near"] + st["entries_face"] + st["entries_fibre"] for st in last)
     value = entries_step * args.steps / elapsed
-    # dominant kernel: the far-field phase with the largest device time over the step (each
-    # phase's launches are timed with HIP events on the stream they run on)
-    phase_ms = np.mean([[sum(st["ms_far_phase"][k] for st in stp) for k in range(4)]
-                        for stp in all_stats], axis=0)
-    phase_flops = [sum(st["far_flops_phase"][k] for st in last) for k in range(4)]
-    phase_launch = [sum(st["launches_phase"][k] for st in last) for k in range(4)]
-    dom = int(np.argmax(phase_ms))
+    # dominant kernel: the far-field kernel with the largest device time over the step; each
+    # launch is timed with HIP events on the stream it runs on
+    kern = dominant_kernels(kernels, all_stats)
+    dom_name = max(kern, key=lambda k: kern[k]["ms"])
+    dom = kern[dom_name]
     far_ms = np.mean([sum(st["ms_far_kernel"] for st in stp) for stp in all_stats])
     near_ms = np.mean([sum(st["ms_near_kernel"] for st in stp) for stp in all_stats])
-    achieved = phase_flops[dom] / (phase_ms[dom] * 1e-3) / 1e12
+    achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
+    phase_ms = np.mean([[sum(st["ms_far_phase"][k] for st in stp) for k in range(4)]
+                        for stp in all_stats], axis=0)
     out = {
         "metric": "3-way ACA build s + kernel entries/s, FP64 vs mixed-prec at stated rel err",
         "value": value,
@@ -171,14 +196,17 @@ def main():
                   for k, st in zip(kernels, last)},
         "compression": {k: st["compression"] for k, st in zip(kernels, last)},
         "setup_s": t_setup,
-        "far_phases": {name: {"ms": float(phase_ms[k]), "tflops": phase_flops[k] / max(phase_ms[k], 1e-9) / 1e9,
-                              "launches": phase_launch[k]} for k, name in enumerate(PHASES)},
+        "far_phase_ms": {name: float(phase_ms[k]) for k, name in enumerate(PHASES)},
+        "far_kernels": {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
+                            "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3)}
+                        for k, v in kern.items()},
         "far_iters": {k: st["far_iters"] for k, st in zip(kernels, last)},
-        "roofline": {"bound": "alu", "kernel": PHASE_KERNELS[dom],
+        "aca_block_max_ms": {k: st["ms_far_aca_block_max"] for k, st in zip(kernels, last)},
+        "roofline": {"bound": "alu", "kernel": dom_name,
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "launches_per_step": phase_launch[dom],
-                     "ms_per_launch": float(phase_ms[dom] / max(1, phase_launch[dom]))},
+                     "launches_per_step": dom["launches"],
+                     "ms_per_launch": dom["ms"] / max(1, dom["launches"])},
     }
     if not args.no_mixed:
         out["mixed"] = mixed_leg(gaca, ctx, xyz, tri, s, cfg, X, kernels, stream, prob, args)

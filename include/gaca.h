@@ -117,6 +117,8 @@ typedef struct {
      * 2304 and sides <= 96 (LDS, 256 threads), 2 m n <= 4096 (FP64) or 8192 (mixed) and
      * sides <= 128 (LDS, 512 threads), 3 larger (HBM, 256 to 1024 threads) */
     double ms_far_by_kind[4];
+    int32_t launches_by_kind[4];
+    double far_flops_by_kind[4];  /* algorithmic flops of the class's face-ACA launches */
     double ms_far_aca_block_max;  /* longest total face-ACA time of one block (device clock) */
     double ms_host_setup;         /* host time of the build before the far-field launches */
     double ms_host_finish;        /* host time of the build after the far field completed */

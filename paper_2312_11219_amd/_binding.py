@@ -47,6 +47,7 @@ class Stats(ctypes.Structure):
                 ("far_kernel_evals", F64), ("near_kernel_evals", F64),
                 ("ms_far_phase", F64 * 4), ("launches_phase", I32 * 4),
                 ("far_flops_phase", F64 * 4), ("ms_far_by_kind", F64 * 4),
+                ("launches_by_kind", I32 * 4), ("far_flops_by_kind", F64 * 4),
                 ("ms_far_aca_block_max", F64), ("ms_host_setup", F64), ("ms_host_finish", F64)]
 
 

@@ -680,6 +680,8 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
     const double f_eval = dense ? 0.0 : (h->kernel == 1 ? 113.0 : 105.0);
     const double qpe = h->kernel == 2 ? 36.0 : 6.0;
     double ms_phase[4] = {0, 0, 0, 0}, ms_kind[4] = {0, 0, 0, 0}, fl_phase[4] = {0, 0, 0, 0};
+    double fl_kind[4] = {0, 0, 0, 0};
+    int launches_kind[4] = {0, 0, 0, 0};
     int launches_phase[4] = {0, 0, 0, 0};
     int iters_max = 0, n_launch = 0;
     double evals = 0.0;
@@ -863,7 +865,10 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             ms_phase[2] += elapsed(EV_J, EV_X);
             ms_phase[3] += elapsed(EV_X, EV_T);
             for (int k = 0; k < 4; ++k)
-                if (cnt[k]) ms_kind[k] += elapsed(EV_F1, EV_K0 + k);
+                if (cnt[k]) {
+                    ms_kind[k] += elapsed(EV_F1, EV_K0 + k);
+                    launches_kind[k] += 1;
+                }
             launches_phase[0] += 1;
             launches_phase[1] += nl;
             launches_phase[2] += ntile > 0;
@@ -892,11 +897,18 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
                     ell_h[lb] = ell + 1;
                     hcur[lb] = -1;
                     fcur[lb] = -1;
+                    // face ACA: kind 3 corrects rows / columns from the factor history and
+                    // forms the cross terms of |S|^2, 2 (m + n) q complex MACs at step q; the
+                    // LDS kinds update R and S in place (2 m n per step) and form the Gram row
                     if (kd == 3) {
-                        fl_phase[1] += 8.0 * (d.m + d.n) * (double)rho * (rho - 1.0);
+                        const double f = 8.0 * (d.m + d.n) * (double)rho * (rho - 1.0);
+                        fl_phase[1] += f;
+                        fl_kind[3] += f;
                         fl_phase[2] += 8.0 * mn * (rho + ell);
                     } else {
-                        fl_phase[1] += 8.0 * mn * (2.0 * rho + ell);
+                        const double f = 8.0 * mn * (2.0 * rho + ell);
+                        fl_phase[1] += f;
+                        fl_kind[kd] += f;
                     }
                     fl_phase[3] += (double)L * qpe * f_eval + 16.0 * L * ell + 8.0 * (ell + 1.0) * (ell + 1.0);
                     evals += (double)L * qpe;
@@ -958,7 +970,11 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
         st.far_flops_phase[k] = fl_phase[k];
         st.far_flops += fl_phase[k];
     }
-    for (int k = 0; k < 4; ++k) st.ms_far_by_kind[k] = ms_kind[k];
+    for (int k = 0; k < 4; ++k) {
+        st.ms_far_by_kind[k] = ms_kind[k];
+        st.launches_by_kind[k] = launches_kind[k];
+        st.far_flops_by_kind[k] = fl_kind[k];
+    }
     int wclk_khz = 0;
     if (hipDeviceGetAttribute(&wclk_khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess ||
         wclk_khz <= 0) {
