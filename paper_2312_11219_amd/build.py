@@ -20,7 +20,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 HOST_SRC = ["host.cpp", "lib.cpp"]
-HIP_SRC = ["near.hip", "far_aca.hip", "apply.hip"]
+HIP_SRC = ["near.hip", "far_aca.hip", "apply.hip", "apply_mfma.hip"]
 COMMON = ["-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I" + CSRC,
           "-I" + os.path.join(ROOT, "include")]
 

@@ -1,0 +1,284 @@
+// Reordered product eq. (product), SUM mode, on the matrix cores: complex64 right-hand
+// sides, FP32 products with FP32 accumulation (v_mfma_f32_16x16x4f32; a complex product is
+// four real ones).  Factors and near field are read in their storage type (FP32 in the
+// mixed build, FP64 otherwise) and rounded to FP32 as they are staged.
+//
+//   far blocks (tau = column cluster, r crosses):
+//     T_b[l][j][c] = sum_k f_l[k] X_k[tau_j][c]           (r x L) . (L x n nrc)
+//     Z_b[l][q][c] = sum_j W_l[q][j] T_b[l][j][c]          (rho_l x n) . (n x nrc)
+//   per leaf (row tile of <= 32 rows, owner computes, no atomics):
+//     Y[rows][c] = sum_near N[rows][(k, j)] X_k[tau_j][c] + sum_far U_b[rows][q] Z_b[q][c]
+//
+// Right-hand sides are processed in chunks of nrc columns; the permutation to tree order
+// is applied by the loaders (X and Y stay in the caller's element order).
+#include <hip/hip_runtime.h>
+
+#include "device_util.h"
+#include "kernels.h"
+
+namespace gaca {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float2 to_f2(float2 v) { return v; }
+__device__ __forceinline__ float2 to_f2(double2 v) { return make_float2((float)v.x, (float)v.y); }
+
+// One 32 x TN complex tile of C += A B per workgroup of 256 threads (4 waves); wave w owns
+// columns [w TN / 4, (w + 1) TN / 4) as 2 x TN/64 MFMA tiles of 16 x 16.  A and B are
+// staged in LDS in slices of KS = 16 along K: As[k][r] (32 rows), Bs[k][c] (TN columns).
+// Lane layout of the 16x16x4 instruction: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and holds D[4 (l / 16) + t][l % 16], t = 0..3.
+template <int TN>
+struct CTile {
+    static constexpr int KS = 16, TM = 32, WN = TN / 4, NJ = WN / 16;
+    static_assert(NJ >= 1, "TN must be a multiple of 64");
+    v4f cr[2][NJ], ci[2][NJ];
+    __device__ void zero() {
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int nj = 0; nj < NJ; ++nj) {
+                cr[mi][nj] = v4f{0.f, 0.f, 0.f, 0.f};
+                ci[mi][nj] = v4f{0.f, 0.f, 0.f, 0.f};
+            }
+    }
+    __device__ void step(const float2 *As, const float2 *Bs) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = 4 * s + kq;
+            float2 a[2], b[NJ];
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi) a[mi] = As[k * TM + 16 * mi + i];
+#pragma unroll
+            for (int nj = 0; nj < NJ; ++nj) b[nj] = Bs[k * TN + wave * WN + 16 * nj + i];
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int nj = 0; nj < NJ; ++nj) {
+                    cr[mi][nj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi].x, b[nj].x, cr[mi][nj], 0, 0, 0);
+                    cr[mi][nj] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[mi].y, b[nj].y, cr[mi][nj], 0, 0, 0);
+                    ci[mi][nj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi].x, b[nj].y, ci[mi][nj], 0, 0, 0);
+                    ci[mi][nj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi].y, b[nj].x, ci[mi][nj], 0, 0, 0);
+                }
+        }
+    }
+    // visit every accumulated element: f(row, col, value), rows < 32, cols < TN
+    template <class F>
+    __device__ void visit(const F &f) const {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int nj = 0; nj < NJ; ++nj)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    f(16 * mi + 4 * (lane >> 4) + t, wave * WN + 16 * nj + (lane & 15),
+                      make_float2(cr[mi][nj][t], ci[mi][nj][t]));
+    }
+};
+
+// Stage A rows [0, 32) x K slice [k0, k0 + 16) into As[k][r]; a(r, k) returns the value,
+// valid(r, k) whether it exists.  KMAJOR: consecutive threads walk k (row-major A), else r.
+template <bool KMAJOR, class GA>
+__device__ __forceinline__ void stage_a(float2 *As, int k0, int nrow, int kmax, const GA &ga) {
+    for (int idx = threadIdx.x; idx < 16 * 32; idx += 256) {
+        int r, k;
+        if (KMAJOR) {
+            r = idx >> 4;
+            k = idx & 15;
+        } else {
+            k = idx >> 5;
+            r = idx & 31;
+        }
+        const int kk = k0 + k;
+        As[k * 32 + r] = (r < nrow && kk < kmax) ? ga(r, kk) : make_float2(0.f, 0.f);
+    }
+}
+
+template <int TN, class GB>
+__device__ __forceinline__ void stage_b(float2 *Bs, int k0, int kmax, int ncol, const GB &gb) {
+    for (int idx = threadIdx.x; idx < 16 * TN; idx += 256) {
+        const int k = idx / TN, c = idx - k * TN;
+        const int kk = k0 + k;
+        Bs[idx] = (kk < kmax && c < ncol) ? gb(kk, c) : make_float2(0.f, 0.f);
+    }
+}
+
+// last index a with key[a] <= v (key ascending, key[0] = 0)
+__device__ __forceinline__ int find_le(const int64_t *key, int n, int64_t v) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (key[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------------------
+// T_b = F_b X_b: tile (block b, row tile mt of the crosses, column tile nt of (j, c)).
+template <class FacT>
+__global__ void __launch_bounds__(256)
+    apply_far_t_kernel(ApplyDev a, MfmaApplyDev d, const float2 *X, float2 *T) {
+    constexpr int TN = 256;
+    __shared__ float2 As[16 * 32];
+    __shared__ float2 Bs[16 * TN];
+    __shared__ int sh_w;
+    if (threadIdx.x == 0) sh_w = find_le(d.t_tile0, d.nt_items, (int64_t)blockIdx.x);
+    __syncthreads();
+    const MfmaTItem it = d.t_items[sh_w];
+    const int b = it.b;
+    const int64_t tile = blockIdx.x - d.t_tile0[sh_w];
+    const int m_tiles = it.m_tiles;
+    const int mt = (int)(tile % m_tiles), nt = (int)(tile / m_tiles);
+    const int rank = a.meta[b].rank, n = a.far4[4 * b + 3], c0b = a.far4[4 * b + 2];
+    const int L = a.L, nrc = d.nrc;
+    const int64_t ncols = (int64_t)n * nrc;
+    const double2 *F = a.fib_arena + a.fib_off[b];
+    const int r0 = 32 * mt;
+    const int64_t n0 = (int64_t)nt * TN;
+    CTile<TN> acc;
+    acc.zero();
+    for (int k0 = 0; k0 < L; k0 += 16) {
+        __syncthreads();
+        stage_a<true>(As, k0, rank - r0, L, [&](int r, int k) {
+            return to_f2(F[(int64_t)(r0 + r) * L + k]);
+        });
+        stage_b<TN>(Bs, k0, L, (int)min<int64_t>(TN, ncols - n0), [&](int k, int c) {
+            const int64_t nn = n0 + c;
+            const int j = (int)(nn / nrc), cc = (int)(nn - (int64_t)j * nrc);
+            return X[((int64_t)k * a.M + a.perm[c0b + j]) * d.ldx + d.c0 + cc];
+        });
+        __syncthreads();
+        acc.step(As, Bs);
+    }
+    float2 *Tb = T + it.t_off;
+    acc.visit([&](int r, int c, float2 v) {
+        if (r0 + r < rank && n0 + c < ncols) Tb[(int64_t)(r0 + r) * ncols + n0 + c] = v;
+    });
+}
+
+// Z_{b,l} = W_l T_l: tile (block b, cross l, row tile of rho_l, column tile).
+template <class FacT>
+__global__ void __launch_bounds__(256)
+    apply_far_z_kernel(ApplyDev a, MfmaApplyDev d, const float2 *T, float2 *Z) {
+    constexpr int TN = 64;
+    __shared__ float2 As[16 * 32];
+    __shared__ float2 Bs[16 * TN];
+    const MfmaZItem it = d.z_items[blockIdx.x];
+    const int b = it.b, l = it.l;
+    const int n = a.far4[4 * b + 3], m = a.far4[4 * b + 1];
+    const CrossMeta cm = a.cmeta[(int64_t)b * a.rcap + l];
+    const FacT *W = reinterpret_cast<const FacT *>(a.arena) + a.cross_off[(int64_t)b * a.rcap + l] +
+                    (int64_t)cm.rho * m;
+    const int nrc = d.nrc;
+    const int q0 = it.q0, c0 = blockIdx.y * TN;
+    const float2 *Tl = T + it.t_off + (int64_t)l * n * nrc;
+    CTile<TN> acc;
+    acc.zero();
+    for (int k0 = 0; k0 < n; k0 += 16) {
+        __syncthreads();
+        stage_a<true>(As, k0, cm.rho - q0, n, [&](int r, int k) {
+            return to_f2(W[(int64_t)(q0 + r) * n + k]);
+        });
+        stage_b<TN>(Bs, k0, n, nrc - c0, [&](int k, int c) { return Tl[(int64_t)k * nrc + c0 + c]; });
+        __syncthreads();
+        acc.step(As, Bs);
+    }
+    float2 *Zl = Z + it.z_off;
+    acc.visit([&](int r, int c, float2 v) {
+        if (q0 + r < cm.rho && c0 + c < nrc) Zl[(int64_t)(q0 + r) * nrc + c0 + c] = v;
+    });
+}
+
+// Y rows of one leaf (row tile of 32) for one column tile: near blocks and far blocks of
+// the leaf, one K stream.
+template <class FacT, class NearT>
+__global__ void __launch_bounds__(256)
+    apply_leaf_mfma_kernel(ApplyDev a, MfmaApplyDev d, const float2 *X, const float2 *Z,
+                           float2 *Y) {
+    constexpr int TN = 64;
+    __shared__ float2 As[16 * 32];
+    __shared__ float2 Bs[16 * TN];
+    __shared__ int64_t qaddr[kMfmaMaxSumRho];
+    const int leaf = blockIdx.x;
+    const int lr0 = a.leaf_r0[leaf] + 32 * blockIdx.z, lm = min(32, a.leaf_m[leaf] - 32 * (int)blockIdx.z);
+    if (lm <= 0) return;
+    const int c0 = blockIdx.y * TN, nrc = d.nrc;
+    const int L = a.L;
+    const int64_t M = a.M;
+    const NearT *nearv = a.near64 ? reinterpret_cast<const NearT *>(a.near64)
+                                  : reinterpret_cast<const NearT *>(a.near32);
+    const FacT *arena = reinterpret_cast<const FacT *>(a.arena);
+    CTile<TN> acc;
+    acc.zero();
+    for (int e = a.leaf_near_ptr[leaf]; e < a.leaf_near_ptr[leaf + 1]; ++e) {
+        const NearBlockDev nb = a.nblocks[a.leaf_near_idx[e]];
+        const int ro = lr0 - nb.r0, n = nb.n;
+        const int K = L * n;
+        const NearT *A0 = nearv + nb.off + (int64_t)ro * K;
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            __syncthreads();
+            stage_a<true>(As, k0, lm, K, [&](int r, int kk) { return to_f2(A0[(int64_t)r * K + kk]); });
+            stage_b<TN>(Bs, k0, K, nrc - c0, [&](int kk, int c) {
+                const int k = kk / n, j = kk - k * n;
+                return X[((int64_t)k * M + a.perm[nb.c0 + j]) * d.ldx + d.c0 + c0 + c];
+            });
+            __syncthreads();
+            acc.step(As, Bs);
+        }
+    }
+    for (int e = a.leaf_far_ptr[leaf]; e < a.leaf_far_ptr[leaf + 1]; ++e) {
+        const int b = a.leaf_far_idx[e];
+        const int mb = a.far4[4 * b + 1], ro = lr0 - a.far4[4 * b];
+        const int rank = a.meta[b].rank;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int q = 0;
+            for (int l = 0; l < rank; ++l) {
+                const CrossMeta cm = a.cmeta[(int64_t)b * a.rcap + l];
+                const int64_t base = a.cross_off[(int64_t)b * a.rcap + l];
+                for (int t = 0; t < cm.rho && q < kMfmaMaxSumRho; ++t, ++q) qaddr[q] = base + (int64_t)t * mb + ro;
+            }
+        }
+        __syncthreads();
+        const int K = min(d.sum_rho[b], kMfmaMaxSumRho);
+        const float2 *Zb = Z + d.z_off[b];
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            __syncthreads();
+            stage_a<false>(As, k0, lm, K, [&](int r, int q) { return to_f2(arena[qaddr[q] + r]); });
+            stage_b<TN>(Bs, k0, K, nrc - c0, [&](int q, int c) { return Zb[(int64_t)q * nrc + c0 + c]; });
+            __syncthreads();
+            acc.step(As, Bs);
+        }
+    }
+    acc.visit([&](int r, int c, float2 v) {
+        if (r < lm && c0 + c < nrc) Y[a.perm[lr0 + r] * d.ldy + d.c0 + c0 + c] = v;
+    });
+}
+
+void launch_apply_far_t(const ApplyDev &a, const MfmaApplyDev &d, int64_t ntiles, const float2 *X,
+                        float2 *T, hipStream_t st) {
+    if (ntiles <= 0) return;
+    if (a.fac_fp32) apply_far_t_kernel<float2><<<(unsigned)ntiles, 256, 0, st>>>(a, d, X, T);
+    else apply_far_t_kernel<double2><<<(unsigned)ntiles, 256, 0, st>>>(a, d, X, T);
+}
+
+void launch_apply_far_z(const ApplyDev &a, const MfmaApplyDev &d, int nitems, const float2 *T,
+                        float2 *Z, hipStream_t st) {
+    if (nitems <= 0) return;
+    dim3 grid(nitems, (d.nrc + 63) / 64);
+    if (a.fac_fp32) apply_far_z_kernel<float2><<<grid, 256, 0, st>>>(a, d, T, Z);
+    else apply_far_z_kernel<double2><<<grid, 256, 0, st>>>(a, d, T, Z);
+}
+
+void launch_apply_leaf_mfma(const ApplyDev &a, const MfmaApplyDev &d, int row_tiles,
+                            const float2 *X, const float2 *Z, float2 *Y, hipStream_t st) {
+    dim3 grid(a.nleaf, (d.nrc + 63) / 64, row_tiles);
+    if (a.fac_fp32) apply_leaf_mfma_kernel<float2, float2><<<grid, 256, 0, st>>>(a, d, X, Z, Y);
+    else apply_leaf_mfma_kernel<double2, double2><<<grid, 256, 0, st>>>(a, d, X, Z, Y);
+}
+
+}  // namespace gaca

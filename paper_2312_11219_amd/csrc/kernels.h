@@ -129,6 +129,34 @@ struct ApplyDev {
     const int32_t *leaf_near_ptr, *leaf_near_idx;
     const int64_t *z_off;         // [nfar] offset of the block's z (sum_rho x nrhs) or v
 };
+// Matrix-core apply (SUM mode, complex64 right-hand sides), csrc/apply_mfma.hip.
+constexpr int kMfmaMaxSumRho = 4096;   // sum of face ranks of one far block
+struct MfmaTItem {        // T_b = F_b X_b for one far block: its tiles start at t_tile0[item]
+    int32_t b, m_tiles;   // block, row tiles of its crosses (32 rows each)
+    int64_t t_off;        // T_b offset (elements, [rank][n][nrc])
+};
+struct MfmaZItem {        // Z_{b,l} rows [q0, q0 + 32)
+    int32_t b, l, q0, pad;
+    int64_t t_off, z_off; // T_b and Z_{b,l} offsets (elements)
+};
+struct MfmaApplyDev {
+    int32_t nrc;          // right-hand sides of this chunk
+    int32_t ldx, ldy;     // leading dimensions (nrhs) of X [L][M][nrhs] and Y [M][nrhs]
+    int32_t c0;           // first right-hand side of the chunk
+    const MfmaTItem *t_items;
+    const int64_t *t_tile0;
+    int32_t nt_items;
+    const MfmaZItem *z_items;
+    const int64_t *z_off; // [nfar] Z_b offsets ([sum_rho][nrc])
+    const int32_t *sum_rho;
+};
+void launch_apply_far_t(const ApplyDev &a, const MfmaApplyDev &d, int64_t ntiles, const float2 *X,
+                        float2 *T, hipStream_t st);
+void launch_apply_far_z(const ApplyDev &a, const MfmaApplyDev &d, int nitems, const float2 *T,
+                        float2 *Z, hipStream_t st);
+void launch_apply_leaf_mfma(const ApplyDev &a, const MfmaApplyDev &d, int row_tiles,
+                            const float2 *X, const float2 *Z, float2 *Y, hipStream_t st);
+
 // x_fp32: X, Y and the workspace are complex64 (FP32 arithmetic), else complex128.
 // Workspace pointers are in elements of that type.
 void launch_apply(const ApplyDev &a, int mode, int x_fp32, const void *X, void *Y, void *Xp,

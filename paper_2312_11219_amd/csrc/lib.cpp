@@ -177,6 +177,7 @@ struct gaca_hmatrix {
     int32_t ws_nrhs = -1, ws_mode = -1, ws_dtype = -1;
     DevBuf d_xp, d_yp, d_z, d_t, d_toff, d_zoff, d_yb, d_yoff;
     DevBuf d_leaf_r0, d_leaf_m, d_lfp, d_lfi, d_lnp, d_lni;
+    DevBuf d_mz, d_mt, d_mtitems, d_mttile0, d_mzitems, d_mzoff, d_msumrho;   // matrix-core apply
     bool leaf_ready = false;
 };
 
@@ -1242,22 +1243,14 @@ static void prepare_leaves(gaca_hmatrix *h) {
     h->leaf_ready = true;
 }
 
-gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, const void *X,
-                       void *Y, gaca_dtype dtype, void *hip_stream) {
-    return guarded([&] {
-        REQUIRE(h && X && Y, "null argument");
-        REQUIRE(nrhs >= 1, "nrhs must be >= 1");
-        REQUIRE(mode == GACA_APPLY_SUM || mode == GACA_APPLY_PER_FREQ, "bad mode");
-        REQUIRE(dtype == GACA_C128 || dtype == GACA_C64, "bad dtype");
-        REQUIRE(!h->p->synthetic, "apply needs a mesh problem");
-        gaca_problem *p = h->p;
-        gaca_context *ctx = p->ctx;
-        hipStream_t st = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : ctx->stream;
-        prepare_leaves(h);
-        const int L = p->L;
-        const int64_t M = p->M;
-        const size_t xs = dtype == GACA_C64 ? sizeof(float2) : sizeof(double2);
-        if (h->ws_nrhs != nrhs || h->ws_mode != (int)mode || h->ws_dtype != (int)dtype) {
+// Workspace of the VALU apply (tree-order copies of X and Y, z, t and per-block y).
+static void alloc_apply_workspace(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, gaca_dtype dtype) {
+    gaca_problem *p = h->p;
+    gaca_context *ctx = p->ctx;
+    const int L = p->L;
+    const int64_t M = p->M;
+    const size_t xs = dtype == GACA_C64 ? sizeof(float2) : sizeof(double2);
+    {
             std::vector<int64_t> zoff(std::max<int64_t>(h->nfar, 1)), toff(std::max<int64_t>(h->nfar, 1)),
                 yoff(std::max<int64_t>(h->nfar, 1));
             int64_t zacc = 0, tacc = 0, yacc = 0;
@@ -1283,6 +1276,127 @@ gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, cons
             h->ws_mode = (int)mode;
             h->ws_dtype = (int)dtype;
         }
+}
+
+// The matrix-core apply stages the U rows of one far block by their sum of face ranks.
+static bool mfma_supported(const gaca_hmatrix *h) {
+    for (int64_t b = 0; b < h->nfar; ++b)
+        if (h->meta[b].sum_rho > kMfmaMaxSumRho) return false;
+    return true;
+}
+
+// SUM mode on the matrix cores: right-hand sides in chunks of up to 64 columns; per chunk
+// the far blocks in batches whose T fits the workspace, then one pass over the leaves.
+static void apply_mfma(gaca_hmatrix *h, const ApplyDev &a, int32_t nrhs, const float2 *X,
+                       float2 *Y, hipStream_t st) {
+    gaca_problem *p = h->p;
+    gaca_context *ctx = p->ctx;
+    const int nrc_max = std::min(nrhs, 64);
+    const int64_t nfar = h->nfar;
+    std::vector<int32_t> sum_rho(std::max<int64_t>(nfar, 1), 0);
+    int64_t rho_tot = 0;
+    for (int64_t b = 0; b < nfar; ++b) {
+        sum_rho[b] = h->meta[b].sum_rho;
+        rho_tot += sum_rho[b];
+    }
+    h->d_msumrho.upload(ctx, sum_rho);
+    ensure(ctx, h->d_mz, (size_t)std::max<int64_t>(rho_tot * nrc_max, 1) * sizeof(float2));
+    int max_leaf = 1;
+    for (int32_t m : p->leaf_m) max_leaf = std::max(max_leaf, m);
+    const int row_tiles = (max_leaf + 31) / 32;
+    const size_t t_budget = (size_t)1 << 31;   // bytes of T per far batch
+    for (int c0 = 0; c0 < nrhs; c0 += nrc_max) {
+        const int nrc = std::min(nrc_max, nrhs - c0);
+        MfmaApplyDev d{};
+        d.nrc = nrc;
+        d.ldx = nrhs;
+        d.ldy = nrhs;
+        d.c0 = c0;
+        std::vector<int64_t> zoff(std::max<int64_t>(nfar, 1), 0);
+        int64_t zacc = 0;
+        for (int64_t b = 0; b < nfar; ++b) {
+            zoff[b] = zacc;
+            zacc += (int64_t)sum_rho[b] * nrc;
+        }
+        h->d_mzoff.upload(ctx, zoff);
+        d.z_off = h->d_mzoff.as<int64_t>();
+        d.sum_rho = h->d_msumrho.as<int32_t>();
+        for (int64_t s0 = 0; s0 < nfar;) {
+            std::vector<MfmaTItem> ti;
+            std::vector<int64_t> tt0;
+            std::vector<MfmaZItem> zi;
+            int64_t tacc = 0, ntiles = 0, e = s0;
+            for (; e < nfar; ++e) {
+                const FarMeta &mt = h->meta[e];
+                const int n = (int)p->part.far[e][3];
+                const int64_t tb = (int64_t)mt.rank * n * nrc;
+                if (e > s0 && (size_t)(tacc + tb) * sizeof(float2) > t_budget) break;
+                if (mt.rank == 0) continue;
+                MfmaTItem it{};
+                it.b = (int32_t)e;
+                it.m_tiles = (mt.rank + 31) / 32;
+                it.t_off = tacc;
+                tt0.push_back(ntiles);
+                ti.push_back(it);
+                ntiles += (int64_t)it.m_tiles * (((int64_t)n * nrc + 255) / 256);
+                int64_t qoff = 0;
+                for (int l = 0; l < mt.rank; ++l) {
+                    const CrossMeta &cm = h->cmeta[e * h->rcap + l];
+                    for (int q0 = 0; q0 < cm.rho; q0 += 32) {
+                        MfmaZItem z{};
+                        z.b = (int32_t)e;
+                        z.l = l;
+                        z.q0 = q0;
+                        z.t_off = tacc;
+                        z.z_off = zoff[e] + qoff * nrc;
+                        zi.push_back(z);
+                    }
+                    qoff += cm.rho;
+                }
+                tacc += tb;
+            }
+            if (!ti.empty()) {
+                ensure(ctx, h->d_mt, (size_t)std::max<int64_t>(tacc, 1) * sizeof(float2));
+                h->d_mtitems.upload(ctx, ti);
+                h->d_mttile0.upload(ctx, tt0);
+                h->d_mzitems.upload(ctx, zi);
+                d.t_items = h->d_mtitems.as<MfmaTItem>();
+                d.t_tile0 = h->d_mttile0.as<int64_t>();
+                d.nt_items = (int32_t)ti.size();
+                d.z_items = h->d_mzitems.as<MfmaZItem>();
+                launch_apply_far_t(a, d, ntiles, X, h->d_mt.as<float2>(), st);
+                launch_apply_far_z(a, d, (int)zi.size(), h->d_mt.as<float2>(), h->d_mz.as<float2>(), st);
+                GACA_HIP_CHECK(hipGetLastError());
+                // the next batch reuses T and the item lists
+                GACA_HIP_CHECK(hipStreamSynchronize(st));
+            }
+            s0 = e;
+        }
+        launch_apply_leaf_mfma(a, d, row_tiles, X, h->d_mz.as<float2>(), Y, st);
+        GACA_HIP_CHECK(hipGetLastError());
+        // the next chunk rewrites Z and the offsets
+        GACA_HIP_CHECK(hipStreamSynchronize(st));
+    }
+}
+
+gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, const void *X,
+                       void *Y, gaca_dtype dtype, void *hip_stream) {
+    return guarded([&] {
+        REQUIRE(h && X && Y, "null argument");
+        REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+        REQUIRE(mode == GACA_APPLY_SUM || mode == GACA_APPLY_PER_FREQ, "bad mode");
+        REQUIRE(dtype == GACA_C128 || dtype == GACA_C64, "bad dtype");
+        REQUIRE(!h->p->synthetic, "apply needs a mesh problem");
+        gaca_problem *p = h->p;
+        gaca_context *ctx = p->ctx;
+        hipStream_t st = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : ctx->stream;
+        prepare_leaves(h);
+        const int L = p->L;
+        const int64_t M = p->M;
+        const size_t xs = dtype == GACA_C64 ? sizeof(float2) : sizeof(double2);
+        const bool mfma = mode == GACA_APPLY_SUM && dtype == GACA_C64 && mfma_supported(h);
+        if (!mfma && (h->ws_nrhs != nrhs || h->ws_mode != (int)mode || h->ws_dtype != (int)dtype))
+            alloc_apply_workspace(h, mode, nrhs, dtype);
         ApplyDev a{};
         a.L = L;
         a.nrhs = nrhs;
@@ -1310,6 +1424,10 @@ gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, cons
         a.leaf_near_ptr = h->d_lnp.as<int32_t>();
         a.leaf_near_idx = h->d_lni.as<int32_t>();
         a.z_off = h->d_zoff.as<int64_t>();
+        if (mfma) {
+            apply_mfma(h, a, nrhs, reinterpret_cast<const float2 *>(X), reinterpret_cast<float2 *>(Y), st);
+            return;
+        }
         launch_apply(a, (int)mode, dtype == GACA_C64 ? 1 : 0, X, Y, h->d_xp.ptr, h->d_yp.ptr,
                      h->d_z.ptr, h->d_t.ptr, h->d_toff.as<int64_t>(), h->d_yb.ptr,
                      h->d_yoff.as<int64_t>(), st);
