@@ -75,6 +75,7 @@ typedef struct {
     int32_t threads_large;    /* face-ACA workgroup size for faces with m n > 2304 (256, 512
                                  or 1024; default 0: 1024 while an iteration has at most two
                                  such faces per compute unit, else 256) */
+    int32_t verbose;          /* 1: one progress line per far-field batch on stderr */
 } gaca_options;
 
 typedef struct gaca_context gaca_context;
@@ -122,6 +123,12 @@ typedef struct {
     double ms_far_aca_block_max;  /* longest total face-ACA time of one block (device clock) */
     double ms_host_setup;         /* host time of the build before the far-field launches */
     double ms_host_finish;        /* host time of the build after the far field completed */
+    /* last matrix-core apply (SUM mode, complex64): device time, algorithmic flops (complex
+     * multiply-add = 8), stored operator bytes it streamed (near field + factors + fibres) */
+    double ms_apply;
+    double apply_flops;
+    double apply_operator_bytes;
+    int32_t arena_in_place;       /* 1: the factor arena grows in place (virtual memory) */
 } gaca_stats;
 
 int gaca_abi_version(void);

@@ -32,7 +32,7 @@ class Options(ctypes.Structure):
                 ("precision", I32), ("n_duffy", I32), ("n_galerkin", I32), ("tie", F64),
                 ("delta_zero", F64), ("max_rank3d", I32), ("max_face_rank", I32),
                 ("max_device_bytes", U64), ("batch_bytes", U64), ("threads_small", I32),
-                ("threads_large", I32)]
+                ("threads_large", I32), ("verbose", I32)]
 
 
 class Stats(ctypes.Structure):
@@ -48,7 +48,9 @@ class Stats(ctypes.Structure):
                 ("ms_far_phase", F64 * 4), ("launches_phase", I32 * 4),
                 ("far_flops_phase", F64 * 4), ("ms_far_by_kind", F64 * 4),
                 ("launches_by_kind", I32 * 4), ("far_flops_by_kind", F64 * 4),
-                ("ms_far_aca_block_max", F64), ("ms_host_setup", F64), ("ms_host_finish", F64)]
+                ("ms_far_aca_block_max", F64), ("ms_host_setup", F64), ("ms_host_finish", F64),
+                ("ms_apply", F64), ("apply_flops", F64), ("apply_operator_bytes", F64),
+                ("arena_in_place", I32)]
 
 
 def lib_path() -> str:

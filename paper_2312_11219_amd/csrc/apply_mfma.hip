@@ -10,7 +10,9 @@
 //     Y[rows][c] = sum_near N[rows][(k, j)] X_k[tau_j][c] + sum_far U_b[rows][q] Z_b[q][c]
 //
 // Right-hand sides are processed in chunks of nrc columns; the permutation to tree order
-// is applied by the loaders (X and Y stay in the caller's element order).
+// is applied by the loaders (X and Y stay in the caller's element order).  Sums are formed
+// in segments of at most kFold K-elements (one block's contribution, or 256 terms) that are
+// then added up, which keeps the FP32 accumulation error at the level of a 256-term sum.
 #include <hip/hip_runtime.h>
 
 #include "device_util.h"
@@ -19,6 +21,7 @@
 namespace gaca {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int kFold = 256;
 
 __device__ __forceinline__ float2 to_f2(float2 v) { return v; }
 __device__ __forceinline__ float2 to_f2(double2 v) { return make_float2((float)v.x, (float)v.y); }
@@ -63,6 +66,19 @@ struct CTile {
                     ci[mi][nj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi].y, b[nj].x, ci[mi][nj], 0, 0, 0);
                 }
         }
+    }
+    // this += o, then o = 0 (two-level summation: segments of K are summed separately and
+    // added up, so the FP32 rounding grows with the segment length, not with the whole K)
+    __device__ void fold(CTile &o) {
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int nj = 0; nj < NJ; ++nj) {
+                cr[mi][nj] += o.cr[mi][nj];
+                ci[mi][nj] += o.ci[mi][nj];
+                o.cr[mi][nj] = v4f{0.f, 0.f, 0.f, 0.f};
+                o.ci[mi][nj] = v4f{0.f, 0.f, 0.f, 0.f};
+            }
     }
     // visit every accumulated element: f(row, col, value), rows < 32, cols < TN
     template <class F>
@@ -139,9 +155,11 @@ __global__ void __launch_bounds__(256)
     const double2 *F = a.fib_arena + a.fib_off[b];
     const int r0 = 32 * mt;
     const int64_t n0 = (int64_t)nt * TN;
-    CTile<TN> acc;
+    CTile<TN> acc, seg;
     acc.zero();
+    seg.zero();
     for (int k0 = 0; k0 < L; k0 += 16) {
+        if (k0 > 0 && k0 % kFold == 0) acc.fold(seg);
         __syncthreads();
         stage_a<true>(As, k0, rank - r0, L, [&](int r, int k) {
             return to_f2(F[(int64_t)(r0 + r) * L + k]);
@@ -152,8 +170,9 @@ __global__ void __launch_bounds__(256)
             return X[((int64_t)k * a.M + a.perm[c0b + j]) * d.ldx + d.c0 + cc];
         });
         __syncthreads();
-        acc.step(As, Bs);
+        seg.step(As, Bs);
     }
+    acc.fold(seg);
     float2 *Tb = T + it.t_off;
     acc.visit([&](int r, int c, float2 v) {
         if (r0 + r < rank && n0 + c < ncols) Tb[(int64_t)(r0 + r) * ncols + n0 + c] = v;
@@ -176,17 +195,20 @@ __global__ void __launch_bounds__(256)
     const int nrc = d.nrc;
     const int q0 = it.q0, c0 = blockIdx.y * TN;
     const float2 *Tl = T + it.t_off + (int64_t)l * n * nrc;
-    CTile<TN> acc;
+    CTile<TN> acc, seg;
     acc.zero();
+    seg.zero();
     for (int k0 = 0; k0 < n; k0 += 16) {
+        if (k0 > 0 && k0 % kFold == 0) acc.fold(seg);
         __syncthreads();
         stage_a<true>(As, k0, cm.rho - q0, n, [&](int r, int k) {
             return to_f2(W[(int64_t)(q0 + r) * n + k]);
         });
         stage_b<TN>(Bs, k0, n, nrc - c0, [&](int k, int c) { return Tl[(int64_t)k * nrc + c0 + c]; });
         __syncthreads();
-        acc.step(As, Bs);
+        seg.step(As, Bs);
     }
+    acc.fold(seg);
     float2 *Zl = Z + it.z_off;
     acc.visit([&](int r, int c, float2 v) {
         if (q0 + r < cm.rho && c0 + c < nrc) Zl[(int64_t)(q0 + r) * nrc + c0 + c] = v;
@@ -212,14 +234,16 @@ __global__ void __launch_bounds__(256)
     const NearT *nearv = a.near64 ? reinterpret_cast<const NearT *>(a.near64)
                                   : reinterpret_cast<const NearT *>(a.near32);
     const FacT *arena = reinterpret_cast<const FacT *>(a.arena);
-    CTile<TN> acc;
+    CTile<TN> acc, seg;
     acc.zero();
+    seg.zero();
     for (int e = a.leaf_near_ptr[leaf]; e < a.leaf_near_ptr[leaf + 1]; ++e) {
         const NearBlockDev nb = a.nblocks[a.leaf_near_idx[e]];
         const int ro = lr0 - nb.r0, n = nb.n;
         const int K = L * n;
         const NearT *A0 = nearv + nb.off + (int64_t)ro * K;
         for (int k0 = 0; k0 < K; k0 += 16) {
+            if (k0 > 0 && k0 % kFold == 0) acc.fold(seg);
             __syncthreads();
             stage_a<true>(As, k0, lm, K, [&](int r, int kk) { return to_f2(A0[(int64_t)r * K + kk]); });
             stage_b<TN>(Bs, k0, K, nrc - c0, [&](int kk, int c) {
@@ -227,8 +251,9 @@ __global__ void __launch_bounds__(256)
                 return X[((int64_t)k * M + a.perm[nb.c0 + j]) * d.ldx + d.c0 + c0 + c];
             });
             __syncthreads();
-            acc.step(As, Bs);
+            seg.step(As, Bs);
         }
+        acc.fold(seg);
     }
     for (int e = a.leaf_far_ptr[leaf]; e < a.leaf_far_ptr[leaf + 1]; ++e) {
         const int b = a.leaf_far_idx[e];
@@ -247,12 +272,14 @@ __global__ void __launch_bounds__(256)
         const int K = min(d.sum_rho[b], kMfmaMaxSumRho);
         const float2 *Zb = Z + d.z_off[b];
         for (int k0 = 0; k0 < K; k0 += 16) {
+            if (k0 > 0 && k0 % kFold == 0) acc.fold(seg);
             __syncthreads();
             stage_a<false>(As, k0, lm, K, [&](int r, int q) { return to_f2(arena[qaddr[q] + r]); });
             stage_b<TN>(Bs, k0, K, nrc - c0, [&](int q, int c) { return Zb[(int64_t)q * nrc + c0 + c]; });
             __syncthreads();
-            acc.step(As, Bs);
+            seg.step(As, Bs);
         }
+        acc.fold(seg);
     }
     acc.visit([&](int r, int c, float2 v) {
         if (r < lm && c0 + c < nrc) Y[a.perm[lr0 + r] * d.ldy + d.c0 + c0 + c] = v;

@@ -33,6 +33,7 @@ void options_default(gaca_options *o) {
     o->batch_bytes = 24ull << 30;
     o->threads_small = 64;
     o->threads_large = 0;
+    o->verbose = 0;
 }
 
 // ---- Gauss-Legendre on [0, 1] by Newton iteration on the Legendre recurrence ----------

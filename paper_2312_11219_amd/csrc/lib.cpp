@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <functional>
@@ -68,6 +69,176 @@ struct DevBuf {
     }
 };
 
+// Device buffer that grows in place: a virtual address range is reserved once and physical
+// chunks are mapped behind its end as needed (HIP virtual memory), so growing never copies
+// and never holds the old and the new buffer at once; shrinking unmaps the tail.  Where the
+// virtual-memory calls are not available it falls back to allocate-copy-free.
+struct GrowBuf {
+    void *ptr = nullptr;      // base address
+    size_t bytes = 0;         // usable (mapped) bytes
+    gaca_context *ctx = nullptr;
+    bool vmm = false;
+    size_t reserved = 0, gran = 0;
+    int device = 0;
+    std::vector<std::pair<hipMemGenericAllocationHandle_t, size_t>> chunks;
+    DevBuf plain;             // fallback storage
+    GrowBuf() = default;
+    GrowBuf(const GrowBuf &) = delete;
+    GrowBuf &operator=(const GrowBuf &) = delete;
+    ~GrowBuf() { release(); }
+    template <class T>
+    T *as() const { return reinterpret_cast<T *>(ptr); }
+
+    void release() {
+        if (vmm && ptr) {
+            (void)hipDeviceSynchronize();
+            size_t off = 0;
+            for (auto &c : chunks) {
+                (void)hipMemUnmap(static_cast<char *>(ptr) + off, c.second);
+                (void)hipMemRelease(c.first);
+                if (ctx) ctx->in_use -= c.second;
+                off += c.second;
+            }
+            chunks.clear();
+            (void)hipMemAddressFree(ptr, reserved);
+        }
+        plain.release();
+        ptr = nullptr;
+        bytes = 0;
+        reserved = 0;
+        vmm = false;
+    }
+
+    // map at least `add` more bytes (rounded to the granularity); false when out of memory
+    bool map_more(size_t add) {
+        const size_t sz = (add + gran - 1) / gran * gran;
+        if (bytes + sz > reserved) return false;
+        if (ctx->limit && ctx->in_use + sz > ctx->limit) return false;
+        hipMemAllocationProp prop{};
+        prop.type = hipMemAllocationTypePinned;
+        prop.location.type = hipMemLocationTypeDevice;
+        prop.location.id = device;
+        hipMemGenericAllocationHandle_t hd{};
+        if (hipMemCreate(&hd, sz, &prop, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        char *at = static_cast<char *>(ptr) + bytes;
+        if (hipMemMap(at, sz, 0, hd, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipMemRelease(hd);
+            return false;
+        }
+        hipMemAccessDesc desc{};
+        desc.location.type = hipMemLocationTypeDevice;
+        desc.location.id = device;
+        desc.flags = hipMemAccessFlagsProtReadWrite;
+        if (hipMemSetAccess(at, sz, &desc, 1) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipMemUnmap(at, sz);
+            (void)hipMemRelease(hd);
+            return false;
+        }
+        chunks.emplace_back(hd, sz);
+        bytes += sz;
+        ctx->in_use += sz;
+        return true;
+    }
+
+    // first use: reserve the address range (the device's memory size) and map `need` bytes
+    void start(gaca_context *c, size_t need) {
+        release();
+        ctx = c;
+        device = c->device;
+        int supported = 0;
+        size_t free_b = 0, total_b = 0;
+        hipMemAllocationProp prop{};
+        prop.type = hipMemAllocationTypePinned;
+        prop.location.type = hipMemLocationTypeDevice;
+        prop.location.id = device;
+        if (hipDeviceGetAttribute(&supported, hipDeviceAttributeVirtualMemoryManagementSupported, device) ==
+                hipSuccess &&
+            supported && hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+            hipMemGetAllocationGranularity(&gran, &prop, hipMemAllocationGranularityMinimum) == hipSuccess &&
+            gran > 0) {
+            // chunks in whole 2 MiB pages, so every chunk starts on a page boundary
+            gran = (((size_t)2 << 20) + gran - 1) / gran * gran;
+            reserved = (total_b + gran - 1) / gran * gran;
+            if (hipMemAddressReserve(&ptr, reserved, 0, nullptr, 0) == hipSuccess) {
+                vmm = true;
+                if (!map_more(std::max<size_t>(need, gran))) {
+                    release();
+                    throw Error{GACA_ERR_OOM, "device memory exhausted (mapping a growable buffer)"};
+                }
+                return;
+            }
+            ptr = nullptr;
+        }
+        (void)hipGetLastError();
+        vmm = false;
+        plain.alloc(c, std::max<size_t>(need, 16));
+        ptr = plain.ptr;
+        bytes = plain.bytes;
+    }
+
+    // at least `need` bytes, keeping the first `used`; work on `st` that uses the buffer
+    // must be complete or ordered before the copy of the fallback path
+    void grow(gaca_context *c, size_t need, size_t used, hipStream_t st) {
+        if (!ptr) {
+            start(c, need);
+            return;
+        }
+        if (need <= bytes) return;
+        if (vmm) {
+            // steps of half the size, at most 4 GiB (mapped memory is never over-committed by
+            // much), at least 256 MiB
+            const size_t step = std::min<size_t>(bytes / 2, (size_t)4 << 30);
+            const size_t want = std::max(need - bytes, std::max<size_t>(step, (size_t)256 << 20));
+            if (map_more(want) || map_more(need - bytes)) return;
+            // the mapping could not be extended: move to an ordinary allocation
+            DevBuf nb;
+            nb.alloc(c, std::max(need, bytes + bytes / 2));
+            if (used > 0)
+                GACA_HIP_CHECK(hipMemcpyAsync(nb.ptr, ptr, std::min(used, bytes), hipMemcpyDeviceToDevice, st));
+            GACA_HIP_CHECK(hipStreamSynchronize(st));
+            release();
+            ctx = c;
+            std::swap(plain.ptr, nb.ptr);
+            std::swap(plain.bytes, nb.bytes);
+            plain.ctx = c;
+            nb.ctx = nullptr;
+            ptr = plain.ptr;
+            bytes = plain.bytes;
+            return;
+        }
+        DevBuf nb;
+        nb.alloc(c, std::max(need, bytes + bytes / 2));
+        if (used > 0)
+            GACA_HIP_CHECK(hipMemcpyAsync(nb.ptr, plain.ptr, std::min(used, bytes), hipMemcpyDeviceToDevice, st));
+        GACA_HIP_CHECK(hipStreamSynchronize(st));
+        std::swap(plain.ptr, nb.ptr);
+        std::swap(plain.bytes, nb.bytes);
+        ptr = plain.ptr;
+        bytes = plain.bytes;
+    }
+
+    // drop the mapped tail beyond `used` bytes (whole chunks only; used = 0 unmaps all and
+    // keeps the address range); the buffer must be idle
+    void shrink(size_t used) {
+        if (!vmm || chunks.empty()) return;
+        if (used > bytes) return;
+        (void)hipDeviceSynchronize();
+        while (!chunks.empty() && bytes - chunks.back().second >= used) {
+            const auto c = chunks.back();
+            bytes -= c.second;
+            (void)hipMemUnmap(static_cast<char *>(ptr) + bytes, c.second);
+            (void)hipMemRelease(c.first);
+            ctx->in_use -= c.second;
+            chunks.pop_back();
+        }
+    }
+};
+
 // Pinned host staging buffer (per-iteration uploads and status read-back).
 struct PinnedBuf {
     void *ptr = nullptr;
@@ -93,8 +264,9 @@ struct PinnedBuf {
 
 // Far-field working memory, kept by the problem across builds (it only grows).
 struct FarScratch {
-    DevBuf blk, state, coef, hs, fs, usedk, hpool, fgpool, uw, part, act, map_chunk, map_tile,
-        status, copies, gathers;
+    DevBuf blk, state, coef, hs, fs, usedk, uw, part, act, map_chunk, map_tile, status, copies,
+        gathers;
+    GrowBuf hpool, fgpool;
     PinnedBuf h_act, h_status, h_copies, h_gathers;
 };
 
@@ -167,7 +339,8 @@ struct gaca_hmatrix {
     int32_t rcap = 0;
     int64_t nfar = 0;
     double eps_aca_used = 0.0;
-    DevBuf d_near, d_arena, d_fib, d_meta, d_cmeta, d_cross_off, d_fib_off, d_far4;
+    DevBuf d_near, d_meta, d_cmeta, d_cross_off, d_fib_off, d_far4;
+    GrowBuf d_arena, d_fib;   // factor and fibre arenas (grow in place)
     std::vector<FarMeta> meta;
     std::vector<CrossMeta> cmeta;
     std::vector<int64_t> cross_off, fib_off;
@@ -521,6 +694,22 @@ static void ensure(gaca_context *ctx, DevBuf &buf, size_t need) {
 }
 
 // Replace buf by a copy holding its first `used` bytes when that frees a useful amount.
+static void compact(gaca_context *ctx, DevBuf &buf, size_t used, hipStream_t st);
+
+static void grow_keep(gaca_context *ctx, GrowBuf &buf, size_t need, size_t used, hipStream_t st) {
+    buf.grow(ctx, need, used, st);
+}
+
+static void compact(gaca_context *ctx, GrowBuf &buf, size_t used, hipStream_t st) {
+    if (buf.vmm) {
+        buf.shrink(used);
+        return;
+    }
+    compact(ctx, buf.plain, used, st);
+    buf.ptr = buf.plain.ptr;
+    buf.bytes = buf.plain.bytes;
+}
+
 static void compact(gaca_context *ctx, DevBuf &buf, size_t used, hipStream_t st) {
     if (used == 0 || buf.bytes < (64u << 20) || used > buf.bytes / 4 * 3) return;
     DevBuf tight;
@@ -590,8 +779,16 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
     // block descriptors, launch classes and memory estimates
     std::vector<FarBlockDev> desc(nfar);
     std::vector<int> kind(nfar);
-    std::vector<double> est(nfar);
-    const int rguess = std::min(rcap, 24);
+    // memory estimate of a block in a batch with rg faces per block (pool slots, fibres and
+    // Gram rows, current factors, expand partials, state)
+    auto est_of = [&](int64_t b, double rg) {
+        const double m = (double)far[b][1], n = (double)far[b][3], mn = m * n;
+        const double rho_max = std::min(m, n);
+        const double tiles = far_kind((int)m, (int)n, mixed) == 3 ? std::ceil(m / 32.0) * std::ceil(n / 32.0) : 1.0;
+        return rho_max * (m + n) * es + (rg + 1) * mn * es + rg * (double)(L + rcap) * 16 +
+               tiles * PS * 8 + sizeof(FarStateDev) + sizeof(FarBlockDev) + rcap * 32.0 + L + 64;
+    };
+    double rguess = std::min(rcap, 24);
     double factor_guess = 0.0;
     for (int64_t b = 0; b < nfar; ++b) {
         const int m = (int)far[b][1], n = (int)far[b][3];
@@ -627,10 +824,6 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
         desc[b] = d;
         kind[b] = far_kind(m, n, mixed);
         const double mn = (double)m * n;
-        const double tiles = kind[b] == 3 ? std::ceil(m / 32.0) * std::ceil(n / 32.0) : 1.0;
-        est[b] = (double)rho_max * (m + n) * es + (rguess + 1) * mn * es +
-                 rguess * (double)(L + rcap) * 16 + tiles * PS * 8 + sizeof(FarStateDev) +
-                 sizeof(FarBlockDev) + rcap * 32.0 + L + 64;
         // first guess of the factor storage (the arena grows by half when it runs short)
         factor_guess += std::min(mn * L, (double)std::min(rcap, 8) * std::min(rho_max, 16) * (m + n));
     }
@@ -638,15 +831,6 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
         (void)hipGetLastError();
         free_b = (size_t)p->opt.batch_bytes;
-    }
-    const double budget = std::max(64.0 * (1 << 20), std::min((double)p->opt.batch_bytes, 0.5 * free_b));
-    std::vector<std::pair<int64_t, int64_t>> batches;
-    for (int64_t s0 = 0; s0 < nfar;) {
-        int64_t e = s0;
-        double acc = 0.0;
-        while (e < nfar && (e == s0 || acc + est[e] <= budget)) acc += est[e++];
-        batches.emplace_back(s0, e);
-        s0 = e;
     }
 
     main_work();   // near field on the context stream, concurrently with the far field
@@ -672,8 +856,8 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
 
     FarScratch &W = p->fsc;
     size_t arena_used = 0, fib_used = 0;
-    h->d_arena.alloc(ctx, (size_t)std::max(1.0e5, factor_guess) * es);
-    h->d_fib.alloc(ctx, (size_t)std::max<int64_t>(1024, nfar * (int64_t)std::min(rcap, 16) * L) *
+    h->d_arena.start(ctx, (size_t)std::max(1.0e5, factor_guess) * es);
+    h->d_fib.start(ctx, (size_t)std::max<int64_t>(1024, nfar * (int64_t)std::min(rcap, 16) * L) *
                             sizeof(double2));
     // algorithmic work model (flops; a complex multiply-add is 8): per quadrature point x
     // frequency the single layer costs 105 (distance 8, sqrt 13, exp 31, sincos 36,
@@ -687,7 +871,29 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
     int iters_max = 0, n_launch = 0;
     double evals = 0.0;
 
-    for (const auto &bt : batches) {
+    // batches of consecutive blocks whose estimate fits the memory free at their start; the
+    // faces-per-block guess of the estimate follows what the previous batches used
+    for (int64_t bnext = 0; bnext < nfar;) {
+        double budget = 0.0;
+        {
+            size_t fb = 0, tb = 0;
+            if (hipMemGetInfo(&fb, &tb) != hipSuccess) {
+                (void)hipGetLastError();
+                fb = (size_t)p->opt.batch_bytes;
+            }
+            // the pools held from the previous batch are reused
+            fb += W.hpool.bytes + W.fgpool.bytes + W.uw.bytes + W.part.bytes;
+            budget = std::max(64.0 * (1 << 20), std::min((double)p->opt.batch_bytes, 0.5 * (double)fb));
+        }
+        int64_t blast = bnext;
+        for (double acc = 0.0; blast < nfar;) {
+            const double e = est_of(blast, rguess);
+            if (blast > bnext && acc + e > budget) break;
+            acc += e;
+            ++blast;
+        }
+        const std::pair<int64_t, int64_t> bt{bnext, blast};
+        bnext = blast;
         const int64_t base = bt.first;
         const int nb = (int)(bt.second - bt.first);
         std::vector<FarBlockDev> bdesc(desc.begin() + bt.first, desc.begin() + bt.second);
@@ -771,13 +977,13 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
                 }
             }
             if (iter == 0) {
-                // first guess of the pool sizes (12 faces per block), kept by the problem
-                // across builds; both grow by half when they run short
+                // first guess of the pool sizes (rguess faces per block), kept by the problem
+                // across builds; both grow in place when they run short
                 double hg = 0.0;
                 for (int lb = 0; lb < nb; ++lb) hg += (double)bdesc[lb].m * bdesc[lb].n;
-                const double hcap = std::min(13.0 * hg, std::max((double)hused, 0.3 * free_b / es));
+                const double hcap = std::min((rguess + 1) * hg, std::max((double)hused, 0.3 * free_b / es));
                 grow_keep(ctx, W.hpool, (size_t)std::max((double)hused, hcap) * es, 0, s0);
-                grow_keep(ctx, W.fgpool, (size_t)nb * 13 * (L + rcap) * sizeof(double2), 0, s0);
+                grow_keep(ctx, W.fgpool, (size_t)(nb * (rguess + 1)) * (L + rcap) * sizeof(double2), 0, s0);
             }
             grow_keep(ctx, W.hpool, (size_t)hused * es, (size_t)hprev * es, s0);
             grow_keep(ctx, W.fgpool, (size_t)fused * sizeof(double2), (size_t)fprev * sizeof(double2), s0);
@@ -946,6 +1152,36 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
         ++n_launch;
         GACA_HIP_CHECK(hipStreamSynchronize(s0));
         iters_max = std::max(iters_max, iter);
+        {
+            double mn_sum = 0.0;
+            for (int lb = 0; lb < nb; ++lb) mn_sum += (double)bdesc[lb].m * bdesc[lb].n;
+            rguess = std::min((double)rcap, std::max(4.0, 1.25 * (double)hused / std::max(mn_sum, 1.0)));
+        }
+        if (p->opt.verbose) {
+            size_t fb = 0, tb = 0;
+            if (hipMemGetInfo(&fb, &tb) != hipSuccess) (void)hipGetLastError();
+            std::fprintf(stderr, "gaca far field: batch of blocks %lld..%lld of %lld done, %d iterations, "
+                         "%.1f ms since the start; factors %.2f GB, fibres %.2f GB, face pool %.2f GB, "
+                         "free %.2f GB\n", (long long)bt.first, (long long)bt.second, (long long)nfar, iter,
+                         wall_ms_since(t_entry), arena_used * es / 1e9, fib_used * 16.0 / 1e9,
+                         W.hpool.bytes / 1e9, fb / 1e9);
+            std::fflush(stderr);
+        }
+        // give the pools' pages back between batches (in-place pools regrow without copies)
+        if (bnext < nfar) {
+            if (W.hpool.vmm) W.hpool.shrink(0);
+            if (W.fgpool.vmm) W.fgpool.shrink(0);
+        }
+    }
+    // large pools are not kept for the next build (they hold no result)
+    {
+        size_t held = W.hpool.bytes + W.fgpool.bytes + W.uw.bytes + W.part.bytes;
+        if (total_b > 0 && held > total_b / 8) {
+            W.hpool.release();
+            W.fgpool.release();
+            W.uw.release();
+            W.part.release();
+        }
     }
     GACA_HIP_CHECK(hipEventRecord(ev[EV_END], s0));
     GACA_HIP_CHECK(hipStreamWaitEvent(ctx->stream, ev[EV_END], 0));
@@ -986,6 +1222,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
     for (const auto &mt : h->meta) tmax = std::max<int64_t>(tmax, mt.aca_ticks);
     st.ms_far_aca_block_max = (double)tmax / wclk_khz;
     st.ms_host_setup = ms_setup;
+    st.arena_in_place = h->d_arena.vmm ? 1 : 0;
     st.ms_host_finish = wall_ms_since(t_fin);
 }
 
@@ -1291,7 +1528,6 @@ static void apply_mfma(gaca_hmatrix *h, const ApplyDev &a, int32_t nrhs, const f
                        float2 *Y, hipStream_t st) {
     gaca_problem *p = h->p;
     gaca_context *ctx = p->ctx;
-    const int nrc_max = std::min(nrhs, 64);
     const int64_t nfar = h->nfar;
     std::vector<int32_t> sum_rho(std::max<int64_t>(nfar, 1), 0);
     int64_t rho_tot = 0;
@@ -1299,11 +1535,38 @@ static void apply_mfma(gaca_hmatrix *h, const ApplyDev &a, int32_t nrhs, const f
         sum_rho[b] = h->meta[b].sum_rho;
         rho_tot += sum_rho[b];
     }
+    // right-hand sides per chunk: up to 64, with Z (sum of face ranks x chunk) within a
+    // quarter of the free memory
+    int nrc_max = std::min(nrhs, 64);
+    {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && rho_tot > 0) {
+            const double fit = 0.25 * (double)free_b / ((double)rho_tot * sizeof(float2));
+            nrc_max = std::max(1, std::min(nrc_max, (int)std::min(fit, 64.0)));
+        } else {
+            (void)hipGetLastError();
+        }
+    }
     h->d_msumrho.upload(ctx, sum_rho);
     ensure(ctx, h->d_mz, (size_t)std::max<int64_t>(rho_tot * nrc_max, 1) * sizeof(float2));
     int max_leaf = 1;
     for (int32_t m : p->leaf_m) max_leaf = std::max(max_leaf, m);
     const int row_tiles = (max_leaf + 31) / 32;
+    // algorithmic work of the whole apply (complex multiply-add = 8 flops)
+    {
+        const int L = p->L;
+        double macs = (double)p->near_elems * nrhs;
+        for (int64_t b = 0; b < nfar; ++b) {
+            const double m = (double)p->part.far[b][1], n = (double)p->part.far[b][3];
+            macs += ((double)h->meta[b].rank * L * n + (double)sum_rho[b] * (m + n)) * nrhs;
+        }
+        h->st.apply_flops = 8.0 * macs;
+        h->st.apply_operator_bytes = (double)(h->st.bytes_far + h->st.bytes_near);
+    }
+    hipEvent_t ev0, ev1;
+    GACA_HIP_CHECK(hipEventCreate(&ev0));
+    GACA_HIP_CHECK(hipEventCreate(&ev1));
+    GACA_HIP_CHECK(hipEventRecord(ev0, st));
     const size_t t_budget = (size_t)1 << 31;   // bytes of T per far batch
     for (int c0 = 0; c0 < nrhs; c0 += nrc_max) {
         const int nrc = std::min(nrc_max, nrhs - c0);
@@ -1377,6 +1640,13 @@ static void apply_mfma(gaca_hmatrix *h, const ApplyDev &a, int32_t nrhs, const f
         // the next chunk rewrites Z and the offsets
         GACA_HIP_CHECK(hipStreamSynchronize(st));
     }
+    GACA_HIP_CHECK(hipEventRecord(ev1, st));
+    GACA_HIP_CHECK(hipEventSynchronize(ev1));
+    float ms = 0.0f;
+    GACA_HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    h->st.ms_apply = ms;
 }
 
 gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, const void *X,
