@@ -74,7 +74,7 @@ typedef struct {
                                  128; default 64) */
     int32_t threads_large;    /* face-ACA workgroup size for faces with m n > 2304 (256, 512
                                  or 1024; default 0: 1024 while an iteration has at most two
-                                 such faces per compute unit, else 256) */
+                                 such faces per compute unit, else 512) */
     int32_t verbose;          /* 1: one progress line per far-field batch on stderr */
 } gaca_options;
 
@@ -128,6 +128,8 @@ typedef struct {
     double ms_apply;
     double apply_flops;
     double apply_operator_bytes;
+    double ms_apply_part[3];      /* device time of the apply kernels: far T = F X, far Z = W T, leaf */
+    double apply_flops_part[3];
     int32_t arena_in_place;       /* 1: the factor arena grows in place (virtual memory) */
 } gaca_stats;
 

@@ -50,7 +50,7 @@ class Stats(ctypes.Structure):
                 ("launches_by_kind", I32 * 4), ("far_flops_by_kind", F64 * 4),
                 ("ms_far_aca_block_max", F64), ("ms_host_setup", F64), ("ms_host_finish", F64),
                 ("ms_apply", F64), ("apply_flops", F64), ("apply_operator_bytes", F64),
-                ("arena_in_place", I32)]
+                ("ms_apply_part", F64 * 3), ("apply_flops_part", F64 * 3), ("arena_in_place", I32)]
 
 
 def lib_path() -> str:

@@ -889,8 +889,8 @@ static void aca_dispatch(int kind, int threads, const AcaParams &P, const FarBat
         // R and S in 128 KB of LDS: 4096 FP64 or 8192 FP32 complex entries each
         far_aca_small_kernel<512, MX, (MX ? 8192 : 4096), 128><<<nact, 512, 0, st>>>(P, bd, act);
     } else {
-        // latency shapes (few faces, one per CU): 1024 or 512 threads with ~110 KB of LDS
-        // history; throughput shape (many faces): 256 threads with 32 KB, several per CU
+        // one face per CU: 1024 or 512 threads with ~110 KB of LDS history; 256 threads with
+        // 32 KB, several faces per CU
         if (threads >= 1024)
             far_aca_large_kernel<1024, MX, 106496><<<nact, 1024, 0, st>>>(P, bd, act);
         else if (threads >= 512)

@@ -82,6 +82,7 @@ struct GrowBuf {
     int device = 0;
     std::vector<std::pair<hipMemGenericAllocationHandle_t, size_t>> chunks;
     DevBuf plain;             // fallback storage
+    std::string last_fail;    // the call that failed last (for error messages)
     GrowBuf() = default;
     GrowBuf(const GrowBuf &) = delete;
     GrowBuf &operator=(const GrowBuf &) = delete;
@@ -109,9 +110,19 @@ struct GrowBuf {
         vmm = false;
     }
 
-    // map at least `add` more bytes (rounded to the granularity); false when out of memory
+    // map at least `add` more bytes as chunks of one size, `gran` (the runtime refused access
+    // rights on some mixes of chunk sizes; uniform chunks were always accepted); false when
+    // out of memory
     bool map_more(size_t add) {
-        const size_t sz = (add + gran - 1) / gran * gran;
+        size_t left = (add + gran - 1) / gran * gran;
+        while (left > 0) {
+            if (!map_chunk(gran)) return false;
+            left -= gran;
+        }
+        return true;
+    }
+
+    bool map_chunk(size_t sz) {
         if (bytes + sz > reserved) return false;
         if (ctx->limit && ctx->in_use + sz > ctx->limit) return false;
         hipMemAllocationProp prop{};
@@ -119,25 +130,29 @@ struct GrowBuf {
         prop.location.type = hipMemLocationTypeDevice;
         prop.location.id = device;
         hipMemGenericAllocationHandle_t hd{};
-        if (hipMemCreate(&hd, sz, &prop, 0) != hipSuccess) {
+        auto fail = [&](const char *what, hipError_t e) {
+            last_fail = std::string(what) + " of " + std::to_string(sz >> 20) + " MiB at offset " +
+                        std::to_string(bytes >> 20) + " MiB: " + hipGetErrorString(e);
             (void)hipGetLastError();
             return false;
-        }
+        };
+        hipError_t e = hipMemCreate(&hd, sz, &prop, 0);
+        if (e != hipSuccess) return fail("hipMemCreate", e);
         char *at = static_cast<char *>(ptr) + bytes;
-        if (hipMemMap(at, sz, 0, hd, 0) != hipSuccess) {
-            (void)hipGetLastError();
+        e = hipMemMap(at, sz, 0, hd, 0);
+        if (e != hipSuccess) {
             (void)hipMemRelease(hd);
-            return false;
+            return fail("hipMemMap", e);
         }
         hipMemAccessDesc desc{};
         desc.location.type = hipMemLocationTypeDevice;
         desc.location.id = device;
         desc.flags = hipMemAccessFlagsProtReadWrite;
-        if (hipMemSetAccess(at, sz, &desc, 1) != hipSuccess) {
-            (void)hipGetLastError();
+        e = hipMemSetAccess(at, sz, &desc, 1);
+        if (e != hipSuccess) {
             (void)hipMemUnmap(at, sz);
             (void)hipMemRelease(hd);
-            return false;
+            return fail("hipMemSetAccess", e);
         }
         chunks.emplace_back(hd, sz);
         bytes += sz;
@@ -161,14 +176,15 @@ struct GrowBuf {
             supported && hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
             hipMemGetAllocationGranularity(&gran, &prop, hipMemAllocationGranularityMinimum) == hipSuccess &&
             gran > 0) {
-            // chunks in whole 2 MiB pages, so every chunk starts on a page boundary
-            gran = (((size_t)2 << 20) + gran - 1) / gran * gran;
+            // uniform 64 MiB chunks (a multiple of the granularity)
+            gran = (((size_t)64 << 20) + gran - 1) / gran * gran;
             reserved = (total_b + gran - 1) / gran * gran;
             if (hipMemAddressReserve(&ptr, reserved, 0, nullptr, 0) == hipSuccess) {
                 vmm = true;
                 if (!map_more(std::max<size_t>(need, gran))) {
+                    const std::string why = last_fail;
                     release();
-                    throw Error{GACA_ERR_OOM, "device memory exhausted (mapping a growable buffer)"};
+                    throw Error{GACA_ERR_OOM, "device memory exhausted (mapping a growable buffer: " + why + ")"};
                 }
                 return;
             }
@@ -190,11 +206,13 @@ struct GrowBuf {
         }
         if (need <= bytes) return;
         if (vmm) {
-            // steps of half the size, at most 4 GiB (mapped memory is never over-committed by
-            // much), at least 256 MiB
+            // grow by half the size, at most 4 GiB (mapped memory is never over-committed by
+            // much), at least 256 MiB; short of that, by what is needed
             const size_t step = std::min<size_t>(bytes / 2, (size_t)4 << 30);
-            const size_t want = std::max(need - bytes, std::max<size_t>(step, (size_t)256 << 20));
-            if (map_more(want) || map_more(need - bytes)) return;
+            const size_t target = bytes + std::max(need - bytes, std::max<size_t>(step, (size_t)256 << 20));
+            while (bytes < target)
+                if (!map_more(gran)) break;
+            if (bytes >= need) return;
             // the mapping could not be extended: move to an ordinary allocation
             DevBuf nb;
             nb.alloc(c, std::max(need, bytes + bytes / 2));
@@ -1037,7 +1055,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             // large faces: one big workgroup per face while they fit the chip at once (the
             // aca phase is then bound by the longest face), else smaller, several per CU
             int tl = p->opt.threads_large;
-            if (tl <= 0) tl = nlarge <= 2 * ctx->n_cu ? 1024 : 256;
+            if (tl <= 0) tl = nlarge <= 2 * ctx->n_cu ? 1024 : 512;
             const int threads[4] = {p->opt.threads_small, 256, 512, tl};
             int nl = 0;
             for (int k = 3; k >= 0; --k) {
@@ -1552,20 +1570,33 @@ static void apply_mfma(gaca_hmatrix *h, const ApplyDev &a, int32_t nrhs, const f
     int max_leaf = 1;
     for (int32_t m : p->leaf_m) max_leaf = std::max(max_leaf, m);
     const int row_tiles = (max_leaf + 31) / 32;
-    // algorithmic work of the whole apply (complex multiply-add = 8 flops)
+    // algorithmic work of the whole apply (complex multiply-add = 8 flops): far T = F X
+    // (r L n per rhs), far Z = W T (sum_rho n), leaf (near m n L + far U Z: sum_rho m)
     {
         const int L = p->L;
-        double macs = (double)p->near_elems * nrhs;
+        double mt = 0.0, mz = 0.0, ml = (double)p->near_elems;
         for (int64_t b = 0; b < nfar; ++b) {
             const double m = (double)p->part.far[b][1], n = (double)p->part.far[b][3];
-            macs += ((double)h->meta[b].rank * L * n + (double)sum_rho[b] * (m + n)) * nrhs;
+            mt += (double)h->meta[b].rank * L * n;
+            mz += (double)sum_rho[b] * n;
+            ml += (double)sum_rho[b] * m;
         }
-        h->st.apply_flops = 8.0 * macs;
+        h->st.apply_flops_part[0] = 8.0 * mt * nrhs;
+        h->st.apply_flops_part[1] = 8.0 * mz * nrhs;
+        h->st.apply_flops_part[2] = 8.0 * ml * nrhs;
+        h->st.apply_flops = 8.0 * (mt + mz + ml) * nrhs;
         h->st.apply_operator_bytes = (double)(h->st.bytes_far + h->st.bytes_near);
     }
-    hipEvent_t ev0, ev1;
+    hipEvent_t ev0, ev1, ep[4];
     GACA_HIP_CHECK(hipEventCreate(&ev0));
     GACA_HIP_CHECK(hipEventCreate(&ev1));
+    for (auto &e : ep) GACA_HIP_CHECK(hipEventCreate(&e));
+    double ms_part[3] = {0, 0, 0};
+    auto part_ms = [&](int x, int y) {
+        float ms = 0.0f;
+        GACA_HIP_CHECK(hipEventElapsedTime(&ms, ep[x], ep[y]));
+        return (double)ms;
+    };
     GACA_HIP_CHECK(hipEventRecord(ev0, st));
     const size_t t_budget = (size_t)1 << 31;   // bytes of T per far batch
     for (int c0 = 0; c0 < nrhs; c0 += nrc_max) {
@@ -1627,18 +1658,26 @@ static void apply_mfma(gaca_hmatrix *h, const ApplyDev &a, int32_t nrhs, const f
                 d.t_tile0 = h->d_mttile0.as<int64_t>();
                 d.nt_items = (int32_t)ti.size();
                 d.z_items = h->d_mzitems.as<MfmaZItem>();
+                GACA_HIP_CHECK(hipEventRecord(ep[0], st));
                 launch_apply_far_t(a, d, ntiles, X, h->d_mt.as<float2>(), st);
+                GACA_HIP_CHECK(hipEventRecord(ep[1], st));
                 launch_apply_far_z(a, d, (int)zi.size(), h->d_mt.as<float2>(), h->d_mz.as<float2>(), st);
+                GACA_HIP_CHECK(hipEventRecord(ep[2], st));
                 GACA_HIP_CHECK(hipGetLastError());
                 // the next batch reuses T and the item lists
                 GACA_HIP_CHECK(hipStreamSynchronize(st));
+                ms_part[0] += part_ms(0, 1);
+                ms_part[1] += part_ms(1, 2);
             }
             s0 = e;
         }
+        GACA_HIP_CHECK(hipEventRecord(ep[2], st));
         launch_apply_leaf_mfma(a, d, row_tiles, X, h->d_mz.as<float2>(), Y, st);
+        GACA_HIP_CHECK(hipEventRecord(ep[3], st));
         GACA_HIP_CHECK(hipGetLastError());
         // the next chunk rewrites Z and the offsets
         GACA_HIP_CHECK(hipStreamSynchronize(st));
+        ms_part[2] += part_ms(2, 3);
     }
     GACA_HIP_CHECK(hipEventRecord(ev1, st));
     GACA_HIP_CHECK(hipEventSynchronize(ev1));
@@ -1646,7 +1685,9 @@ static void apply_mfma(gaca_hmatrix *h, const ApplyDev &a, int32_t nrhs, const f
     GACA_HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
     (void)hipEventDestroy(ev0);
     (void)hipEventDestroy(ev1);
+    for (auto &e : ep) (void)hipEventDestroy(e);
     h->st.ms_apply = ms;
+    for (int k = 0; k < 3; ++k) h->st.ms_apply_part[k] = ms_part[k];
 }
 
 gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, const void *X,
