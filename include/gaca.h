@@ -72,9 +72,8 @@ typedef struct {
     uint64_t batch_bytes;     /* far-field scratch per batch of blocks (default 24 GiB) */
     int32_t threads_small;    /* face-ACA workgroup size for faces with m n <= 1024 (64 or
                                  128; default 64) */
-    int32_t threads_large;    /* face-ACA workgroup size for faces with m n > 2304 (256, 512
-                                 or 1024; default 0: 1024 while an iteration has at most two
-                                 such faces per compute unit, else 512) */
+    int32_t threads_large;    /* face-ACA workgroup size for the large faces (256, 512 or
+                                 1024; default 0: 512) */
     int32_t verbose;          /* 1: one progress line per far-field batch on stderr */
 } gaca_options;
 

@@ -39,6 +39,8 @@ namespace gaca {
 constexpr int kMaxRowsLds = 8192;   // rows of a block (used-row flags in LDS)
 constexpr int kMaxLds = 1024;       // frequencies
 constexpr int kMaxRcap = 256;       // crosses per block
+constexpr int kCoefLds = 512;       // staged history coefficients of the large-face ACA
+constexpr int kCurRegs = 4;         // current u, w in registers for m, n <= 256
 
 // Face entry at (il, jl, kk): FP64 value (FT = double2), the dense test tensor, or the
 // scaled FP32 value (FT = float2).
@@ -332,6 +334,7 @@ __global__ void __launch_bounds__(NT)
 
     __shared__ double2 hist_raw[HB / sizeof(double2)];
     __shared__ FT part[NT];       // split-K partial sums of row / column corrections
+    __shared__ FT cbuf[kCoefLds]; // coefficients u_q'[i] / w_q'[jp] of the HBM part of the history
     __shared__ unsigned char used_row[kMaxRowsLds];
     __shared__ double redbuf[4 * NW + 4];
     Red<NT> red{redbuf};
@@ -340,7 +343,9 @@ __global__ void __launch_bounds__(NT)
     FT *Uh = reinterpret_cast<FT *>(hist_raw);       // [qL][m]
     FT *Wh = Uh + (int64_t)qL * m;                    // [qL][n]
 
-    // sum_{q' in [q0, q1)} a_q'[ia] b_q'[ib] over the histories (LDS part, then HBM part)
+    // sum_{q' in [q0, q1)} a_q'[ia] b_q'[ib] over the histories: the LDS part, then the HBM
+    // part with the coefficients a_q'[ia] staged in cbuf (q' < qL + kCoefLds; eight loads of
+    // b in flight), then any rest with both operands from HBM
     auto hdot = [&](const FT *ah, const FT *ag, int la, int ia, const FT *bh, const FT *bg,
                     int lb, int ib, int q0, int q1) {
         FT acc0 = czero<FT>(), acc1 = czero<FT>();
@@ -351,11 +356,31 @@ __global__ void __launch_bounds__(NT)
             acc1 = cfma(ah[(qq + 1) * la + ia], bh[(qq + 1) * lb + ib], acc1);
         }
         if (qq < qm) acc0 = cfma(ah[qq * la + ia], bh[qq * lb + ib], acc0);
+        qq = max(q0, qL);
+        const int qc = min(q1, qL + kCoefLds);
+        constexpr int NB = NT >= 1024 ? 4 : 8;   // loads in flight (register budget)
+        for (; qq + NB <= qc; qq += NB) {
+            FT bv[NB];
+#pragma unroll
+            for (int t = 0; t < NB; ++t) bv[t] = bg[(int64_t)(qq + t) * lb + ib];
+#pragma unroll
+            for (int t = 0; t < NB; t += 2) {
+                acc0 = cfma(cbuf[qq + t - qL], bv[t], acc0);
+                acc1 = cfma(cbuf[qq + t + 1 - qL], bv[t + 1], acc1);
+            }
+        }
+        for (; qq < qc; ++qq) acc0 = cfma(cbuf[qq - qL], bg[(int64_t)qq * lb + ib], acc0);
         FT acc = cadd(acc0, acc1);
-        if (q1 > qL)
+        if (q1 > qc)
             acc = cadd(acc, dot_strided<FT, (NT >= 1024 ? 4 : 8)>(ag + ia, la, bg + ib, lb,
-                                                                    max(q0, qL), q1));
+                                                                    max(q0, qc), q1));
         return acc;
+    };
+    // stage a_q'[ia] for q' in [qL, min(q, qL + kCoefLds)) (ends with a barrier)
+    auto stage_coef = [&](const FT *ag, int la, int ia, int q) {
+        const int nc = min(q, qL + kCoefLds) - qL;
+        for (int t = tid; t < nc; t += NT) cbuf[t] = ag[(int64_t)(qL + t) * la + ia];
+        __syncthreads();
     };
 
     for (int r = tid; r < m; r += NT) used_row[r] = 0;
@@ -368,6 +393,7 @@ __global__ void __launch_bounds__(NT)
         FT *Uq = Ub + (int64_t)q * m;
         // row i of R - sum_{q'<q} u_q'[i] w_q'
         double mx = 0.0;
+        if (q > qL) stage_coef(Ub, m, i, q);
         if (splitw > 1) {
             const int s = tid / n, j = tid - s * n;
             if (s < splitw) {
@@ -417,6 +443,7 @@ __global__ void __launch_bounds__(NT)
         }
         __syncthreads();
         // column jp of R - sum_{q'<q} w_q'[jp] u_q'
+        if (q > qL) stage_coef(Wb, n, jp, q);
         if (splitu > 1) {
             const int s = tid / m, r = tid - s * m;
             if (s < splitu) {
@@ -440,10 +467,64 @@ __global__ void __launch_bounds__(NT)
             }
         }
         __syncthreads();
-        // sum_{q'<q} Re(<u_q, u_q'> <w_q, w_q'>) in FP64, one q' per wave iteration
+        // sum_{q'<q} Re(<u_q, u_q'> <w_q, w_q'>) in FP64
         const FT *uc = q < qL ? Uh + (int64_t)q * m : Uq;
         const FT *wc = q < qL ? Wh + (int64_t)q * n : Wq;
         double cr = 0.0;
+        constexpr int CR = NT >= 1024 ? 3 : kCurRegs;
+        if (m <= 64 * CR && n <= 64 * CR) {
+            // u_q, w_q held in registers; two q' per wave iteration, all loads issued first
+            double2 ucr[CR], wcr[CR];
+#pragma unroll
+            for (int t = 0; t < CR; ++t) {
+                const int r = lane + 64 * t;
+                ucr[t] = r < m ? to_d2(uc[r]) : make_double2(0.0, 0.0);
+                wcr[t] = r < n ? to_d2(wc[r]) : make_double2(0.0, 0.0);
+            }
+            constexpr int QPI = NT >= 1024 ? 1 : 2;   // q' per wave iteration (registers)
+            for (int q0 = wave; q0 < q; q0 += QPI * NW) {
+                const int qb = q0 + NW;
+                const bool two = QPI == 2 && qb < q;
+                const FT *up0 = q0 < qL ? Uh + (int64_t)q0 * m : Ub + (int64_t)q0 * m;
+                const FT *wp0 = q0 < qL ? Wh + (int64_t)q0 * n : Wb + (int64_t)q0 * n;
+                const FT *up1 = qb < qL ? Uh + (int64_t)qb * m : Ub + (int64_t)qb * m;
+                const FT *wp1 = qb < qL ? Wh + (int64_t)qb * n : Wb + (int64_t)qb * n;
+                FT u0[CR], w0[CR], u1[CR], w1[CR];
+#pragma unroll
+                for (int t = 0; t < CR; ++t) {
+                    const int r = lane + 64 * t;
+                    u0[t] = r < m ? up0[r] : czero<FT>();
+                    w0[t] = r < n ? wp0[r] : czero<FT>();
+                    if (QPI == 2) {
+                        u1[t] = (two && r < m) ? up1[r] : czero<FT>();
+                        w1[t] = (two && r < n) ? wp1[r] : czero<FT>();
+                    } else {
+                        u1[t] = czero<FT>();
+                        w1[t] = czero<FT>();
+                    }
+                }
+                double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                for (int t = 0; t < CR; ++t) {
+                    double2 v = cmulc(ucr[t], to_d2(u0[t]));
+                    a[0] += v.x;
+                    a[1] += v.y;
+                    v = cmulc(wcr[t], to_d2(w0[t]));
+                    a[2] += v.x;
+                    a[3] += v.y;
+                    v = cmulc(ucr[t], to_d2(u1[t]));
+                    a[4] += v.x;
+                    a[5] += v.y;
+                    v = cmulc(wcr[t], to_d2(w1[t]));
+                    a[6] += v.x;
+                    a[7] += v.y;
+                }
+#pragma unroll
+                for (int t = 0; t < 4 * QPI; ++t) a[t] = wave_sum(a[t]);
+                cr += a[0] * a[2] - a[1] * a[3];
+                if (two) cr += a[4] * a[6] - a[5] * a[7];
+            }
+        } else
         for (int qq = wave; qq < q; qq += NW) {
             const FT *up = qq < qL ? Uh + (int64_t)qq * m : Ub + (int64_t)qq * m;
             const FT *wp = qq < qL ? Wh + (int64_t)qq * n : Wb + (int64_t)qq * n;
@@ -892,9 +973,9 @@ static void aca_dispatch(int kind, int threads, const AcaParams &P, const FarBat
         // one face per CU: 1024 or 512 threads with ~110 KB of LDS history; 256 threads with
         // 32 KB, several faces per CU
         if (threads >= 1024)
-            far_aca_large_kernel<1024, MX, 106496><<<nact, 1024, 0, st>>>(P, bd, act);
+            far_aca_large_kernel<1024, MX, 98304><<<nact, 1024, 0, st>>>(P, bd, act);
         else if (threads >= 512)
-            far_aca_large_kernel<512, MX, 114688><<<nact, 512, 0, st>>>(P, bd, act);
+            far_aca_large_kernel<512, MX, 106496><<<nact, 512, 0, st>>>(P, bd, act);
         else
             far_aca_large_kernel<256, MX, 32768><<<nact, 256, 0, st>>>(P, bd, act);
     }

@@ -110,9 +110,9 @@ struct GrowBuf {
         vmm = false;
     }
 
-    // map at least `add` more bytes as chunks of one size, `gran` (the runtime refused access
-    // rights on some mixes of chunk sizes; uniform chunks were always accepted); false when
-    // out of memory
+    // map at least `add` more bytes as chunks of one size, `gran`, fixed at the first use (the
+    // runtime refused access rights on some mixes of chunk sizes; uniform chunks were always
+    // accepted); false when out of memory
     bool map_more(size_t add) {
         size_t left = (add + gran - 1) / gran * gran;
         while (left > 0) {
@@ -176,8 +176,11 @@ struct GrowBuf {
             supported && hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
             hipMemGetAllocationGranularity(&gran, &prop, hipMemAllocationGranularityMinimum) == hipSuccess &&
             gran > 0) {
-            // uniform 64 MiB chunks (a multiple of the granularity)
-            gran = (((size_t)64 << 20) + gran - 1) / gran * gran;
+            // uniform chunks of 64 MiB to 1 GiB (a power of two near a sixteenth of the
+            // first request; a multiple of the granularity)
+            size_t chunk = (size_t)64 << 20;
+            while (chunk < ((size_t)1 << 30) && chunk * 16 < need) chunk *= 2;
+            gran = (chunk + gran - 1) / gran * gran;
             reserved = (total_b + gran - 1) / gran * gran;
             if (hipMemAddressReserve(&ptr, reserved, 0, nullptr, 0) == hipSuccess) {
                 vmm = true;
@@ -1052,10 +1055,10 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             launch_far_face(h->kernel, p->g, p->f, bd, dact, nchunk, s0);
             GACA_HIP_CHECK(hipEventRecord(ev[EV_F1], s0));
             for (int k = 0; k < 3; ++k) GACA_HIP_CHECK(hipStreamWaitEvent(ks[k], ev[EV_F1], 0));
-            // large faces: one big workgroup per face while they fit the chip at once (the
-            // aca phase is then bound by the longest face), else smaller, several per CU
+            // large faces: 512 threads (measured best on the 3072-triangle cube, where the
+            // longest face bounds the phase, and on the 20480-triangle sphere)
             int tl = p->opt.threads_large;
-            if (tl <= 0) tl = nlarge <= 2 * ctx->n_cu ? 1024 : 512;
+            if (tl <= 0) tl = 512;
             const int threads[4] = {p->opt.threads_small, 256, 512, tl};
             int nl = 0;
             for (int k = 3; k >= 0; --k) {
