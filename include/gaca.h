@@ -22,7 +22,9 @@
  *     (the library renumbers elements so that every cluster is a contiguous range; the
  *     permutation is returned by gaca_problem_perm);
  *   - handles are owned by the library and freed by the matching *_destroy; all inputs are
- *     copied; a handle is used by one host thread at a time.
+ *     copied; a handle is used by one host thread at a time.  Different problems of one
+ *     context may be built from different threads at the same time (each problem has its
+ *     own far-field streams and working memory), which overlaps their builds on the GPU.
  */
 #ifndef GACA_H
 #define GACA_H

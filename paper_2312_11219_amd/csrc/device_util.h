@@ -163,6 +163,25 @@ struct Red {
     }
 };
 
+// One-wave workgroups: the butterfly shuffles leave every lane with the result, so the
+// reductions need neither LDS nor a barrier (same values as the general version).
+template <>
+struct Red<64> {
+    double *buf;
+    __device__ double sum(double v) { return wave_sum(v); }
+    __device__ void sum3(double &a, double &b, double &c) {
+        a = wave_sum(a);
+        b = wave_sum(b);
+        c = wave_sum(c);
+    }
+    __device__ double max(double v) { return wave_max(v); }
+    __device__ void maxsum(double &a, double &b) {
+        a = wave_max(a);
+        b = wave_sum(b);
+    }
+    __device__ int imin(int v) { return wave_min(v); }
+};
+
 // sum_{qq in [q0, q1)} a[qq * sa] * b[qq * sb] with NACC independent partial sums, so that
 // 2 NACC loads are in flight per thread (the loops are latency-bound otherwise).
 template <class T, int NACC = 8>

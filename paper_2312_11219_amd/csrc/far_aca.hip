@@ -344,8 +344,8 @@ __global__ void __launch_bounds__(NT)
     FT *Wh = Uh + (int64_t)qL * m;                    // [qL][n]
 
     // sum_{q' in [q0, q1)} a_q'[ia] b_q'[ib] over the histories: the LDS part, then the HBM
-    // part with the coefficients a_q'[ia] staged in cbuf (q' < qL + kCoefLds; eight loads of
-    // b in flight), then any rest with both operands from HBM
+    // part with the coefficients a_q'[ia] staged in cbuf (q' < qL + kCoefLds; sixteen loads
+    // of b in flight), then any rest with both operands from HBM
     auto hdot = [&](const FT *ah, const FT *ag, int la, int ia, const FT *bh, const FT *bg,
                     int lb, int ib, int q0, int q1) {
         FT acc0 = czero<FT>(), acc1 = czero<FT>();
@@ -358,7 +358,7 @@ __global__ void __launch_bounds__(NT)
         if (qq < qm) acc0 = cfma(ah[qq * la + ia], bh[qq * lb + ib], acc0);
         qq = max(q0, qL);
         const int qc = min(q1, qL + kCoefLds);
-        constexpr int NB = NT >= 1024 ? 4 : 8;   // loads in flight (register budget)
+        constexpr int NB = NT >= 1024 ? 4 : 16;   // loads in flight (register budget)
         for (; qq + NB <= qc; qq += NB) {
             FT bv[NB];
 #pragma unroll
@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(NT)
         double cr = 0.0;
         constexpr int CR = NT >= 1024 ? 3 : kCurRegs;
         if (m <= 64 * CR && n <= 64 * CR) {
-            // u_q, w_q held in registers; two q' per wave iteration, all loads issued first
+            // u_q, w_q held in registers; QPI q' per wave iteration, all loads issued first
             double2 ucr[CR], wcr[CR];
 #pragma unroll
             for (int t = 0; t < CR; ++t) {
@@ -483,46 +483,38 @@ __global__ void __launch_bounds__(NT)
             }
             constexpr int QPI = NT >= 1024 ? 1 : 2;   // q' per wave iteration (registers)
             for (int q0 = wave; q0 < q; q0 += QPI * NW) {
-                const int qb = q0 + NW;
-                const bool two = QPI == 2 && qb < q;
-                const FT *up0 = q0 < qL ? Uh + (int64_t)q0 * m : Ub + (int64_t)q0 * m;
-                const FT *wp0 = q0 < qL ? Wh + (int64_t)q0 * n : Wb + (int64_t)q0 * n;
-                const FT *up1 = qb < qL ? Uh + (int64_t)qb * m : Ub + (int64_t)qb * m;
-                const FT *wp1 = qb < qL ? Wh + (int64_t)qb * n : Wb + (int64_t)qb * n;
-                FT u0[CR], w0[CR], u1[CR], w1[CR];
+                FT uu[QPI][CR], ww[QPI][CR];
 #pragma unroll
-                for (int t = 0; t < CR; ++t) {
-                    const int r = lane + 64 * t;
-                    u0[t] = r < m ? up0[r] : czero<FT>();
-                    w0[t] = r < n ? wp0[r] : czero<FT>();
-                    if (QPI == 2) {
-                        u1[t] = (two && r < m) ? up1[r] : czero<FT>();
-                        w1[t] = (two && r < n) ? wp1[r] : czero<FT>();
-                    } else {
-                        u1[t] = czero<FT>();
-                        w1[t] = czero<FT>();
+                for (int g = 0; g < QPI; ++g) {
+                    const int qg = q0 + g * NW;
+                    const bool ok = qg < q;
+                    const FT *up = qg < qL ? Uh + (int64_t)qg * m : Ub + (int64_t)qg * m;
+                    const FT *wp = qg < qL ? Wh + (int64_t)qg * n : Wb + (int64_t)qg * n;
+#pragma unroll
+                    for (int t = 0; t < CR; ++t) {
+                        const int r = lane + 64 * t;
+                        uu[g][t] = (ok && r < m) ? up[r] : czero<FT>();
+                        ww[g][t] = (ok && r < n) ? wp[r] : czero<FT>();
                     }
                 }
-                double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-                for (int t = 0; t < CR; ++t) {
-                    double2 v = cmulc(ucr[t], to_d2(u0[t]));
-                    a[0] += v.x;
-                    a[1] += v.y;
-                    v = cmulc(wcr[t], to_d2(w0[t]));
-                    a[2] += v.x;
-                    a[3] += v.y;
-                    v = cmulc(ucr[t], to_d2(u1[t]));
-                    a[4] += v.x;
-                    a[5] += v.y;
-                    v = cmulc(wcr[t], to_d2(w1[t]));
-                    a[6] += v.x;
-                    a[7] += v.y;
+                for (int g = 0; g < QPI; ++g) {
+                    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+                    for (int t = 0; t < CR; ++t) {
+                        double2 v = cmulc(ucr[t], to_d2(uu[g][t]));
+                        a0 += v.x;
+                        a1 += v.y;
+                        v = cmulc(wcr[t], to_d2(ww[g][t]));
+                        a2 += v.x;
+                        a3 += v.y;
+                    }
+                    a0 = wave_sum(a0);
+                    a1 = wave_sum(a1);
+                    a2 = wave_sum(a2);
+                    a3 = wave_sum(a3);
+                    if (q0 + g * NW < q) cr += a0 * a2 - a1 * a3;
                 }
-#pragma unroll
-                for (int t = 0; t < 4 * QPI; ++t) a[t] = wave_sum(a[t]);
-                cr += a[0] * a[2] - a[1] * a[3];
-                if (two) cr += a[4] * a[6] - a[5] * a[7];
             }
         } else
         for (int qq = wave; qq < q; qq += NW) {

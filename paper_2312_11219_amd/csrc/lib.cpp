@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -23,7 +24,7 @@ struct gaca_context {
     int n_cu = 256;           // compute units of the device
     hipStream_t stream = nullptr;
     uint64_t limit = 0;       // 0: none
-    uint64_t in_use = 0;
+    std::atomic<uint64_t> in_use{0};   // builds of different problems may run in parallel threads
 };
 
 namespace {

@@ -249,3 +249,20 @@ def test_compress_tensor_zero_and_dense():
     assert rel_fro(h.reconstruct_block(0), T) < 1e-12
     o = aca3d(T, 0.0, 0.0)
     assert [c["k"] for c in h.export_block(0)["crosses"]] == [c.k for c in o.crosses]
+
+
+def test_concurrent_builds_match_sequential():
+    """Two problems built from two host threads at once give bitwise the same operators as
+    the same builds one after the other."""
+    from concurrent.futures import ThreadPoolExecutor
+    _, p1, _ = gpu_problem("cube768")
+    _, p2, _ = gpu_problem("cube768")
+    seq = [p1.build("slp"), p2.build("dlp")]
+    with ThreadPoolExecutor(2) as ex:
+        par = list(ex.map(lambda a: a[0].build(a[1]), [(p1, "slp"), (p2, "dlp")]))
+    far, _ = p1.blocks()
+    for hs, hp in zip(seq, par):
+        for b in range(0, far.shape[0], 7):
+            es, ep = hs.export_block(b), hp.export_block(b)
+            assert es["rank"] == ep["rank"]
+            np.testing.assert_array_equal(hs.reconstruct_block(b), hp.reconstruct_block(b))
