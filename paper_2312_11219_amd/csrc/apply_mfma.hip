@@ -134,48 +134,51 @@ __device__ __forceinline__ int find_le(const int64_t *key, int n, int64_t v) {
 }
 
 // ---------------------------------------------------------------------------------------
-// T_b = F_b X_b: tile (block b, row tile mt of the crosses, column tile nt of (j, c)).
+// T = F X for one column cluster: tile (group, row tile mt of the stacked crosses, column
+// tile nt of (j, c)); the tiles of one column tile are consecutive, so the X slab they share
+// stays in L2.
 template <class FacT>
 __global__ void __launch_bounds__(256)
     apply_far_t_kernel(ApplyDev a, MfmaApplyDev d, const float2 *X, float2 *T) {
     constexpr int TN = 256;
     __shared__ float2 As[16 * 32];
     __shared__ float2 Bs[16 * TN];
-    __shared__ int sh_w;
-    if (threadIdx.x == 0) sh_w = find_le(d.t_tile0, d.nt_items, (int64_t)blockIdx.x);
+    __shared__ int sh_g;
+    __shared__ int64_t fo[32], to[32];
+    if (threadIdx.x == 0) sh_g = find_le(d.t_tile0, d.nt_groups, (int64_t)blockIdx.x);
     __syncthreads();
-    const MfmaTItem it = d.t_items[sh_w];
-    const int b = it.b;
-    const int64_t tile = blockIdx.x - d.t_tile0[sh_w];
-    const int m_tiles = it.m_tiles;
-    const int mt = (int)(tile % m_tiles), nt = (int)(tile / m_tiles);
-    const int rank = a.meta[b].rank, n = a.far4[4 * b + 3], c0b = a.far4[4 * b + 2];
-    const int L = a.L, nrc = d.nrc;
+    const MfmaTGroup G = d.t_groups[sh_g];
+    const int64_t tile = blockIdx.x - d.t_tile0[sh_g];
+    const int mt = (int)(tile % G.m_tiles), nt = (int)(tile / G.m_tiles);
+    const int L = a.L, nrc = d.nrc, n = G.n, c0b = G.c0;
     const int64_t ncols = (int64_t)n * nrc;
-    const double2 *F = a.fib_arena + a.fib_off[b];
-    const int r0 = 32 * mt;
+    const int r0 = 32 * mt, nrow = min(32, G.rows - r0);
     const int64_t n0 = (int64_t)nt * TN;
+    if (threadIdx.x < nrow) {
+        const MfmaTRow rw = d.t_rows[G.row0 + r0 + threadIdx.x];
+        fo[threadIdx.x] = rw.f_off;
+        to[threadIdx.x] = rw.t_off;
+    }
+    __syncthreads();
     CTile<TN> acc, seg;
     acc.zero();
     seg.zero();
     for (int k0 = 0; k0 < L; k0 += 16) {
         if (k0 > 0 && k0 % kFold == 0) acc.fold(seg);
         __syncthreads();
-        stage_a<true>(As, k0, rank - r0, L, [&](int r, int k) {
-            return to_f2(F[(int64_t)(r0 + r) * L + k]);
-        });
+        stage_a<true>(As, k0, nrow, L, [&](int r, int k) { return to_f2(a.fib_arena[fo[r] + k]); });
         stage_b<TN>(Bs, k0, L, (int)min<int64_t>(TN, ncols - n0), [&](int k, int c) {
             const int64_t nn = n0 + c;
-            const int j = (int)(nn / nrc), cc = (int)(nn - (int64_t)j * nrc);
-            return X[((int64_t)k * a.M + a.perm[c0b + j]) * d.ldx + d.c0 + cc];
+            const int j = (int)(nn >> d.lg_nrc), cc = (int)(nn & (nrc - 1));
+            return cc < d.ncur ? X[((int64_t)k * a.M + a.perm[c0b + j]) * d.ldx + d.c0 + cc]
+                               : make_float2(0.f, 0.f);
         });
         __syncthreads();
         seg.step(As, Bs);
     }
     acc.fold(seg);
-    float2 *Tb = T + it.t_off;
     acc.visit([&](int r, int c, float2 v) {
-        if (r0 + r < rank && n0 + c < ncols) Tb[(int64_t)(r0 + r) * ncols + n0 + c] = v;
+        if (r < nrow && n0 + c < ncols) T[to[r] + n0 + c] = v;
     });
 }
 
@@ -225,6 +228,7 @@ __global__ void __launch_bounds__(256)
     __shared__ float2 As[16 * 32];
     __shared__ float2 Bs[16 * TN];
     __shared__ int64_t qaddr[kMfmaMaxSumRho];
+    __shared__ int64_t xrow[kMfmaMaxNearCols];
     const int leaf = blockIdx.x;
     const int lr0 = a.leaf_r0[leaf] + 32 * blockIdx.z, lm = min(32, a.leaf_m[leaf] - 32 * (int)blockIdx.z);
     if (lm <= 0) return;
@@ -242,17 +246,26 @@ __global__ void __launch_bounds__(256)
         const int ro = lr0 - nb.r0, n = nb.n;
         const int K = L * n;
         const NearT *A0 = nearv + nb.off + (int64_t)ro * K;
-        for (int k0 = 0; k0 < K; k0 += 16) {
-            if (k0 > 0 && k0 % kFold == 0) acc.fold(seg);
-            __syncthreads();
-            stage_a<true>(As, k0, lm, K, [&](int r, int kk) { return to_f2(A0[(int64_t)r * K + kk]); });
-            stage_b<TN>(Bs, k0, K, nrc - c0, [&](int kk, int c) {
-                const int k = kk / n, j = kk - k * n;
-                return X[((int64_t)k * M + a.perm[nb.c0 + j]) * d.ldx + d.c0 + c0 + c];
-            });
-            __syncthreads();
-            seg.step(As, Bs);
-        }
+        // K in slices of 16 columns j at one frequency k: no index division per element
+        __syncthreads();
+        for (int j = threadIdx.x; j < n; j += 256) xrow[j] = a.perm[nb.c0 + j] * (int64_t)d.ldx;
+        int steps = 0;
+        for (int k = 0; k < L; ++k)
+            for (int j0 = 0; j0 < n; j0 += 16) {
+                if (steps > 0 && steps % (kFold / 16) == 0) acc.fold(seg);
+                ++steps;
+                __syncthreads();
+                const int kb = k * n + j0;
+                stage_a<true>(As, 0, lm, min(16, n - j0), [&](int r, int t) {
+                    return to_f2(A0[(int64_t)r * K + kb + t]);
+                });
+                const float2 *Xk = X + (int64_t)k * M * d.ldx + d.c0 + c0;
+                stage_b<TN>(Bs, 0, min(16, n - j0), d.ncur - c0, [&](int t, int c) {
+                    return Xk[xrow[j0 + t] + c];
+                });
+                __syncthreads();
+                seg.step(As, Bs);
+            }
         acc.fold(seg);
     }
     for (int e = a.leaf_far_ptr[leaf]; e < a.leaf_far_ptr[leaf + 1]; ++e) {
@@ -282,7 +295,7 @@ __global__ void __launch_bounds__(256)
         acc.fold(seg);
     }
     acc.visit([&](int r, int c, float2 v) {
-        if (r < lm && c0 + c < nrc) Y[a.perm[lr0 + r] * d.ldy + d.c0 + c0 + c] = v;
+        if (r < lm && c0 + c < d.ncur) Y[a.perm[lr0 + r] * d.ldy + d.c0 + c0 + c] = v;
     });
 }
 

@@ -131,21 +131,32 @@ struct ApplyDev {
 };
 // Matrix-core apply (SUM mode, complex64 right-hand sides), csrc/apply_mfma.hip.
 constexpr int kMfmaMaxSumRho = 4096;   // sum of face ranks of one far block
-struct MfmaTItem {        // T_b = F_b X_b for one far block: its tiles start at t_tile0[item]
-    int32_t b, m_tiles;   // block, row tiles of its crosses (32 rows each)
-    int64_t t_off;        // T_b offset (elements, [rank][n][nrc])
+constexpr int kMfmaMaxNearCols = 1024; // columns of one near block
+// T = F X for the far blocks that share one column cluster tau: their fibre rows are
+// stacked (rows of 32 per tile), so one slab X[:, tau, chunk] serves all of them.
+struct MfmaTGroup {
+    int32_t c0, n;        // column cluster (tree order)
+    int32_t rows, m_tiles;
+    int64_t row0;         // first row in the row table
+};
+struct MfmaTRow {         // one cross of one block
+    int64_t f_off;        // its fibre (double2 offset in the fibre arena)
+    int64_t t_off;        // its T row ([n][nrc], element offset)
 };
 struct MfmaZItem {        // Z_{b,l} rows [q0, q0 + 32)
     int32_t b, l, q0, pad;
     int64_t t_off, z_off; // T_b and Z_{b,l} offsets (elements)
 };
 struct MfmaApplyDev {
-    int32_t nrc;          // right-hand sides of this chunk
+    int32_t nrc;          // columns of this chunk in T and Z (a power of two)
+    int32_t lg_nrc;       // log2(nrc)
+    int32_t ncur;         // right-hand sides of this chunk (<= nrc; the rest are zero)
     int32_t ldx, ldy;     // leading dimensions (nrhs) of X [L][M][nrhs] and Y [M][nrhs]
     int32_t c0;           // first right-hand side of the chunk
-    const MfmaTItem *t_items;
-    const int64_t *t_tile0;
-    int32_t nt_items;
+    const MfmaTGroup *t_groups;
+    const int64_t *t_tile0;   // first tile of each group
+    int32_t nt_groups;
+    const MfmaTRow *t_rows;
     const MfmaZItem *z_items;
     const int64_t *z_off; // [nfar] Z_b offsets ([sum_rho][nrc])
     const int32_t *sum_rho;

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <functional>
 #include <numeric>
@@ -372,7 +373,7 @@ struct gaca_hmatrix {
     int32_t ws_nrhs = -1, ws_mode = -1, ws_dtype = -1;
     DevBuf d_xp, d_yp, d_z, d_t, d_toff, d_zoff, d_yb, d_yoff;
     DevBuf d_leaf_r0, d_leaf_m, d_lfp, d_lfi, d_lnp, d_lni;
-    DevBuf d_mz, d_mt, d_mtitems, d_mttile0, d_mzitems, d_mzoff, d_msumrho;   // matrix-core apply
+    DevBuf d_mz, d_mt, d_mtitems, d_mttile0, d_mtrows, d_mzitems, d_mzoff, d_msumrho;   // matrix-core apply
     bool leaf_ready = false;
 };
 
@@ -1537,10 +1538,13 @@ static void alloc_apply_workspace(gaca_hmatrix *h, gaca_apply_mode mode, int32_t
         }
 }
 
-// The matrix-core apply stages the U rows of one far block by their sum of face ranks.
+// The matrix-core apply stages the U rows of one far block by their sum of face ranks and
+// the X rows of one near block by its columns.
 static bool mfma_supported(const gaca_hmatrix *h) {
     for (int64_t b = 0; b < h->nfar; ++b)
         if (h->meta[b].sum_rho > kMfmaMaxSumRho) return false;
+    for (const auto &nb : h->p->nblocks)
+        if (nb.n > kMfmaMaxNearCols) return false;
     return true;
 }
 
@@ -1557,14 +1561,16 @@ static void apply_mfma(gaca_hmatrix *h, const ApplyDev &a, int32_t nrhs, const f
         sum_rho[b] = h->meta[b].sum_rho;
         rho_tot += sum_rho[b];
     }
-    // right-hand sides per chunk: up to 64, with Z (sum of face ranks x chunk) within a
-    // quarter of the free memory
-    int nrc_max = std::min(nrhs, 64);
+    // right-hand sides per chunk: a power of two up to 64 (the kernels split column indices
+    // with shifts; columns past the last right-hand side are zero), halved while Z (sum of
+    // face ranks x chunk) would exceed 40 % of the free memory
+    int nrc_max = 64;
+    while (nrc_max > 1 && nrc_max / 2 >= nrhs) nrc_max /= 2;
     {
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && rho_tot > 0) {
-            const double fit = 0.25 * (double)free_b / ((double)rho_tot * sizeof(float2));
-            nrc_max = std::max(1, std::min(nrc_max, (int)std::min(fit, 64.0)));
+            while (nrc_max > 1 && (double)rho_tot * nrc_max * sizeof(float2) > 0.4 * (double)free_b)
+                nrc_max /= 2;
         } else {
             (void)hipGetLastError();
         }
@@ -1603,10 +1609,31 @@ static void apply_mfma(gaca_hmatrix *h, const ApplyDev &a, int32_t nrhs, const f
     };
     GACA_HIP_CHECK(hipEventRecord(ev0, st));
     const size_t t_budget = (size_t)1 << 31;   // bytes of T per far batch
+    // far blocks grouped by column cluster (tree-order start and size), in first-seen order
+    std::vector<std::vector<int64_t>> groups;
+    {
+        std::map<std::pair<int64_t, int64_t>, size_t> gid;
+        for (int64_t b = 0; b < nfar; ++b) {
+            const auto key = std::make_pair(p->part.far[b][2], p->part.far[b][3]);
+            auto it = gid.find(key);
+            if (it == gid.end()) {
+                gid.emplace(key, groups.size());
+                groups.push_back({b});
+            } else {
+                groups[it->second].push_back(b);
+            }
+        }
+    }
     for (int c0 = 0; c0 < nrhs; c0 += nrc_max) {
-        const int nrc = std::min(nrc_max, nrhs - c0);
+        const int ncur = std::min(nrc_max, nrhs - c0);
+        int nrc = 1;
+        while (nrc < ncur) nrc *= 2;
+        int lg = 0;
+        while ((1 << lg) < nrc) ++lg;
         MfmaApplyDev d{};
         d.nrc = nrc;
+        d.lg_nrc = lg;
+        d.ncur = ncur;
         d.ldx = nrhs;
         d.ldy = nrhs;
         d.c0 = c0;
@@ -1619,48 +1646,62 @@ static void apply_mfma(gaca_hmatrix *h, const ApplyDev &a, int32_t nrhs, const f
         h->d_mzoff.upload(ctx, zoff);
         d.z_off = h->d_mzoff.as<int64_t>();
         d.sum_rho = h->d_msumrho.as<int32_t>();
-        for (int64_t s0 = 0; s0 < nfar;) {
-            std::vector<MfmaTItem> ti;
+        for (size_t g0 = 0; g0 < groups.size();) {
+            std::vector<MfmaTGroup> tg;
             std::vector<int64_t> tt0;
+            std::vector<MfmaTRow> trows;
             std::vector<MfmaZItem> zi;
-            int64_t tacc = 0, ntiles = 0, e = s0;
-            for (; e < nfar; ++e) {
-                const FarMeta &mt = h->meta[e];
-                const int n = (int)p->part.far[e][3];
-                const int64_t tb = (int64_t)mt.rank * n * nrc;
-                if (e > s0 && (size_t)(tacc + tb) * sizeof(float2) > t_budget) break;
-                if (mt.rank == 0) continue;
-                MfmaTItem it{};
-                it.b = (int32_t)e;
-                it.m_tiles = (mt.rank + 31) / 32;
-                it.t_off = tacc;
+            int64_t tacc = 0, ntiles = 0;
+            size_t g1 = g0;
+            for (; g1 < groups.size(); ++g1) {
+                const auto &grp = groups[g1];
+                const int n = (int)p->part.far[grp[0]][3];
+                int64_t rows = 0;
+                for (int64_t e : grp) rows += h->meta[e].rank;
+                const int64_t tg_bytes = rows * n * nrc * (int64_t)sizeof(float2);
+                if (g1 > g0 && (size_t)(tacc * sizeof(float2) + tg_bytes) > t_budget) break;
+                if (rows == 0) continue;
+                MfmaTGroup G{};
+                G.c0 = (int32_t)p->part.far[grp[0]][2];
+                G.n = n;
+                G.rows = (int32_t)rows;
+                G.m_tiles = (int32_t)((rows + 31) / 32);
+                G.row0 = (int64_t)trows.size();
                 tt0.push_back(ntiles);
-                ti.push_back(it);
-                ntiles += (int64_t)it.m_tiles * (((int64_t)n * nrc + 255) / 256);
-                int64_t qoff = 0;
-                for (int l = 0; l < mt.rank; ++l) {
-                    const CrossMeta &cm = h->cmeta[e * h->rcap + l];
-                    for (int q0 = 0; q0 < cm.rho; q0 += 32) {
-                        MfmaZItem z{};
-                        z.b = (int32_t)e;
-                        z.l = l;
-                        z.q0 = q0;
-                        z.t_off = tacc;
-                        z.z_off = zoff[e] + qoff * nrc;
-                        zi.push_back(z);
+                tg.push_back(G);
+                ntiles += (int64_t)G.m_tiles * (((int64_t)n * nrc + 255) / 256);
+                for (int64_t e : grp) {
+                    const FarMeta &mt = h->meta[e];
+                    if (mt.rank == 0) continue;
+                    const int64_t t_b = tacc;
+                    int64_t qoff = 0;
+                    for (int l = 0; l < mt.rank; ++l) {
+                        trows.push_back(MfmaTRow{h->fib_off[e] + (int64_t)l * p->L, t_b + (int64_t)l * n * nrc});
+                        const CrossMeta &cm = h->cmeta[e * h->rcap + l];
+                        for (int q0 = 0; q0 < cm.rho; q0 += 32) {
+                            MfmaZItem z{};
+                            z.b = (int32_t)e;
+                            z.l = l;
+                            z.q0 = q0;
+                            z.t_off = t_b;
+                            z.z_off = zoff[e] + qoff * nrc;
+                            zi.push_back(z);
+                        }
+                        qoff += cm.rho;
                     }
-                    qoff += cm.rho;
+                    tacc += (int64_t)mt.rank * n * nrc;
                 }
-                tacc += tb;
             }
-            if (!ti.empty()) {
+            if (!tg.empty()) {
                 ensure(ctx, h->d_mt, (size_t)std::max<int64_t>(tacc, 1) * sizeof(float2));
-                h->d_mtitems.upload(ctx, ti);
+                h->d_mtitems.upload(ctx, tg);
                 h->d_mttile0.upload(ctx, tt0);
+                h->d_mtrows.upload(ctx, trows);
                 h->d_mzitems.upload(ctx, zi);
-                d.t_items = h->d_mtitems.as<MfmaTItem>();
+                d.t_groups = h->d_mtitems.as<MfmaTGroup>();
                 d.t_tile0 = h->d_mttile0.as<int64_t>();
-                d.nt_items = (int32_t)ti.size();
+                d.nt_groups = (int32_t)tg.size();
+                d.t_rows = h->d_mtrows.as<MfmaTRow>();
                 d.z_items = h->d_mzitems.as<MfmaZItem>();
                 GACA_HIP_CHECK(hipEventRecord(ep[0], st));
                 launch_apply_far_t(a, d, ntiles, X, h->d_mt.as<float2>(), st);
@@ -1673,7 +1714,7 @@ static void apply_mfma(gaca_hmatrix *h, const ApplyDev &a, int32_t nrhs, const f
                 ms_part[0] += part_ms(0, 1);
                 ms_part[1] += part_ms(1, 2);
             }
-            s0 = e;
+            g0 = g1;
         }
         GACA_HIP_CHECK(hipEventRecord(ep[2], st));
         launch_apply_leaf_mfma(a, d, row_tiles, X, h->d_mz.as<float2>(), Y, st);
