@@ -133,6 +133,31 @@ struct Red {
         for (int w = 1; w < NW; ++w) t = fmax(t, buf[w]);
         return t;
     }
+    // sums of a, b, c and max of d in one round (buf: 4 NW doubles)
+    __device__ void sum3max(double &a, double &b, double &c, double &d) {
+        a = wave_sum(a);
+        b = wave_sum(b);
+        c = wave_sum(c);
+        d = wave_max(d);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) {
+            double *o = buf + 4 * (threadIdx.x >> 6);
+            o[0] = a;
+            o[1] = b;
+            o[2] = c;
+            o[3] = d;
+        }
+        __syncthreads();
+        a = b = c = 0.0;
+        d = buf[3];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            a += buf[4 * w];
+            b += buf[4 * w + 1];
+            c += buf[4 * w + 2];
+            d = fmax(d, buf[4 * w + 3]);
+        }
+    }
     // max of a and sum of b in one round
     __device__ void maxsum(double &a, double &b) {
         a = wave_max(a);
@@ -175,6 +200,12 @@ struct Red<64> {
         c = wave_sum(c);
     }
     __device__ double max(double v) { return wave_max(v); }
+    __device__ void sum3max(double &a, double &b, double &c, double &d) {
+        a = wave_sum(a);
+        b = wave_sum(b);
+        c = wave_sum(c);
+        d = wave_max(d);
+    }
     __device__ void maxsum(double &a, double &b) {
         a = wave_max(a);
         b = wave_sum(b);

@@ -337,6 +337,8 @@ __global__ void __launch_bounds__(NT)
     __shared__ FT cbuf[kCoefLds]; // coefficients u_q'[i] / w_q'[jp] of the HBM part of the history
     __shared__ unsigned char used_row[kMaxRowsLds];
     __shared__ double redbuf[4 * NW + 4];
+    __shared__ double2 xbuf[NT];  // current w (face type), then split partials of v
+    __shared__ double2 bvec[NT];  // conj <w_q, w_q'> for q' < q
     Red<NT> red{redbuf};
     const double tie2 = (1.0 - P.tie) * (1.0 - P.tie);
     const int qL = min(B.rho_max, (int)(HB / ((int64_t)(m + n) * (int64_t)sizeof(FT))));
@@ -388,6 +390,160 @@ __global__ void __launch_bounds__(NT)
     int q = 0, i = 0, nused = 0;
     double s2 = 0.0;
     const int splitw = max(1, NT / n), splitu = max(1, NT / m);
+    if (m <= NT && n <= NT) {
+        // One row entry and one column entry per thread, kept in registers.  The cross terms
+        // sum_{q'<q} Re(<u_q, u_q'> <w_q, w_q'>) of the stopping norm are taken as
+        // Re <u_q, v> with v = sum_{q'<q} conj(b_q') u_q', b_q' = <w_q, w_q'>: b is one
+        // grouped pass over the w history, v is summed in the column pass, which reads the
+        // u history anyway.
+        FT *xw = reinterpret_cast<FT *>(xbuf);   // w_q (before the column pass)
+        double2 *xv = xbuf;                      // split partials of v (column pass)
+        while (true) {
+            FT *Wq = Wb + (int64_t)q * n;
+            FT *Uq = Ub + (int64_t)q * m;
+            const FT rv = tid < n ? R[(int64_t)i * n + tid] : czero<FT>();
+            if (q > qL) stage_coef(Ub, m, i, q);
+            if (tid < splitw * n) {
+                const int s = tid / n, j = tid - s * n;
+                const int q0 = (int)((int64_t)q * s / splitw), q1 = (int)((int64_t)q * (s + 1) / splitw);
+                part[tid] = hdot(Uh, Ub, m, i, Wh, Wb, n, j, q0, q1);
+            }
+            __syncthreads();
+            FT v = rv;
+            double mx = 0.0;
+            if (tid < n) {
+                for (int t = 0; t < splitw; ++t) v = csub(v, part[t * n + tid]);
+                part[tid] = v;   // the only reader of part[tid] above is this thread
+                mx = cabs2(v);
+            }
+            mx = red.max(mx);
+            if (tid == 0) used_row[i] = 1;
+            ++nused;
+            if (sqrt(mx) <= zero_tol) {
+                __syncthreads();
+                const int cand = first_unused<NT>(used_row, m, red);
+                if (cand >= m) break;
+                i = cand;
+                continue;
+            }
+            const double thr = tie2 * mx;
+            const int jp = min(red.imin(tid < n && cabs2(v) >= thr ? tid : n), n - 1);
+            const FT piv = part[jp];
+            const FT cv = tid < m ? R[(int64_t)tid * n + jp] : czero<FT>();
+            double nw2 = 0.0;
+            if (tid < n) {
+                const FT w = cdiv(v, piv);
+                Wq[tid] = w;
+                if (q < qL) Wh[q * n + tid] = w;
+                xw[tid] = w;
+                nw2 = cabs2(w);
+            }
+            __syncthreads();
+            if (q > 0) {
+                // b_q' = <w_q, w_q'>: G lanes per q' (G a power of two, G q <= NT)
+                int lg = 6;
+                while (lg > 0 && (q << lg) > NT) --lg;
+                const int G = 1 << lg, qq = tid >> lg, g = tid & (G - 1);
+                double2 a0 = make_double2(0.0, 0.0), a1 = a0;
+                if (qq < q) {
+                    if (qq < qL) {
+                        const FT *wp = Wh + qq * n;
+                        for (int j = g; j < n; j += G) a0 = cfma(to_d2(xw[j]), conj_d2(to_d2(wp[j])), a0);
+                    } else {
+                        const FT *wp = Wb + (int64_t)qq * n;
+                        constexpr int NBW = 8;
+                        int j = g;
+                        for (; j + (NBW - 1) * G < n; j += NBW * G) {
+                            FT wv[NBW];
+#pragma unroll
+                            for (int t = 0; t < NBW; ++t) wv[t] = wp[j + t * G];
+#pragma unroll
+                            for (int t = 0; t < NBW; t += 2) {
+                                a0 = cfma(to_d2(xw[j + t * G]), conj_d2(to_d2(wv[t])), a0);
+                                a1 = cfma(to_d2(xw[j + (t + 1) * G]), conj_d2(to_d2(wv[t + 1])), a1);
+                            }
+                        }
+                        for (; j < n; j += G) a0 = cfma(to_d2(xw[j]), conj_d2(to_d2(wp[j])), a0);
+                    }
+                }
+                a0 = cadd(a0, a1);
+                for (int o = G >> 1; o > 0; o >>= 1) {
+                    a0.x += __shfl_xor(a0.x, o, 64);
+                    a0.y += __shfl_xor(a0.y, o, 64);
+                }
+                if (g == 0 && qq < q) bvec[qq] = conj_d2(a0);
+                __syncthreads();
+            }
+            if (q > qL) stage_coef(Wb, n, jp, q);
+            if (tid < splitu * m) {
+                // column jp of R - sum_{q'<q} w_q'[jp] u_q', and v, over this thread's q'
+                const int s = tid / m, r = tid - s * m;
+                const int q0 = (int)((int64_t)q * s / splitu), q1 = (int)((int64_t)q * (s + 1) / splitu);
+                FT c0 = czero<FT>(), c1 = czero<FT>();
+                double2 v0 = make_double2(0.0, 0.0), v1 = v0;
+                const int qm = min(q1, qL);
+                int qq = q0;
+                for (; qq < qm; ++qq) {
+                    const FT uu = Uh[qq * m + r];
+                    c0 = cfma(Wh[qq * n + jp], uu, c0);
+                    v0 = cfma(bvec[qq], to_d2(uu), v0);
+                }
+                qq = max(q0, qL);
+                const int qc = min(q1, qL + kCoefLds);
+                constexpr int NB = NT >= 1024 ? 4 : 16;
+                for (; qq + NB <= qc; qq += NB) {
+                    FT uv[NB];
+#pragma unroll
+                    for (int t = 0; t < NB; ++t) uv[t] = Ub[(int64_t)(qq + t) * m + r];
+#pragma unroll
+                    for (int t = 0; t < NB; t += 2) {
+                        c0 = cfma(cbuf[qq + t - qL], uv[t], c0);
+                        c1 = cfma(cbuf[qq + t + 1 - qL], uv[t + 1], c1);
+                        v0 = cfma(bvec[qq + t], to_d2(uv[t]), v0);
+                        v1 = cfma(bvec[qq + t + 1], to_d2(uv[t + 1]), v1);
+                    }
+                }
+                for (; qq < qc; ++qq) {
+                    const FT uu = Ub[(int64_t)qq * m + r];
+                    c0 = cfma(cbuf[qq - qL], uu, c0);
+                    v0 = cfma(bvec[qq], to_d2(uu), v0);
+                }
+                for (qq = max(q0, qc); qq < q1; ++qq) {
+                    const FT uu = Ub[(int64_t)qq * m + r];
+                    c0 = cfma(Wb[(int64_t)qq * n + jp], uu, c0);
+                    v0 = cfma(bvec[qq], to_d2(uu), v0);
+                }
+                part[tid] = cadd(c0, c1);
+                xv[tid] = cadd(v0, v1);
+            }
+            __syncthreads();
+            double nu2 = 0.0, cr = 0.0, mxu = -1.0;
+            FT u = cv;
+            if (tid < m) {
+                double2 vs = make_double2(0.0, 0.0);
+                for (int t = 0; t < splitu; ++t) {
+                    u = csub(u, part[t * m + tid]);
+                    vs = cadd(vs, xv[t * m + tid]);
+                }
+                Uq[tid] = u;
+                if (q < qL) Uh[q * m + tid] = u;
+                nu2 = cabs2(u);
+                const double2 ud = to_d2(u);
+                cr = ud.x * vs.x + ud.y * vs.y;
+                if (!used_row[tid]) mxu = nu2;
+            }
+            red.sum3max(nu2, nw2, cr, mxu);
+            s2 = s2 + 2.0 * cr + nu2 * nw2;
+            ++q;
+            if (sqrt(nu2 * nw2) <= P.eps_aca * sqrt(ref2 + s2) || nused >= m || q >= B.rho_max)
+                break;
+            // next row: tie-argmax of |u_q| over the unused rows
+            const double thu = tie2 * mxu;
+            int c = red.imin(tid < m && !used_row[tid] && cabs2(u) >= thu ? tid : m);
+            if (c >= m) c = first_unused<NT>(used_row, m, red);
+            i = min(c, m - 1);
+        }
+    } else
     while (true) {
         FT *Wq = Wb + (int64_t)q * n;
         FT *Uq = Ub + (int64_t)q * m;
@@ -965,7 +1121,7 @@ static void aca_dispatch(int kind, int threads, const AcaParams &P, const FarBat
         // one face per CU: 1024 or 512 threads with ~110 KB of LDS history; 256 threads with
         // 32 KB, several faces per CU
         if (threads >= 1024)
-            far_aca_large_kernel<1024, MX, 98304><<<nact, 1024, 0, st>>>(P, bd, act);
+            far_aca_large_kernel<1024, MX, 90112><<<nact, 1024, 0, st>>>(P, bd, act);
         else if (threads >= 512)
             far_aca_large_kernel<512, MX, 106496><<<nact, 512, 0, st>>>(P, bd, act);
         else
