@@ -1050,18 +1050,33 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------------------
-// Factors of accepted crosses -> arena (U: rho x m, then W: rho x n).
+// Factors of accepted crosses -> arena (U: rho x m, then W: rho x n), kFarCopyChunk elements
+// per workgroup with all loads of a thread issued before its stores.
 template <class FT>
 __global__ void __launch_bounds__(256) far_copy_kernel(FarBatchDev bd, const FarCopy *cp,
                                                        FT *arena, int64_t *cross_off) {
+    constexpr int PER = kFarCopyChunk / 256;
     const FarCopy C = cp[blockIdx.x];
     const FarBlockDev B = bd.blk[C.b];
     const FT *Ub = reinterpret_cast<const FT *>(bd.uw) + B.uw_off;
     const FT *Wb = Ub + (int64_t)B.rho_max * B.m;
-    const int64_t nu = (int64_t)C.rho * B.m, nw = (int64_t)C.rho * B.n;
-    for (int64_t t = threadIdx.x; t < nu; t += 256) arena[C.off + t] = Ub[t];
-    for (int64_t t = threadIdx.x; t < nw; t += 256) arena[C.off + nu + t] = Wb[t];
-    if (threadIdx.x == 0) cross_off[(int64_t)B.out_idx * bd.rcap + C.p] = C.off;
+    const int64_t nu = (int64_t)C.rho * B.m, tot = nu + (int64_t)C.rho * B.n;
+    const int64_t e0 = (int64_t)C.chunk * kFarCopyChunk + threadIdx.x;
+    FT v[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int64_t e = e0 + 256 * t;
+        FT x = czero<FT>();
+        if (e < nu) x = Ub[e];
+        else if (e < tot) x = Wb[e - nu];
+        v[t] = x;
+    }
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int64_t e = e0 + 256 * t;
+        if (e < tot) arena[C.off + e] = v[t];
+    }
+    if (C.chunk == 0 && threadIdx.x == 0) cross_off[(int64_t)B.out_idx * bd.rcap + C.p] = C.off;
 }
 
 // Fibres of finished blocks -> fibre arena (rank x L, contiguous per block).

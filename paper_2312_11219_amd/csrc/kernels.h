@@ -52,10 +52,11 @@ struct FarActive {
     int64_t tile0;      // first expand tile (kind 3) or the face's partial row (kinds 0-2)
 };
 
-struct FarCopy {        // factors of an accepted cross -> arena
-    int32_t b, p, rho, pad;
+struct FarCopy {        // one chunk of the factors of an accepted cross -> arena
+    int32_t b, p, rho, chunk;
     int64_t off;
 };
+constexpr int kFarCopyChunk = 4096;   // elements per copy workgroup
 struct FarGather {      // fibres of a finished block -> fibre arena
     int32_t b, rank;
     int64_t off;

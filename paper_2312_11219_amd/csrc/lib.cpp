@@ -865,7 +865,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
     hipStream_t s0 = p->far_streams[0];
     // the aca phase of kind k runs on ks[k] (kind 3, the large faces, on the main far stream)
     const hipStream_t ks[4] = {p->far_streams[3], p->far_streams[2], p->far_streams[1], s0};
-    enum { EV_BEGIN, EV_END, EV_F0, EV_F1, EV_K0, EV_K1, EV_K2, EV_K3, EV_J, EV_X, EV_T, EV_N };
+    enum { EV_BEGIN, EV_END, EV_F0, EV_F1, EV_K0, EV_K1, EV_K2, EV_K3, EV_J, EV_X, EV_T, EV_C, EV_N };
     hipEvent_t ev[EV_N];
     for (auto &e : ev) GACA_HIP_CHECK(hipEventCreate(&e));
     struct EvGuard {
@@ -973,16 +973,32 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             bd.L = L;
             return bd;
         };
-        auto flush_copies = [&]() {
-            if (pending.empty()) return;
-            std::memcpy(W.h_copies.ptr, pending.data(), pending.size() * sizeof(FarCopy));
-            GACA_HIP_CHECK(hipMemcpyAsync(W.copies.ptr, W.h_copies.ptr, pending.size() * sizeof(FarCopy),
-                                          hipMemcpyHostToDevice, s0));
-            launch_far_copy(batch_dev(), W.copies.as<FarCopy>(), (int)pending.size(), h->d_arena.ptr,
-                            h->d_cross_off.as<int64_t>(), s0);
+        // factors of the crosses accepted in the last iteration -> arena, one workgroup per
+        // kFarCopyChunk elements; returns whether a copy was launched on stream cs
+        std::vector<FarCopy> chunks;
+        auto flush_copies = [&](hipStream_t cs) {
+            if (pending.empty()) return false;
+            chunks.clear();
+            for (const FarCopy &c : pending) {
+                const int64_t tot = (int64_t)c.rho * (bdesc[c.b].m + bdesc[c.b].n);
+                const int64_t nch = std::max<int64_t>(1, (tot + kFarCopyChunk - 1) / kFarCopyChunk);
+                for (int64_t k = 0; k < nch; ++k) {
+                    FarCopy x = c;
+                    x.chunk = (int32_t)k;
+                    chunks.push_back(x);
+                }
+            }
+            ensure(ctx, W.copies, chunks.size() * sizeof(FarCopy));
+            W.h_copies.ensure(chunks.size() * sizeof(FarCopy));
+            std::memcpy(W.h_copies.ptr, chunks.data(), chunks.size() * sizeof(FarCopy));
+            GACA_HIP_CHECK(hipMemcpyAsync(W.copies.ptr, W.h_copies.ptr, chunks.size() * sizeof(FarCopy),
+                                          hipMemcpyHostToDevice, cs));
+            launch_far_copy(batch_dev(), W.copies.as<FarCopy>(), (int)chunks.size(), h->d_arena.ptr,
+                            h->d_cross_off.as<int64_t>(), cs);
             GACA_HIP_CHECK(hipGetLastError());
             ++n_launch;
             pending.clear();
+            return true;
         };
 
         while (!active.empty()) {
@@ -1046,7 +1062,10 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             ensure(ctx, W.part, (size_t)std::max<int64_t>(nparts, 1) * PS * sizeof(double));
             GACA_HIP_CHECK(hipMemcpyAsync(W.act.ptr, W.h_act.ptr, nact * sizeof(FarActive),
                                           hipMemcpyHostToDevice, s0));
-            flush_copies();
+            // the copy reads the face factors that this iteration's ACA overwrites: it runs
+            // beside the map and face phases, and every ACA launch waits for it
+            const bool copied = flush_copies(ks[0]);
+            if (copied) GACA_HIP_CHECK(hipEventRecord(ev[EV_C], ks[0]));
             const FarBatchDev bd = batch_dev();
             const FarActive *dact = W.act.as<FarActive>();
             const int nlarge = cnt[3];
@@ -1057,6 +1076,8 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             launch_far_face(h->kernel, p->g, p->f, bd, dact, nchunk, s0);
             GACA_HIP_CHECK(hipEventRecord(ev[EV_F1], s0));
             for (int k = 0; k < 3; ++k) GACA_HIP_CHECK(hipStreamWaitEvent(ks[k], ev[EV_F1], 0));
+            if (copied)
+                for (int k = 1; k < 4; ++k) GACA_HIP_CHECK(hipStreamWaitEvent(ks[k], ev[EV_C], 0));
             // large faces: 512 threads (measured best on the 3072-triangle cube, where the
             // longest face bounds the phase, and on the 20480-triangle sphere)
             int tl = p->opt.threads_large;
@@ -1152,7 +1173,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             active.swap(next);
             ++iter;
         }
-        flush_copies();
+        flush_copies(s0);
         // fibres of the batch -> fibre arena, contiguous per block
         std::vector<FarGather> gth;
         const size_t fib_before = fib_used;
