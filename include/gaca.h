@@ -178,6 +178,10 @@ gaca_status gaca_quadrature_rule(int kind, int n, double *nodes, double *weights
  * Synchronous: returns when the device work is done.  GACA_ERR_NOT_CONVERGED if a rank
  * cap was hit (the handle is still returned and usable). */
 gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out);
+/* An H-matrix refers to its problem: destroy it before the problem.  Destroying it waits
+ * for the device to be idle; its factor and fibre arenas (when mapped in place and at most
+ * an eighth of the device memory) are kept by the problem and reused by its next build,
+ * and are freed with the problem. */
 gaca_status gaca_hmatrix_destroy(gaca_hmatrix *h);
 gaca_status gaca_hmatrix_stats(const gaca_hmatrix *h, gaca_stats *st);
 /* Frequency-usage histogram: hist[k] = number of far blocks whose crosses use s_k. */

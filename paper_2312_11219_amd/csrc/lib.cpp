@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <functional>
 #include <numeric>
 
@@ -30,6 +31,25 @@ struct gaca_context {
 
 namespace {
 
+// Host time spent in device-memory management calls (allocation, mapping, release), for
+// the verbose progress lines.
+static std::atomic<int64_t> g_mem_ns{0}, g_mem_calls{0};
+static std::atomic<int> g_mem_verbose{0};   // report memory calls slower than 10 ms
+struct MemTimer {
+    const char *what;
+    size_t size;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    explicit MemTimer(const char *w = "", size_t sz = 0) : what(w), size(sz) {}
+    ~MemTimer() {
+        const int64_t ns =
+            std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now() - t0).count();
+        g_mem_ns += ns;
+        ++g_mem_calls;
+        if (g_mem_verbose.load() && ns > 10000000)
+            std::fprintf(stderr, "gaca memory: %s of %.1f MiB took %.1f ms\n", what, size / 1048576.0, ns / 1e6);
+    }
+};
+
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
@@ -40,6 +60,7 @@ struct DevBuf {
     ~DevBuf() { release(); }
     void release() {
         if (ptr) {
+            MemTimer mt("hipFree", bytes);
             (void)hipFree(ptr);
             if (ctx) ctx->in_use -= bytes;
         }
@@ -52,7 +73,11 @@ struct DevBuf {
         if (nbytes == 0) nbytes = 16;
         if (c->limit && c->in_use + nbytes > c->limit)
             throw Error{GACA_ERR_OOM, "device memory cap exceeded (max_device_bytes)"};
-        hipError_t e = hipMalloc(&ptr, nbytes);
+        hipError_t e;
+        {
+            MemTimer mt("hipMalloc", nbytes);
+            e = hipMalloc(&ptr, nbytes);
+        }
         if (e != hipSuccess) {
             ptr = nullptr;
             (void)hipGetLastError();
@@ -60,6 +85,11 @@ struct DevBuf {
         }
         bytes = nbytes;
         c->in_use += nbytes;
+    }
+    void swap(DevBuf &o) {
+        std::swap(ptr, o.ptr);
+        std::swap(bytes, o.bytes);
+        std::swap(ctx, o.ctx);
     }
     template <class T>
     T *as() const { return reinterpret_cast<T *>(ptr); }
@@ -91,9 +121,22 @@ struct GrowBuf {
     ~GrowBuf() { release(); }
     template <class T>
     T *as() const { return reinterpret_cast<T *>(ptr); }
+    void swap(GrowBuf &o) {
+        std::swap(ptr, o.ptr);
+        std::swap(bytes, o.bytes);
+        std::swap(ctx, o.ctx);
+        std::swap(vmm, o.vmm);
+        std::swap(reserved, o.reserved);
+        std::swap(gran, o.gran);
+        std::swap(device, o.device);
+        chunks.swap(o.chunks);
+        plain.swap(o.plain);
+        last_fail.swap(o.last_fail);
+    }
 
     void release() {
         if (vmm && ptr) {
+            MemTimer mt("release of a mapped buffer", bytes);
             (void)hipDeviceSynchronize();
             size_t off = 0;
             for (auto &c : chunks) {
@@ -127,6 +170,7 @@ struct GrowBuf {
     bool map_chunk(size_t sz) {
         if (bytes + sz > reserved) return false;
         if (ctx->limit && ctx->in_use + sz > ctx->limit) return false;
+        MemTimer mt("mapping a chunk", sz);
         hipMemAllocationProp prop{};
         prop.type = hipMemAllocationTypePinned;
         prop.location.type = hipMemLocationTypeDevice;
@@ -219,6 +263,9 @@ struct GrowBuf {
                 if (!map_more(gran)) break;
             if (bytes >= need) return;
             // the mapping could not be extended: move to an ordinary allocation
+            if (g_mem_verbose.load())
+                std::fprintf(stderr, "gaca memory: mapping failed (%s), copying %.1f MiB to a plain allocation\n",
+                             last_fail.c_str(), used / 1048576.0);
             DevBuf nb;
             nb.alloc(c, std::max(need, bytes + bytes / 2));
             if (used > 0)
@@ -250,6 +297,7 @@ struct GrowBuf {
     void shrink(size_t used) {
         if (!vmm || chunks.empty()) return;
         if (used > bytes) return;
+        MemTimer mt("shrinking a mapped buffer", bytes);
         (void)hipDeviceSynchronize();
         while (!chunks.empty() && bytes - chunks.back().second >= used) {
             const auto c = chunks.back();
@@ -274,6 +322,7 @@ struct PinnedBuf {
     }
     void ensure(size_t need) {
         if (need <= bytes && ptr) return;
+        MemTimer mt("pinned host allocation", need);
         if (ptr) (void)hipHostFree(ptr);
         ptr = nullptr;
         const size_t want = std::max<size_t>({need, bytes + bytes / 2, 4096});
@@ -348,6 +397,10 @@ struct gaca_problem {
     hipStream_t far_streams[4] = {nullptr, nullptr, nullptr, nullptr};
     bool far_streams_ready = false;
     FarScratch fsc;
+    // mapped factor / fibre arenas of destroyed H-matrices, reused by the next build (mapping
+    // fresh pages costs milliseconds per GiB); guarded by spare_mu
+    std::mutex spare_mu;
+    GrowBuf spare_arena, spare_fib;
     ~gaca_problem() {
         if (far_streams_ready)
             for (auto &s : far_streams) (void)hipStreamDestroy(s);
@@ -876,12 +929,23 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
     } ev_guard{ev};
     GACA_HIP_CHECK(hipEventRecord(ev[EV_BEGIN], s0));
     const double ms_setup = wall_ms_since(t_entry);
+    double ms_wait = 0.0;   // host time blocked on the per-iteration status read-back
+    g_mem_verbose = p->opt.verbose;
+    const int64_t mem_ns0 = g_mem_ns.load(), mem_calls0 = g_mem_calls.load();
 
     FarScratch &W = p->fsc;
     size_t arena_used = 0, fib_used = 0;
-    h->d_arena.start(ctx, (size_t)std::max(1.0e5, factor_guess) * es);
-    h->d_fib.start(ctx, (size_t)std::max<int64_t>(1024, nfar * (int64_t)std::min(rcap, 16) * L) *
-                            sizeof(double2));
+    auto start_arena = [&](GrowBuf &dst, GrowBuf &spare, size_t need) {
+        {
+            std::lock_guard<std::mutex> lk(p->spare_mu);
+            if (spare.ptr) dst.swap(spare);
+        }
+        if (dst.ptr) dst.grow(ctx, need, 0, s0);
+        else dst.start(ctx, need);
+    };
+    start_arena(h->d_arena, p->spare_arena, (size_t)std::max(1.0e5, factor_guess) * es);
+    start_arena(h->d_fib, p->spare_fib,
+                (size_t)std::max<int64_t>(1024, nfar * (int64_t)std::min(rcap, 16) * L) * sizeof(double2));
     // algorithmic work model (flops; a complex multiply-add is 8): per quadrature point x
     // frequency the single layer costs 105 (distance 8, sqrt 13, exp 31, sincos 36,
     // 1/(4 pi r) 8, weight and accumulation 9), the double layer 113
@@ -1104,7 +1168,11 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             GACA_HIP_CHECK(hipEventRecord(ev[EV_T], s0));
             GACA_HIP_CHECK(hipMemcpyAsync(W.h_status.ptr, W.status.ptr, nact * 2 * sizeof(int32_t),
                                           hipMemcpyDeviceToHost, s0));
-            GACA_HIP_CHECK(hipStreamSynchronize(s0));
+            {
+                const auto tw = std::chrono::steady_clock::now();
+                GACA_HIP_CHECK(hipStreamSynchronize(s0));
+                ms_wait += wall_ms_since(tw);
+            }
             n_launch += 3 + nl + (ntile > 0);
             auto elapsed = [&](int x, int y) {
                 float ms = 0.0f;
@@ -1205,16 +1273,28 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             size_t fb = 0, tb = 0;
             if (hipMemGetInfo(&fb, &tb) != hipSuccess) (void)hipGetLastError();
             std::fprintf(stderr, "gaca far field: batch of blocks %lld..%lld of %lld done, %d iterations, "
-                         "%.1f ms since the start; factors %.2f GB, fibres %.2f GB, face pool %.2f GB, "
-                         "free %.2f GB\n", (long long)bt.first, (long long)bt.second, (long long)nfar, iter,
-                         wall_ms_since(t_entry), arena_used * es / 1e9, fib_used * 16.0 / 1e9,
-                         W.hpool.bytes / 1e9, fb / 1e9);
+                         "%.1f ms since the start (%.1f ms waiting for the device, %.1f ms in %lld memory "
+                         "calls); factors %.2f GB, fibres %.2f GB, face pool %.2f GB, free %.2f GB\n",
+                         (long long)bt.first, (long long)bt.second, (long long)nfar, iter,
+                         wall_ms_since(t_entry), ms_wait, (g_mem_ns.load() - mem_ns0) / 1e6,
+                         (long long)(g_mem_calls.load() - mem_calls0),
+                         arena_used * es / 1e9, fib_used * 16.0 / 1e9, W.hpool.bytes / 1e9, fb / 1e9);
             std::fflush(stderr);
         }
-        // give the pools' pages back between batches (in-place pools regrow without copies)
+        // give the pools' pages back between batches when memory is short (the arena needs
+        // them; in-place pools regrow without copies).  Mapping fresh pages is slow (tens of
+        // ms per GiB when the driver has to clear recently released memory), so pools stay
+        // mapped while the free memory exceeds their size.
         if (bnext < nfar) {
-            if (W.hpool.vmm) W.hpool.shrink(0);
-            if (W.fgpool.vmm) W.fgpool.shrink(0);
+            size_t fb = 0, tb = 0;
+            if (hipMemGetInfo(&fb, &tb) != hipSuccess) {
+                (void)hipGetLastError();
+                fb = 0;
+            }
+            if (fb < W.hpool.bytes + W.fgpool.bytes) {
+                if (W.hpool.vmm) W.hpool.shrink(0);
+                if (W.fgpool.vmm) W.fgpool.shrink(0);
+            }
         }
     }
     // large pools are not kept for the next build (they hold no result)
@@ -1396,6 +1476,27 @@ gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out) 
 }
 
 gaca_status gaca_hmatrix_destroy(gaca_hmatrix *h) {
+    if (h && h->p && !h->owned_problem) {
+        // keep mapped arenas of moderate size for the problem's next build
+        gaca_problem *p = h->p;
+        size_t fb = 0, tb = 0;
+        if (hipMemGetInfo(&fb, &tb) != hipSuccess) {
+            (void)hipGetLastError();
+            tb = 0;
+        }
+        std::lock_guard<std::mutex> lk(p->spare_mu);
+        bool synced = false;
+        auto donate = [&](GrowBuf &src, GrowBuf &spare) {
+            if (!src.vmm || !src.ptr || spare.ptr || src.bytes > tb / 8) return;
+            if (!synced) {
+                (void)hipDeviceSynchronize();   // no kernel may still use the arena
+                synced = true;
+            }
+            spare.swap(src);
+        };
+        donate(h->d_arena, p->spare_arena);
+        donate(h->d_fib, p->spare_fib);
+    }
     delete h;
     return GACA_OK;
 }
