@@ -4,9 +4,9 @@ One step = the whole hot path on the 3072-triangle cube workload (collocation, L
 s_l = 20 (1 + 0.95 e^{i 2 pi (l + 1/2)/64}), leaf 32, eta 1, eps 1e-6, FP64): the dense
 near field and the 3D-ACA of every far block for the single layer AND the double layer,
 plus one reordered product (eq. product, 2 right-hand sides per frequency) with each.
-The two operators are built from two host threads (one problem each), so their builds
-overlap on the GPU.  The problems (mesh, tree, partition, device geometry) are created
-before the timed region; the right-hand sides are resident in HBM.
+The two operators are built together (gaca_build_both: the far blocks of both share every
+far-field launch).  The problem (mesh, tree, partition, device geometry) is created before
+the timed region; the right-hand sides are resident in HBM.
 
 Prints ONE JSON line.  value = kernel entries per second, where the entries are the
 tensor entries the method needs: the dense near field (m n L per near block), the rows
@@ -16,7 +16,6 @@ from __future__ import annotations
 
 import argparse
 import json
-from concurrent.futures import ThreadPoolExecutor
 import os
 import sys
 import time
@@ -34,12 +33,14 @@ def dominant_kernels(kernels, all_stats):
     """Per-kernel device time (mean over steps), launches and algorithmic flops of one step,
     keyed by the kernel's name as the profiler lists it (FP64 build).  The face-ACA classes
     0-2 share their stream with the Gram-row kernel, so only class 3 (one kernel per launch
-    window) is listed as a single kernel."""
+    window) is listed as a single kernel.  A joint build of both operators reports its shared
+    launches in the stats of each operator: they are counted once, as kernel id -1."""
     out = {}
     nsteps = len(all_stats)
     for stp in all_stats:
-        for k, st in zip(kernels, stp):
-            kid = KID[k]
+        joint = stp[0]["joint_build"] > 1
+        for k, st in zip(kernels[:1] if joint else kernels, stp):
+            kid = -1 if joint else KID[k]
             rows = [(f"far_face_kernel<{kid}, false, false>", st["ms_far_phase"][0],
                      st["launches_phase"][0], st["far_flops_phase"][0]),
                     ("far_expand_kernel<false>", st["ms_far_phase"][2], st["launches_phase"][2],
@@ -194,6 +195,14 @@ def apply_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def build_all(prob, kernels):
+    """The operators `kernels` of prob: both collocation operators in one joint build."""
+    if sorted(kernels) == ["dlp", "slp"]:
+        hs, hd = prob.build_both()
+        return [hs, hd] if kernels[0] == "slp" else [hd, hs]
+    return [prob.build(k) for k in kernels]
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -219,24 +228,21 @@ def main():
     stream = torch.cuda.current_stream(dev)
     ctx = gaca.Context(0, stream=stream)
     kernels = cfg["kernels"]
-    # one problem per operator: the operators are built from one host thread each, so their
-    # builds overlap on the GPU (each problem has its own far-field streams and memory)
+    # one problem; with both operators they are built together (gaca_build_both: the blocks of
+    # both share every far-field launch)
     t_setup = time.perf_counter()
-    probs = {k: gaca.Problem(ctx, xyz, tri, s, leaf_size=cfg["leaf"], eta=cfg["eta"],
-                             eps3d=cfg["eps"], eps_aca=cfg["eps_aca"]) for k in kernels}
+    prob = gaca.Problem(ctx, xyz, tri, s, leaf_size=cfg["leaf"], eta=cfg["eta"],
+                        eps3d=cfg["eps"], eps_aca=cfg["eps_aca"])
     t_setup = time.perf_counter() - t_setup
     X = torch.from_numpy(random_rhs(L, M, args.nrhs, seed=0)).to(dev)
-    pool = ThreadPoolExecutor(len(kernels))
-
-    def one(k):
-        h = probs[k].build(k)
-        h.apply(X, stream=stream)
-        st = h.stats()
-        del h
-        return st
 
     def step():
-        return list(pool.map(one, kernels))
+        hs = build_all(prob, kernels)
+        for h in hs:
+            h.apply(X, stream=stream)
+        out = [h.stats() for h in hs]
+        del hs
+        return out
 
     for _ in range(args.warmup):
         step()
@@ -256,11 +262,12 @@ def main():
     kern = dominant_kernels(kernels, all_stats)
     dom_name = max(kern, key=lambda k: kern[k]["ms"])
     dom = kern[dom_name]
-    far_ms = np.mean([sum(st["ms_far_kernel"] for st in stp) for stp in all_stats])
+    far_ms = np.mean([sum(st["ms_far_kernel"] for st in stp) / stp[0]["joint_build"]
+                      for stp in all_stats])
     near_ms = np.mean([sum(st["ms_near_kernel"] for st in stp) for stp in all_stats])
     achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
-    phase_ms = np.mean([[sum(st["ms_far_phase"][k] for st in stp) for k in range(4)]
-                        for stp in all_stats], axis=0)
+    phase_ms = np.mean([[sum(st["ms_far_phase"][k] for st in stp) / stp[0]["joint_build"]
+                         for k in range(4)] for stp in all_stats], axis=0)
     out = {
         "metric": "3-way ACA build s + kernel entries/s, FP64 vs mixed-prec at stated rel err",
         "value": value,
@@ -301,32 +308,27 @@ def main():
                      "ms_per_launch": dom["ms"] / max(1, dom["launches"])},
     }
     if not args.no_mixed:
-        out["mixed"] = mixed_leg(gaca, ctx, xyz, tri, s, cfg, X, kernels, stream, probs, pool, args)
+        out["mixed"] = mixed_leg(gaca, ctx, xyz, tri, s, cfg, X, kernels, stream, prob, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, xyz, tri, s, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
-def mixed_leg(gaca, ctx, xyz, tri, s, cfg, X, kernels, stream, probs64, pool, args):
+def mixed_leg(gaca, ctx, xyz, tri, s, cfg, X, kernels, stream, prob64, args):
     """The same step with the mixed-precision build (FP32 far-field faces and factors with
     the per-(block, frequency) scale, FP64 fibres/norms; near field stored FP32) and the
     relative difference of its apply from the FP64 build's apply (same X)."""
     import numpy as np
     import torch
-    pms = {k: gaca.Problem(ctx, xyz, tri, s, leaf_size=cfg["leaf"], eta=cfg["eta"],
-                           eps3d=cfg["eps"], eps_aca=cfg["eps_aca"], precision="mixed")
-           for k in kernels}
+    pm = gaca.Problem(ctx, xyz, tri, s, leaf_size=cfg["leaf"], eta=cfg["eta"],
+                      eps3d=cfg["eps"], eps_aca=cfg["eps_aca"], precision="mixed")
     X32 = X.to(torch.complex64)
 
-    def one(k):
-        h = pms[k].build(k)
-        y = h.apply(X32, stream=stream)
-        st = h.stats()
-        del h
-        return st, y
-
     def step():
-        return list(pool.map(one, kernels))
+        hs = build_all(pm, kernels)
+        out = [(h.stats(), h.apply(X32, stream=stream)) for h in hs]
+        del hs
+        return out
 
     step()
     torch.cuda.synchronize()
@@ -337,19 +339,20 @@ def mixed_leg(gaca, ctx, xyz, tri, s, cfg, X, kernels, stream, probs64, pool, ar
     last = runs[-1]
     entries = sum(st["entries_near"] + st["entries_face"] + st["entries_fibre"] for st, _ in last)
     errs = {}
-    for k, (st, y) in zip(kernels, last):
-        h64 = probs64[k].build(k)
+    h64s = build_all(prob64, kernels)
+    for k, (st, y), h64 in zip(kernels, last, h64s):
         y64 = h64.apply(X, stream=stream)
         torch.cuda.synchronize()
         d = (y.to(torch.complex128) - y64).norm().item() / y64.norm().item()
         errs[k] = d
-        del h64
+    del h64s
     return {"value": entries * len(runs) / el, "unit": "entries/s",
             "ms_per_step": el / len(runs) * 1e3,
             "build_ms": {k: st["ms_total"] for k, (st, _) in zip(kernels, last)},
-            "far_kernel_ms": float(np.mean([sum(st["ms_far_kernel"] for st, _ in r) for r in runs])),
-            "far_phase_ms": [float(np.mean([sum(st["ms_far_phase"][k] for st, _ in r) for r in runs]))
-                             for k in range(4)],
+            "far_kernel_ms": float(np.mean([sum(st["ms_far_kernel"] for st, _ in r) / r[0][0]["joint_build"]
+                                            for r in runs])),
+            "far_phase_ms": [float(np.mean([sum(st["ms_far_phase"][k] for st, _ in r) / r[0][0]["joint_build"]
+                                            for r in runs])) for k in range(4)],
             "apply_rel_diff_vs_fp64": errs,
             "ranks": {k: [st["rank_min"], st["rank_max"], round(st["rank_mean"], 2)]
                       for k, (st, _) in zip(kernels, last)}}

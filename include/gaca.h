@@ -72,8 +72,8 @@ typedef struct {
     int32_t max_face_rank;    /* cap on a face's ACA rank (default min(m, n)) */
     uint64_t max_device_bytes;/* 0 = no limit; otherwise total library device memory cap */
     uint64_t batch_bytes;     /* far-field scratch per batch of blocks (default 24 GiB) */
-    int32_t threads_small;    /* face-ACA workgroup size for faces with m n <= 1024 (64 or
-                                 128; default 64) */
+    int32_t threads_small;    /* face-ACA workgroup size for faces with m n <= 1024: 128
+                                 (default) or 64 (one wave per face) */
     int32_t threads_large;    /* face-ACA workgroup size for the large faces (256, 512 or
                                  1024; default 0: 512) */
     int32_t verbose;          /* 1: one progress line per far-field batch on stderr */
@@ -132,6 +132,9 @@ typedef struct {
     double ms_apply_part[3];      /* device time of the apply kernels: far T = F X, far Z = W T, leaf */
     double apply_flops_part[3];
     int32_t arena_in_place;       /* 1: the factor arena grows in place (virtual memory) */
+    int32_t joint_build;          /* operators built together (gaca_build_both: 2); the far-field
+                                     timings, launch counts, kernel evaluations and flops above
+                                     then describe the shared launches of the joint build */
 } gaca_stats;
 
 int gaca_abi_version(void);
@@ -178,6 +181,12 @@ gaca_status gaca_quadrature_rule(int kind, int n, double *nodes, double *weights
  * Synchronous: returns when the device work is done.  GACA_ERR_NOT_CONVERGED if a rank
  * cap was hit (the handle is still returned and usable). */
 gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out);
+/* Builds the single and double layer operators of a collocation problem together (Algorithm 1
+ * on every far block of both; Sec. 4): the blocks of both operators advance in the same
+ * far-field iterations, so each launch carries the faces of both; results are those of two
+ * gaca_build calls.  GACA_ERR_UNSUPPORTED for a Galerkin problem.  GACA_ERR_NOT_CONVERGED as
+ * gaca_build (both handles returned). */
+gaca_status gaca_build_both(gaca_problem *p, gaca_hmatrix **slp_out, gaca_hmatrix **dlp_out);
 /* An H-matrix refers to its problem: destroy it before the problem.  Destroying it waits
  * for the device to be idle; its factor and fibre arenas (when mapped in place and at most
  * an eighth of the device memory) are kept by the problem and reused by its next build,
@@ -188,7 +197,8 @@ gaca_status gaca_hmatrix_stats(const gaca_hmatrix *h, gaca_stats *st);
 gaca_status gaca_hmatrix_freq_hist(const gaca_hmatrix *h, int64_t *hist);
 
 /* Export of far block idx (tree-order rows/cols, see gaca_problem_blocks):
- * info[8] = {row_start, m, col_start, n, r, sum_rho, capped, zero_faces}.
+ * info[9] = {row_start, m, col_start, n, r, sum_rho, capped, zero_faces, aca_ticks}
+ * (aca_ticks: device wall-clock ticks, 100 MHz, spent in the block's face ACAs).
  * Then (host buffers sized from info): ks[r], pi[r], pj[r] (tree-local pivots), rho[r],
  * U: sum_rho * m complex (cross by cross, column-major m x rho_l),
  * W: sum_rho * n complex (column-major n x rho_l), F: r * L complex (FP64 fibres),

@@ -50,7 +50,8 @@ class Stats(ctypes.Structure):
                 ("launches_by_kind", I32 * 4), ("far_flops_by_kind", F64 * 4),
                 ("ms_far_aca_block_max", F64), ("ms_host_setup", F64), ("ms_host_finish", F64),
                 ("ms_apply", F64), ("apply_flops", F64), ("apply_operator_bytes", F64),
-                ("ms_apply_part", F64 * 3), ("apply_flops_part", F64 * 3), ("arena_in_place", I32)]
+                ("ms_apply_part", F64 * 3), ("apply_flops_part", F64 * 3), ("arena_in_place", I32),
+                ("joint_build", I32)]
 
 
 def lib_path() -> str:
@@ -83,6 +84,7 @@ def load_library():
         "gaca_problem_blocks": (I32, [P, P, P]),
         "gaca_partition_host": (I32, [P, I64, P, I64, I32, F64, P, I64, P, P, P, P]),
         "gaca_build": (I32, [P, ctypes.c_int, P]),
+        "gaca_build_both": (I32, [P, P, P]),
         "gaca_hmatrix_destroy": (I32, [P]),
         "gaca_hmatrix_stats": (I32, [P, P]),
         "gaca_hmatrix_freq_hist": (I32, [P, P]),
@@ -226,6 +228,14 @@ class Problem:
         rc = _check(self._lib.gaca_build(self.handle, KERNELS[kernel], ctypes.byref(h)), allow)
         return HMatrix(self, h, kernel, converged=(rc == 0))
 
+    def build_both(self, allow_not_converged=True):
+        """Single and double layer operators built together (gaca_build_both)."""
+        hs, hd = P(), P()
+        allow = (-5,) if allow_not_converged else ()
+        rc = _check(self._lib.gaca_build_both(self.handle, ctypes.byref(hs), ctypes.byref(hd)), allow)
+        return (HMatrix(self, hs, "slp", converged=(rc == 0)),
+                HMatrix(self, hd, "dlp", converged=(rc == 0)))
+
     def eval_entries(self, kernel, i, j, k, far):
         i = np.ascontiguousarray(i, dtype=np.int32)
         j = np.ascontiguousarray(j, dtype=np.int32)
@@ -273,11 +283,11 @@ class HMatrix:
         return out
 
     def block_info(self, idx):
-        info = np.zeros(8, dtype=np.int64)
+        info = np.zeros(9, dtype=np.int64)
         _check(self._lib.gaca_hmatrix_block_info(self.handle, idx, _ptr(info)))
         return dict(r0=int(info[0]), m=int(info[1]), c0=int(info[2]), n=int(info[3]),
                     rank=int(info[4]), sum_rho=int(info[5]), capped=int(info[6]),
-                    zero_faces=int(info[7]))
+                    zero_faces=int(info[7]), aca_ticks=int(info[8]))
 
     def export_block(self, idx):
         inf = self.block_info(idx)

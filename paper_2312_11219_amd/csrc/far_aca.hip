@@ -47,6 +47,10 @@ constexpr int kCurRegs = 4;         // current u, w in registers for m, n <= 256
 template <int KERNEL, bool DENSE, class FT>
 __device__ __forceinline__ FT face_entry(const GeoDev &g, const FreqDev &f, const double2 *dense,
                                          const FarBlockDev &B, int il, int jl, int kk) {
+    if constexpr (KERNEL < 0) {   // joint build: the block's own collocation kernel
+        return B.kern == 0 ? face_entry<0, DENSE, FT>(g, f, dense, B, il, jl, kk)
+                           : face_entry<1, DENSE, FT>(g, f, dense, B, il, jl, kk);
+    }
     if (DENSE) return from_d2<FT>(dense[((int64_t)il * B.n + jl) * f.L + kk]);
     const int64_t gi = B.r0 + il, gj = B.c0 + jl;
     if constexpr (KERNEL == 2) {
@@ -85,6 +89,10 @@ template <int KERNEL, bool DENSE>
 __device__ __forceinline__ double2 fibre_entry(const GeoDev &g, const FreqDev &f,
                                                const double2 *dense, const FarBlockDev &B,
                                                int il, int jl, int kk) {
+    if constexpr (KERNEL < 0) {
+        return B.kern == 0 ? fibre_entry<0, DENSE>(g, f, dense, B, il, jl, kk)
+                           : fibre_entry<1, DENSE>(g, f, dense, B, il, jl, kk);
+    }
     if (DENSE) return dense[((int64_t)il * B.n + jl) * f.L + kk];
     const int64_t gi = B.r0 + il, gj = B.c0 + jl;
     double er, ei;
@@ -192,13 +200,17 @@ __device__ int first_unused(const unsigned char *used, int len, Red<NT> &red) {
 }
 
 // ---------------------------------------------------------------------------------------
-// ACA phase, small faces: R and S in LDS, updated in place by the rank-1 steps.  Also
-// stores H_l = S over R, and finds its max, norm and pivot (the Gram row against the
-// previous faces follows in far_gram_small_kernel).
+// ACA phase, small faces: R and S = sum_q u_q w_q^T in registers, E = MNMAX / NT entries
+// per thread (entry idx = tid + NT t), updated in place by the rank-1 steps; only the current
+// row, column and w live in LDS, so several faces share a CU.  Also stores H_l = S over R and
+// finds its max, norm and pivot (the Gram row against the previous faces follows in
+// far_gram_small_kernel).
 template <int NT, bool MIXED, int MNMAX, int SIDE>
 __global__ void __launch_bounds__(NT)
     far_aca_small_kernel(AcaParams P, FarBatchDev bd, const FarActive *act) {
     using FT = face_t<MIXED>;
+    constexpr int E = MNMAX / NT;
+    static_assert(E * NT == MNMAX, "MNMAX must be a multiple of NT");
     const FarActive A = act[blockIdx.x];
     const int b = A.b;
     const FarBlockDev B = bd.blk[b];
@@ -210,8 +222,7 @@ __global__ void __launch_bounds__(NT)
     FT *Wb = Ub + (int64_t)B.rho_max * m;
 
     const int64_t t_start = wall_clock64();
-    __shared__ FT Rs[MNMAX];
-    __shared__ FT Ss[MNMAX];
+    __shared__ FT rowv[SIDE];
     __shared__ FT ucol[SIDE];
     __shared__ FT wrow[SIDE];
     __shared__ unsigned char used_row[SIDE];
@@ -219,18 +230,26 @@ __global__ void __launch_bounds__(NT)
     Red<NT> red{redbuf};
     const double tie2 = (1.0 - P.tie) * (1.0 - P.tie);
 
-#pragma unroll 8
-    for (int idx = tid; idx < mn; idx += NT) {
-        Rs[idx] = R[idx];
-        Ss[idx] = czero<FT>();
+    FT rr[E], ss[E];
+    int ri[E];   // row of entry t; m for entries beyond the face
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int idx = tid + NT * t;
+        ri[t] = idx < mn ? idx / n : m;
+        rr[t] = idx < mn ? R[idx] : czero<FT>();
+        ss[t] = czero<FT>();
     }
     for (int r = tid; r < m; r += NT) used_row[r] = 0;
-    __syncthreads();
     int q = 0, i = 0, nused = 0;
     double s2 = 0.0;
     while (true) {
+        // row i of the residual -> LDS (its owners write it)
+#pragma unroll
+        for (int t = 0; t < E; ++t)
+            if (ri[t] == i) rowv[tid + NT * t - i * n] = rr[t];
+        __syncthreads();
         double mx = 0.0;
-        for (int j = tid; j < n; j += NT) mx = fmax(mx, cabs2(Rs[i * n + j]));
+        for (int j = tid; j < n; j += NT) mx = fmax(mx, cabs2(rowv[j]));
         mx = red.max(mx);
         if (tid == 0) used_row[i] = 1;
         ++nused;
@@ -244,35 +263,38 @@ __global__ void __launch_bounds__(NT)
         const double thr = tie2 * mx;
         int jc = n;
         for (int j = tid; j < n; j += NT)
-            if (cabs2(Rs[i * n + j]) >= thr) {
+            if (cabs2(rowv[j]) >= thr) {
                 jc = j;
                 break;
             }
         const int jp = min(red.imin(jc), n - 1);   // in range even for NaN rows
-        const FT piv = Rs[i * n + jp];
+        const FT piv = rowv[jp];
         double nw2 = 0.0, nu2 = 0.0;
         for (int j = tid; j < n; j += NT) {
-            const FT w = cdiv(Rs[i * n + j], piv);
+            const FT w = cdiv(rowv[j], piv);
             wrow[j] = w;
             Wb[(int64_t)q * n + j] = w;
             nw2 += cabs2(w);
         }
-        for (int r = tid; r < m; r += NT) {
-            const FT u = Rs[r * n + jp];
-            ucol[r] = u;
-            Ub[(int64_t)q * m + r] = u;
-            nu2 += cabs2(u);
-        }
+        // column jp of the residual (its owners write it)
+#pragma unroll
+        for (int t = 0; t < E; ++t)
+            if (ri[t] < m && tid + NT * t - ri[t] * n == jp) {
+                const FT u = rr[t];
+                ucol[ri[t]] = u;
+                Ub[(int64_t)q * m + ri[t]] = u;
+                nu2 += cabs2(u);
+            }
         __syncthreads();
         double sp = 0.0;
-        for (int idx = tid; idx < mn; idx += NT) {
-            const int r = idx / n, j = idx - r * n;
-            const FT t = cmul(ucol[r], wrow[j]);
-            Rs[idx] = csub(Rs[idx], t);
-            const FT sv = cadd(Ss[idx], t);
-            Ss[idx] = sv;
-            sp += cabs2(sv);
-        }
+#pragma unroll
+        for (int t = 0; t < E; ++t)
+            if (ri[t] < m) {
+                const FT tt = cmul(ucol[ri[t]], wrow[tid + NT * t - ri[t] * n]);
+                rr[t] = csub(rr[t], tt);
+                ss[t] = cadd(ss[t], tt);
+                sp += cabs2(ss[t]);
+            }
         red.sum3(nu2, nw2, sp);
         s2 = sp;
         ++q;
@@ -284,21 +306,20 @@ __global__ void __launch_bounds__(NT)
     int pidx = 0;
     double mxh = 0.0, h2 = 0.0;
     if (rho > 0) {
-        for (int idx = tid; idx < mn; idx += NT) {
-            const FT h = Ss[idx];
-            R[idx] = h;
-            const double a2 = cabs2(h);
-            mxh = fmax(mxh, a2);
-            h2 += a2;
-        }
+#pragma unroll
+        for (int t = 0; t < E; ++t)
+            if (ri[t] < m) {
+                R[tid + NT * t] = ss[t];
+                const double a2 = cabs2(ss[t]);
+                mxh = fmax(mxh, a2);
+                h2 += a2;
+            }
         red.maxsum(mxh, h2);
         const double thh = tie2 * mxh;
         int pc = 0x7fffffff;
-        for (int idx = tid; idx < mn; idx += NT)
-            if (cabs2(Ss[idx]) >= thh) {
-                pc = idx;
-                break;
-            }
+#pragma unroll
+        for (int t = E - 1; t >= 0; --t)   // lowest own index at the threshold
+            if (ri[t] < m && cabs2(ss[t]) >= thh) pc = tid + NT * t;
         pidx = min(red.imin(pc), mn - 1);
     }
     if (tid == 0) {
@@ -1054,9 +1075,10 @@ __global__ void __launch_bounds__(256)
 // per workgroup with all loads of a thread issued before its stores.
 template <class FT>
 __global__ void __launch_bounds__(256) far_copy_kernel(FarBatchDev bd, const FarCopy *cp,
-                                                       FT *arena, int64_t *cross_off) {
+                                                       FT *arena0, FT *arena1, int64_t *cross_off) {
     constexpr int PER = kFarCopyChunk / 256;
     const FarCopy C = cp[blockIdx.x];
+    FT *arena = C.which ? arena1 : arena0;
     const FarBlockDev B = bd.blk[C.b];
     const FT *Ub = reinterpret_cast<const FT *>(bd.uw) + B.uw_off;
     const FT *Wb = Ub + (int64_t)B.rho_max * B.m;
@@ -1081,8 +1103,9 @@ __global__ void __launch_bounds__(256) far_copy_kernel(FarBatchDev bd, const Far
 
 // Fibres of finished blocks -> fibre arena (rank x L, contiguous per block).
 __global__ void __launch_bounds__(256) far_gather_kernel(FarBatchDev bd, const FarGather *gt,
-                                                         double2 *fib_arena, int64_t *fib_off) {
+                                                         double2 *fib0, double2 *fib1, int64_t *fib_off) {
     const FarGather G = gt[blockIdx.x];
+    double2 *fib_arena = G.which ? fib1 : fib0;
     const FarBlockDev B = bd.blk[G.b];
     const int L = bd.L;
     for (int p = 0; p < G.rank; ++p) {
@@ -1110,7 +1133,10 @@ void launch_far_face(int kernel, const GeoDev &g, const FreqDev &f, const FarBat
                      const FarActive *act, int64_t nchunk, hipStream_t st) {
     if (nchunk <= 0) return;
     if (bd.dense) face_dispatch<0, true, false>(g, f, bd, act, nchunk, st);
-    else if (!bd.mixed) {
+    else if (kernel < 0) {
+        if (bd.mixed) face_dispatch<-1, false, true>(g, f, bd, act, nchunk, st);
+        else face_dispatch<-1, false, false>(g, f, bd, act, nchunk, st);
+    } else if (!bd.mixed) {
         if (kernel == 0) face_dispatch<0, false, false>(g, f, bd, act, nchunk, st);
         else if (kernel == 1) face_dispatch<1, false, false>(g, f, bd, act, nchunk, st);
         else face_dispatch<2, false, false>(g, f, bd, act, nchunk, st);
@@ -1124,24 +1150,35 @@ void launch_far_face(int kernel, const GeoDev &g, const FreqDev &f, const FarBat
 template <bool MX>
 static void aca_dispatch(int kind, int threads, const AcaParams &P, const FarBatchDev &bd,
                          const FarActive *act, int nact, hipStream_t st) {
-    if (kind == 0) {
-        if (threads >= 128) far_aca_small_kernel<128, MX, 1024, 64><<<nact, 128, 0, st>>>(P, bd, act);
-        else far_aca_small_kernel<64, MX, 1024, 64><<<nact, 64, 0, st>>>(P, bd, act);
-    } else if (kind == 1) {
+    // large faces: one face per CU with 1024 or 512 threads and ~100 KB of LDS history, or
+    // 256 threads with 32 KB, several per CU
+    (void)kind;
+    if (threads >= 1024)
+        far_aca_large_kernel<1024, MX, 90112><<<nact, 1024, 0, st>>>(P, bd, act);
+    else if (threads >= 512)
+        far_aca_large_kernel<512, MX, 106496><<<nact, 512, 0, st>>>(P, bd, act);
+    else
+        far_aca_large_kernel<256, MX, 32768><<<nact, 256, 0, st>>>(P, bd, act);
+}
+
+template <bool MX>
+static void aca_small_dispatch(int mnmax, int threads, const AcaParams &P, const FarBatchDev &bd,
+                               const FarActive *act, int nact, hipStream_t st) {
+    constexpr int K2 = MX ? 8192 : 4096;
+    if (mnmax <= 576 && threads <= 64)
+        far_aca_small_kernel<64, MX, 576, 64><<<nact, 64, 0, st>>>(P, bd, act);
+    else if (mnmax <= 1024 && threads <= 64)
+        far_aca_small_kernel<64, MX, 1024, 64><<<nact, 64, 0, st>>>(P, bd, act);
+    else if (mnmax <= 1024)
+        far_aca_small_kernel<128, MX, 1024, 64><<<nact, 128, 0, st>>>(P, bd, act);
+    else if (mnmax <= 2304 && threads <= 64)
+        far_aca_small_kernel<64, MX, 2304, 96><<<nact, 64, 0, st>>>(P, bd, act);
+    else if (mnmax <= 2304 && threads <= 128)
+        far_aca_small_kernel<128, MX, 2304, 96><<<nact, 128, 0, st>>>(P, bd, act);
+    else if (mnmax <= 2304)
         far_aca_small_kernel<256, MX, 2304, 96><<<nact, 256, 0, st>>>(P, bd, act);
-    } else if (kind == 2) {
-        // R and S in 128 KB of LDS: 4096 FP64 or 8192 FP32 complex entries each
-        far_aca_small_kernel<512, MX, (MX ? 8192 : 4096), 128><<<nact, 512, 0, st>>>(P, bd, act);
-    } else {
-        // one face per CU: 1024 or 512 threads with ~110 KB of LDS history; 256 threads with
-        // 32 KB, several faces per CU
-        if (threads >= 1024)
-            far_aca_large_kernel<1024, MX, 90112><<<nact, 1024, 0, st>>>(P, bd, act);
-        else if (threads >= 512)
-            far_aca_large_kernel<512, MX, 106496><<<nact, 512, 0, st>>>(P, bd, act);
-        else
-            far_aca_large_kernel<256, MX, 32768><<<nact, 256, 0, st>>>(P, bd, act);
-    }
+    else
+        far_aca_small_kernel<512, MX, K2, 128><<<nact, 512, 0, st>>>(P, bd, act);
 }
 
 void launch_far_aca(int kind, int threads, const AcaParams &P, const FarBatchDev &bd,
@@ -1149,6 +1186,13 @@ void launch_far_aca(int kind, int threads, const AcaParams &P, const FarBatchDev
     if (nact <= 0) return;
     if (bd.mixed) aca_dispatch<true>(kind, threads, P, bd, act, nact, st);
     else aca_dispatch<false>(kind, threads, P, bd, act, nact, st);
+}
+
+void launch_far_aca_small(int mnmax, int threads, const AcaParams &P, const FarBatchDev &bd,
+                          const FarActive *act, int nact, hipStream_t st) {
+    if (nact <= 0) return;
+    if (bd.mixed) aca_small_dispatch<true>(mnmax, threads, P, bd, act, nact, st);
+    else aca_small_dispatch<false>(mnmax, threads, P, bd, act, nact, st);
 }
 
 void launch_far_expand(const FarBatchDev &bd, const FarActive *act, int64_t ntile, hipStream_t st) {
@@ -1174,7 +1218,10 @@ void launch_far_tail(int kernel, const GeoDev &g, const FreqDev &f, const AcaPar
                      hipStream_t st) {
     if (nact <= 0) return;
     if (bd.dense) tail_dispatch<0, true, false>(g, f, P, bd, act, nact, nlarge, st);
-    else if (!bd.mixed) {
+    else if (kernel < 0) {
+        if (bd.mixed) tail_dispatch<-1, false, true>(g, f, P, bd, act, nact, nlarge, st);
+        else tail_dispatch<-1, false, false>(g, f, P, bd, act, nact, nlarge, st);
+    } else if (!bd.mixed) {
         if (kernel == 0) tail_dispatch<0, false, false>(g, f, P, bd, act, nact, nlarge, st);
         else if (kernel == 1) tail_dispatch<1, false, false>(g, f, P, bd, act, nact, nlarge, st);
         else tail_dispatch<2, false, false>(g, f, P, bd, act, nact, nlarge, st);
@@ -1185,19 +1232,21 @@ void launch_far_tail(int kernel, const GeoDev &g, const FreqDev &f, const AcaPar
     }
 }
 
-void launch_far_copy(const FarBatchDev &bd, const FarCopy *c, int n, void *arena,
+void launch_far_copy(const FarBatchDev &bd, const FarCopy *c, int n, void *const arena[2],
                      int64_t *cross_off, hipStream_t st) {
     if (n <= 0) return;
     if (bd.mixed)
-        far_copy_kernel<float2><<<n, 256, 0, st>>>(bd, c, reinterpret_cast<float2 *>(arena), cross_off);
+        far_copy_kernel<float2><<<n, 256, 0, st>>>(bd, c, reinterpret_cast<float2 *>(arena[0]),
+                                                  reinterpret_cast<float2 *>(arena[1]), cross_off);
     else
-        far_copy_kernel<double2><<<n, 256, 0, st>>>(bd, c, reinterpret_cast<double2 *>(arena), cross_off);
+        far_copy_kernel<double2><<<n, 256, 0, st>>>(bd, c, reinterpret_cast<double2 *>(arena[0]),
+                                                   reinterpret_cast<double2 *>(arena[1]), cross_off);
 }
 
-void launch_far_gather(const FarBatchDev &bd, const FarGather *gt, int n, double2 *fib_arena,
+void launch_far_gather(const FarBatchDev &bd, const FarGather *gt, int n, double2 *const fib_arena[2],
                        int64_t *fib_off, hipStream_t st) {
     if (n <= 0) return;
-    far_gather_kernel<<<n, 256, 0, st>>>(bd, gt, fib_arena, fib_off);
+    far_gather_kernel<<<n, 256, 0, st>>>(bd, gt, fib_arena[0], fib_arena[1], fib_off);
 }
 
 }  // namespace gaca

@@ -79,7 +79,10 @@ struct FarBlockDev {
     // Dh = fl32(D), d0f = fl32(|D|), kappa = |Dh|^2 - d0f^2 (exact in FP64) and
     // xs_adj = x_sigma - (D - Dh) (so row offsets absorb the rounding of D)
     double xs_adj[3], yt[3];
-    float Dh[3], d0f, kappa, pad_[3];
+    float Dh[3], d0f, kappa;
+    int32_t kern;              // kernel id of the block's operator (joint builds mix 0 and 1)
+    int32_t which;             // operator index of a joint build (0 or 1)
+    int32_t pad_;
 };
 
 // Mutable 3D-ACA state of one far block between the phases of an iteration.

@@ -27,7 +27,8 @@ void launch_near_galerkin(int tier, const GeoDev &g, const QuadDev &q, const Fre
                           double2 *out64, float2 *out32, hipStream_t st);
 
 // Kernel ids used by the far-field and eval launches: 0 collocation single layer,
-// 1 collocation double layer, 2 Galerkin single layer.
+// 1 collocation double layer, 2 Galerkin single layer; the face and tail launches also take
+// -1, a joint build of both collocation operators (each block's kernel in FarBlockDev::kern).
 //
 // Far field 3D-ACA, run as iterations over all unfinished blocks of a batch; one iteration
 // adds one face (one 3-D cross, or one zero face) to every active block in four phases:
@@ -54,11 +55,13 @@ struct FarActive {
 
 struct FarCopy {        // one chunk of the factors of an accepted cross -> arena
     int32_t b, p, rho, chunk;
+    int32_t which, pad;   // operator (arena) of a joint build
     int64_t off;
 };
 constexpr int kFarCopyChunk = 4096;   // elements per copy workgroup
 struct FarGather {      // fibres of a finished block -> fibre arena
     int32_t b, rank;
+    int32_t which, pad;   // operator (fibre arena) of a joint build
     int64_t off;
 };
 
@@ -86,19 +89,24 @@ void launch_far_map(const FarBatchDev &bd, const FarActive *act, int nact, int n
 void launch_far_face(int kernel, const GeoDev &g, const FreqDev &f, const FarBatchDev &bd,
                      const FarActive *act, int64_t nchunk, hipStream_t st);
 // Classes: kind 0 m n <= 1024, sides <= 64; kind 1 m n <= 2304, sides <= 96; kind 2 m n <=
-// 4096 (FP64) or 8192 (mixed), sides <= 128; kind 3 larger.  threads: workgroup size
-// (kind 0: 64 or 128; kind 3: 256, 512 or 1024; kind 1: 256; kind 2: 512).
+// 4096 (FP64) or 8192 (mixed), sides <= 128; kind 3 larger.
+// Kind 3 (R in HBM): threads 256, 512 or 1024.
 void launch_far_aca(int kind, int threads, const AcaParams &P, const FarBatchDev &bd,
                     const FarActive *act, int nact, hipStream_t st);
+// Kinds 0-2 (R and S in registers): faces with m n <= mnmax (576, 1024, 2304, or the kind-2
+// bound) and workgroups of `threads` (64: one wave per face, 128, 256; kind 2: 512).
+void launch_far_aca_small(int mnmax, int threads, const AcaParams &P, const FarBatchDev &bd,
+                          const FarActive *act, int nact, hipStream_t st);
 void launch_far_expand(const FarBatchDev &bd, const FarActive *act, int64_t ntile, hipStream_t st);
 // Gram rows of LDS-resident faces (kinds 0-2) into their single partial row (FarActive::tile0)
 void launch_far_gram_small(const FarBatchDev &bd, const FarActive *act, int nact, hipStream_t st);
 void launch_far_tail(int kernel, const GeoDev &g, const FreqDev &f, const AcaParams &P,
                      const FarBatchDev &bd, const FarActive *act, int nact, int nlarge,
                      hipStream_t st);
-void launch_far_copy(const FarBatchDev &bd, const FarCopy *c, int n, void *arena,
+// arena[w] / fib_arena[w]: output arenas of operator w (FarCopy::which, FarGather::which)
+void launch_far_copy(const FarBatchDev &bd, const FarCopy *c, int n, void *const arena[2],
                      int64_t *cross_off, hipStream_t st);
-void launch_far_gather(const FarBatchDev &bd, const FarGather *gt, int n, double2 *fib_arena,
+void launch_far_gather(const FarBatchDev &bd, const FarGather *gt, int n, double2 *const fib_arena[2],
                        int64_t *fib_off, hipStream_t st);
 
 // Test hook: entries of (row, col) tree positions with given tiers at frequency k.

@@ -400,7 +400,7 @@ struct gaca_problem {
     // mapped factor / fibre arenas of destroyed H-matrices, reused by the next build (mapping
     // fresh pages costs milliseconds per GiB); guarded by spare_mu
     std::mutex spare_mu;
-    GrowBuf spare_arena, spare_fib;
+    GrowBuf spare_arena[2], spare_fib[2];
     ~gaca_problem() {
         if (far_streams_ready)
             for (auto &s : far_streams) (void)hipStreamDestroy(s);
@@ -742,6 +742,9 @@ gaca_status gaca_problem_blocks(const gaca_problem *p, int64_t *far4, int64_t *n
 // far-field build
 // Launch class of a far block in the aca phase: faces of kinds 0-2 stay in LDS (R and S,
 // up to 128 KB), kind 3 keeps R in HBM.
+// Large faces with both sides at most this run as medium faces (see run_far).
+constexpr int kMediumSide = 128;
+
 static int far_kind(int m, int n, bool mixed) {
     const int64_t mn = (int64_t)m * n;
     if (mn <= 1024 && m <= 64 && n <= 64) return 0;
@@ -804,38 +807,62 @@ static double wall_ms_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<void()> &main_work) {
+// Far field of one operator, or (H of size 2) of the single and double layer operators of
+// one collocation problem at once: their blocks are interleaved in one block list, so every
+// iteration's launches carry faces of both (each block's kernel in FarBlockDev::kern), and
+// the outputs go to each operator's own arenas and tables.
+static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
+                    const std::function<void()> &main_work) {
     const auto t_entry = std::chrono::steady_clock::now();
+    gaca_hmatrix *h = H[0];   // problem, precision and rank cap are common to all of H
+    const int nh = (int)H.size();
     gaca_problem *p = h->p;
     gaca_context *ctx = p->ctx;
     const auto &far = p->part.far;
     const int64_t nfar = (int64_t)far.size();
-    h->nfar = nfar;
+    const int64_t ntot = nh * nfar;   // block gb: operator gb % nh, far block gb / nh
     const int L = p->L;
     const int rcap = h->rcap;
     const bool mixed = h->prec == GACA_MIXED;
     const size_t es = mixed ? sizeof(float2) : sizeof(double2);
     const int PS = far_part_stride(rcap);
-    h->meta.assign(nfar, FarMeta{});
-    h->cmeta.assign(nfar * rcap, CrossMeta{});
-    h->cross_off.assign(nfar * rcap, -1);
-    h->fib_off.assign(nfar, -1);
+    const int fk = nh == 1 ? h->kernel : -1;   // face / tail launch kernel id
     std::vector<int32_t> far4(4 * std::max<int64_t>(nfar, 1));
     for (int64_t b = 0; b < nfar; ++b)
         for (int k = 0; k < 4; ++k) far4[4 * b + k] = (int32_t)far[b][k];
-    h->d_far4.upload(ctx, far4);
+    for (gaca_hmatrix *hh : H) {
+        hh->nfar = nfar;
+        hh->meta.assign(nfar, FarMeta{});
+        hh->cmeta.assign(nfar * rcap, CrossMeta{});
+        hh->cross_off.assign(nfar * rcap, -1);
+        hh->fib_off.assign(nfar, -1);
+        hh->d_far4.upload(ctx, far4);
+    }
     if (nfar == 0) {
         main_work();
         return;
     }
-    h->d_meta.alloc(ctx, nfar * sizeof(FarMeta));
-    h->d_cmeta.alloc(ctx, nfar * rcap * sizeof(CrossMeta));
-    h->d_cross_off.alloc(ctx, nfar * rcap * sizeof(int64_t));
-    h->d_fib_off.alloc(ctx, nfar * sizeof(int64_t));
-    GACA_HIP_CHECK(hipMemset(h->d_meta.ptr, 0, nfar * sizeof(FarMeta)));
-    GACA_HIP_CHECK(hipMemset(h->d_cmeta.ptr, 0, nfar * rcap * sizeof(CrossMeta)));
-    GACA_HIP_CHECK(hipMemset(h->d_cross_off.ptr, 0xff, nfar * rcap * sizeof(int64_t)));
-    GACA_HIP_CHECK(hipMemset(h->d_fib_off.ptr, 0xff, nfar * sizeof(int64_t)));
+    for (gaca_hmatrix *hh : H) {
+        hh->d_meta.alloc(ctx, nfar * sizeof(FarMeta));
+        hh->d_cmeta.alloc(ctx, nfar * rcap * sizeof(CrossMeta));
+        hh->d_cross_off.alloc(ctx, nfar * rcap * sizeof(int64_t));
+        hh->d_fib_off.alloc(ctx, nfar * sizeof(int64_t));
+    }
+    // per-block outputs, indexed by FarBlockDev::out_idx = operator * nfar + far block: the
+    // first operator's tables directly, or joint tables split at the end
+    DevBuf j_meta, j_cmeta, j_cross_off, j_fib_off;
+    if (nh > 1) {
+        j_meta.alloc(ctx, ntot * sizeof(FarMeta));
+        j_cmeta.alloc(ctx, ntot * rcap * sizeof(CrossMeta));
+        j_cross_off.alloc(ctx, ntot * rcap * sizeof(int64_t));
+        j_fib_off.alloc(ctx, ntot * sizeof(int64_t));
+    }
+    DevBuf &o_meta = nh > 1 ? j_meta : h->d_meta, &o_cmeta = nh > 1 ? j_cmeta : h->d_cmeta;
+    DevBuf &o_cross_off = nh > 1 ? j_cross_off : h->d_cross_off, &o_fib_off = nh > 1 ? j_fib_off : h->d_fib_off;
+    GACA_HIP_CHECK(hipMemset(o_meta.ptr, 0, ntot * sizeof(FarMeta)));
+    GACA_HIP_CHECK(hipMemset(o_cmeta.ptr, 0, ntot * rcap * sizeof(CrossMeta)));
+    GACA_HIP_CHECK(hipMemset(o_cross_off.ptr, 0xff, ntot * rcap * sizeof(int64_t)));
+    GACA_HIP_CHECK(hipMemset(o_fib_off.ptr, 0xff, ntot * sizeof(int64_t)));
     AcaParams P{};
     P.eps = p->opt.eps3d;
     P.eps_aca = p->opt.eps_aca;
@@ -848,16 +875,17 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
         P.tie = std::max(P.tie, 1e-4);
         P.delta = std::max(P.delta, 1e-6);
     }
-    h->eps_aca_used = P.eps_aca;
+    for (gaca_hmatrix *hh : H) hh->eps_aca_used = P.eps_aca;
     P.rcap = rcap;
-    P.kernel = h->kernel;
+    P.kernel = fk;
 
     // block descriptors, launch classes and memory estimates
-    std::vector<FarBlockDev> desc(nfar);
-    std::vector<int> kind(nfar);
+    std::vector<FarBlockDev> desc(ntot);
+    std::vector<int> kind(ntot);
     // memory estimate of a block in a batch with rg faces per block (pool slots, fibres and
     // Gram rows, current factors, expand partials, state)
-    auto est_of = [&](int64_t b, double rg) {
+    auto est_of = [&](int64_t gb, double rg) {
+        const int64_t b = gb / nh;
         const double m = (double)far[b][1], n = (double)far[b][3], mn = m * n;
         const double rho_max = std::min(m, n);
         const double tiles = far_kind((int)m, (int)n, mixed) == 3 ? std::ceil(m / 32.0) * std::ceil(n / 32.0) : 1.0;
@@ -878,7 +906,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
         d.c0 = (int32_t)far[b][2];
         d.n = n;
         d.rho_max = rho_max;
-        d.out_idx = (int32_t)b;
+        d.out_idx = (int32_t)b;   // operator 0; copies below for the others
         if (!p->synthetic && p->part.far_nodes.size() == far.size()) {
             // mixed scaling geometry from the cluster boxes
             const auto &ns = p->tree.nodes[p->part.far_nodes[b][0]];
@@ -897,8 +925,14 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             for (int k = 0; k < 3; ++k) kap += (double)d.Dh[k] * (double)d.Dh[k];
             d.kappa = (float)kap;
         }
-        desc[b] = d;
-        kind[b] = far_kind(m, n, mixed);
+        for (int w = 0; w < nh; ++w) {
+            FarBlockDev dw = d;
+            dw.out_idx = (int32_t)(w * nfar + b);
+            dw.kern = H[w]->kernel;
+            dw.which = w;
+            desc[nh * b + w] = dw;
+            kind[nh * b + w] = far_kind(m, n, mixed);
+        }
         const double mn = (double)m * n;
         // first guess of the factor storage (the arena grows by half when it runs short)
         factor_guess += std::min(mn * L, (double)std::min(rcap, 8) * std::min(rho_max, 16) * (m + n));
@@ -934,22 +968,25 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
     const int64_t mem_ns0 = g_mem_ns.load(), mem_calls0 = g_mem_calls.load();
 
     FarScratch &W = p->fsc;
-    size_t arena_used = 0, fib_used = 0;
-    auto start_arena = [&](GrowBuf &dst, GrowBuf &spare, size_t need) {
+    size_t arena_used[2] = {0, 0}, fib_used[2] = {0, 0};
+    auto start_arena = [&](GrowBuf &dst, GrowBuf *spare, size_t need) {
         {
             std::lock_guard<std::mutex> lk(p->spare_mu);
-            if (spare.ptr) dst.swap(spare);
+            for (int k = 0; k < 2 && !dst.ptr; ++k)
+                if (spare[k].ptr) dst.swap(spare[k]);
         }
         if (dst.ptr) dst.grow(ctx, need, 0, s0);
         else dst.start(ctx, need);
     };
-    start_arena(h->d_arena, p->spare_arena, (size_t)std::max(1.0e5, factor_guess) * es);
-    start_arena(h->d_fib, p->spare_fib,
-                (size_t)std::max<int64_t>(1024, nfar * (int64_t)std::min(rcap, 16) * L) * sizeof(double2));
+    for (gaca_hmatrix *hh : H) {
+        start_arena(hh->d_arena, p->spare_arena, (size_t)std::max(1.0e5, factor_guess) * es);
+        start_arena(hh->d_fib, p->spare_fib,
+                    (size_t)std::max<int64_t>(1024, nfar * (int64_t)std::min(rcap, 16) * L) * sizeof(double2));
+    }
     // algorithmic work model (flops; a complex multiply-add is 8): per quadrature point x
     // frequency the single layer costs 105 (distance 8, sqrt 13, exp 31, sincos 36,
     // 1/(4 pi r) 8, weight and accumulation 9), the double layer 113
-    const double f_eval = dense ? 0.0 : (h->kernel == 1 ? 113.0 : 105.0);
+    auto f_eval_of = [&](int kern) { return dense ? 0.0 : (kern == 1 ? 113.0 : 105.0); };
     const double qpe = h->kernel == 2 ? 36.0 : 6.0;
     double ms_phase[4] = {0, 0, 0, 0}, ms_kind[4] = {0, 0, 0, 0}, fl_phase[4] = {0, 0, 0, 0};
     double fl_kind[4] = {0, 0, 0, 0};
@@ -960,7 +997,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
 
     // batches of consecutive blocks whose estimate fits the memory free at their start; the
     // faces-per-block guess of the estimate follows what the previous batches used
-    for (int64_t bnext = 0; bnext < nfar;) {
+    for (int64_t bnext = 0; bnext < ntot;) {
         double budget = 0.0;
         {
             size_t fb = 0, tb = 0;
@@ -973,7 +1010,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             budget = std::max(64.0 * (1 << 20), std::min((double)p->opt.batch_bytes, 0.5 * (double)fb));
         }
         int64_t blast = bnext;
-        for (double acc = 0.0; blast < nfar;) {
+        for (double acc = 0.0; blast < ntot;) {
             const double e = est_of(blast, rguess);
             if (blast > bnext && acc + e > budget) break;
             acc += e;
@@ -1029,8 +1066,8 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             bd.map_chunk = W.map_chunk.as<int32_t>();
             bd.map_tile = W.map_tile.as<int32_t>();
             bd.status = W.status.as<int32_t>();
-            bd.meta = h->d_meta.as<FarMeta>();
-            bd.cmeta = h->d_cmeta.as<CrossMeta>();
+            bd.meta = o_meta.as<FarMeta>();
+            bd.cmeta = o_cmeta.as<CrossMeta>();
             bd.dense = dense;
             bd.mixed = mixed ? 1 : 0;
             bd.rcap = rcap;
@@ -1057,8 +1094,9 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             std::memcpy(W.h_copies.ptr, chunks.data(), chunks.size() * sizeof(FarCopy));
             GACA_HIP_CHECK(hipMemcpyAsync(W.copies.ptr, W.h_copies.ptr, chunks.size() * sizeof(FarCopy),
                                           hipMemcpyHostToDevice, cs));
-            launch_far_copy(batch_dev(), W.copies.as<FarCopy>(), (int)chunks.size(), h->d_arena.ptr,
-                            h->d_cross_off.as<int64_t>(), cs);
+            void *const arenas[2] = {h->d_arena.ptr, H[nh - 1]->d_arena.ptr};
+            launch_far_copy(batch_dev(), W.copies.as<FarCopy>(), (int)chunks.size(), arenas,
+                            o_cross_off.as<int64_t>(), cs);
             GACA_HIP_CHECK(hipGetLastError());
             ++n_launch;
             pending.clear();
@@ -1090,10 +1128,16 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             }
             grow_keep(ctx, W.hpool, (size_t)hused * es, (size_t)hprev * es, s0);
             grow_keep(ctx, W.fgpool, (size_t)fused * sizeof(double2), (size_t)fprev * sizeof(double2), s0);
+            // kind 3 first (large faces with a side above kMediumSide before the medium ones),
+            // then 2, 1, 0; larger faces first within a class
+            auto big = [&](int x) { return std::max(bdesc[x].m, bdesc[x].n) > kMediumSide; };
             std::stable_sort(active.begin(), active.end(), [&](int x, int y) {
                 if (kind[base + x] != kind[base + y]) return kind[base + x] > kind[base + y];
+                if (kind[base + x] == 3 && big(x) != big(y)) return big(x);
                 return (int64_t)bdesc[x].m * bdesc[x].n > (int64_t)bdesc[y].m * bdesc[y].n;
             });
+            int nbig = 0;
+            while (nbig < (int)active.size() && kind[base + active[nbig]] == 3 && big(active[nbig])) ++nbig;
             const int nact = (int)active.size();
             FarActive *ha = W.h_act.as<FarActive>();
             int64_t nchunk = 0, ntile = 0;
@@ -1116,7 +1160,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
                 cnt[kd]++;
                 ha[a] = A;
                 evals += (double)mn * qpe;
-                fl_face += (double)mn * (qpe * f_eval + 8.0 * ell_h[lb]);
+                fl_face += (double)mn * (qpe * f_eval_of(d.kern) + 8.0 * ell_h[lb]);
             }
             // small faces: one partial row each (their Gram row), after the expand tiles
             for (int a = cnt[3]; a < nact; ++a) ha[a].tile0 = ntile + (a - cnt[3]);
@@ -1137,25 +1181,43 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             const int first[4] = {cnt[3] + cnt[2] + cnt[1], cnt[3] + cnt[2], cnt[3], 0};
             launch_far_map(bd, dact, nact, nlarge, s0);
             GACA_HIP_CHECK(hipEventRecord(ev[EV_F0], s0));
-            launch_far_face(h->kernel, p->g, p->f, bd, dact, nchunk, s0);
+            launch_far_face(fk, p->g, p->f, bd, dact, nchunk, s0);
             GACA_HIP_CHECK(hipEventRecord(ev[EV_F1], s0));
             for (int k = 0; k < 3; ++k) GACA_HIP_CHECK(hipStreamWaitEvent(ks[k], ev[EV_F1], 0));
             if (copied)
                 for (int k = 1; k < 4; ++k) GACA_HIP_CHECK(hipStreamWaitEvent(ks[k], ev[EV_C], 0));
-            // large faces: 512 threads (measured best on the 3072-triangle cube, where the
-            // longest face bounds the phase, and on the 20480-triangle sphere)
+            // large faces: 512 threads and ~104 KB of LDS history, one face per CU (the
+            // longest face bounds the phase); medium faces (sides <= kMediumSide) 256 threads
+            // and 32 KB, several per CU, on the kind-2 stream, so that they do not hold whole
+            // CUs against the small-face kinds
             int tl = p->opt.threads_large;
             if (tl <= 0) tl = 512;
-            const int threads[4] = {p->opt.threads_small, 256, 512, tl};
+            const int ts = p->opt.threads_small;
             int nl = 0;
             for (int k = 3; k >= 0; --k) {
                 if (cnt[k] == 0) continue;
-                launch_far_aca(k, threads[k], P, bd, dact + first[k], cnt[k], ks[k]);
-                ++nl;
-                if (k < 3) {
-                    launch_far_gram_small(bd, dact + first[k], cnt[k], ks[k]);
+                if (k == 3) {
+                    launch_far_aca(3, tl, P, bd, dact, nbig, ks[3]);
+                    launch_far_aca(3, 256, P, bd, dact + nbig, cnt[3] - nbig, ks[2]);
+                    nl += (nbig > 0) + (cnt[3] > nbig);
+                    continue;
+                }
+                if (k == 0 && ts <= 64) {
+                    // one wave per face: faces with m n <= 576 (after the larger ones) hold
+                    // nine register entries per lane instead of sixteen
+                    int a = first[0];
+                    while (a < first[0] + cnt[0] && (int64_t)bdesc[ha[a].b].m * bdesc[ha[a].b].n > 576) ++a;
+                    launch_far_aca_small(1024, 64, P, bd, dact + first[0], a - first[0], ks[0]);
+                    launch_far_aca_small(576, 64, P, bd, dact + a, first[0] + cnt[0] - a, ks[0]);
+                    nl += (a > first[0]) + (a < first[0] + cnt[0]);
+                } else {
+                    const int mnmax = k == 0 ? 1024 : k == 1 ? 2304 : (mixed ? 8192 : 4096);
+                    launch_far_aca_small(mnmax, k == 0 ? ts : k == 1 ? 256 : 512, P, bd, dact + first[k],
+                                         cnt[k], ks[k]);
                     ++nl;
                 }
+                launch_far_gram_small(bd, dact + first[k], cnt[k], ks[k]);
+                ++nl;
             }
             GACA_HIP_CHECK(hipGetLastError());
             for (int k = 0; k < 4; ++k) GACA_HIP_CHECK(hipEventRecord(ev[EV_K0 + k], ks[k]));
@@ -1163,7 +1225,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             GACA_HIP_CHECK(hipEventRecord(ev[EV_J], s0));
             launch_far_expand(bd, dact, ntile, s0);
             GACA_HIP_CHECK(hipEventRecord(ev[EV_X], s0));
-            launch_far_tail(h->kernel, p->g, p->f, P, bd, dact, nact, nlarge, s0);
+            launch_far_tail(fk, p->g, p->f, P, bd, dact, nact, nlarge, s0);
             GACA_HIP_CHECK(hipGetLastError());
             GACA_HIP_CHECK(hipEventRecord(ev[EV_T], s0));
             GACA_HIP_CHECK(hipMemcpyAsync(W.h_status.ptr, W.status.ptr, nact * 2 * sizeof(int32_t),
@@ -1197,7 +1259,7 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             const int32_t *hs_ = W.h_status.as<int32_t>();
             std::vector<int> next;
             next.reserve(nact);
-            const size_t arena_before = arena_used;
+            const size_t arena_before[2] = {arena_used[0], arena_used[1]};
             for (int a = 0; a < nact; ++a) {
                 const int lb = ha[a].b;
                 const FarBlockDev &d = bdesc[lb];
@@ -1210,8 +1272,9 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
                     c.b = lb;
                     c.p = ell;
                     c.rho = rho;
-                    c.off = (int64_t)arena_used;
-                    arena_used += (size_t)rho * (d.m + d.n);
+                    c.which = d.which;
+                    c.off = (int64_t)arena_used[d.which];
+                    arena_used[d.which] += (size_t)rho * (d.m + d.n);
                     pending.push_back(c);
                     ell_h[lb] = ell + 1;
                     hcur[lb] = -1;
@@ -1229,37 +1292,40 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
                         fl_phase[1] += f;
                         fl_kind[kd] += f;
                     }
-                    fl_phase[3] += (double)L * qpe * f_eval + 16.0 * L * ell + 8.0 * (ell + 1.0) * (ell + 1.0);
+                    fl_phase[3] += (double)L * qpe * f_eval_of(d.kern) + 16.0 * L * ell + 8.0 * (ell + 1.0) * (ell + 1.0);
                     evals += (double)L * qpe;
                 } else {
                     fl_phase[3] += 8.0 * (double)ell * ell;
                 }
                 if (!(code & 2)) next.push_back(lb);
             }
-            if (arena_used > h->d_arena.bytes / es)
-                grow_keep(ctx, h->d_arena, arena_used * es, arena_before * es, s0);
+            for (int w = 0; w < nh; ++w)
+                if (arena_used[w] > H[w]->d_arena.bytes / es)
+                    grow_keep(ctx, H[w]->d_arena, arena_used[w] * es, arena_before[w] * es, s0);
             active.swap(next);
             ++iter;
         }
         flush_copies(s0);
         // fibres of the batch -> fibre arena, contiguous per block
         std::vector<FarGather> gth;
-        const size_t fib_before = fib_used;
+        const size_t fib_before[2] = {fib_used[0], fib_used[1]};
         for (int lb = 0; lb < nb; ++lb) {
             FarGather g{};
             g.b = lb;
             g.rank = ell_h[lb];
-            g.off = (int64_t)fib_used;
-            fib_used += (size_t)ell_h[lb] * L;
+            g.which = bdesc[lb].which;
+            g.off = (int64_t)fib_used[g.which];
+            fib_used[g.which] += (size_t)ell_h[lb] * L;
             gth.push_back(g);
         }
-        grow_keep(ctx, h->d_fib, std::max<size_t>(fib_used, 1) * sizeof(double2),
-                  fib_before * sizeof(double2), s0);
+        for (int w = 0; w < nh; ++w)
+            grow_keep(ctx, H[w]->d_fib, std::max<size_t>(fib_used[w], 1) * sizeof(double2),
+                      fib_before[w] * sizeof(double2), s0);
         std::memcpy(W.h_gathers.ptr, gth.data(), gth.size() * sizeof(FarGather));
         GACA_HIP_CHECK(hipMemcpyAsync(W.gathers.ptr, W.h_gathers.ptr, gth.size() * sizeof(FarGather),
                                       hipMemcpyHostToDevice, s0));
-        launch_far_gather(batch_dev(), W.gathers.as<FarGather>(), nb, h->d_fib.as<double2>(),
-                          h->d_fib_off.as<int64_t>(), s0);
+        double2 *const fibs[2] = {h->d_fib.as<double2>(), H[nh - 1]->d_fib.as<double2>()};
+        launch_far_gather(batch_dev(), W.gathers.as<FarGather>(), nb, fibs, o_fib_off.as<int64_t>(), s0);
         GACA_HIP_CHECK(hipGetLastError());
         ++n_launch;
         GACA_HIP_CHECK(hipStreamSynchronize(s0));
@@ -1275,17 +1341,18 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
             std::fprintf(stderr, "gaca far field: batch of blocks %lld..%lld of %lld done, %d iterations, "
                          "%.1f ms since the start (%.1f ms waiting for the device, %.1f ms in %lld memory "
                          "calls); factors %.2f GB, fibres %.2f GB, face pool %.2f GB, free %.2f GB\n",
-                         (long long)bt.first, (long long)bt.second, (long long)nfar, iter,
+                         (long long)bt.first, (long long)bt.second, (long long)ntot, iter,
                          wall_ms_since(t_entry), ms_wait, (g_mem_ns.load() - mem_ns0) / 1e6,
                          (long long)(g_mem_calls.load() - mem_calls0),
-                         arena_used * es / 1e9, fib_used * 16.0 / 1e9, W.hpool.bytes / 1e9, fb / 1e9);
+                         (arena_used[0] + arena_used[1]) * es / 1e9, (fib_used[0] + fib_used[1]) * 16.0 / 1e9,
+                         W.hpool.bytes / 1e9, fb / 1e9);
             std::fflush(stderr);
         }
         // give the pools' pages back between batches when memory is short (the arena needs
         // them; in-place pools regrow without copies).  Mapping fresh pages is slow (tens of
         // ms per GiB when the driver has to clear recently released memory), so pools stay
         // mapped while the free memory exceeds their size.
-        if (bnext < nfar) {
+        if (bnext < ntot) {
             size_t fb = 0, tb = 0;
             if (hipMemGetInfo(&fb, &tb) != hipSuccess) {
                 (void)hipGetLastError();
@@ -1313,28 +1380,20 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
     float span = 0.0f;
     GACA_HIP_CHECK(hipEventElapsedTime(&span, ev[EV_BEGIN], ev[EV_END]));
     const auto t_fin = std::chrono::steady_clock::now();
-    compact(ctx, h->d_arena, arena_used * es, s0);
-    compact(ctx, h->d_fib, fib_used * sizeof(double2), s0);
-    GACA_HIP_CHECK(hipMemcpy(h->meta.data(), h->d_meta.ptr, nfar * sizeof(FarMeta), hipMemcpyDeviceToHost));
-    GACA_HIP_CHECK(hipMemcpy(h->cmeta.data(), h->d_cmeta.ptr, nfar * rcap * sizeof(CrossMeta), hipMemcpyDeviceToHost));
-    GACA_HIP_CHECK(hipMemcpy(h->cross_off.data(), h->d_cross_off.ptr, nfar * rcap * sizeof(int64_t), hipMemcpyDeviceToHost));
-    GACA_HIP_CHECK(hipMemcpy(h->fib_off.data(), h->d_fib_off.ptr, nfar * sizeof(int64_t), hipMemcpyDeviceToHost));
-    gaca_stats &st = h->st;
-    st.ms_far_kernel = span;
-    st.n_far_launches = n_launch;
-    st.far_iters = iters_max;
-    st.far_kernel_evals = evals;
-    st.far_flops = 0.0;
-    for (int k = 0; k < 4; ++k) {
-        st.ms_far_phase[k] = ms_phase[k];
-        st.launches_phase[k] = launches_phase[k];
-        st.far_flops_phase[k] = fl_phase[k];
-        st.far_flops += fl_phase[k];
-    }
-    for (int k = 0; k < 4; ++k) {
-        st.ms_far_by_kind[k] = ms_kind[k];
-        st.launches_by_kind[k] = launches_kind[k];
-        st.far_flops_by_kind[k] = fl_kind[k];
+    if (nh > 1) {
+        // joint tables -> each operator's own (rows w * nfar ... of the joint tables)
+        for (int w = 0; w < nh; ++w) {
+            gaca_hmatrix *hh = H[w];
+            GACA_HIP_CHECK(hipMemcpyAsync(hh->d_meta.ptr, j_meta.as<FarMeta>() + w * nfar,
+                                          nfar * sizeof(FarMeta), hipMemcpyDeviceToDevice, s0));
+            GACA_HIP_CHECK(hipMemcpyAsync(hh->d_cmeta.ptr, j_cmeta.as<CrossMeta>() + w * nfar * rcap,
+                                          nfar * rcap * sizeof(CrossMeta), hipMemcpyDeviceToDevice, s0));
+            GACA_HIP_CHECK(hipMemcpyAsync(hh->d_cross_off.ptr, j_cross_off.as<int64_t>() + w * nfar * rcap,
+                                          nfar * rcap * sizeof(int64_t), hipMemcpyDeviceToDevice, s0));
+            GACA_HIP_CHECK(hipMemcpyAsync(hh->d_fib_off.ptr, j_fib_off.as<int64_t>() + w * nfar,
+                                          nfar * sizeof(int64_t), hipMemcpyDeviceToDevice, s0));
+        }
+        GACA_HIP_CHECK(hipStreamSynchronize(s0));
     }
     int wclk_khz = 0;
     if (hipDeviceGetAttribute(&wclk_khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess ||
@@ -1342,12 +1401,43 @@ static void run_far(gaca_hmatrix *h, const double2 *dense, const std::function<v
         (void)hipGetLastError();
         wclk_khz = 100000;
     }
-    int64_t tmax = 0;
-    for (const auto &mt : h->meta) tmax = std::max<int64_t>(tmax, mt.aca_ticks);
-    st.ms_far_aca_block_max = (double)tmax / wclk_khz;
-    st.ms_host_setup = ms_setup;
-    st.arena_in_place = h->d_arena.vmm ? 1 : 0;
-    st.ms_host_finish = wall_ms_since(t_fin);
+    for (int w = 0; w < nh; ++w) {
+        gaca_hmatrix *hh = H[w];
+        compact(ctx, hh->d_arena, arena_used[w] * es, s0);
+        compact(ctx, hh->d_fib, fib_used[w] * sizeof(double2), s0);
+        GACA_HIP_CHECK(hipMemcpy(hh->meta.data(), hh->d_meta.ptr, nfar * sizeof(FarMeta), hipMemcpyDeviceToHost));
+        GACA_HIP_CHECK(hipMemcpy(hh->cmeta.data(), hh->d_cmeta.ptr, nfar * rcap * sizeof(CrossMeta),
+                                 hipMemcpyDeviceToHost));
+        GACA_HIP_CHECK(hipMemcpy(hh->cross_off.data(), hh->d_cross_off.ptr, nfar * rcap * sizeof(int64_t),
+                                 hipMemcpyDeviceToHost));
+        GACA_HIP_CHECK(hipMemcpy(hh->fib_off.data(), hh->d_fib_off.ptr, nfar * sizeof(int64_t),
+                                 hipMemcpyDeviceToHost));
+        // timings and work of the shared launches (identical in every operator of a joint build)
+        gaca_stats &st = hh->st;
+        st.joint_build = nh;
+        st.ms_far_kernel = span;
+        st.n_far_launches = n_launch;
+        st.far_iters = iters_max;
+        st.far_kernel_evals = evals;
+        st.far_flops = 0.0;
+        for (int k = 0; k < 4; ++k) {
+            st.ms_far_phase[k] = ms_phase[k];
+            st.launches_phase[k] = launches_phase[k];
+            st.far_flops_phase[k] = fl_phase[k];
+            st.far_flops += fl_phase[k];
+        }
+        for (int k = 0; k < 4; ++k) {
+            st.ms_far_by_kind[k] = ms_kind[k];
+            st.launches_by_kind[k] = launches_kind[k];
+            st.far_flops_by_kind[k] = fl_kind[k];
+        }
+        int64_t tmax = 0;
+        for (const auto &mt : hh->meta) tmax = std::max<int64_t>(tmax, mt.aca_ticks);
+        st.ms_far_aca_block_max = (double)tmax / wclk_khz;
+        st.ms_host_setup = ms_setup;
+        st.arena_in_place = hh->d_arena.vmm ? 1 : 0;
+    }
+    for (gaca_hmatrix *hh : H) hh->st.ms_host_finish = wall_ms_since(t_fin);
 }
 
 static void fill_stats(gaca_hmatrix *h) {
@@ -1401,32 +1491,50 @@ static void fill_stats(gaca_hmatrix *h) {
     s.entries_near = (double)p->near_elems;
 }
 
-gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out) {
-    bool capped = false;
-    gaca_status rc = guarded([&] {
-        REQUIRE(p && out, "null argument");
+// Builds the operators `kernels` (one, or the collocation single and double layer) of p:
+// near fields on the context stream, far fields in one joint run.  Returns whether a rank
+// cap was hit.
+static bool build_ops(gaca_problem *p, const std::vector<gaca_kernel> &kernels,
+                      std::vector<std::unique_ptr<gaca_hmatrix>> &out) {
+    REQUIRE(!p->synthetic, "build needs a mesh problem");
+    REQUIRE(p->opt.precision == GACA_FP64 || p->opt.precision == GACA_MIXED, "bad precision");
+    for (gaca_kernel kernel : kernels) {
         REQUIRE(kernel == GACA_SLP || kernel == GACA_DLP, "bad kernel");
-        REQUIRE(!p->synthetic, "build needs a mesh problem");
-        REQUIRE(p->opt.precision == GACA_FP64 || p->opt.precision == GACA_MIXED, "bad precision");
         if (p->scheme == GACA_GALERKIN_P0 && kernel != GACA_SLP)
             throw Error{GACA_ERR_UNSUPPORTED, "Galerkin is available for the single layer only"};
-        gaca_context *ctx = p->ctx;
-        GACA_HIP_CHECK(hipSetDevice(ctx->device));
+    }
+    gaca_context *ctx = p->ctx;
+    GACA_HIP_CHECK(hipSetDevice(ctx->device));
+    const hipStream_t st = ctx->stream;
+    const bool mixed = p->opt.precision == GACA_MIXED;
+    const int nh = (int)kernels.size();
+    std::vector<gaca_hmatrix *> H;
+    out.clear();
+    for (gaca_kernel kernel : kernels) {
         auto h = std::make_unique<gaca_hmatrix>();
         h->p = p;
         h->kernel = p->kid(kernel);
         h->prec = p->opt.precision;
         h->rcap = std::max(1, std::min({p->L, p->opt.max_rank3d > 0 ? p->opt.max_rank3d : p->L, 256}));
-        const hipStream_t st = ctx->stream;
-        const bool mixed = h->prec == GACA_MIXED;
         // near field: FP64 quadrature, stored FP64 or (mixed) FP32
-        h->d_near.alloc(ctx, std::max<int64_t>(1, p->near_elems) *
-                                 (mixed ? sizeof(float2) : sizeof(double2)));
-        hipEvent_t ev[4];
-        for (auto &e : ev) GACA_HIP_CHECK(hipEventCreate(&e));
-        GACA_HIP_CHECK(hipEventRecord(ev[0], st));
-        auto near_work = [&] {
-            GACA_HIP_CHECK(hipEventRecord(ev[1], st));
+        h->d_near.alloc(ctx, std::max<int64_t>(1, p->near_elems) * (mixed ? sizeof(float2) : sizeof(double2)));
+        H.push_back(h.get());
+        out.push_back(std::move(h));
+    }
+    // events: begin, then per operator near start / near end, then end
+    std::vector<hipEvent_t> ev(2 + 2 * nh);
+    for (auto &e : ev) GACA_HIP_CHECK(hipEventCreate(&e));
+    struct EvGuard {
+        std::vector<hipEvent_t> &e;
+        ~EvGuard() {
+            for (auto x : e) (void)hipEventDestroy(x);
+        }
+    } ev_guard{ev};
+    GACA_HIP_CHECK(hipEventRecord(ev[0], st));
+    auto near_work = [&] {
+        for (int w = 0; w < nh; ++w) {
+            gaca_hmatrix *h = H[w];
+            GACA_HIP_CHECK(hipEventRecord(ev[1 + 2 * w], st));
             double2 *n64 = mixed ? nullptr : h->d_near.as<double2>();
             float2 *n32 = mixed ? h->d_near.as<float2>() : nullptr;
             for (int t = 0; t < kNumTiers; ++t) {
@@ -1434,39 +1542,70 @@ gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out) 
                     launch_near_galerkin(t, p->g, p->q, p->f, p->d_pairs[t].as<NearPair>(),
                                          p->npairs[t], p->d_nblocks.as<NearBlockDev>(), n64, n32, st);
                 else if (t < 4)
-                    launch_near(kernel, t, p->g, p->q, p->f, p->d_pairs[t].as<NearPair>(),
+                    launch_near(kernels[w], t, p->g, p->q, p->f, p->d_pairs[t].as<NearPair>(),
                                 p->npairs[t], p->d_nblocks.as<NearBlockDev>(), n64, n32, st);
             }
             GACA_HIP_CHECK(hipGetLastError());
-            GACA_HIP_CHECK(hipEventRecord(ev[2], st));
-        };
-        run_far(h.get(), nullptr, near_work);
-        GACA_HIP_CHECK(hipEventRecord(ev[3], st));
-        GACA_HIP_CHECK(hipEventSynchronize(ev[3]));
-        float ms_near = 0, ms_total = 0;
-        GACA_HIP_CHECK(hipEventElapsedTime(&ms_near, ev[1], ev[2]));
-        GACA_HIP_CHECK(hipEventElapsedTime(&ms_total, ev[0], ev[3]));
-        for (auto &e : ev) (void)hipEventDestroy(e);
-        fill_stats(h.get());
+            GACA_HIP_CHECK(hipEventRecord(ev[2 + 2 * w], st));
+        }
+    };
+    run_far(H, nullptr, near_work);
+    GACA_HIP_CHECK(hipEventRecord(ev[1 + 2 * nh], st));
+    GACA_HIP_CHECK(hipEventSynchronize(ev[1 + 2 * nh]));
+    float ms_total = 0;
+    GACA_HIP_CHECK(hipEventElapsedTime(&ms_total, ev[0], ev[1 + 2 * nh]));
+    bool capped = false;
+    for (int w = 0; w < nh; ++w) {
+        gaca_hmatrix *h = H[w];
+        float ms_near = 0;
+        GACA_HIP_CHECK(hipEventElapsedTime(&ms_near, ev[1 + 2 * w], ev[2 + 2 * w]));
+        fill_stats(h);
         h->st.ms_near = ms_near;
         h->st.ms_near_kernel = ms_near;
-        {
-            const double le = p->f.L_eval;
-            const double ng2 = (double)p->opt.n_galerkin * p->opt.n_galerkin;
-            double qp[kNumTiers] = {6.0, 16.0, 64.0, kernel == 0 ? 3.0 * p->opt.n_duffy * p->opt.n_duffy : 0.0, 0.0, 0.0};
-            if (p->scheme == GACA_GALERKIN_P0) {
-                const double g6[kNumTiers] = {36.0, 256.0, 3.0 * ng2 * ng2, 3.0 * ng2 * ng2,
-                                              3.0 * ng2 * ng2, 6.0 * kGalerkinNTheta};
-                for (int t = 0; t < kNumTiers; ++t) qp[t] = g6[t];
-            }
-            double evn = 0.0;
-            for (int t = 0; t < kNumTiers; ++t) evn += (double)p->npairs[t] * le * qp[t];
-            h->st.near_kernel_evals = evn;
+        const double le = p->f.L_eval;
+        const double ng2 = (double)p->opt.n_galerkin * p->opt.n_galerkin;
+        double qp[kNumTiers] = {6.0, 16.0, 64.0, kernels[w] == 0 ? 3.0 * p->opt.n_duffy * p->opt.n_duffy : 0.0,
+                                0.0, 0.0};
+        if (p->scheme == GACA_GALERKIN_P0) {
+            const double g6[kNumTiers] = {36.0, 256.0, 3.0 * ng2 * ng2, 3.0 * ng2 * ng2,
+                                          3.0 * ng2 * ng2, 6.0 * kGalerkinNTheta};
+            for (int t = 0; t < kNumTiers; ++t) qp[t] = g6[t];
         }
+        double evn = 0.0;
+        for (int t = 0; t < kNumTiers; ++t) evn += (double)p->npairs[t] * le * qp[t];
+        h->st.near_kernel_evals = evn;
         h->st.ms_far = h->st.ms_far_kernel;
         h->st.ms_total = ms_total;
-        capped = h->st.n_capped > 0;
-        *out = h.release();
+        capped = capped || h->st.n_capped > 0;
+    }
+    return capped;
+}
+
+gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out) {
+    bool capped = false;
+    gaca_status rc = guarded([&] {
+        REQUIRE(p && out, "null argument");
+        std::vector<std::unique_ptr<gaca_hmatrix>> hs;
+        capped = build_ops(p, {kernel}, hs);
+        *out = hs[0].release();
+    });
+    if (rc == GACA_OK && capped) {
+        set_error("rank cap hit in at least one block");
+        return GACA_ERR_NOT_CONVERGED;
+    }
+    return rc;
+}
+
+gaca_status gaca_build_both(gaca_problem *p, gaca_hmatrix **slp_out, gaca_hmatrix **dlp_out) {
+    bool capped = false;
+    gaca_status rc = guarded([&] {
+        REQUIRE(p && slp_out && dlp_out, "null argument");
+        if (p->scheme == GACA_GALERKIN_P0)
+            throw Error{GACA_ERR_UNSUPPORTED, "Galerkin is available for the single layer only"};
+        std::vector<std::unique_ptr<gaca_hmatrix>> hs;
+        capped = build_ops(p, {GACA_SLP, GACA_DLP}, hs);
+        *slp_out = hs[0].release();
+        *dlp_out = hs[1].release();
     });
     if (rc == GACA_OK && capped) {
         set_error("rank cap hit in at least one block");
@@ -1486,13 +1625,17 @@ gaca_status gaca_hmatrix_destroy(gaca_hmatrix *h) {
         }
         std::lock_guard<std::mutex> lk(p->spare_mu);
         bool synced = false;
-        auto donate = [&](GrowBuf &src, GrowBuf &spare) {
-            if (!src.vmm || !src.ptr || spare.ptr || src.bytes > tb / 8) return;
-            if (!synced) {
-                (void)hipDeviceSynchronize();   // no kernel may still use the arena
-                synced = true;
-            }
-            spare.swap(src);
+        auto donate = [&](GrowBuf &src, GrowBuf *spare) {
+            if (!src.vmm || !src.ptr || src.bytes > tb / 8) return;
+            for (int k = 0; k < 2; ++k)
+                if (!spare[k].ptr) {
+                    if (!synced) {
+                        (void)hipDeviceSynchronize();   // no kernel may still use the arena
+                        synced = true;
+                    }
+                    spare[k].swap(src);
+                    return;
+                }
         };
         donate(h->d_arena, p->spare_arena);
         donate(h->d_fib, p->spare_fib);
@@ -1529,6 +1672,7 @@ gaca_status gaca_hmatrix_block_info(const gaca_hmatrix *h, int64_t idx, int64_t 
         info[5] = mt.sum_rho;
         info[6] = mt.capped;
         info[7] = mt.zero_faces;
+        info[8] = mt.aca_ticks;
     });
 }
 
@@ -1985,7 +2129,7 @@ gaca_status gaca_compress_tensor(gaca_context *ctx, const void *dev_tensor, int6
         h->prec = GACA_FP64;
         h->rcap = std::max(1, std::min({L, p->opt.max_rank3d > 0 ? p->opt.max_rank3d : L, 256}));
         GACA_HIP_CHECK(hipSetDevice(ctx->device));
-        run_far(h.get(), reinterpret_cast<const double2 *>(dev_tensor), [] {});
+        run_far({h.get()}, reinterpret_cast<const double2 *>(dev_tensor), [] {});
         fill_stats(h.get());
         capped = h->st.n_capped > 0;
         h->owned_problem = std::move(p);

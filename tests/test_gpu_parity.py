@@ -266,3 +266,30 @@ def test_concurrent_builds_match_sequential():
             es, ep = hs.export_block(b), hp.export_block(b)
             assert es["rank"] == ep["rank"]
             np.testing.assert_array_equal(hs.reconstruct_block(b), hp.reconstruct_block(b))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_joint_build_matches_separate(precision):
+    """gaca_build_both gives bitwise the operators of two separate builds (the blocks of both
+    operators share the far-field launches; every block's arithmetic is unchanged)."""
+    import torch
+    from inputs import random_rhs
+    _, prob, (xyz, tri, s) = gpu_problem("cube768", precision=precision)
+    sep = [prob.build("slp"), prob.build("dlp")]
+    joint = prob.build_both()
+    far, _ = prob.blocks()
+    X = torch.from_numpy(random_rhs(len(s), tri.shape[0], 3, seed=7)).cuda()
+    for hs, hj in zip(sep, joint):
+        ss, sj = hs.stats(), hj.stats()
+        assert sj["joint_build"] == 2 and ss["joint_build"] == 1
+        for key in ("n_far", "rank_min", "rank_max", "face_rank_max", "entries_face",
+                    "entries_fibre", "n_capped", "n_zero_blocks"):
+            assert ss[key] == sj[key], key
+        for b in range(0, far.shape[0], 5):
+            es, ej = hs.export_block(b), hj.export_block(b)
+            assert es["rank"] == ej["rank"]
+            np.testing.assert_array_equal(hs.reconstruct_block(b), hj.reconstruct_block(b))
+        ys, yj = hs.apply(X, mode="sum"), hj.apply(X, mode="sum")
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(ys.cpu().numpy(), yj.cpu().numpy())
+    log(f"joint build ({precision}) matches separate builds on {far.shape[0]} far blocks")
