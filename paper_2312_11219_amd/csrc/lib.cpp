@@ -339,7 +339,7 @@ struct FarScratch {
     DevBuf blk, state, coef, hs, fs, usedk, uw, part, act, map_chunk, map_tile, status, copies,
         gathers;
     GrowBuf hpool, fgpool;
-    PinnedBuf h_act, h_status, h_copies, h_gathers;
+    PinnedBuf h_act, h_status, h_copies, h_gathers, h_blk;
 };
 
 template <class F>
@@ -964,19 +964,21 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
     GACA_HIP_CHECK(hipEventRecord(ev[EV_BEGIN], s0));
     const double ms_setup = wall_ms_since(t_entry);
     double ms_wait = 0.0;   // host time blocked on the per-iteration status read-back
+    double ms_prep = 0.0, ms_launch = 0.0;   // host time preparing / enqueuing iterations
     g_mem_verbose = p->opt.verbose;
     const int64_t mem_ns0 = g_mem_ns.load(), mem_calls0 = g_mem_calls.load();
 
     FarScratch &W = p->fsc;
     size_t arena_used[2] = {0, 0}, fib_used[2] = {0, 0};
+    // a spare arena (the same problem's last build needed about its size) is taken as it is
+    // and grows only when this build outgrows it; otherwise a new one starts at `need`
     auto start_arena = [&](GrowBuf &dst, GrowBuf *spare, size_t need) {
         {
             std::lock_guard<std::mutex> lk(p->spare_mu);
             for (int k = 0; k < 2 && !dst.ptr; ++k)
                 if (spare[k].ptr) dst.swap(spare[k]);
         }
-        if (dst.ptr) dst.grow(ctx, need, 0, s0);
-        else dst.start(ctx, need);
+        if (!dst.ptr) dst.start(ctx, need);
     };
     for (gaca_hmatrix *hh : H) {
         start_arena(hh->d_arena, p->spare_arena, (size_t)std::max(1.0e5, factor_guess) * es);
@@ -1026,7 +1028,12 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             d.uw_off = uw_total;
             uw_total += (int64_t)d.rho_max * (d.m + d.n);
         }
-        W.blk.upload(ctx, bdesc);
+        // upload without reallocating: a free would wait for the near field running beside
+        ensure(ctx, W.blk, bdesc.size() * sizeof(FarBlockDev));
+        W.h_blk.ensure(bdesc.size() * sizeof(FarBlockDev));
+        std::memcpy(W.h_blk.ptr, bdesc.data(), bdesc.size() * sizeof(FarBlockDev));
+        GACA_HIP_CHECK(hipMemcpyAsync(W.blk.ptr, W.h_blk.ptr, bdesc.size() * sizeof(FarBlockDev),
+                                      hipMemcpyHostToDevice, s0));
         ensure(ctx, W.state, nb * sizeof(FarStateDev));
         ensure(ctx, W.coef, (size_t)nb * rcap * sizeof(double2));
         ensure(ctx, W.hs, (size_t)nb * rcap * sizeof(int64_t));
@@ -1104,6 +1111,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
         };
 
         while (!active.empty()) {
+            const auto t_it = std::chrono::steady_clock::now();
             // slots of this iteration's faces (a zero face keeps its slots for the next one)
             const int64_t hprev = hused, fprev = fused;
             for (int lb : active) {
@@ -1139,6 +1147,8 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             int nbig = 0;
             while (nbig < (int)active.size() && kind[base + active[nbig]] == 3 && big(active[nbig])) ++nbig;
             const int nact = (int)active.size();
+            ms_prep += wall_ms_since(t_it);
+            const auto t_launch = std::chrono::steady_clock::now();
             FarActive *ha = W.h_act.as<FarActive>();
             int64_t nchunk = 0, ntile = 0;
             int cnt[4] = {0, 0, 0, 0};
@@ -1228,6 +1238,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             launch_far_tail(fk, p->g, p->f, P, bd, dact, nact, nlarge, s0);
             GACA_HIP_CHECK(hipGetLastError());
             GACA_HIP_CHECK(hipEventRecord(ev[EV_T], s0));
+            ms_launch += wall_ms_since(t_launch);
             GACA_HIP_CHECK(hipMemcpyAsync(W.h_status.ptr, W.status.ptr, nact * 2 * sizeof(int32_t),
                                           hipMemcpyDeviceToHost, s0));
             {
@@ -1339,10 +1350,11 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             size_t fb = 0, tb = 0;
             if (hipMemGetInfo(&fb, &tb) != hipSuccess) (void)hipGetLastError();
             std::fprintf(stderr, "gaca far field: batch of blocks %lld..%lld of %lld done, %d iterations, "
-                         "%.1f ms since the start (%.1f ms waiting for the device, %.1f ms in %lld memory "
-                         "calls); factors %.2f GB, fibres %.2f GB, face pool %.2f GB, free %.2f GB\n",
+                         "%.1f ms since the start (%.1f ms waiting for the device, %.1f ms preparing and "
+                         "%.1f ms enqueuing iterations, %.1f ms in %lld memory calls); factors %.2f GB, "
+                         "fibres %.2f GB, face pool %.2f GB, free %.2f GB\n",
                          (long long)bt.first, (long long)bt.second, (long long)ntot, iter,
-                         wall_ms_since(t_entry), ms_wait, (g_mem_ns.load() - mem_ns0) / 1e6,
+                         wall_ms_since(t_entry), ms_wait, ms_prep, ms_launch, (g_mem_ns.load() - mem_ns0) / 1e6,
                          (long long)(g_mem_calls.load() - mem_calls0),
                          (arena_used[0] + arena_used[1]) * es / 1e9, (fib_used[0] + fib_used[1]) * 16.0 / 1e9,
                          W.hpool.bytes / 1e9, fb / 1e9);
