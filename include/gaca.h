@@ -115,9 +115,11 @@ typedef struct {
     double ms_far_phase[4];       /* sum of launch durations (HIP events on the launch stream) */
     int32_t launches_phase[4];
     double far_flops_phase[4];    /* algorithmic flops of the phase */
-    /* aca phase by launch class: 0 m n <= 1024 and sides <= 64 (LDS, 64 threads), 1 m n <=
-     * 2304 and sides <= 96 (LDS, 256 threads), 2 m n <= 4096 (FP64) or 8192 (mixed) and
-     * sides <= 128 (LDS, 512 threads), 3 larger (HBM, 256 to 1024 threads) */
+    /* aca phase by launch class (device time of the class's launches on its stream): 0 m n <= 1024 and sides <= 64 (registers, 128 or 64 threads),
+     * 1 m n <= 2304 and sides <= 96 (registers, 256 threads), 2 m n <= 4096 (FP64) or 8192
+     * (mixed) and sides <= 128 (registers, 512 threads) together with the larger faces whose
+     * sides are <= 128 (R in HBM, 256 threads), 3 the faces with a side above 128 (R in HBM,
+     * 512 threads by default) */
     double ms_far_by_kind[4];
     int32_t launches_by_kind[4];
     double far_flops_by_kind[4];  /* algorithmic flops of the class's face-ACA launches */
@@ -212,7 +214,8 @@ gaca_status gaca_hmatrix_near_export(const gaca_hmatrix *h, int64_t idx, double 
 
 /* Apply (eq. product).  X: device pointer, [L][M][nrhs] complex in ORIGINAL element order;
  * Y: device pointer, [M][nrhs] (SUM) or [L][M][nrhs] (PER_FREQ).  dtype GACA_C128 runs the
- * FP64 apply, GACA_C64 the FP32 apply.  Asynchronous on `hip_stream` (NULL: context
+ * FP64 apply, GACA_C64 the FP32 apply (SUM mode with nrhs >= 16: products on the matrix
+ * cores, v_mfma_f32_16x16x4f32, FP32 sums).  Asynchronous on `hip_stream` (NULL: context
  * stream); X, Y are caller-owned; the library uses internal workspace sized at the
  * first call for this nrhs. */
 gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, const void *X,

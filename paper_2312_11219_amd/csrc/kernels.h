@@ -141,6 +141,7 @@ struct ApplyDev {
 // Matrix-core apply (SUM mode, complex64 right-hand sides), csrc/apply_mfma.hip.
 constexpr int kMfmaMaxSumRho = 4096;   // sum of face ranks of one far block
 constexpr int kMfmaMaxNearCols = 1024; // columns of one near block
+constexpr int kMfmaMinRhs = 16;        // fewer right-hand sides take the VALU apply
 // T = F X for the far blocks that share one column cluster tau: their fibre rows are
 // stacked (rows of 32 per tile), so one slab X[:, tau, chunk] serves all of them.
 struct MfmaTGroup {

@@ -952,7 +952,8 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
     hipStream_t s0 = p->far_streams[0];
     // the aca phase of kind k runs on ks[k] (kind 3, the large faces, on the main far stream)
     const hipStream_t ks[4] = {p->far_streams[3], p->far_streams[2], p->far_streams[1], s0};
-    enum { EV_BEGIN, EV_END, EV_F0, EV_F1, EV_K0, EV_K1, EV_K2, EV_K3, EV_J, EV_X, EV_T, EV_C, EV_N };
+    enum { EV_BEGIN, EV_END, EV_F0, EV_F1, EV_K0, EV_K1, EV_K2, EV_K3, EV_S0, EV_S1, EV_S2, EV_S3, EV_J, EV_X,
+           EV_T, EV_C, EV_N };
     hipEvent_t ev[EV_N];
     for (auto &e : ev) GACA_HIP_CHECK(hipEventCreate(&e));
     struct EvGuard {
@@ -1203,6 +1204,8 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             int tl = p->opt.threads_large;
             if (tl <= 0) tl = 512;
             const int ts = p->opt.threads_small;
+            // class k's launches run between EV_S0 + k and EV_K0 + k on ks[k] (after its waits)
+            for (int k = 0; k < 4; ++k) GACA_HIP_CHECK(hipEventRecord(ev[EV_S0 + k], ks[k]));
             int nl = 0;
             for (int k = 3; k >= 0; --k) {
                 if (cnt[k] == 0) continue;
@@ -1256,9 +1259,12 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             ms_phase[1] += elapsed(EV_F1, EV_J);
             ms_phase[2] += elapsed(EV_J, EV_X);
             ms_phase[3] += elapsed(EV_X, EV_T);
+            // launch classes by stream: 0, 1, 2 (kind 2 and the medium large faces), 3 (the
+            // large faces with a side above kMediumSide)
+            const int ccls[4] = {cnt[0], cnt[1], cnt[2] + cnt[3] - nbig, nbig};
             for (int k = 0; k < 4; ++k)
-                if (cnt[k]) {
-                    ms_kind[k] += elapsed(EV_F1, EV_K0 + k);
+                if (ccls[k]) {
+                    ms_kind[k] += elapsed(EV_S0 + k, EV_K0 + k);
                     launches_kind[k] += 1;
                 }
             launches_phase[0] += 1;
@@ -1296,7 +1302,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                     if (kd == 3) {
                         const double f = 8.0 * (d.m + d.n) * (double)rho * (rho - 1.0);
                         fl_phase[1] += f;
-                        fl_kind[3] += f;
+                        fl_kind[std::max(d.m, d.n) > kMediumSide ? 3 : 2] += f;
                         fl_phase[2] += 8.0 * mn * (rho + ell);
                     } else {
                         const double f = 8.0 * mn * (2.0 * rho + ell);
@@ -2028,7 +2034,10 @@ gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, cons
         const int L = p->L;
         const int64_t M = p->M;
         const size_t xs = dtype == GACA_C64 ? sizeof(float2) : sizeof(double2);
-        const bool mfma = mode == GACA_APPLY_SUM && dtype == GACA_C64 && mfma_supported(h);
+        // matrix cores from kMfmaMinRhs right-hand sides on (below, their 16-column tiles are
+        // mostly padding and the VALU apply is faster)
+        const bool mfma = mode == GACA_APPLY_SUM && dtype == GACA_C64 && nrhs >= kMfmaMinRhs &&
+                          mfma_supported(h);
         if (!mfma && (h->ws_nrhs != nrhs || h->ws_mode != (int)mode || h->ws_dtype != (int)dtype))
             alloc_apply_workspace(h, mode, nrhs, dtype);
         ApplyDev a{};
