@@ -22,6 +22,7 @@ namespace gaca {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kFold = 256;
+constexpr int kSlicesPerStage = 1;   // K slices of 16 staged per barrier pair in kloop
 
 __device__ __forceinline__ float2 to_f2(float2 v) { return v; }
 __device__ __forceinline__ float2 to_f2(double2 v) { return make_float2((float)v.x, (float)v.y); }
@@ -218,16 +219,74 @@ __global__ void __launch_bounds__(256)
     });
 }
 
+// One K loop of nslice slices of 16 on the matrix cores, software-pipelined: the operands of
+// the next pair of slices are loaded into registers while the matrix cores work on the
+// current pair (staged in LDS as As[k][32 rows], Bs[k][TN columns]).  pre(s) gives what
+// slice s needs once per slice; ga(info, r, t) and gb(info, t, c) return its A and B
+// elements (zero outside the operand).  KMAJOR_A: consecutive threads load consecutive t of
+// one row (row-major A), else consecutive rows.  nk counts the K elements in seg since its
+// last fold into acc; seg is folded once nk reaches kFold (the caller folds at the end of
+// a block).
+template <int TN, bool KMAJOR_A, class PRE, class GA, class GB>
+__device__ __forceinline__ void kloop(CTile<TN> &acc, CTile<TN> &seg, int &nk, float2 *As, float2 *Bs,
+                                      int nslice, const PRE &pre, const GA &ga, const GB &gb) {
+    constexpr int PA = 16 * 32 / 256, PB = 16 * TN / 256, SP = kSlicesPerStage;
+    const int tid = threadIdx.x;
+    float2 ra[SP][PA], rb[SP][PB];
+    auto load = [&](int s) {
+#pragma unroll
+        for (int h = 0; h < SP; ++h) {
+            const int ss = s + h;
+            const bool ok = ss < nslice;
+            const auto info = pre(ok ? ss : 0);
+#pragma unroll
+            for (int i = 0; i < PA; ++i) {
+                const int idx = tid + 256 * i;
+                const int r = KMAJOR_A ? idx >> 4 : idx & 31, t = KMAJOR_A ? idx & 15 : idx >> 5;
+                ra[h][i] = ok ? ga(info, r, t) : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int i = 0; i < PB; ++i) {
+                const int idx = tid + 256 * i;
+                rb[h][i] = ok ? gb(info, idx / TN, idx % TN) : make_float2(0.f, 0.f);
+            }
+        }
+    };
+    load(0);
+    for (int s = 0; s < nslice; s += SP) {
+        if (nk >= kFold) {
+            acc.fold(seg);
+            nk = 0;
+        }
+        nk += 16 * SP;
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < SP; ++h) {
+#pragma unroll
+            for (int i = 0; i < PA; ++i) {
+                const int idx = tid + 256 * i;
+                const int r = KMAJOR_A ? idx >> 4 : idx & 31, t = KMAJOR_A ? idx & 15 : idx >> 5;
+                As[h * 16 * 32 + t * 32 + r] = ra[h][i];
+            }
+#pragma unroll
+            for (int i = 0; i < PB; ++i) Bs[h * 16 * TN + tid + 256 * i] = rb[h][i];
+        }
+        __syncthreads();
+        if (s + SP < nslice) load(s + SP);
+        seg.step(As, Bs);
+        if (SP > 1 && s + 1 < nslice) seg.step(As + 16 * 32, Bs + 16 * TN);
+    }
+}
+
 // Y rows of one leaf (row tile of 32) for one column tile: near blocks and far blocks of
-// the leaf, one K stream.
+// the leaf, one K stream per block.
 template <class FacT, class NearT>
 __global__ void __launch_bounds__(256)
     apply_leaf_mfma_kernel(ApplyDev a, MfmaApplyDev d, const float2 *X, const float2 *Z,
                            float2 *Y) {
     constexpr int TN = 64;
-    __shared__ float2 As[16 * 32];
-    __shared__ float2 Bs[16 * TN];
-    __shared__ int64_t qaddr[kMfmaMaxSumRho];
+    __shared__ float2 As[kSlicesPerStage * 16 * 32];
+    __shared__ float2 Bs[kSlicesPerStage * 16 * TN];
     __shared__ int64_t xrow[kMfmaMaxNearCols];
     const int leaf = blockIdx.x;
     const int lr0 = a.leaf_r0[leaf] + 32 * blockIdx.z, lm = min(32, a.leaf_m[leaf] - 32 * (int)blockIdx.z);
@@ -238,59 +297,61 @@ __global__ void __launch_bounds__(256)
     const NearT *nearv = a.near64 ? reinterpret_cast<const NearT *>(a.near64)
                                   : reinterpret_cast<const NearT *>(a.near32);
     const FacT *arena = reinterpret_cast<const FacT *>(a.arena);
+    const int ncol = d.ncur - c0;
     CTile<TN> acc, seg;
     acc.zero();
     seg.zero();
     for (int e = a.leaf_near_ptr[leaf]; e < a.leaf_near_ptr[leaf + 1]; ++e) {
         const NearBlockDev nb = a.nblocks[a.leaf_near_idx[e]];
         const int ro = lr0 - nb.r0, n = nb.n;
-        const int K = L * n;
+        const int K = L * n, nj = (n + 15) >> 4;
         const NearT *A0 = nearv + nb.off + (int64_t)ro * K;
-        // K in slices of 16 columns j at one frequency k: no index division per element
+        const float2 *Xc = X + d.c0 + c0;
         __syncthreads();
         for (int j = threadIdx.x; j < n; j += 256) xrow[j] = a.perm[nb.c0 + j] * (int64_t)d.ldx;
-        int steps = 0;
-        for (int k = 0; k < L; ++k)
-            for (int j0 = 0; j0 < n; j0 += 16) {
-                if (steps > 0 && steps % (kFold / 16) == 0) acc.fold(seg);
-                ++steps;
-                __syncthreads();
-                const int kb = k * n + j0;
-                stage_a<true>(As, 0, lm, min(16, n - j0), [&](int r, int t) {
-                    return to_f2(A0[(int64_t)r * K + kb + t]);
-                });
-                const float2 *Xk = X + (int64_t)k * M * d.ldx + d.c0 + c0;
-                stage_b<TN>(Bs, 0, min(16, n - j0), d.ncur - c0, [&](int t, int c) {
-                    return Xk[xrow[j0 + t] + c];
-                });
-                __syncthreads();
-                seg.step(As, Bs);
-            }
+        __syncthreads();
+        // slice s: frequency k = s / nj, columns j0 = 16 (s mod nj) + [0, 16)
+        struct NearSlice {
+            const NearT *a;      // A row 0 at column (k, j0)
+            const float2 *x;     // X_k
+            int j0;
+        };
+        int nk = 0;
+        kloop<TN, true>(acc, seg, nk, As, Bs, L * nj,
+            [&](int s) {
+                const int k = s / nj, j0 = (s - k * nj) << 4;
+                return NearSlice{A0 + (int64_t)k * n + j0, Xc + (int64_t)k * M * d.ldx, j0};
+            },
+            [&](const NearSlice &S, int r, int t) {
+                return (r < lm && S.j0 + t < n) ? to_f2(S.a[(int64_t)r * K + t]) : make_float2(0.f, 0.f);
+            },
+            [&](const NearSlice &S, int t, int c) {
+                return (S.j0 + t < n && c < ncol) ? S.x[xrow[S.j0 + t] + c] : make_float2(0.f, 0.f);
+            });
         acc.fold(seg);
     }
     for (int e = a.leaf_far_ptr[leaf]; e < a.leaf_far_ptr[leaf + 1]; ++e) {
         const int b = a.leaf_far_idx[e];
         const int mb = a.far4[4 * b + 1], ro = lr0 - a.far4[4 * b];
         const int rank = a.meta[b].rank;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int q = 0;
-            for (int l = 0; l < rank; ++l) {
-                const CrossMeta cm = a.cmeta[(int64_t)b * a.rcap + l];
-                const int64_t base = a.cross_off[(int64_t)b * a.rcap + l];
-                for (int t = 0; t < cm.rho && q < kMfmaMaxSumRho; ++t, ++q) qaddr[q] = base + (int64_t)t * mb + ro;
-            }
-        }
-        __syncthreads();
-        const int K = min(d.sum_rho[b], kMfmaMaxSumRho);
-        const float2 *Zb = Z + d.z_off[b];
-        for (int k0 = 0; k0 < K; k0 += 16) {
-            if (k0 > 0 && k0 % kFold == 0) acc.fold(seg);
-            __syncthreads();
-            stage_a<false>(As, k0, lm, K, [&](int r, int q) { return to_f2(arena[qaddr[q] + r]); });
-            stage_b<TN>(Bs, k0, K, nrc - c0, [&](int q, int c) { return Zb[(int64_t)q * nrc + c0 + c]; });
-            __syncthreads();
-            seg.step(As, Bs);
+        const float2 *Zb = Z + d.z_off[b] + c0;
+        int q0 = 0, nk = 0;
+        for (int l = 0; l < rank && q0 < kMfmaMaxSumRho; ++l) {
+            const CrossMeta cm = a.cmeta[(int64_t)b * a.rcap + l];
+            const FacT *U = arena + a.cross_off[(int64_t)b * a.rcap + l] + ro;   // rho_l x mb
+            const int rho = min(cm.rho, kMfmaMaxSumRho - q0);
+            const float2 *Zl = Zb + (int64_t)q0 * nrc;
+            kloop<TN, false>(acc, seg, nk, As, Bs, (rho + 15) >> 4,
+                [&](int s) { return s << 4; },
+                [&](int q0s, int r, int t) {
+                    const int q = q0s + t;
+                    return (r < lm && q < rho) ? to_f2(U[(int64_t)q * mb + r]) : make_float2(0.f, 0.f);
+                },
+                [&](int q0s, int t, int c) {
+                    const int q = q0s + t;
+                    return (q < rho && c0 + c < nrc) ? Zl[(int64_t)q * nrc + c] : make_float2(0.f, 0.f);
+                });
+            q0 += rho;
         }
         acc.fold(seg);
     }
