@@ -134,91 +134,6 @@ __device__ __forceinline__ int find_le(const int64_t *key, int n, int64_t v) {
     return lo;
 }
 
-// ---------------------------------------------------------------------------------------
-// T = F X for one column cluster: tile (group, row tile mt of the stacked crosses, column
-// tile nt of (j, c)); the tiles of one column tile are consecutive, so the X slab they share
-// stays in L2.
-template <class FacT>
-__global__ void __launch_bounds__(256)
-    apply_far_t_kernel(ApplyDev a, MfmaApplyDev d, const float2 *X, float2 *T) {
-    constexpr int TN = 256;
-    __shared__ float2 As[16 * 32];
-    __shared__ float2 Bs[16 * TN];
-    __shared__ int sh_g;
-    __shared__ int64_t fo[32], to[32];
-    if (threadIdx.x == 0) sh_g = find_le(d.t_tile0, d.nt_groups, (int64_t)blockIdx.x);
-    __syncthreads();
-    const MfmaTGroup G = d.t_groups[sh_g];
-    const int64_t tile = blockIdx.x - d.t_tile0[sh_g];
-    const int mt = (int)(tile % G.m_tiles), nt = (int)(tile / G.m_tiles);
-    const int L = a.L, nrc = d.nrc, n = G.n, c0b = G.c0;
-    const int64_t ncols = (int64_t)n * nrc;
-    const int r0 = 32 * mt, nrow = min(32, G.rows - r0);
-    const int64_t n0 = (int64_t)nt * TN;
-    if (threadIdx.x < nrow) {
-        const MfmaTRow rw = d.t_rows[G.row0 + r0 + threadIdx.x];
-        fo[threadIdx.x] = rw.f_off;
-        to[threadIdx.x] = rw.t_off;
-    }
-    __syncthreads();
-    CTile<TN> acc, seg;
-    acc.zero();
-    seg.zero();
-    for (int k0 = 0; k0 < L; k0 += 16) {
-        if (k0 > 0 && k0 % kFold == 0) acc.fold(seg);
-        __syncthreads();
-        stage_a<true>(As, k0, nrow, L, [&](int r, int k) { return to_f2(a.fib_arena[fo[r] + k]); });
-        stage_b<TN>(Bs, k0, L, (int)min<int64_t>(TN, ncols - n0), [&](int k, int c) {
-            const int64_t nn = n0 + c;
-            const int j = (int)(nn >> d.lg_nrc), cc = (int)(nn & (nrc - 1));
-            return cc < d.ncur ? X[((int64_t)k * a.M + a.perm[c0b + j]) * d.ldx + d.c0 + cc]
-                               : make_float2(0.f, 0.f);
-        });
-        __syncthreads();
-        seg.step(As, Bs);
-    }
-    acc.fold(seg);
-    acc.visit([&](int r, int c, float2 v) {
-        if (r < nrow && n0 + c < ncols) T[to[r] + n0 + c] = v;
-    });
-}
-
-// Z_{b,l} = W_l T_l: tile (block b, cross l, row tile of rho_l, column tile).
-template <class FacT>
-__global__ void __launch_bounds__(256)
-    apply_far_z_kernel(ApplyDev a, MfmaApplyDev d, const float2 *T, float2 *Z) {
-    constexpr int TN = 64;
-    __shared__ float2 As[16 * 32];
-    __shared__ float2 Bs[16 * TN];
-    const MfmaZItem it = d.z_items[blockIdx.x];
-    const int b = it.b, l = it.l;
-    const int n = a.far4[4 * b + 3], m = a.far4[4 * b + 1];
-    const CrossMeta cm = a.cmeta[(int64_t)b * a.rcap + l];
-    const FacT *W = reinterpret_cast<const FacT *>(a.arena) + a.cross_off[(int64_t)b * a.rcap + l] +
-                    (int64_t)cm.rho * m;
-    const int nrc = d.nrc;
-    const int q0 = it.q0, c0 = blockIdx.y * TN;
-    const float2 *Tl = T + it.t_off + (int64_t)l * n * nrc;
-    CTile<TN> acc, seg;
-    acc.zero();
-    seg.zero();
-    for (int k0 = 0; k0 < n; k0 += 16) {
-        if (k0 > 0 && k0 % kFold == 0) acc.fold(seg);
-        __syncthreads();
-        stage_a<true>(As, k0, cm.rho - q0, n, [&](int r, int k) {
-            return to_f2(W[(int64_t)(q0 + r) * n + k]);
-        });
-        stage_b<TN>(Bs, k0, n, nrc - c0, [&](int k, int c) { return Tl[(int64_t)k * nrc + c0 + c]; });
-        __syncthreads();
-        seg.step(As, Bs);
-    }
-    acc.fold(seg);
-    float2 *Zl = Z + it.z_off;
-    acc.visit([&](int r, int c, float2 v) {
-        if (q0 + r < cm.rho && c0 + c < nrc) Zl[(int64_t)(q0 + r) * nrc + c0 + c] = v;
-    });
-}
-
 // One K loop of nslice slices of 16 on the matrix cores, software-pipelined: the operands of
 // the next pair of slices are loaded into registers while the matrix cores work on the
 // current pair (staged in LDS as As[k][32 rows], Bs[k][TN columns]).  pre(s) gives what
@@ -276,6 +191,98 @@ __device__ __forceinline__ void kloop(CTile<TN> &acc, CTile<TN> &seg, int &nk, f
         seg.step(As, Bs);
         if (SP > 1 && s + 1 < nslice) seg.step(As + 16 * 32, Bs + 16 * TN);
     }
+}
+
+// ---------------------------------------------------------------------------------------
+// T = F X for one column cluster: tile (group, row tile mt of the stacked crosses, column
+// tile nt of (j, c)); the tiles of one column tile are consecutive, so the X slab they share
+// stays in L2.
+template <class FacT>
+__global__ void __launch_bounds__(256)
+    apply_far_t_kernel(ApplyDev a, MfmaApplyDev d, const float2 *X, float2 *T) {
+    constexpr int TN = 256;
+    __shared__ float2 As[kSlicesPerStage * 16 * 32];
+    __shared__ float2 Bs[kSlicesPerStage * 16 * TN];
+    __shared__ int sh_g;
+    __shared__ int64_t fo[32], to[32];
+    if (threadIdx.x == 0) sh_g = find_le(d.t_tile0, d.nt_groups, (int64_t)blockIdx.x);
+    __syncthreads();
+    const MfmaTGroup G = d.t_groups[sh_g];
+    const int64_t tile = blockIdx.x - d.t_tile0[sh_g];
+    const int mt = (int)(tile % G.m_tiles), nt = (int)(tile / G.m_tiles);
+    const int L = a.L, nrc = d.nrc, n = G.n, c0b = G.c0;
+    const int64_t ncols = (int64_t)n * nrc;
+    const int r0 = 32 * mt, nrow = min(32, G.rows - r0);
+    const int64_t n0 = (int64_t)nt * TN;
+    if (threadIdx.x < nrow) {
+        const MfmaTRow rw = d.t_rows[G.row0 + r0 + threadIdx.x];
+        fo[threadIdx.x] = rw.f_off;
+        to[threadIdx.x] = rw.t_off;
+    }
+    __syncthreads();
+    CTile<TN> acc, seg;
+    acc.zero();
+    seg.zero();
+    // with TN = 256 every B element a thread stages lies in its own column c = threadIdx.x:
+    // the column's X offset is formed once
+    const int64_t nn = n0 + threadIdx.x;
+    const int jj = (int)(nn >> d.lg_nrc), cc = (int)(nn & (nrc - 1));
+    const bool bok = nn < ncols && cc < d.ncur;
+    const int64_t xoff = bok ? a.perm[c0b + jj] * (int64_t)d.ldx + d.c0 + cc : 0;
+    const int64_t xk = a.M * (int64_t)d.ldx;
+    int nk = 0;
+    kloop<TN, true>(acc, seg, nk, As, Bs, (L + 15) >> 4,
+        [&](int s) { return s << 4; },
+        [&](int k0, int r, int t) {
+            const int k = k0 + t;
+            return (r < nrow && k < L) ? to_f2(a.fib_arena[fo[r] + k]) : make_float2(0.f, 0.f);
+        },
+        [&](int k0, int t, int) {
+            const int k = k0 + t;
+            return (k < L && bok) ? X[(int64_t)k * xk + xoff] : make_float2(0.f, 0.f);
+        });
+    acc.fold(seg);
+    acc.visit([&](int r, int c, float2 v) {
+        if (r < nrow && n0 + c < ncols) T[to[r] + n0 + c] = v;
+    });
+}
+
+// Z_{b,l} = W_l T_l: tile (block b, cross l, row tile of rho_l, column tile).
+template <class FacT>
+__global__ void __launch_bounds__(256)
+    apply_far_z_kernel(ApplyDev a, MfmaApplyDev d, const float2 *T, float2 *Z) {
+    constexpr int TN = 64;
+    __shared__ float2 As[kSlicesPerStage * 16 * 32];
+    __shared__ float2 Bs[kSlicesPerStage * 16 * TN];
+    const MfmaZItem it = d.z_items[blockIdx.x];
+    const int b = it.b, l = it.l;
+    const int n = a.far4[4 * b + 3], m = a.far4[4 * b + 1];
+    const CrossMeta cm = a.cmeta[(int64_t)b * a.rcap + l];
+    const FacT *W = reinterpret_cast<const FacT *>(a.arena) + a.cross_off[(int64_t)b * a.rcap + l] +
+                    (int64_t)cm.rho * m;
+    const int nrc = d.nrc;
+    const int q0 = it.q0, c0 = blockIdx.y * TN;
+    const float2 *Tl = T + it.t_off + (int64_t)l * n * nrc;
+    CTile<TN> acc, seg;
+    acc.zero();
+    seg.zero();
+    const int nrow = cm.rho - q0, ncl = nrc - c0;
+    int nk = 0;
+    kloop<TN, true>(acc, seg, nk, As, Bs, (n + 15) >> 4,
+        [&](int s) { return s << 4; },
+        [&](int k0, int r, int t) {
+            const int k = k0 + t;
+            return (r < nrow && k < n) ? to_f2(W[(int64_t)(q0 + r) * n + k]) : make_float2(0.f, 0.f);
+        },
+        [&](int k0, int t, int c) {
+            const int k = k0 + t;
+            return (k < n && c < ncl) ? Tl[(int64_t)k * nrc + c0 + c] : make_float2(0.f, 0.f);
+        });
+    acc.fold(seg);
+    float2 *Zl = Z + it.z_off;
+    acc.visit([&](int r, int c, float2 v) {
+        if (q0 + r < cm.rho && c0 + c < nrc) Zl[(int64_t)(q0 + r) * nrc + c0 + c] = v;
+    });
 }
 
 // Y rows of one leaf (row tile of 32) for one column tile: near blocks and far blocks of
