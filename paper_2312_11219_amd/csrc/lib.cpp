@@ -1853,6 +1853,7 @@ static void apply_mfma(gaca_hmatrix *h, const ApplyDev &a, int32_t nrhs, const f
     {
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && rho_tot > 0) {
+            free_b += h->d_mz.bytes;   // this operator's Z workspace of an earlier call is reused
             while (nrc_max > 1 && (double)rho_tot * nrc_max * sizeof(float2) > 0.4 * (double)free_b)
                 nrc_max /= 2;
         } else {
