@@ -47,7 +47,7 @@ def dominant_kernels(kernels, all_stats):
                      st["far_flops_phase"][2]),
                     (f"far_tail_kernel<{kid}, false, false>", st["ms_far_phase"][3],
                      st["launches_phase"][3], st["far_flops_phase"][3]),
-                    ("far_aca_large_kernel<512, false, 106496> (faces with a side above 128)",
+                    ("far_aca_large_kernel<512, false, 106496, 1> (faces with a side above 128)",
                      st["ms_far_by_kind"][3], st["launches_by_kind"][3], st["far_flops_by_kind"][3])]
             for name, ms, nl, fl in rows:
                 e = out.setdefault(name, {"ms": 0.0, "launches": 0, "flops": 0.0})

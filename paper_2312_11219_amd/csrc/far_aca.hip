@@ -41,6 +41,8 @@ constexpr int kMaxLds = 1024;       // frequencies
 constexpr int kMaxRcap = 256;       // crosses per block
 constexpr int kCoefLds = 512;       // staged history coefficients of the large-face ACA
 constexpr int kCurRegs = 4;         // current u, w in registers for m, n <= 256
+constexpr int kMultiE = kFarMultiE; // large faces: up to this many row / column entries per thread
+constexpr int kBV = 1024;           // steps of a large face on the register paths (then the general one)
 
 // Face entry at (il, jl, kk): FP64 value (FT = double2), the dense test tensor, or the
 // scaled FP32 value (FT = float2).
@@ -199,6 +201,25 @@ __device__ int first_unused(const unsigned char *used, int len, Red<NT> &red) {
     return red.imin(c);
 }
 
+// First row r >= r0 of the m x n face R (HBM) with an entry above zero_tol in modulus, or m;
+// rows in chunks of about 16 NT entries.  A row is zero for the face ACA when the square
+// root of its largest |R|^2 is at most zero_tol, i.e. when no entry exceeds it.
+template <int NT, class FT>
+__device__ int first_nonzero_row(const FT *R, int m, int n, int r0, double zero_tol, Red<NT> &red) {
+    const int rb = max(1, 16 * NT / n);
+    for (; r0 < m; r0 += rb) {
+        const int r1 = min(m, r0 + rb);
+        const int64_t cnt = (int64_t)(r1 - r0) * n;
+        const FT *base = R + (int64_t)r0 * n;
+        int c = m;
+        for (int64_t idx = threadIdx.x; idx < cnt; idx += NT)
+            if (sqrt(cabs2(base[idx])) > zero_tol) c = min(c, r0 + (int)(idx / n));
+        c = red.imin(c);
+        if (c < m) return c;
+    }
+    return m;
+}
+
 // ---------------------------------------------------------------------------------------
 // ACA phase, small faces: R and S = sum_q u_q w_q^T in registers, E = MNMAX / NT entries
 // per thread (entry idx = tid + NT t), updated in place by the rank-1 steps; only the current
@@ -254,8 +275,21 @@ __global__ void __launch_bounds__(NT)
         if (tid == 0) used_row[i] = 1;
         ++nused;
         if (sqrt(mx) <= zero_tol) {
+            // A zero row: the ACA goes on with the unused rows in index order, and every one
+            // below the first with a nonzero residual entry is zero as well; find that row in
+            // one pass over the register-held residual and mark the zero ones used.
             __syncthreads();
-            const int cand = first_unused<NT>(used_row, m, red);
+            int cand = m;
+#pragma unroll
+            for (int t = 0; t < E; ++t)
+                if (ri[t] < m && !used_row[ri[t]] && sqrt(cabs2(rr[t])) > zero_tol) cand = min(cand, ri[t]);
+            cand = red.imin(cand);
+            double cnt = 0.0;
+            for (int r = tid; r < cand; r += NT)
+                if (!used_row[r]) cnt += 1.0;
+            cnt = red.sum(cnt);
+            for (int r = tid; r < cand; r += NT) used_row[r] = 1;
+            nused += (int)cnt;
             if (cand >= m) break;
             i = cand;
             continue;
@@ -336,7 +370,10 @@ __global__ void __launch_bounds__(NT)
 // steps (as many as fit) and in HBM beyond, so the row / column corrections and the cross
 // terms of the stopping norm mostly read LDS.  Row and column corrections are split over
 // thread groups.
-template <int NT, bool MIXED, int HB>
+// PATH 1: faces with m, n <= NT (one entry per thread); 2: m, n <= kMultiE NT (several
+// entries per thread, the general loop after kBV steps; NT = 512 only); 0: any face (general
+// loop).  Each launch takes faces of one class, so each kernel holds only its own loops.
+template <int NT, bool MIXED, int HB, int PATH>
 __global__ void __launch_bounds__(NT)
     far_aca_large_kernel(AcaParams P, FarBatchDev bd, const FarActive *act) {
     using FT = face_t<MIXED>;
@@ -359,7 +396,7 @@ __global__ void __launch_bounds__(NT)
     __shared__ unsigned char used_row[kMaxRowsLds];
     __shared__ double redbuf[4 * NW + 4];
     __shared__ double2 xbuf[NT];  // current w (face type), then split partials of v
-    __shared__ double2 bvec[NT];  // conj <w_q, w_q'> for q' < q
+    __shared__ double2 bvec[kBV];  // conj <w_q, w_q'> for q' < q
     Red<NT> red{redbuf};
     const double tie2 = (1.0 - P.tie) * (1.0 - P.tie);
     const int qL = min(B.rho_max, (int)(HB / ((int64_t)(m + n) * (int64_t)sizeof(FT))));
@@ -411,7 +448,9 @@ __global__ void __launch_bounds__(NT)
     int q = 0, i = 0, nused = 0;
     double s2 = 0.0;
     const int splitw = max(1, NT / n), splitu = max(1, NT / m);
-    if (m <= NT && n <= NT) {
+    bool fin = false;   // the face ACA has ended (else the general path continues it)
+    if constexpr (PATH == 1) {
+        fin = true;
         // One row entry and one column entry per thread, kept in registers.  The cross terms
         // sum_{q'<q} Re(<u_q, u_q'> <w_q, w_q'>) of the stopping norm are taken as
         // Re <u_q, v> with v = sum_{q'<q} conj(b_q') u_q', b_q' = <w_q, w_q'>: b is one
@@ -442,7 +481,16 @@ __global__ void __launch_bounds__(NT)
             ++nused;
             if (sqrt(mx) <= zero_tol) {
                 __syncthreads();
-                const int cand = first_unused<NT>(used_row, m, red);
+                int cand;
+                if (q == 0) {
+                    // no factors yet: the rows are visited in index order up to the first
+                    // nonzero one, found in one pass over the face
+                    cand = first_nonzero_row<NT>(R, m, n, i + 1, zero_tol, red);
+                    for (int r = i + 1 + tid; r < cand; r += NT) used_row[r] = 1;
+                    nused += cand - (i + 1);
+                } else {
+                    cand = first_unused<NT>(used_row, m, red);
+                }
                 if (cand >= m) break;
                 i = cand;
                 continue;
@@ -564,7 +612,246 @@ __global__ void __launch_bounds__(NT)
             if (c >= m) c = first_unused<NT>(used_row, m, red);
             i = min(c, m - 1);
         }
-    } else
+    } else if constexpr (PATH == 2) {
+        // Several row and column entries per thread (j = tid + NT e, r = tid + NT e), kept in
+        // registers.  The corrections read the history q' by q' for all of a thread's entries
+        // at once (QB steps per batch, addresses clamped into the face, surplus terms masked
+        // by a zero coefficient); b_q' = <w_q, w_q'> is formed by all threads from w_q in
+        // registers, QB steps at a time, each wave's sums written to LDS and added up in a
+        // fixed order; v is summed in the column pass as on the one-entry path.  After kBV
+        // steps the face continues on the general path.
+        constexpr int EM = kMultiE;
+        constexpr int QB = MIXED ? 8 : 3;
+        double2 *wpart = xbuf;   // [NW][64] per-wave partial sums of b
+        FT *pivbuf = part;
+        auto cmask = [](bool ok, FT a) {
+            FT r;
+            r.x = ok ? a.x : 0;
+            r.y = ok ? a.y : 0;
+            return r;
+        };
+        while (q < kBV) {
+            FT *Wq = Wb + (int64_t)q * n;
+            FT *Uq = Ub + (int64_t)q * m;
+            FT v[EM];
+#pragma unroll
+            for (int e = 0; e < EM; ++e) v[e] = R[(int64_t)i * n + min(tid + NT * e, n - 1)];
+            if (q > qL) stage_coef(Ub, m, i, q);
+            {
+                // row i of R - sum_{q'<q} u_q'[i] w_q'
+                FT acc[EM];
+#pragma unroll
+                for (int e = 0; e < EM; ++e) acc[e] = czero<FT>();
+                const int qm = min(q, qL);
+                for (int qq = 0; qq < qm; ++qq) {
+                    const FT c = Uh[qq * m + i];
+#pragma unroll
+                    for (int e = 0; e < EM; ++e) acc[e] = cfma(c, Wh[qq * n + min(tid + NT * e, n - 1)], acc[e]);
+                }
+                const int qc = min(q, qL + kCoefLds);
+                for (int qq = qL; qq < qc; qq += QB) {
+                    FT x[QB][EM];
+#pragma unroll
+                    for (int qb = 0; qb < QB; ++qb) {
+                        const FT *wp = Wb + (int64_t)min(qq + qb, qc - 1) * n;
+#pragma unroll
+                        for (int e = 0; e < EM; ++e) x[qb][e] = wp[min(tid + NT * e, n - 1)];
+                    }
+#pragma unroll
+                    for (int qb = 0; qb < QB; ++qb) {
+                        const FT c = cmask(qq + qb < qc, cbuf[min(qq + qb, qc - 1) - qL]);
+#pragma unroll
+                        for (int e = 0; e < EM; ++e) acc[e] = cfma(c, x[qb][e], acc[e]);
+                    }
+                }
+                for (int qq = qL + kCoefLds; qq < q; ++qq) {
+                    const FT c = Ub[(int64_t)qq * m + i];
+#pragma unroll
+                    for (int e = 0; e < EM; ++e)
+                        acc[e] = cfma(c, Wb[(int64_t)qq * n + min(tid + NT * e, n - 1)], acc[e]);
+                }
+#pragma unroll
+                for (int e = 0; e < EM; ++e) v[e] = csub(v[e], acc[e]);
+            }
+            double mx = 0.0;
+#pragma unroll
+            for (int e = 0; e < EM; ++e)
+                if (tid + NT * e < n) mx = fmax(mx, cabs2(v[e]));
+            mx = red.max(mx);
+            if (tid == 0) used_row[i] = 1;
+            ++nused;
+            if (sqrt(mx) <= zero_tol) {
+                __syncthreads();
+                int cand;
+                if (q == 0) {
+                    cand = first_nonzero_row<NT>(R, m, n, i + 1, zero_tol, red);
+                    for (int r = i + 1 + tid; r < cand; r += NT) used_row[r] = 1;
+                    nused += cand - (i + 1);
+                } else {
+                    cand = first_unused<NT>(used_row, m, red);
+                }
+                if (cand >= m) {
+                    fin = true;
+                    break;
+                }
+                i = cand;
+                continue;
+            }
+            const double thr = tie2 * mx;
+            int jc = n;
+#pragma unroll
+            for (int e = EM - 1; e >= 0; --e)   // lowest own column at the threshold
+                if (tid + NT * e < n && cabs2(v[e]) >= thr) jc = tid + NT * e;
+            const int jp = min(red.imin(jc), n - 1);   // in range even for NaN rows
+#pragma unroll
+            for (int e = 0; e < EM; ++e)
+                if (tid + NT * e == jp) pivbuf[0] = v[e];
+            __syncthreads();
+            const FT piv = pivbuf[0];
+            FT cv[EM];
+#pragma unroll
+            for (int e = 0; e < EM; ++e) cv[e] = R[(int64_t)min(tid + NT * e, m - 1) * n + jp];
+            double nw2 = 0.0;
+#pragma unroll
+            for (int e = 0; e < EM; ++e) {   // v <- w_q (zero beyond the face)
+                const int j = tid + NT * e;
+                if (j < n) {
+                    const FT w = cdiv(v[e], piv);
+                    v[e] = w;
+                    Wq[j] = w;
+                    if (q < qL) Wh[q * n + j] = w;
+                    nw2 += cabs2(w);
+                } else {
+                    v[e] = czero<FT>();
+                }
+            }
+            if (q > 0) {
+                // b_q' = <w_q, w_q'>, 64 steps q' per round
+                for (int qc0 = 0; qc0 < q; qc0 += 64) {
+                    const int qn = min(64, q - qc0);
+                    for (int qq = qc0; qq < qc0 + qn; qq += QB) {
+                        FT x[QB][EM];
+#pragma unroll
+                        for (int qb = 0; qb < QB; ++qb) {
+                            const int qe = min(qq + qb, q - 1);
+                            const FT *wp = qe < qL ? Wh + qe * n : Wb + (int64_t)qe * n;
+#pragma unroll
+                            for (int e = 0; e < EM; ++e) x[qb][e] = wp[min(tid + NT * e, n - 1)];
+                        }
+#pragma unroll
+                        for (int qb = 0; qb < QB; ++qb) {
+                            double2 pb = make_double2(0.0, 0.0);
+#pragma unroll
+                            for (int e = 0; e < EM; ++e) pb = cfma(to_d2(v[e]), conj_d2(to_d2(x[qb][e])), pb);
+                            pb.x = wave_sum(pb.x);
+                            pb.y = wave_sum(pb.y);
+                            if (lane == 0 && qq + qb < qc0 + qn) wpart[wave * 64 + qq + qb - qc0] = pb;
+                        }
+                    }
+                    __syncthreads();
+                    for (int t = tid; t < qn; t += NT) {
+                        double2 sb = make_double2(0.0, 0.0);
+                        for (int w = 0; w < NW; ++w) sb = cadd(sb, wpart[w * 64 + t]);
+                        bvec[qc0 + t] = conj_d2(sb);
+                    }
+                    __syncthreads();
+                }
+            }
+            if (q > qL) stage_coef(Wb, n, jp, q);
+            // column jp of R - sum_{q'<q} w_q'[jp] u_q', and v = sum_{q'<q} conj(b_q') u_q'
+            FT u[EM];
+            double2 vv[EM];
+            {
+                FT acc[EM];
+#pragma unroll
+                for (int e = 0; e < EM; ++e) {
+                    acc[e] = czero<FT>();
+                    vv[e] = make_double2(0.0, 0.0);
+                }
+                const int qm = min(q, qL);
+                for (int qq = 0; qq < qm; ++qq) {
+                    const FT c = Wh[qq * n + jp];
+                    const double2 bq = bvec[qq];
+#pragma unroll
+                    for (int e = 0; e < EM; ++e) {
+                        const FT x = Uh[qq * m + min(tid + NT * e, m - 1)];
+                        acc[e] = cfma(c, x, acc[e]);
+                        vv[e] = cfma(bq, to_d2(x), vv[e]);
+                    }
+                }
+                const int qc = min(q, qL + kCoefLds);
+                for (int qq = qL; qq < qc; qq += QB) {
+                    FT x[QB][EM];
+#pragma unroll
+                    for (int qb = 0; qb < QB; ++qb) {
+                        const FT *up = Ub + (int64_t)min(qq + qb, qc - 1) * m;
+#pragma unroll
+                        for (int e = 0; e < EM; ++e) x[qb][e] = up[min(tid + NT * e, m - 1)];
+                    }
+#pragma unroll
+                    for (int qb = 0; qb < QB; ++qb) {
+                        const bool ok = qq + qb < qc;
+                        const int qe = min(qq + qb, qc - 1);
+                        const FT c = cmask(ok, cbuf[qe - qL]);
+                        double2 bq = bvec[qe];
+                        bq.x = ok ? bq.x : 0.0;
+                        bq.y = ok ? bq.y : 0.0;
+#pragma unroll
+                        for (int e = 0; e < EM; ++e) {
+                            acc[e] = cfma(c, x[qb][e], acc[e]);
+                            vv[e] = cfma(bq, to_d2(x[qb][e]), vv[e]);
+                        }
+                    }
+                }
+                for (int qq = qL + kCoefLds; qq < q; ++qq) {
+                    const FT c = Wb[(int64_t)qq * n + jp];
+                    const double2 bq = bvec[qq];
+#pragma unroll
+                    for (int e = 0; e < EM; ++e) {
+                        const FT x = Ub[(int64_t)qq * m + min(tid + NT * e, m - 1)];
+                        acc[e] = cfma(c, x, acc[e]);
+                        vv[e] = cfma(bq, to_d2(x), vv[e]);
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < EM; ++e) u[e] = csub(cv[e], acc[e]);
+            }
+            double nu2 = 0.0, cr = 0.0, mxu = -1.0;
+#pragma unroll
+            for (int e = 0; e < EM; ++e) {
+                const int r = tid + NT * e;
+                if (r < m) {
+                    Uq[r] = u[e];
+                    if (q < qL) Uh[q * m + r] = u[e];
+                    const double a2 = cabs2(u[e]);
+                    nu2 += a2;
+                    const double2 ud = to_d2(u[e]);
+                    cr += ud.x * vv[e].x + ud.y * vv[e].y;
+                    if (!used_row[r]) mxu = fmax(mxu, a2);
+                }
+            }
+            red.sum3max(nu2, nw2, cr, mxu);
+            s2 = s2 + 2.0 * cr + nu2 * nw2;
+            ++q;
+            if (sqrt(nu2 * nw2) <= P.eps_aca * sqrt(ref2 + s2) || nused >= m || q >= B.rho_max) {
+                fin = true;
+                break;
+            }
+            // next row: tie-argmax of |u_q| over the unused rows
+            const double thu = tie2 * mxu;
+            int c = m;
+#pragma unroll
+            for (int e = EM - 1; e >= 0; --e) {
+                const int r = tid + NT * e;
+                if (r < m && !used_row[r] && cabs2(u[e]) >= thu) c = r;
+            }
+            c = red.imin(c);
+            if (c >= m) c = first_unused<NT>(used_row, m, red);
+            i = min(c, m - 1);
+        }
+    }
+    if constexpr (PATH != 1)
+    if (!fin)
     while (true) {
         FT *Wq = Wb + (int64_t)q * n;
         FT *Uq = Ub + (int64_t)q * m;
@@ -596,7 +883,14 @@ __global__ void __launch_bounds__(NT)
         ++nused;
         if (sqrt(mx) <= zero_tol) {
             __syncthreads();
-            const int cand = first_unused<NT>(used_row, m, red);
+            int cand;
+            if (q == 0) {
+                cand = first_nonzero_row<NT>(R, m, n, i + 1, zero_tol, red);
+                for (int r = i + 1 + tid; r < cand; r += NT) used_row[r] = 1;
+                nused += cand - (i + 1);
+            } else {
+                cand = first_unused<NT>(used_row, m, red);
+            }
             if (cand >= m) break;
             i = cand;
             continue;
@@ -1147,18 +1441,29 @@ void launch_far_face(int kernel, const GeoDev &g, const FreqDev &f, const FarBat
     }
 }
 
-template <bool MX>
-static void aca_dispatch(int kind, int threads, const AcaParams &P, const FarBatchDev &bd,
-                         const FarActive *act, int nact, hipStream_t st) {
+template <bool MX, int PATH>
+static void large_dispatch(int threads, const AcaParams &P, const FarBatchDev &bd,
+                           const FarActive *act, int nact, hipStream_t st) {
     // large faces: one face per CU with 1024 or 512 threads and ~100 KB of LDS history, or
     // 256 threads with 32 KB, several per CU
-    (void)kind;
-    if (threads >= 1024)
-        far_aca_large_kernel<1024, MX, 90112><<<nact, 1024, 0, st>>>(P, bd, act);
-    else if (threads >= 512)
-        far_aca_large_kernel<512, MX, 106496><<<nact, 512, 0, st>>>(P, bd, act);
-    else
-        far_aca_large_kernel<256, MX, 32768><<<nact, 256, 0, st>>>(P, bd, act);
+    if constexpr (PATH == 2) {
+        far_aca_large_kernel<512, MX, 106496, 2><<<nact, 512, 0, st>>>(P, bd, act);
+    } else {
+        if (threads >= 1024)
+            far_aca_large_kernel<1024, MX, 90112, PATH><<<nact, 1024, 0, st>>>(P, bd, act);
+        else if (threads >= 512)
+            far_aca_large_kernel<512, MX, 106496, PATH><<<nact, 512, 0, st>>>(P, bd, act);
+        else
+            far_aca_large_kernel<256, MX, 32768, PATH><<<nact, 256, 0, st>>>(P, bd, act);
+    }
+}
+
+template <bool MX>
+static void aca_dispatch(int path, int threads, const AcaParams &P, const FarBatchDev &bd,
+                         const FarActive *act, int nact, hipStream_t st) {
+    if (path == 1) large_dispatch<MX, 1>(threads, P, bd, act, nact, st);
+    else if (path == 2) large_dispatch<MX, 2>(threads, P, bd, act, nact, st);
+    else large_dispatch<MX, 0>(threads, P, bd, act, nact, st);
 }
 
 template <bool MX>
@@ -1181,11 +1486,11 @@ static void aca_small_dispatch(int mnmax, int threads, const AcaParams &P, const
         far_aca_small_kernel<512, MX, K2, 128><<<nact, 512, 0, st>>>(P, bd, act);
 }
 
-void launch_far_aca(int kind, int threads, const AcaParams &P, const FarBatchDev &bd,
+void launch_far_aca(int path, int threads, const AcaParams &P, const FarBatchDev &bd,
                     const FarActive *act, int nact, hipStream_t st) {
     if (nact <= 0) return;
-    if (bd.mixed) aca_dispatch<true>(kind, threads, P, bd, act, nact, st);
-    else aca_dispatch<false>(kind, threads, P, bd, act, nact, st);
+    if (bd.mixed) aca_dispatch<true>(path, threads, P, bd, act, nact, st);
+    else aca_dispatch<false>(path, threads, P, bd, act, nact, st);
 }
 
 void launch_far_aca_small(int mnmax, int threads, const AcaParams &P, const FarBatchDev &bd,

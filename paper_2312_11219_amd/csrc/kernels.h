@@ -90,8 +90,10 @@ void launch_far_face(int kernel, const GeoDev &g, const FreqDev &f, const FarBat
                      const FarActive *act, int64_t nchunk, hipStream_t st);
 // Classes: kind 0 m n <= 1024, sides <= 64; kind 1 m n <= 2304, sides <= 96; kind 2 m n <=
 // 4096 (FP64) or 8192 (mixed), sides <= 128; kind 3 larger.
-// Kind 3 (R in HBM): threads 256, 512 or 1024.
-void launch_far_aca(int kind, int threads, const AcaParams &P, const FarBatchDev &bd,
+// Kind 3 (R in HBM): threads 256, 512 or 1024; path 1: faces with m, n <= threads; 2: m, n
+// <= kFarMultiE * 512 (512 threads); 0: any face.
+constexpr int kFarMultiE = 5;
+void launch_far_aca(int path, int threads, const AcaParams &P, const FarBatchDev &bd,
                     const FarActive *act, int nact, hipStream_t st);
 // Kinds 0-2 (R and S in registers): faces with m n <= mnmax (576, 1024, 2304, or the kind-2
 // bound) and workgroups of `threads` (64: one wave per face, 128, 256; kind 2: 512).

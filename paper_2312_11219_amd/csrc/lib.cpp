@@ -1140,13 +1140,24 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             // kind 3 first (large faces with a side above kMediumSide before the medium ones),
             // then 2, 1, 0; larger faces first within a class
             auto big = [&](int x) { return std::max(bdesc[x].m, bdesc[x].n) > kMediumSide; };
+            // large-face kernel path of a big face: 0 general (several entries per thread
+            // beyond the register paths), 2 several entries per thread, 1 one entry per thread
+            const int tlx = p->opt.threads_large > 0 ? p->opt.threads_large : 512;
+            auto path = [&](int x) {
+                const int side = std::max(bdesc[x].m, bdesc[x].n);
+                if (side <= tlx) return 1;
+                return (tlx == 512 && side <= kFarMultiE * 512) ? 2 : 0;
+            };
+            auto prank = [&](int x) { const int pth = path(x); return pth == 0 ? 0 : pth == 2 ? 1 : 2; };
             std::stable_sort(active.begin(), active.end(), [&](int x, int y) {
                 if (kind[base + x] != kind[base + y]) return kind[base + x] > kind[base + y];
                 if (kind[base + x] == 3 && big(x) != big(y)) return big(x);
+                if (kind[base + x] == 3 && big(x) && prank(x) != prank(y)) return prank(x) < prank(y);
                 return (int64_t)bdesc[x].m * bdesc[x].n > (int64_t)bdesc[y].m * bdesc[y].n;
             });
-            int nbig = 0;
-            while (nbig < (int)active.size() && kind[base + active[nbig]] == 3 && big(active[nbig])) ++nbig;
+            int nbig = 0, npath[3] = {0, 0, 0};
+            while (nbig < (int)active.size() && kind[base + active[nbig]] == 3 && big(active[nbig]))
+                ++npath[path(active[nbig++])];
             const int nact = (int)active.size();
             ms_prep += wall_ms_since(t_it);
             const auto t_launch = std::chrono::steady_clock::now();
@@ -1210,9 +1221,13 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             for (int k = 3; k >= 0; --k) {
                 if (cnt[k] == 0) continue;
                 if (k == 3) {
-                    launch_far_aca(3, tl, P, bd, dact, nbig, ks[3]);
-                    launch_far_aca(3, 256, P, bd, dact + nbig, cnt[3] - nbig, ks[2]);
-                    nl += (nbig > 0) + (cnt[3] > nbig);
+                    // big faces by path (general, several entries, one entry per thread),
+                    // one after the other on the kind-3 stream
+                    launch_far_aca(0, tl, P, bd, dact, npath[0], ks[3]);
+                    launch_far_aca(2, tl, P, bd, dact + npath[0], npath[2], ks[3]);
+                    launch_far_aca(1, tl, P, bd, dact + npath[0] + npath[2], npath[1], ks[3]);
+                    launch_far_aca(1, 256, P, bd, dact + nbig, cnt[3] - nbig, ks[2]);
+                    nl += (npath[0] > 0) + (npath[2] > 0) + (npath[1] > 0) + (cnt[3] > nbig);
                     continue;
                 }
                 if (k == 0 && ts <= 64) {

@@ -233,6 +233,32 @@ def test_compress_tensor_known_rank(R, rho):
     assert [(c["i"], c["j"]) for c in b["crosses"]] == [(c.i, c.j) for c in o.crosses]
 
 
+@pytest.mark.parametrize("m,n", [(300, 900), (700, 1100), (1500, 420)])
+def test_compress_tensor_large_faces(m, n):
+    """Faces with a side above 512 (several row / column entries per thread, history mostly
+    in HBM): exact reconstruction of a known-rank tensor and the oracle's pivots."""
+    import torch
+    import paper_2312_11219_amd as gaca
+    from gpu_common import context
+    from oracle.aca3d import aca3d
+    rng = np.random.default_rng(m + n)
+    L, R, rho = 6, 2, 12
+    T = np.zeros((m, n, L), dtype=complex)
+    for _ in range(R):
+        H = (rng.standard_normal((m, rho)) + 1j * rng.standard_normal((m, rho))) @ \
+            (rng.standard_normal((rho, n)) + 1j * rng.standard_normal((rho, n)))
+        T += H[:, :, None] * (rng.standard_normal(L) + 1j * rng.standard_normal(L))[None, None, :]
+    h = gaca.compress_tensor(context(), torch.from_numpy(T).cuda(), eps3d=1e-10, eps_aca=1e-12)
+    b = h.export_block(0)
+    o = aca3d(T, 1e-10, 1e-12)
+    err = rel_fro(h.reconstruct_block(0), T)
+    log(f"large faces {m} x {n}: rank {b['rank']} (oracle {o.rank}), rel err {err:.2e}")
+    assert b["rank"] == R == o.rank
+    assert err < 1e-11
+    assert [c["k"] for c in b["crosses"]] == [c.k for c in o.crosses]
+    assert [(c["i"], c["j"]) for c in b["crosses"]] == [(c.i, c.j) for c in o.crosses]
+
+
 def test_compress_tensor_zero_and_dense():
     import torch
     import paper_2312_11219_amd as gaca
