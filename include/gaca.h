@@ -77,6 +77,9 @@ typedef struct {
     int32_t threads_large;    /* face-ACA workgroup size for the large faces (256, 512 or
                                  1024; default 0: 512) */
     int32_t verbose;          /* 1: one progress line per far-field batch on stderr */
+    int32_t zero_rows_batch;  /* face ACA of the large faces, after a zero row: 1 (default)
+                                 tries several unused rows per pass over the history, 0 one
+                                 row per pass; both end at the same row */
 } gaca_options;
 
 typedef struct gaca_context gaca_context;

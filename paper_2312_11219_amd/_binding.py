@@ -32,7 +32,7 @@ class Options(ctypes.Structure):
                 ("precision", I32), ("n_duffy", I32), ("n_galerkin", I32), ("tie", F64),
                 ("delta_zero", F64), ("max_rank3d", I32), ("max_face_rank", I32),
                 ("max_device_bytes", U64), ("batch_bytes", U64), ("threads_small", I32),
-                ("threads_large", I32), ("verbose", I32)]
+                ("threads_large", I32), ("verbose", I32), ("zero_rows_batch", I32)]
 
 
 class Stats(ctypes.Structure):

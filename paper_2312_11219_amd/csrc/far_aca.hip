@@ -220,6 +220,205 @@ __device__ int first_nonzero_row(const FT *R, int m, int n, int r0, double zero_
     return m;
 }
 
+// Zero rows after the first cross.  A zero row sends the face ACA to the unused rows in
+// index order until one has a residual entry above zero_tol; each try is a full pass over
+// the history.  The large-face kernels try G rows per pass instead: the history is read once
+// for all of them and every candidate's residual entries are formed by the same chain of
+// operations as the row pass (terms of a padded step carry a zero coefficient and add an
+// exact zero), so the first nonzero candidate is the row where the one-at-a-time search
+// would stop; the zero ones before it are marked used.
+
+// The G lowest unused rows from r0 up, ascending, in every lane of every wave (each wave
+// scans for itself); returns their count (< G when fewer remain); c[g] past the count
+// repeats the last row found.
+template <int G>
+__device__ int scan_unused(const unsigned char *used, int m, int r0, int (&c)[G]) {
+    const int lane = threadIdx.x & 63;
+    auto window = [&](int base) {
+        const int r = base + lane;
+        return (unsigned long long)__ballot(r < m && !used[r]);
+    };
+    unsigned long long bal = r0 < m ? window(r0) : 0ull;
+    int cnt = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        while (bal == 0ull && r0 + 64 < m) {
+            r0 += 64;
+            bal = window(r0);
+        }
+        if (bal != 0ull) {
+            c[g] = r0 + __ffsll(bal) - 1;
+            bal &= bal - 1ull;
+            cnt = g + 1;
+        } else {
+            c[g] = g > 0 ? c[g - 1] : 0;
+        }
+    }
+    return cnt;
+}
+
+// Multi-entry layout (entries j = tid + NT e, e < NE): max_j |R(c_g, j) - sum_{q'<q}
+// u_q'[c_g] w_q'[j]|^2 for each candidate, as one chain over q' per entry; the u
+// coefficients of the HBM history are staged CH steps at a time in cs ([G][CH]); wm holds
+// NW * G doubles.  mx[g] is the same in every thread.
+template <int NT, int G, int NE, class FT>
+__device__ void zero_rows_multi(const FT *R, const FT *Uh, const FT *Wh, const FT *Ub,
+                                const FT *Wb, int m, int n, int q, int qL, const int (&c)[G],
+                                FT *cs, int CH, double *wm, double (&mx)[G]) {
+    constexpr int NW = NT / 64;
+    constexpr int QZ = 2;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    int jj[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) jj[e] = min(tid + NT * e, n - 1);
+    FT acc[G][NE];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int e = 0; e < NE; ++e) acc[g][e] = czero<FT>();
+    const int qm = min(q, qL);
+    for (int qq = 0; qq < qm; ++qq) {
+        FT x[NE];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) x[e] = Wh[qq * n + jj[e]];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const FT cg = Uh[qq * m + c[g]];
+#pragma unroll
+            for (int e = 0; e < NE; ++e) acc[g][e] = cfma(cg, x[e], acc[g][e]);
+        }
+    }
+    for (int qa = qL; qa < q; qa += CH) {
+        const int nq = min(CH, q - qa);
+        __syncthreads();
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            for (int k = tid; k < nq; k += NT) cs[g * CH + k] = Ub[(int64_t)(qa + k) * m + c[g]];
+        __syncthreads();
+        for (int k = 0; k < nq; k += QZ) {
+            FT x[QZ][NE];
+#pragma unroll
+            for (int qb = 0; qb < QZ; ++qb) {
+                const FT *wp = Wb + (int64_t)(qa + min(k + qb, nq - 1)) * n;
+#pragma unroll
+                for (int e = 0; e < NE; ++e) x[qb][e] = wp[jj[e]];
+            }
+#pragma unroll
+            for (int qb = 0; qb < QZ; ++qb) {
+                const bool ok = k + qb < nq;
+                const int kk = min(k + qb, nq - 1);
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    FT cg = cs[g * CH + kk];
+                    cg.x = ok ? cg.x : 0;
+                    cg.y = ok ? cg.y : 0;
+#pragma unroll
+                    for (int e = 0; e < NE; ++e) acc[g][e] = cfma(cg, x[qb][e], acc[g][e]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        double mv = 0.0;
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+            if (tid + NT * e < n) mv = fmax(mv, cabs2(csub(R[(int64_t)c[g] * n + jj[e]], acc[g][e])));
+        mv = wave_max(mv);
+        if (lane == 0) wm[wave * G + g] = mv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        double t = wm[g];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) t = fmax(t, wm[w * G + g]);
+        mx[g] = t;
+    }
+}
+
+// One-entry layout with the history split over splitw thread groups (m, n <= NT): thread
+// (s, j) sums steps [q s / splitw, q (s + 1) / splitw) in two interleaved accumulators,
+// exactly as the row pass's history dot product does (LDS part in pairs, HBM part in groups
+// of NB with the u coefficients from cs = [G][kCoefLds], q <= qL + kCoefLds); the group
+// partials s >= 1 go through pp[g], and the row is R - p_0 - p_1 - ... as in the row pass.
+template <int NT, int G, class FT>
+__device__ void zero_rows_split(const FT *R, const FT *Uh, const FT *Wh, const FT *Wb, int m,
+                                int n, int q, int qL, int splitw, const int (&c)[G],
+                                const FT *cs, FT *const (&pp)[G], double *wm, double (&mx)[G]) {
+    constexpr int NW = NT / 64;
+    constexpr int NB = NT >= 1024 ? 4 : 16;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    FT p[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) p[g] = czero<FT>();
+    if (tid < splitw * n) {
+        const int s = tid / n, j = tid - s * n;
+        const int q0 = (int)((int64_t)q * s / splitw), q1 = (int)((int64_t)q * (s + 1) / splitw);
+        FT a0[G], a1[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) a0[g] = a1[g] = czero<FT>();
+        const int qm = min(q1, qL);
+        int qq = q0;
+        for (; qq + 1 < qm; qq += 2) {
+            const FT x0 = Wh[qq * n + j], x1 = Wh[(qq + 1) * n + j];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                a0[g] = cfma(Uh[qq * m + c[g]], x0, a0[g]);
+                a1[g] = cfma(Uh[(qq + 1) * m + c[g]], x1, a1[g]);
+            }
+        }
+        if (qq < qm) {
+            const FT x0 = Wh[qq * n + j];
+#pragma unroll
+            for (int g = 0; g < G; ++g) a0[g] = cfma(Uh[qq * m + c[g]], x0, a0[g]);
+        }
+        qq = max(q0, qL);
+        for (; qq + NB <= q1; qq += NB) {
+            FT bv[NB];
+#pragma unroll
+            for (int t = 0; t < NB; ++t) bv[t] = Wb[(int64_t)(qq + t) * n + j];
+#pragma unroll
+            for (int t = 0; t < NB; t += 2)
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    a0[g] = cfma(cs[g * kCoefLds + qq + t - qL], bv[t], a0[g]);
+                    a1[g] = cfma(cs[g * kCoefLds + qq + t + 1 - qL], bv[t + 1], a1[g]);
+                }
+        }
+        for (; qq < q1; ++qq) {
+            const FT x0 = Wb[(int64_t)qq * n + j];
+#pragma unroll
+            for (int g = 0; g < G; ++g) a0[g] = cfma(cs[g * kCoefLds + qq - qL], x0, a0[g]);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            p[g] = cadd(a0[g], a1[g]);
+            if (s > 0) pp[g][(s - 1) * n + j] = p[g];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        double mv = 0.0;
+        if (tid < n) {
+            FT v = csub(R[(int64_t)c[g] * n + tid], p[g]);
+            for (int t = 1; t < splitw; ++t) v = csub(v, pp[g][(t - 1) * n + tid]);
+            mv = cabs2(v);
+        }
+        mv = wave_max(mv);
+        if (lane == 0) wm[wave * G + g] = mv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        double t = wm[g];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) t = fmax(t, wm[w * G + g]);
+        mx[g] = t;
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // ACA phase, small faces: R and S = sum_q u_q w_q^T in registers, E = MNMAX / NT entries
 // per thread (entry idx = tid + NT t), updated in place by the rank-1 steps; only the current
@@ -449,6 +648,98 @@ __global__ void __launch_bounds__(NT)
     double s2 = 0.0;
     const int splitw = max(1, NT / n), splitu = max(1, NT / m);
     bool fin = false;   // the face ACA has ended (else the general path continues it)
+    int fu = 0;   // every row below fu is used
+    // the zero-row search after the first cross (see scan_unused): the row it ends at, or m
+    auto zero_run = [&]() -> int {
+        if constexpr (PATH == 2) {
+            // candidates per pass: G NE accumulators per thread (register budget)
+            auto pass = [&](auto gc, auto ec) -> int {
+                constexpr int G = decltype(gc)::value, NE = decltype(ec)::value;
+                constexpr int CH = (int)(kBV * sizeof(double2) / sizeof(FT)) / G;
+                __syncthreads();
+                int c[G];
+                const int nc = scan_unused<G>(used_row, m, fu, c);
+                if (nc == 0) return m;
+                fu = c[0];
+                double mx[G];
+                zero_rows_multi<NT, G, NE>(R, Uh, Wh, Ub, Wb, m, n, q, qL, c,
+                                           reinterpret_cast<FT *>(bvec), CH,
+                                           reinterpret_cast<double *>(xbuf), mx);
+                int gs = nc;
+#pragma unroll
+                for (int g = G - 1; g >= 0; --g)
+                    if (g < nc && !(sqrt(mx[g]) <= zero_tol)) gs = g;
+                if (tid == 0)
+#pragma unroll
+                    for (int g = 0; g < G; ++g)
+                        if (g < gs) used_row[c[g]] = 1;
+                nused += gs;
+                if (gs < nc) {
+                    int r = c[0];
+#pragma unroll
+                    for (int g = 1; g < G; ++g)
+                        if (g == gs) r = c[g];
+                    return r;
+                }
+                return nc < G ? m : -1;
+            };
+            using std::integral_constant;
+            const int ne = min(kMultiE, (n + NT - 1) / NT);
+            while (true) {
+                int r;
+                if (ne <= 1) r = pass(integral_constant<int, MIXED ? 8 : 4>{}, integral_constant<int, 1>{});
+                else if (ne == 2) r = pass(integral_constant<int, MIXED ? 8 : 4>{}, integral_constant<int, 2>{});
+                else if (ne == 3) r = pass(integral_constant<int, MIXED ? 6 : 3>{}, integral_constant<int, 3>{});
+                else if (ne == 4) r = pass(integral_constant<int, MIXED ? 5 : 2>{}, integral_constant<int, 4>{});
+                else r = pass(integral_constant<int, MIXED ? 4 : 2>{}, integral_constant<int, kMultiE>{});
+                if (r >= 0) return r;
+            }
+        } else {
+            constexpr int G = MIXED ? 4 : 2;
+            if (NT > kCoefLds || q > qL + kCoefLds) return first_unused<NT>(used_row, m, red);
+            FT *cs = reinterpret_cast<FT *>(bvec);   // [G][kCoefLds]
+            FT *pp[G];                               // [G][< NT] group partials
+            if constexpr (MIXED) {
+                pp[0] = part;
+                pp[1] = cbuf;
+                pp[2] = reinterpret_cast<FT *>(xbuf);
+                pp[3] = pp[2] + NT;
+            } else {
+                pp[0] = part;
+                pp[1] = reinterpret_cast<FT *>(xbuf);
+            }
+            while (true) {
+                __syncthreads();
+                int c[G];
+                const int nc = scan_unused<G>(used_row, m, fu, c);
+                if (nc == 0) return m;
+                fu = c[0];
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    for (int k = tid; k < q - qL; k += NT) cs[g * kCoefLds + k] = Ub[(int64_t)(qL + k) * m + c[g]];
+                __syncthreads();
+                double mx[G];
+                zero_rows_split<NT, G>(R, Uh, Wh, Wb, m, n, q, qL, splitw, c, cs, pp, redbuf, mx);
+                int gs = nc;
+#pragma unroll
+                for (int g = G - 1; g >= 0; --g)
+                    if (g < nc && !(sqrt(mx[g]) <= zero_tol)) gs = g;
+                if (tid == 0)
+#pragma unroll
+                    for (int g = 0; g < G; ++g)
+                        if (g < gs) used_row[c[g]] = 1;
+                nused += gs;
+                if (gs < nc) {
+                    int r = c[0];
+#pragma unroll
+                    for (int g = 1; g < G; ++g)
+                        if (g == gs) r = c[g];
+                    return r;
+                }
+                if (nc < G) return m;
+            }
+        }
+    };
     if constexpr (PATH == 1) {
         fin = true;
         // One row entry and one column entry per thread, kept in registers.  The cross terms
@@ -489,7 +780,7 @@ __global__ void __launch_bounds__(NT)
                     for (int r = i + 1 + tid; r < cand; r += NT) used_row[r] = 1;
                     nused += cand - (i + 1);
                 } else {
-                    cand = first_unused<NT>(used_row, m, red);
+                    cand = P.zero_batch ? zero_run() : first_unused<NT>(used_row, m, red);
                 }
                 if (cand >= m) break;
                 i = cand;
@@ -688,7 +979,7 @@ __global__ void __launch_bounds__(NT)
                     for (int r = i + 1 + tid; r < cand; r += NT) used_row[r] = 1;
                     nused += cand - (i + 1);
                 } else {
-                    cand = first_unused<NT>(used_row, m, red);
+                    cand = P.zero_batch ? zero_run() : first_unused<NT>(used_row, m, red);
                 }
                 if (cand >= m) {
                     fin = true;

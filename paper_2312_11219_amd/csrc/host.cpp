@@ -34,6 +34,7 @@ void options_default(gaca_options *o) {
     o->threads_small = 128;
     o->threads_large = 0;
     o->verbose = 0;
+    o->zero_rows_batch = 1;
 }
 
 // ---- Gauss-Legendre on [0, 1] by Newton iteration on the Legendre recurrence ----------

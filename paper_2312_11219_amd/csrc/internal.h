@@ -115,7 +115,7 @@ struct AcaParams {
     int32_t rcap;              // crosses per block
     int32_t kernel;            // 0 SLP, 1 DLP
     int32_t galerkin;          // 1 Galerkin
-    int32_t _pad;
+    int32_t zero_batch;        // several rows per pass in the large-face zero-row search
 };
 
 }  // namespace gaca

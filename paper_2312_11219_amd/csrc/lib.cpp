@@ -878,6 +878,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
     for (gaca_hmatrix *hh : H) hh->eps_aca_used = P.eps_aca;
     P.rcap = rcap;
     P.kernel = fk;
+    P.zero_batch = p->opt.zero_rows_batch != 0;
 
     // block descriptors, launch classes and memory estimates
     std::vector<FarBlockDev> desc(ntot);

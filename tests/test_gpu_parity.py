@@ -319,3 +319,34 @@ def test_joint_build_matches_separate(precision):
         torch.cuda.synchronize()
         np.testing.assert_array_equal(ys.cpu().numpy(), yj.cpu().numpy())
     log(f"joint build ({precision}) matches separate builds on {far.shape[0]} far blocks")
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision,delta", [("mixed", None), ("fp64", 1e-7)])
+def test_zero_row_batch_matches_one_row(precision, delta):
+    """After a zero row the face ACA tries the unused rows in index order (partial-pivot ACA
+    of the faces, Sec. 4).  The large-face kernels try several rows per pass over the history;
+    the operator must be bitwise the one of the one-row-per-pass search.  20480-triangle
+    sphere, L = 128: its mixed build walks millions of zero rows on faces of both large-face
+    layouts; the FP64 case raises the zero threshold to 1e-7 to walk them in FP64 too."""
+    import torch
+    from inputs import random_rhs
+    kw = dict(precision=precision)
+    if delta is not None:
+        kw["delta_zero"] = delta
+    _, pb, (xyz, tri, s) = gpu_problem("C3", zero_rows_batch=1, **kw)
+    _, p1, _ = gpu_problem("C3", zero_rows_batch=0, **kw)
+    hb, h1 = pb.build("slp"), p1.build("slp")
+    sb, s1 = hb.stats(), h1.stats()
+    for key in ("n_far", "rank_min", "rank_max", "rank_mean", "face_rank_max", "face_rank_mean",
+                "entries_face", "entries_fibre", "n_capped", "n_zero_blocks", "bytes_far"):
+        assert sb[key] == s1[key], key
+    far, _ = pb.blocks()
+    for b in range(0, far.shape[0], max(1, far.shape[0] // 40)):
+        assert hb.export_block(b)["rank"] == h1.export_block(b)["rank"]
+    X = torch.from_numpy(random_rhs(len(s), tri.shape[0], 2, seed=11)).cuda()
+    yb, y1 = hb.apply(X, mode="sum"), h1.apply(X, mode="sum")
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(yb.cpu().numpy(), y1.cpu().numpy())
+    log(f"zero-row batch ({precision}) matches the one-row search: {far.shape[0]} far blocks, "
+        f"build {sb['ms_far']:.0f} ms vs {s1['ms_far']:.0f} ms")
