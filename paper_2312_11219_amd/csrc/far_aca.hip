@@ -259,23 +259,25 @@ __device__ int scan_unused(const unsigned char *used, int m, int r0, int (&c)[G]
 
 // Multi-entry layout (entries j = tid + NT e, e < NE): max_j |R(c_g, j) - sum_{q'<q}
 // u_q'[c_g] w_q'[j]|^2 for each candidate, as one chain over q' per entry; the u
-// coefficients of the HBM history are staged CH steps at a time in cs ([G][CH]); wm holds
-// NW * G doubles.  mx[g] is the same in every thread.
-template <int NT, int G, int NE, class FT>
+// coefficients of the HBM history are staged CH steps at a time in cs ([G][CH]), the w rows
+// are loaded QZ steps at a time; wm holds NW * G doubles.  mx[g] is the same in every thread.
+template <int NT, int G, int NE, int QZ, class FT>
 __device__ void zero_rows_multi(const FT *R, const FT *Uh, const FT *Wh, const FT *Ub,
                                 const FT *Wb, int m, int n, int q, int qL, const int (&c)[G],
                                 FT *cs, int CH, double *wm, double (&mx)[G]) {
     constexpr int NW = NT / 64;
-    constexpr int QZ = 2;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     int jj[NE];
 #pragma unroll
     for (int e = 0; e < NE; ++e) jj[e] = min(tid + NT * e, n - 1);
-    FT acc[G][NE];
+    FT rv[G][NE], acc[G][NE];
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int e = 0; e < NE; ++e) acc[g][e] = czero<FT>();
+        for (int e = 0; e < NE; ++e) {
+            rv[g][e] = R[(int64_t)c[g] * n + jj[e]];
+            acc[g][e] = czero<FT>();
+        }
     const int qm = min(q, qL);
     for (int qq = 0; qq < qm; ++qq) {
         FT x[NE];
@@ -323,7 +325,7 @@ __device__ void zero_rows_multi(const FT *R, const FT *Uh, const FT *Wh, const F
         double mv = 0.0;
 #pragma unroll
         for (int e = 0; e < NE; ++e)
-            if (tid + NT * e < n) mv = fmax(mv, cabs2(csub(R[(int64_t)c[g] * n + jj[e]], acc[g][e])));
+            if (tid + NT * e < n) mv = fmax(mv, cabs2(csub(rv[g][e], acc[g][e])));
         mv = wave_max(mv);
         if (lane == 0) wm[wave * G + g] = mv;
     }
@@ -340,18 +342,22 @@ __device__ void zero_rows_multi(const FT *R, const FT *Uh, const FT *Wh, const F
 // One-entry layout with the history split over splitw thread groups (m, n <= NT): thread
 // (s, j) sums steps [q s / splitw, q (s + 1) / splitw) in two interleaved accumulators,
 // exactly as the row pass's history dot product does (LDS part in pairs, HBM part in groups
-// of NB with the u coefficients from cs = [G][kCoefLds], q <= qL + kCoefLds); the group
-// partials s >= 1 go through pp[g], and the row is R - p_0 - p_1 - ... as in the row pass.
-template <int NT, int G, class FT>
+// of NB with the u coefficients from cs = [G][kCoefLds], q <= qL + kCoefLds; PF: the next
+// group loaded during the arithmetic of this one); the group partials s >= 1 go through
+// pp[g], and the row is R - p_0 - p_1 - ... as in the row pass.
+template <int NT, int G, bool PF, class FT>
 __device__ void zero_rows_split(const FT *R, const FT *Uh, const FT *Wh, const FT *Wb, int m,
                                 int n, int q, int qL, int splitw, const int (&c)[G],
                                 const FT *cs, FT *const (&pp)[G], double *wm, double (&mx)[G]) {
     constexpr int NW = NT / 64;
     constexpr int NB = NT >= 1024 ? 4 : 16;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    FT p[G];
+    FT p[G], rv[G];
 #pragma unroll
-    for (int g = 0; g < G; ++g) p[g] = czero<FT>();
+    for (int g = 0; g < G; ++g) {
+        p[g] = czero<FT>();
+        rv[g] = tid < n ? R[(int64_t)c[g] * n + tid] : czero<FT>();
+    }
     if (tid < splitw * n) {
         const int s = tid / n, j = tid - s * n;
         const int q0 = (int)((int64_t)q * s / splitw), q1 = (int)((int64_t)q * (s + 1) / splitw);
@@ -374,17 +380,39 @@ __device__ void zero_rows_split(const FT *R, const FT *Uh, const FT *Wh, const F
             for (int g = 0; g < G; ++g) a0[g] = cfma(Uh[qq * m + c[g]], x0, a0[g]);
         }
         qq = max(q0, qL);
-        for (; qq + NB <= q1; qq += NB) {
-            FT bv[NB];
+        auto ld = [&](FT (&bv)[NB], int qs) {
 #pragma unroll
-            for (int t = 0; t < NB; ++t) bv[t] = Wb[(int64_t)(qq + t) * n + j];
+            for (int t = 0; t < NB; ++t) bv[t] = Wb[(int64_t)(qs + t) * n + j];
+        };
+        auto fm = [&](const FT (&bv)[NB], int qs) {
 #pragma unroll
             for (int t = 0; t < NB; t += 2)
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    a0[g] = cfma(cs[g * kCoefLds + qq + t - qL], bv[t], a0[g]);
-                    a1[g] = cfma(cs[g * kCoefLds + qq + t + 1 - qL], bv[t + 1], a1[g]);
+                    a0[g] = cfma(cs[g * kCoefLds + qs + t - qL], bv[t], a0[g]);
+                    a1[g] = cfma(cs[g * kCoefLds + qs + t + 1 - qL], bv[t + 1], a1[g]);
                 }
+        };
+        if constexpr (PF) {
+            // the next group's loads in flight during this group's arithmetic
+            const int ng = max(0, (q1 - qq) / NB);
+            FT ba[NB], bb[NB];
+            if (ng > 0) ld(ba, qq);
+            for (int gi = 0; gi < ng; gi += 2) {
+                if (gi + 1 < ng) ld(bb, qq + (gi + 1) * NB);
+                fm(ba, qq + gi * NB);
+                if (gi + 1 < ng) {
+                    if (gi + 2 < ng) ld(ba, qq + (gi + 2) * NB);
+                    fm(bb, qq + (gi + 1) * NB);
+                }
+            }
+            qq += ng * NB;
+        } else {
+            for (; qq + NB <= q1; qq += NB) {
+                FT bv[NB];
+                ld(bv, qq);
+                fm(bv, qq);
+            }
         }
         for (; qq < q1; ++qq) {
             const FT x0 = Wb[(int64_t)qq * n + j];
@@ -402,7 +430,7 @@ __device__ void zero_rows_split(const FT *R, const FT *Uh, const FT *Wh, const F
     for (int g = 0; g < G; ++g) {
         double mv = 0.0;
         if (tid < n) {
-            FT v = csub(R[(int64_t)c[g] * n + tid], p[g]);
+            FT v = csub(rv[g], p[g]);
             for (int t = 1; t < splitw; ++t) v = csub(v, pp[g][(t - 1) * n + tid]);
             mv = cabs2(v);
         }
@@ -662,7 +690,7 @@ __global__ void __launch_bounds__(NT)
                 if (nc == 0) return m;
                 fu = c[0];
                 double mx[G];
-                zero_rows_multi<NT, G, NE>(R, Uh, Wh, Ub, Wb, m, n, q, qL, c,
+                zero_rows_multi<NT, G, NE, MIXED ? 8 : 4>(R, Uh, Wh, Ub, Wb, m, n, q, qL, c,
                                            reinterpret_cast<FT *>(bvec), CH,
                                            reinterpret_cast<double *>(xbuf), mx);
                 int gs = nc;
@@ -719,7 +747,7 @@ __global__ void __launch_bounds__(NT)
                     for (int k = tid; k < q - qL; k += NT) cs[g * kCoefLds + k] = Ub[(int64_t)(qL + k) * m + c[g]];
                 __syncthreads();
                 double mx[G];
-                zero_rows_split<NT, G>(R, Uh, Wh, Wb, m, n, q, qL, splitw, c, cs, pp, redbuf, mx);
+                zero_rows_split<NT, G, MIXED>(R, Uh, Wh, Wb, m, n, q, qL, splitw, c, cs, pp, redbuf, mx);
                 int gs = nc;
 #pragma unroll
                 for (int g = G - 1; g >= 0; --g)
