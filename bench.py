@@ -27,6 +27,26 @@ FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 PHASES = ["face", "aca", "expand", "tail"]
 KID = {"slp": 0, "dlp": 1}
+# HBM traffic of the dominant kernel from hardware counters, taken with the kernel source
+# whose SHA-256 is stored beside it; any later change of that source voids the figure
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "far_aca_large_cube3072_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2312_11219_amd", "csrc", "far_aca.hip")
+
+
+def measured_traffic(kernel_name):
+    """Bytes per launch of kernel_name from the stored counter runs, or None when there are
+    none for it or its source has changed since."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+        with open(KERNEL_SOURCE, "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != sha or not kernel_name.startswith(rec.get("kernel", "\0")):
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def dominant_kernels(kernels, all_stats):
@@ -69,6 +89,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    # counter calibration: one y = 1.0 * x pass over this many bytes of FP32 before the
+    # warm-up (a kernel of known traffic for the FETCH_SIZE / WRITE_SIZE scale)
+    ap.add_argument("--copy-calibration", type=int, default=0)
     return ap.parse_args()
 
 
@@ -247,6 +270,14 @@ def main():
         del hs
         return out
 
+    if args.copy_calibration > 0:
+        n = args.copy_calibration // 4
+        xc = torch.ones(n, dtype=torch.float32, device=dev)
+        yc = torch.empty_like(xc)
+        torch.cuda.synchronize()
+        torch.mul(xc, 1.0, out=yc)
+        torch.cuda.synchronize()
+        del xc, yc
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -306,7 +337,7 @@ def main():
         "aca_block_max_ms": {k: st["ms_far_aca_block_max"] for k, st in zip(kernels, last)},
         "roofline": {"bound": "alu", "kernel": dom_name,
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(dom_name),
                      "launches_per_step": dom["launches"],
                      "ms_per_launch": dom["ms"] / max(1, dom["launches"])},
     }
