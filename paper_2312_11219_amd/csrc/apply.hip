@@ -40,7 +40,10 @@ __global__ void scatter_y_kernel(const XT *Yp, XT *Y, const int64_t *perm, int n
     Y[(l * M + perm[p]) * nrhs + c] = Yp[t];
 }
 
-// SUM: T = sum_k f_l[k] X_k[tau] (n x nrhs), z_l = W_l^T T for every cross of block b.
+// SUM: T_l = sum_k f_l[k] X_k[tau] (n x nrhs), z_l = W_l^T T_l for every cross of block b,
+// kApplyCB crosses at a time: each X_k[tau] element is read once per group of crosses, and
+// z_l's rows are dot products over j taken by 8 lanes each (W rows read in order, partial
+// sums added by a fixed butterfly).
 // PER_FREQ: v_l[q][k][c] = sum_j W_l[q][j] X_k[tau_j][c].
 template <class FacT, class XT>
 __global__ void __launch_bounds__(256) apply_far_a_kernel(ApplyDev a, int mode, const XT *Xp,
@@ -54,44 +57,105 @@ __global__ void __launch_bounds__(256) apply_far_a_kernel(ApplyDev a, int mode, 
     XT *T = tbuf + t_off[b];
     const FacT *arena = reinterpret_cast<const FacT *>(a.arena);
     const double2 *F = a.fib_arena + a.fib_off[b];
+    if (mode == 0) {
+        constexpr int CB = kApplyCB;
+        __shared__ int64_t s_w[CB], s_z[CB];
+        __shared__ int s_rho[CB + 1];
+        __shared__ XT s_f[CB * kApplyKF];
+        const int nt = n * nr;
+        int64_t zo = 0;
+        for (int cg = 0; cg < mt.rank; cg += CB) {
+            const int cb = min(CB, mt.rank - cg);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int rows = 0;
+                for (int c = 0; c < cb; ++c) {
+                    const CrossMeta cm = a.cmeta[(int64_t)b * a.rcap + cg + c];
+                    s_w[c] = a.cross_off[(int64_t)b * a.rcap + cg + c] + (int64_t)cm.rho * m;
+                    s_z[c] = zo;
+                    s_rho[c] = rows;
+                    rows += cm.rho;
+                    zo += (int64_t)cm.rho * nr;
+                }
+                s_rho[cb] = rows;
+            }
+            // T_c for the crosses of the group ([c][j][rhs]); the fibres pass through LDS
+            // kApplyKF frequencies at a time
+            for (int t0 = 0; t0 < nt; t0 += blockDim.x) {
+                const int t = t0 + threadIdx.x;
+                const int j = t / nr, cc = t - j * nr;
+                const XT *xp = Xp + (int64_t)(c0 + min(j, n - 1)) * nr + cc;
+                XT acc[CB];
+#pragma unroll
+                for (int c = 0; c < CB; ++c) acc[c] = czero<XT>();
+                for (int k0 = 0; k0 < L; k0 += kApplyKF) {
+                    const int nk = min(kApplyKF, L - k0);
+                    __syncthreads();
+                    for (int i = threadIdx.x; i < cb * nk; i += blockDim.x) {
+                        const int c = i / nk, kk = i - c * nk;
+                        s_f[c * kApplyKF + kk] = cast_c<XT>(F[(int64_t)(cg + c) * L + k0 + kk]);
+                    }
+                    __syncthreads();
+#pragma unroll 8
+                    for (int kk = 0; kk < nk; ++kk) {
+                        const XT x = xp[(int64_t)(k0 + kk) * M * nr];
+#pragma unroll
+                        for (int c = 0; c < CB; ++c)
+                            if (c < cb) acc[c] = cfma(s_f[c * kApplyKF + kk], x, acc[c]);
+                    }
+                }
+                if (t < nt)
+#pragma unroll
+                    for (int c = 0; c < CB; ++c)
+                        if (c < cb) T[(int64_t)c * nt + t] = acc[c];
+            }
+            __syncthreads();
+            // z rows (cross c, step q) of the group, 8 lanes per row and right-hand side
+            const int rows = s_rho[cb];
+            const int l8 = threadIdx.x & 7;
+            for (int g = threadIdx.x >> 3; g < rows * nr; g += blockDim.x >> 3) {
+                const int ri = g / nr, cc = g - ri * nr;
+                int c = 0;
+                while (c + 1 < cb && s_rho[c + 1] <= ri) ++c;
+                const int q = ri - s_rho[c];
+                const FacT *w = arena + s_w[c] + (int64_t)q * n;
+                const XT *tc = T + (int64_t)c * nt + cc;
+                XT acc = czero<XT>();
+#pragma unroll 4
+                for (int j = l8; j < n; j += 8) acc = cfma(cast_c<XT>(w[j]), tc[(int64_t)j * nr], acc);
+                double ax = acc.x, ay = acc.y;
+#pragma unroll
+                for (int o = 4; o > 0; o >>= 1) {
+                    ax += __shfl_xor(ax, o, 8);
+                    ay += __shfl_xor(ay, o, 8);
+                }
+                if (l8 == 0) {
+                    XT r;
+                    r.x = ax;
+                    r.y = ay;
+                    z[s_z[c] + (int64_t)q * nr + cc] = r;
+                }
+            }
+        }
+        return;
+    }
     int64_t zo = 0;
     for (int c = 0; c < mt.rank; ++c) {
         const CrossMeta cm = a.cmeta[(int64_t)b * a.rcap + c];
         const FacT *W = arena + a.cross_off[(int64_t)b * a.rcap + c] + (int64_t)cm.rho * m;
-        if (mode == 0) {
-            for (int64_t t = threadIdx.x; t < (int64_t)n * nr; t += blockDim.x) {
-                const int j = (int)(t / nr), cc = (int)(t - (int64_t)j * nr);
-                XT acc = czero<XT>();
-                for (int k = 0; k < L; ++k)
-                    acc = cfma(cast_c<XT>(F[(int64_t)c * L + k]),
-                               Xp[((int64_t)k * M + c0 + j) * nr + cc], acc);
-                T[t] = acc;
-            }
-            __syncthreads();
-            for (int64_t t = threadIdx.x; t < (int64_t)cm.rho * nr; t += blockDim.x) {
-                const int qq = (int)(t / nr), cc = (int)(t - (int64_t)qq * nr);
-                XT acc = czero<XT>();
-                for (int j = 0; j < n; ++j)
-                    acc = cfma(cast_c<XT>(W[(int64_t)qq * n + j]), T[(int64_t)j * nr + cc], acc);
-                z[zo + t] = acc;
-            }
-            __syncthreads();
-            zo += (int64_t)cm.rho * nr;
-        } else {
-            const int64_t cnt = (int64_t)cm.rho * L * nr;
-            for (int64_t t = threadIdx.x; t < cnt; t += blockDim.x) {
-                const int cc = (int)(t % nr);
-                const int64_t rest = t / nr;
-                const int k = (int)(rest % L);
-                const int qq = (int)(rest / L);
-                XT acc = czero<XT>();
-                for (int j = 0; j < n; ++j)
-                    acc = cfma(cast_c<XT>(W[(int64_t)qq * n + j]),
-                               Xp[((int64_t)k * M + c0 + j) * nr + cc], acc);
-                z[zo + t] = acc;
-            }
-            zo += cnt;
+        const int64_t cnt = (int64_t)cm.rho * L * nr;
+        for (int64_t t = threadIdx.x; t < cnt; t += blockDim.x) {
+            const int cc = (int)(t % nr);
+            const int64_t rest = t / nr;
+            const int k = (int)(rest % L);
+            const int qq = (int)(rest / L);
+            XT acc = czero<XT>();
+            for (int j = 0; j < n; ++j)
+                acc = cfma(cast_c<XT>(W[(int64_t)qq * n + j]),
+                           Xp[((int64_t)k * M + c0 + j) * nr + cc], acc);
+            z[zo + t] = acc;
         }
+        zo += cnt;
     }
 }
 
@@ -112,6 +176,7 @@ __global__ void __launch_bounds__(256) apply_far_y_kernel(ApplyDev a, const XT *
         for (int c = 0; c < mt.rank; ++c) {
             const CrossMeta cm = a.cmeta[(int64_t)b * a.rcap + c];
             const FacT *U = arena + a.cross_off[(int64_t)b * a.rcap + c];
+#pragma unroll 8
             for (int qq = 0; qq < cm.rho; ++qq)
                 acc = cfma(cast_c<XT>(U[(int64_t)qq * m + r]), z[zo + (int64_t)qq * nr + cc], acc);
             zo += (int64_t)cm.rho * nr;
@@ -120,58 +185,69 @@ __global__ void __launch_bounds__(256) apply_far_y_kernel(ApplyDev a, const XT *
     }
 }
 
-// SUM per leaf: Y[leaf rows] = sum over covering far blocks of y_b rows + near blocks'
-// sum_k N_k X_k.  Outputs (row, rhs) are split over S thread groups that each take a
-// share of the (near block, frequency) pairs; partial sums are added in a fixed order.
-template <class NearT, class XT>
+// SUM per row: Y[row] = sum over the leaf's near blocks of sum_k N_k[row] X_k + the rows
+// y_b of the covering far blocks.  One wave per row: a near block stores row ro as L n
+// contiguous entries ([m][L][n]), which the lanes read in order (entry t: frequency t / n,
+// column t % n); RC right-hand sides per pass, lane sums added by a fixed-order wave
+// reduction.  Grid (leaf, rows / 4).
+template <class NearT, class XT, int RC>
 __global__ void __launch_bounds__(256) apply_leaf_sum_kernel(ApplyDev a, const XT *Xp,
                                                              const XT *ybuf, const int64_t *y_off,
                                                              XT *Yp) {
-    __shared__ XT part[256];
     const int leaf = blockIdx.x;
-    const int lr0 = a.leaf_r0[leaf], lm = a.leaf_m[leaf];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = blockIdx.y * 4 + wave;
+    if (r >= a.leaf_m[leaf]) return;   // the whole wave; no workgroup barrier below
+    const int row = a.leaf_r0[leaf] + r;
     const int L = a.L, nr = a.nrhs;
     const int64_t M = a.M;
-    const int O = lm * nr;
     const int np0 = a.leaf_near_ptr[leaf], np1 = a.leaf_near_ptr[leaf + 1];
+    const int fp0 = a.leaf_far_ptr[leaf], fp1 = a.leaf_far_ptr[leaf + 1];
     const NearT *nearv = a.near64 ? reinterpret_cast<const NearT *>(a.near64)
                                   : reinterpret_cast<const NearT *>(a.near32);
-    for (int o0 = 0; o0 < O; o0 += 256) {
-        const int Oc = min(256, O - o0);
-        const int S = max(1, 256 / Oc);
-        const int t = threadIdx.x;
-        const int s = t / Oc, o = o0 + (t - s * Oc);
-        XT acc = czero<XT>();
-        if (s < S) {
-            const int r = o / nr, cc = o - r * nr;
-            const int row = lr0 + r;
-            const int npairs = (np1 - np0) * L;
-            for (int e = s; e < npairs; e += S) {
-                const NearBlockDev nb = a.nblocks[a.leaf_near_idx[np0 + e / L]];
-                const int k = e - (e / L) * L;
-                const int ro = row - nb.r0;
-                const NearT *nrow = nearv + nb.off + ((int64_t)ro * L + k) * nb.n;
-                const XT *xk = Xp + ((int64_t)k * M + nb.c0) * nr + cc;
-                for (int j = 0; j < nb.n; ++j)
-                    acc = cfma(cast_c<XT>(nrow[j]), xk[(int64_t)j * nr], acc);
-            }
-            if (s == 0) {
-                for (int e = a.leaf_far_ptr[leaf]; e < a.leaf_far_ptr[leaf + 1]; ++e) {
-                    const int b = a.leaf_far_idx[e];
-                    const int ro = row - a.far4[4 * b];
-                    acc = cadd(acc, ybuf[y_off[b] + (int64_t)ro * nr + cc]);
+    for (int cr = 0; cr < nr; cr += RC) {
+        XT acc[RC];
+#pragma unroll
+        for (int c = 0; c < RC; ++c) acc[c] = czero<XT>();
+        for (int e = np0; e < np1; ++e) {
+            const NearBlockDev nb = a.nblocks[a.leaf_near_idx[e]];
+            const int n = nb.n, E = L * n;
+            const NearT *base = nearv + nb.off + (int64_t)(row - nb.r0) * E;
+            const XT *xb = Xp + (int64_t)nb.c0 * nr + cr;
+            // (k, j) of entry t = lane + 64 i, advanced by 64 entries per step
+            int k = lane / n, j = lane - k * n;
+            const int dk = 64 / n, dj = 64 - dk * n;
+            for (int t = lane; t < E; t += 64) {
+                const XT nv = cast_c<XT>(base[t]);
+                const XT *xp = xb + ((int64_t)k * M + j) * nr;
+#pragma unroll
+                for (int c = 0; c < RC; ++c)
+                    if (cr + c < nr) acc[c] = cfma(nv, xp[c], acc[c]);
+                k += dk;
+                j += dj;
+                if (j >= n) {
+                    j -= n;
+                    ++k;
                 }
             }
         }
-        part[t] = acc;
-        __syncthreads();
-        if (t < Oc) {
-            XT tot = part[t];
-            for (int q = 1; q < S; ++q) tot = cadd(tot, part[q * Oc + t]);
-            const int r = (o0 + t) / nr, cc = (o0 + t) - r * nr;
-            Yp[(int64_t)(lr0 + r) * nr + cc] = tot;
+#pragma unroll
+        for (int c = 0; c < RC; ++c) {
+            const double sx = wave_sum((double)acc[c].x), sy = wave_sum((double)acc[c].y);
+            acc[c].x = sx;
+            acc[c].y = sy;
         }
-        __syncthreads();
+        if (lane < RC && cr + lane < nr) {
+            XT tot = acc[0];
+#pragma unroll
+            for (int c = 1; c < RC; ++c)
+                if (lane == c) tot = acc[c];
+            for (int e = fp0; e < fp1; ++e) {
+                const int b = a.leaf_far_idx[e];
+                tot = cadd(tot, ybuf[y_off[b] + (int64_t)(row - a.far4[4 * b]) * nr + cr + lane]);
+            }
+            Yp[(int64_t)row * nr + cr + lane] = tot;
+        }
     }
 }
 
@@ -233,7 +309,13 @@ static void apply_impl(const ApplyDev &a, int mode, const XT *X, XT *Y, XT *Xp, 
     const int nl = mode == 0 ? 1 : a.L;
     if (mode == 0) {
         if (a.nfar > 0) apply_far_y_kernel<FacT, XT><<<a.nfar, 256, 0, st>>>(a, zbuf, ybuf, y_off);
-        apply_leaf_sum_kernel<FacT, XT><<<a.nleaf, 256, 0, st>>>(a, Xp, ybuf, y_off, Yp);
+        const dim3 grid(a.nleaf, (a.max_leaf_m + 3) / 4);
+        if (a.nrhs == 1)
+            apply_leaf_sum_kernel<FacT, XT, 1><<<grid, 256, 0, st>>>(a, Xp, ybuf, y_off, Yp);
+        else if (a.nrhs == 2)
+            apply_leaf_sum_kernel<FacT, XT, 2><<<grid, 256, 0, st>>>(a, Xp, ybuf, y_off, Yp);
+        else
+            apply_leaf_sum_kernel<FacT, XT, 4><<<grid, 256, 0, st>>>(a, Xp, ybuf, y_off, Yp);
     } else {
         apply_leaf_freq_kernel<FacT, FacT, XT><<<dim3(a.nleaf, nl), 256, 0, st>>>(a, Xp, zbuf, Yp);
     }

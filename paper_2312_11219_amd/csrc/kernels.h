@@ -117,6 +117,8 @@ void launch_eval(int kernel, const GeoDev &g, const QuadDev &q, const FreqDev &f
                  const int32_t *tiers, double2 *out, hipStream_t st);
 
 // Apply (FP64, VALU reference path).
+constexpr int kApplyCB = 8;   // crosses per T = F X group of the VALU SUM apply (T workspace)
+constexpr int kApplyKF = 64;  // fibre entries per LDS stage of that group
 struct ApplyDev {
     int32_t L, nrhs;
     int64_t M;
@@ -134,7 +136,7 @@ struct ApplyDev {
     const double2 *near64;
     const float2 *near32;
     // leaf CSR: leaf -> covering far blocks / near blocks
-    int32_t nleaf;
+    int32_t nleaf, max_leaf_m;
     const int32_t *leaf_r0, *leaf_m;
     const int32_t *leaf_far_ptr, *leaf_far_idx;
     const int32_t *leaf_near_ptr, *leaf_near_idx;

@@ -1821,7 +1821,9 @@ static void alloc_apply_workspace(gaca_hmatrix *h, gaca_apply_mode mode, int32_t
                 yacc += p->part.far[b][1] * (int64_t)nrhs;
                 const int64_t sr = h->meta[b].sum_rho;
                 zacc += mode == GACA_APPLY_SUM ? sr * nrhs : sr * (int64_t)L * nrhs;
-                tacc += mode == GACA_APPLY_SUM ? p->part.far[b][3] * (int64_t)nrhs : 0;
+                tacc += mode == GACA_APPLY_SUM ? std::min<int64_t>(h->meta[b].rank, kApplyCB) *
+                                                     p->part.far[b][3] * (int64_t)nrhs
+                                               : 0;
             }
             h->d_zoff.upload(ctx, zoff);
             h->d_toff.upload(ctx, toff);
@@ -2077,6 +2079,8 @@ gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, cons
         a.near64 = h->prec == GACA_MIXED ? nullptr : h->d_near.as<double2>();
         a.near32 = h->prec == GACA_MIXED ? h->d_near.as<float2>() : nullptr;
         a.nleaf = (int32_t)p->leaf_r0.size();
+        a.max_leaf_m = 1;
+        for (int32_t lm : p->leaf_m) a.max_leaf_m = std::max(a.max_leaf_m, lm);
         a.leaf_r0 = h->d_leaf_r0.as<int32_t>();
         a.leaf_m = h->d_leaf_m.as<int32_t>();
         a.leaf_far_ptr = h->d_lfp.as<int32_t>();
