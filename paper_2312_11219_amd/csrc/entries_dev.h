@@ -16,22 +16,24 @@ namespace gaca {
 
 constexpr double kFourPi = 12.566370614359172953850573533118;  // 4 pi
 
+constexpr double kInvFourPi = 0.079577471545947667884441881686257181;  // 1 / (4 pi)
+
 // Accumulate w * G(s, r) (SLP) or w * exp(-s r)(1 + s r)/(4 pi r^3) (DLP, numerator applied
-// by the caller) into (ar, ai).
+// by the caller) into (ar, ai); ir = 1 / r.
 template <int KERNEL>
-__device__ __forceinline__ void kacc(double r, double sre, double sim, double w, double &ar,
-                                     double &ai) {
+__device__ __forceinline__ void kacc(double r, double ir, double sre, double sim, double w,
+                                     double &ar, double &ai) {
     double mag = exp(-sre * r);
     double sn, cs;
     sincos(sim * r, &sn, &cs);
     double er = mag * cs, ei = -mag * sn;
     if (KERNEL == 0) {
-        double c = w / (kFourPi * r);
+        double c = w * kInvFourPi * ir;
         ar += c * er;
         ai += c * ei;
     } else {
         double fr = 1.0 + sre * r, fi = sim * r;
-        double c = w / (kFourPi * r * r * r);
+        double c = w * kInvFourPi * (ir * ir * ir);
         ar += c * (er * fr - ei * fi);
         ai += c * (er * fi + ei * fr);
     }
@@ -43,6 +45,23 @@ __device__ __forceinline__ double dist3(double x, double y, double z, double px,
     return sqrt(dx * dx + dy * dy + dz * dz);
 }
 
+// r = |x - p| and ir = 1 / r from one reciprocal square root: the hardware estimate of
+// d^-1/2 refined by two Newton-Raphson steps t <- t + t (1 - d t^2) / 2 (each roughly
+// doubles the correct bits), then r = d t.
+__device__ __forceinline__ double dist3_inv(double x, double y, double z, double px, double py,
+                                            double pz, double &ir) {
+    const double dx = x - px, dy = y - py, dz = z - pz;
+    const double d = dx * dx + dy * dy + dz * dz;
+    double t = __builtin_amdgcn_rsq(d);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-d * t, t, 1.0);
+        t = fma(0.5 * t, e, t);
+    }
+    ir = t;
+    return d * t;
+}
+
 // Far rule entry at one frequency for collocation point x (row element i) and element j.
 template <int KERNEL>
 __device__ __forceinline__ void entry_far6(const GeoDev &g, double x, double y, double z,
@@ -52,8 +71,9 @@ __device__ __forceinline__ void entry_far6(const GeoDev &g, double x, double y, 
     const int64_t M = g.M;
 #pragma unroll
     for (int p = 0; p < 6; ++p) {
-        double r = dist3(x, y, z, g.q6x[p * M + j], g.q6y[p * M + j], g.q6z[p * M + j]);
-        kacc<KERNEL>(r, sre, sim, g.q6w[p * M + j], ar, ai);
+        double ir;
+        double r = dist3_inv(x, y, z, g.q6x[p * M + j], g.q6y[p * M + j], g.q6z[p * M + j], ir);
+        kacc<KERNEL>(r, ir, sre, sim, g.q6w[p * M + j], ar, ai);
     }
     if (KERNEL == 1) {
         double num = g.nx[j] * x + g.ny[j] * y + g.nz[j] * z - g.d[j];
@@ -139,10 +159,11 @@ __device__ __forceinline__ void collapsed_acc(double x, double y, double z, cons
             double py = a[1] + u * e1y + uv * e2y;
             double pz = a[2] + u * e1z + uv * e2z;
             double w = wu * wv * u * two_area * wscale;
-            double r = dist3(x, y, z, px, py, pz);
+            double ir;
+            double r = dist3_inv(x, y, z, px, py, pz, ir);
 #pragma unroll
             for (int t = 0; t < NF; ++t)
-                if (t < nl) kacc<KERNEL>(r, f.re[l0 + t], f.im[l0 + t], w, ar[t], ai[t]);
+                if (t < nl) kacc<KERNEL>(r, ir, f.re[l0 + t], f.im[l0 + t], w, ar[t], ai[t]);
         }
     }
 }
@@ -165,11 +186,12 @@ __device__ void near_entry(const GeoDev &g, const QuadDev &q, const FreqDev &f, 
     if (tier == TIER_FAR6) {
         const int64_t M = g.M;
         for (int p = 0; p < 6; ++p) {
-            double r = dist3(x, y, z, g.q6x[p * M + j], g.q6y[p * M + j], g.q6z[p * M + j]);
+            double ir;
+            double r = dist3_inv(x, y, z, g.q6x[p * M + j], g.q6y[p * M + j], g.q6z[p * M + j], ir);
             double w = g.q6w[p * M + j];
 #pragma unroll
             for (int t = 0; t < NF; ++t)
-                if (t < nl) kacc<KERNEL>(r, f.re[l0 + t], f.im[l0 + t], w, ar[t], ai[t]);
+                if (t < nl) kacc<KERNEL>(r, ir, f.re[l0 + t], f.im[l0 + t], w, ar[t], ai[t]);
         }
     } else if (tier == TIER_MID4) {
         collapsed_acc<KERNEL, NF>(x, y, z, a, b, c, q.n4, q.g4, f, l0, nl, ar, ai);

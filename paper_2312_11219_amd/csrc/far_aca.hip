@@ -454,7 +454,7 @@ __device__ void zero_rows_split(const FT *R, const FT *Uh, const FT *Wh, const F
 // finds its max, norm and pivot (the Gram row against the previous faces follows in
 // far_gram_small_kernel).
 template <int NT, bool MIXED, int MNMAX, int SIDE>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT, (NT == 256 && MNMAX == 2304) ? 3 : 1)
     far_aca_small_kernel(AcaParams P, FarBatchDev bd, const FarActive *act) {
     using FT = face_t<MIXED>;
     constexpr int E = MNMAX / NT;

@@ -33,8 +33,9 @@ __device__ __forceinline__ void entry_gal36(const GeoDev &g, int64_t i, int64_t 
         const double wx = g.q6w[p * M + i];
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            const double r = dist3(x, y, z, g.q6x[q * M + j], g.q6y[q * M + j], g.q6z[q * M + j]);
-            kacc<0>(r, sre, sim, wx * g.q6w[q * M + j], ar, ai);
+            double ir;
+            const double r = dist3_inv(x, y, z, g.q6x[q * M + j], g.q6y[q * M + j], g.q6z[q * M + j], ir);
+            kacc<0>(r, ir, sre, sim, wx * g.q6w[q * M + j], ar, ai);
         }
     }
     er = ar;
@@ -142,12 +143,13 @@ __device__ __forceinline__ void gal_inner_split(const double *x, double wx, cons
             for (int iv = 0; iv < n; ++iv) {
                 const double v = gt[2 * iv], wv = gt[2 * iv + 1];
                 const double uv = u * v;
-                const double r = dist3(x[0], x[1], x[2], p[0] + u * e1x + uv * e2x,
-                                       p[1] + u * e1y + uv * e2y, p[2] + u * e1z + uv * e2z);
+                double ir;
+                const double r = dist3_inv(x[0], x[1], x[2], p[0] + u * e1x + uv * e2x,
+                                           p[1] + u * e1y + uv * e2y, p[2] + u * e1z + uv * e2z, ir);
                 const double w = wx * wu * wv * u * two_area;
 #pragma unroll
                 for (int t = 0; t < NF; ++t)
-                    if (t < nl) kacc<0>(r, f.re[l0 + t], f.im[l0 + t], w, ar[t], ai[t]);
+                    if (t < nl) kacc<0>(r, ir, f.re[l0 + t], f.im[l0 + t], w, ar[t], ai[t]);
             }
         }
     }
@@ -282,12 +284,13 @@ __device__ void gal_near_entry(const GeoDev &g, const QuadDev &q, const FreqDev 
             const double x = g.q6x[p * M + i], y = g.q6y[p * M + i], z = g.q6z[p * M + i];
             const double wx = g.q6w[p * M + i];
             for (int qq = 0; qq < 6; ++qq) {
+                double ir;
                 const double r =
-                    dist3(x, y, z, g.q6x[qq * M + j], g.q6y[qq * M + j], g.q6z[qq * M + j]);
+                    dist3_inv(x, y, z, g.q6x[qq * M + j], g.q6y[qq * M + j], g.q6z[qq * M + j], ir);
                 const double w = wx * g.q6w[qq * M + j];
 #pragma unroll
                 for (int t = 0; t < NF; ++t)
-                    if (t < nl) kacc<0>(r, f.re[l0 + t], f.im[l0 + t], w, ar[t], ai[t]);
+                    if (t < nl) kacc<0>(r, ir, f.re[l0 + t], f.im[l0 + t], w, ar[t], ai[t]);
             }
         }
         return;

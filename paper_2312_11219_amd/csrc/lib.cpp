@@ -1150,12 +1150,16 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                 return (tlx == 512 && side <= kFarMultiE * 512) ? 2 : 0;
             };
             auto prank = [&](int x) { const int pth = path(x); return pth == 0 ? 0 : pth == 2 ? 1 : 2; };
-            std::stable_sort(active.begin(), active.end(), [&](int x, int y) {
+            auto launch_order = [&](int x, int y) {
                 if (kind[base + x] != kind[base + y]) return kind[base + x] > kind[base + y];
                 if (kind[base + x] == 3 && big(x) != big(y)) return big(x);
                 if (kind[base + x] == 3 && big(x) && prank(x) != prank(y)) return prank(x) < prank(y);
                 return (int64_t)bdesc[x].m * bdesc[x].n > (int64_t)bdesc[y].m * bdesc[y].n;
-            });
+            };
+            // the keys are fixed per block and finished blocks leave in order, so after the
+            // first iteration the list is already in launch order
+            if (!std::is_sorted(active.begin(), active.end(), launch_order))
+                std::stable_sort(active.begin(), active.end(), launch_order);
             int nbig = 0, npath[3] = {0, 0, 0};
             while (nbig < (int)active.size() && kind[base + active[nbig]] == 3 && big(active[nbig]))
                 ++npath[path(active[nbig++])];
