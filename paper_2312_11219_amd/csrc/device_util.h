@@ -114,102 +114,111 @@ __device__ __forceinline__ int wave_min(int v) {
                min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
-// Workgroup reductions; buf must hold >= 4 * NT / 64 doubles of shared memory.  Every
-// call starts with a barrier, so consecutive calls may reuse the same buffer.
+// Workgroup reductions; buf must hold >= 8 * NT / 64 doubles of shared memory.  Each call
+// writes the per-wave values into one of two slots (alternating from call to call), passes
+// one barrier and reads the slot back: a slot is written again only two calls later, after
+// the barrier of the call in between, which every thread reaches only once it has read the
+// slot.  Every call holds exactly one barrier.
 template <int NT>
 struct Red {
     static constexpr int NW = NT / 64;
     double *buf;
+    int sl = 0;
+    __device__ double *slot() {
+        double *b = buf + sl;
+        sl ^= 4 * NW;
+        return b;
+    }
     __device__ double sum(double v) {
         v = wave_sum(v);
-        __syncthreads();
-        if ((threadIdx.x & 63) == 0) buf[threadIdx.x >> 6] = v;
+        double *b = slot();
+        if ((threadIdx.x & 63) == 0) b[threadIdx.x >> 6] = v;
         __syncthreads();
         double t = 0.0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) t += buf[w];
+        for (int w = 0; w < NW; ++w) t += b[w];
         return t;
     }
-    __device__ void sum3(double &a, double &b, double &c) {
+    __device__ void sum3(double &a, double &bb, double &c) {
         a = wave_sum(a);
-        b = wave_sum(b);
+        bb = wave_sum(bb);
         c = wave_sum(c);
-        __syncthreads();
+        double *b = slot();
         if ((threadIdx.x & 63) == 0) {
-            buf[3 * (threadIdx.x >> 6)] = a;
-            buf[3 * (threadIdx.x >> 6) + 1] = b;
-            buf[3 * (threadIdx.x >> 6) + 2] = c;
+            b[3 * (threadIdx.x >> 6)] = a;
+            b[3 * (threadIdx.x >> 6) + 1] = bb;
+            b[3 * (threadIdx.x >> 6) + 2] = c;
         }
         __syncthreads();
-        a = b = c = 0.0;
+        a = bb = c = 0.0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
-            a += buf[3 * w];
-            b += buf[3 * w + 1];
-            c += buf[3 * w + 2];
+            a += b[3 * w];
+            bb += b[3 * w + 1];
+            c += b[3 * w + 2];
         }
     }
     __device__ double max(double v) {
         v = wave_max(v);
+        double *b = slot();
+        if ((threadIdx.x & 63) == 0) b[threadIdx.x >> 6] = v;
         __syncthreads();
-        if ((threadIdx.x & 63) == 0) buf[threadIdx.x >> 6] = v;
-        __syncthreads();
-        double t = buf[0];
+        double t = b[0];
 #pragma unroll
-        for (int w = 1; w < NW; ++w) t = fmax(t, buf[w]);
+        for (int w = 1; w < NW; ++w) t = fmax(t, b[w]);
         return t;
     }
-    // sums of a, b, c and max of d in one round (buf: 4 NW doubles)
-    __device__ void sum3max(double &a, double &b, double &c, double &d) {
+    // sums of a, b, c and max of d in one round (4 NW doubles)
+    __device__ void sum3max(double &a, double &bb, double &c, double &d) {
         a = wave_sum(a);
-        b = wave_sum(b);
+        bb = wave_sum(bb);
         c = wave_sum(c);
         d = wave_max(d);
-        __syncthreads();
+        double *b = slot();
         if ((threadIdx.x & 63) == 0) {
-            double *o = buf + 4 * (threadIdx.x >> 6);
+            double *o = b + 4 * (threadIdx.x >> 6);
             o[0] = a;
-            o[1] = b;
+            o[1] = bb;
             o[2] = c;
             o[3] = d;
         }
         __syncthreads();
-        a = b = c = 0.0;
-        d = buf[3];
+        a = bb = c = 0.0;
+        d = b[3];
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
-            a += buf[4 * w];
-            b += buf[4 * w + 1];
-            c += buf[4 * w + 2];
-            d = fmax(d, buf[4 * w + 3]);
+            a += b[4 * w];
+            bb += b[4 * w + 1];
+            c += b[4 * w + 2];
+            d = fmax(d, b[4 * w + 3]);
         }
     }
     // max of a and sum of b in one round
-    __device__ void maxsum(double &a, double &b) {
+    __device__ void maxsum(double &a, double &bb) {
         a = wave_max(a);
-        b = wave_sum(b);
-        __syncthreads();
+        bb = wave_sum(bb);
+        double *b = slot();
         if ((threadIdx.x & 63) == 0) {
-            buf[2 * (threadIdx.x >> 6)] = a;
-            buf[2 * (threadIdx.x >> 6) + 1] = b;
+            b[2 * (threadIdx.x >> 6)] = a;
+            b[2 * (threadIdx.x >> 6) + 1] = bb;
         }
         __syncthreads();
-        a = buf[0];
-        b = 0.0;
+        a = b[0];
+        bb = 0.0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
-            a = fmax(a, buf[2 * w]);
-            b += buf[2 * w + 1];
+            a = fmax(a, b[2 * w]);
+            bb += b[2 * w + 1];
         }
     }
     __device__ int imin(int v) {
         v = wave_min(v);
+        int *b = reinterpret_cast<int *>(slot());
+        if ((threadIdx.x & 63) == 0) b[threadIdx.x >> 6] = v;
         __syncthreads();
-        if ((threadIdx.x & 63) == 0) reinterpret_cast<int *>(buf)[threadIdx.x >> 6] = v;
-        __syncthreads();
-        int t = reinterpret_cast<int *>(buf)[0];
+        int t = b[0];
 #pragma unroll
-        for (int w = 1; w < NW; ++w) t = min(t, reinterpret_cast<int *>(buf)[w]);
+        for (int w = 1; w < NW; ++w) t = min(t, b[w]);
         return t;
     }
 };

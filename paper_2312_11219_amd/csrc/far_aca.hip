@@ -474,7 +474,7 @@ __global__ void __launch_bounds__(NT, (NT == 256 && MNMAX == 2304) ? 3 : 1)
     __shared__ FT ucol[SIDE];
     __shared__ FT wrow[SIDE];
     __shared__ unsigned char used_row[SIDE];
-    __shared__ double redbuf[4 * (NT / 64) + 4];
+    __shared__ double redbuf[8 * (NT / 64) + 4];
     Red<NT> red{redbuf};
     const double tie2 = (1.0 - P.tie) * (1.0 - P.tie);
 
@@ -621,7 +621,7 @@ __global__ void __launch_bounds__(NT)
     __shared__ FT part[NT];       // split-K partial sums of row / column corrections
     __shared__ FT cbuf[kCoefLds]; // coefficients u_q'[i] / w_q'[jp] of the HBM part of the history
     __shared__ unsigned char used_row[kMaxRowsLds];
-    __shared__ double redbuf[4 * NW + 4];
+    __shared__ double redbuf[8 * NW + 4];
     __shared__ double2 xbuf[NT];  // current w (face type), then split partials of v
     __shared__ double2 bvec[kBV];  // conj <w_q, w_q'> for q' < q
     Red<NT> red{redbuf};
@@ -1513,7 +1513,7 @@ __global__ void __launch_bounds__(256)
     __shared__ unsigned char used_k[kMaxLds];
     __shared__ int64_t fsl[kMaxRcap], hsl[kMaxRcap];
     __shared__ double2 gsh[kMaxRcap], hpiv_p[kMaxRcap], coefs[kMaxRcap];
-    __shared__ double redbuf[4 * NW + 4];
+    __shared__ double redbuf[8 * NW + 4];
     Red<NT> red{redbuf};
 
     for (int kk = tid; kk < L; kk += NT) used_k[kk] = bd.usedk[(int64_t)b * L + kk];
