@@ -193,6 +193,28 @@ def test_apply_matches_exported_dense(mode):
     assert err < 1e-12
 
 
+@pytest.mark.parametrize("nrhs", [1, 2, 5])
+def test_apply_sum_matches_per_freq(nrhs):
+    """eq. (product) two ways on the 3072-triangle cube (far blocks of 3D rank up to 15, so
+    several groups of crosses per block): the SUM apply against the PER_FREQ apply summed
+    over the frequencies (separate kernels for the far part and the near rows), with 1, 2 and
+    5 right-hand sides (the last one in two passes of the row kernel)."""
+    import torch
+    from inputs import random_rhs
+    cfg, prob, (xyz, tri, s) = gpu_problem("C2")
+    h = prob.build("slp")
+    assert h.stats()["rank_max"] > 8
+    M, L = tri.shape[0], s.shape[0]
+    X = torch.from_numpy(random_rhs(L, M, nrhs, seed=21)).cuda()
+    ys = h.apply(X, mode="sum")
+    yf = h.apply(X, mode="per_freq")
+    torch.cuda.synchronize()
+    ref = yf.cpu().numpy().sum(axis=0)
+    err = rel_fro(ys.cpu().numpy(), ref)
+    log(f"sum vs per-frequency apply, {nrhs} rhs: {err:.3e}")
+    assert err < 1e-12
+
+
 def test_apply_vs_oracle_apply():
     import torch
     from inputs import random_rhs
