@@ -339,7 +339,7 @@ struct FarScratch {
     DevBuf blk, state, coef, hs, fs, usedk, uw, part, act, map_chunk, map_tile, status, copies,
         gathers;
     GrowBuf hpool, fgpool;
-    PinnedBuf h_act, h_status, h_copies, h_gathers, h_blk;
+    PinnedBuf h_act, h_status, h_copies, h_gathers, h_blk, h_out;
 };
 
 template <class F>
@@ -400,6 +400,15 @@ struct gaca_problem {
     // mapped factor / fibre arenas of destroyed H-matrices, reused by the next build (mapping
     // fresh pages costs milliseconds per GiB); guarded by spare_mu
     std::mutex spare_mu;
+    // leaf CSR of the partition (leaf -> far / near blocks covering its rows), shared by the
+    // applies of every operator of the problem
+    std::mutex leaf_mu;
+    bool leaf_ready = false;
+    DevBuf d_leaf_r0, d_leaf_m, d_lfp, d_lfi, d_lnp, d_lni;
+    // VALU apply workspace (X, Y in tree order, z, t, y) handed back by destroyed operators
+    DevBuf ws_spare[5];
+    // near-field storage handed back by destroyed operators (slot kernel & 1)
+    DevBuf near_spare[2];
     GrowBuf spare_arena[2], spare_fib[2];
     ~gaca_problem() {
         if (far_streams_ready)
@@ -425,9 +434,7 @@ struct gaca_hmatrix {
     // apply workspace
     int32_t ws_nrhs = -1, ws_mode = -1, ws_dtype = -1;
     DevBuf d_xp, d_yp, d_z, d_t, d_toff, d_zoff, d_yb, d_yoff;
-    DevBuf d_leaf_r0, d_leaf_m, d_lfp, d_lfi, d_lnp, d_lni;
     DevBuf d_mz, d_mt, d_mtitems, d_mttile0, d_mtrows, d_mzitems, d_mzoff, d_msumrho;   // matrix-core apply
-    bool leaf_ready = false;
 };
 
 // ---------------------------------------------------------------------------------------
@@ -973,18 +980,23 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
     FarScratch &W = p->fsc;
     size_t arena_used[2] = {0, 0}, fib_used[2] = {0, 0};
     // a spare arena (the same problem's last build needed about its size) is taken as it is
-    // and grows only when this build outgrows it; otherwise a new one starts at `need`
-    auto start_arena = [&](GrowBuf &dst, GrowBuf *spare, size_t need) {
+    // and grows only when this build outgrows it; otherwise a new one starts at `need`.  The
+    // spare of the same operator (slot kernel & 1) is tried first, so that the single and
+    // double layer do not trade arenas of slightly different sizes from build to build (each
+    // trade maps and unmaps chunks)
+    auto start_arena = [&](GrowBuf &dst, GrowBuf *spare, int pref, size_t need) {
         {
             std::lock_guard<std::mutex> lk(p->spare_mu);
-            for (int k = 0; k < 2 && !dst.ptr; ++k)
+            for (int t = 0; t < 2 && !dst.ptr; ++t) {
+                const int k = t == 0 ? pref : 1 - pref;
                 if (spare[k].ptr) dst.swap(spare[k]);
+            }
         }
         if (!dst.ptr) dst.start(ctx, need);
     };
     for (gaca_hmatrix *hh : H) {
-        start_arena(hh->d_arena, p->spare_arena, (size_t)std::max(1.0e5, factor_guess) * es);
-        start_arena(hh->d_fib, p->spare_fib,
+        start_arena(hh->d_arena, p->spare_arena, hh->kernel & 1, (size_t)std::max(1.0e5, factor_guess) * es);
+        start_arena(hh->d_fib, p->spare_fib, hh->kernel & 1,
                     (size_t)std::max<int64_t>(1024, nfar * (int64_t)std::min(rcap, 16) * L) * sizeof(double2));
     }
     // algorithmic work model (flops; a complex multiply-add is 8): per quadrature point x
@@ -1431,8 +1443,24 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             GACA_HIP_CHECK(hipMemcpyAsync(hh->d_fib_off.ptr, j_fib_off.as<int64_t>() + w * nfar,
                                           nfar * sizeof(int64_t), hipMemcpyDeviceToDevice, s0));
         }
-        GACA_HIP_CHECK(hipStreamSynchronize(s0));
     }
+    // result tables of every operator -> host through one pinned staging buffer, in stream
+    // order after the joint-table split, with one synchronisation
+    const size_t b_meta = nfar * sizeof(FarMeta), b_cmeta = (size_t)nfar * rcap * sizeof(CrossMeta),
+                 b_coff = (size_t)nfar * rcap * sizeof(int64_t), b_foff = nfar * sizeof(int64_t);
+    const size_t b_op = b_meta + b_cmeta + b_coff + b_foff;
+    W.h_out.ensure(std::max<size_t>(b_op * nh, 1));
+    for (int w = 0; w < nh; ++w) {
+        gaca_hmatrix *hh = H[w];
+        char *o = W.h_out.as<char>() + w * b_op;
+        GACA_HIP_CHECK(hipMemcpyAsync(o, hh->d_meta.ptr, b_meta, hipMemcpyDeviceToHost, s0));
+        GACA_HIP_CHECK(hipMemcpyAsync(o + b_meta, hh->d_cmeta.ptr, b_cmeta, hipMemcpyDeviceToHost, s0));
+        GACA_HIP_CHECK(hipMemcpyAsync(o + b_meta + b_cmeta, hh->d_cross_off.ptr, b_coff,
+                                      hipMemcpyDeviceToHost, s0));
+        GACA_HIP_CHECK(hipMemcpyAsync(o + b_meta + b_cmeta + b_coff, hh->d_fib_off.ptr, b_foff,
+                                      hipMemcpyDeviceToHost, s0));
+    }
+    GACA_HIP_CHECK(hipStreamSynchronize(s0));
     int wclk_khz = 0;
     if (hipDeviceGetAttribute(&wclk_khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess ||
         wclk_khz <= 0) {
@@ -1443,13 +1471,13 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
         gaca_hmatrix *hh = H[w];
         compact(ctx, hh->d_arena, arena_used[w] * es, s0);
         compact(ctx, hh->d_fib, fib_used[w] * sizeof(double2), s0);
-        GACA_HIP_CHECK(hipMemcpy(hh->meta.data(), hh->d_meta.ptr, nfar * sizeof(FarMeta), hipMemcpyDeviceToHost));
-        GACA_HIP_CHECK(hipMemcpy(hh->cmeta.data(), hh->d_cmeta.ptr, nfar * rcap * sizeof(CrossMeta),
-                                 hipMemcpyDeviceToHost));
-        GACA_HIP_CHECK(hipMemcpy(hh->cross_off.data(), hh->d_cross_off.ptr, nfar * rcap * sizeof(int64_t),
-                                 hipMemcpyDeviceToHost));
-        GACA_HIP_CHECK(hipMemcpy(hh->fib_off.data(), hh->d_fib_off.ptr, nfar * sizeof(int64_t),
-                                 hipMemcpyDeviceToHost));
+        {
+            const char *o = W.h_out.as<char>() + w * b_op;
+            std::memcpy(hh->meta.data(), o, b_meta);
+            std::memcpy(hh->cmeta.data(), o + b_meta, b_cmeta);
+            std::memcpy(hh->cross_off.data(), o + b_meta + b_cmeta, b_coff);
+            std::memcpy(hh->fib_off.data(), o + b_meta + b_cmeta + b_coff, b_foff);
+        }
         // timings and work of the shared launches (identical in every operator of a joint build)
         gaca_stats &st = hh->st;
         st.joint_build = nh;
@@ -1554,8 +1582,14 @@ static bool build_ops(gaca_problem *p, const std::vector<gaca_kernel> &kernels,
         h->kernel = p->kid(kernel);
         h->prec = p->opt.precision;
         h->rcap = std::max(1, std::min({p->L, p->opt.max_rank3d > 0 ? p->opt.max_rank3d : p->L, 256}));
-        // near field: FP64 quadrature, stored FP64 or (mixed) FP32
-        h->d_near.alloc(ctx, std::max<int64_t>(1, p->near_elems) * (mixed ? sizeof(float2) : sizeof(double2)));
+        // near field: FP64 quadrature, stored FP64 or (mixed) FP32 (every entry is written)
+        const size_t nbytes = std::max<int64_t>(1, p->near_elems) * (mixed ? sizeof(float2) : sizeof(double2));
+        {
+            std::lock_guard<std::mutex> lk(p->spare_mu);
+            DevBuf &sp = p->near_spare[h->kernel & 1];
+            if (sp.ptr && sp.bytes == nbytes) h->d_near.swap(sp);
+        }
+        if (!h->d_near.ptr) h->d_near.alloc(ctx, nbytes);
         H.push_back(h.get());
         out.push_back(std::move(h));
     }
@@ -1665,7 +1699,8 @@ gaca_status gaca_hmatrix_destroy(gaca_hmatrix *h) {
         bool synced = false;
         auto donate = [&](GrowBuf &src, GrowBuf *spare) {
             if (!src.vmm || !src.ptr || src.bytes > tb / 8) return;
-            for (int k = 0; k < 2; ++k)
+            for (int t = 0; t < 2; ++t) {
+                const int k = t == 0 ? (h->kernel & 1) : 1 - (h->kernel & 1);
                 if (!spare[k].ptr) {
                     if (!synced) {
                         (void)hipDeviceSynchronize();   // no kernel may still use the arena
@@ -1674,9 +1709,31 @@ gaca_status gaca_hmatrix_destroy(gaca_hmatrix *h) {
                     spare[k].swap(src);
                     return;
                 }
+            }
         };
         donate(h->d_arena, p->spare_arena);
         donate(h->d_fib, p->spare_fib);
+        // near field of the same size as the next build's (kept up to an eighth of the memory)
+        {
+            DevBuf &sp = p->near_spare[h->kernel & 1];
+            if (h->d_near.ptr && h->d_near.bytes <= tb / 8 && !sp.ptr) {
+                if (!synced) {
+                    (void)hipDeviceSynchronize();
+                    synced = true;
+                }
+                sp.swap(h->d_near);
+            }
+        }
+        // VALU apply workspace: kept when no larger buffer of its kind is kept already
+        DevBuf *ws[5] = {&h->d_yb, &h->d_z, &h->d_t, &h->d_xp, &h->d_yp};
+        for (int k = 0; k < 5; ++k) {
+            if (!ws[k]->ptr || ws[k]->bytes > tb / 16 || p->ws_spare[k].bytes >= ws[k]->bytes) continue;
+            if (!synced) {
+                (void)hipDeviceSynchronize();   // no kernel may still use the buffer
+                synced = true;
+            }
+            p->ws_spare[k].swap(*ws[k]);
+        }
     }
     delete h;
     return GACA_OK;
@@ -1778,8 +1835,9 @@ gaca_status gaca_hmatrix_near_export(const gaca_hmatrix *h, int64_t idx, double 
 
 // ---------------------------------------------------------------------------------------
 static void prepare_leaves(gaca_hmatrix *h) {
-    if (h->leaf_ready) return;
     gaca_problem *p = h->p;
+    std::lock_guard<std::mutex> lk(p->leaf_mu);
+    if (p->leaf_ready) return;
     gaca_context *ctx = p->ctx;
     const size_t nleaf = p->leaf_r0.size();
     std::vector<std::vector<int32_t>> lf(nleaf), ln(nleaf);
@@ -1787,7 +1845,7 @@ static void prepare_leaves(gaca_hmatrix *h) {
         auto it = std::lower_bound(p->leaf_r0.begin(), p->leaf_r0.end(), (int32_t)r0);
         for (size_t k = it - p->leaf_r0.begin(); k < nleaf && p->leaf_r0[k] < r0 + m; ++k) fn(k);
     };
-    for (int64_t b = 0; b < h->nfar; ++b)
+    for (size_t b = 0; b < p->part.far.size(); ++b)
         leaves_in(p->part.far[b][0], p->part.far[b][1], [&](size_t k) { lf[k].push_back((int32_t)b); });
     for (size_t b = 0; b < p->part.near.size(); ++b)
         leaves_in(p->part.near[b][0], p->part.near[b][1], [&](size_t k) { ln[k].push_back((int32_t)b); });
@@ -1798,13 +1856,13 @@ static void prepare_leaves(gaca_hmatrix *h) {
         ni.insert(ni.end(), ln[k].begin(), ln[k].end());
         np.push_back((int32_t)ni.size());
     }
-    h->d_leaf_r0.upload(ctx, p->leaf_r0);
-    h->d_leaf_m.upload(ctx, p->leaf_m);
-    h->d_lfp.upload(ctx, fp);
-    h->d_lfi.upload(ctx, fi);
-    h->d_lnp.upload(ctx, np);
-    h->d_lni.upload(ctx, ni);
-    h->leaf_ready = true;
+    p->d_leaf_r0.upload(ctx, p->leaf_r0);
+    p->d_leaf_m.upload(ctx, p->leaf_m);
+    p->d_lfp.upload(ctx, fp);
+    p->d_lfi.upload(ctx, fi);
+    p->d_lnp.upload(ctx, np);
+    p->d_lni.upload(ctx, ni);
+    p->leaf_ready = true;
 }
 
 // Workspace of the VALU apply (tree-order copies of X and Y, z, t and per-block y).
@@ -1832,12 +1890,27 @@ static void alloc_apply_workspace(gaca_hmatrix *h, gaca_apply_mode mode, int32_t
             h->d_zoff.upload(ctx, zoff);
             h->d_toff.upload(ctx, toff);
             h->d_yoff.upload(ctx, yoff);
-            h->d_yb.alloc(ctx, std::max<int64_t>(yacc, 1) * xs);
-            h->d_z.alloc(ctx, std::max<int64_t>(zacc, 1) * xs);
-            h->d_t.alloc(ctx, std::max<int64_t>(tacc, 1) * xs);
-            h->d_xp.alloc(ctx, (size_t)L * M * nrhs * xs);
+            // a buffer handed back by an operator of the same problem serves when it is large
+            // enough (every byte of the workspace is written before it is read)
+            auto take = [&](DevBuf &dst, int slot, size_t need) {
+                if (dst.ptr && dst.bytes >= need) return;
+                dst.release();
+                {
+                    std::lock_guard<std::mutex> lk(p->spare_mu);
+                    DevBuf &sp = p->ws_spare[slot];
+                    if (sp.ptr && sp.bytes >= need) {
+                        dst.swap(sp);
+                        return;
+                    }
+                }
+                dst.alloc(ctx, need);
+            };
             const int nl = mode == GACA_APPLY_SUM ? 1 : L;
-            h->d_yp.alloc(ctx, (size_t)nl * M * nrhs * xs);
+            take(h->d_yb, 0, (size_t)std::max<int64_t>(yacc, 1) * xs);
+            take(h->d_z, 1, (size_t)std::max<int64_t>(zacc, 1) * xs);
+            take(h->d_t, 2, (size_t)std::max<int64_t>(tacc, 1) * xs);
+            take(h->d_xp, 3, (size_t)L * M * nrhs * xs);
+            take(h->d_yp, 4, (size_t)nl * M * nrhs * xs);
             h->ws_nrhs = nrhs;
             h->ws_mode = (int)mode;
             h->ws_dtype = (int)dtype;
@@ -2085,12 +2158,12 @@ gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, cons
         a.nleaf = (int32_t)p->leaf_r0.size();
         a.max_leaf_m = 1;
         for (int32_t lm : p->leaf_m) a.max_leaf_m = std::max(a.max_leaf_m, lm);
-        a.leaf_r0 = h->d_leaf_r0.as<int32_t>();
-        a.leaf_m = h->d_leaf_m.as<int32_t>();
-        a.leaf_far_ptr = h->d_lfp.as<int32_t>();
-        a.leaf_far_idx = h->d_lfi.as<int32_t>();
-        a.leaf_near_ptr = h->d_lnp.as<int32_t>();
-        a.leaf_near_idx = h->d_lni.as<int32_t>();
+        a.leaf_r0 = p->d_leaf_r0.as<int32_t>();
+        a.leaf_m = p->d_leaf_m.as<int32_t>();
+        a.leaf_far_ptr = p->d_lfp.as<int32_t>();
+        a.leaf_far_idx = p->d_lfi.as<int32_t>();
+        a.leaf_near_ptr = p->d_lnp.as<int32_t>();
+        a.leaf_near_idx = p->d_lni.as<int32_t>();
         a.z_off = h->d_zoff.as<int64_t>();
         if (mfma) {
             apply_mfma(h, a, nrhs, reinterpret_cast<const float2 *>(X), reinterpret_cast<float2 *>(Y), st);
