@@ -41,7 +41,8 @@ __global__ void scatter_y_kernel(const XT *Yp, XT *Y, const int64_t *perm, int n
 }
 
 // SUM: T_l = sum_k f_l[k] X_k[tau] (n x nrhs), z_l = W_l^T T_l for every cross of block b,
-// kApplyCB crosses at a time: each X_k[tau] element is read once per group of crosses, and
+// a.apply_cb (<= kApplyCB) crosses at a time: each X_k[tau] element is read once per group
+// of crosses (the group size keeps the T workspace within its budget), and
 // z_l's rows are dot products over j taken by 8 lanes each (W rows read in order, partial
 // sums added by a fixed butterfly).
 // PER_FREQ: v_l[q][k][c] = sum_j W_l[q][j] X_k[tau_j][c].
@@ -64,8 +65,9 @@ __global__ void __launch_bounds__(256) apply_far_a_kernel(ApplyDev a, int mode, 
         __shared__ XT s_f[CB * kApplyKF];
         const int nt = n * nr;
         int64_t zo = 0;
-        for (int cg = 0; cg < mt.rank; cg += CB) {
-            const int cb = min(CB, mt.rank - cg);
+        const int cbr = max(1, min(CB, a.apply_cb));
+        for (int cg = 0; cg < mt.rank; cg += cbr) {
+            const int cb = min(cbr, mt.rank - cg);
             __syncthreads();
             if (threadIdx.x == 0) {
                 int rows = 0;

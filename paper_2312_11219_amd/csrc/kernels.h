@@ -117,7 +117,7 @@ void launch_eval(int kernel, const GeoDev &g, const QuadDev &q, const FreqDev &f
                  const int32_t *tiers, double2 *out, hipStream_t st);
 
 // Apply (FP64, VALU reference path).
-constexpr int kApplyCB = 8;   // crosses per T = F X group of the VALU SUM apply (T workspace)
+constexpr int kApplyCB = 8;   // most crosses per T = F X group of the VALU SUM apply
 constexpr int kApplyKF = 64;  // fibre entries per LDS stage of that group
 struct ApplyDev {
     int32_t L, nrhs;
@@ -137,6 +137,7 @@ struct ApplyDev {
     const float2 *near32;
     // leaf CSR: leaf -> covering far blocks / near blocks
     int32_t nleaf, max_leaf_m;
+    int32_t apply_cb;             // crosses per T group of the VALU SUM apply (1..kApplyCB)
     const int32_t *leaf_r0, *leaf_m;
     const int32_t *leaf_far_ptr, *leaf_far_idx;
     const int32_t *leaf_near_ptr, *leaf_near_idx;

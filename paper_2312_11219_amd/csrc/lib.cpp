@@ -432,7 +432,7 @@ struct gaca_hmatrix {
     gaca_stats st{};
     std::vector<int64_t> freq_hist;
     // apply workspace
-    int32_t ws_nrhs = -1, ws_mode = -1, ws_dtype = -1;
+    int32_t ws_nrhs = -1, ws_mode = -1, ws_dtype = -1, ws_cb = 1;
     DevBuf d_xp, d_yp, d_z, d_t, d_toff, d_zoff, d_yb, d_yoff;
     DevBuf d_mz, d_mt, d_mtitems, d_mttile0, d_mtrows, d_mzitems, d_mzoff, d_msumrho;   // matrix-core apply
 };
@@ -1875,6 +1875,13 @@ static void alloc_apply_workspace(gaca_hmatrix *h, gaca_apply_mode mode, int32_t
     {
             std::vector<int64_t> zoff(std::max<int64_t>(h->nfar, 1)), toff(std::max<int64_t>(h->nfar, 1)),
                 yoff(std::max<int64_t>(h->nfar, 1));
+            // crosses per T group: up to kApplyCB while the T workspace stays within 2 GiB
+            int64_t nsum = 0;
+            for (int64_t b = 0; b < h->nfar; ++b) nsum += p->part.far[b][3];
+            const double t_one = (double)nsum * nrhs * xs;
+            const int cb = mode == GACA_APPLY_SUM
+                               ? (int)std::max(1.0, std::min((double)kApplyCB, std::floor(2147483648.0 / std::max(t_one, 1.0))))
+                               : 1;
             int64_t zacc = 0, tacc = 0, yacc = 0;
             for (int64_t b = 0; b < h->nfar; ++b) {
                 zoff[b] = zacc;
@@ -1883,7 +1890,7 @@ static void alloc_apply_workspace(gaca_hmatrix *h, gaca_apply_mode mode, int32_t
                 yacc += p->part.far[b][1] * (int64_t)nrhs;
                 const int64_t sr = h->meta[b].sum_rho;
                 zacc += mode == GACA_APPLY_SUM ? sr * nrhs : sr * (int64_t)L * nrhs;
-                tacc += mode == GACA_APPLY_SUM ? std::min<int64_t>(h->meta[b].rank, kApplyCB) *
+                tacc += mode == GACA_APPLY_SUM ? std::min<int64_t>(h->meta[b].rank, cb) *
                                                      p->part.far[b][3] * (int64_t)nrhs
                                                : 0;
             }
@@ -1914,6 +1921,7 @@ static void alloc_apply_workspace(gaca_hmatrix *h, gaca_apply_mode mode, int32_t
             h->ws_nrhs = nrhs;
             h->ws_mode = (int)mode;
             h->ws_dtype = (int)dtype;
+            h->ws_cb = cb;
         }
 }
 
@@ -2156,6 +2164,7 @@ gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, cons
         a.near64 = h->prec == GACA_MIXED ? nullptr : h->d_near.as<double2>();
         a.near32 = h->prec == GACA_MIXED ? h->d_near.as<float2>() : nullptr;
         a.nleaf = (int32_t)p->leaf_r0.size();
+        a.apply_cb = h->ws_cb;
         a.max_leaf_m = 1;
         for (int32_t lm : p->leaf_m) a.max_leaf_m = std::max(a.max_leaf_m, lm);
         a.leaf_r0 = p->d_leaf_r0.as<int32_t>();

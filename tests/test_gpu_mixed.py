@@ -97,3 +97,44 @@ def test_mixed_apply_fp32_vs_fp64_same_factors(mode):
     err = rel_fro(Y32.astype(np.complex128), Y64)
     log("apply fp32 vs fp64 on mixed factors", mode, err)
     assert err < 1e-5
+
+
+def test_mixed_c5_sampled_blocks_and_apply():
+    """The 81920-triangle sphere (L = 256, eps 1e-6) built in mixed precision as bench.py
+    builds it: error against the FP64 oracle's dense tensor on seeded sampled far blocks with
+    sides 64-256 (the oracle assembles each in under a second), and the matrix-core apply of
+    16 right-hand sides against the FP64 VALU apply of the same operator on 8 of them."""
+    import torch
+    cfg, prob, (xyz, tri, s) = gpu_problem("C5", precision="mixed", batch_bytes=80 << 30)
+    h = prob.build("slp")
+    far, _ = prob.blocks()
+    ocfg, op = _oracle_problem("C5")
+    assert len(op.far) == far.shape[0]
+    rng = np.random.default_rng(5)
+    sizes = np.maximum(far[:, 1], far[:, 3])
+    cand = np.nonzero((sizes >= 64) & (sizes <= 256))[0]
+    pick = sorted(rng.choice(cand, 8, replace=False).tolist())
+    num = den = 0.0
+    for b in pick:
+        blk = tuple(int(v) for v in far[b])
+        assert blk == tuple(int(v) for v in op.far[b])
+        T = op.block_tensor("slp", blk, True)
+        num += np.linalg.norm(h.reconstruct_block(b) - T) ** 2
+        den += np.linalg.norm(T) ** 2
+    err = float(np.sqrt(num / den))
+    M, L = tri.shape[0], len(s)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    X = torch.empty((L, M, 16), dtype=torch.complex64, device="cuda")
+    X.real.normal_(generator=g)
+    X.imag.normal_(generator=g)
+    Y32 = h.apply(X, mode="sum")
+    X64 = X[:, :, :8].to(torch.complex128).contiguous()
+    del X
+    Y64 = h.apply(X64, mode="sum")
+    torch.cuda.synchronize()
+    d = ((Y32[:, :8].to(torch.complex128) - Y64).norm() / Y64.norm()).item()
+    log(f"C5 mixed: sampled blocks {pick} error vs oracle {err:.3e}; matrix-core apply vs FP64 "
+        f"apply {d:.3e}; build {h.stats()['ms_total']:.0f} ms")
+    assert err <= 10 * cfg["eps"] + 1e-5
+    assert d <= 1e-5
