@@ -155,6 +155,7 @@ __global__ void __launch_bounds__(kFarChunk)
     const int i = (int)(idx / B.n), j = (int)(idx - (int64_t)i * B.n);
     const FT *H = reinterpret_cast<const FT *>(bd.hpool);
     FT e = face_entry<KERNEL, DENSE, FT>(g, f, bd.dense, B, i, j, k);
+#pragma unroll 4
     for (int p = 0; p < ell; ++p) e = csub(e, cmul(from_d2<FT>(coef[p]), H[hsl[p] + idx]));
     reinterpret_cast<FT *>(bd.hpool)[A.hslot + idx] = e;
 }
@@ -1598,6 +1599,7 @@ __global__ void __launch_bounds__(256)
         double2 *fl_ = fg + A.fgslot;
         for (int kk = tid; kk < L; kk += NT) {
             double2 e = fibre_entry<KERNEL, DENSE>(g, f, bd.dense, B, ip, jpv, kk);
+#pragma unroll 4
             for (int p = 0; p < ell; ++p) e = csub(e, cmul(hpiv_p[p], fg[fsl[p] + kk]));
             fl_[kk] = cdiv(e, hpiv);
         }
