@@ -343,10 +343,10 @@ __device__ void zero_rows_multi(const FT *R, const FT *Uh, const FT *Wh, const F
 // One-entry layout with the history split over splitw thread groups (m, n <= NT): thread
 // (s, j) sums steps [q s / splitw, q (s + 1) / splitw) in two interleaved accumulators,
 // exactly as the row pass's history dot product does (LDS part in pairs, HBM part in groups
-// of NB with the u coefficients from cs = [G][kCoefLds], q <= qL + kCoefLds; PF: the next
+// of NB with the u coefficients from cs = [G][CL], q <= qL + CL; PF: the next
 // group loaded during the arithmetic of this one); the group partials s >= 1 go through
 // pp[g], and the row is R - p_0 - p_1 - ... as in the row pass.
-template <int NT, int G, bool PF, class FT>
+template <int NT, int G, bool PF, int CL, class FT>
 __device__ void zero_rows_split(const FT *R, const FT *Uh, const FT *Wh, const FT *Wb, int m,
                                 int n, int q, int qL, int splitw, const int (&c)[G],
                                 const FT *cs, FT *const (&pp)[G], double *wm, double (&mx)[G]) {
@@ -390,8 +390,8 @@ __device__ void zero_rows_split(const FT *R, const FT *Uh, const FT *Wh, const F
             for (int t = 0; t < NB; t += 2)
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    a0[g] = cfma(cs[g * kCoefLds + qs + t - qL], bv[t], a0[g]);
-                    a1[g] = cfma(cs[g * kCoefLds + qs + t + 1 - qL], bv[t + 1], a1[g]);
+                    a0[g] = cfma(cs[g * CL + qs + t - qL], bv[t], a0[g]);
+                    a1[g] = cfma(cs[g * CL + qs + t + 1 - qL], bv[t + 1], a1[g]);
                 }
         };
         if constexpr (PF) {
@@ -418,7 +418,7 @@ __device__ void zero_rows_split(const FT *R, const FT *Uh, const FT *Wh, const F
         for (; qq < q1; ++qq) {
             const FT x0 = Wb[(int64_t)qq * n + j];
 #pragma unroll
-            for (int g = 0; g < G; ++g) a0[g] = cfma(cs[g * kCoefLds + qq - qL], x0, a0[g]);
+            for (int g = 0; g < G; ++g) a0[g] = cfma(cs[g * CL + qq - qL], x0, a0[g]);
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -620,11 +620,19 @@ __global__ void __launch_bounds__(NT)
 
     __shared__ double2 hist_raw[HB / sizeof(double2)];
     __shared__ FT part[NT];       // split-K partial sums of row / column corrections
-    __shared__ FT cbuf[kCoefLds]; // coefficients u_q'[i] / w_q'[jp] of the HBM part of the history
-    __shared__ unsigned char used_row[kMaxRowsLds];
+    // LDS sizes: the one-entry path (m, n <= NT, so at most NT rows and steps) needs used-row
+    // flags and staged coefficients for NT rows / steps and Gram entries for NT steps (or the
+    // zero-row candidates' coefficients, [G][CL]); the other paths the general bounds
+    constexpr int CL = PATH == 1 && NT < kCoefLds ? NT : kCoefLds;
+    constexpr int RL = PATH == 1 ? NT : kMaxRowsLds;
+    constexpr int GZ = MIXED ? 4 : 2;
+    constexpr int BZ = (int)(GZ * CL * sizeof(FT) / sizeof(double2));
+    constexpr int BVL = PATH == 1 ? (NT > BZ ? NT : BZ) : kBV;
+    __shared__ FT cbuf[CL];       // coefficients u_q'[i] / w_q'[jp] of the HBM part of the history
+    __shared__ unsigned char used_row[RL];
     __shared__ double redbuf[8 * NW + 4];
     __shared__ double2 xbuf[NT];  // current w (face type), then split partials of v
-    __shared__ double2 bvec[kBV];  // conj <w_q, w_q'> for q' < q
+    __shared__ double2 bvec[BVL];  // conj <w_q, w_q'> for q' < q
     Red<NT> red{redbuf};
     const double tie2 = (1.0 - P.tie) * (1.0 - P.tie);
     const int qL = min(B.rho_max, (int)(HB / ((int64_t)(m + n) * (int64_t)sizeof(FT))));
@@ -632,7 +640,7 @@ __global__ void __launch_bounds__(NT)
     FT *Wh = Uh + (int64_t)qL * m;                    // [qL][n]
 
     // sum_{q' in [q0, q1)} a_q'[ia] b_q'[ib] over the histories: the LDS part, then the HBM
-    // part with the coefficients a_q'[ia] staged in cbuf (q' < qL + kCoefLds; sixteen loads
+    // part with the coefficients a_q'[ia] staged in cbuf (q' < qL + CL; sixteen loads
     // of b in flight), then any rest with both operands from HBM
     auto hdot = [&](const FT *ah, const FT *ag, int la, int ia, const FT *bh, const FT *bg,
                     int lb, int ib, int q0, int q1) {
@@ -645,7 +653,7 @@ __global__ void __launch_bounds__(NT)
         }
         if (qq < qm) acc0 = cfma(ah[qq * la + ia], bh[qq * lb + ib], acc0);
         qq = max(q0, qL);
-        const int qc = min(q1, qL + kCoefLds);
+        const int qc = min(q1, qL + CL);
         constexpr int NB = NT >= 1024 ? 4 : 16;   // loads in flight (register budget)
         for (; qq + NB <= qc; qq += NB) {
             FT bv[NB];
@@ -664,9 +672,9 @@ __global__ void __launch_bounds__(NT)
                                                                     max(q0, qc), q1));
         return acc;
     };
-    // stage a_q'[ia] for q' in [qL, min(q, qL + kCoefLds)) (ends with a barrier)
+    // stage a_q'[ia] for q' in [qL, min(q, qL + CL)) (ends with a barrier)
     auto stage_coef = [&](const FT *ag, int la, int ia, int q) {
-        const int nc = min(q, qL + kCoefLds) - qL;
+        const int nc = min(q, qL + CL) - qL;
         for (int t = tid; t < nc; t += NT) cbuf[t] = ag[(int64_t)(qL + t) * la + ia];
         __syncthreads();
     };
@@ -684,7 +692,7 @@ __global__ void __launch_bounds__(NT)
             // candidates per pass: G NE accumulators per thread (register budget)
             auto pass = [&](auto gc, auto ec) -> int {
                 constexpr int G = decltype(gc)::value, NE = decltype(ec)::value;
-                constexpr int CH = (int)(kBV * sizeof(double2) / sizeof(FT)) / G;
+                constexpr int CH = (int)(BVL * sizeof(double2) / sizeof(FT)) / G;
                 __syncthreads();
                 int c[G];
                 const int nc = scan_unused<G>(used_row, m, fu, c);
@@ -724,9 +732,9 @@ __global__ void __launch_bounds__(NT)
                 if (r >= 0) return r;
             }
         } else {
-            constexpr int G = MIXED ? 4 : 2;
-            if (NT > kCoefLds || q > qL + kCoefLds) return first_unused<NT>(used_row, m, red);
-            FT *cs = reinterpret_cast<FT *>(bvec);   // [G][kCoefLds]
+            constexpr int G = GZ;
+            if (NT > CL || q > qL + CL) return first_unused<NT>(used_row, m, red);
+            FT *cs = reinterpret_cast<FT *>(bvec);   // [G][CL]
             FT *pp[G];                               // [G][< NT] group partials
             if constexpr (MIXED) {
                 pp[0] = part;
@@ -745,10 +753,10 @@ __global__ void __launch_bounds__(NT)
                 fu = c[0];
 #pragma unroll
                 for (int g = 0; g < G; ++g)
-                    for (int k = tid; k < q - qL; k += NT) cs[g * kCoefLds + k] = Ub[(int64_t)(qL + k) * m + c[g]];
+                    for (int k = tid; k < q - qL; k += NT) cs[g * CL + k] = Ub[(int64_t)(qL + k) * m + c[g]];
                 __syncthreads();
                 double mx[G];
-                zero_rows_split<NT, G, MIXED>(R, Uh, Wh, Wb, m, n, q, qL, splitw, c, cs, pp, redbuf, mx);
+                zero_rows_split<NT, G, MIXED, CL>(R, Uh, Wh, Wb, m, n, q, qL, splitw, c, cs, pp, redbuf, mx);
                 int gs = nc;
 #pragma unroll
                 for (int g = G - 1; g >= 0; --g)
@@ -878,7 +886,7 @@ __global__ void __launch_bounds__(NT)
                     v0 = cfma(bvec[qq], to_d2(uu), v0);
                 }
                 qq = max(q0, qL);
-                const int qc = min(q1, qL + kCoefLds);
+                const int qc = min(q1, qL + CL);
                 constexpr int NB = NT >= 1024 ? 4 : 16;
                 for (; qq + NB <= qc; qq += NB) {
                     FT uv[NB];
@@ -968,7 +976,7 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
                     for (int e = 0; e < EM; ++e) acc[e] = cfma(c, Wh[qq * n + min(tid + NT * e, n - 1)], acc[e]);
                 }
-                const int qc = min(q, qL + kCoefLds);
+                const int qc = min(q, qL + CL);
                 for (int qq = qL; qq < qc; qq += QB) {
                     FT x[QB][EM];
 #pragma unroll
@@ -984,7 +992,7 @@ __global__ void __launch_bounds__(NT)
                         for (int e = 0; e < EM; ++e) acc[e] = cfma(c, x[qb][e], acc[e]);
                     }
                 }
-                for (int qq = qL + kCoefLds; qq < q; ++qq) {
+                for (int qq = qL + CL; qq < q; ++qq) {
                     const FT c = Ub[(int64_t)qq * m + i];
 #pragma unroll
                     for (int e = 0; e < EM; ++e)
@@ -1099,7 +1107,7 @@ __global__ void __launch_bounds__(NT)
                         vv[e] = cfma(bq, to_d2(x), vv[e]);
                     }
                 }
-                const int qc = min(q, qL + kCoefLds);
+                const int qc = min(q, qL + CL);
                 for (int qq = qL; qq < qc; qq += QB) {
                     FT x[QB][EM];
 #pragma unroll
@@ -1123,7 +1131,7 @@ __global__ void __launch_bounds__(NT)
                         }
                     }
                 }
-                for (int qq = qL + kCoefLds; qq < q; ++qq) {
+                for (int qq = qL + CL; qq < q; ++qq) {
                     const FT c = Wb[(int64_t)qq * n + jp];
                     const double2 bq = bvec[qq];
 #pragma unroll
@@ -1766,7 +1774,7 @@ template <bool MX, int PATH>
 static void large_dispatch(int threads, const AcaParams &P, const FarBatchDev &bd,
                            const FarActive *act, int nact, hipStream_t st) {
     // large faces: one face per CU with 1024 or 512 threads and ~100 KB of LDS history, or
-    // 256 threads with 32 KB, several per CU
+    // 256 threads with 59 KB (one entry per thread) or 32 KB, two per CU
     if constexpr (PATH == 2) {
         far_aca_large_kernel<512, MX, 106496, 2><<<nact, 512, 0, st>>>(P, bd, act);
     } else {
@@ -1774,8 +1782,8 @@ static void large_dispatch(int threads, const AcaParams &P, const FarBatchDev &b
             far_aca_large_kernel<1024, MX, 90112, PATH><<<nact, 1024, 0, st>>>(P, bd, act);
         else if (threads >= 512)
             far_aca_large_kernel<512, MX, 106496, PATH><<<nact, 512, 0, st>>>(P, bd, act);
-        else
-            far_aca_large_kernel<256, MX, 32768, PATH><<<nact, 256, 0, st>>>(P, bd, act);
+        else   // one-entry path: smaller flag / coefficient / Gram arrays leave ~59 KB of history
+            far_aca_large_kernel<256, MX, PATH == 1 ? 60800 : 32768, PATH><<<nact, 256, 0, st>>>(P, bd, act);
     }
 }
 
