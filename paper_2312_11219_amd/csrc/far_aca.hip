@@ -557,12 +557,28 @@ __global__ void __launch_bounds__(NT, (NT == 256 && MNMAX == 2304) ? 3 : 1)
                 ss[t] = cadd(ss[t], tt);
                 sp += cabs2(ss[t]);
             }
-        red.sum3(nu2, nw2, sp);
+        // the maximum of |u_q|^2 over the unused rows (for the next-row pick) shares the
+        // reduction round of the norms
+        double mxu = -1.0;
+        for (int r = tid; r < m; r += NT)
+            if (!used_row[r]) mxu = fmax(mxu, cabs2(ucol[r]));
+        red.sum3max(nu2, nw2, sp, mxu);
         s2 = sp;
         ++q;
         if (sqrt(nu2 * nw2) <= P.eps_aca * sqrt(ref2 + s2) || nused >= m || q >= B.rho_max)
             break;
-        i = pick_unused<NT>(ucol, used_row, m, tie2, red);
+        // next row: the lowest unused row with |u_q|^2 at the tie threshold of that maximum
+        // (the first unused row if none compares)
+        const double thu = tie2 * mxu;
+        int c = 0x7fffffff;
+        for (int r = tid; r < m; r += NT)
+            if (!used_row[r] && cabs2(ucol[r]) >= thu) {
+                c = r;
+                break;
+            }
+        c = red.imin(c);
+        if (c >= m) c = first_unused<NT>(used_row, m, red);
+        i = min(c, m - 1);
     }
     const int rho = q;
     int pidx = 0;
