@@ -281,6 +281,30 @@ def test_compress_tensor_large_faces(m, n):
     assert [(c["i"], c["j"]) for c in b["crosses"]] == [(c.i, c.j) for c in o.crosses]
 
 
+@pytest.mark.parametrize("m,n,L", [(1, 1, 1), (1, 1, 5), (1, 37, 4), (37, 1, 4), (5, 64, 1),
+                                   (64, 64, 2)])
+def test_compress_tensor_degenerate_shapes(m, n, L):
+    """Single rows, single columns, one frequency (Algorithm 1 then stops after its first
+    face, every frequency used): a separable rank-1 tensor u v^T g is recovered exactly, with
+    the oracle's pivots."""
+    import torch
+    import paper_2312_11219_amd as gaca
+    from gpu_common import context
+    from oracle.aca3d import aca3d
+    rng = np.random.default_rng(m * 1000 + n * 10 + L)
+    u = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    v = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    g = rng.standard_normal(L) + 1j * rng.standard_normal(L)
+    T = u[:, None, None] * v[None, :, None] * g[None, None, :]
+    h = gaca.compress_tensor(context(), torch.from_numpy(T).cuda(), eps3d=1e-10, eps_aca=1e-12)
+    b = h.export_block(0)
+    o = aca3d(T, 1e-10, 1e-12)
+    assert b["rank"] == o.rank == 1
+    assert rel_fro(h.reconstruct_block(0), T) < 1e-12
+    assert [c["k"] for c in b["crosses"]] == [c.k for c in o.crosses]
+    assert [(c["i"], c["j"]) for c in b["crosses"]] == [(c.i, c.j) for c in o.crosses]
+
+
 def test_compress_tensor_zero_and_dense():
     import torch
     import paper_2312_11219_amd as gaca
