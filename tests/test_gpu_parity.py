@@ -396,3 +396,34 @@ def test_zero_row_batch_matches_one_row(precision, delta):
     np.testing.assert_array_equal(yb.cpu().numpy(), y1.cpu().numpy())
     log(f"zero-row batch ({precision}) matches the one-row search: {far.shape[0]} far blocks, "
         f"build {sb['ms_far']:.0f} ms vs {s1['ms_far']:.0f} ms")
+
+
+def test_error_paths():
+    """The boundary's error behaviour: invalid arguments come back as status codes (no
+    device work is started): tensor sides outside [1, 8192], a block index out of range,
+    the Galerkin double layer (unsupported), nrhs = 0."""
+    import ctypes
+    import torch
+    import paper_2312_11219_amd as gaca
+    from paper_2312_11219_amd._binding import GacaError, load_library
+    from gpu_common import context
+    T = torch.zeros((8193, 1, 2), dtype=torch.complex128, device="cuda")
+    with pytest.raises(GacaError) as e:
+        gaca.compress_tensor(context(), T)
+    assert e.value.code == -1   # GACA_ERR_INVALID_ARG
+    cfg, prob, (xyz, tri, s) = gpu_problem("cube768")
+    h = prob.build("slp")
+    with pytest.raises(GacaError) as e:
+        h.block_info(10 ** 9)
+    assert e.value.code == -1
+    lib = load_library()
+    X = torch.zeros((len(s), tri.shape[0], 1), dtype=torch.complex128, device="cuda")
+    Y = torch.zeros((tri.shape[0], 1), dtype=torch.complex128, device="cuda")
+    rc = lib.gaca_apply(h.handle, 0, 0, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                        0, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == -1
+    _, pg, _ = gpu_problem("lshape768")
+    with pytest.raises(GacaError) as e:
+        pg.build("dlp")
+    assert e.value.code == -6   # GACA_ERR_UNSUPPORTED
+    log("error paths: invalid sides, block index, nrhs 0 and the Galerkin double layer rejected")
