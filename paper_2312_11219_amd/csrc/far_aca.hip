@@ -688,6 +688,51 @@ __global__ void __launch_bounds__(NT)
                                                                     max(q0, qc), q1));
         return acc;
     };
+    // the same sum with both operands of the HBM part loaded per thread (the coefficient
+    // a_q'[ia] is one address across the row, so no staging pass and barrier before it);
+    // the one-entry path, whose steps are all below qL + CL
+    auto hdot_direct = [&](const FT *ah, const FT *ag, int la, int ia, const FT *bh, const FT *bg,
+                           int lb, int ib, int q0, int q1) {
+        FT acc0 = czero<FT>(), acc1 = czero<FT>();
+        const int qm = min(q1, qL);
+        int qq = q0;
+#pragma unroll 4
+        for (; qq + 1 < qm; qq += 2) {
+            acc0 = cfma(ah[qq * la + ia], bh[qq * lb + ib], acc0);
+            acc1 = cfma(ah[(qq + 1) * la + ia], bh[(qq + 1) * lb + ib], acc1);
+        }
+        if (qq < qm) acc0 = cfma(ah[qq * la + ia], bh[qq * lb + ib], acc0);
+        qq = max(q0, qL);
+        constexpr int NB = NT >= 1024 ? 4 : 16;
+        for (; qq + NB <= q1; qq += NB) {
+            FT av[NB], bv[NB];
+#pragma unroll
+            for (int t = 0; t < NB; ++t) {
+                av[t] = ag[(int64_t)(qq + t) * la + ia];
+                bv[t] = bg[(int64_t)(qq + t) * lb + ib];
+            }
+#pragma unroll
+            for (int t = 0; t < NB; t += 2) {
+                acc0 = cfma(av[t], bv[t], acc0);
+                acc1 = cfma(av[t + 1], bv[t + 1], acc1);
+            }
+        }
+        if (qq < q1) {
+            // the rest (fewer than NB terms): its loads in flight together (indices clamped
+            // into range), summed one at a time in order
+            FT av[NB], bv[NB];
+#pragma unroll
+            for (int t = 0; t < NB; ++t) {
+                const int qt = min(qq + t, q1 - 1);
+                av[t] = ag[(int64_t)qt * la + ia];
+                bv[t] = bg[(int64_t)qt * lb + ib];
+            }
+#pragma unroll
+            for (int t = 0; t < NB; ++t)
+                if (qq + t < q1) acc0 = cfma(av[t], bv[t], acc0);
+        }
+        return cadd(acc0, acc1);
+    };
     // stage a_q'[ia] for q' in [qL, min(q, qL + CL)) (ends with a barrier)
     auto stage_coef = [&](const FT *ag, int la, int ia, int q) {
         const int nc = min(q, qL + CL) - qL;
@@ -806,11 +851,10 @@ __global__ void __launch_bounds__(NT)
             FT *Wq = Wb + (int64_t)q * n;
             FT *Uq = Ub + (int64_t)q * m;
             const FT rv = tid < n ? R[(int64_t)i * n + tid] : czero<FT>();
-            if (q > qL) stage_coef(Ub, m, i, q);
             if (tid < splitw * n) {
                 const int s = tid / n, j = tid - s * n;
                 const int q0 = (int)((int64_t)q * s / splitw), q1 = (int)((int64_t)q * (s + 1) / splitw);
-                part[tid] = hdot(Uh, Ub, m, i, Wh, Wb, n, j, q0, q1);
+                part[tid] = hdot_direct(Uh, Ub, m, i, Wh, Wb, n, j, q0, q1);
             }
             __syncthreads();
             FT v = rv;
@@ -861,6 +905,7 @@ __global__ void __launch_bounds__(NT)
                 if (qq < q) {
                     if (qq < qL) {
                         const FT *wp = Wh + qq * n;
+#pragma unroll 4
                         for (int j = g; j < n; j += G) a0 = cfma(to_d2(xw[j]), conj_d2(to_d2(wp[j])), a0);
                     } else {
                         const FT *wp = Wb + (int64_t)qq * n;
@@ -876,7 +921,16 @@ __global__ void __launch_bounds__(NT)
                                 a1 = cfma(to_d2(xw[j + (t + 1) * G]), conj_d2(to_d2(wv[t + 1])), a1);
                             }
                         }
-                        for (; j < n; j += G) a0 = cfma(to_d2(xw[j]), conj_d2(to_d2(wp[j])), a0);
+                        if (j < n) {
+                            // the rest in one round of loads (indices clamped into range),
+                            // summed in order
+                            FT wv[NBW];
+#pragma unroll
+                            for (int t = 0; t < NBW; ++t) wv[t] = wp[min(j + t * G, n - 1)];
+#pragma unroll
+                            for (int t = 0; t < NBW; ++t)
+                                if (j + t * G < n) a0 = cfma(to_d2(xw[min(j + t * G, n - 1)]), conj_d2(to_d2(wv[t])), a0);
+                        }
                     }
                 }
                 a0 = cadd(a0, a1);
@@ -887,44 +941,53 @@ __global__ void __launch_bounds__(NT)
                 if (g == 0 && qq < q) bvec[qq] = conj_d2(a0);
                 __syncthreads();
             }
-            if (q > qL) stage_coef(Wb, n, jp, q);
             if (tid < splitu * m) {
-                // column jp of R - sum_{q'<q} w_q'[jp] u_q', and v, over this thread's q'
+                // column jp of R - sum_{q'<q} w_q'[jp] u_q', and v, over this thread's q' (the
+                // coefficients w_q'[jp] of the HBM part loaded per thread, one address per row)
                 const int s = tid / m, r = tid - s * m;
                 const int q0 = (int)((int64_t)q * s / splitu), q1 = (int)((int64_t)q * (s + 1) / splitu);
                 FT c0 = czero<FT>(), c1 = czero<FT>();
                 double2 v0 = make_double2(0.0, 0.0), v1 = v0;
                 const int qm = min(q1, qL);
                 int qq = q0;
+#pragma unroll 4
                 for (; qq < qm; ++qq) {
                     const FT uu = Uh[qq * m + r];
                     c0 = cfma(Wh[qq * n + jp], uu, c0);
                     v0 = cfma(bvec[qq], to_d2(uu), v0);
                 }
                 qq = max(q0, qL);
-                const int qc = min(q1, qL + CL);
                 constexpr int NB = NT >= 1024 ? 4 : 16;
-                for (; qq + NB <= qc; qq += NB) {
-                    FT uv[NB];
+                for (; qq + NB <= q1; qq += NB) {
+                    FT uv[NB], wv[NB];
 #pragma unroll
-                    for (int t = 0; t < NB; ++t) uv[t] = Ub[(int64_t)(qq + t) * m + r];
+                    for (int t = 0; t < NB; ++t) {
+                        uv[t] = Ub[(int64_t)(qq + t) * m + r];
+                        wv[t] = Wb[(int64_t)(qq + t) * n + jp];
+                    }
 #pragma unroll
                     for (int t = 0; t < NB; t += 2) {
-                        c0 = cfma(cbuf[qq + t - qL], uv[t], c0);
-                        c1 = cfma(cbuf[qq + t + 1 - qL], uv[t + 1], c1);
+                        c0 = cfma(wv[t], uv[t], c0);
+                        c1 = cfma(wv[t + 1], uv[t + 1], c1);
                         v0 = cfma(bvec[qq + t], to_d2(uv[t]), v0);
                         v1 = cfma(bvec[qq + t + 1], to_d2(uv[t + 1]), v1);
                     }
                 }
-                for (; qq < qc; ++qq) {
-                    const FT uu = Ub[(int64_t)qq * m + r];
-                    c0 = cfma(cbuf[qq - qL], uu, c0);
-                    v0 = cfma(bvec[qq], to_d2(uu), v0);
-                }
-                for (qq = max(q0, qc); qq < q1; ++qq) {
-                    const FT uu = Ub[(int64_t)qq * m + r];
-                    c0 = cfma(Wb[(int64_t)qq * n + jp], uu, c0);
-                    v0 = cfma(bvec[qq], to_d2(uu), v0);
+                if (qq < q1) {
+                    // the rest in one round of loads (clamped), summed in order
+                    FT uv[NB], wv[NB];
+#pragma unroll
+                    for (int t = 0; t < NB; ++t) {
+                        const int qt = min(qq + t, q1 - 1);
+                        uv[t] = Ub[(int64_t)qt * m + r];
+                        wv[t] = Wb[(int64_t)qt * n + jp];
+                    }
+#pragma unroll
+                    for (int t = 0; t < NB; ++t)
+                        if (qq + t < q1) {
+                            c0 = cfma(wv[t], uv[t], c0);
+                            v0 = cfma(bvec[min(qq + t, q1 - 1)], to_d2(uv[t]), v0);
+                        }
                 }
                 part[tid] = cadd(c0, c1);
                 xv[tid] = cadd(v0, v1);
