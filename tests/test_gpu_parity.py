@@ -70,8 +70,8 @@ def test_near_field_c1_all_entries():
     assert st["n_far"] == 0 and st["entries_near"] == 192 * 192 * 16
 
 
-def _compare_far(name, kernel, pick=None, eps_mult=10.0):
-    cfg, prob, _ = gpu_problem(name)
+def _compare_far(name, kernel, pick=None, eps_mult=10.0, **opts):
+    cfg, prob, _ = gpu_problem(name, **opts)
     ocfg, op = _oracle_problem(name)
     from oracle.aca3d import aca3d
     h = prob.build(kernel)
@@ -126,6 +126,51 @@ def test_far_aca_c2_sampled_blocks(kernel):
     del prob
     n_same, n = _compare_far("C2", kernel, pick)
     assert n_same >= n - 2
+
+
+@pytest.mark.parametrize("opts", [dict(threads_large=256), dict(threads_large=1024),
+                                  dict(threads_small=64)], ids=["large256", "large1024", "small64"])
+def test_workgroup_size_options(opts):
+    """The other face-ACA workgroup sizes of the options (large faces on 256 or 1024 threads,
+    the smallest faces on one wave) against the oracle on sampled C2 blocks, the largest
+    block among them."""
+    log("workgroup sizes", opts)
+    cfg, prob, _ = gpu_problem("C2")
+    far, _ = prob.blocks()
+    rng = np.random.default_rng(23)
+    pick = sorted(set(rng.choice(far.shape[0], 5, replace=False).tolist() +
+                      [int(np.argmax(far[:, 1] * far[:, 3]))]))
+    del prob
+    n_same, n = _compare_far("C2", "slp", pick, **opts)
+    assert n_same >= n - 1
+
+
+@pytest.mark.parametrize("tl,m,n", [(1024, 700, 900), (256, 200, 240)])
+def test_compress_tensor_one_entry_path_sizes(tl, m, n):
+    """Faces on the one-entry-per-thread path at 1024 and 256 threads: exact reconstruction
+    of a known-rank tensor with the oracle's pivots."""
+    import torch
+    import paper_2312_11219_amd as gaca
+    from gpu_common import context
+    from oracle.aca3d import aca3d
+    rng = np.random.default_rng(m * n)
+    L, R, rho = 5, 2, 30
+    T = np.zeros((m, n, L), dtype=complex)
+    for _ in range(R):
+        H = (rng.standard_normal((m, rho)) + 1j * rng.standard_normal((m, rho))) @ \
+            (rng.standard_normal((rho, n)) + 1j * rng.standard_normal((rho, n)))
+        T += H[:, :, None] * (rng.standard_normal(L) + 1j * rng.standard_normal(L))[None, None, :]
+    h = gaca.compress_tensor(context(), torch.from_numpy(T).cuda(), eps3d=1e-10, eps_aca=1e-12,
+                             threads_large=tl)
+    b = h.export_block(0)
+    o = aca3d(T, 1e-10, 1e-12)
+    err = rel_fro(h.reconstruct_block(0), T)
+    log(f"one-entry path {tl} threads, {m} x {n}: rank {b['rank']} (oracle {o.rank}), "
+        f"face ranks {[c['rho'] for c in b['crosses']]}, rel err {err:.2e}")
+    assert b["rank"] == R == o.rank
+    assert err < 1e-11
+    assert [c["k"] for c in b["crosses"]] == [c.k for c in o.crosses]
+    assert [(c["i"], c["j"]) for c in b["crosses"]] == [(c.i, c.j) for c in o.crosses]
 
 
 def test_c2_near_sampled():
