@@ -689,8 +689,8 @@ __global__ void __launch_bounds__(NT)
         return acc;
     };
     // the same sum with both operands of the HBM part loaded per thread (the coefficient
-    // a_q'[ia] is one address across the row, so no staging pass and barrier before it);
-    // the one-entry path, whose steps are all below qL + CL
+    // a_q'[ia] is one address across the row, so no staging pass and barrier before it)
+    // for every q' >= qL; used by the one-entry path
     auto hdot_direct = [&](const FT *ah, const FT *ag, int la, int ia, const FT *bh, const FT *bg,
                            int lb, int ib, int q0, int q1) {
         FT acc0 = czero<FT>(), acc1 = czero<FT>();
