@@ -342,16 +342,23 @@ def main():
                      "ms_per_launch": dom["ms"] / max(1, dom["launches"])},
     }
     if not args.no_mixed:
-        out["mixed"] = mixed_leg(gaca, ctx, xyz, tri, s, cfg, X, kernels, stream, prob, args)
+        # the FP64 apply of the same X as the mixed leg's reference, then the FP64 problem is
+        # released (the mixed problem takes over its far-field streams)
+        h64s = build_all(prob, kernels)
+        y64s = [h.apply(X, stream=stream) for h in h64s]
+        torch.cuda.synchronize()
+        del h64s
+        prob.close()
+        out["mixed"] = mixed_leg(gaca, ctx, xyz, tri, s, cfg, X, kernels, stream, y64s, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, xyz, tri, s, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
-def mixed_leg(gaca, ctx, xyz, tri, s, cfg, X, kernels, stream, prob64, args):
+def mixed_leg(gaca, ctx, xyz, tri, s, cfg, X, kernels, stream, y64s, args):
     """The same step with the mixed-precision build (FP32 far-field faces and factors with
     the per-(block, frequency) scale, FP64 fibres/norms; near field stored FP32) and the
-    relative difference of its apply from the FP64 build's apply (same X)."""
+    relative difference of its apply from the FP64 build's apply of the same X (y64s)."""
     import numpy as np
     import torch
     pm = gaca.Problem(ctx, xyz, tri, s, leaf_size=cfg["leaf"], eta=cfg["eta"],
@@ -373,13 +380,9 @@ def mixed_leg(gaca, ctx, xyz, tri, s, cfg, X, kernels, stream, prob64, args):
     last = runs[-1]
     entries = sum(st["entries_near"] + st["entries_face"] + st["entries_fibre"] for st, _ in last)
     errs = {}
-    h64s = build_all(prob64, kernels)
-    for k, (st, y), h64 in zip(kernels, last, h64s):
-        y64 = h64.apply(X, stream=stream)
-        torch.cuda.synchronize()
+    for k, (st, y), y64 in zip(kernels, last, y64s):
         d = (y.to(torch.complex128) - y64).norm().item() / y64.norm().item()
         errs[k] = d
-    del h64s
     return {"value": entries * len(runs) / el, "unit": "entries/s",
             "ms_per_step": el / len(runs) * 1e3,
             "build_ms": {k: st["ms_total"] for k, (st, _) in zip(kernels, last)},

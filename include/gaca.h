@@ -147,7 +147,10 @@ const char *gaca_last_error(void);
 void gaca_options_default(gaca_options *opt);
 
 /* Context on HIP device `device`, launching on `hip_stream` (a hipStream_t, may be NULL
- * for the default stream; not owned).  GACA_ERR_STATE if no usable GPU. */
+ * for the default stream; not owned).  GACA_ERR_STATE if no usable GPU.  Destroy every
+ * problem and operator made on a context before the context itself: they account their
+ * device memory in it, and a destroyed problem hands its far-field streams back to it for
+ * the next problem. */
 gaca_status gaca_context_create(int device, void *hip_stream, gaca_context **out);
 gaca_status gaca_context_destroy(gaca_context *ctx);
 

@@ -366,4 +366,6 @@ def compress_tensor(ctx: Context, T, **options) -> HMatrix:
     h = P()
     rc = _check(lib.gaca_compress_tensor(ctx.handle, P(T.data_ptr()), m, n, L, ctypes.byref(opt),
                                          ctypes.byref(h)), (-5,))
-    return HMatrix(None, h, "tensor", converged=(rc == 0), L=L)
+    hm = HMatrix(None, h, "tensor", converged=(rc == 0), L=L)
+    hm.ctx = ctx   # the operator uses its context until it is destroyed
+    return hm

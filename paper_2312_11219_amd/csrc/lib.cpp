@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -13,6 +14,7 @@
 #include <mutex>
 #include <functional>
 #include <numeric>
+#include <vector>
 
 #include "host.h"
 #include "kernels.h"
@@ -27,6 +29,16 @@ struct gaca_context {
     hipStream_t stream = nullptr;
     uint64_t limit = 0;       // 0: none
     std::atomic<uint64_t> in_use{0};   // builds of different problems may run in parallel threads
+    // far-field stream sets (four streams each) of destroyed problems, taken again by later
+    // problems: the runtime spreads streams over a few hardware queues in creation order, so
+    // fresh streams for every problem can land two face classes on one queue, where they
+    // run one after the other
+    std::mutex stream_mu;
+    std::vector<std::array<hipStream_t, 4>> stream_pool;
+    ~gaca_context() {
+        for (auto &set : stream_pool)
+            for (hipStream_t st : set) (void)hipStreamDestroy(st);
+    }
 };
 
 namespace {
@@ -411,8 +423,10 @@ struct gaca_problem {
     DevBuf near_spare[2];
     GrowBuf spare_arena[2], spare_fib[2];
     ~gaca_problem() {
-        if (far_streams_ready)
-            for (auto &s : far_streams) (void)hipStreamDestroy(s);
+        if (far_streams_ready) {
+            std::lock_guard<std::mutex> lk(ctx->stream_mu);
+            ctx->stream_pool.push_back({far_streams[0], far_streams[1], far_streams[2], far_streams[3]});
+        }
     }
 };
 
@@ -953,9 +967,19 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
 
     main_work();   // near field on the context stream, concurrently with the far field
     if (!p->far_streams_ready) {
-        for (int k = 0; k < 4; ++k)
-            GACA_HIP_CHECK(hipStreamCreateWithFlags(&p->far_streams[k], hipStreamNonBlocking));
-        p->far_streams_ready = true;
+        {
+            std::lock_guard<std::mutex> lk(ctx->stream_mu);
+            if (!ctx->stream_pool.empty()) {
+                for (int k = 0; k < 4; ++k) p->far_streams[k] = ctx->stream_pool.back()[k];
+                ctx->stream_pool.pop_back();
+                p->far_streams_ready = true;
+            }
+        }
+        if (!p->far_streams_ready) {
+            for (int k = 0; k < 4; ++k)
+                GACA_HIP_CHECK(hipStreamCreateWithFlags(&p->far_streams[k], hipStreamNonBlocking));
+            p->far_streams_ready = true;
+        }
     }
     hipStream_t s0 = p->far_streams[0];
     // the aca phase of kind k runs on ks[k] (kind 3, the large faces, on the main far stream)
