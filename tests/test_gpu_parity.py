@@ -208,6 +208,23 @@ def test_build_deterministic():
             assert np.array_equal(c1["U"], c2["U"]) and np.array_equal(c1["f"], c2["f"])
 
 
+def test_problem_after_destroyed_problem():
+    """A problem built after an earlier one was destroyed (it takes over that problem's
+    far-field streams) gives bitwise the same operator as the first."""
+    from inputs import random_rhs
+    import torch
+    ys = []
+    for _ in range(2):
+        cfg, prob, (xyz, tri, s) = gpu_problem("cube768")
+        h = prob.build("dlp")
+        X = torch.from_numpy(random_rhs(cfg["L"], tri.shape[0], 3, seed=5)).cuda()
+        ys.append(h.apply(X).cpu().numpy())
+        del h
+        prob.close()
+    log("problem after a destroyed problem: max |diff|", float(np.abs(ys[0] - ys[1]).max()))
+    assert np.array_equal(ys[0], ys[1])
+
+
 @pytest.mark.parametrize("mode", ["sum", "per_freq"])
 def test_apply_matches_exported_dense(mode):
     import torch
