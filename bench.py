@@ -392,7 +392,8 @@ def mixed_leg(gaca, ctx, xyz, tri, s, cfg, X, kernels, stream, y64s, args):
                                             for r in runs])) for k in range(4)],
             "apply_rel_diff_vs_fp64": errs,
             "ranks": {k: [st["rank_min"], st["rank_max"], round(st["rank_mean"], 2)]
-                      for k, (st, _) in zip(kernels, last)}}
+                      for k, (st, _) in zip(kernels, last)},
+            "far_iters": {k: st["far_iters"] for k, (st, _) in zip(kernels, last)}}
 
 
 if __name__ == "__main__":
