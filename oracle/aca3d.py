@@ -64,11 +64,13 @@ def argmax_tie(a2: np.ndarray, mask: np.ndarray | None = None, tie: float = TIE)
 
 
 def face_aca(R: np.ndarray, eps_aca: float, zero_tol: float, max_rank: int, tie: float = TIE,
-             ref2: float = 0.0):
+             ref2: float = 0.0, return_pivots: bool = False):
     """Partial-pivot ACA of the dense residual face R (m x n): R ~ U W^T.  ``ref2`` is the
-    squared norm of the part of the face already represented (added to ||S||^2 in the stop test)."""
+    squared norm of the part of the face already represented (added to ||S||^2 in the stop test).
+    With ``return_pivots`` also the pivot rows and columns of the crosses, in order."""
     m, n = R.shape
     us, ws = [], []
+    piv = []
     used = np.zeros(m, dtype=bool)
     s2 = 0.0
     i = 0
@@ -98,13 +100,16 @@ def face_aca(R: np.ndarray, eps_aca: float, zero_tol: float, max_rank: int, tie:
         s2 = s2 + 2.0 * cross + nu2 * nw2
         us.append(u_new)
         ws.append(w_new)
+        piv.append((i, int(j)))
         if np.sqrt(nu2 * nw2) <= eps_aca * np.sqrt(ref2 + s2) or used.all() or len(us) >= max_rank:
             break
         au = u_new.real ** 2 + u_new.imag ** 2
         i = argmax_tie(au, ~used, tie=tie)
     if not us:
-        return np.zeros((m, 0), complex), np.zeros((n, 0), complex)
-    return np.stack(us, axis=1), np.stack(ws, axis=1)
+        U, W = np.zeros((m, 0), complex), np.zeros((n, 0), complex)
+    else:
+        U, W = np.stack(us, axis=1), np.stack(ws, axis=1)
+    return (U, W, piv) if return_pivots else (U, W)
 
 
 @dataclass

@@ -49,7 +49,7 @@ def _load():
         lib.oracle_collocation_entries_order.restype = None
         lib.oracle_galerkin_entries.argtypes = [
             P, P, ctypes.c_int, P, P, ctypes.c_int64, P, P, P, P, ctypes.c_int, P,
-            ctypes.c_int, P, ctypes.c_int, P, P, P]
+            ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int, P, P, P]
         lib.oracle_galerkin_entries.restype = None
         _lib = lib
     return _lib

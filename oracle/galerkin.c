@@ -4,14 +4,28 @@
  *
  * TEST INFRASTRUCTURE ONLY -- plain FP64 loops; shares no code with the GPU library.
  *
- * Quadrature reading (the paper cites the Erichsen-Sauter scheme for the weakly singular
- * integrals and a distance heuristic for the regular ones, without orders):
+ * Quadrature reading (the paper treats the weakly singular Galerkin integrals with the
+ * regularising transformations of Erichsen and Sauter and the regular ones with a
+ * distance heuristic, without orders):
  *   far blocks, and disjoint near pairs with q >= 4:  6-point rule x 6-point rule;
  *   disjoint near pairs with 2 <= q < 4:              collapsed 4x4 x collapsed 4x4;
- *   disjoint near pairs with q < 2, and pairs sharing an edge or a vertex:
- *       outer collapsed n_G x n_G rule on tau_i (collapsed at a shared vertex when there is
- *       one), inner integral over tau_j split at the point of tau_j nearest to the outer
+ *   disjoint near pairs with q < 2 (no shared vertex): outer collapsed n_G x n_G rule on
+ *       tau_i, inner integral over tau_j split at the point of tau_j nearest to the outer
  *       point into three Duffy sub-triangles with n_G x n_G points each;
+ *   pairs sharing an edge or a vertex: the Sauter-Schwab regularising maps of [0,1]^4
+ *       (the family of the Erichsen-Sauter scheme).  Both triangles are mapped from the
+ *       reference triangle {0 <= t2 <= t1 <= 1} by x(t) = P0 + t1 (P1 - P0) + t2 (P2 - P1)
+ *       with the shared vertex at P0 (and, for an edge, the shared edge at t2 = 0).  The
+ *       product of the two reference triangles splits into 2 (vertex) or 5 (edge) regions,
+ *       each mapped from (xi, eta1, eta2, eta3) in [0,1]^4 so that x - y = xi d(eta)
+ *       (vertex) or xi eta1 d(eta2, eta3) (edge) with |d| bounded away from zero.  The
+ *       kernel depends on xi (and eta1) only through exp(-s r) / r, so these integrals are
+ *       done exactly: vertex int_0^1 xi^2 e^{-t xi} d xi = phi2(t) =
+ *       (2 - e^{-t}(t^2 + 2t + 2)) / t^3 (series sum_k (-t)^k / (k! (k + 3)) for |t| <= 1),
+ *       edge int_0^1 eta1 phi2(t eta1) d eta1 = (t - 2 + e^{-t}(t + 2)) / t^3 (series
+ *       sum_k (-t)^k / (k! (k + 2) (k + 3)) for |t| <= 1); the remaining smooth integral
+ *       over (eta1, eta2, eta3) (vertex) or (eta2, eta3) (edge) takes n_S Gauss-Legendre
+ *       points per direction;
  *   coincident pairs (i == j): exact reduction to one angle.  For a flat triangle T the
  *       kernel depends on z = x - y only, so V = int k(z) |T cap (T + z)| dz, and with the
  *       barycentric functions l_i (linear parts ell_i) |T cap (T + z)| =
@@ -22,6 +36,9 @@
  *       the six sectors between the edge directions are integrated with n_theta
  *       Gauss-Legendre points each.
  *   q = |x_i - x_j| / max(h_i, h_j).
+ * Vertex order of the touching maps: for a shared edge, P0 and P1 are the shared vertices
+ * in the order they appear in tau_i's vertex list and P2 each triangle's third vertex;
+ * for a shared vertex V, each triangle's list is rotated cyclically to start at V.
  *
  * Parity pins: tests/test_oracle_galerkin.py.
  */
@@ -241,6 +258,108 @@ static void coincident(const gtri_t *t, int L, const double *s_re, const double 
     }
 }
 
+
+/* phi2(t) = int_0^1 xi^2 e^{-t xi} d xi */
+static double complex phi2(double complex t) {
+    if (cabs(t) <= 1.0) {
+        double complex term = 1.0, sum = 0.0;   /* term = (-t)^k / k! */
+        for (int k = 0; k < 30; ++k) {
+            sum += term / (double)(k + 3);
+            term *= -t / (double)(k + 1);
+        }
+        return sum;
+    }
+    return (2.0 - cexp(-t) * (t * t + 2.0 * t + 2.0)) / (t * t * t);
+}
+
+/* one region term of the vertex maps: weight * phi2(s rho) / (4 pi rho), every frequency */
+static void ss_add(const double *d, double wg, int L, const double *s_re, const double *s_im,
+                   double *acc) {
+    double rho = norm3(d);
+    for (int l = 0; l < L; ++l) {
+        double complex s = s_re[l] + I * s_im[l];
+        double complex v = wg * phi2(s * rho) / (4.0 * PI * rho);
+        acc[2 * l] += creal(v);
+        acc[2 * l + 1] += cimag(v);
+    }
+}
+
+/* Common vertex V: tau_i = (V, a1, a2), tau_j = (V, b1, b2). */
+static void ss_vertex(const double *V, const double *a1, const double *a2, const double *b1,
+                      const double *b2, double area_i, double area_j, int n, const double *g,
+                      int L, const double *s_re, const double *s_im, double *out) {
+    double X1[3], X2[3], Y1[3], Y2[3];
+    sub3(a1, V, X1);
+    sub3(a2, a1, X2);
+    sub3(b1, V, Y1);
+    sub3(b2, b1, Y2);
+    for (int l = 0; l < 2 * L; ++l) out[l] = 0.0;
+    for (int p1 = 0; p1 < n; ++p1)
+        for (int p2 = 0; p2 < n; ++p2)
+            for (int p3 = 0; p3 < n; ++p3) {
+                double e1 = g[2 * p1], e2 = g[2 * p2], e3 = g[2 * p3];
+                double w = g[2 * p1 + 1] * g[2 * p2 + 1] * g[2 * p3 + 1];
+                double d[3];
+                /* region t1 >= u1: t = xi (1, e1), u = xi e2 (1, e3) */
+                for (int k = 0; k < 3; ++k)
+                    d[k] = (X1[k] + e1 * X2[k]) - e2 * (Y1[k] + e3 * Y2[k]);
+                ss_add(d, w * e2, L, s_re, s_im, out);
+                /* region u1 > t1: u = xi (1, e1), t = xi e2 (1, e3) */
+                for (int k = 0; k < 3; ++k)
+                    d[k] = e2 * (X1[k] + e3 * X2[k]) - (Y1[k] + e1 * Y2[k]);
+                ss_add(d, w * e2, L, s_re, s_im, out);
+            }
+    for (int l = 0; l < 2 * L; ++l) out[l] *= 4.0 * area_i * area_j;
+}
+
+/* Phi(t) = int_0^1 eta int_0^1 xi^2 e^{-t eta xi} d xi d eta = (t - 2 + e^{-t} (t + 2)) / t^3 */
+static double complex phi_edge(double complex t) {
+    if (cabs(t) <= 1.0) {
+        double complex term = 1.0, sum = 0.0;   /* term = (-t)^k / k! */
+        for (int k = 0; k < 30; ++k) {
+            sum += term / ((double)(k + 2) * (double)(k + 3));
+            term *= -t / (double)(k + 1);
+        }
+        return sum;
+    }
+    return (t - 2.0 + cexp(-t) * (t + 2.0)) / (t * t * t);
+}
+
+/* Common edge (P0, P1): tau_i = (P0, P1, a), tau_j = (P0, P1, b).  In every region
+ * x - y = xi eta1 d(eta2, eta3), so both the xi and the eta1 integral are exact (phi_edge)
+ * and n x n Gauss points remain per region. */
+static void ss_edge(const double *P0, const double *P1, const double *a, const double *b,
+                    double area_i, double area_j, int n, const double *g, int L,
+                    const double *s_re, const double *s_im, double *out) {
+    double E[3], A[3], B[3];
+    sub3(P1, P0, E);
+    sub3(a, P1, A);
+    sub3(b, P1, B);
+    for (int l = 0; l < 2 * L; ++l) out[l] = 0.0;
+    for (int p2 = 0; p2 < n; ++p2)
+        for (int p3 = 0; p3 < n; ++p3) {
+            double e2 = g[2 * p2], e3 = g[2 * p3];
+            double w = g[2 * p2 + 1] * g[2 * p3 + 1];
+            double c[5][3] = {{e2, e3, -(1.0 - e2)},
+                              {e2 * e3, 1.0, -e2 * (1.0 - e3)},
+                              {-e2, 1.0 - e2, -e2 * e3},
+                              {-e2 * e3, e2 * (1.0 - e3), -1.0},
+                              {-e2 * e3, 1.0 - e2 * e3, -e2}};
+            for (int r = 0; r < 5; ++r) {
+                double d[3];
+                for (int k = 0; k < 3; ++k) d[k] = c[r][0] * E[k] + c[r][1] * A[k] + c[r][2] * B[k];
+                double rho = norm3(d), wr = w * (r == 0 ? 1.0 : e2);
+                for (int l = 0; l < L; ++l) {
+                    double complex s = s_re[l] + I * s_im[l];
+                    double complex v = wr * phi_edge(s * rho) / (4.0 * PI * rho);
+                    out[2 * l] += creal(v);
+                    out[2 * l + 1] += cimag(v);
+                }
+            }
+        }
+    for (int l = 0; l < 2 * L; ++l) out[l] *= 4.0 * area_i * area_j;
+}
+
 enum { G_FAR36 = 0, G_MID = 1, G_NEAR = 2, G_EDGE = 3, G_VERTEX = 4, G_COINC = 5 };
 
 /*
@@ -251,7 +370,8 @@ void oracle_galerkin_entries(const double *tri9, const int32_t *tri, int L, cons
                              const double *s_im, int64_t npair, const int64_t *ii,
                              const int64_t *jj, const int32_t *far, const double *r6,
                              int n4, const double *g4, int ng, const double *gg, int nt,
-                             const double *gt, double *out, int32_t *tier_out) {
+                             const double *gt, int nss, const double *gs, double *out,
+                             int32_t *tier_out) {
     int maxq = 3 * ng * ng;
     if (n4 * n4 > maxq) maxq = n4 * n4;
     if (maxq < 6) maxq = 6;
@@ -273,11 +393,13 @@ void oracle_galerkin_entries(const double *tri9, const int32_t *tri, int L, cons
             make_gtri(tri9 + 9 * j, &tj);
             double *o = out + 2 * (size_t)L * p;
             for (int l = 0; l < 2 * L; ++l) o[l] = 0.0;
-            int shared = 0, sv_i = -1;
+            /* shared vertices: positions in tau_i (ascending) and in tau_j */
+            int shared = 0, pos_i[3], pos_j[3];
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b)
                     if (tri[3 * i + a] == tri[3 * j + b]) {
-                        if (sv_i < 0) sv_i = a;
+                        pos_i[shared] = a;
+                        pos_j[shared] = b;
                         ++shared;
                     }
             int tier;
@@ -310,9 +432,21 @@ void oracle_galerkin_entries(const double *tri9, const int32_t *tri, int L, cons
                 for (int a = 0; a < qout.n; ++a) accumulate(qout.y + 3 * a, qout.w[a], &qin, L, s_re, s_im, o);
                 continue;
             }
-            /* outer collapsed rule, collapsed at a shared vertex if there is one */
-            int c0 = sv_i < 0 ? 0 : sv_i;
-            collapsed(ti.v[c0], ti.v[(c0 + 1) % 3], ti.v[(c0 + 2) % 3], ng, gg, &qout);
+            if (tier == G_EDGE) {
+                int ta = 3 - pos_i[0] - pos_i[1], tb = 3 - pos_j[0] - pos_j[1];
+                ss_edge(ti.v[pos_i[0]], ti.v[pos_i[1]], ti.v[ta], tj.v[tb], ti.area, tj.area, nss,
+                        gs, L, s_re, s_im, o);
+                continue;
+            }
+            if (tier == G_VERTEX) {
+                int a = pos_i[0], b = pos_j[0];
+                ss_vertex(ti.v[a], ti.v[(a + 1) % 3], ti.v[(a + 2) % 3], tj.v[(b + 1) % 3],
+                          tj.v[(b + 2) % 3], ti.area, tj.area, nss, gs, L, s_re, s_im, o);
+                continue;
+            }
+            /* disjoint q < 2: outer collapsed rule at vertex a of tau_i, inner split at the
+             * nearest point */
+            collapsed(ti.v[0], ti.v[1], ti.v[2], ng, gg, &qout);
             for (int a = 0; a < qout.n; ++a) {
                 const double *x = qout.y + 3 * a;
                 double pnt[3];

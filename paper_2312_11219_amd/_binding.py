@@ -317,13 +317,6 @@ class HMatrix:
         inf["crosses"] = crosses
         return inf
 
-    def reconstruct_block(self, idx):
-        b = self.export_block(idx)
-        out = np.zeros((b["m"], b["n"], self.L), dtype=complex)
-        for c in b["crosses"]:
-            out += (c["U"] @ c["W"].T)[:, :, None] * c["f"][None, None, :]
-        return out
-
     def near_block(self, idx, m, n):
         out = np.zeros(2 * m * n * self.L)
         _check(self._lib.gaca_hmatrix_near_export(self.handle, idx, _ptr(out)))

@@ -60,3 +60,13 @@ def oracle_problem(name):
 def rel_fro(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a)
+
+
+def reconstruct(h, idx):
+    """Dense m x n x L tensor of far block idx from its exported factors: the sum over the
+    block's crosses of (U_l W_l^T) outer f_l (Sec. 4, eq. (outerProd)), in FP64 on the CPU."""
+    b = h.export_block(idx)
+    out = np.zeros((b["m"], b["n"], h.L), dtype=complex)
+    for c in b["crosses"]:
+        out += (c["U"] @ c["W"].T)[:, :, None] * c["f"][None, None, :]
+    return out

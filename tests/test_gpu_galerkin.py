@@ -3,7 +3,7 @@ against the FP64 oracle, through the C ABI.  Same bars as the collocation tests.
 import numpy as np
 import pytest
 
-from gpu_common import gpu_problem, log, oracle_problem, rel_fro, workload
+from gpu_common import gpu_problem, log, oracle_problem, reconstruct, rel_fro, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -64,7 +64,7 @@ def test_galerkin_far_aca(precision):
         blk = tuple(int(v) for v in far[b])
         T = op.block_tensor("slp", blk, True)
         o = aca3d(T, cfg["eps"], cfg["eps_aca"])
-        C = h.reconstruct_block(b)
+        C = reconstruct(h, b)
         Co = o.reconstruct(blk[1], blk[3], op.L)
         e = h.export_block(b)
         same += e["rank"] == o.rank and all(c["k"] == oc.k and c["i"] == oc.i and c["j"] == oc.j
@@ -96,7 +96,7 @@ def test_c4_sampled_blocks():
         blk = tuple(int(v) for v in far[b])
         T = op.block_tensor("slp", blk, True)
         o = aca3d(T, cfg["eps"], cfg["eps_aca"])
-        C = h.reconstruct_block(b)
+        C = reconstruct(h, b)
         pnum += np.linalg.norm(C - o.reconstruct(blk[1], blk[3], op.L)) ** 2
         num += np.linalg.norm(C - T) ** 2
         den += np.linalg.norm(T) ** 2

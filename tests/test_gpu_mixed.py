@@ -10,7 +10,7 @@ agrees with the FP64 apply of the same factors within 1e-5; stored near field wi
 import numpy as np
 import pytest
 
-from gpu_common import gpu_problem, log, rel_fro, workload
+from gpu_common import gpu_problem, log, reconstruct, rel_fro, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -34,8 +34,8 @@ def _errors(name, kernel, pick=None):
     for b in idx:
         blk = tuple(int(v) for v in far[b])
         T = op.block_tensor(kernel, blk, True)
-        e64 = np.linalg.norm(h64.reconstruct_block(b) - T)
-        emx = np.linalg.norm(hmx.reconstruct_block(b) - T)
+        e64 = np.linalg.norm(reconstruct(h64, b) - T)
+        emx = np.linalg.norm(reconstruct(hmx, b) - T)
         nt = np.linalg.norm(T)
         n64 += e64 ** 2
         nmx += emx ** 2
@@ -119,7 +119,7 @@ def test_mixed_c5_sampled_blocks_and_apply():
         blk = tuple(int(v) for v in far[b])
         assert blk == tuple(int(v) for v in op.far[b])
         T = op.block_tensor("slp", blk, True)
-        num += np.linalg.norm(h.reconstruct_block(b) - T) ** 2
+        num += np.linalg.norm(reconstruct(h, b) - T) ** 2
         den += np.linalg.norm(T) ** 2
     err = float(np.sqrt(num / den))
     M, L = tri.shape[0], len(s)

@@ -8,7 +8,7 @@ pivot sequences agree), and each error against the dense tensor <= 10 eps; apply
 import numpy as np
 import pytest
 
-from gpu_common import gpu_problem, log, rel_fro, workload
+from gpu_common import gpu_problem, log, reconstruct, rel_fro, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -84,7 +84,7 @@ def _compare_far(name, kernel, pick=None, eps_mult=10.0, **opts):
         Tb = op.block_tensor(kernel, blk, True)
         ores = aca3d(Tb, cfg["eps"], cfg["eps_aca"])
         gb = h.export_block(b)
-        C_g = h.reconstruct_block(b)
+        C_g = reconstruct(h, b)
         C_o = ores.reconstruct(blk[1], blk[3], op.L)
         same = (gb["rank"] == ores.rank and
                 all(c["k"] == oc.k and c["i"] == oc.i and c["j"] == oc.j and c["rho"] == oc.U.shape[1]
@@ -164,7 +164,7 @@ def test_compress_tensor_one_entry_path_sizes(tl, m, n):
                              threads_large=tl)
     b = h.export_block(0)
     o = aca3d(T, 1e-10, 1e-12)
-    err = rel_fro(h.reconstruct_block(0), T)
+    err = rel_fro(reconstruct(h, 0), T)
     log(f"one-entry path {tl} threads, {m} x {n}: rank {b['rank']} (oracle {o.rank}), "
         f"face ranks {[c['rho'] for c in b['crosses']]}, rel err {err:.2e}")
     assert b["rank"] == R == o.rank
@@ -239,7 +239,7 @@ def test_apply_matches_exported_dense(mode):
     for b, blk in enumerate(far):
         rows = perm[blk[0]:blk[0] + blk[1]]
         cols = perm[blk[2]:blk[2] + blk[3]]
-        C[np.ix_(rows, cols)] = h.reconstruct_block(b)
+        C[np.ix_(rows, cols)] = reconstruct(h, b)
     for b, blk in enumerate(near):
         rows = perm[blk[0]:blk[0] + blk[1]]
         cols = perm[blk[2]:blk[2] + blk[3]]
@@ -309,7 +309,7 @@ def test_compress_tensor_known_rank(R, rho):
         T += H[:, :, None] * (rng.standard_normal(L) + 1j * rng.standard_normal(L))[None, None, :]
     h = gaca.compress_tensor(context(), torch.from_numpy(T).cuda(), eps3d=1e-10, eps_aca=1e-12)
     b = h.export_block(0)
-    C = h.reconstruct_block(0)
+    C = reconstruct(h, 0)
     o = aca3d(T, 1e-10, 1e-12)
     assert b["rank"] == R == o.rank
     assert rel_fro(C, T) < 1e-12
@@ -335,7 +335,7 @@ def test_compress_tensor_large_faces(m, n):
     h = gaca.compress_tensor(context(), torch.from_numpy(T).cuda(), eps3d=1e-10, eps_aca=1e-12)
     b = h.export_block(0)
     o = aca3d(T, 1e-10, 1e-12)
-    err = rel_fro(h.reconstruct_block(0), T)
+    err = rel_fro(reconstruct(h, 0), T)
     log(f"large faces {m} x {n}: rank {b['rank']} (oracle {o.rank}), rel err {err:.2e}")
     assert b["rank"] == R == o.rank
     assert err < 1e-11
@@ -362,7 +362,7 @@ def test_compress_tensor_degenerate_shapes(m, n, L):
     b = h.export_block(0)
     o = aca3d(T, 1e-10, 1e-12)
     assert b["rank"] == o.rank == 1
-    assert rel_fro(h.reconstruct_block(0), T) < 1e-12
+    assert rel_fro(reconstruct(h, 0), T) < 1e-12
     assert [c["k"] for c in b["crosses"]] == [c.k for c in o.crosses]
     assert [(c["i"], c["j"]) for c in b["crosses"]] == [(c.i, c.j) for c in o.crosses]
 
@@ -380,7 +380,7 @@ def test_compress_tensor_zero_and_dense():
     T = rng.standard_normal((6, 5, 4)) + 1j * rng.standard_normal((6, 5, 4))
     h = gaca.compress_tensor(context(), torch.from_numpy(T).cuda(), eps3d=0.0, eps_aca=0.0)
     assert h.export_block(0)["rank"] == 4
-    assert rel_fro(h.reconstruct_block(0), T) < 1e-12
+    assert rel_fro(reconstruct(h, 0), T) < 1e-12
     o = aca3d(T, 0.0, 0.0)
     assert [c["k"] for c in h.export_block(0)["crosses"]] == [c.k for c in o.crosses]
 
@@ -399,7 +399,7 @@ def test_concurrent_builds_match_sequential():
         for b in range(0, far.shape[0], 7):
             es, ep = hs.export_block(b), hp.export_block(b)
             assert es["rank"] == ep["rank"]
-            np.testing.assert_array_equal(hs.reconstruct_block(b), hp.reconstruct_block(b))
+            np.testing.assert_array_equal(reconstruct(hs, b), reconstruct(hp, b))
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -422,7 +422,7 @@ def test_joint_build_matches_separate(precision):
         for b in range(0, far.shape[0], 5):
             es, ej = hs.export_block(b), hj.export_block(b)
             assert es["rank"] == ej["rank"]
-            np.testing.assert_array_equal(hs.reconstruct_block(b), hj.reconstruct_block(b))
+            np.testing.assert_array_equal(reconstruct(hs, b), reconstruct(hj, b))
         ys, yj = hs.apply(X, mode="sum"), hj.apply(X, mode="sum")
         torch.cuda.synchronize()
         np.testing.assert_array_equal(ys.cpu().numpy(), yj.cpu().numpy())

@@ -114,6 +114,29 @@ def test_face_aca_exact_low_rank(rho):
     assert np.linalg.norm(U @ W.T - A) < 1e-12 * np.linalg.norm(A)
 
 
+def test_face_aca_zero_rows():
+    """Zero rows (rows 0, 3 and 7 exactly zero) and a residual that turns zero while rows of a
+    second, decoupled block remain: R = [[A, 0], [0, B]] with A (rows 0-7, columns 0-5) of
+    rank 2 and B (rows 8-15, columns 6-11) of rank 3.  The search starts at row 0 (zero, so
+    row 1 is next in index order); once A is exhausted every unused row of A has a zero
+    residual and is passed over in index order, so the first cross in B is at row 8; the
+    face is recovered exactly with 5 crosses."""
+    rng = np.random.default_rng(11)
+    cplx = lambda *sh: rng.standard_normal(sh) + 1j * rng.standard_normal(sh)
+    R = np.zeros((16, 12), complex)
+    A = cplx(8, 2) @ cplx(2, 6)
+    A[[0, 3, 7]] = 0.0
+    R[:8, :6] = A
+    R[8:, 6:] = cplx(8, 3) @ cplx(3, 6)
+    U, W, piv = face_aca(R, 1e-14, 1e-10 * np.abs(R).max(), 16, return_pivots=True)
+    rows = [p[0] for p in piv]
+    assert U.shape[1] == 5 and len(rows) == 5
+    assert rows[0] == 1 and rows[2] == 8
+    assert not {0, 3, 7} & set(rows)
+    assert set(rows[:2]) <= {1, 2, 4, 5, 6} and set(rows[2:]) <= set(range(8, 16))
+    assert np.linalg.norm(U @ W.T - R) <= 1e-12 * np.linalg.norm(R)
+
+
 def test_face_aca_smooth_kernel_vs_svd():
     # two separated point clouds, Laplace-domain kernel at one frequency
     rng = np.random.default_rng(6)
