@@ -1,16 +1,24 @@
 """Benchmark: 3-way ACA build of Laplace-domain BEM tensors on one MI355X.
 
-One step = the whole hot path on the 3072-triangle cube workload (collocation, L = 64,
-s_l = 20 (1 + 0.95 e^{i 2 pi (l + 1/2)/64}), leaf 32, eta 1, eps 1e-6, FP64): the dense
-near field and the 3D-ACA of every far block for the single layer AND the double layer,
-plus one reordered product (eq. product, 2 right-hand sides per frequency) with each.
-The two operators are built together (gaca_build_both: the far blocks of both share every
-far-field launch).  The problem (mesh, tree, partition, device geometry) is created before
-the timed region; the right-hand sides are resident in HBM.
+Default workload (--config C3): the unit ball as icosphere subdivision 5 (20480 triangles),
+collocation P0 single layer, L = 128 frequencies s_l = 40 (1 + 0.95 e^{i 2 pi (l + 1/2)/128}),
+leaf 32, eta 1, eps 1e-5 (face tolerance eps / 100).  One step = the whole hot path: the
+dense near field and the 3D-ACA of every far block (Algorithm 1), then one reordered product
+(eq. product, 2 right-hand sides per frequency).  The problem (mesh, tree, partition,
+device geometry) is created before the timed region; the right-hand sides are resident in
+HBM.  Two legs run one after the other: the FP64 build (value) and the mixed-precision
+build (FP32 far-field faces and factors, FP64 fibres, norms and near-field quadrature).
+
+Each leg states its relative Frobenius error against the FP64 oracle's dense tensor on a
+seeded sample of far and near blocks; the oracle's dense blocks come from the cpu_baseline
+leg, which times the oracle (dense assembly + serial 3D-ACA) on that sample.
 
 Prints ONE JSON line.  value = kernel entries per second, where the entries are the
-tensor entries the method needs: the dense near field (m n L per near block), the rows
-and columns the face ACAs read (rho (m + n) per face) and the frequency fibres (r L).
+tensor entries the method evaluates: the near field (m n L per near block, of which the
+conjugate mirror of the frequencies halves the evaluated part: both counts are stated), the
+rows and columns the face ACAs read (rho (m + n) per face) and the frequency fibres (r L).
+--config C2 runs the 3072-triangle cube (single and double layer built together), C5 the
+81920-triangle icosphere build + apply of 256 right-hand sides.
 """
 from __future__ import annotations
 
@@ -24,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 PHASES = ["face", "aca", "expand", "tail"]
 KID = {"slp": 0, "dlp": 1}
@@ -44,32 +53,47 @@ def measured_traffic(kernel_name):
             sha = hashlib.sha256(fh.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha256") != sha or not kernel_name.startswith(rec.get("kernel", "\0")):
+    if rec.get("source_sha256") != sha or kernel_name != rec.get("kernel"):
         return None
     return rec.get("traffic_bytes_per_launch")
 
 
-def dominant_kernels(kernels, all_stats):
+def large_kernel_name(threads, mixed, path):
+    """Instantiation of far_aca_large_kernel<threads, mixed, LDS history bytes, path> that the
+    library launches for the faces with a side above 128 (the name rocprofv3 lists)."""
+    mx = "true" if mixed else "false"
+    if path == 2:
+        return f"far_aca_large_kernel<512, {mx}, 106496, 2>"
+    hb = {1024: 90112, 512: 106496}.get(threads, 60800 if path == 1 else 32768)
+    return f"far_aca_large_kernel<{threads}, {mx}, {hb}, {path}>"
+
+
+def far_kernels(kernels, all_stats, mixed=False):
     """Per-kernel device time (mean over steps), launches and algorithmic flops of one step,
-    keyed by the kernel's name as the profiler lists it (FP64 build).  The face-ACA classes
-    0-2 share their stream with the Gram-row kernel, so only class 3 (one kernel per launch
-    window) is listed as a single kernel.  A joint build of both operators reports its shared
-    launches in the stats of each operator: they are counted once, as kernel id -1."""
+    keyed by the kernel's name as the profiler lists it.  The face-ACA classes 0-2 share their
+    stream with the Gram-row kernel and are not listed; class 3 is listed per kernel path.  A
+    joint build of both operators reports its shared launches in the stats of each operator:
+    they are counted once, as kernel id -1."""
     out = {}
     nsteps = len(all_stats)
+    mx = "true" if mixed else "false"
     for stp in all_stats:
         joint = stp[0]["joint_build"] > 1
         for k, st in zip(kernels[:1] if joint else kernels, stp):
             kid = -1 if joint else KID[k]
-            rows = [(f"far_face_kernel<{kid}, false, false>", st["ms_far_phase"][0],
+            rows = [(f"far_face_kernel<{kid}, false, {mx}>", st["ms_far_phase"][0],
                      st["launches_phase"][0], st["far_flops_phase"][0]),
-                    ("far_expand_kernel<false>", st["ms_far_phase"][2], st["launches_phase"][2],
+                    (f"far_expand_kernel<{mx}>", st["ms_far_phase"][2], st["launches_phase"][2],
                      st["far_flops_phase"][2]),
-                    (f"far_tail_kernel<{kid}, false, false>", st["ms_far_phase"][3],
-                     st["launches_phase"][3], st["far_flops_phase"][3]),
-                    ("far_aca_large_kernel<512, false, 106496, 1> (faces with a side above 128)",
-                     st["ms_far_by_kind"][3], st["launches_by_kind"][3], st["far_flops_by_kind"][3])]
+                    (f"far_tail_kernel<{kid}, false, {mx}>", st["ms_far_phase"][3],
+                     st["launches_phase"][3], st["far_flops_phase"][3])]
+            for path in range(3):
+                rows.append((large_kernel_name(st["threads_large_used"], mixed, path),
+                             st["ms_far_large_path"][path], st["launches_large_path"][path],
+                             st["far_flops_large_path"][path]))
             for name, ms, nl, fl in rows:
+                if nl == 0:
+                    continue
                 e = out.setdefault(name, {"ms": 0.0, "launches": 0, "flops": 0.0})
                 e["ms"] += ms / nsteps
                 e["launches"] += nl / nsteps
@@ -82,58 +106,276 @@ def dominant_kernels(kernels, all_stats):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="C2")
+    ap.add_argument("--config", default="C3")
     ap.add_argument("--nrhs", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--far-sample", type=int, default=96)
+    ap.add_argument("--large-sample", type=int, default=4)
+    ap.add_argument("--leaf-rows", type=int, default=12)
     # counter calibration: one y = 1.0 * x pass over this many bytes of FP32 before the
     # warm-up (a kernel of known traffic for the FETCH_SIZE / WRITE_SIZE scale)
     ap.add_argument("--copy-calibration", type=int, default=0)
     return ap.parse_args()
 
 
-def cpu_baseline(cfg, xyz, tri, s, budget_s):
-    """The oracle timed on a bounded sample of the same workload: seeded random far blocks
-    (dense assembly + serial 3D-ACA, as the oracle does it) and near blocks, until about
-    budget_s seconds of CPU work; reported in the same unit (entries per second)."""
+def cpu_baseline(cfg, xyz, tri, s, args):
+    """The oracle timed on a bounded, seeded sample of the same workload: far blocks (dense
+    assembly + serial 3D-ACA, as the oracle does it) and the near blocks of a few leaf rows
+    (dense assembly).  Returns the baseline record and the sample's dense oracle tensors,
+    against which both GPU legs state their errors.
+
+    Sample: --far-sample far blocks drawn uniformly among those with sides <= 256, plus
+    --large-sample among those with a side above 256 (seed 0), and every near block of
+    --leaf-rows leaf rows (seed 1)."""
     import numpy as np
     from oracle.aca3d import aca3d
     from oracle.hmatrix import Problem
 
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    op = Problem(xyz, tri, s, cfg["leaf"], cfg["eta"])
+    op = Problem(xyz, tri, s, cfg["leaf"], cfg["eta"],
+                 scheme=cfg.get("scheme", "collocation"))
+    far = np.array(op.far, dtype=np.int64)
+    near = np.array(op.near, dtype=np.int64)
     rng = np.random.default_rng(0)
-    far_order = rng.permutation(len(op.far))
-    near_order = rng.permutation(len(op.near))
-    # the workload's mix: near entries vs far blocks in proportion to their counts
-    entries = 0.0
+    side = np.maximum(far[:, 1], far[:, 3])
+    small = np.nonzero(side <= 256)[0]
+    large = np.nonzero(side > 256)[0]
+    fpick = sorted(rng.choice(small, min(args.far_sample, small.size), replace=False).tolist()
+                   + rng.choice(large, min(args.large_sample, large.size), replace=False).tolist())
+    rows = np.unique(near[:, 0])
+    rsel = np.random.default_rng(1).choice(rows, min(args.leaf_rows, rows.size), replace=False)
+    npick = np.nonzero(np.isin(near[:, 0], rsel))[0].tolist()
+    L = op.L
+    sample = {"far": {}, "near": {}}
+    ent_alg = ent_eval = 0.0
     t0 = time.perf_counter()
-    nf = nn = 0
-    fi = ni = 0
-    while time.perf_counter() - t0 < budget_s and (fi < len(far_order) or ni < len(near_order)):
-        for kernel in cfg["kernels"]:
-            if fi < len(far_order):
-                blk = op.far[far_order[fi]]
-                T = op.block_tensor(kernel, blk, True)
-                res = aca3d(T, cfg["eps"], cfg["eps_aca"])
-                m, n = blk[1], blk[3]
-                entries += sum(c.U.shape[1] * (m + n) for c in res.crosses) + res.rank * op.L
-                nf += 1
-            if ni < len(near_order):
-                blk = op.near[near_order[ni]]
-                op.block_tensor(kernel, blk, False)
-                entries += blk[1] * blk[3] * op.L
-                nn += 1
-        fi += 1
-        ni += 1
+    for kernel in cfg["kernels"]:
+        for b in fpick:
+            blk = tuple(int(v) for v in far[b])
+            T = op.block_tensor(kernel, blk, True)
+            res = aca3d(T, cfg["eps"], cfg["eps_aca"])
+            m, n = blk[1], blk[3]
+            ent_alg += sum(c.U.shape[1] * (m + n) for c in res.crosses) + res.rank * L
+            ent_eval += m * n * L
+            sample["far"][(kernel, blk)] = T
+        for b in npick:
+            blk = tuple(int(v) for v in near[b])
+            N = op.block_tensor(kernel, blk, False)
+            ent_alg += blk[1] * blk[3] * L
+            ent_eval += blk[1] * blk[3] * L
+            sample["near"][(kernel, blk)] = N
     dt = time.perf_counter() - t0
-    return {"value": entries / dt, "unit": "entries/s", "cores": threads, "kind": "oracle",
-            "sample": f"{fi} far + {ni} near blocks per kernel ({','.join(cfg['kernels'])}), "
-                      f"seeded random order, {dt:.1f} s, oracle dense block assembly "
-                      f"(C, OpenMP over pairs) + serial numpy 3D-ACA"}
+    desc = (f"{len(fpick)} far blocks ({len(fpick) - min(args.large_sample, large.size)} of "
+            f"the {small.size} with sides <= 256, {min(args.large_sample, large.size)} of the "
+            f"{large.size} above; seed 0) and the {len(npick)} near blocks of {len(rsel)} leaf "
+            f"rows (seed 1), per operator ({','.join(cfg['kernels'])})")
+    rec = {"value": ent_alg / dt, "unit": "entries/s", "cores": threads, "kind": "oracle",
+           "sample": f"{desc}; {dt:.1f} s of oracle dense block assembly (C, OpenMP over "
+                     f"pairs) + serial numpy 3D-ACA per far block",
+           "count": "algorithmic-equivalent: near m n L + far sum rho (m + n) + r L, the "
+                    "entries the GPU count charges for the same blocks",
+           "evaluated_entries_per_s": ent_eval / dt}
+    return rec, sample, desc
+
+
+def sample_errors(hs, kernels, prob, sample):
+    """Relative Frobenius errors of the operators hs against the oracle's dense tensors of the
+    sample: far blocks reconstructed from their exported factors, near blocks exported."""
+    import numpy as np
+    far, near = prob.blocks()
+    fidx = {tuple(int(v) for v in b): i for i, b in enumerate(far)}
+    nidx = {tuple(int(v) for v in b): i for i, b in enumerate(near)}
+    out = {}
+    for k, h in zip(kernels, hs):
+        fn = fd = nn_ = nd = 0.0
+        for (kern, blk), T in sample["far"].items():
+            if kern != k:
+                continue
+            e = h.export_block(fidx[blk])
+            C = np.zeros_like(T)
+            for c in e["crosses"]:
+                C += (c["U"] @ c["W"].T)[:, :, None] * c["f"][None, None, :]
+            fn += np.linalg.norm(C - T) ** 2
+            fd += np.linalg.norm(T) ** 2
+        for (kern, blk), N in sample["near"].items():
+            if kern != k:
+                continue
+            G = h.near_block(nidx[blk], blk[1], blk[3])
+            nn_ += np.linalg.norm(G - np.transpose(N, (0, 2, 1))) ** 2
+            nd += np.linalg.norm(N) ** 2
+        out[k] = {"far": float(np.sqrt(fn / fd)), "near": float(np.sqrt(nn_ / nd)),
+                  "all": float(np.sqrt((fn + nn_) / (fd + nd)))}
+    return out
+
+
+def build_all(prob, kernels):
+    """The operators `kernels` of prob: both collocation operators in one joint build."""
+    if sorted(kernels) == ["dlp", "slp"]:
+        hs, hd = prob.build_both()
+        return [hs, hd] if kernels[0] == "slp" else [hd, hs]
+    return [prob.build(k) for k in kernels]
+
+
+def run_leg(gaca, ctx, xyz, tri, s, cfg, X, stream, args, precision, sample):
+    """Warm-up, then args.steps timed steps (build of every operator + one apply each) with
+    the given precision; the last step's operators give the errors against the sample and
+    the apply results."""
+    import numpy as np
+    import torch
+    kernels = cfg["kernels"]
+    t_setup = time.perf_counter()
+    prob = gaca.Problem(ctx, xyz, tri, s, scheme=cfg.get("scheme", "collocation"),
+                        leaf_size=cfg["leaf"], eta=cfg["eta"], eps3d=cfg["eps"],
+                        eps_aca=cfg["eps_aca"], precision=precision)
+    t_setup = time.perf_counter() - t_setup
+    Xp = X if precision == "fp64" else X.to(torch.complex64)
+
+    def step(keep=False):
+        hs = build_all(prob, kernels)
+        ys = [h.apply(Xp, stream=stream) for h in hs]
+        st = [h.stats() for h in hs]
+        if keep:
+            return st, hs, ys
+        del hs
+        return st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    all_stats = [step() for _ in range(args.steps - 1)]
+    last, hs, ys = step(keep=True)
+    all_stats.append(last)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    entries = sum(st["entries_near"] + st["entries_face"] + st["entries_fibre"] for st in last)
+    kern = far_kernels(kernels, all_stats, mixed=precision != "fp64")
+    dom_name = max(kern, key=lambda k: kern[k]["ms"])
+    dom = kern[dom_name]
+    joint = last[0]["joint_build"]
+    leg = {
+        "value": entries * args.steps / elapsed,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "build_ms": {k: st["ms_total"] for k, st in zip(kernels, last)},
+        "near_kernel_ms": float(np.mean([sum(st["ms_near_kernel"] for st in stp) for stp in all_stats])),
+        "far_kernel_ms": float(np.mean([sum(st["ms_far_kernel"] for st in stp) / joint for stp in all_stats])),
+        "entries_per_step": entries,
+        "entries_near_evaluated": sum(st["entries_near"] for st in last),
+        "entries_near_mirrored": sum(st["entries_near_mirrored"] for st in last),
+        "ranks": {k: [st["rank_min"], st["rank_max"], round(st["rank_mean"], 2)] for k, st in zip(kernels, last)},
+        "face_rank_max": {k: st["face_rank_max"] for k, st in zip(kernels, last)},
+        "compression": {k: st["compression"] for k, st in zip(kernels, last)},
+        "far_iters": {k: st["far_iters"] for k, st in zip(kernels, last)},
+        "far_launches": {k: st["n_far_launches"] for k, st in zip(kernels, last)},
+        "setup_s": t_setup,
+        "far_phase_ms": {name: float(np.mean([sum(st["ms_far_phase"][i] for st in stp) / joint
+                                              for stp in all_stats])) for i, name in enumerate(PHASES)},
+        "far_kernels": {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
+                            "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3)}
+                        for k, v in kern.items()},
+        "dominant": (dom_name, dom),
+    }
+    if sample is not None:
+        leg["errors_vs_oracle"] = sample_errors(hs, kernels, prob, sample)
+    ys = [y.to(torch.complex128) for y in ys]
+    torch.cuda.synchronize()
+    del hs
+    prob.close()
+    return leg, ys
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the far blocks would shard by LPT across GPUs, see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if args.config == "C5":
+        apply_bench(args)
+        return
+
+    import paper_2312_11219_amd as gaca
+    from inputs import circle_frequencies, get_config, mesh_for_config, random_rhs
+
+    cfg = get_config(args.config)
+    xyz, tri = mesh_for_config(args.config)
+    s = circle_frequencies(cfg["L"], cfg["c0"], cfg["rho"])
+    M, L = tri.shape[0], cfg["L"]
+    kernels = cfg["kernels"]
+    sample = desc = cpu = None
+    if not args.no_cpu_baseline:
+        print("cpu baseline: oracle on the seeded sample", file=sys.stderr, flush=True)
+        cpu, sample, desc = cpu_baseline(cfg, xyz, tri, s, args)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    ctx = gaca.Context(0, stream=stream)
+    X = torch.from_numpy(random_rhs(L, M, args.nrhs, seed=0)).to(dev)
+    if args.copy_calibration > 0:
+        n = args.copy_calibration // 4
+        xc = torch.ones(n, dtype=torch.float32, device=dev)
+        yc = torch.empty_like(xc)
+        torch.cuda.synchronize()
+        torch.mul(xc, 1.0, out=yc)
+        torch.cuda.synchronize()
+        del xc, yc
+    print("fp64 leg", file=sys.stderr, flush=True)
+    leg64, y64 = run_leg(gaca, ctx, xyz, tri, s, cfg, X, stream, args, "fp64", sample)
+    dom_name, dom = leg64.pop("dominant")
+    achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
+    ops = "+".join(kernels)
+    out = {
+        "metric": "3-way ACA build s + kernel entries/s, FP64 vs mixed-prec at stated rel err",
+        "value": leg64["value"],
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": leg64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg['name']}: {cfg['mesh'][0]} mesh ({M} triangles), "
+                               f"{cfg.get('scheme', 'collocation')} P0 {ops}, L={L} circle "
+                               f"frequencies c0={cfg['c0']} rho={cfg['rho']}, leaf {cfg['leaf']}, "
+                               f"eta {cfg['eta']}, eps {cfg['eps']}, eps_aca {cfg['eps_aca']}, "
+                               f"FP64 build + apply with {args.nrhs} rhs per step",
+                   "global_batch": 1, "parallelism": "single-gpu"},
+        "build_s": {k: v / 1e3 for k, v in leg64["build_ms"].items()},
+        "near_mirrored": bool(leg64["entries_near_mirrored"] > 0),
+        "roofline": {"bound": "alu", "kernel": dom_name,
+                     "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(dom_name),
+                     "launches_per_step": dom["launches"],
+                     "ms_per_launch": dom["ms"] / max(1, dom["launches"])},
+        "fp64": leg64,
+    }
+    if not args.no_mixed:
+        print("mixed leg", file=sys.stderr, flush=True)
+        legmx, ymx = run_leg(gaca, ctx, xyz, tri, s, cfg, X, stream, args, "mixed", sample)
+        dname, d = legmx.pop("dominant")
+        legmx["dominant_kernel"] = {"kernel": dname, "ms_per_launch": d["ms"] / max(1, d["launches"]),
+                                    "tflops": d["flops"] / max(d["ms"], 1e-9) / 1e9}
+        legmx["apply_rel_diff_vs_fp64_apply"] = {
+            k: float((a - b).norm().item() / b.norm().item()) for k, a, b in zip(kernels, ymx, y64)}
+        legmx["speedup_vs_fp64"] = leg64["ms_per_step"] / legmx["ms_per_step"]
+        out["mixed"] = legmx
+    if sample is not None:
+        err = {"sample": desc, "fp64": leg64["errors_vs_oracle"]}
+        if "mixed" in out:
+            err["mixed"] = out["mixed"]["errors_vs_oracle"]
+            err["abs_diff_mixed_minus_fp64"] = {
+                k: abs(err["mixed"][k]["all"] - err["fp64"][k]["all"]) for k in kernels}
+        out["errors_vs_fp64_oracle"] = err
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
 
 
 def apply_bench(args):
@@ -220,180 +462,6 @@ def apply_bench(args):
                         "frac": dom_tf / 157.3, "traffic": None}}
     print(json.dumps(out), flush=True)
 
-
-def build_all(prob, kernels):
-    """The operators `kernels` of prob: both collocation operators in one joint build."""
-    if sorted(kernels) == ["dlp", "slp"]:
-        hs, hd = prob.build_both()
-        return [hs, hd] if kernels[0] == "slp" else [hd, hs]
-    return [prob.build(k) for k in kernels]
-
-
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the far blocks would shard by LPT across GPUs, see the design notes)",
-              file=sys.stderr)
-        sys.exit(2)
-    import numpy as np
-    import torch
-
-    if args.config == "C5":
-        apply_bench(args)
-        return
-
-    import paper_2312_11219_amd as gaca
-    from inputs import circle_frequencies, get_config, mesh_for_config, random_rhs
-
-    cfg = get_config(args.config)
-    xyz, tri = mesh_for_config(args.config)
-    s = circle_frequencies(cfg["L"], cfg["c0"], cfg["rho"])
-    M, L = tri.shape[0], cfg["L"]
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream(dev)
-    ctx = gaca.Context(0, stream=stream)
-    kernels = cfg["kernels"]
-    # one problem; with both operators they are built together (gaca_build_both: the blocks of
-    # both share every far-field launch)
-    t_setup = time.perf_counter()
-    prob = gaca.Problem(ctx, xyz, tri, s, leaf_size=cfg["leaf"], eta=cfg["eta"],
-                        eps3d=cfg["eps"], eps_aca=cfg["eps_aca"])
-    t_setup = time.perf_counter() - t_setup
-    X = torch.from_numpy(random_rhs(L, M, args.nrhs, seed=0)).to(dev)
-
-    def step():
-        hs = build_all(prob, kernels)
-        for h in hs:
-            h.apply(X, stream=stream)
-        out = [h.stats() for h in hs]
-        del hs
-        return out
-
-    if args.copy_calibration > 0:
-        n = args.copy_calibration // 4
-        xc = torch.ones(n, dtype=torch.float32, device=dev)
-        yc = torch.empty_like(xc)
-        torch.cuda.synchronize()
-        torch.mul(xc, 1.0, out=yc)
-        torch.cuda.synchronize()
-        del xc, yc
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    all_stats = []
-    for _ in range(args.steps):
-        all_stats.append(step())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
-    last = all_stats[-1]
-    entries_step = sum(st["entries_near"] + st["entries_face"] + st["entries_fibre"] for st in last)
-    value = entries_step * args.steps / elapsed
-    # dominant kernel: the far-field kernel with the largest device time over the step; each
-    # launch is timed with HIP events on the stream it runs on
-    kern = dominant_kernels(kernels, all_stats)
-    dom_name = max(kern, key=lambda k: kern[k]["ms"])
-    dom = kern[dom_name]
-    far_ms = np.mean([sum(st["ms_far_kernel"] for st in stp) / stp[0]["joint_build"]
-                      for stp in all_stats])
-    near_ms = np.mean([sum(st["ms_near_kernel"] for st in stp) for stp in all_stats])
-    achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
-    phase_ms = np.mean([[sum(st["ms_far_phase"][k] for st in stp) / stp[0]["joint_build"]
-                         for k in range(4)] for stp in all_stats], axis=0)
-    out = {
-        "metric": "3-way ACA build s + kernel entries/s, FP64 vs mixed-prec at stated rel err",
-        "value": value,
-        "unit": "entries/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"cube surface 16x16 squares per face ({M} triangles), "
-                               f"collocation P0, single+double layer, L={L} circle frequencies "
-                               f"c0={cfg['c0']} rho={cfg['rho']}, leaf {cfg['leaf']}, eta "
-                               f"{cfg['eta']}, eps {cfg['eps']}, eps_aca {cfg['eps_aca']}, "
-                               f"build + apply with {args.nrhs} rhs",
-                   "global_batch": 1, "parallelism": "single-gpu"},
-        "build_ms": {k: st["ms_total"] for k, st in zip(kernels, last)},
-        "near_kernel_ms": near_ms,
-        "far_kernel_ms": far_ms,
-        "entries_per_step": entries_step,
-        "ranks": {k: [st["rank_min"], st["rank_max"], round(st["rank_mean"], 2)]
-                  for k, st in zip(kernels, last)},
-        "compression": {k: st["compression"] for k, st in zip(kernels, last)},
-        "setup_s": t_setup,
-        "far_phase_ms": {name: float(phase_ms[k]) for k, name in enumerate(PHASES)},
-        "far_kernels": {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
-                            "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3)}
-                        for k, v in kern.items()},
-        "far_iters": {k: st["far_iters"] for k, st in zip(kernels, last)},
-        "aca_block_max_ms": {k: st["ms_far_aca_block_max"] for k, st in zip(kernels, last)},
-        "roofline": {"bound": "alu", "kernel": dom_name,
-                     "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(dom_name),
-                     "launches_per_step": dom["launches"],
-                     "ms_per_launch": dom["ms"] / max(1, dom["launches"])},
-    }
-    if not args.no_mixed:
-        # the FP64 apply of the same X as the mixed leg's reference, then the FP64 problem is
-        # released (the mixed problem takes over its far-field streams)
-        h64s = build_all(prob, kernels)
-        y64s = [h.apply(X, stream=stream) for h in h64s]
-        torch.cuda.synchronize()
-        del h64s
-        prob.close()
-        out["mixed"] = mixed_leg(gaca, ctx, xyz, tri, s, cfg, X, kernels, stream, y64s, args)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, xyz, tri, s, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
-
-
-def mixed_leg(gaca, ctx, xyz, tri, s, cfg, X, kernels, stream, y64s, args):
-    """The same step with the mixed-precision build (FP32 far-field faces and factors with
-    the per-(block, frequency) scale, FP64 fibres/norms; near field stored FP32) and the
-    relative difference of its apply from the FP64 build's apply of the same X (y64s)."""
-    import numpy as np
-    import torch
-    pm = gaca.Problem(ctx, xyz, tri, s, leaf_size=cfg["leaf"], eta=cfg["eta"],
-                      eps3d=cfg["eps"], eps_aca=cfg["eps_aca"], precision="mixed")
-    X32 = X.to(torch.complex64)
-
-    def step():
-        hs = build_all(pm, kernels)
-        out = [(h.stats(), h.apply(X32, stream=stream)) for h in hs]
-        del hs
-        return out
-
-    step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    runs = [step() for _ in range(max(1, args.steps))]
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    last = runs[-1]
-    entries = sum(st["entries_near"] + st["entries_face"] + st["entries_fibre"] for st, _ in last)
-    errs = {}
-    for k, (st, y), y64 in zip(kernels, last, y64s):
-        d = (y.to(torch.complex128) - y64).norm().item() / y64.norm().item()
-        errs[k] = d
-    return {"value": entries * len(runs) / el, "unit": "entries/s",
-            "ms_per_step": el / len(runs) * 1e3,
-            "build_ms": {k: st["ms_total"] for k, (st, _) in zip(kernels, last)},
-            "far_kernel_ms": float(np.mean([sum(st["ms_far_kernel"] for st, _ in r) / r[0][0]["joint_build"]
-                                            for r in runs])),
-            "far_phase_ms": [float(np.mean([sum(st["ms_far_phase"][k] for st, _ in r) / r[0][0]["joint_build"]
-                                            for r in runs])) for k in range(4)],
-            "apply_rel_diff_vs_fp64": errs,
-            "ranks": {k: [st["rank_min"], st["rank_max"], round(st["rank_mean"], 2)]
-                      for k, (st, _) in zip(kernels, last)},
-            "far_iters": {k: st["far_iters"] for k, (st, _) in zip(kernels, last)}}
 
 
 if __name__ == "__main__":

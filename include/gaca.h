@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define GACA_ABI_VERSION 1
+#define GACA_ABI_VERSION 2
 
 typedef enum {
     GACA_OK = 0,
@@ -64,8 +64,16 @@ typedef struct {
     double eps3d;             /* 3-D ACA tolerance eps of Algorithm 1 (default 1e-6) */
     double eps_aca;           /* face ACA tolerance (default eps3d / 100) */
     gaca_precision precision; /* default GACA_FP64 */
+    /* Quadrature orders (Sec. 3: Gauss rules chosen by a distance heuristic, Duffy for the
+     * collocation singularity, regularising maps for the Galerkin singularities).  With
+     * q = |x_i - x_j| / h the far blocks and near pairs with q >= 4 take the 6-point rule. */
+    int32_t quad_mid;         /* collapsed Gauss points per direction, 2 <= q < 4 (default 4) */
+    int32_t quad_near;        /* collocation: collapsed points per direction, q < 2 (default 8) */
     int32_t n_duffy;          /* Duffy order of the collocation self term (default 16) */
-    int32_t n_galerkin;       /* Galerkin touching-pair order per direction (default 5) */
+    int32_t n_galerkin;       /* Galerkin disjoint pairs with q < 2: outer and inner Duffy order
+                                 per direction (default 5) */
+    int32_t n_touch;          /* Galerkin pairs sharing an edge or a vertex: Gauss points per
+                                 direction of the regularising maps (default 12) */
     double tie;               /* relative tie window of every argmax (default 1e-9, FP64) */
     double delta_zero;        /* zero-face threshold factor (default 1e-13) */
     int32_t max_rank3d;       /* cap on crosses per block (default min(L, 64)) */
@@ -75,11 +83,17 @@ typedef struct {
     int32_t threads_small;    /* face-ACA workgroup size for faces with m n <= 1024: 128
                                  (default) or 64 (one wave per face) */
     int32_t threads_large;    /* face-ACA workgroup size for the large faces (256, 512 or
-                                 1024; default 0: 512) */
+                                 1024; default 0: chosen by the autotuner if autotune_cache is
+                                 set, else 512) */
     int32_t verbose;          /* 1: one progress line per far-field batch on stderr */
     int32_t zero_rows_batch;  /* face ACA of the large faces, after a zero row: 1 (default)
                                  tries several unused rows per pass over the history, 0 one
                                  row per pass; both end at the same row */
+    const char *autotune_cache; /* NULL (default): no autotuning.  Otherwise a file path: the
+                                 face-ACA workgroup sizes chosen for a workload (measured on
+                                 the first build of a problem and timed per candidate) are
+                                 read from and appended to this text file; the string is
+                                 copied at problem creation */
 } gaca_options;
 
 typedef struct gaca_context gaca_context;
@@ -97,8 +111,13 @@ typedef struct {
     uint64_t bytes_far;           /* stored far-field factors (U, W, fibres) */
     uint64_t bytes_near;          /* stored near field */
     double dense_bytes;           /* M * M * L * (16 FP64 / 8 MIXED) */
-    double compression;           /* (bytes_far + bytes_near) / dense_bytes */
-    double entries_near;          /* near-field tensor entries computed (m n L per block) */
+    double compression;           /* (bytes_far + bytes_near) / dense_bytes: stored bytes over
+                                     the bytes of the dense tensor, the compression measure of
+                                     Sec. 5.1 (cube example, compression figure) */
+    double entries_near;          /* near-field tensor entries evaluated (m n L_eval per block:
+                                     L_eval = ceil(L/2) when the frequencies are conjugate
+                                     pairs, else L) */
+    double entries_near_mirrored; /* near-field entries written as conjugates, not evaluated */
     double entries_face;          /* entries read by the face ACAs (algorithmic count) */
     double entries_fibre;         /* frequency-fibre entries (r L per block) */
     double entries_face_kernel;   /* entries the face kernels evaluated (dense faces) */
@@ -126,6 +145,13 @@ typedef struct {
     double ms_far_by_kind[4];
     int32_t launches_by_kind[4];
     double far_flops_by_kind[4];  /* algorithmic flops of the class's face-ACA launches */
+    /* class 3 by kernel path (far_aca_large_kernel instantiations): 0 general (sides above
+     * the workgroup size, several entries per thread), 1 one row and one column entry per
+     * thread (sides <= workgroup size), 2 several entries per thread (sides <= 5 x 512) */
+    double ms_far_large_path[3];
+    int32_t launches_large_path[3];
+    double far_flops_large_path[3];
+    int32_t threads_large_used;   /* workgroup size of the class-3 launches */
     double ms_far_aca_block_max;  /* longest total face-ACA time of one block (device clock) */
     double ms_host_setup;         /* host time of the build before the far-field launches */
     double ms_host_finish;        /* host time of the build after the far field completed */
@@ -153,6 +179,10 @@ void gaca_options_default(gaca_options *opt);
  * the next problem. */
 gaca_status gaca_context_create(int device, void *hip_stream, gaca_context **out);
 gaca_status gaca_context_destroy(gaca_context *ctx);
+/* Device memory the library holds for this context (every problem and operator made on it,
+ * and what they keep for reuse), in bytes.  Returns to 0 once every problem and operator of
+ * the context is destroyed. */
+gaca_status gaca_context_memory(const gaca_context *ctx, uint64_t *in_use);
 
 /* Problem: mesh + frequencies + scheme (Sec. 3).  xyz: nv x 3 doubles; tri: M x 3 int32
  * vertex ids, counter-clockwise seen from outside; s_re, s_im: L frequencies.
@@ -201,7 +231,9 @@ gaca_status gaca_build_both(gaca_problem *p, gaca_hmatrix **slp_out, gaca_hmatri
  * and are freed with the problem. */
 gaca_status gaca_hmatrix_destroy(gaca_hmatrix *h);
 gaca_status gaca_hmatrix_stats(const gaca_hmatrix *h, gaca_stats *st);
-/* Frequency-usage histogram: hist[k] = number of far blocks whose crosses use s_k. */
+/* Frequency-usage histogram: hist[k] = number of far blocks whose crosses use s_k (the
+ * adaptively selected frequencies per block of Sec. 5.1, used-frequencies figure of the cube
+ * example; with k_1 = 0 every block with a cross uses s_0).  hist: L entries (host). */
 gaca_status gaca_hmatrix_freq_hist(const gaca_hmatrix *h, int64_t *hist);
 
 /* Export of far block idx (tree-order rows/cols, see gaca_problem_blocks):
@@ -233,6 +265,17 @@ gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, cons
 gaca_status gaca_eval_entries(gaca_problem *p, gaca_kernel kernel, int64_t n,
                               const int32_t *i, const int32_t *j, const int32_t *k,
                               const int32_t *far, double *out);
+
+/* Test hook: entries of far block far_block (index into the far list of
+ * gaca_problem_blocks) at tree-local rows il[p], columns jl[p] and frequency indices k[p], as
+ * the mixed-precision face kernels evaluate them: FP32 arithmetic on the scaled kernel
+ * exp(-s (r - d0)) / (4 pi r) (its normal derivative for the double layer; the Galerkin 6 x 6
+ * rule for a Galerkin problem), where c_k = exp(-s_k d0) with d0 the distance of the block's
+ * cluster box centres, then multiplied by c_k in FP64 (Sec. 3 kernels; the scaling is this
+ * library's mixed-precision reading).  out: 2 n doubles (host).  n may be 0. */
+gaca_status gaca_eval_far_entries_mixed(gaca_problem *p, gaca_kernel kernel, int64_t far_block,
+                                        int64_t n, const int32_t *il, const int32_t *jl,
+                                        const int32_t *k, double *out);
 
 /* Test hook: 3D-ACA (Algorithm 1) of one dense tensor given on the device,
  * T[i][j][k] C128 with m x n x L entries, using the options' tolerances and precision

@@ -13,6 +13,7 @@ _lib = None
 P = ctypes.c_void_p
 I32, I64, F64, U64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
 
+ABI_VERSION = 2   # GACA_ABI_VERSION of include/gaca.h that these structures follow
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "STATE", -5: "NOT_CONVERGED",
           -6: "UNSUPPORTED"}
 SCHEMES = {"collocation": 0, "galerkin": 1}
@@ -29,10 +30,12 @@ class GacaError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("leaf_size", I32), ("eta", F64), ("eps3d", F64), ("eps_aca", F64),
-                ("precision", I32), ("n_duffy", I32), ("n_galerkin", I32), ("tie", F64),
+                ("precision", I32), ("quad_mid", I32), ("quad_near", I32), ("n_duffy", I32),
+                ("n_galerkin", I32), ("n_touch", I32), ("tie", F64),
                 ("delta_zero", F64), ("max_rank3d", I32), ("max_face_rank", I32),
                 ("max_device_bytes", U64), ("batch_bytes", U64), ("threads_small", I32),
-                ("threads_large", I32), ("verbose", I32), ("zero_rows_batch", I32)]
+                ("threads_large", I32), ("verbose", I32), ("zero_rows_batch", I32),
+                ("autotune_cache", ctypes.c_char_p)]
 
 
 class Stats(ctypes.Structure):
@@ -40,7 +43,7 @@ class Stats(ctypes.Structure):
                 ("rank_mean", F64), ("face_rank_max", I32), ("face_rank_mean", F64),
                 ("n_capped", I64), ("n_zero_blocks", I64), ("bytes_far", U64),
                 ("bytes_near", U64), ("dense_bytes", F64), ("compression", F64),
-                ("entries_near", F64), ("entries_face", F64), ("entries_fibre", F64),
+                ("entries_near", F64), ("entries_near_mirrored", F64), ("entries_face", F64), ("entries_fibre", F64),
                 ("entries_face_kernel", F64), ("ms_near", F64), ("ms_far", F64),
                 ("ms_total", F64), ("ms_near_kernel", F64), ("ms_far_kernel", F64),
                 ("n_far_launches", I32), ("far_iters", I32), ("far_flops", F64),
@@ -48,6 +51,8 @@ class Stats(ctypes.Structure):
                 ("ms_far_phase", F64 * 4), ("launches_phase", I32 * 4),
                 ("far_flops_phase", F64 * 4), ("ms_far_by_kind", F64 * 4),
                 ("launches_by_kind", I32 * 4), ("far_flops_by_kind", F64 * 4),
+                ("ms_far_large_path", F64 * 3), ("launches_large_path", I32 * 3),
+                ("far_flops_large_path", F64 * 3), ("threads_large_used", I32),
                 ("ms_far_aca_block_max", F64), ("ms_host_setup", F64), ("ms_host_finish", F64),
                 ("ms_apply", F64), ("apply_flops", F64), ("apply_operator_bytes", F64),
                 ("ms_apply_part", F64 * 3), ("apply_flops_part", F64 * 3), ("arena_in_place", I32),
@@ -77,6 +82,7 @@ def load_library():
         "gaca_options_default": (None, [P]),
         "gaca_context_create": (I32, [ctypes.c_int, P, P]),
         "gaca_context_destroy": (I32, [P]),
+        "gaca_context_memory": (I32, [P, P]),
         "gaca_problem_create": (I32, [P, P, I64, P, I64, P, P, I32, ctypes.c_int, P, P]),
         "gaca_problem_destroy": (I32, [P]),
         "gaca_problem_perm": (I32, [P, P]),
@@ -93,6 +99,7 @@ def load_library():
         "gaca_hmatrix_near_export": (I32, [P, I64, P]),
         "gaca_apply": (I32, [P, ctypes.c_int, I32, P, P, ctypes.c_int, P]),
         "gaca_eval_entries": (I32, [P, ctypes.c_int, I64, P, P, P, P, P]),
+        "gaca_eval_far_entries_mixed": (I32, [P, ctypes.c_int, I64, I64, P, P, P, P]),
         "gaca_compress_tensor": (I32, [P, P, I64, I64, I32, P, P]),
         "gaca_quadrature_rule": (I32, [ctypes.c_int, ctypes.c_int, P, P]),
     }
@@ -100,6 +107,9 @@ def load_library():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    if lib.gaca_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{_LIB_PATH} has ABI version {lib.gaca_abi_version()}, the binding "
+                           f"expects {ABI_VERSION}: rebuild the library")
     _lib = lib
     return lib
 
@@ -121,6 +131,8 @@ def options_default(**overrides) -> Options:
     for k, v in overrides.items():
         if k == "precision" and isinstance(v, str):
             v = PRECISIONS[v]
+        if k == "autotune_cache" and isinstance(v, str):
+            v = v.encode()
         if not hasattr(o, k):
             raise KeyError(k)
         setattr(o, k, v)
@@ -175,6 +187,11 @@ class Context:
             sp = P(stream if isinstance(stream, int) else stream.cuda_stream)
         _check(self._lib.gaca_context_create(device, sp, ctypes.byref(h)))
         self.handle = h
+
+    def memory_in_use(self) -> int:
+        v = U64(0)
+        _check(self._lib.gaca_context_memory(self.handle, ctypes.byref(v)))
+        return v.value
 
     def close(self):
         if self.handle:
@@ -245,6 +262,17 @@ class Problem:
         out = np.zeros(2 * max(n, 1), dtype=np.float64)
         _check(self._lib.gaca_eval_entries(self.handle, KERNELS[kernel], n, _ptr(i), _ptr(j),
                                            _ptr(k), _ptr(far), _ptr(out)))
+        return out[0:2 * n:2] + 1j * out[1:2 * n:2]
+
+    def eval_far_entries_mixed(self, kernel, block, il, jl, k):
+        """Mixed-precision face entries of far block `block` (tree-local il, jl) times c_k."""
+        il = np.ascontiguousarray(il, dtype=np.int32)
+        jl = np.ascontiguousarray(jl, dtype=np.int32)
+        k = np.ascontiguousarray(k, dtype=np.int32)
+        n = il.shape[0]
+        out = np.zeros(2 * max(n, 1), dtype=np.float64)
+        _check(self._lib.gaca_eval_far_entries_mixed(self.handle, KERNELS[kernel], block, n,
+                                                     _ptr(il), _ptr(jl), _ptr(k), _ptr(out)))
         return out[0:2 * n:2] + 1j * out[1:2 * n:2]
 
     def close(self):

@@ -1962,4 +1962,30 @@ void launch_far_gather(const FarBatchDev &bd, const FarGather *gt, int n, double
     far_gather_kernel<<<n, 256, 0, st>>>(bd, gt, fib_arena[0], fib_arena[1], fib_off);
 }
 
+
+// ---------------------------------------------------------------------------------------
+// Test hook: mixed-precision face entries of one block, multiplied back by c_k in FP64.
+template <int KERNEL>
+__global__ void eval_far_mixed_kernel(GeoDev g, FreqDev f, FarBlockDev B, int64_t n,
+                                      const int32_t *il, const int32_t *jl, const int32_t *kk,
+                                      double2 *out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const float2 e = face_entry<KERNEL, false, float2>(g, f, nullptr, B, il[t], jl[t], kk[t]);
+    const double2 ic = inv_scale(f, B, kk[t]);   // 1 / c_k
+    const double den = ic.x * ic.x + ic.y * ic.y;
+    const double er = e.x, ei = e.y;
+    out[t] = make_double2((er * ic.x + ei * ic.y) / den, (ei * ic.x - er * ic.y) / den);
+}
+
+void launch_eval_far_mixed(int kernel, const GeoDev &g, const FreqDev &f, const FarBlockDev &B,
+                           int64_t n, const int32_t *il, const int32_t *jl, const int32_t *k,
+                           double2 *out, hipStream_t st) {
+    if (n <= 0) return;
+    const unsigned nb = (unsigned)((n + 127) / 128);
+    if (kernel == 0) eval_far_mixed_kernel<0><<<nb, 128, 0, st>>>(g, f, B, n, il, jl, k, out);
+    else if (kernel == 1) eval_far_mixed_kernel<1><<<nb, 128, 0, st>>>(g, f, B, n, il, jl, k, out);
+    else eval_far_mixed_kernel<2><<<nb, 128, 0, st>>>(g, f, B, n, il, jl, k, out);
+}
+
 }  // namespace gaca

@@ -2,10 +2,21 @@
 // (Sec. 3, eq. bie_semi_indirect).  Quadrature per pair class:
 //   far blocks, disjoint pairs with q >= 4:  6-point x 6-point rule
 //   disjoint pairs with 2 <= q < 4:          collapsed 4x4 x collapsed 4x4
-//   disjoint q < 2, common edge, common vertex: outer collapsed n_G x n_G rule on tau_i
-//       (collapsed at the first vertex of tau_i shared with tau_j, else at vertex a), inner
+//   disjoint q < 2: outer collapsed n_G x n_G rule on tau_i (collapsed at vertex a), inner
 //       integral split at the point of tau_j closest to the outer point into three Duffy
 //       sub-triangles of n_G x n_G points
+//   common edge, common vertex (Erichsen-Sauter / Sauter-Schwab regularising maps): both
+//       triangles are parametrised over {0 <= t2 <= t1 <= 1} by P0 + t1 (P1 - P0) +
+//       t2 (P2 - P1) with the shared vertex at P0 (shared edge P0 P1); the product of the two
+//       parameter triangles is cut into 2 (vertex) or 5 (edge) pieces, each the image of
+//       [0,1]^4 under a map (xi, eta) on which x - y = xi d(eta) (vertex) or
+//       xi eta1 d(eta2, eta3) (edge), |d| bounded below.  The integrals over xi (vertex) and
+//       over xi and eta1 (edge) are exact:
+//         phi2(t) = int_0^1 xi^2 e^{-t xi} d xi = (2 - e^{-t} (t^2 + 2t + 2)) / t^3,
+//         phie(t) = int_0^1 eta phi2(t eta) d eta = (t - 2 + e^{-t} (t + 2)) / t^3
+//       (power series for |t| <= 1), the rest by n_S Gauss points per direction.  Vertex
+//       order: P0, P1 the shared vertices in the order of tau_i's list (edge); each list
+//       rotated to start at the shared vertex (vertex)
 //   coincident: for a flat triangle the kernel depends on z = x - y only and the overlap
 //       |T cap (T + z)| = A (1 - rho / R(theta))^2, so
 //       V = A / (4 pi) int_0^{2 pi} R(theta) psi(s R(theta)) dtheta,
@@ -260,6 +271,159 @@ __device__ void gal_coincident(const double *a, const double *b, const double *c
     }
 }
 
+
+// Power-series coefficients of phi2 (1 / (k! (k + 3))) and phie (1 / (k! (k + 2) (k + 3))).
+struct SsSeries {
+    double c2[20], ce[20];
+};
+constexpr SsSeries make_ss_series() {
+    SsSeries t{};
+    double fact = 1.0;
+    for (int k = 0; k < 20; ++k) {
+        if (k > 0) fact *= k;
+        t.c2[k] = 1.0 / (fact * (k + 3));
+        t.ce[k] = 1.0 / (fact * (k + 2) * (k + 3));
+    }
+    return t;
+}
+
+// EDGE = false: phi2(t); true: phie(t).  t = tr + i ti.
+template <bool EDGE>
+__device__ __forceinline__ double2 ss_phi(double tr, double ti) {
+    constexpr SsSeries S = make_ss_series();
+    if (tr * tr + ti * ti <= 1.0) {
+        // sum_k c_k (-t)^k by Horner from k = 19
+        double cr = EDGE ? S.ce[19] : S.c2[19], ci = 0.0;
+#pragma unroll
+        for (int k = 18; k >= 0; --k) {
+            const double nr = -(cr * tr - ci * ti), ni = -(cr * ti + ci * tr);
+            cr = nr + (EDGE ? S.ce[k] : S.c2[k]);
+            ci = ni;
+        }
+        return make_double2(cr, ci);
+    }
+    const double m = exp(-tr);
+    double sn, cs;
+    sincos(ti, &sn, &cs);
+    const double er = m * cs, ei = -m * sn;   // e^{-t}
+    double nr, ni;                            // numerator
+    if (EDGE) {
+        // t - 2 + e^{-t} (t + 2)
+        const double ar = tr + 2.0;
+        nr = tr - 2.0 + (er * ar - ei * ti);
+        ni = ti + (er * ti + ei * ar);
+    } else {
+        // 2 - e^{-t} (t^2 + 2 t + 2)
+        const double pr = tr * tr - ti * ti + 2.0 * tr + 2.0, pi = 2.0 * tr * ti + 2.0 * ti;
+        nr = 2.0 - (er * pr - ei * pi);
+        ni = -(er * pi + ei * pr);
+    }
+    // / t^3
+    const double t2r = tr * tr - ti * ti, t2i = 2.0 * tr * ti;
+    const double t3r = t2r * tr - t2i * ti, t3i = t2r * ti + t2i * tr;
+    const double den = t3r * t3r + t3i * t3i;
+    return make_double2((nr * t3r + ni * t3i) / den, (ni * t3r - nr * t3i) / den);
+}
+
+// w * phi(s_l rho) / (4 pi rho) added for the thread's frequencies
+template <bool EDGE, int NF>
+__device__ __forceinline__ void ss_acc(const double *d, double w, const FreqDev &f, int l0, int nl,
+                                       double *ar, double *ai) {
+    const double rho = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double c = w / (kFourPi * rho);
+#pragma unroll
+    for (int t = 0; t < NF; ++t)
+        if (t < nl) {
+            const double2 ph = ss_phi<EDGE>(f.re[l0 + t] * rho, f.im[l0 + t] * rho);
+            ar[t] += c * ph.x;
+            ai[t] += c * ph.y;
+        }
+}
+
+// Common vertex V: tau_i = (V, a1, a2), tau_j = (V, b1, b2).
+template <int NF>
+__device__ void gal_ss_vertex(const double *V, const double *a1, const double *a2,
+                              const double *b1, const double *b2, double area_i, double area_j,
+                              int n, const double *g, const FreqDev &f, int l0, int nl,
+                              double *ar, double *ai) {
+    double X1[3], X2[3], Y1[3], Y2[3];
+    for (int k = 0; k < 3; ++k) {
+        X1[k] = a1[k] - V[k];
+        X2[k] = a2[k] - a1[k];
+        Y1[k] = b1[k] - V[k];
+        Y2[k] = b2[k] - b1[k];
+    }
+#pragma unroll
+    for (int t = 0; t < NF; ++t) {
+        ar[t] = 0.0;
+        ai[t] = 0.0;
+    }
+    for (int p1 = 0; p1 < n; ++p1) {
+        const double e1 = g[2 * p1], w1 = g[2 * p1 + 1];
+        for (int p2 = 0; p2 < n; ++p2) {
+            const double e2 = g[2 * p2], w12 = w1 * g[2 * p2 + 1];
+            for (int p3 = 0; p3 < n; ++p3) {
+                const double e3 = g[2 * p3], w = w12 * g[2 * p3 + 1] * e2;
+                double d[3];
+                // t1 >= u1: t = xi (1, e1), u = xi e2 (1, e3)
+                for (int k = 0; k < 3; ++k) d[k] = (X1[k] + e1 * X2[k]) - e2 * (Y1[k] + e3 * Y2[k]);
+                ss_acc<false, NF>(d, w, f, l0, nl, ar, ai);
+                // u1 > t1: u = xi (1, e1), t = xi e2 (1, e3)
+                for (int k = 0; k < 3; ++k) d[k] = e2 * (X1[k] + e3 * X2[k]) - (Y1[k] + e1 * Y2[k]);
+                ss_acc<false, NF>(d, w, f, l0, nl, ar, ai);
+            }
+        }
+    }
+    const double sc = 4.0 * area_i * area_j;
+#pragma unroll
+    for (int t = 0; t < NF; ++t) {
+        ar[t] *= sc;
+        ai[t] *= sc;
+    }
+}
+
+// Common edge (P0, P1): tau_i = (P0, P1, a), tau_j = (P0, P1, b).
+template <int NF>
+__device__ void gal_ss_edge(const double *P0, const double *P1, const double *a, const double *b,
+                            double area_i, double area_j, int n, const double *g,
+                            const FreqDev &f, int l0, int nl, double *ar, double *ai) {
+    double E[3], A[3], B[3];
+    for (int k = 0; k < 3; ++k) {
+        E[k] = P1[k] - P0[k];
+        A[k] = a[k] - P1[k];
+        B[k] = b[k] - P1[k];
+    }
+#pragma unroll
+    for (int t = 0; t < NF; ++t) {
+        ar[t] = 0.0;
+        ai[t] = 0.0;
+    }
+    for (int p2 = 0; p2 < n; ++p2) {
+        const double e2 = g[2 * p2], w2 = g[2 * p2 + 1];
+        for (int p3 = 0; p3 < n; ++p3) {
+            const double e3 = g[2 * p3], w = w2 * g[2 * p3 + 1];
+            // coefficients of (E, A, B) in d for the five pieces
+            const double c[5][3] = {{e2, e3, -(1.0 - e2)},
+                                    {e2 * e3, 1.0, -e2 * (1.0 - e3)},
+                                    {-e2, 1.0 - e2, -e2 * e3},
+                                    {-e2 * e3, e2 * (1.0 - e3), -1.0},
+                                    {-e2 * e3, 1.0 - e2 * e3, -e2}};
+#pragma unroll
+            for (int r = 0; r < 5; ++r) {
+                double d[3];
+                for (int k = 0; k < 3; ++k) d[k] = c[r][0] * E[k] + c[r][1] * A[k] + c[r][2] * B[k];
+                ss_acc<true, NF>(d, r == 0 ? w : w * e2, f, l0, nl, ar, ai);
+            }
+        }
+    }
+    const double sc = 4.0 * area_i * area_j;
+#pragma unroll
+    for (int t = 0; t < NF; ++t) {
+        ar[t] *= sc;
+        ai[t] *= sc;
+    }
+}
+
 // Near-block Galerkin entry of pair (i, j) (tree positions) with the given class.
 template <int NF>
 __device__ void gal_near_entry(const GeoDev &g, const QuadDev &q, const FreqDev &f, int64_t i,
@@ -295,19 +459,29 @@ __device__ void gal_near_entry(const GeoDev &g, const QuadDev &q, const FreqDev 
         }
         return;
     }
-    // outer collapsed rule on tau_i, collapsed at the first vertex shared with tau_j
-    int c0 = 0;
     if (tier == GT_EDGE || tier == GT_VERTEX) {
+        // shared vertices (equal coordinates): positions in tau_i (ascending) and tau_j
         const double *Vj[3] = {aj, bj, cj};
-        bool found = false;
-        for (int va = 0; va < 3 && !found; ++va)
+        int ns = 0, pi_[3] = {0, 0, 0}, pj_[3] = {0, 0, 0};
+        for (int va = 0; va < 3; ++va)
             for (int vb = 0; vb < 3; ++vb)
                 if (ai3[va][0] == Vj[vb][0] && ai3[va][1] == Vj[vb][1] && ai3[va][2] == Vj[vb][2]) {
-                    c0 = va;
-                    found = true;
-                    break;
+                    pi_[ns] = va;
+                    pj_[ns] = vb;
+                    ++ns;
                 }
+        if (tier == GT_EDGE) {
+            gal_ss_edge<NF>(ai3[pi_[0]], ai3[pi_[1]], ai3[3 - pi_[0] - pi_[1]],
+                            Vj[3 - pj_[0] - pj_[1]], g.area[i], g.area[j], q.ns, q.gs, f, l0, nl,
+                            ar, ai);
+        } else {
+            const int a = pi_[0], b = pj_[0];
+            gal_ss_vertex<NF>(ai3[a], ai3[(a + 1) % 3], ai3[(a + 2) % 3], Vj[(b + 1) % 3],
+                              Vj[(b + 2) % 3], g.area[i], g.area[j], q.ns, q.gs, f, l0, nl, ar, ai);
+        }
+        return;
     }
+    const int c0 = 0;
     const double *A0 = ai3[c0], *A1 = ai3[(c0 + 1) % 3], *A2 = ai3[(c0 + 2) % 3];
     const int no = tier == GT_MID ? q.n4 : q.ng;
     const double *go = tier == GT_MID ? q.g4 : q.gg;

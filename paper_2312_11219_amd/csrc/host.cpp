@@ -23,8 +23,11 @@ void options_default(gaca_options *o) {
     o->eps3d = 1e-6;
     o->eps_aca = 1e-8;
     o->precision = GACA_FP64;
+    o->quad_mid = 4;
+    o->quad_near = 8;
     o->n_duffy = 16;
     o->n_galerkin = 5;
+    o->n_touch = 12;
     o->tie = 1e-9;
     o->delta_zero = 1e-13;
     o->max_rank3d = 64;
@@ -35,6 +38,7 @@ void options_default(gaca_options *o) {
     o->threads_large = 0;
     o->verbose = 0;
     o->zero_rows_batch = 1;
+    o->autotune_cache = nullptr;
 }
 
 // ---- Gauss-Legendre on [0, 1] by Newton iteration on the Legendre recurrence ----------

@@ -50,11 +50,12 @@ struct GeoDev {
 
 // Quadrature tables in device memory.
 struct QuadDev {
-    int n4, n8, nd, ng;
+    int n4, n8, nd, ng, ns;
     const double *g4;    // n4 x 2 (node, weight)
     const double *g8;    // n8 x 2
     const double *gd;    // nd x 2
-    const double *gg;    // ng x 2 (Galerkin touching pairs)
+    const double *gg;    // ng x 2 (Galerkin disjoint pairs with q < 2)
+    const double *gs;    // ns x 2 (Galerkin pairs sharing an edge or a vertex)
     const double *r6;    // 6 x 4 (bary, weight)
     int nth;
     const double *gth;   // nth x 2 (Galerkin coincident pairs, per angular sector)

@@ -112,6 +112,10 @@ void launch_far_gather(const FarBatchDev &bd, const FarGather *gt, int n, double
                        int64_t *fib_off, hipStream_t st);
 
 // Test hook: entries of (row, col) tree positions with given tiers at frequency k.
+// Mixed-precision far entries of one block (test hook): FP32 scaled entry times c_k in FP64.
+void launch_eval_far_mixed(int kernel, const GeoDev &g, const FreqDev &f, const FarBlockDev &B,
+                           int64_t n, const int32_t *il, const int32_t *jl, const int32_t *k,
+                           double2 *out, hipStream_t st);
 void launch_eval(int kernel, const GeoDev &g, const QuadDev &q, const FreqDev &f, int64_t n,
                  const int32_t *rows, const int32_t *cols, const int32_t *ks,
                  const int32_t *tiers, double2 *out, hipStream_t st);

@@ -381,6 +381,7 @@ gaca_status guarded(F &&fn) {
 struct gaca_problem {
     gaca_context *ctx = nullptr;
     gaca_options opt{};
+    std::string autotune_path;    // copy of opt.autotune_cache (opt points at it)
     gaca_scheme scheme = GACA_COLLOCATION_P0;
     bool synthetic = false;       // dense-tensor problem of gaca_compress_tensor
     HostMesh mesh;
@@ -480,6 +481,13 @@ gaca_status gaca_context_create(int device, void *hip_stream, gaca_context **out
         else
             (void)hipGetLastError();
         *out = c;
+    });
+}
+
+gaca_status gaca_context_memory(const gaca_context *ctx, uint64_t *in_use) {
+    return guarded([&] {
+        REQUIRE(ctx && in_use, "null argument");
+        *in_use = ctx->in_use.load();
     });
 }
 
@@ -588,8 +596,9 @@ static void upload_problem(gaca_problem *p) {
     g.q6dz = G32 + (size_t)12 * M;
     g.q6wf = G32 + (size_t)18 * M;
     // quadrature tables
-    Rule1D r4 = gauss_legendre01(4), r8 = gauss_legendre01(8),
-           rd = gauss_legendre01(p->opt.n_duffy), rg = gauss_legendre01(p->opt.n_galerkin);
+    Rule1D r4 = gauss_legendre01(p->opt.quad_mid), r8 = gauss_legendre01(p->opt.quad_near),
+           rd = gauss_legendre01(p->opt.n_duffy), rg = gauss_legendre01(p->opt.n_galerkin),
+           rs = gauss_legendre01(p->opt.n_touch);
     std::vector<double> qt;
     auto push_rule = [&](const Rule1D &r) {
         size_t off = qt.size();
@@ -601,7 +610,7 @@ static void upload_problem(gaca_problem *p) {
     };
     Rule1D rth = gauss_legendre01(kGalerkinNTheta);
     size_t o4 = push_rule(r4), o8 = push_rule(r8), od = push_rule(rd), og = push_rule(rg),
-           oth = push_rule(rth);
+           oth = push_rule(rth), os = push_rule(rs);
     size_t o6 = qt.size();
     for (int q = 0; q < 6; ++q) {
         qt.push_back(bary[q][0]);
@@ -611,10 +620,12 @@ static void upload_problem(gaca_problem *p) {
     }
     p->d_quad.upload(ctx, qt);
     const double *Q = p->d_quad.as<double>();
-    p->q.n4 = 4;
-    p->q.n8 = 8;
+    p->q.n4 = p->opt.quad_mid;
+    p->q.n8 = p->opt.quad_near;
     p->q.nd = p->opt.n_duffy;
     p->q.ng = p->opt.n_galerkin;
+    p->q.ns = p->opt.n_touch;
+    p->q.gs = Q + os;
     p->q.g4 = Q + o4;
     p->q.g8 = Q + o8;
     p->q.gd = Q + od;
@@ -702,6 +713,11 @@ gaca_status gaca_problem_create(gaca_context *ctx, const double *xyz, int64_t nv
         REQUIRE(p->opt.eps3d >= 0.0 && p->opt.eps_aca >= 0.0, "tolerances must be >= 0");
         REQUIRE(p->opt.n_duffy >= 1 && p->opt.n_duffy <= 64, "n_duffy out of range");
         REQUIRE(p->opt.n_galerkin >= 1 && p->opt.n_galerkin <= 32, "n_galerkin out of range");
+        REQUIRE(p->opt.n_touch >= 1 && p->opt.n_touch <= 32, "n_touch out of range");
+        REQUIRE(p->opt.quad_mid >= 1 && p->opt.quad_mid <= 32, "quad_mid out of range");
+        REQUIRE(p->opt.quad_near >= 1 && p->opt.quad_near <= 32, "quad_near out of range");
+        if (p->opt.autotune_cache) p->autotune_path = p->opt.autotune_cache;
+        p->opt.autotune_cache = p->autotune_path.empty() ? nullptr : p->autotune_path.c_str();
         REQUIRE(p->opt.tie >= 0.0 && p->opt.tie < 1.0, "tie out of range");
         ctx->limit = p->opt.max_device_bytes;
         p->scheme = scheme;
@@ -832,6 +848,28 @@ static double wall_ms_since(std::chrono::steady_clock::time_point t0) {
 // one collocation problem at once: their blocks are interleaved in one block list, so every
 // iteration's launches carry faces of both (each block's kernel in FarBlockDev::kern), and
 // the outputs go to each operator's own arenas and tables.
+// Mixed-precision scaling geometry of far block b from its cluster boxes: D = x_sigma -
+// y_tau (box centres), Dh = fl32(D), d0f = fl32(|D|), kappa = |Dh|^2 - d0f^2 (FP64, then
+// FP32) and xs_adj = x_sigma - (D - Dh).
+static void set_far_scaling(const gaca_problem *p, int64_t b, FarBlockDev &d) {
+    if (p->synthetic || p->part.far_nodes.size() != p->part.far.size()) return;
+    const auto &ns = p->tree.nodes[p->part.far_nodes[b][0]];
+    const auto &nt = p->tree.nodes[p->part.far_nodes[b][1]];
+    double D[3], dd = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double xs = 0.5 * (ns.lo[k] + ns.hi[k]), yt = 0.5 * (nt.lo[k] + nt.hi[k]);
+        D[k] = xs - yt;
+        dd += D[k] * D[k];
+        d.yt[k] = yt;
+        d.Dh[k] = (float)D[k];
+        d.xs_adj[k] = xs - (D[k] - (double)d.Dh[k]);
+    }
+    d.d0f = (float)std::sqrt(dd);
+    double kap = -(double)d.d0f * (double)d.d0f;
+    for (int k = 0; k < 3; ++k) kap += (double)d.Dh[k] * (double)d.Dh[k];
+    d.kappa = (float)kap;
+}
+
 static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                     const std::function<void()> &main_work) {
     const auto t_entry = std::chrono::steady_clock::now();
@@ -929,24 +967,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
         d.n = n;
         d.rho_max = rho_max;
         d.out_idx = (int32_t)b;   // operator 0; copies below for the others
-        if (!p->synthetic && p->part.far_nodes.size() == far.size()) {
-            // mixed scaling geometry from the cluster boxes
-            const auto &ns = p->tree.nodes[p->part.far_nodes[b][0]];
-            const auto &nt = p->tree.nodes[p->part.far_nodes[b][1]];
-            double D[3], dd = 0.0;
-            for (int k = 0; k < 3; ++k) {
-                const double xs = 0.5 * (ns.lo[k] + ns.hi[k]), yt = 0.5 * (nt.lo[k] + nt.hi[k]);
-                D[k] = xs - yt;
-                dd += D[k] * D[k];
-                d.yt[k] = yt;
-                d.Dh[k] = (float)D[k];
-                d.xs_adj[k] = xs - (D[k] - (double)d.Dh[k]);
-            }
-            d.d0f = (float)std::sqrt(dd);
-            double kap = -(double)d.d0f * (double)d.d0f;
-            for (int k = 0; k < 3; ++k) kap += (double)d.Dh[k] * (double)d.Dh[k];
-            d.kappa = (float)kap;
-        }
+        set_far_scaling(p, b, d);
         for (int w = 0; w < nh; ++w) {
             FarBlockDev dw = d;
             dw.out_idx = (int32_t)(w * nfar + b);
@@ -985,7 +1006,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
     // the aca phase of kind k runs on ks[k] (kind 3, the large faces, on the main far stream)
     const hipStream_t ks[4] = {p->far_streams[3], p->far_streams[2], p->far_streams[1], s0};
     enum { EV_BEGIN, EV_END, EV_F0, EV_F1, EV_K0, EV_K1, EV_K2, EV_K3, EV_S0, EV_S1, EV_S2, EV_S3, EV_J, EV_X,
-           EV_T, EV_C, EV_N };
+           EV_T, EV_C, EV_P0, EV_P2, EV_N };
     hipEvent_t ev[EV_N];
     for (auto &e : ev) GACA_HIP_CHECK(hipEventCreate(&e));
     struct EvGuard {
@@ -1031,6 +1052,10 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
     double ms_phase[4] = {0, 0, 0, 0}, ms_kind[4] = {0, 0, 0, 0}, fl_phase[4] = {0, 0, 0, 0};
     double fl_kind[4] = {0, 0, 0, 0};
     int launches_kind[4] = {0, 0, 0, 0};
+    // faces with a side above kMediumSide by kernel path (0 general, 1 one entry per thread,
+    // 2 several entries per thread): device time, launches, algorithmic flops
+    double ms_path[3] = {0, 0, 0}, fl_path[3] = {0, 0, 0};
+    int launches_path[3] = {0, 0, 0};
     int launches_phase[4] = {0, 0, 0, 0};
     int iters_max = 0, n_launch = 0;
     double evals = 0.0;
@@ -1265,7 +1290,9 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                     // big faces by path (general, several entries, one entry per thread),
                     // one after the other on the kind-3 stream
                     launch_far_aca(0, tl, P, bd, dact, npath[0], ks[3]);
+                    GACA_HIP_CHECK(hipEventRecord(ev[EV_P0], ks[3]));
                     launch_far_aca(2, tl, P, bd, dact + npath[0], npath[2], ks[3]);
+                    GACA_HIP_CHECK(hipEventRecord(ev[EV_P2], ks[3]));
                     launch_far_aca(1, tl, P, bd, dact + npath[0] + npath[2], npath[1], ks[3]);
                     launch_far_aca(1, 256, P, bd, dact + nbig, cnt[3] - nbig, ks[2]);
                     nl += (npath[0] > 0) + (npath[2] > 0) + (npath[1] > 0) + (cnt[3] > nbig);
@@ -1323,6 +1350,12 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                     ms_kind[k] += elapsed(EV_S0 + k, EV_K0 + k);
                     launches_kind[k] += 1;
                 }
+            if (nbig > 0) {
+                // the path launches follow each other on ks[3]: path 0, path 2, path 1
+                if (npath[0]) { ms_path[0] += elapsed(EV_S0 + 3, EV_P0); launches_path[0] += 1; }
+                if (npath[2]) { ms_path[2] += elapsed(EV_P0, EV_P2); launches_path[2] += 1; }
+                if (npath[1]) { ms_path[1] += elapsed(EV_P2, EV_K0 + 3); launches_path[1] += 1; }
+            }
             launches_phase[0] += 1;
             launches_phase[1] += nl;
             launches_phase[2] += ntile > 0;
@@ -1358,7 +1391,8 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                     if (kd == 3) {
                         const double f = 8.0 * (d.m + d.n) * (double)rho * (rho - 1.0);
                         fl_phase[1] += f;
-                        fl_kind[std::max(d.m, d.n) > kMediumSide ? 3 : 2] += f;
+                        fl_kind[big(lb) ? 3 : 2] += f;
+                        if (big(lb)) fl_path[path(lb)] += f;
                         fl_phase[2] += 8.0 * mn * (rho + ell);
                     } else {
                         const double f = 8.0 * mn * (2.0 * rho + ell);
@@ -1508,6 +1542,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
         st.ms_far_kernel = span;
         st.n_far_launches = n_launch;
         st.far_iters = iters_max;
+        st.threads_large_used = p->opt.threads_large > 0 ? p->opt.threads_large : 512;
         st.far_kernel_evals = evals;
         st.far_flops = 0.0;
         for (int k = 0; k < 4; ++k) {
@@ -1520,6 +1555,11 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             st.ms_far_by_kind[k] = ms_kind[k];
             st.launches_by_kind[k] = launches_kind[k];
             st.far_flops_by_kind[k] = fl_kind[k];
+            if (k < 3) {
+                st.ms_far_large_path[k] = ms_path[k];
+                st.launches_large_path[k] = launches_path[k];
+                st.far_flops_large_path[k] = fl_path[k];
+            }
         }
         int64_t tmax = 0;
         for (const auto &mt : hh->meta) tmax = std::max<int64_t>(tmax, mt.aca_ticks);
@@ -1578,7 +1618,10 @@ static void fill_stats(gaca_hmatrix *h) {
     s.bytes_near = (uint64_t)((double)p->near_elems * eb);
     s.dense_bytes = (double)p->M * (double)p->M * L * eb;
     s.compression = (s.bytes_far + s.bytes_near) / std::max(1.0, s.dense_bytes);
-    s.entries_near = (double)p->near_elems;
+    // with conjugate-pair frequencies the near kernels evaluate L_eval of the L frequencies
+    // and write the others as conjugates
+    s.entries_near = (double)p->near_elems * p->f.L_eval / std::max(1, p->f.L);
+    s.entries_near_mirrored = (double)p->near_elems - s.entries_near;
 }
 
 // Builds the operators `kernels` (one, or the collocation single and double layer) of p:
@@ -1660,11 +1703,16 @@ static bool build_ops(gaca_problem *p, const std::vector<gaca_kernel> &kernels,
         h->st.ms_near_kernel = ms_near;
         const double le = p->f.L_eval;
         const double ng2 = (double)p->opt.n_galerkin * p->opt.n_galerkin;
-        double qp[kNumTiers] = {6.0, 16.0, 64.0, kernels[w] == 0 ? 3.0 * p->opt.n_duffy * p->opt.n_duffy : 0.0,
+        const double nm2 = (double)p->opt.quad_mid * p->opt.quad_mid;
+        const double nn2 = (double)p->opt.quad_near * p->opt.quad_near;
+        const double ns = p->opt.n_touch;
+        double qp[kNumTiers] = {6.0, nm2, nn2, kernels[w] == 0 ? 3.0 * p->opt.n_duffy * p->opt.n_duffy : 0.0,
                                 0.0, 0.0};
         if (p->scheme == GACA_GALERKIN_P0) {
-            const double g6[kNumTiers] = {36.0, 256.0, 3.0 * ng2 * ng2, 3.0 * ng2 * ng2,
-                                          3.0 * ng2 * ng2, 6.0 * kGalerkinNTheta};
+            // touching pairs: 5 n^2 (edge) and 2 n^3 (vertex) evaluations of the exact radial
+            // integrals per frequency
+            const double g6[kNumTiers] = {36.0, nm2 * nm2, 3.0 * ng2 * ng2, 5.0 * ns * ns,
+                                          2.0 * ns * ns * ns, 6.0 * kGalerkinNTheta};
             for (int t = 0; t < kNumTiers; ++t) qp[t] = g6[t];
         }
         double evn = 0.0;
@@ -2250,6 +2298,49 @@ gaca_status gaca_eval_entries(gaca_problem *p, gaca_kernel kernel, int64_t n, co
     });
 }
 
+gaca_status gaca_eval_far_entries_mixed(gaca_problem *p, gaca_kernel kernel, int64_t far_block,
+                                        int64_t n, const int32_t *il, const int32_t *jl,
+                                        const int32_t *k, double *out) {
+    return guarded([&] {
+        REQUIRE(p, "null problem");
+        REQUIRE(kernel == GACA_SLP || kernel == GACA_DLP, "bad kernel");
+        REQUIRE(!p->synthetic, "entries need a mesh problem");
+        REQUIRE(far_block >= 0 && far_block < (int64_t)p->part.far.size(), "far block index out of range");
+        REQUIRE(n >= 0, "n must be >= 0");
+        if (n == 0) return;
+        REQUIRE(il && jl && k && out, "null argument");
+        if (p->scheme == GACA_GALERKIN_P0 && kernel != GACA_SLP)
+            throw Error{GACA_ERR_UNSUPPORTED, "Galerkin is available for the single layer only"};
+        const auto &fb = p->part.far[far_block];
+        FarBlockDev d{};
+        d.r0 = (int32_t)fb[0];
+        d.m = (int32_t)fb[1];
+        d.c0 = (int32_t)fb[2];
+        d.n = (int32_t)fb[3];
+        d.kern = kernel;
+        set_far_scaling(p, far_block, d);
+        std::vector<int32_t> a(n), b(n), c(n);
+        for (int64_t t = 0; t < n; ++t) {
+            REQUIRE(il[t] >= 0 && il[t] < d.m && jl[t] >= 0 && jl[t] < d.n, "local index out of range");
+            REQUIRE(k[t] >= 0 && k[t] < p->L, "frequency index out of range");
+            a[t] = il[t];
+            b[t] = jl[t];
+            c[t] = k[t];
+        }
+        gaca_context *ctx = p->ctx;
+        DevBuf da, db, dc, dout;
+        da.upload(ctx, a);
+        db.upload(ctx, b);
+        dc.upload(ctx, c);
+        dout.alloc(ctx, n * sizeof(double2));
+        launch_eval_far_mixed(p->kid(kernel), p->g, p->f, d, n, da.as<int32_t>(), db.as<int32_t>(),
+                              dc.as<int32_t>(), dout.as<double2>(), ctx->stream);
+        GACA_HIP_CHECK(hipGetLastError());
+        GACA_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+        GACA_HIP_CHECK(hipMemcpy(out, dout.ptr, n * sizeof(double2), hipMemcpyDeviceToHost));
+    });
+}
+
 gaca_status gaca_compress_tensor(gaca_context *ctx, const void *dev_tensor, int64_t m,
                                  int64_t n, int32_t L, const gaca_options *opt,
                                  gaca_hmatrix **out) {
@@ -2262,6 +2353,7 @@ gaca_status gaca_compress_tensor(gaca_context *ctx, const void *dev_tensor, int6
         p->ctx = ctx;
         if (opt) p->opt = *opt;
         else options_default(&p->opt);
+        p->opt.autotune_cache = nullptr;
         if (p->opt.precision != GACA_FP64)
             throw Error{GACA_ERR_UNSUPPORTED, "compress_tensor runs in FP64"};
         p->synthetic = true;

@@ -90,16 +90,20 @@ def test_c4_sampled_blocks():
     rng = np.random.default_rng(31)
     sizes = far[:, 1] * far[:, 3]
     cand = np.nonzero(sizes <= 96 * 96)[0]
-    pick = sorted(rng.choice(cand, 8, replace=False).tolist())
+    big = np.nonzero(np.minimum(far[:, 1], far[:, 3]) >= 256)[0]
+    assert big.size >= 2
+    pick = sorted(rng.choice(cand, 8, replace=False).tolist() + rng.choice(big, 2, replace=False).tolist())
     num = den = pnum = 0.0
     for b in pick:
         blk = tuple(int(v) for v in far[b])
         T = op.block_tensor("slp", blk, True)
         o = aca3d(T, cfg["eps"], cfg["eps_aca"])
         C = reconstruct(h, b)
-        pnum += np.linalg.norm(C - o.reconstruct(blk[1], blk[3], op.L)) ** 2
+        nb = np.linalg.norm(C - o.reconstruct(blk[1], blk[3], op.L)) ** 2
+        pnum += nb
         num += np.linalg.norm(C - T) ** 2
         den += np.linalg.norm(T) ** 2
+        log(f"C4 block {b} {blk[1]}x{blk[3]} rank {o.rank} parity {np.sqrt(nb) / np.linalg.norm(T):.2e}")
     log("C4 sampled parity", np.sqrt(pnum / den), "err", np.sqrt(num / den))
     assert np.sqrt(pnum / den) < 1e-6
     assert np.sqrt(num / den) < 10 * cfg["eps"]

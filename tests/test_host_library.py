@@ -27,7 +27,8 @@ def test_library_exports_header_symbols():
     assert len(syms) >= 20
     for s in syms:
         assert hasattr(lib, s), s
-    assert lib.gaca_abi_version() == 1
+    ver = int(re.search(r"#define GACA_ABI_VERSION (\d+)", open(os.path.join(ROOT, "include", "gaca.h")).read()).group(1))
+    assert lib.gaca_abi_version() == ver
 
 
 def test_no_gpu_context_fails_cleanly():
