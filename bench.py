@@ -112,9 +112,9 @@ def parse():
     ap.add_argument("--nrhs", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--far-sample", type=int, default=96)
-    ap.add_argument("--large-sample", type=int, default=4)
-    ap.add_argument("--leaf-rows", type=int, default=12)
+    ap.add_argument("--far-sample", type=int, default=256)
+    ap.add_argument("--large-sample", type=int, default=8)
+    ap.add_argument("--leaf-rows", type=int, default=32)
     # counter calibration: one y = 1.0 * x pass over this many bytes of FP32 before the
     # warm-up (a kernel of known traffic for the FETCH_SIZE / WRITE_SIZE scale)
     ap.add_argument("--copy-calibration", type=int, default=0)
