@@ -259,6 +259,20 @@ gaca_status gaca_hmatrix_near_export(const gaca_hmatrix *h, int64_t idx, double 
 gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, const void *X,
                        void *Y, gaca_dtype dtype, void *hip_stream);
 
+/* Allocation-free apply, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments and
+ * results as gaca_apply, computed with the VALU kernels of gaca_apply (no matrix-core path);
+ * its workspace (tree-order copies of X and Y, the per-block z, T and y and their offsets)
+ * lives in a fixed 64 MiB scratch array per device instead of memory allocated per operator.
+ * The call allocates nothing and frees nothing.  GACA_ERR_INVALID_ARG if the workspace of
+ * this operator, mode, nrhs and dtype exceeds 64 MiB (it grows as L M nrhs); GACA_ERR_STATE
+ * if the operator's apply tables are missing.  Every call on one GPU shares that GPU's
+ * array: calls that overlap in time on one GPU (different streams or host threads) race and
+ * must be serialised by the caller; the array keeps the last call's contents, and every byte
+ * a call reads is written earlier in the same call. */
+gaca_status gaca_apply_noalloc(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, const void *X,
+                               void *Y, gaca_dtype dtype, void *hip_stream);
+
 /* Test hook: entries E(i[p], j[p], k[p]) (ORIGINAL element ids) with the quadrature the
  * build uses for a pair in a far block (far[p] = 1) or a near block (far[p] = 0), FP64,
  * evaluated on the device.  out: 2 * n doubles (host).  n may be 0. */

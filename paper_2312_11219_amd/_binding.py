@@ -98,6 +98,7 @@ def load_library():
         "gaca_hmatrix_block_export": (I32, [P, I64, P, P, P, P, P, P, P]),
         "gaca_hmatrix_near_export": (I32, [P, I64, P]),
         "gaca_apply": (I32, [P, ctypes.c_int, I32, P, P, ctypes.c_int, P]),
+        "gaca_apply_noalloc": (I32, [P, ctypes.c_int, I32, P, P, ctypes.c_int, P]),
         "gaca_eval_entries": (I32, [P, ctypes.c_int, I64, P, P, P, P, P]),
         "gaca_eval_far_entries_mixed": (I32, [P, ctypes.c_int, I64, I64, P, P, P, P]),
         "gaca_compress_tensor": (I32, [P, P, I64, I64, I32, P, P]),
@@ -350,8 +351,9 @@ class HMatrix:
         _check(self._lib.gaca_hmatrix_near_export(self.handle, idx, _ptr(out)))
         return (out[0::2] + 1j * out[1::2]).reshape(m, self.L, n)
 
-    def apply(self, X, mode="sum", Y=None, stream=None):
-        """X: torch complex tensor [L, M, nrhs] on the GPU (original element order)."""
+    def apply(self, X, mode="sum", Y=None, stream=None, noalloc=False):
+        """X: torch complex tensor [L, M, nrhs] on the GPU (original element order).
+        noalloc: gaca_apply_noalloc (workspace in the library's fixed scratch array)."""
         import torch
         if X.dim() != 3 or X.shape[0] != self.L:
             raise ValueError("X must be [L, M, nrhs]")
@@ -363,8 +365,8 @@ class HMatrix:
             shape = (M, nrhs) if mode == "sum" else (L, M, nrhs)
             Y = torch.empty(shape, dtype=X.dtype, device=X.device)
         sp = P(stream.cuda_stream) if stream is not None else P(torch.cuda.current_stream().cuda_stream)
-        _check(self._lib.gaca_apply(self.handle, MODES[mode], nrhs, P(X.data_ptr()),
-                                    P(Y.data_ptr()), dtype, sp))
+        fn = self._lib.gaca_apply_noalloc if noalloc else self._lib.gaca_apply
+        _check(fn(self.handle, MODES[mode], nrhs, P(X.data_ptr()), P(Y.data_ptr()), dtype, sp))
         return Y
 
     def close(self):

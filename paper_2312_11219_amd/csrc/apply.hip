@@ -9,10 +9,97 @@
 // every sum in a fixed order (deterministic).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "device_util.h"
 #include "kernels.h"
 
 namespace gaca {
+
+// ---------------------------------------------------------------------------------------
+// Workspace of the allocation-free apply: one fixed array per device, alive until the
+// process ends.  Host code never passes `scratch` itself to a kernel (in host code the name
+// is a host-side stand-in): it uses the device address that hipGetSymbolAddress returns,
+// taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_addr[device]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[device] = ptr;
+    return hipSuccess;
+}
+
+void *scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_addr[device];
+}
+
+// Per-block workspace offsets of the VALU apply from the block metadata (what the host
+// computes for the allocated workspace): z_off = prefix of sum_rho * nrhs (SUM) or
+// sum_rho * L * nrhs (PER_FREQ), t_off = prefix of min(rank, cb) * n * nrhs (SUM; 0 else),
+// y_off = prefix of m * nrhs.  One workgroup: each thread sums a contiguous run of blocks,
+// the run totals are scanned in LDS, then each thread writes its run's prefixes.
+__global__ void __launch_bounds__(1024) apply_offsets_kernel(ApplyDev a, int mode, int cb,
+                                                             int64_t *zoff, int64_t *toff,
+                                                             int64_t *yoff) {
+    __shared__ int64_t sz[1024], st[1024], sy[1024];
+    const int nb = a.nfar, t = threadIdx.x;
+    const int per = (nb + 1023) / 1024;
+    const int b0 = min(nb, t * per), b1 = min(nb, b0 + per);
+    const int64_t zmul = mode == 0 ? a.nrhs : (int64_t)a.L * a.nrhs;
+    int64_t z = 0, tt = 0, y = 0;
+    for (int b = b0; b < b1; ++b) {
+        z += (int64_t)a.meta[b].sum_rho * zmul;
+        if (mode == 0) tt += (int64_t)min(a.meta[b].rank, cb) * a.far4[4 * b + 3] * a.nrhs;
+        y += (int64_t)a.far4[4 * b + 1] * a.nrhs;
+    }
+    sz[t] = z;
+    st[t] = tt;
+    sy[t] = y;
+    __syncthreads();
+    // inclusive scan of the run totals (Hillis-Steele)
+    for (int d = 1; d < 1024; d <<= 1) {
+        int64_t vz = 0, vt = 0, vy = 0;
+        if (t >= d) {
+            vz = sz[t - d];
+            vt = st[t - d];
+            vy = sy[t - d];
+        }
+        __syncthreads();
+        sz[t] += vz;
+        st[t] += vt;
+        sy[t] += vy;
+        __syncthreads();
+    }
+    z = sz[t] - z;
+    tt = st[t] - tt;
+    y = sy[t] - y;
+    for (int b = b0; b < b1; ++b) {
+        zoff[b] = z;
+        toff[b] = tt;
+        yoff[b] = y;
+        z += (int64_t)a.meta[b].sum_rho * zmul;
+        if (mode == 0) tt += (int64_t)min(a.meta[b].rank, cb) * a.far4[4 * b + 3] * a.nrhs;
+        y += (int64_t)a.far4[4 * b + 1] * a.nrhs;
+    }
+}
+
+void launch_apply_offsets(const ApplyDev &a, int mode, int cb, int64_t *zoff, int64_t *toff,
+                          int64_t *yoff, hipStream_t st) {
+    if (a.nfar <= 0) return;
+    apply_offsets_kernel<<<1, 1024, 0, st>>>(a, mode, cb, zoff, toff, yoff);
+}
 
 template <class XT>
 __global__ void permute_x_kernel(const XT *X, XT *Xp, const int64_t *perm, int L, int64_t M,

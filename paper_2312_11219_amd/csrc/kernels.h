@@ -147,6 +147,18 @@ struct ApplyDev {
     const int32_t *leaf_near_ptr, *leaf_near_idx;
     const int64_t *z_off;         // [nfar] offset of the block's z (sum_rho x nrhs) or v
 };
+// Allocation-free apply: fixed per-device scratch array in apply.hip.
+constexpr size_t kScratchBytes = 64ull << 20;   // 64 MiB per device
+constexpr int kMaxDevices = 64;
+// Takes the device address of the scratch array for `device` (which must be current) once;
+// later calls return at once.
+hipError_t scratch_setup(int device);
+// The device address taken by scratch_setup, or nullptr before it.
+void *scratch_address(int device);
+// Workspace offsets of the VALU apply (z, t, per-block y) written on the device.
+void launch_apply_offsets(const ApplyDev &a, int mode, int cb, int64_t *zoff, int64_t *toff,
+                          int64_t *yoff, hipStream_t st);
+
 // Matrix-core apply (SUM mode, complex64 right-hand sides), csrc/apply_mfma.hip.
 constexpr int kMfmaMaxSumRho = 4096;   // sum of face ranks of one far block
 constexpr int kMfmaMaxNearCols = 1024; // columns of one near block

@@ -471,6 +471,8 @@ gaca_status gaca_context_create(int device, void *hip_stream, gaca_context **out
         }
         REQUIRE(device >= 0 && device < count, "device index out of range");
         GACA_HIP_CHECK(hipSetDevice(device));
+        // device address of the allocation-free apply's scratch array on this device
+        GACA_HIP_CHECK(scratch_setup(device));
         auto *c = new gaca_context;
         c->device = device;
         c->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -1627,6 +1629,8 @@ static void fill_stats(gaca_hmatrix *h) {
 // Builds the operators `kernels` (one, or the collocation single and double layer) of p:
 // near fields on the context stream, far fields in one joint run.  Returns whether a rank
 // cap was hit.
+static void prepare_leaves(gaca_hmatrix *h);
+
 static bool build_ops(gaca_problem *p, const std::vector<gaca_kernel> &kernels,
                       std::vector<std::unique_ptr<gaca_hmatrix>> &out) {
     REQUIRE(!p->synthetic, "build needs a mesh problem");
@@ -1722,6 +1726,8 @@ static bool build_ops(gaca_problem *p, const std::vector<gaca_kernel> &kernels,
         h->st.ms_total = ms_total;
         capped = capped || h->st.n_capped > 0;
     }
+    // leaf tables of the apply (per problem, once): built here so that no apply allocates them
+    prepare_leaves(out[0].get());
     return capped;
 }
 
@@ -2195,6 +2201,41 @@ static void apply_mfma(gaca_hmatrix *h, const ApplyDev &a, int32_t nrhs, const f
     for (int k = 0; k < 3; ++k) h->st.ms_apply_part[k] = ms_part[k];
 }
 
+// Device view of an operator for the apply kernels (workspace offsets and the T group size
+// are set by the caller).
+static ApplyDev apply_view(gaca_hmatrix *h, int32_t nrhs) {
+    gaca_problem *p = h->p;
+    ApplyDev a{};
+    a.L = p->L;
+    a.nrhs = nrhs;
+    a.M = p->M;
+    a.perm = p->d_perm.as<int64_t>();
+    a.nfar = (int32_t)h->nfar;
+    a.nnear = (int32_t)p->nblocks.size();
+    a.rcap = h->rcap;
+    a.far4 = h->d_far4.as<int32_t>();
+    a.meta = h->d_meta.as<FarMeta>();
+    a.cmeta = h->d_cmeta.as<CrossMeta>();
+    a.cross_off = h->d_cross_off.as<int64_t>();
+    a.arena = h->d_arena.ptr;
+    a.fac_fp32 = h->prec == GACA_MIXED ? 1 : 0;
+    a.fib_off = h->d_fib_off.as<int64_t>();
+    a.fib_arena = h->d_fib.as<double2>();
+    a.nblocks = p->d_nblocks.as<NearBlockDev>();
+    a.near64 = h->prec == GACA_MIXED ? nullptr : h->d_near.as<double2>();
+    a.near32 = h->prec == GACA_MIXED ? h->d_near.as<float2>() : nullptr;
+    a.nleaf = (int32_t)p->leaf_r0.size();
+    a.max_leaf_m = 1;
+    for (int32_t lm : p->leaf_m) a.max_leaf_m = std::max(a.max_leaf_m, lm);
+    a.leaf_r0 = p->d_leaf_r0.as<int32_t>();
+    a.leaf_m = p->d_leaf_m.as<int32_t>();
+    a.leaf_far_ptr = p->d_lfp.as<int32_t>();
+    a.leaf_far_idx = p->d_lfi.as<int32_t>();
+    a.leaf_near_ptr = p->d_lnp.as<int32_t>();
+    a.leaf_near_idx = p->d_lni.as<int32_t>();
+    return a;
+}
+
 gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, const void *X,
                        void *Y, gaca_dtype dtype, void *hip_stream) {
     return guarded([&] {
@@ -2216,35 +2257,8 @@ gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, cons
                           mfma_supported(h);
         if (!mfma && (h->ws_nrhs != nrhs || h->ws_mode != (int)mode || h->ws_dtype != (int)dtype))
             alloc_apply_workspace(h, mode, nrhs, dtype);
-        ApplyDev a{};
-        a.L = L;
-        a.nrhs = nrhs;
-        a.M = M;
-        a.perm = p->d_perm.as<int64_t>();
-        a.nfar = (int32_t)h->nfar;
-        a.nnear = (int32_t)p->nblocks.size();
-        a.rcap = h->rcap;
-        a.far4 = h->d_far4.as<int32_t>();
-        a.meta = h->d_meta.as<FarMeta>();
-        a.cmeta = h->d_cmeta.as<CrossMeta>();
-        a.cross_off = h->d_cross_off.as<int64_t>();
-        a.arena = h->d_arena.ptr;
-        a.fac_fp32 = h->prec == GACA_MIXED ? 1 : 0;
-        a.fib_off = h->d_fib_off.as<int64_t>();
-        a.fib_arena = h->d_fib.as<double2>();
-        a.nblocks = p->d_nblocks.as<NearBlockDev>();
-        a.near64 = h->prec == GACA_MIXED ? nullptr : h->d_near.as<double2>();
-        a.near32 = h->prec == GACA_MIXED ? h->d_near.as<float2>() : nullptr;
-        a.nleaf = (int32_t)p->leaf_r0.size();
+        ApplyDev a = apply_view(h, nrhs);
         a.apply_cb = h->ws_cb;
-        a.max_leaf_m = 1;
-        for (int32_t lm : p->leaf_m) a.max_leaf_m = std::max(a.max_leaf_m, lm);
-        a.leaf_r0 = p->d_leaf_r0.as<int32_t>();
-        a.leaf_m = p->d_leaf_m.as<int32_t>();
-        a.leaf_far_ptr = p->d_lfp.as<int32_t>();
-        a.leaf_far_idx = p->d_lfi.as<int32_t>();
-        a.leaf_near_ptr = p->d_lnp.as<int32_t>();
-        a.leaf_near_idx = p->d_lni.as<int32_t>();
         a.z_off = h->d_zoff.as<int64_t>();
         if (mfma) {
             apply_mfma(h, a, nrhs, reinterpret_cast<const float2 *>(X), reinterpret_cast<float2 *>(Y), st);
@@ -2253,6 +2267,60 @@ gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, cons
         launch_apply(a, (int)mode, dtype == GACA_C64 ? 1 : 0, X, Y, h->d_xp.ptr, h->d_yp.ptr,
                      h->d_z.ptr, h->d_t.ptr, h->d_toff.as<int64_t>(), h->d_yb.ptr,
                      h->d_yoff.as<int64_t>(), st);
+        GACA_HIP_CHECK(hipGetLastError());
+    });
+}
+
+gaca_status gaca_apply_noalloc(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, const void *X,
+                               void *Y, gaca_dtype dtype, void *hip_stream) {
+    return guarded([&] {
+        REQUIRE(h && X && Y, "null argument");
+        REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+        REQUIRE(mode == GACA_APPLY_SUM || mode == GACA_APPLY_PER_FREQ, "bad mode");
+        REQUIRE(dtype == GACA_C128 || dtype == GACA_C64, "bad dtype");
+        REQUIRE(!h->p->synthetic, "apply needs a mesh problem");
+        gaca_problem *p = h->p;
+        gaca_context *ctx = p->ctx;
+        if (!p->leaf_ready) throw Error{GACA_ERR_STATE, "leaf tables missing (built with the operator)"};
+        void *base = scratch_address(ctx->device);
+        if (!base) throw Error{GACA_ERR_STATE, "scratch array not set up on this device"};
+        hipStream_t st = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : ctx->stream;
+        const int L = p->L;
+        const int64_t M = p->M;
+        const size_t xs = dtype == GACA_C64 ? sizeof(float2) : sizeof(double2);
+        const int cb = kApplyCB;
+        // workspace sizes (elements), as the allocated workspace of gaca_apply
+        int64_t zacc = 0, tacc = 0, yacc = 0;
+        for (int64_t b = 0; b < h->nfar; ++b) {
+            const int64_t sr = h->meta[b].sum_rho;
+            yacc += p->part.far[b][1] * (int64_t)nrhs;
+            zacc += mode == GACA_APPLY_SUM ? sr * nrhs : sr * (int64_t)L * nrhs;
+            if (mode == GACA_APPLY_SUM)
+                tacc += std::min<int64_t>(h->meta[b].rank, cb) * p->part.far[b][3] * (int64_t)nrhs;
+        }
+        const int nl = mode == GACA_APPLY_SUM ? 1 : L;
+        auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+        const size_t o_off = 0;
+        const size_t o_xp = al(o_off + 3 * (size_t)std::max<int64_t>(h->nfar, 1) * sizeof(int64_t));
+        const size_t o_yp = al(o_xp + (size_t)L * M * nrhs * xs);
+        const size_t o_z = al(o_yp + (size_t)nl * M * nrhs * xs);
+        const size_t o_t = al(o_z + (size_t)std::max<int64_t>(zacc, 1) * xs);
+        const size_t o_yb = al(o_t + (size_t)std::max<int64_t>(tacc, 1) * xs);
+        const size_t need = al(o_yb + (size_t)std::max<int64_t>(yacc, 1) * xs);
+        if (need > kScratchBytes)
+            throw Error{GACA_ERR_INVALID_ARG,
+                        "apply workspace of " + std::to_string(need) + " bytes exceeds the " +
+                            std::to_string(kScratchBytes) + "-byte scratch array of the allocation-free apply"};
+        unsigned char *sb = static_cast<unsigned char *>(base);
+        int64_t *zoff = reinterpret_cast<int64_t *>(sb + o_off);
+        int64_t *toff = zoff + std::max<int64_t>(h->nfar, 1);
+        int64_t *yoff = toff + std::max<int64_t>(h->nfar, 1);
+        ApplyDev a = apply_view(h, nrhs);
+        a.apply_cb = cb;
+        a.z_off = zoff;
+        launch_apply_offsets(a, (int)mode, cb, zoff, toff, yoff, st);
+        launch_apply(a, (int)mode, dtype == GACA_C64 ? 1 : 0, X, Y, sb + o_xp, sb + o_yp, sb + o_z,
+                     sb + o_t, toff, sb + o_yb, yoff, st);
         GACA_HIP_CHECK(hipGetLastError());
     });
 }
