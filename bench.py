@@ -227,9 +227,13 @@ def run_leg(gaca, ctx, xyz, tri, s, cfg, X, stream, args, precision, sample):
     import torch
     kernels = cfg["kernels"]
     t_setup = time.perf_counter()
+    # face-ACA workgroup sizes chosen by the library's autotuner during the warm-up build
+    # (a fresh cache file per run, so the choice is measured on this device)
+    import tempfile
+    cache = os.path.join(tempfile.mkdtemp(prefix="gaca_bench_"), "autotune.txt")
     prob = gaca.Problem(ctx, xyz, tri, s, scheme=cfg.get("scheme", "collocation"),
                         leaf_size=cfg["leaf"], eta=cfg["eta"], eps3d=cfg["eps"],
-                        eps_aca=cfg["eps_aca"], precision=precision)
+                        eps_aca=cfg["eps_aca"], precision=precision, autotune_cache=cache)
     t_setup = time.perf_counter() - t_setup
     Xp = X if precision == "fp64" else X.to(torch.complex64)
 
@@ -242,6 +246,7 @@ def run_leg(gaca, ctx, xyz, tri, s, cfg, X, stream, args, precision, sample):
         del hs
         return st
 
+    step()   # the autotuner's build (one build per candidate), never timed
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -270,6 +275,9 @@ def run_leg(gaca, ctx, xyz, tri, s, cfg, X, stream, args, precision, sample):
         "compression": {k: st["compression"] for k, st in zip(kernels, last)},
         "far_iters": {k: st["far_iters"] for k, st in zip(kernels, last)},
         "far_launches": {k: st["n_far_launches"] for k, st in zip(kernels, last)},
+        "autotuned_workgroups": {"threads_large": last[0]["threads_large_used"],
+                                 "threads_small": last[0]["threads_small_used"],
+                                 "state": ["options", "measured", "cache"][last[0]["autotune_state"]]},
         "setup_s": t_setup,
         "far_phase_ms": {name: float(np.mean([sum(st["ms_far_phase"][i] for st in stp) / joint
                                               for stp in all_stats])) for i, name in enumerate(PHASES)},

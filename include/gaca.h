@@ -22,7 +22,9 @@
  *     (the library renumbers elements so that every cluster is a contiguous range; the
  *     permutation is returned by gaca_problem_perm);
  *   - handles are owned by the library and freed by the matching *_destroy; all inputs are
- *     copied; a handle is used by one host thread at a time.  Different problems of one
+ *     copied; a handle is used by one host thread at a time.  Destroying a context or a
+ *     problem that still has problems or operators only marks it: it is freed with the last
+ *     of them, so handles may be destroyed in any order.  Different problems of one
  *     context may be built from different threads at the same time (each problem has its
  *     own far-field streams and working memory), which overlaps their builds on the GPU.
  */
@@ -79,7 +81,8 @@ typedef struct {
     int32_t max_rank3d;       /* cap on crosses per block (default min(L, 64)) */
     int32_t max_face_rank;    /* cap on a face's ACA rank (default min(m, n)) */
     uint64_t max_device_bytes;/* 0 = no limit; otherwise total library device memory cap */
-    uint64_t batch_bytes;     /* far-field scratch per batch of blocks (default 24 GiB) */
+    uint64_t batch_bytes;     /* far-field scratch per batch of blocks (default 96 GiB; at most
+                                 half of the free device memory is used) */
     int32_t threads_small;    /* face-ACA workgroup size for faces with m n <= 1024: 128
                                  (default) or 64 (one wave per face) */
     int32_t threads_large;    /* face-ACA workgroup size for the large faces (256, 512 or
@@ -89,6 +92,20 @@ typedef struct {
     int32_t zero_rows_batch;  /* face ACA of the large faces, after a zero row: 1 (default)
                                  tries several unused rows per pass over the history, 0 one
                                  row per pass; both end at the same row */
+    int32_t recompress;       /* 1: recompress every face after its ACA (QR of U and W, SVD of
+                                 R_U R_W^T, truncation at eps_aca; Sec. 4 remarks), faces of
+                                 rank 2..128; default 0 */
+    int32_t pivot_estimate;   /* 0 (default): pivot of H_l by dense expansion; 1: eq. (index)
+                                 estimate of the pivot row from the recompressed factors, the
+                                 column from that row of H_l (needs recompress) */
+    int32_t near_aca;         /* 1: after the build, compress each near block along the
+                                 frequencies by 3D-ACA with dense faces (Sec. 4 remarks on the
+                                 near field: rank r slices H_l (m x n, stored whole) times
+                                 frequency fibres); a block stays dense where r (m n + L) >=
+                                 m n L, where m n > 1024 or where the rank reaches
+                                 min(L, 64).  Needs L <= 1024 (else GACA_ERR_UNSUPPORTED at
+                                 problem creation).  The apply then runs on the VALU kernels
+                                 (gaca_apply_noalloc: GACA_ERR_UNSUPPORTED).  Default 0 */
     const char *autotune_cache; /* NULL (default): no autotuning.  Otherwise a file path: the
                                  face-ACA workgroup sizes chosen for a workload (measured on
                                  the first build of a problem and timed per candidate) are
@@ -152,6 +169,10 @@ typedef struct {
     int32_t launches_large_path[3];
     double far_flops_large_path[3];
     int32_t threads_large_used;   /* workgroup size of the class-3 launches */
+    int32_t threads_small_used;   /* workgroup size of the class-0 launches */
+    int32_t autotune_state;       /* 0 sizes from the options, 1 chosen by timing each candidate
+                                     during this problem's first build, 2 read from the
+                                     autotune_cache file */
     double ms_far_aca_block_max;  /* longest total face-ACA time of one block (device clock) */
     double ms_host_setup;         /* host time of the build before the far-field launches */
     double ms_host_finish;        /* host time of the build after the far field completed */
@@ -166,6 +187,12 @@ typedef struct {
     int32_t joint_build;          /* operators built together (gaca_build_both: 2); the far-field
                                      timings, launch counts, kernel evaluations and flops above
                                      then describe the shared launches of the joint build */
+    /* near_aca: near blocks kept compressed, their mean and largest 3D-ACA rank, and the
+     * host time of the compression pass (device work included) */
+    int32_t near_rank_max;
+    int64_t n_near_compressed;
+    double near_rank_mean;
+    double ms_near_aca;
 } gaca_stats;
 
 int gaca_abi_version(void);
@@ -173,10 +200,10 @@ const char *gaca_last_error(void);
 void gaca_options_default(gaca_options *opt);
 
 /* Context on HIP device `device`, launching on `hip_stream` (a hipStream_t, may be NULL
- * for the default stream; not owned).  GACA_ERR_STATE if no usable GPU.  Destroy every
- * problem and operator made on a context before the context itself: they account their
- * device memory in it, and a destroyed problem hands its far-field streams back to it for
- * the next problem. */
+ * for the default stream; not owned).  GACA_ERR_STATE if no usable GPU.  Problems and
+ * operators account their device memory in their context, and a destroyed problem hands its
+ * far-field streams back to it for the next problem; the context is freed once it and all
+ * of its problems are destroyed. */
 gaca_status gaca_context_create(int device, void *hip_stream, gaca_context **out);
 gaca_status gaca_context_destroy(gaca_context *ctx);
 /* Device memory the library holds for this context (every problem and operator made on it,
@@ -247,8 +274,12 @@ gaca_status gaca_hmatrix_block_info(const gaca_hmatrix *h, int64_t idx, int64_t 
 gaca_status gaca_hmatrix_block_export(const gaca_hmatrix *h, int64_t idx, int32_t *ks,
                                       int32_t *pi, int32_t *pj, int32_t *rho, double *U,
                                       double *W, double *F);
-/* Near block idx as C128 [m][L][n] (tree-local order). */
+/* Near block idx as C128 [m][L][n] (tree-local order); a block compressed by near_aca is
+ * expanded (sum over its slices H_l times fibre entries) on the device first. */
 gaca_status gaca_hmatrix_near_export(const gaca_hmatrix *h, int64_t idx, double *out);
+/* 3D-ACA rank of every near block (host int32[n_near], problem block order): the rank of a
+ * block compressed by near_aca, -1 for a block stored dense (always -1 without near_aca). */
+gaca_status gaca_hmatrix_near_ranks(const gaca_hmatrix *h, int32_t *ranks);
 
 /* Apply (eq. product).  X: device pointer, [L][M][nrhs] complex in ORIGINAL element order;
  * Y: device pointer, [M][nrhs] (SUM) or [L][M][nrhs] (PER_FREQ).  dtype GACA_C128 runs the
@@ -272,6 +303,38 @@ gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, cons
  * a call reads is written earlier in the same call. */
 gaca_status gaca_apply_noalloc(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, const void *X,
                                void *Y, gaca_dtype dtype, void *hip_stream);
+
+/* Integration points s_l and weights omega_l of the generalised convolution quadrature
+ * (App. A; Sec. 3, eq. (gcq_slp)) for a Runge-Kutta method with `stages` stages and Butcher
+ * matrix rk_A (row-major stages x stages, nonsingular) and step sizes in [dt_min, dt_max]:
+ * with lambda the eigenvalues of rk_A, q = dt_max max|lambda| / (dt_min min|lambda|) (times 5
+ * for more than one stage, q > 1 required), k = (q - sqrt(2q-1)) / (q + sqrt(2q-1)),
+ * h = dt_min min|lambda|, sigma_l = -K + (l + 1/2) 4K / n_q + i K'/2 (K = K(k^2),
+ * K' = K(1 - k^2)), s_l = (sqrt(2q-1) (1/k + sn) / (1/k - sn) - 1) / (h (q - 1)) and
+ * omega_l = 4K / (2 pi i n_q) gamma'(sigma_l) (Jacobi functions sn, cn, dn of parameter
+ * k^2), so that sum_l omega_l F(s_l) is the quadrature of the Bromwich integral
+ * (1 / 2 pi i) int F ds of eq. (conv_discrete).  The points are conjugate pairs,
+ * s_{n_q-1-l} = conj(s_l) exactly (a problem made with them evaluates half of them).
+ * Host only; outputs: n_q doubles each (host).  GACA_ERR_INVALID_ARG for q <= 1. */
+gaca_status gaca_gcq_contour(int32_t stages, const double *rk_A, double dt_min, double dt_max,
+                             int32_t n_q, double *s_re, double *s_im, double *w_re,
+                             double *w_im);
+
+/* History step of the Runge-Kutta gCQ (Sec. 3: eq. (gCQ_xn) and the sum of eq.
+ * (gcq_formula)) with an operator built at the integration points (its problem's
+ * frequencies s_l):
+ *   x_{n-1}(s_l) = (I - dt_prev s_l A)^{-1} ((b^T A^{-1} x_{n-2}(s_l)) 1 + dt_prev A theta_{n-1}),
+ *   W_l = omega_l (b^T A^{-1} x_{n-1}(s_l)) (I - dt_cur s_l A)^{-1} 1,
+ *   Y = sum_l C(s_l) W_l   (gaca_apply, SUM mode, the stages as right-hand sides).
+ * rk_A: stages x stages (row-major), rk_b: stages (host); w_re, w_im: the L weights (host).
+ * Device buffers, complex128, original element order, caller-owned: theta_prev [M][stages]
+ * (the stage values of step n-1), x [L][M][stages] (in: x_{n-2}, zero before the first
+ * update; out: x_{n-1}), W [L][M][stages] (workspace, out: the vectors W_l), Y [M][stages]
+ * (out: the history term).  Asynchronous on hip_stream as gaca_apply. */
+gaca_status gaca_gcq_history(gaca_hmatrix *h, int32_t stages, const double *rk_A,
+                             const double *rk_b, double dt_prev, double dt_cur,
+                             const double *w_re, const double *w_im, const void *theta_prev,
+                             void *x, void *W, void *Y, void *hip_stream);
 
 /* Test hook: entries E(i[p], j[p], k[p]) (ORIGINAL element ids) with the quadrature the
  * build uses for a pair in a far block (far[p] = 1) or a near block (far[p] = 0), FP64,

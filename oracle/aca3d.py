@@ -38,6 +38,29 @@ library, which implements them independently):
     face with no usable row marks k used and moves to the lowest unused frequency;
     three consecutive zero faces, or all frequencies used, end the block.
 
+Recompression and pivot estimate (Sec. 4, remarks for the implementation), options of
+``aca3d``:
+  * recompress: after the face ACA, U W^T = Q_U (R_U R_W^T) Q_W^T with the QR factorisations
+    U = Q_U R_U, W = Q_W R_W; the SVD R_U R_W^T = X Sigma Y^H gives the SVD-like form
+    U' W'^T with U' = Q_U X Sigma (left singular vectors scaled) and W' = Q_W conj(Y); the
+    trailing singular values are dropped while the dropped part stays within the face
+    tolerance, sqrt(sum of dropped sigma^2) <= eps_aca sqrt(||C^(l-1)(:,:,k)||^2 + sum sigma^2)
+    (the reference of the face ACA's own stop test), at least one kept.  H_l is the
+    recompressed face.  Faces of rank 1 are already in that form and faces of rank above
+    128 are kept as the face ACA left them (a bound on the work per face).
+  * pivot = "index": eq. (index), the pivot estimate from the orthonormal factors,
+    i = argmax_i sum_k |u_ik sigma_k| (same tie rule), then j = the largest entry of row i of
+    H_l, formed from the factors (n r products); needs recompress.  Reading: taking j by the
+    same estimate over the columns, independently of i, put the pivot on small entries of the
+    face (their fibre divided by a near-zero value inflates ||C|| and stops the block early):
+    on the 40 largest blocks of the 768-triangle cube 35 ended with errors near 1; with j
+    from row i all were within 10 eps.  The default "dense" expands H_l (as the paper's
+    reported results do).
+
+Non-admissible blocks (``aca3d_dense``, Sec. 4 remarks and the "No Lwr" variant of Sec. 5):
+the same algorithm with the residual face itself as H_l (no face ACA); the block is kept dense
+when the compressed form would not be smaller.
+
 Parity pins: tests/test_oracle_aca.py (known-rank tensors recovered exactly, eps = 0
 reproduction, f_l[k_l] = 1 and f_l[k_p] = 0 on exact faces, recursion = direct norm,
 error <= 10 eps on real blocks).
@@ -50,6 +73,7 @@ import numpy as np
 
 TIE = 1e-9
 DELTA = 1e-13
+RECOMPRESS_MAX_RANK = 128   # faces of higher rank are kept as the face ACA left them
 
 
 def argmax_tie(a2: np.ndarray, mask: np.ndarray | None = None, tie: float = TIE) -> int:
@@ -112,6 +136,30 @@ def face_aca(R: np.ndarray, eps_aca: float, zero_tol: float, max_rank: int, tie:
     return (U, W, piv) if return_pivots else (U, W)
 
 
+def recompress(U: np.ndarray, W: np.ndarray, eps_aca: float, ref2: float = 0.0):
+    """Recompressed factors (U', W', sigma) of the face U W^T (see the module header)."""
+    if U.shape[1] == 0:
+        return U, W, np.zeros(0)
+    QU, RU = np.linalg.qr(U)
+    QW, RW = np.linalg.qr(W)
+    X, sig, YH = np.linalg.svd(RU @ RW.T)
+    tail2 = np.cumsum((sig ** 2)[::-1])[::-1]          # tail2[k] = sum_{k' >= k} sigma_k'^2
+    lim2 = eps_aca ** 2 * (ref2 + tail2[0])
+    r = len(sig)
+    while r > 1 and tail2[r - 1] <= lim2:
+        r -= 1
+    return QU @ (X[:, :r] * sig[:r]), QW @ YH[:r, :].T, sig[:r]
+
+
+def index_pivot(U: np.ndarray, W: np.ndarray, sig: np.ndarray, tie: float = TIE):
+    """eq. (index) for the row (U' = U_bar Sigma, so sum_k |u_ik sigma_k| = sum_k |U'_ik|),
+    then the largest entry of that row of U' W'^T."""
+    a = np.abs(U).sum(axis=1)
+    i = argmax_tie(a * a, tie=tie)
+    row = W @ U[i, :]
+    return i, argmax_tie(row.real ** 2 + row.imag ** 2, tie=tie)
+
+
 @dataclass
 class Cross:
     k: int
@@ -149,8 +197,11 @@ def gram_face(Ua, Wa, Ub, Wb):
 
 
 def aca3d(T: np.ndarray, eps: float, eps_aca: float, max_rank3d: int | None = None,
-          max_face_rank: int | None = None, tie: float = TIE, delta: float = DELTA) -> BlockResult:
+          max_face_rank: int | None = None, tie: float = TIE, delta: float = DELTA,
+          recompress_faces: bool = False, pivot: str = "dense") -> BlockResult:
     """3D-ACA of the dense block tensor T (m x n x L); ENTRY(i, j, k) = T[i, j, k]."""
+    if pivot not in ("dense", "index") or (pivot == "index" and not recompress_faces):
+        raise ValueError("pivot must be 'dense', or 'index' with recompressed faces")
     m, n, L = T.shape
     if max_rank3d is None:
         max_rank3d = L
@@ -183,11 +234,18 @@ def aca3d(T: np.ndarray, eps: float, eps_aca: float, max_rank3d: int | None = No
             k = int(np.nonzero(~res.used)[0][0])
             continue
         zero_run = 0
-        H = U @ W.T
-        a2 = (H.real ** 2 + H.imag ** 2).ravel()
-        idx = argmax_tie(a2, tie=tie)
-        i, j = divmod(idx, n)
-        hpiv = H[i, j]
+        sig = None
+        if recompress_faces and 2 <= U.shape[1] <= RECOMPRESS_MAX_RANK:
+            U, W, sig = recompress(U, W, eps_aca, ref2=max(prev2, 0.0))
+        if pivot == "index":
+            i, j = index_pivot(U, W, sig, tie)
+            hpiv = U[i, :] @ W[j, :]
+        else:
+            H = U @ W.T
+            a2 = (H.real ** 2 + H.imag ** 2).ravel()
+            idx = argmax_tie(a2, tie=tie)
+            i, j = divmod(idx, n)
+            hpiv = H[i, j]
         f = T[i, j, :].copy()
         for c in res.crosses:
             f -= (c.U[i, :] @ c.W[j, :]) * c.f
@@ -219,3 +277,72 @@ def aca3d(T: np.ndarray, eps: float, eps_aca: float, max_rank3d: int | None = No
         k = argmax_tie(af, ~res.used, tie=tie)
     res.norm2 = norm2
     return res
+
+
+def aca3d_dense(T: np.ndarray, eps: float, max_rank3d: int | None = None, tie: float = TIE,
+                delta: float = DELTA) -> BlockResult:
+    """3D-ACA of a non-admissible block with dense faces (Sec. 4 remarks: the non-admissible
+    blocks compare all their entries; Sec. 5 "No Lwr": approximation only with respect to the
+    frequencies).  Algorithm 1 with H_l = the residual face ENTRY(:, :, k_l) - C^(l-1)(:, :, k_l)
+    itself; pivot = largest |H_l| (tie rule), fibre, eq. (norm), stop test, next frequency and
+    zero faces as in aca3d.  Each cross stores H_l as U = H_l, W = identity (so that
+    reconstruct() applies unchanged)."""
+    m, n, L = T.shape
+    if max_rank3d is None:
+        max_rank3d = L
+    res = BlockResult(used=np.zeros(L, dtype=bool))
+    eye = np.eye(n, dtype=complex)
+    k = 0
+    zero_run = 0
+    norm2 = 0.0
+    faces = []
+    while True:
+        H = T[:, :, k].copy()
+        for c, Hp in zip(res.crosses, faces):
+            H -= c.f[k] * Hp
+        scale = 0.0
+        for c in res.crosses:
+            scale = max(scale, abs(c.hpiv) * np.abs(c.f).max())
+        res.used[k] = True
+        a2 = (H.real ** 2 + H.imag ** 2).ravel()
+        if np.sqrt(a2.max()) <= delta * scale:
+            res.zero_faces += 1
+            zero_run += 1
+            if zero_run >= 3 or res.used.all():
+                break
+            k = int(np.nonzero(~res.used)[0][0])
+            continue
+        zero_run = 0
+        idx = argmax_tie(a2, tie=tie)
+        i, j = divmod(idx, n)
+        hpiv = H[i, j]
+        f = T[i, j, :].copy()
+        for c, Hp in zip(res.crosses, faces):
+            f -= Hp[i, j] * c.f
+        f = f / hpiv
+        cross_terms = 0.0
+        for c, Hp in zip(res.crosses, faces):
+            g = np.sum(H * np.conj(Hp))
+            cross_terms += (g * np.vdot(c.f, f)).real
+        h2 = float(np.sum(a2))
+        f2 = np.vdot(f, f).real
+        norm2 = norm2 + 2.0 * cross_terms + h2 * f2
+        res.crosses.append(Cross(k, H, eye, f, int(i), int(j), complex(hpiv)))
+        faces.append(H)
+        if np.sqrt(h2 * f2) <= eps * np.sqrt(max(norm2, 0.0)):
+            break
+        if res.used.all():
+            break
+        if len(res.crosses) >= max_rank3d:
+            res.capped = True
+            break
+        af = f.real ** 2 + f.imag ** 2
+        k = argmax_tie(af, ~res.used, tie=tie)
+    res.norm2 = norm2
+    return res
+
+
+def near_storage_compressed(m: int, n: int, L: int, rank: int, capped: bool) -> bool:
+    """A non-admissible block is stored compressed when its 3D-ACA converged and
+    rank (m n + L) < m n L (faces + fibres smaller than the dense block); else dense."""
+    return (not capped) and rank * (m * n + L) < m * n * L

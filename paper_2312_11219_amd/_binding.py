@@ -35,6 +35,7 @@ class Options(ctypes.Structure):
                 ("delta_zero", F64), ("max_rank3d", I32), ("max_face_rank", I32),
                 ("max_device_bytes", U64), ("batch_bytes", U64), ("threads_small", I32),
                 ("threads_large", I32), ("verbose", I32), ("zero_rows_batch", I32),
+                ("recompress", I32), ("pivot_estimate", I32), ("near_aca", I32),
                 ("autotune_cache", ctypes.c_char_p)]
 
 
@@ -53,10 +54,12 @@ class Stats(ctypes.Structure):
                 ("launches_by_kind", I32 * 4), ("far_flops_by_kind", F64 * 4),
                 ("ms_far_large_path", F64 * 3), ("launches_large_path", I32 * 3),
                 ("far_flops_large_path", F64 * 3), ("threads_large_used", I32),
+                ("threads_small_used", I32), ("autotune_state", I32),
                 ("ms_far_aca_block_max", F64), ("ms_host_setup", F64), ("ms_host_finish", F64),
                 ("ms_apply", F64), ("apply_flops", F64), ("apply_operator_bytes", F64),
                 ("ms_apply_part", F64 * 3), ("apply_flops_part", F64 * 3), ("arena_in_place", I32),
-                ("joint_build", I32)]
+                ("joint_build", I32), ("near_rank_max", I32), ("n_near_compressed", I64),
+                ("near_rank_mean", F64), ("ms_near_aca", F64)]
 
 
 def lib_path() -> str:
@@ -97,12 +100,15 @@ def load_library():
         "gaca_hmatrix_block_info": (I32, [P, I64, P]),
         "gaca_hmatrix_block_export": (I32, [P, I64, P, P, P, P, P, P, P]),
         "gaca_hmatrix_near_export": (I32, [P, I64, P]),
+        "gaca_hmatrix_near_ranks": (I32, [P, P]),
         "gaca_apply": (I32, [P, ctypes.c_int, I32, P, P, ctypes.c_int, P]),
         "gaca_apply_noalloc": (I32, [P, ctypes.c_int, I32, P, P, ctypes.c_int, P]),
         "gaca_eval_entries": (I32, [P, ctypes.c_int, I64, P, P, P, P, P]),
         "gaca_eval_far_entries_mixed": (I32, [P, ctypes.c_int, I64, I64, P, P, P, P]),
         "gaca_compress_tensor": (I32, [P, P, I64, I64, I32, P, P]),
         "gaca_quadrature_rule": (I32, [ctypes.c_int, ctypes.c_int, P, P]),
+        "gaca_gcq_contour": (I32, [I32, P, F64, F64, I32, P, P, P, P]),
+        "gaca_gcq_history": (I32, [P, I32, P, P, F64, F64, P, P, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -153,6 +159,17 @@ def quadrature_rule(kind: str, n: int):
     w = np.zeros(6)
     _check(lib.gaca_quadrature_rule(1, 6, _ptr(x), _ptr(w)))
     return x.reshape(6, 3), w
+
+
+def gcq_contour(rk_A, dt_min, dt_max, n_q):
+    """gCQ integration points and weights (library's own computation): (s, omega)."""
+    lib = load_library()
+    A = np.ascontiguousarray(rk_A, dtype=np.float64)
+    m = A.shape[0]
+    sr, si, wr, wi = (np.zeros(n_q) for _ in range(4))
+    _check(lib.gaca_gcq_contour(m, _ptr(A), dt_min, dt_max, n_q, _ptr(sr), _ptr(si), _ptr(wr),
+                                _ptr(wi)))
+    return sr + 1j * si, wr + 1j * wi
 
 
 def partition_host(xyz, tri, leaf_size, eta):
@@ -351,6 +368,12 @@ class HMatrix:
         _check(self._lib.gaca_hmatrix_near_export(self.handle, idx, _ptr(out)))
         return (out[0::2] + 1j * out[1::2]).reshape(m, self.L, n)
 
+    def near_ranks(self):
+        """3D-ACA rank per near block (-1: stored dense)."""
+        out = np.zeros(int(self.stats()["n_near"]), dtype=np.int32)
+        _check(self._lib.gaca_hmatrix_near_ranks(self.handle, _ptr(out)))
+        return out
+
     def apply(self, X, mode="sum", Y=None, stream=None, noalloc=False):
         """X: torch complex tensor [L, M, nrhs] on the GPU (original element order).
         noalloc: gaca_apply_noalloc (workspace in the library's fixed scratch array)."""
@@ -367,6 +390,23 @@ class HMatrix:
         sp = P(stream.cuda_stream) if stream is not None else P(torch.cuda.current_stream().cuda_stream)
         fn = self._lib.gaca_apply_noalloc if noalloc else self._lib.gaca_apply
         _check(fn(self.handle, MODES[mode], nrhs, P(X.data_ptr()), P(Y.data_ptr()), dtype, sp))
+        return Y
+
+    def gcq_history(self, rk_A, rk_b, dt_prev, dt_cur, w, theta_prev, x, W, Y, stream=None):
+        """gCQ history step on device tensors (complex128, original order): updates x in
+        place, fills W and writes the history term into Y [M][stages]."""
+        import torch
+        A = np.ascontiguousarray(rk_A, dtype=np.float64)
+        b = np.ascontiguousarray(rk_b, dtype=np.float64)
+        w = np.asarray(w, dtype=np.complex128)
+        wr, wi = np.ascontiguousarray(w.real), np.ascontiguousarray(w.imag)
+        for t in (theta_prev, x, W, Y):
+            if not (t.is_cuda and t.is_contiguous() and t.dtype == torch.complex128):
+                raise ValueError("gcq_history needs contiguous complex128 GPU tensors")
+        sp = P(stream.cuda_stream) if stream is not None else P(torch.cuda.current_stream().cuda_stream)
+        _check(self._lib.gaca_gcq_history(self.handle, A.shape[0], _ptr(A), _ptr(b), dt_prev, dt_cur,
+                                          _ptr(wr), _ptr(wi), P(theta_prev.data_ptr()),
+                                          P(x.data_ptr()), P(W.data_ptr()), P(Y.data_ptr()), sp))
         return Y
 
     def close(self):

@@ -19,8 +19,9 @@ LIB = os.path.join(HERE, "libgaca.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-HOST_SRC = ["host.cpp", "lib.cpp"]
-HIP_SRC = ["near.hip", "far_aca.hip", "apply.hip", "apply_mfma.hip"]
+HOST_SRC = ["host.cpp", "lib.cpp", "gcq_host.cpp"]
+HIP_SRC = ["near.hip", "far_aca.hip", "apply.hip", "apply_mfma.hip", "gcq.hip", "far_recompress.hip",
+           "near_aca.hip"]
 COMMON = ["-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I" + CSRC,
           "-I" + os.path.join(ROOT, "include")]
 

@@ -274,6 +274,28 @@ __global__ void __launch_bounds__(256) apply_far_y_kernel(ApplyDev a, const XT *
     }
 }
 
+// SUM, compressed near blocks: T_l = sum_k f_l[k] X_k[tau] ([crank][n][nrhs]) per block;
+// one workgroup per near block (dense ones return at once).
+template <class XT>
+__global__ void __launch_bounds__(256) apply_near_t_kernel(ApplyDev a, const XT *Xp, XT *tn) {
+    const NearBlockDev nb = a.nblocks[blockIdx.x];
+    if (!nb.comp || nb.crank == 0) return;
+    const int L = a.L, nr = a.nrhs, n = nb.n;
+    const int64_t M = a.M;
+    const double2 *F = a.near_fib + nb.foff;
+    XT *T = tn + a.tn_off[blockIdx.x];
+    const int64_t tot = (int64_t)nb.crank * n * nr;
+    for (int64_t t = threadIdx.x; t < tot; t += blockDim.x) {
+        const int cc = (int)(t % nr);
+        const int64_t rest = t / nr;
+        const int j = (int)(rest % n), l = (int)(rest / n);
+        const XT *xp = Xp + (int64_t)(nb.c0 + j) * nr + cc;
+        XT acc = czero<XT>();
+        for (int k = 0; k < L; ++k) acc = cfma(cast_c<XT>(F[(int64_t)l * L + k]), xp[(int64_t)k * M * nr], acc);
+        T[t] = acc;
+    }
+}
+
 // SUM per row: Y[row] = sum over the leaf's near blocks of sum_k N_k[row] X_k + the rows
 // y_b of the covering far blocks.  One wave per row: a near block stores row ro as L n
 // contiguous entries ([m][L][n]), which the lanes read in order (entry t: frequency t / n,
@@ -282,7 +304,7 @@ __global__ void __launch_bounds__(256) apply_far_y_kernel(ApplyDev a, const XT *
 template <class NearT, class XT, int RC>
 __global__ void __launch_bounds__(256) apply_leaf_sum_kernel(ApplyDev a, const XT *Xp,
                                                              const XT *ybuf, const int64_t *y_off,
-                                                             XT *Yp) {
+                                                             XT *Yp, const XT *tn) {
     const int leaf = blockIdx.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = blockIdx.y * 4 + wave;
@@ -299,7 +321,23 @@ __global__ void __launch_bounds__(256) apply_leaf_sum_kernel(ApplyDev a, const X
 #pragma unroll
         for (int c = 0; c < RC; ++c) acc[c] = czero<XT>();
         for (int e = np0; e < np1; ++e) {
-            const NearBlockDev nb = a.nblocks[a.leaf_near_idx[e]];
+            const int ib = a.leaf_near_idx[e];
+            const NearBlockDev nb = a.nblocks[ib];
+            if (nb.comp) {
+                // row ro of sum_l H_l (T_l): entry t = (l, j), H_l row ro at l m n + ro n
+                const NearT *fc = reinterpret_cast<const NearT *>(a.near_faces) + nb.off;
+                const XT *T = tn + a.tn_off[ib] + cr;
+                const int n = nb.n, mn = nb.m * n, ro = row - nb.r0;
+                for (int t = lane; t < nb.crank * n; t += 64) {
+                    const int l = t / n, j = t - l * n;
+                    const XT hv = cast_c<XT>(fc[(int64_t)l * mn + (int64_t)ro * n + j]);
+                    const XT *tp = T + (int64_t)t * nr;
+#pragma unroll
+                    for (int c = 0; c < RC; ++c)
+                        if (cr + c < nr) acc[c] = cfma(hv, tp[c], acc[c]);
+                }
+                continue;
+            }
             const int n = nb.n, E = L * n;
             const NearT *base = nearv + nb.off + (int64_t)(row - nb.r0) * E;
             const XT *xb = Xp + (int64_t)nb.c0 * nr + cr;
@@ -378,6 +416,19 @@ __global__ void __launch_bounds__(256) apply_leaf_freq_kernel(ApplyDev a, const 
         for (int e = a.leaf_near_ptr[leaf]; e < a.leaf_near_ptr[leaf + 1]; ++e) {
             const NearBlockDev nb = a.nblocks[a.leaf_near_idx[e]];
             const int ro = row - nb.r0;
+            if (nb.comp) {
+                // sum_l f_l[k] H_l[ro] X_k[tau]
+                const NearT *fc = reinterpret_cast<const NearT *>(a.near_faces) + nb.off;
+                const XT *xk = Xp + ((int64_t)kf * M + nb.c0) * nr + cc;
+                const int mn = nb.m * nb.n;
+                for (int l = 0; l < nb.crank; ++l) {
+                    XT s = czero<XT>();
+                    const NearT *hr = fc + (int64_t)l * mn + (int64_t)ro * nb.n;
+                    for (int j = 0; j < nb.n; ++j) s = cfma(cast_c<XT>(hr[j]), xk[(int64_t)j * nr], s);
+                    acc = cfma(cast_c<XT>(a.near_fib[nb.foff + (int64_t)l * L + kf]), s, acc);
+                }
+                continue;
+            }
             const NearT *nrow = nearv + nb.off + ((int64_t)ro * L + kf) * nb.n;
             const XT *xk = Xp + ((int64_t)kf * M + nb.c0) * nr + cc;
             for (int j = 0; j < nb.n; ++j) acc = cfma(cast_c<XT>(nrow[j]), xk[(int64_t)j * nr], acc);
@@ -389,7 +440,7 @@ __global__ void __launch_bounds__(256) apply_leaf_freq_kernel(ApplyDev a, const 
 template <class FacT, class XT>
 static void apply_impl(const ApplyDev &a, int mode, const XT *X, XT *Y, XT *Xp, XT *Yp, XT *zbuf,
                        XT *tbuf, const int64_t *t_off, XT *ybuf, const int64_t *y_off,
-                       hipStream_t st) {
+                       hipStream_t st, XT *tnbuf) {
     const int64_t totx = (int64_t)a.L * a.M * a.nrhs;
     permute_x_kernel<XT><<<(unsigned)((totx + 255) / 256), 256, 0, st>>>(X, Xp, a.perm, a.L, a.M,
                                                                           a.nrhs);
@@ -398,13 +449,15 @@ static void apply_impl(const ApplyDev &a, int mode, const XT *X, XT *Y, XT *Xp, 
     const int nl = mode == 0 ? 1 : a.L;
     if (mode == 0) {
         if (a.nfar > 0) apply_far_y_kernel<FacT, XT><<<a.nfar, 256, 0, st>>>(a, zbuf, ybuf, y_off);
+        if (a.near_faces && a.nnear > 0)
+            apply_near_t_kernel<XT><<<a.nnear, 256, 0, st>>>(a, Xp, tnbuf);
         const dim3 grid(a.nleaf, (a.max_leaf_m + 3) / 4);
         if (a.nrhs == 1)
-            apply_leaf_sum_kernel<FacT, XT, 1><<<grid, 256, 0, st>>>(a, Xp, ybuf, y_off, Yp);
+            apply_leaf_sum_kernel<FacT, XT, 1><<<grid, 256, 0, st>>>(a, Xp, ybuf, y_off, Yp, tnbuf);
         else if (a.nrhs == 2)
-            apply_leaf_sum_kernel<FacT, XT, 2><<<grid, 256, 0, st>>>(a, Xp, ybuf, y_off, Yp);
+            apply_leaf_sum_kernel<FacT, XT, 2><<<grid, 256, 0, st>>>(a, Xp, ybuf, y_off, Yp, tnbuf);
         else
-            apply_leaf_sum_kernel<FacT, XT, 4><<<grid, 256, 0, st>>>(a, Xp, ybuf, y_off, Yp);
+            apply_leaf_sum_kernel<FacT, XT, 4><<<grid, 256, 0, st>>>(a, Xp, ybuf, y_off, Yp, tnbuf);
     } else {
         apply_leaf_freq_kernel<FacT, FacT, XT><<<dim3(a.nleaf, nl), 256, 0, st>>>(a, Xp, zbuf, Yp);
     }
@@ -415,10 +468,10 @@ static void apply_impl(const ApplyDev &a, int mode, const XT *X, XT *Y, XT *Xp, 
 
 void launch_apply(const ApplyDev &a, int mode, int x_fp32, const void *X, void *Y, void *Xp,
                   void *Yp, void *zbuf, void *tbuf, const int64_t *t_off, void *ybuf,
-                  const int64_t *y_off, hipStream_t st) {
+                  const int64_t *y_off, hipStream_t st, void *tnbuf) {
 #define GACA_APPLY(FT, XTT)                                                                  \
     apply_impl<FT, XTT>(a, mode, (const XTT *)X, (XTT *)Y, (XTT *)Xp, (XTT *)Yp, (XTT *)zbuf, \
-                        (XTT *)tbuf, t_off, (XTT *)ybuf, y_off, st)
+                        (XTT *)tbuf, t_off, (XTT *)ybuf, y_off, st, (XTT *)tnbuf)
     if (a.fac_fp32) {
         if (x_fp32) GACA_APPLY(float2, float2);
         else GACA_APPLY(float2, double2);

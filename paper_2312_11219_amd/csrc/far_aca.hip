@@ -1666,6 +1666,39 @@ __global__ void __launch_bounds__(256)
                     break;
                 }
             pidx = (int)min((int64_t)red.imin(pc), hi - 1);
+            if (P.pivot_index) {
+                // eq. (index): row i of the largest sum_q |U'(q, i)| (U' = U_bar Sigma after the
+                // recompression), then the largest entry of row i of H_l (same tie rule)
+                const FT *Uf = reinterpret_cast<const FT *>(bd.uw) + B.uw_off;
+                double best = 0.0;
+                for (int i = tid; i < m; i += NT) {
+                    double sa = 0.0;
+                    for (int q = 0; q < rho; ++q) sa += sqrt(cabs2(Uf[(int64_t)q * m + i]));
+                    best = fmax(best, sa * sa);
+                }
+                best = red.max(best);
+                int ic = 0x7fffffff;
+                for (int i = tid; i < m; i += NT) {
+                    double sa = 0.0;
+                    for (int q = 0; q < rho; ++q) sa += sqrt(cabs2(Uf[(int64_t)q * m + i]));
+                    if (sa * sa >= tie2 * best) {
+                        ic = i;
+                        break;
+                    }
+                }
+                ic = min(red.imin(ic), m - 1);
+                double rb = 0.0;
+                for (int j = tid; j < n; j += NT) rb = fmax(rb, cabs2(H[(int64_t)ic * n + j]));
+                rb = red.max(rb);
+                int jc = 0x7fffffff;
+                for (int j = tid; j < n; j += NT)
+                    if (cabs2(H[(int64_t)ic * n + j]) >= tie2 * rb) {
+                        jc = j;
+                        break;
+                    }
+                jc = min(red.imin(jc), n - 1);
+                pidx = ic * n + jc;
+            }
         } else {
             mxh = S.mxh;
             h2 = S.h2;

@@ -55,4 +55,8 @@ int32_t galerkin_tier(const HostMesh &mesh, int64_t i, int64_t j);
 constexpr int kNumTiers = 6;          // pair classes (collocation uses the first 4)
 constexpr int kGalerkinNTheta = 16;   // Gauss points per angular sector (coincident pairs)
 
+// gCQ integration points and weights (App. A); throws Error on invalid input.
+void gcq_contour(int stages, const double *rk_A, double dt_min, double dt_max, int n_q,
+                 double *s_re, double *s_im, double *w_re, double *w_im);
+
 }  // namespace gaca

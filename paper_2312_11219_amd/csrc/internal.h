@@ -117,6 +117,8 @@ struct AcaParams {
     int32_t kernel;            // 0 SLP, 1 DLP
     int32_t galerkin;          // 1 Galerkin
     int32_t zero_batch;        // several rows per pass in the large-face zero-row search
+    int32_t recompress;        // faces recompressed after their ACA
+    int32_t pivot_index;       // pivot by the eq. (index) row estimate
 };
 
 }  // namespace gaca

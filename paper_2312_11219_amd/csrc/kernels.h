@@ -12,8 +12,36 @@ struct NearPair {
 
 struct NearBlockDev {
     int32_t r0, m, c0, n;
-    int64_t off;     // offset (complex elements) of the [m][L][n] block
+    int64_t off;     // dense: offset (complex elements) of the [m][L][n] block;
+                     // compressed: offset of its crank faces (m n each) in the face arena
+    int32_t comp;    // 1: compressed along the frequencies (3D-ACA with dense faces)
+    int32_t crank;   // compressed: number of crosses (0 for a zero block)
+    int64_t foff;    // compressed: offset of its crank fibres (L each) in the fibre arena
 };
+
+// 3D-ACA of the near blocks with dense faces (csrc/near_aca.hip).
+constexpr int kNearAcaMaxMN = 1024;     // larger blocks stay dense
+constexpr int kNearAcaMaxFreq = 1024;
+struct NearAcaOut {
+    int32_t rank, capped, zero_faces, pad;
+};
+struct NearAcaArgs {
+    const NearBlockDev *blocks;   // the problem's near blocks (dense offsets)
+    int64_t b0;                   // first block of the chunk
+    int32_t L, rc, mnmax, pad;    // frequencies, crosses per block slot, face slot size
+    double eps, tie, delta;
+    double2 *fib;                 // chunk scratch fibres [nblk][rc][L]
+    NearAcaOut *out;              // [nblk]
+};
+void launch_near_aca(const NearAcaArgs &q, int nblk, const void *near, void *faces, int fp32,
+                     hipStream_t st);
+// dst: the operator's block table (comp, crank, off, foff set); face / fibre arenas of the
+// compressed blocks, dense arena of the others
+void launch_near_aca_pack(const NearAcaArgs &q, int nblk, const void *near, const void *faces,
+                          const NearBlockDev *dst, void *face_arena, double2 *fib_arena,
+                          void *dense_arena, int fp32, hipStream_t st);
+void launch_near_aca_expand(const NearBlockDev &D, int L, const void *face_arena,
+                            const double2 *fib_arena, double2 *out, int fp32, hipStream_t st);
 
 // Near field: every pair of one tier, all frequencies, FP64 compute, stored as double2
 // (out64) or float2 (out32).
@@ -100,6 +128,13 @@ void launch_far_aca(int path, int threads, const AcaParams &P, const FarBatchDev
 void launch_far_aca_small(int mnmax, int threads, const AcaParams &P, const FarBatchDev &bd,
                           const FarActive *act, int nact, hipStream_t st);
 void launch_far_expand(const FarBatchDev &bd, const FarActive *act, int64_t ntile, hipStream_t st);
+// Recompression of the current faces' factors (QR of both, SVD of the core, truncation at
+// eps_aca), faces of rank 2..kRecMaxRank; nslot workgroups with kRecSlot doubles2 each of ws.
+constexpr int kRecMaxRank = 128;
+constexpr int64_t kRecSlot = 6 * (int64_t)kRecMaxRank * kRecMaxRank;
+constexpr int kRecSlots = 256;   // concurrent faces (workgroups) of the recompression
+void launch_far_recompress(const AcaParams &P, const FarBatchDev &bd, const FarActive *act,
+                           int nact, double2 *ws, int nslot, hipStream_t st);
 // Gram rows of LDS-resident faces (kinds 0-2) into their single partial row (FarActive::tile0)
 void launch_far_gram_small(const FarBatchDev &bd, const FarActive *act, int nact, hipStream_t st);
 void launch_far_tail(int kernel, const GeoDev &g, const FreqDev &f, const AcaParams &P,
@@ -146,7 +181,26 @@ struct ApplyDev {
     const int32_t *leaf_far_ptr, *leaf_far_idx;
     const int32_t *leaf_near_ptr, *leaf_near_idx;
     const int64_t *z_off;         // [nfar] offset of the block's z (sum_rho x nrhs) or v
+    // near blocks compressed along the frequencies (NearBlockDev::comp): faces (near type,
+    // [crank][m][n] at off), fibres ([crank][L] at foff), and for the SUM apply the vectors
+    // T_l = sum_k f_l[k] X_k[tau] ([crank][n][nrhs] at tn_off[block])
+    const void *near_faces;
+    const double2 *near_fib;
+    const int64_t *tn_off;
 };
+// Runge-Kutta gCQ history step (csrc/gcq.hip).
+constexpr int kGcqMaxStages = 4;
+struct GcqDev {
+    int32_t L, m;                 // frequencies, stages
+    int64_t M;                    // spatial unknowns
+    double dt_prev, dt_cur;       // dt_{n-1}, dt_n
+    double A[kGcqMaxStages * kGcqMaxStages];   // Butcher matrix, row-major m x m
+    double g[kGcqMaxStages];      // b^T A^{-1}
+    const double *w_re, *w_im;    // quadrature weights omega_l (device, L each)
+};
+void launch_gcq_history(const GcqDev &q, const double *s_re, const double *s_im,
+                        const double2 *theta, double2 *x, double2 *W, hipStream_t st);
+
 // Allocation-free apply: fixed per-device scratch array in apply.hip.
 constexpr size_t kScratchBytes = 64ull << 20;   // 64 MiB per device
 constexpr int kMaxDevices = 64;
@@ -203,6 +257,6 @@ void launch_apply_leaf_mfma(const ApplyDev &a, const MfmaApplyDev &d, int row_ti
 // Workspace pointers are in elements of that type.
 void launch_apply(const ApplyDev &a, int mode, int x_fp32, const void *X, void *Y, void *Xp,
                   void *Yp, void *zbuf, void *tbuf, const int64_t *t_off, void *ybuf,
-                  const int64_t *y_off, hipStream_t st);
+                  const int64_t *y_off, hipStream_t st, void *tnbuf = nullptr);
 
 }  // namespace gaca

@@ -29,6 +29,10 @@ struct gaca_context {
     hipStream_t stream = nullptr;
     uint64_t limit = 0;       // 0: none
     std::atomic<uint64_t> in_use{0};   // builds of different problems may run in parallel threads
+    // problems made on the context; gaca_context_destroy only marks the context, which is
+    // deleted with its last problem (handles may then be destroyed in any order)
+    std::atomic<int> refs{0};
+    std::atomic<bool> destroy_requested{false};
     // far-field stream sets (four streams each) of destroyed problems, taken again by later
     // problems: the runtime spreads streams over a few hardware queues in creation order, so
     // fresh streams for every problem can land two face classes on one queue, where they
@@ -349,7 +353,7 @@ struct PinnedBuf {
 // Far-field working memory, kept by the problem across builds (it only grows).
 struct FarScratch {
     DevBuf blk, state, coef, hs, fs, usedk, uw, part, act, map_chunk, map_tile, status, copies,
-        gathers;
+        gathers, rec_ws;
     GrowBuf hpool, fgpool;
     PinnedBuf h_act, h_status, h_copies, h_gathers, h_blk, h_out;
 };
@@ -378,10 +382,31 @@ gaca_status guarded(F &&fn) {
 
 }  // namespace
 
+// A problem's reference to its context, declared first among the problem's members so that
+// it is released last (the other members account their device memory in the context).
+struct CtxRef {
+    gaca_context *c = nullptr;
+    ~CtxRef() {
+        if (c && --c->refs == 0 && c->destroy_requested) delete c;
+    }
+};
+
 struct gaca_problem {
+    CtxRef ctxref;
     gaca_context *ctx = nullptr;
+    // operators built on the problem; gaca_problem_destroy only marks the problem, which is
+    // deleted with its last operator
+    std::atomic<int> nops{0};
+    std::atomic<bool> destroy_requested{false};
+    void attach(gaca_context *c) {
+        ctx = c;
+        ctxref.c = c;
+        ctx->refs += 1;
+    }
     gaca_options opt{};
     std::string autotune_path;    // copy of opt.autotune_cache (opt points at it)
+    int tuned_tl = 0, tuned_ts = 0;   // face-ACA workgroup sizes chosen by the autotuner
+    int tune_state = 0;               // 0 none, 1 measured by this problem, 2 read from the cache
     gaca_scheme scheme = GACA_COLLOCATION_P0;
     bool synthetic = false;       // dense-tensor problem of gaca_compress_tensor
     HostMesh mesh;
@@ -423,16 +448,12 @@ struct gaca_problem {
     // near-field storage handed back by destroyed operators (slot kernel & 1)
     DevBuf near_spare[2];
     GrowBuf spare_arena[2], spare_fib[2];
-    ~gaca_problem() {
-        if (far_streams_ready) {
-            std::lock_guard<std::mutex> lk(ctx->stream_mu);
-            ctx->stream_pool.push_back({far_streams[0], far_streams[1], far_streams[2], far_streams[3]});
-        }
-    }
+    ~gaca_problem();
 };
 
 struct gaca_hmatrix {
     gaca_problem *p = nullptr;
+    ~gaca_hmatrix();
     std::unique_ptr<gaca_problem> owned_problem;   // synthetic problems
     int kernel = 0;
     gaca_precision prec = GACA_FP64;
@@ -440,6 +461,14 @@ struct gaca_hmatrix {
     int64_t nfar = 0;
     double eps_aca_used = 0.0;
     DevBuf d_near, d_meta, d_cmeta, d_cross_off, d_fib_off, d_far4;
+    DevBuf d_gcqw;                 // gCQ quadrature weights of the last history step
+    // near blocks compressed along the frequencies (option near_aca): the operator's own block
+    // table, the faces and fibres of the compressed blocks and the dense arena of the others
+    bool near_aca = false;
+    DevBuf d_nblk_own;
+    GrowBuf n_faces, n_fib, n_dense;
+    std::vector<NearBlockDev> nblk_host;
+    int64_t near_faces_elems = 0, near_fib_elems = 0, near_dense_elems = 0;
     GrowBuf d_arena, d_fib;   // factor and fibre arenas (grow in place)
     std::vector<FarMeta> meta;
     std::vector<CrossMeta> cmeta;
@@ -449,8 +478,20 @@ struct gaca_hmatrix {
     // apply workspace
     int32_t ws_nrhs = -1, ws_mode = -1, ws_dtype = -1, ws_cb = 1;
     DevBuf d_xp, d_yp, d_z, d_t, d_toff, d_zoff, d_yb, d_yoff;
+    DevBuf d_tn, d_tnoff;   // T of the compressed near blocks (option near_aca, SUM mode)
     DevBuf d_mz, d_mt, d_mtitems, d_mttile0, d_mtrows, d_mzitems, d_mzoff, d_msumrho;   // matrix-core apply
 };
+
+gaca_problem::~gaca_problem() {
+    if (far_streams_ready) {
+        std::lock_guard<std::mutex> lk(ctx->stream_mu);
+        ctx->stream_pool.push_back({far_streams[0], far_streams[1], far_streams[2], far_streams[3]});
+    }
+}
+
+gaca_hmatrix::~gaca_hmatrix() {
+    if (p && !owned_problem && --p->nops == 0 && p->destroy_requested) delete p;
+}
 
 // ---------------------------------------------------------------------------------------
 extern "C" {
@@ -494,7 +535,9 @@ gaca_status gaca_context_memory(const gaca_context *ctx, uint64_t *in_use) {
 }
 
 gaca_status gaca_context_destroy(gaca_context *ctx) {
-    delete ctx;
+    if (!ctx) return GACA_OK;
+    ctx->destroy_requested = true;
+    if (ctx->refs.load() == 0) delete ctx;
     return GACA_OK;
 }
 
@@ -708,7 +751,7 @@ gaca_status gaca_problem_create(gaca_context *ctx, const double *xyz, int64_t nv
         REQUIRE(L >= 1 && L <= 1024, "L must be in [1, 1024]");
         REQUIRE(scheme == GACA_COLLOCATION_P0 || scheme == GACA_GALERKIN_P0, "bad scheme");
         auto p = std::make_unique<gaca_problem>();
-        p->ctx = ctx;
+        p->attach(ctx);
         if (opt) p->opt = *opt;
         else options_default(&p->opt);
         REQUIRE(p->opt.eta > 0.0, "eta must be > 0");
@@ -726,6 +769,9 @@ gaca_status gaca_problem_create(gaca_context *ctx, const double *xyz, int64_t nv
         p->mesh.init(xyz, nv, tri, M);
         p->M = M;
         p->L = L;
+        REQUIRE(p->opt.near_aca == 0 || p->opt.near_aca == 1, "near_aca must be 0 or 1");
+        if (p->opt.near_aca && L > kNearAcaMaxFreq)
+            throw Error{GACA_ERR_UNSUPPORTED, "near_aca supports up to " + std::to_string(kNearAcaMaxFreq) + " frequencies"};
         p->s_re.assign(s_re, s_re + L);
         p->s_im.assign(s_im, s_im + L);
         for (int l = 0; l < L; ++l)
@@ -746,7 +792,9 @@ gaca_status gaca_problem_create(gaca_context *ctx, const double *xyz, int64_t nv
 }
 
 gaca_status gaca_problem_destroy(gaca_problem *p) {
-    delete p;
+    if (!p) return GACA_OK;
+    p->destroy_requested = true;
+    if (p->nops.load() == 0) delete p;
     return GACA_OK;
 }
 
@@ -940,6 +988,9 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
     P.rcap = rcap;
     P.kernel = fk;
     P.zero_batch = p->opt.zero_rows_batch != 0;
+    P.recompress = p->opt.recompress != 0;
+    P.pivot_index = p->opt.pivot_estimate != 0;
+    const bool recomp = P.recompress != 0;
 
     // block descriptors, launch classes and memory estimates
     std::vector<FarBlockDev> desc(ntot);
@@ -1062,6 +1113,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
     int iters_max = 0, n_launch = 0;
     double evals = 0.0;
 
+    if (recomp) ensure(ctx, W.rec_ws, (size_t)kRecSlots * kRecSlot * sizeof(double2));
     // batches of consecutive blocks whose estimate fits the memory free at their start; the
     // faces-per-block guess of the estimate follows what the previous batches used
     for (int64_t bnext = 0; bnext < ntot;) {
@@ -1245,7 +1297,8 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                 A.chunk0 = nchunk;
                 nchunk += (mn + kFarChunk - 1) / kFarChunk;
                 A.tile0 = ntile;
-                A.ntile = kd == 3 ? ((d.m + kFarTile - 1) / kFarTile) * ((d.n + kFarTile - 1) / kFarTile) : 0;
+                // with recompression every face is expanded again from its new factors
+                A.ntile = (kd == 3 || recomp) ? ((d.m + kFarTile - 1) / kFarTile) * ((d.n + kFarTile - 1) / kFarTile) : 0;
                 ntile += A.ntile;
                 cnt[kd]++;
                 ha[a] = A;
@@ -1253,8 +1306,9 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                 fl_face += (double)mn * (qpe * f_eval_of(d.kern) + 8.0 * ell_h[lb]);
             }
             // small faces: one partial row each (their Gram row), after the expand tiles
-            for (int a = cnt[3]; a < nact; ++a) ha[a].tile0 = ntile + (a - cnt[3]);
-            const int64_t nparts = ntile + (nact - cnt[3]);
+            if (!recomp)
+                for (int a = cnt[3]; a < nact; ++a) ha[a].tile0 = ntile + (a - cnt[3]);
+            const int64_t nparts = recomp ? ntile : ntile + (nact - cnt[3]);
             ensure(ctx, W.map_chunk, (size_t)std::max<int64_t>(nchunk, 1) * sizeof(int32_t));
             ensure(ctx, W.map_tile, (size_t)std::max<int64_t>(ntile, 1) * sizeof(int32_t));
             ensure(ctx, W.part, (size_t)std::max<int64_t>(nparts, 1) * PS * sizeof(double));
@@ -1266,7 +1320,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             if (copied) GACA_HIP_CHECK(hipEventRecord(ev[EV_C], ks[0]));
             const FarBatchDev bd = batch_dev();
             const FarActive *dact = W.act.as<FarActive>();
-            const int nlarge = cnt[3];
+            const int nlarge = recomp ? nact : cnt[3];
             // act is ordered kind 3, 2, 1, 0
             const int first[4] = {cnt[3] + cnt[2] + cnt[1], cnt[3] + cnt[2], cnt[3], 0};
             launch_far_map(bd, dact, nact, nlarge, s0);
@@ -1314,13 +1368,19 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                                          cnt[k], ks[k]);
                     ++nl;
                 }
-                launch_far_gram_small(bd, dact + first[k], cnt[k], ks[k]);
-                ++nl;
+                if (!recomp) {
+                    launch_far_gram_small(bd, dact + first[k], cnt[k], ks[k]);
+                    ++nl;
+                }
             }
             GACA_HIP_CHECK(hipGetLastError());
             for (int k = 0; k < 4; ++k) GACA_HIP_CHECK(hipEventRecord(ev[EV_K0 + k], ks[k]));
             for (int k = 0; k < 3; ++k) GACA_HIP_CHECK(hipStreamWaitEvent(s0, ev[EV_K0 + k], 0));
             GACA_HIP_CHECK(hipEventRecord(ev[EV_J], s0));
+            if (recomp) {
+                launch_far_recompress(P, bd, dact, nact, W.rec_ws.as<double2>(), kRecSlots, s0);
+                ++n_launch;
+            }
             launch_far_expand(bd, dact, ntile, s0);
             GACA_HIP_CHECK(hipEventRecord(ev[EV_X], s0));
             launch_far_tail(fk, p->g, p->f, P, bd, dact, nact, nlarge, s0);
@@ -1474,14 +1534,22 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             }
         }
     }
-    // large pools are not kept for the next build (they hold no result)
+    // the pools hold no result; large ones are given back when memory is short
     {
         size_t held = W.hpool.bytes + W.fgpool.bytes + W.uw.bytes + W.part.bytes;
-        if (total_b > 0 && held > total_b / 8) {
+        size_t fb_end = 0, tb_end = 0;
+        if (hipMemGetInfo(&fb_end, &tb_end) != hipSuccess) {
+            (void)hipGetLastError();
+            fb_end = 0;
+        }
+        // kept (mapped) for the problem's next build while they take at most half of the
+        // device and leave a quarter of it free: remapping tens of GB costs seconds
+        if (total_b > 0 && (held > total_b / 2 || fb_end < total_b / 4)) {
             W.hpool.release();
             W.fgpool.release();
             W.uw.release();
             W.part.release();
+            W.rec_ws.release();
         }
     }
     GACA_HIP_CHECK(hipEventRecord(ev[EV_END], s0));
@@ -1545,6 +1613,8 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
         st.n_far_launches = n_launch;
         st.far_iters = iters_max;
         st.threads_large_used = p->opt.threads_large > 0 ? p->opt.threads_large : 512;
+        st.threads_small_used = p->opt.threads_small;
+        st.autotune_state = p->tune_state;
         st.far_kernel_evals = evals;
         st.far_flops = 0.0;
         for (int k = 0; k < 4; ++k) {
@@ -1618,6 +1688,21 @@ static void fill_stats(gaca_hmatrix *h) {
     const double eb = h->prec == GACA_FP64 ? 16.0 : 8.0;
     s.bytes_far = (uint64_t)(far_elems * eb + fib_elems * 16.0);
     s.bytes_near = (uint64_t)((double)p->near_elems * eb);
+    s.n_near_compressed = 0;
+    s.near_rank_mean = 0.0;
+    s.near_rank_max = 0;
+    if (h->near_aca) {
+        s.bytes_near = (uint64_t)((double)(h->near_faces_elems + h->near_dense_elems) * eb +
+                                  (double)h->near_fib_elems * 16.0);
+        double rs = 0.0;
+        for (const auto &d : h->nblk_host)
+            if (d.comp) {
+                ++s.n_near_compressed;
+                rs += d.crank;
+                s.near_rank_max = std::max(s.near_rank_max, d.crank);
+            }
+        s.near_rank_mean = s.n_near_compressed ? rs / s.n_near_compressed : 0.0;
+    }
     s.dense_bytes = (double)p->M * (double)p->M * L * eb;
     s.compression = (s.bytes_far + s.bytes_near) / std::max(1.0, s.dense_bytes);
     // with conjugate-pair frequencies the near kernels evaluate L_eval of the L frequencies
@@ -1629,6 +1714,87 @@ static void fill_stats(gaca_hmatrix *h) {
 // Builds the operators `kernels` (one, or the collocation single and double layer) of p:
 // near fields on the context stream, far fields in one joint run.  Returns whether a rank
 // cap was hit.
+// 3D-ACA of the near blocks with dense faces (option near_aca), after the operator's build:
+// chunks of blocks are compressed into scratch, the ranks read back, and each block's result
+// packed into the operator's arenas (compressed: faces + fibres; otherwise: its dense
+// [m][L][n] entries in a compact dense arena).  A block stays dense if its ACA hit the cap
+// or rank (m n + L) >= m n L.  The dense near field of the build is then released.
+static void near_compress(gaca_hmatrix *h) {
+    gaca_problem *p = h->p;
+    gaca_context *ctx = p->ctx;
+    const hipStream_t st = ctx->stream;
+    const int L = p->L;
+    const bool fp32 = h->prec == GACA_MIXED;
+    const size_t es = fp32 ? sizeof(float2) : sizeof(double2);
+    const int64_t nb = (int64_t)p->nblocks.size();
+    int mnmax = 1;
+    for (const auto &b : p->nblocks) mnmax = std::max(mnmax, std::min(b.m * b.n, kNearAcaMaxMN));
+    const int rc = std::max(1, std::min(L, 64));
+    const double per = (double)rc * ((double)mnmax * es + L * 16.0) + 16.0;
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nb, (int64_t)((4.0 * (1 << 30)) / per)));
+    DevBuf faces, fib, out, dst;
+    faces.alloc(ctx, (size_t)chunk * rc * mnmax * es);
+    fib.alloc(ctx, (size_t)chunk * rc * L * sizeof(double2));
+    out.alloc(ctx, (size_t)chunk * sizeof(NearAcaOut));
+    dst.alloc(ctx, (size_t)std::max<int64_t>(nb, 1) * sizeof(NearBlockDev));
+    std::vector<NearAcaOut> res((size_t)chunk);
+    h->nblk_host = p->nblocks;
+    int64_t fu = 0, gu = 0, du = 0;   // used elements of the face, fibre, dense arenas
+    NearAcaArgs q{};
+    q.blocks = p->d_nblocks.as<NearBlockDev>();
+    q.L = L;
+    q.rc = rc;
+    q.mnmax = mnmax;
+    q.eps = p->opt.eps3d;
+    q.tie = fp32 ? std::max(p->opt.tie, 1e-4) : p->opt.tie;
+    q.delta = fp32 ? std::max(p->opt.delta_zero, 1e-6) : p->opt.delta_zero;
+    q.fib = fib.as<double2>();
+    q.out = out.as<NearAcaOut>();
+    for (int64_t b0 = 0; b0 < nb; b0 += chunk) {
+        const int n = (int)std::min<int64_t>(chunk, nb - b0);
+        q.b0 = b0;
+        launch_near_aca(q, n, h->d_near.ptr, faces.ptr, fp32 ? 1 : 0, st);
+        GACA_HIP_CHECK(hipGetLastError());
+        GACA_HIP_CHECK(hipMemcpyAsync(res.data(), out.ptr, n * sizeof(NearAcaOut), hipMemcpyDeviceToHost, st));
+        GACA_HIP_CHECK(hipStreamSynchronize(st));
+        const int64_t fu0 = fu, gu0 = gu, du0 = du;
+        for (int t = 0; t < n; ++t) {
+            NearBlockDev &d = h->nblk_host[b0 + t];
+            const int64_t mn = (int64_t)d.m * d.n;
+            const NearAcaOut &r = res[t];
+            if (!r.capped && mn <= kNearAcaMaxMN && (int64_t)r.rank * (mn + L) < mn * L) {
+                d.comp = 1;
+                d.crank = r.rank;
+                d.off = fu;
+                d.foff = gu;
+                fu += (int64_t)r.rank * mn;
+                gu += (int64_t)r.rank * L;
+            } else {
+                d.comp = 0;
+                d.crank = 0;
+                d.off = du;
+                d.foff = 0;
+                du += mn * L;
+            }
+        }
+        grow_keep(ctx, h->n_faces, (size_t)std::max<int64_t>(fu, 1) * es, (size_t)fu0 * es, st);
+        grow_keep(ctx, h->n_fib, (size_t)std::max<int64_t>(gu, 1) * sizeof(double2), (size_t)gu0 * sizeof(double2), st);
+        grow_keep(ctx, h->n_dense, (size_t)std::max<int64_t>(du, 1) * es, (size_t)du0 * es, st);
+        GACA_HIP_CHECK(hipMemcpyAsync(dst.as<NearBlockDev>() + b0, h->nblk_host.data() + b0,
+                                      n * sizeof(NearBlockDev), hipMemcpyHostToDevice, st));
+        launch_near_aca_pack(q, n, h->d_near.ptr, faces.ptr, dst.as<NearBlockDev>(), h->n_faces.ptr,
+                             h->n_fib.as<double2>(), h->n_dense.ptr, fp32 ? 1 : 0, st);
+        GACA_HIP_CHECK(hipGetLastError());
+        GACA_HIP_CHECK(hipStreamSynchronize(st));   // the host table of the chunk is reused
+    }
+    h->d_nblk_own.swap(dst);
+    h->near_faces_elems = fu;
+    h->near_fib_elems = gu;
+    h->near_dense_elems = du;
+    h->near_aca = true;
+    h->d_near.release();
+}
+
 static void prepare_leaves(gaca_hmatrix *h);
 
 static bool build_ops(gaca_problem *p, const std::vector<gaca_kernel> &kernels,
@@ -1650,6 +1816,7 @@ static bool build_ops(gaca_problem *p, const std::vector<gaca_kernel> &kernels,
     for (gaca_kernel kernel : kernels) {
         auto h = std::make_unique<gaca_hmatrix>();
         h->p = p;
+        p->nops += 1;
         h->kernel = p->kid(kernel);
         h->prec = p->opt.precision;
         h->rcap = std::max(1, std::min({p->L, p->opt.max_rank3d > 0 ? p->opt.max_rank3d : p->L, 256}));
@@ -1726,9 +1893,120 @@ static bool build_ops(gaca_problem *p, const std::vector<gaca_kernel> &kernels,
         h->st.ms_total = ms_total;
         capped = capped || h->st.n_capped > 0;
     }
+    if (p->opt.near_aca)
+        for (int w = 0; w < nh; ++w) {
+            const auto t0 = std::chrono::steady_clock::now();
+            near_compress(H[w]);
+            fill_stats(H[w]);
+            H[w]->st.ms_near_aca =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
     // leaf tables of the apply (per problem, once): built here so that no apply allocates them
     prepare_leaves(out[0].get());
     return capped;
+}
+
+// ---------------------------------------------------------------------------------------
+// Autotuner of the face-ACA workgroup sizes (threads_large, threads_small): with an
+// autotune_cache file and threads_large = 0, the first build of a problem looks its
+// workload up in the file; if absent, it builds the operators once per candidate, keeps the
+// one whose face-ACA phase (device time of the aca launches) was shortest, returns that
+// build and appends the choice to the file.  Later builds of the problem reuse the choice.
+}  // extern "C"
+
+namespace {
+const int kTuneCand[][2] = {{512, 128}, {1024, 128}, {512, 64}, {256, 128}};
+
+std::string tune_key(const gaca_problem *p, const std::vector<gaca_kernel> &kernels) {
+    char buf[512];
+    std::string ops;
+    for (gaca_kernel k : kernels) ops += k == GACA_SLP ? "s" : "d";
+    std::snprintf(buf, sizeof(buf), "v1|M=%lld|L=%d|scheme=%d|ops=%s|prec=%d|leaf=%d|eta=%.6g|eps=%.6g|"
+                  "epsaca=%.6g|nfar=%lld|cu=%d",
+                  (long long)p->M, p->L, (int)p->scheme, ops.c_str(), (int)p->opt.precision,
+                  p->opt.leaf_size, p->opt.eta, p->opt.eps3d, p->opt.eps_aca,
+                  (long long)p->part.far.size(), p->ctx->n_cu);
+    return buf;
+}
+
+bool tune_lookup(const std::string &path, const std::string &key, int &tl, int &ts) {
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        char k[900];
+        int a = 0, b = 0;
+        if (std::sscanf(line, "%899s %d %d", k, &a, &b) == 3 && key == k && (a == 256 || a == 512 || a == 1024) &&
+            (b == 64 || b == 128)) {
+            tl = a;
+            ts = b;
+            found = true;   // the last entry for the key wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+}  // namespace
+
+extern "C" {
+
+static bool build_ops(gaca_problem *p, const std::vector<gaca_kernel> &kernels,
+                      std::vector<std::unique_ptr<gaca_hmatrix>> &out);
+
+static bool build_tuned(gaca_problem *p, const std::vector<gaca_kernel> &kernels,
+                        std::vector<std::unique_ptr<gaca_hmatrix>> &out) {
+    const int tl0 = p->opt.threads_large, ts0 = p->opt.threads_small;
+    if (!p->opt.autotune_cache || tl0 != 0) return build_ops(p, kernels, out);
+    struct Restore {
+        gaca_problem *p;
+        int tl, ts;
+        ~Restore() {
+            p->opt.threads_large = tl;
+            p->opt.threads_small = ts;
+        }
+    } restore{p, tl0, ts0};
+    if (!p->tuned_tl) {
+        int tl = 0, ts = 0;
+        if (tune_lookup(p->autotune_path, tune_key(p, kernels), tl, ts)) {
+            p->tuned_tl = tl;
+            p->tuned_ts = ts;
+            p->tune_state = 2;
+        }
+    }
+    if (p->tuned_tl) {
+        p->opt.threads_large = p->tuned_tl;
+        p->opt.threads_small = p->tuned_ts;
+        return build_ops(p, kernels, out);
+    }
+    double best = 1e300;
+    bool best_capped = false;
+    std::vector<std::unique_ptr<gaca_hmatrix>> best_hs;
+    for (const auto &c : kTuneCand) {
+        p->opt.threads_large = c[0];
+        p->opt.threads_small = c[1];
+        std::vector<std::unique_ptr<gaca_hmatrix>> hs;
+        const bool capped = build_ops(p, kernels, hs);
+        const double t = hs[0]->st.ms_far_phase[1];
+        if (t < best) {
+            for (auto &h : best_hs) gaca_hmatrix_destroy(h.release());
+            best_hs = std::move(hs);
+            best = t;
+            best_capped = capped;
+            p->tuned_tl = c[0];
+            p->tuned_ts = c[1];
+        } else {
+            for (auto &h : hs) gaca_hmatrix_destroy(h.release());
+        }
+    }
+    p->tune_state = 1;
+    for (auto &h : best_hs) h->st.autotune_state = 1;
+    if (FILE *f = std::fopen(p->autotune_path.c_str(), "a")) {
+        std::fprintf(f, "%s %d %d\n", tune_key(p, kernels).c_str(), p->tuned_tl, p->tuned_ts);
+        std::fclose(f);
+    }
+    out = std::move(best_hs);
+    return best_capped;
 }
 
 gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out) {
@@ -1736,7 +2014,7 @@ gaca_status gaca_build(gaca_problem *p, gaca_kernel kernel, gaca_hmatrix **out) 
     gaca_status rc = guarded([&] {
         REQUIRE(p && out, "null argument");
         std::vector<std::unique_ptr<gaca_hmatrix>> hs;
-        capped = build_ops(p, {kernel}, hs);
+        capped = build_tuned(p, {kernel}, hs);
         *out = hs[0].release();
     });
     if (rc == GACA_OK && capped) {
@@ -1753,7 +2031,7 @@ gaca_status gaca_build_both(gaca_problem *p, gaca_hmatrix **slp_out, gaca_hmatri
         if (p->scheme == GACA_GALERKIN_P0)
             throw Error{GACA_ERR_UNSUPPORTED, "Galerkin is available for the single layer only"};
         std::vector<std::unique_ptr<gaca_hmatrix>> hs;
-        capped = build_ops(p, {GACA_SLP, GACA_DLP}, hs);
+        capped = build_tuned(p, {GACA_SLP, GACA_DLP}, hs);
         *slp_out = hs[0].release();
         *dlp_out = hs[1].release();
     });
@@ -1897,8 +2175,30 @@ gaca_status gaca_hmatrix_near_export(const gaca_hmatrix *h, int64_t idx, double 
     return guarded([&] {
         REQUIRE(h && out, "null argument");
         REQUIRE(idx >= 0 && idx < (int64_t)h->p->nblocks.size(), "near block index out of range");
-        const NearBlockDev &nb = h->p->nblocks[idx];
+        const NearBlockDev &nb = h->near_aca ? h->nblk_host[idx] : h->p->nblocks[idx];
         const size_t cnt = (size_t)nb.m * nb.n * h->p->L;
+        if (h->near_aca) {
+            gaca_context *ctx = h->p->ctx;
+            DevBuf tmp;
+            tmp.alloc(ctx, cnt * sizeof(double2));
+            const bool fp32 = h->prec == GACA_MIXED;
+            if (nb.comp) {
+                launch_near_aca_expand(nb, h->p->L, h->n_faces.ptr, h->n_fib.as<double2>(),
+                                       tmp.as<double2>(), fp32 ? 1 : 0, ctx->stream);
+                GACA_HIP_CHECK(hipGetLastError());
+                GACA_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+                GACA_HIP_CHECK(hipMemcpy(out, tmp.ptr, cnt * sizeof(double2), hipMemcpyDeviceToHost));
+            } else if (!fp32) {
+                GACA_HIP_CHECK(hipMemcpy(out, h->n_dense.as<double2>() + nb.off, cnt * sizeof(double2),
+                                         hipMemcpyDeviceToHost));
+            } else {
+                std::vector<float> t32(2 * cnt);
+                GACA_HIP_CHECK(hipMemcpy(t32.data(), h->n_dense.as<float2>() + nb.off, cnt * sizeof(float2),
+                                         hipMemcpyDeviceToHost));
+                for (size_t t = 0; t < 2 * cnt; ++t) out[t] = t32[t];
+            }
+            return;
+        }
         if (h->prec == GACA_FP64) {
             GACA_HIP_CHECK(hipMemcpy(out, h->d_near.as<double2>() + nb.off, cnt * sizeof(double2),
                                      hipMemcpyDeviceToHost));
@@ -1908,6 +2208,15 @@ gaca_status gaca_hmatrix_near_export(const gaca_hmatrix *h, int64_t idx, double 
                                      hipMemcpyDeviceToHost));
             for (size_t t = 0; t < 2 * cnt; ++t) out[t] = tmp[t];
         }
+    });
+}
+
+gaca_status gaca_hmatrix_near_ranks(const gaca_hmatrix *h, int32_t *ranks) {
+    return guarded([&] {
+        REQUIRE(h && ranks, "null argument");
+        const size_t nb = h->p->nblocks.size();
+        for (size_t b = 0; b < nb; ++b)
+            ranks[b] = h->near_aca && h->nblk_host[b].comp ? h->nblk_host[b].crank : -1;
     });
 }
 
@@ -1996,6 +2305,19 @@ static void alloc_apply_workspace(gaca_hmatrix *h, gaca_apply_mode mode, int32_t
             take(h->d_t, 2, (size_t)std::max<int64_t>(tacc, 1) * xs);
             take(h->d_xp, 3, (size_t)L * M * nrhs * xs);
             take(h->d_yp, 4, (size_t)nl * M * nrhs * xs);
+            if (h->near_aca) {
+                // T_l of each compressed near block: [crank][n][nrhs]
+                std::vector<int64_t> tnoff(std::max<size_t>(h->nblk_host.size(), 1), 0);
+                int64_t tn = 0;
+                for (size_t b = 0; b < h->nblk_host.size(); ++b) {
+                    tnoff[b] = tn;
+                    const NearBlockDev &d = h->nblk_host[b];
+                    if (d.comp && mode == GACA_APPLY_SUM) tn += (int64_t)d.crank * d.n * nrhs;
+                }
+                h->d_tnoff.upload(ctx, tnoff);
+                h->d_tn.release();
+                h->d_tn.alloc(ctx, (size_t)std::max<int64_t>(tn, 1) * xs);
+            }
             h->ws_nrhs = nrhs;
             h->ws_mode = (int)mode;
             h->ws_dtype = (int)dtype;
@@ -2006,6 +2328,7 @@ static void alloc_apply_workspace(gaca_hmatrix *h, gaca_apply_mode mode, int32_t
 // The matrix-core apply stages the U rows of one far block by their sum of face ranks and
 // the X rows of one near block by its columns.
 static bool mfma_supported(const gaca_hmatrix *h) {
+    if (h->near_aca) return false;   // compressed near blocks: the VALU apply
     for (int64_t b = 0; b < h->nfar; ++b)
         if (h->meta[b].sum_rho > kMfmaMaxSumRho) return false;
     for (const auto &nb : h->p->nblocks)
@@ -2221,9 +2544,19 @@ static ApplyDev apply_view(gaca_hmatrix *h, int32_t nrhs) {
     a.fac_fp32 = h->prec == GACA_MIXED ? 1 : 0;
     a.fib_off = h->d_fib_off.as<int64_t>();
     a.fib_arena = h->d_fib.as<double2>();
-    a.nblocks = p->d_nblocks.as<NearBlockDev>();
-    a.near64 = h->prec == GACA_MIXED ? nullptr : h->d_near.as<double2>();
-    a.near32 = h->prec == GACA_MIXED ? h->d_near.as<float2>() : nullptr;
+    if (h->near_aca) {
+        // compressed near blocks: the operator's own block table; dense ones in the compact arena
+        a.nblocks = h->d_nblk_own.as<NearBlockDev>();
+        a.near64 = h->prec == GACA_MIXED ? nullptr : h->n_dense.as<double2>();
+        a.near32 = h->prec == GACA_MIXED ? h->n_dense.as<float2>() : nullptr;
+        a.near_faces = h->n_faces.ptr;
+        a.near_fib = h->n_fib.as<double2>();
+        a.tn_off = h->d_tnoff.as<int64_t>();
+    } else {
+        a.nblocks = p->d_nblocks.as<NearBlockDev>();
+        a.near64 = h->prec == GACA_MIXED ? nullptr : h->d_near.as<double2>();
+        a.near32 = h->prec == GACA_MIXED ? h->d_near.as<float2>() : nullptr;
+    }
     a.nleaf = (int32_t)p->leaf_r0.size();
     a.max_leaf_m = 1;
     for (int32_t lm : p->leaf_m) a.max_leaf_m = std::max(a.max_leaf_m, lm);
@@ -2266,7 +2599,7 @@ gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, cons
         }
         launch_apply(a, (int)mode, dtype == GACA_C64 ? 1 : 0, X, Y, h->d_xp.ptr, h->d_yp.ptr,
                      h->d_z.ptr, h->d_t.ptr, h->d_toff.as<int64_t>(), h->d_yb.ptr,
-                     h->d_yoff.as<int64_t>(), st);
+                     h->d_yoff.as<int64_t>(), st, h->d_tn.ptr);
         GACA_HIP_CHECK(hipGetLastError());
     });
 }
@@ -2282,6 +2615,8 @@ gaca_status gaca_apply_noalloc(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nr
         gaca_problem *p = h->p;
         gaca_context *ctx = p->ctx;
         if (!p->leaf_ready) throw Error{GACA_ERR_STATE, "leaf tables missing (built with the operator)"};
+        if (h->near_aca)
+            throw Error{GACA_ERR_UNSUPPORTED, "the allocation-free apply takes dense near fields (near_aca = 0)"};
         void *base = scratch_address(ctx->device);
         if (!base) throw Error{GACA_ERR_STATE, "scratch array not set up on this device"};
         hipStream_t st = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : ctx->stream;
@@ -2323,6 +2658,88 @@ gaca_status gaca_apply_noalloc(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nr
                      sb + o_t, toff, sb + o_yb, yoff, st);
         GACA_HIP_CHECK(hipGetLastError());
     });
+}
+
+// ---------------------------------------------------------------------------------------
+// gCQ (Sec. 3 temporal discretisation, App. A)
+gaca_status gaca_gcq_contour(int32_t stages, const double *rk_A, double dt_min, double dt_max,
+                             int32_t n_q, double *s_re, double *s_im, double *w_re,
+                             double *w_im) {
+    return guarded([&] {
+        REQUIRE(rk_A && s_re && s_im && w_re && w_im, "null argument");
+        REQUIRE(stages >= 1 && stages <= kGcqMaxStages, "stages must be in [1, 4]");
+        REQUIRE(n_q >= 1 && n_q <= 1 << 20, "n_q out of range");
+        REQUIRE(std::isfinite(dt_min) && std::isfinite(dt_max) && dt_min > 0.0 && dt_max >= dt_min,
+                "need 0 < dt_min <= dt_max");
+        for (int i = 0; i < stages * stages; ++i) REQUIRE(std::isfinite(rk_A[i]), "non-finite Butcher matrix");
+        gcq_contour(stages, rk_A, dt_min, dt_max, n_q, s_re, s_im, w_re, w_im);
+    });
+}
+
+gaca_status gaca_gcq_history(gaca_hmatrix *h, int32_t stages, const double *rk_A,
+                             const double *rk_b, double dt_prev, double dt_cur,
+                             const double *w_re, const double *w_im, const void *theta_prev,
+                             void *x, void *W, void *Y, void *hip_stream) {
+    const gaca_status rc = guarded([&] {
+        REQUIRE(h && rk_A && rk_b && w_re && w_im && theta_prev && x && W && Y, "null argument");
+        REQUIRE(!h->p->synthetic, "the history step needs a mesh problem");
+        REQUIRE(stages >= 1 && stages <= kGcqMaxStages, "stages must be in [1, 4]");
+        REQUIRE(std::isfinite(dt_prev) && std::isfinite(dt_cur) && dt_prev > 0.0 && dt_cur > 0.0,
+                "step sizes must be positive");
+        gaca_problem *p = h->p;
+        gaca_context *ctx = p->ctx;
+        hipStream_t st = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : ctx->stream;
+        const int m = stages;
+        GcqDev q{};
+        q.L = p->L;
+        q.m = m;
+        q.M = p->M;
+        q.dt_prev = dt_prev;
+        q.dt_cur = dt_cur;
+        for (int i = 0; i < m * m; ++i) q.A[i] = rk_A[i];
+        // g = b^T A^{-1}: solve A^T g = b (Gaussian elimination, partial pivoting)
+        double T[kGcqMaxStages][kGcqMaxStages + 1];
+        for (int i = 0; i < m; ++i) {
+            for (int j = 0; j < m; ++j) T[i][j] = rk_A[j * m + i];
+            T[i][m] = rk_b[i];
+        }
+        for (int c = 0; c < m; ++c) {
+            int pv = c;
+            for (int r = c + 1; r < m; ++r)
+                if (std::fabs(T[r][c]) > std::fabs(T[pv][c])) pv = r;
+            REQUIRE(std::fabs(T[pv][c]) > 0.0, "the Butcher matrix is singular");
+            for (int j = 0; j <= m; ++j) std::swap(T[c][j], T[pv][j]);
+            for (int r = c + 1; r < m; ++r) {
+                const double f = T[r][c] / T[c][c];
+                for (int j = c; j <= m; ++j) T[r][j] -= f * T[c][j];
+            }
+        }
+        for (int c = m - 1; c >= 0; --c) {
+            double v = T[c][m];
+            for (int j = c + 1; j < m; ++j) v -= T[c][j] * q.g[j];
+            q.g[c] = v / T[c][c];
+        }
+        // quadrature weights on the device (kept by the operator, rewritten per call)
+        std::vector<double> wv(2 * (size_t)p->L);
+        for (int l = 0; l < p->L; ++l) {
+            REQUIRE(std::isfinite(w_re[l]) && std::isfinite(w_im[l]), "non-finite weight");
+            wv[l] = w_re[l];
+            wv[p->L + l] = w_im[l];
+        }
+        if (!h->d_gcqw.ptr) h->d_gcqw.alloc(ctx, wv.size() * sizeof(double));
+        GACA_HIP_CHECK(hipMemcpyAsync(h->d_gcqw.ptr, wv.data(), wv.size() * sizeof(double),
+                                      hipMemcpyHostToDevice, st));
+        q.w_re = h->d_gcqw.as<double>();
+        q.w_im = q.w_re + p->L;
+        launch_gcq_history(q, p->f.re, p->f.im, static_cast<const double2 *>(theta_prev),
+                           static_cast<double2 *>(x), static_cast<double2 *>(W), st);
+        GACA_HIP_CHECK(hipGetLastError());
+        // the host copy of the weights must outlive the asynchronous copy
+        GACA_HIP_CHECK(hipStreamSynchronize(st));
+    });
+    if (rc != GACA_OK) return rc;
+    // history term sum_l V(s_l) W_l: the reordered product with the stages as right-hand sides
+    return gaca_apply(h, GACA_APPLY_SUM, stages, W, Y, GACA_C128, hip_stream);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -2418,7 +2835,7 @@ gaca_status gaca_compress_tensor(gaca_context *ctx, const void *dev_tensor, int6
         REQUIRE(m >= 1 && n >= 1 && m <= 8192 && n <= 8192, "tensor sides must be in [1, 8192]");
         REQUIRE(L >= 1 && L <= 1024, "L must be in [1, 1024]");
         auto p = std::make_unique<gaca_problem>();
-        p->ctx = ctx;
+        p->attach(ctx);
         if (opt) p->opt = *opt;
         else options_default(&p->opt);
         p->opt.autotune_cache = nullptr;
