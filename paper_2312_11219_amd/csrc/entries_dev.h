@@ -10,6 +10,7 @@
 // where q = |x_i - x_j| / h_j.  The double layer self entry is 0.
 #pragma once
 
+#include "fastmath_dev.h"
 #include "internal.h"
 
 namespace gaca {
@@ -23,9 +24,9 @@ constexpr double kInvFourPi = 0.079577471545947667884441881686257181;  // 1 / (4
 template <int KERNEL>
 __device__ __forceinline__ void kacc(double r, double ir, double sre, double sim, double w,
                                      double &ar, double &ai) {
-    double mag = exp(-sre * r);
+    double mag = fm::exp(-sre * r);
     double sn, cs;
-    sincos(sim * r, &sn, &cs);
+    fm::sincos(sim * r, &sn, &cs);
     double er = mag * cs, ei = -mag * sn;
     if (KERNEL == 0) {
         double c = w * kInvFourPi * ir;

@@ -108,9 +108,9 @@ __device__ __forceinline__ double2 fibre_entry(const GeoDev &g, const FreqDev &f
 // 1 / c_k = exp(s_k d0) (mixed scaling), FP64.
 __device__ __forceinline__ double2 inv_scale(const FreqDev &f, const FarBlockDev &B, int k) {
     const double d0 = (double)B.d0f;
-    const double mag = exp(f.re[k] * d0);
+    const double mag = fm::exp(f.re[k] * d0);
     double sn, cs;
-    sincos(f.im[k] * d0, &sn, &cs);
+    fm::sincos(f.im[k] * d0, &sn, &cs);
     return make_double2(mag * cs, mag * sn);
 }
 

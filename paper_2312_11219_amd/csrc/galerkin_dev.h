@@ -188,9 +188,9 @@ __device__ __forceinline__ double2 gal_psi(double tr, double ti) {
     const double ir = tr / d, ii = -ti / d;                      // 1/t
     const double i2r = ir * ir - ii * ii, i2i = 2.0 * ir * ii;   // 1/t^2
     const double i3r = i2r * ir - i2i * ii, i3i = i2r * ii + i2i * ir;
-    const double m = exp(-tr);
+    const double m = fm::exp(-tr);
     double sn, cs;
-    sincos(ti, &sn, &cs);
+    fm::sincos(ti, &sn, &cs);
     const double er = m * cs, ei = -m * sn;                      // e^{-t}
     const double qr = er * i3r - ei * i3i, qi = er * i3i + ei * i3r;
     return make_double2(ir - 2.0 * i2r + 2.0 * i3r - 2.0 * qr, ii - 2.0 * i2i + 2.0 * i3i - 2.0 * qi);
@@ -302,9 +302,9 @@ __device__ __forceinline__ double2 ss_phi(double tr, double ti) {
         }
         return make_double2(cr, ci);
     }
-    const double m = exp(-tr);
+    const double m = fm::exp(-tr);
     double sn, cs;
-    sincos(ti, &sn, &cs);
+    fm::sincos(ti, &sn, &cs);
     const double er = m * cs, ei = -m * sn;   // e^{-t}
     double nr, ni;                            // numerator
     if (EDGE) {
