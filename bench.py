@@ -36,26 +36,45 @@ FP32_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 PHASES = ["face", "aca", "expand", "tail"]
 KID = {"slp": 0, "dlp": 1}
-# HBM traffic of the dominant kernel from hardware counters, taken with the kernel source
-# whose SHA-256 is stored beside it; any later change of that source voids the figure
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "far_aca_large_cube3072_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2312_11219_amd", "csrc", "far_aca.hip")
+# HBM traffic per launch of the far-field kernels from hardware counters (rocprofv3
+# FETCH_SIZE and WRITE_SIZE on this workload, scaled by a plain copy of known size), stored
+# with the SHA-256 of the kernel sources; any later change of those sources voids the figures
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "far_traffic_icosphere20480.json")
 
 
 def measured_traffic(kernel_name):
-    """Bytes per launch of kernel_name from the stored counter runs, or None when there are
-    none for it or its source has changed since."""
+    """HBM bytes per launch of kernel_name from the stored counter runs, or None when there
+    are none for it or its sources have changed since."""
     import hashlib
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
-        with open(KERNEL_SOURCE, "rb") as fh:
-            sha = hashlib.sha256(fh.read()).hexdigest()
-    except (OSError, ValueError):
+        h = hashlib.sha256()
+        for rel in rec["sources"]:
+            with open(os.path.join(ROOT, rel), "rb") as fh:
+                h.update(fh.read())
+    except (OSError, ValueError, KeyError):
         return None
-    if rec.get("source_sha256") != sha or kernel_name != rec.get("kernel"):
+    k = rec.get("kernels", {}).get(kernel_name)
+    if rec.get("source_sha256") != h.hexdigest() or k is None:
         return None
-    return rec.get("traffic_bytes_per_launch")
+    return k.get("traffic_bytes_per_launch")
+
+
+def roofline(name, d):
+    """Roofline of one far-field kernel: the expand kernel streams the face pool (bound by
+    HBM: algorithmic bytes per launch over the launch time), the others by FP64 VALU work
+    (algorithmic flops over the launch time)."""
+    ms = d["ms"] / max(1, d["launches"])
+    if name.startswith("far_expand_kernel") and d.get("bytes", 0) > 0:
+        ach = d["bytes"] / max(1, d["launches"]) / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "kernel": name, "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(name),
+                "launches_per_step": d["launches"], "ms_per_launch": ms}
+    ach = d["flops"] / (d["ms"] * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": name, "achieved": ach, "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": measured_traffic(name),
+            "launches_per_step": d["launches"], "ms_per_launch": ms}
 
 
 def large_kernel_name(threads, mixed, path):
@@ -82,22 +101,23 @@ def far_kernels(kernels, all_stats, mixed=False):
         for k, st in zip(kernels[:1] if joint else kernels, stp):
             kid = -1 if joint else KID[k]
             rows = [(f"far_face_kernel<{kid}, false, {mx}>", st["ms_far_phase"][0],
-                     st["launches_phase"][0], st["far_flops_phase"][0]),
+                     st["launches_phase"][0], st["far_flops_phase"][0], st["far_bytes_phase"][0]),
                     (f"far_expand_kernel<{mx}>", st["ms_far_phase"][2], st["launches_phase"][2],
-                     st["far_flops_phase"][2]),
+                     st["far_flops_phase"][2], st["far_bytes_phase"][2]),
                     (f"far_tail_kernel<{kid}, false, {mx}>", st["ms_far_phase"][3],
-                     st["launches_phase"][3], st["far_flops_phase"][3])]
+                     st["launches_phase"][3], st["far_flops_phase"][3], 0.0)]
             for path in range(3):
                 rows.append((large_kernel_name(st["threads_large_used"], mixed, path),
                              st["ms_far_large_path"][path], st["launches_large_path"][path],
-                             st["far_flops_large_path"][path]))
-            for name, ms, nl, fl in rows:
+                             st["far_flops_large_path"][path], 0.0))
+            for name, ms, nl, fl, by in rows:
                 if nl == 0:
                     continue
-                e = out.setdefault(name, {"ms": 0.0, "launches": 0, "flops": 0.0})
+                e = out.setdefault(name, {"ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0})
                 e["ms"] += ms / nsteps
                 e["launches"] += nl / nsteps
                 e["flops"] += fl / nsteps
+                e["bytes"] += by / nsteps
     for e in out.values():
         e["launches"] = int(round(e["launches"]))
     return out
@@ -282,7 +302,8 @@ def run_leg(gaca, ctx, xyz, tri, s, cfg, X, stream, args, precision, sample):
         "far_phase_ms": {name: float(np.mean([sum(st["ms_far_phase"][i] for st in stp) / joint
                                               for stp in all_stats])) for i, name in enumerate(PHASES)},
         "far_kernels": {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
-                            "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3)}
+                            "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3),
+                            "gbs": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)}
                         for k, v in kern.items()},
         "dominant": (dom_name, dom),
     }
@@ -335,7 +356,6 @@ def main():
     print("fp64 leg", file=sys.stderr, flush=True)
     leg64, y64 = run_leg(gaca, ctx, xyz, tri, s, cfg, X, stream, args, "fp64", sample)
     dom_name, dom = leg64.pop("dominant")
-    achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
     ops = "+".join(kernels)
     out = {
         "metric": "3-way ACA build s + kernel entries/s, FP64 vs mixed-prec at stated rel err",
@@ -358,11 +378,7 @@ def main():
                    "global_batch": 1, "parallelism": "single-gpu"},
         "build_s": {k: v / 1e3 for k, v in leg64["build_ms"].items()},
         "near_mirrored": bool(leg64["entries_near_mirrored"] > 0),
-        "roofline": {"bound": "alu", "kernel": dom_name,
-                     "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(dom_name),
-                     "launches_per_step": dom["launches"],
-                     "ms_per_launch": dom["ms"] / max(1, dom["launches"])},
+        "roofline": roofline(dom_name, dom),
         "fp64": leg64,
     }
     if not args.no_mixed:

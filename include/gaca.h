@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define GACA_ABI_VERSION 2
+#define GACA_ABI_VERSION 3
 
 typedef enum {
     GACA_OK = 0,
@@ -154,6 +154,10 @@ typedef struct {
     double ms_far_phase[4];       /* sum of launch durations (HIP events on the launch stream) */
     int32_t launches_phase[4];
     double far_flops_phase[4];    /* algorithmic flops of the phase */
+    double far_bytes_phase[4];    /* algorithmic HBM bytes of the phase: face = previous faces
+                                     read once + the new face written (m n (l + 1) elements);
+                                     expand = U, W read + H_l written + the previous faces read
+                                     for the Gram row; aca and tail 0 (not modelled) */
     /* aca phase by launch class (device time of the class's launches on its stream): 0 m n <= 1024 and sides <= 64 (registers, 128 or 64 threads),
      * 1 m n <= 2304 and sides <= 96 (registers, 256 threads), 2 m n <= 4096 (FP64) or 8192
      * (mixed) and sides <= 128 (registers, 512 threads) together with the larger faces whose

@@ -13,7 +13,7 @@ _lib = None
 P = ctypes.c_void_p
 I32, I64, F64, U64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
 
-ABI_VERSION = 2   # GACA_ABI_VERSION of include/gaca.h that these structures follow
+ABI_VERSION = 3   # GACA_ABI_VERSION of include/gaca.h that these structures follow
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "STATE", -5: "NOT_CONVERGED",
           -6: "UNSUPPORTED"}
 SCHEMES = {"collocation": 0, "galerkin": 1}
@@ -50,7 +50,8 @@ class Stats(ctypes.Structure):
                 ("n_far_launches", I32), ("far_iters", I32), ("far_flops", F64),
                 ("far_kernel_evals", F64), ("near_kernel_evals", F64),
                 ("ms_far_phase", F64 * 4), ("launches_phase", I32 * 4),
-                ("far_flops_phase", F64 * 4), ("ms_far_by_kind", F64 * 4),
+                ("far_flops_phase", F64 * 4), ("far_bytes_phase", F64 * 4),
+                ("ms_far_by_kind", F64 * 4),
                 ("launches_by_kind", I32 * 4), ("far_flops_by_kind", F64 * 4),
                 ("ms_far_large_path", F64 * 3), ("launches_large_path", I32 * 3),
                 ("far_flops_large_path", F64 * 3), ("threads_large_used", I32),

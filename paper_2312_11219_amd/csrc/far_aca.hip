@@ -1446,7 +1446,11 @@ __global__ void __launch_bounds__(256) far_expand_kernel(FarBatchDev bd, const F
     const int m = B.m, n = B.n;
     const int t = (int)(c - A.tile0), ntj = (n + T - 1) / T;
     const int i0 = (t / ntj) * T, j0 = (t % ntj) * T;
-    const int tid = threadIdx.x, r = tid >> 3, cg = (tid & 7) * 4;
+    // thread (r, cg) owns columns cg, cg + 8, cg + 16, cg + 24 of tile row r: for each of its
+    // four entries the eight threads of a row touch eight consecutive elements, so every
+    // load and store of the face pool covers whole cache lines (with four consecutive
+    // entries per thread the pool reads of the Gram row were fetched 2.3 times over)
+    const int tid = threadIdx.x, r = tid >> 3, cg = tid & 7;
     const FT *Ub = reinterpret_cast<const FT *>(bd.uw) + B.uw_off;
     const FT *Wb = Ub + (int64_t)B.rho_max * m;
     FT *H = reinterpret_cast<FT *>(bd.hpool) + A.hslot;
@@ -1474,7 +1478,7 @@ __global__ void __launch_bounds__(256) far_expand_kernel(FarBatchDev bd, const F
         for (int qq = 0; qq < nq; ++qq) {
             const FT u = Us[qq][r];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[e] = cfma(u, Ws[qq][cg + e], acc[e]);
+            for (int e = 0; e < 4; ++e) acc[e] = cfma(u, Ws[qq][cg + 8 * e], acc[e]);
         }
     }
     const int i = i0 + r;
@@ -1483,7 +1487,7 @@ __global__ void __launch_bounds__(256) far_expand_kernel(FarBatchDev bd, const F
     bool ok[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const int j = j0 + cg + e;
+        const int j = j0 + cg + 8 * e;
         ok[e] = i < m && j < n;
         gidx[e] = (int64_t)i * n + j;
         if (ok[e]) {

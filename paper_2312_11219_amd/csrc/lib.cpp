@@ -1103,6 +1103,8 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
     auto f_eval_of = [&](int kern) { return dense ? 0.0 : (kern == 1 ? 113.0 : 105.0); };
     const double qpe = h->kernel == 2 ? 36.0 : 6.0;
     double ms_phase[4] = {0, 0, 0, 0}, ms_kind[4] = {0, 0, 0, 0}, fl_phase[4] = {0, 0, 0, 0};
+    double by_phase[4] = {0, 0, 0, 0};   // algorithmic HBM bytes of the face and expand phases
+    const double fe_bytes = mixed ? 8.0 : 16.0;   // one face element
     double fl_kind[4] = {0, 0, 0, 0};
     int launches_kind[4] = {0, 0, 0, 0};
     // faces with a side above kMediumSide by kernel path (0 general, 1 one entry per thread,
@@ -1284,7 +1286,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             FarActive *ha = W.h_act.as<FarActive>();
             int64_t nchunk = 0, ntile = 0;
             int cnt[4] = {0, 0, 0, 0};
-            double fl_face = 0.0;
+            double fl_face = 0.0, by_face = 0.0;
             for (int a = 0; a < nact; ++a) {
                 const int lb = active[a];
                 const FarBlockDev &d = bdesc[lb];
@@ -1304,6 +1306,8 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                 ha[a] = A;
                 evals += (double)mn * qpe;
                 fl_face += (double)mn * (qpe * f_eval_of(d.kern) + 8.0 * ell_h[lb]);
+                // the previous faces read once, the new face written once
+                by_face += (double)mn * (ell_h[lb] + 1.0) * fe_bytes;
             }
             // small faces: one partial row each (their Gram row), after the expand tiles
             if (!recomp)
@@ -1423,6 +1427,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             launches_phase[2] += ntile > 0;
             launches_phase[3] += 1;
             fl_phase[0] += fl_face;
+            by_phase[0] += by_face;
             // status: accepted crosses get arena space, finished blocks leave
             const int32_t *hs_ = W.h_status.as<int32_t>();
             std::vector<int> next;
@@ -1456,6 +1461,8 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                         fl_kind[big(lb) ? 3 : 2] += f;
                         if (big(lb)) fl_path[path(lb)] += f;
                         fl_phase[2] += 8.0 * mn * (rho + ell);
+                        // U, W read, H_l written, the previous faces read once (Gram row)
+                        by_phase[2] += ((double)rho * (d.m + d.n) + mn * (ell + 1.0)) * fe_bytes;
                     } else {
                         const double f = 8.0 * mn * (2.0 * rho + ell);
                         fl_phase[1] += f;
@@ -1621,6 +1628,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             st.ms_far_phase[k] = ms_phase[k];
             st.launches_phase[k] = launches_phase[k];
             st.far_flops_phase[k] = fl_phase[k];
+            st.far_bytes_phase[k] = by_phase[k];
             st.far_flops += fl_phase[k];
         }
         for (int k = 0; k < 4; ++k) {
