@@ -274,3 +274,105 @@ void oracle_collocation_entries_order(int kernel, const double *tri9, int L,
         free(q.w);
     }
 }
+
+/* ------------------------------------------------------------------------------------
+ * P1 double layer, collocation at the mesh vertices (eq. bie_semi_diri with the trial
+ * functions phi_j linear continuous, the collocation points x_i at the nodes):
+ *   K_ij(s) = sum over the triangles tau of supp phi_j of
+ *             int_tau dG/dn_y(x_i - y) lambda_{tau,j}(y) dS_y,
+ * lambda_{tau,j} = phi_j on tau = the barycentric coordinate of vertex j in tau.
+ * Per (x_i, tau): a triangle with x_i among its vertices contributes exactly 0 (x_i lies in
+ * its plane, so (x_i - y) . n_tau = 0 on it); otherwise far pairs take the 6-point rule and
+ * near pairs the tier of q = |x_i - c_tau| / h_tau (q >= 4: 6-point, 2 <= q < 4: collapsed
+ * 4 x 4, q < 2: collapsed 8 x 8), the collapsed rules with the collapsed edge at the first
+ * vertex of tau, on which lambda = (1 - u, u (1 - v), u v).
+ * ------------------------------------------------------------------------------------ */
+
+static void rule6_points_p1(const tri_t *t, const rules_t *R, int loc, qlist_t *q) {
+    for (int p = 0; p < 6; ++p) {
+        const double *r = R->r6 + 4 * p;
+        double y[3];
+        for (int k = 0; k < 3; ++k) y[k] = r[0] * t->a[k] + r[1] * t->b[k] + r[2] * t->c[k];
+        push(q, y, r[3] * t->area * r[loc]);
+    }
+}
+
+static void collapsed_points_p1(const tri_t *t, int n, const double *g, int loc, qlist_t *q) {
+    double e1[3], e2[3], nn[3];
+    sub3(t->b, t->a, e1);
+    sub3(t->c, t->b, e2);
+    cross3(e1, e2, nn);
+    double two_area = norm3(nn);
+    for (int iu = 0; iu < n; ++iu) {
+        double u = g[2 * iu], wu = g[2 * iu + 1];
+        for (int iv = 0; iv < n; ++iv) {
+            double v = g[2 * iv], wv = g[2 * iv + 1];
+            double lam = loc == 0 ? 1.0 - u : (loc == 1 ? u * (1.0 - v) : u * v);
+            double y[3];
+            for (int k = 0; k < 3; ++k) y[k] = t->a[k] + u * e1[k] + u * v * e2[k];
+            push(q, y, wu * wv * u * two_area * lam);
+        }
+    }
+}
+
+/*
+ *   xyz:  nv x 3 vertex coordinates;  tri: ntri x 3 vertex ids (counter-clockwise seen
+ *         from outside);  pptr (nv + 1), ptri, ploc: the triangles of each vertex's patch
+ *         and the vertex's local index (0, 1, 2) in each
+ *   ii, jj: vertex ids; far: 1 if the pair lies in an admissible block
+ *   order > 0: every non-zero (x_i, tau) with the collapsed order x order rule instead
+ *   out: npair x L x 2
+ */
+void oracle_p1_dlp_entries(const double *xyz, const int32_t *tri, const int64_t *pptr,
+                           const int32_t *ptri, const int32_t *ploc, int L,
+                           const double *s_re, const double *s_im, int64_t npair,
+                           const int64_t *ii, const int64_t *jj, const int32_t *far,
+                           const double *r6, int n4, const double *g4, int n8,
+                           const double *g8, int order, const double *go, double *out) {
+    rules_t R = {r6, n4, g4, n8, g8, 0, 0};
+    int maxq = 6;
+    if (n4 * n4 > maxq) maxq = n4 * n4;
+    if (n8 * n8 > maxq) maxq = n8 * n8;
+    if (order * order > maxq) maxq = order * order;
+#pragma omp parallel
+    {
+        qlist_t q;
+        q.y = (double *)malloc(sizeof(double) * 3 * maxq);
+        q.w = (double *)malloc(sizeof(double) * maxq);
+        double *tmp = (double *)malloc(sizeof(double) * 2 * L);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t p = 0; p < npair; ++p) {
+            const double *x = xyz + 3 * ii[p];
+            double *o = out + 2 * (size_t)L * p;
+            for (int l = 0; l < 2 * L; ++l) o[l] = 0.0;
+            for (int64_t e = pptr[jj[p]]; e < pptr[jj[p] + 1]; ++e) {
+                const int32_t *tv = tri + 3 * (int64_t)ptri[e];
+                if (tv[0] == ii[p] || tv[1] == ii[p] || tv[2] == ii[p]) continue;
+                double v9[9];
+                for (int c = 0; c < 3; ++c)
+                    for (int k = 0; k < 3; ++k) v9[3 * c + k] = xyz[3 * (int64_t)tv[c] + k];
+                tri_t t;
+                make_tri(v9, &t);
+                q.n = 0;
+                const int loc = ploc[e];
+                if (order > 0) {
+                    collapsed_points_p1(&t, order, go, loc, &q);
+                } else if (far[p]) {
+                    rule6_points_p1(&t, &R, loc, &q);
+                } else {
+                    double dv[3];
+                    sub3(x, t.x, dv);
+                    double qd = norm3(dv) / t.h;
+                    if (qd >= 4.0) rule6_points_p1(&t, &R, loc, &q);
+                    else if (qd >= 2.0) collapsed_points_p1(&t, n4, g4, loc, &q);
+                    else collapsed_points_p1(&t, n8, g8, loc, &q);
+                }
+                integrate(1, x, &t, &q, L, s_re, s_im, tmp);
+                for (int l = 0; l < 2 * L; ++l) o[l] += tmp[l];
+            }
+        }
+        free(q.y);
+        free(q.w);
+        free(tmp);
+    }
+}

@@ -51,6 +51,10 @@ def _load():
             P, P, ctypes.c_int, P, P, ctypes.c_int64, P, P, P, P, ctypes.c_int, P,
             ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int, P, P, P]
         lib.oracle_galerkin_entries.restype = None
+        lib.oracle_p1_dlp_entries.argtypes = [
+            P, P, P, P, P, ctypes.c_int, P, P, ctypes.c_int64, P, P, P, P, ctypes.c_int, P,
+            ctypes.c_int, P, ctypes.c_int, P, P]
+        lib.oracle_p1_dlp_entries.restype = None
         _lib = lib
     return _lib
 
@@ -124,4 +128,48 @@ def collocation_entries_order(geom: Geometry, kernel: str, s, ii, jj, n):
     lib.oracle_collocation_entries_order(KERNELS[kernel], _ptr(geom.tri9), L, _ptr(s_re),
                                          _ptr(s_im), ii.shape[0], _ptr(ii), _ptr(jj), n,
                                          _ptr(g), _ptr(out))
+    return out[..., 0] + 1j * out[..., 1]
+
+
+class P1Geometry:
+    """Vertices and triangles of a mesh for the P1 (vertex-based) double layer: each vertex's
+    patch (the triangles around it, CSR) and the vertex's local index in each triangle."""
+
+    def __init__(self, xyz, tri):
+        self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        self.tri = np.ascontiguousarray(tri, dtype=np.int32)
+        nv = self.xyz.shape[0]
+        t = np.repeat(np.arange(self.tri.shape[0], dtype=np.int32), 3)
+        v = self.tri.ravel()
+        loc = np.tile(np.arange(3, dtype=np.int32), self.tri.shape[0])
+        order = np.lexsort((t, v))
+        self.ptri = np.ascontiguousarray(t[order])
+        self.ploc = np.ascontiguousarray(loc[order])
+        self.pptr = np.zeros(nv + 1, dtype=np.int64)
+        np.add.at(self.pptr, v + 1, 1)
+        self.pptr = np.cumsum(self.pptr)
+        self.M = nv
+
+
+def p1_dlp_entries(geom: P1Geometry, s, ii, jj, far=None, order=0, n_mid=N_MID, n_near=N_NEAR):
+    """K(ii[p], jj[p], l) of the P1 double layer collocated at the vertices, every l:
+    complex array (npair, L).  order > 0: every triangle with the collapsed order x order
+    rule (the reference for the quadrature tiers)."""
+    lib = _load()
+    ii = np.ascontiguousarray(ii, dtype=np.int64)
+    jj = np.ascontiguousarray(jj, dtype=np.int64)
+    npair = ii.shape[0]
+    far = np.zeros(npair, dtype=np.int32) if far is None else np.ascontiguousarray(far, dtype=np.int32)
+    s = np.asarray(s, dtype=np.complex128)
+    L = s.shape[0]
+    s_re = np.ascontiguousarray(s.real)
+    s_im = np.ascontiguousarray(s.imag)
+    out = np.zeros((npair, L, 2), dtype=np.float64)
+    r6 = _rule6_table()
+    g4, g8 = _gauss_table(n_mid), _gauss_table(n_near)
+    go = _gauss_table(max(order, 1))
+    lib.oracle_p1_dlp_entries(_ptr(geom.xyz), _ptr(geom.tri), _ptr(geom.pptr), _ptr(geom.ptri),
+                              _ptr(geom.ploc), L, _ptr(s_re), _ptr(s_im), npair, _ptr(ii),
+                              _ptr(jj), _ptr(far), _ptr(r6), n_mid, _ptr(g4), n_near, _ptr(g8),
+                              order, _ptr(go), _ptr(out))
     return out[..., 0] + 1j * out[..., 1]

@@ -21,13 +21,21 @@ from .entries import Geometry, collocation_entries
 
 
 class Problem:
+    """scheme: "collocation" (P0, centroids), "galerkin" (P0) or "p1" (the P1 double layer
+    collocated at the vertices: rows and columns are vertices)."""
+
     def __init__(self, xyz, tri, s, leaf_size, eta, scheme="collocation"):
-        self.geom = Geometry(xyz, tri)
         self.s = np.asarray(s, dtype=np.complex128)
         self.L = self.s.shape[0]
-        self.M = self.geom.M
         self.scheme = scheme
-        self.perm, self.root = T.build_tree(self.geom.xyz, self.geom.tri, leaf_size)
+        if scheme == "p1":
+            from .entries import P1Geometry
+            self.geom = P1Geometry(xyz, tri)
+            self.perm, self.root = T.build_tree_p1(self.geom.xyz, self.geom.tri, leaf_size)
+        else:
+            self.geom = Geometry(xyz, tri)
+            self.perm, self.root = T.build_tree(self.geom.xyz, self.geom.tri, leaf_size)
+        self.M = self.geom.M
         self.far, self.near = T.build_partition(self.root, eta)
 
     def block_ids(self, blk):
@@ -40,7 +48,12 @@ class Problem:
         ii = np.repeat(rows, n)
         jj = np.tile(cols, m)
         flag = np.full(ii.shape[0], 1 if far else 0, dtype=np.int32)
-        if self.scheme != "collocation":
+        if self.scheme == "p1":
+            from .entries import p1_dlp_entries
+            if kernel != "dlp":
+                raise ValueError("the P1 scheme has the double layer only")
+            vals = p1_dlp_entries(self.geom, self.s, ii, jj, flag)
+        elif self.scheme != "collocation":
             from .galerkin import galerkin_entries
             vals = galerkin_entries(self.geom, kernel, self.s, ii, jj, flag)
         else:

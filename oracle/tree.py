@@ -49,7 +49,27 @@ def build_tree(xyz, tri, leaf_size):
     cen = centroids(xyz, tri)
     vmin = np.minimum(np.minimum(xyz[tri[:, 0]], xyz[tri[:, 1]]), xyz[tri[:, 2]])
     vmax = np.maximum(np.maximum(xyz[tri[:, 0]], xyz[tri[:, 1]]), xyz[tri[:, 2]])
-    perm = np.arange(tri.shape[0], dtype=np.int64)
+    return build_tree_points(cen, vmin, vmax, leaf_size)
+
+
+def build_tree_p1(xyz, tri, leaf_size):
+    """Tree over the vertices (the degrees of freedom of the P1 double layer): split by
+    vertex position, boxes of the supports (the triangles around each vertex), so that an
+    admissible pair has well separated supports."""
+    nv = xyz.shape[0]
+    vmin = np.full((nv, 3), np.inf)
+    vmax = np.full((nv, 3), -np.inf)
+    tmin = np.minimum(np.minimum(xyz[tri[:, 0]], xyz[tri[:, 1]]), xyz[tri[:, 2]])
+    tmax = np.maximum(np.maximum(xyz[tri[:, 0]], xyz[tri[:, 1]]), xyz[tri[:, 2]])
+    for c in range(3):
+        np.minimum.at(vmin, tri[:, c], tmin)
+        np.maximum.at(vmax, tri[:, c], tmax)
+    return build_tree_points(np.asarray(xyz, dtype=np.float64), vmin, vmax, leaf_size)
+
+
+def build_tree_points(cen, vmin, vmax, leaf_size):
+    """Tree over points cen (split coordinates) with boxes [vmin, vmax] per point."""
+    perm = np.arange(cen.shape[0], dtype=np.int64)
 
     def make(start, size, level):
         ids = perm[start:start + size]
@@ -70,7 +90,7 @@ def build_tree(xyz, tri, leaf_size):
                              make(start + half, size - half, level + 1)]
         return node
 
-    root = make(0, tri.shape[0], 0)
+    root = make(0, cen.shape[0], 0)
     return perm, root
 
 
