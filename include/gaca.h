@@ -49,7 +49,15 @@ typedef enum {
     GACA_ERR_UNSUPPORTED = -6    /* combination not implemented */
 } gaca_status;
 
-typedef enum { GACA_COLLOCATION_P0 = 0, GACA_GALERKIN_P0 = 1 } gaca_scheme;
+/* Discretisation (Sec. 3): collocation at the element centroids with piecewise constant
+ * functions (single and double layer, eq. bie_semi_diri read with P0); Galerkin with
+ * piecewise constant functions (single layer, eq. bie_semi_indirect); collocation at the
+ * mesh vertices with piecewise linear continuous trial functions (double layer only,
+ * eq. bie_semi_diri: K[i, j] = sum over the triangles around vertex j of the double layer
+ * kernel at vertex i weighted by the hat function of j).  For GACA_COLLOCATION_P1 the
+ * operator's rows and columns are the nv vertices (original vertex ids, tree-permuted like
+ * the elements of the other schemes), precision must be GACA_FP64 and only GACA_DLP builds. */
+typedef enum { GACA_COLLOCATION_P0 = 0, GACA_GALERKIN_P0 = 1, GACA_COLLOCATION_P1 = 2 } gaca_scheme;
 typedef enum { GACA_SLP = 0, GACA_DLP = 1 } gaca_kernel;
 /* FP64: every step in FP64.  MIXED: far-field faces evaluated and stored in FP32 complex
  * with a per-(block, frequency) scale, FP64 fibres, norms and pivot bookkeeping; near
@@ -239,6 +247,14 @@ gaca_status gaca_partition_host(const double *xyz, int64_t nv, const int32_t *tr
                                 int32_t leaf_size, double eta, int64_t *perm,
                                 int64_t capacity, int64_t *far4, int64_t *n_far,
                                 int64_t *near4, int64_t *n_near);
+/* The same for the vertices of the P1 double layer (GACA_COLLOCATION_P1): split by vertex
+ * position, admissibility (Sec. 4 remarks: purely geometric) on the boxes of the vertices'
+ * patches (the triangles around each vertex, the supports of the hat functions).  perm: nv
+ * entries.  GACA_ERR_INVALID_ARG also for a vertex that no triangle uses. */
+gaca_status gaca_partition_host_p1(const double *xyz, int64_t nv, const int32_t *tri, int64_t M,
+                                   int32_t leaf_size, double eta, int64_t *perm,
+                                   int64_t capacity, int64_t *far4, int64_t *n_far,
+                                   int64_t *near4, int64_t *n_near);
 
 /* Host-only quadrature tables used by the kernels (Sec. 3 regular / Duffy quadrature):
  * kind 0: n-point Gauss-Legendre on [0, 1] -> nodes[n], weights[n];

@@ -10,6 +10,9 @@ C4  reentrant-corner cube, grid 1/32 (12288), Galerkin, single layer, L=96,
     s_l = 20 (1 + 0.95 e^{i theta_l}), leaf 32, eps 1e-5.
 C5  icosphere level 6 (81920), collocation, single layer, L=256,
     s_l = 40 (1 + 0.95 e^{i theta_l}), leaf 32, eps 1e-6, apply with 256 right-hand sides.
+P1  icosphere level 5 (20480 triangles, 10242 vertices), the double layer with linear
+    continuous trial functions collocated at the vertices, L=128, s_l = 40 (1 + 0.95
+    e^{i theta_l}), leaf 32, eps 1e-5, FP64.
 
 The face tolerance is eps_aca = eps / 100 (the paper's choice eps = 100 eps_aca).
 """
@@ -26,6 +29,8 @@ CONFIGS = {
                eps=1e-5, scheme="galerkin", kernels=("slp",), precision="fp64", nrhs=2),
     "C5": dict(mesh=("icosphere", 6), M=81920, L=256, c0=40.0, rho=0.95, leaf=32, eta=1.0,
                eps=1e-6, scheme="collocation", kernels=("slp",), precision="mixed", nrhs=256),
+    "P1": dict(mesh=("icosphere", 5), M=10242, L=128, c0=40.0, rho=0.95, leaf=32, eta=1.0,
+               eps=1e-5, scheme="p1", kernels=("dlp",), precision="fp64", nrhs=2),
 }
 
 

@@ -16,7 +16,7 @@ I32, I64, F64, U64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_u
 ABI_VERSION = 3   # GACA_ABI_VERSION of include/gaca.h that these structures follow
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "STATE", -5: "NOT_CONVERGED",
           -6: "UNSUPPORTED"}
-SCHEMES = {"collocation": 0, "galerkin": 1}
+SCHEMES = {"collocation": 0, "galerkin": 1, "p1": 2}
 KERNELS = {"slp": 0, "dlp": 1}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 MODES = {"sum": 0, "per_freq": 1}
@@ -102,6 +102,7 @@ def load_library():
         "gaca_hmatrix_block_export": (I32, [P, I64, P, P, P, P, P, P, P]),
         "gaca_hmatrix_near_export": (I32, [P, I64, P]),
         "gaca_hmatrix_near_ranks": (I32, [P, P]),
+        "gaca_partition_host_p1": (I32, [P, I64, P, I64, I32, F64, P, I64, P, P, P, P]),
         "gaca_apply": (I32, [P, ctypes.c_int, I32, P, P, ctypes.c_int, P]),
         "gaca_apply_noalloc": (I32, [P, ctypes.c_int, I32, P, P, ctypes.c_int, P]),
         "gaca_eval_entries": (I32, [P, ctypes.c_int, I64, P, P, P, P, P]),
@@ -173,20 +174,23 @@ def gcq_contour(rk_A, dt_min, dt_max, n_q):
     return sr + 1j * si, wr + 1j * wi
 
 
-def partition_host(xyz, tri, leaf_size, eta):
-    """Host-only tree + partition: (perm, far (nf,4), near (nn,4))."""
+def partition_host(xyz, tri, leaf_size, eta, scheme="collocation"):
+    """Host-only tree + partition: (perm, far (nf,4), near (nn,4)); scheme "p1": over the
+    vertices."""
     lib = load_library()
     xyz = np.ascontiguousarray(xyz, dtype=np.float64)
     tri = np.ascontiguousarray(tri, dtype=np.int32)
     M = tri.shape[0]
-    perm = np.zeros(M, dtype=np.int64)
-    cap = max(16, 4 * M * M // max(1, leaf_size) // max(1, leaf_size) + 64)
+    n = xyz.shape[0] if scheme == "p1" else M
+    fn = lib.gaca_partition_host_p1 if scheme == "p1" else lib.gaca_partition_host
+    perm = np.zeros(n, dtype=np.int64)
+    cap = max(16, 4 * n * n // max(1, leaf_size) // max(1, leaf_size) + 64)
     cap = min(cap, 50_000_000)
     while True:
         far = np.zeros((cap, 4), dtype=np.int64)
         near = np.zeros((cap, 4), dtype=np.int64)
         nf, nn = I64(0), I64(0)
-        rc = lib.gaca_partition_host(_ptr(xyz), xyz.shape[0], _ptr(tri), M, leaf_size, eta,
+        rc = fn(_ptr(xyz), xyz.shape[0], _ptr(tri), M, leaf_size, eta,
                                      _ptr(perm), cap, _ptr(far), ctypes.byref(nf), _ptr(near),
                                      ctypes.byref(nn))
         if rc == 0:
@@ -233,13 +237,14 @@ class Problem:
         s = np.asarray(s, dtype=np.complex128)
         self.s = s
         self.L = s.shape[0]
-        self.M = self.tri.shape[0]
+        # operator size: elements, or vertices for the P1 double layer
+        self.M = self.xyz.shape[0] if scheme == "p1" else self.tri.shape[0]
         s_re = np.ascontiguousarray(s.real)
         s_im = np.ascontiguousarray(s.imag)
         self.opt = options_default(**options)
         h = P()
         _check(self._lib.gaca_problem_create(ctx.handle, _ptr(self.xyz), self.xyz.shape[0],
-                                             _ptr(self.tri), self.M, _ptr(s_re), _ptr(s_im),
+                                             _ptr(self.tri), self.tri.shape[0], _ptr(s_re), _ptr(s_im),
                                              self.L, SCHEMES[scheme], ctypes.byref(self.opt),
                                              ctypes.byref(h)))
         self.handle = h

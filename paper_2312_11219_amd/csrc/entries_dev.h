@@ -214,4 +214,134 @@ __device__ void near_entry(const GeoDev &g, const QuadDev &q, const FreqDev &f, 
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// P1 double layer collocated at the vertices (Sec. 3, eq. bie_semi_diri with phi_j linear):
+//   K_ij(s) = sum over the triangles t of the patch of vertex j of
+//             int_t dG/dn_y(x_i - y) lambda_{t,j}(y) dS_y,
+// lambda_{t,j} the barycentric coordinate of vertex j in t.  A triangle that has x_i as a
+// vertex contributes exactly 0 (x_i lies in its plane).  Far pairs take the 6-point rule on
+// every triangle; near pairs per triangle the tier of q = |x_i - c_t| / h_t (q >= 4: 6-point,
+// 2 <= q < 4: collapsed n4 x n4, q < 2: collapsed n8 x n8, collapsed at the triangle's first
+// vertex, where lambda = (1 - u, u (1 - v), u v)).
+
+__device__ __forceinline__ bool p1_holds(const GeoDev &g, int64_t t, int32_t vid) {
+    return g.tv0[t] == vid || g.tv1[t] == vid || g.tv2[t] == vid;
+}
+
+// collapsed rule on triangle (a, b, c) weighted by the barycentric coordinate loc
+template <int NF>
+__device__ __forceinline__ void collapsed_acc_p1(double x, double y, double z, const double *a,
+                                                 const double *b, const double *c, int n,
+                                                 const double *gtab, int loc, const FreqDev &f,
+                                                 int l0, int nl, double *ar, double *ai) {
+    const double e1x = b[0] - a[0], e1y = b[1] - a[1], e1z = b[2] - a[2];
+    const double e2x = c[0] - b[0], e2y = c[1] - b[1], e2z = c[2] - b[2];
+    const double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+    const double two_area = sqrt(nx * nx + ny * ny + nz * nz);
+    for (int iu = 0; iu < n; ++iu) {
+        const double u = gtab[2 * iu], wu = gtab[2 * iu + 1];
+        for (int iv = 0; iv < n; ++iv) {
+            const double v = gtab[2 * iv], wv = gtab[2 * iv + 1];
+            const double uv = u * v;
+            const double lam = loc == 0 ? 1.0 - u : (loc == 1 ? u - uv : uv);
+            const double px = a[0] + u * e1x + uv * e2x;
+            const double py = a[1] + u * e1y + uv * e2y;
+            const double pz = a[2] + u * e1z + uv * e2z;
+            const double w = wu * wv * u * two_area * lam;
+            double ir;
+            const double r = dist3_inv(x, y, z, px, py, pz, ir);
+#pragma unroll
+            for (int t = 0; t < NF; ++t)
+                if (t < nl) kacc<1>(r, ir, f.re[l0 + t], f.im[l0 + t], w, ar[t], ai[t]);
+        }
+    }
+}
+
+// 6-point rule on triangle t weighted by the barycentric coordinate loc
+template <int NF>
+__device__ __forceinline__ void rule6_acc_p1(const GeoDev &g, double x, double y, double z,
+                                             int64_t t, int loc, const FreqDev &f, int l0,
+                                             int nl, double *ar, double *ai) {
+    const int64_t T = g.T;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        double ir;
+        const double r = dist3_inv(x, y, z, g.q6x[p * T + t], g.q6y[p * T + t], g.q6z[p * T + t], ir);
+        const double w = g.q6wl[(int64_t)(loc * 6 + p) * T + t];
+#pragma unroll
+        for (int k = 0; k < NF; ++k)
+            if (k < nl) kacc<1>(r, ir, f.re[l0 + k], f.im[l0 + k], w, ar[k], ai[k]);
+    }
+}
+
+// Entry (i, j) (tree positions) at NF frequencies from l0 (nl valid); far: 6-point rule on
+// every triangle.  Results in ar / ai (zeroed here).
+template <int NF>
+__device__ void p1_entry(const GeoDev &g, const QuadDev &q, const FreqDev &f, int64_t i,
+                         int64_t j, bool far, int l0, int nl, double *ar, double *ai) {
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+        ar[k] = 0.0;
+        ai[k] = 0.0;
+    }
+    const double x = g.xx[i], y = g.xy[i], z = g.xz[i];
+    const int32_t vid = g.dvid[i];
+    for (int32_t e = g.pptr[j]; e < g.pptr[j + 1]; ++e) {
+        const int64_t t = g.ptri[e];
+        if (p1_holds(g, t, vid)) continue;
+        const int loc = g.ploc[e];
+        double tr[NF], ti[NF];
+#pragma unroll
+        for (int k = 0; k < NF; ++k) {
+            tr[k] = 0.0;
+            ti[k] = 0.0;
+        }
+        int tier = TIER_FAR6;
+        if (!far) {
+            const double dx = x - g.tcx[t], dy = y - g.tcy[t], dz = z - g.tcz[t];
+            const double qd = sqrt(dx * dx + dy * dy + dz * dz) / g.h[t];
+            tier = qd >= 4.0 ? TIER_FAR6 : (qd >= 2.0 ? TIER_MID4 : TIER_NEAR8);
+        }
+        if (tier == TIER_FAR6) {
+            rule6_acc_p1<NF>(g, x, y, z, t, loc, f, l0, nl, tr, ti);
+        } else {
+            const double a[3] = {g.ax[t], g.ay[t], g.az[t]};
+            const double b[3] = {g.bx[t], g.by[t], g.bz[t]};
+            const double c[3] = {g.cx[t], g.cy[t], g.cz[t]};
+            if (tier == TIER_MID4) collapsed_acc_p1<NF>(x, y, z, a, b, c, q.n4, q.g4, loc, f, l0, nl, tr, ti);
+            else collapsed_acc_p1<NF>(x, y, z, a, b, c, q.n8, q.g8, loc, f, l0, nl, tr, ti);
+        }
+        const double num = g.nx[t] * x + g.ny[t] * y + g.nz[t] * z - g.d[t];
+#pragma unroll
+        for (int k = 0; k < NF; ++k) {
+            ar[k] += num * tr[k];
+            ai[k] += num * ti[k];
+        }
+    }
+}
+
+// Far entry at one frequency (the face and fibre evaluations of admissible blocks).
+__device__ __forceinline__ void p1_far_entry(const GeoDev &g, int64_t i, int64_t j, double sre,
+                                             double sim, double &er, double &ei) {
+    const double x = g.xx[i], y = g.xy[i], z = g.xz[i];
+    double ar = 0.0, ai = 0.0;
+    for (int32_t e = g.pptr[j]; e < g.pptr[j + 1]; ++e) {
+        const int64_t t = g.ptri[e];
+        const int loc = g.ploc[e];
+        const int64_t T = g.T;
+        double tr = 0.0, ti = 0.0;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            double ir;
+            const double r = dist3_inv(x, y, z, g.q6x[p * T + t], g.q6y[p * T + t], g.q6z[p * T + t], ir);
+            kacc<1>(r, ir, sre, sim, g.q6wl[(int64_t)(loc * 6 + p) * T + t], tr, ti);
+        }
+        const double num = g.nx[t] * x + g.ny[t] * y + g.nz[t] * z - g.d[t];
+        ar += num * tr;
+        ai += num * ti;
+    }
+    er = ar;
+    ei = ai;
+}
+
 }  // namespace gaca

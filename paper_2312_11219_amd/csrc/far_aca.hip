@@ -55,7 +55,11 @@ __device__ __forceinline__ FT face_entry(const GeoDev &g, const FreqDev &f, cons
     }
     if (DENSE) return from_d2<FT>(dense[((int64_t)il * B.n + jl) * f.L + kk]);
     const int64_t gi = B.r0 + il, gj = B.c0 + jl;
-    if constexpr (KERNEL == 2) {
+    if constexpr (KERNEL == 3) {   // P1 double layer (FP64 only)
+        double er, ei;
+        p1_far_entry(g, gi, gj, f.re[kk], f.im[kk], er, ei);
+        return from_d2<FT>(make_double2(er, ei));
+    } else if constexpr (KERNEL == 2) {
         if constexpr (sizeof(FT) == sizeof(double2)) {
             double er, ei;
             entry_gal36(g, gi, gj, f.re[kk], f.im[kk], er, ei);
@@ -98,7 +102,9 @@ __device__ __forceinline__ double2 fibre_entry(const GeoDev &g, const FreqDev &f
     if (DENSE) return dense[((int64_t)il * B.n + jl) * f.L + kk];
     const int64_t gi = B.r0 + il, gj = B.c0 + jl;
     double er, ei;
-    if constexpr (KERNEL == 2)
+    if constexpr (KERNEL == 3)
+        p1_far_entry(g, gi, gj, f.re[kk], f.im[kk], er, ei);
+    else if constexpr (KERNEL == 2)
         entry_gal36(g, gi, gj, f.re[kk], f.im[kk], er, ei);
     else
         entry_far6<KERNEL>(g, g.xx[gi], g.xy[gi], g.xz[gi], gj, f.re[kk], f.im[kk], er, ei);
@@ -1878,6 +1884,7 @@ void launch_far_face(int kernel, const GeoDev &g, const FreqDev &f, const FarBat
     } else if (!bd.mixed) {
         if (kernel == 0) face_dispatch<0, false, false>(g, f, bd, act, nchunk, st);
         else if (kernel == 1) face_dispatch<1, false, false>(g, f, bd, act, nchunk, st);
+        else if (kernel == 3) face_dispatch<3, false, false>(g, f, bd, act, nchunk, st);
         else face_dispatch<2, false, false>(g, f, bd, act, nchunk, st);
     } else {
         if (kernel == 0) face_dispatch<0, false, true>(g, f, bd, act, nchunk, st);
@@ -1974,6 +1981,7 @@ void launch_far_tail(int kernel, const GeoDev &g, const FreqDev &f, const AcaPar
     } else if (!bd.mixed) {
         if (kernel == 0) tail_dispatch<0, false, false>(g, f, P, bd, act, nact, nlarge, st);
         else if (kernel == 1) tail_dispatch<1, false, false>(g, f, P, bd, act, nact, nlarge, st);
+        else if (kernel == 3) tail_dispatch<3, false, false>(g, f, P, bd, act, nact, nlarge, st);
         else tail_dispatch<2, false, false>(g, f, P, bd, act, nact, nlarge, st);
     } else {
         if (kernel == 0) tail_dispatch<0, false, true>(g, f, P, bd, act, nact, nlarge, st);

@@ -46,6 +46,17 @@ struct GeoDev {
     // FP32 copies for the mixed-precision far field: far-rule points relative to the
     // element centroid (small, so FP32 keeps them to ~1e-7 of the element size) and weights
     const float *q6dx, *q6dy, *q6dz, *q6wf;                    // [6][M]
+    // P1 double layer collocated at the vertices (scheme GACA_COLLOCATION_P1): the degrees
+    // of freedom are the M vertices (tree order; xx, xy, xz hold their coordinates); the
+    // triangle arrays (ax .. area, q6x/y/z as [6][T]) are indexed by triangle id in the
+    // original order, tcx/tcy/tcz their centroids; the patch of the vertex at tree position j
+    // is ptri / ploc[pptr[j] .. pptr[j + 1]) (triangle id, local index of the vertex in it);
+    // tv0/tv1/tv2 are the vertex ids of each triangle, dvid the vertex id of each tree
+    // position; q6wl[(loc 6 + p) T + t] = weight x area x barycentric coordinate loc of rule
+    // point p.  For the other schemes T = M and the P1 pointers are null.
+    int64_t T;
+    const int32_t *pptr, *ptri, *ploc, *tv0, *tv1, *tv2, *dvid;
+    const double *tcx, *tcy, *tcz, *q6wl;
 };
 
 // Quadrature tables in device memory.

@@ -43,6 +43,14 @@ void launch_near_aca_pack(const NearAcaArgs &q, int nblk, const void *near, cons
 void launch_near_aca_expand(const NearBlockDev &D, int L, const void *face_arena,
                             const double2 *fib_arena, double2 *out, int fp32, hipStream_t st);
 
+// P1 double layer near field (every pair, all frequencies, FP64, stored as double2) and its
+// entry test hook (far[p] != 0: 6-point rule on every triangle).
+void launch_near_p1(const GeoDev &g, const QuadDev &q, const FreqDev &f, const NearPair *pairs,
+                    int64_t npairs, const NearBlockDev *blocks, double2 *out64, hipStream_t st);
+void launch_eval_p1(const GeoDev &g, const QuadDev &q, const FreqDev &f, int64_t n,
+                    const int32_t *rows, const int32_t *cols, const int32_t *ks,
+                    const int32_t *far, double2 *out, hipStream_t st);
+
 // Near field: every pair of one tier, all frequencies, FP64 compute, stored as double2
 // (out64) or float2 (out32).
 void launch_near(int kernel, int tier, const GeoDev &g, const QuadDev &q, const FreqDev &f,

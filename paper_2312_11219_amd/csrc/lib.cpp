@@ -6,6 +6,7 @@
 #include <array>
 #include <atomic>
 #include <chrono>
+#include <limits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -410,6 +411,13 @@ struct gaca_problem {
     gaca_scheme scheme = GACA_COLLOCATION_P0;
     bool synthetic = false;       // dense-tensor problem of gaca_compress_tensor
     HostMesh mesh;
+    // P1 scheme: the degrees of freedom are the vertices (points at the vertices, boxes of
+    // their patches, for the cluster tree) and each vertex's patch (tree order CSR)
+    HostMesh dofs;
+    std::vector<int32_t> pptr, ptri, ploc;
+    std::vector<double> patch_prefix;    // prefix sums of the patch sizes in tree order
+    double p1_near_points = 0.0;         // quadrature points of the near field per frequency
+    DevBuf d_p1i;
     ClusterTree tree;
     Partition part;
     int32_t L = 0;
@@ -428,7 +436,9 @@ struct gaca_problem {
     DevBuf d_nblocks;
     DevBuf d_pairs[kNumTiers];
     int64_t npairs[kNumTiers] = {0, 0, 0, 0, 0, 0};
-    int kid(gaca_kernel k) const { return scheme == GACA_GALERKIN_P0 ? 2 : (int)k; }
+    int kid(gaca_kernel k) const {
+        return scheme == GACA_GALERKIN_P0 ? 2 : scheme == GACA_COLLOCATION_P1 ? 3 : (int)k;
+    }
     // leaves for the apply
     std::vector<int32_t> leaf_r0, leaf_m;
     // far-field launch classes run concurrently on these streams (default priority)
@@ -541,6 +551,43 @@ gaca_status gaca_context_destroy(gaca_context *ctx) {
     return GACA_OK;
 }
 
+// P1 degrees of freedom: one per vertex.  The cluster tree splits them by vertex position
+// and tests admissibility on the boxes of their patches (the supports of the trial
+// functions), so that an admissible pair has separated supports.
+static void p1_dofs(const HostMesh &m, HostMesh &d) {
+    const int64_t nv = m.nv, T = m.M;
+    d.nv = nv;
+    d.M = nv;
+    d.cen = m.xyz;
+    d.vmin.assign(3 * nv, std::numeric_limits<double>::infinity());
+    d.vmax.assign(3 * nv, -std::numeric_limits<double>::infinity());
+    std::vector<int32_t> cnt(nv, 0);
+    for (int64_t t = 0; t < T; ++t)
+        for (int c = 0; c < 3; ++c) {
+            const int32_t v = m.tri[3 * t + c];
+            ++cnt[v];
+            for (int k = 0; k < 3; ++k) {
+                d.vmin[3 * v + k] = std::min(d.vmin[3 * v + k], m.vmin[3 * t + k]);
+                d.vmax[3 * v + k] = std::max(d.vmax[3 * v + k], m.vmax[3 * t + k]);
+            }
+        }
+    for (int64_t v = 0; v < nv; ++v)
+        if (cnt[v] == 0) throw Error{GACA_ERR_INVALID_ARG, "P1 scheme: a vertex belongs to no triangle"};
+}
+
+// Block lists of a partition into caller arrays (row_start, m, col_start, n each).
+static void write_blocks(const Partition &part, int64_t capacity, int64_t *far4, int64_t *n_far,
+                         int64_t *near4, int64_t *n_near) {
+    *n_far = (int64_t)part.far.size();
+    *n_near = (int64_t)part.near.size();
+    if ((int64_t)part.far.size() > capacity || (int64_t)part.near.size() > capacity)
+        throw Error{GACA_ERR_INVALID_ARG, "block list capacity too small"};
+    for (size_t b = 0; b < part.far.size(); ++b)
+        for (int k = 0; k < 4; ++k) far4[4 * b + k] = part.far[b][k];
+    for (size_t b = 0; b < part.near.size(); ++b)
+        for (int k = 0; k < 4; ++k) near4[4 * b + k] = part.near[b][k];
+}
+
 gaca_status gaca_partition_host(const double *xyz, int64_t nv, const int32_t *tri, int64_t M,
                                 int32_t leaf_size, double eta, int64_t *perm,
                                 int64_t capacity, int64_t *far4, int64_t *n_far,
@@ -555,14 +602,26 @@ gaca_status gaca_partition_host(const double *xyz, int64_t nv, const int32_t *tr
         Partition part;
         part.build(tree, eta);
         std::copy(tree.perm.begin(), tree.perm.end(), perm);
-        *n_far = (int64_t)part.far.size();
-        *n_near = (int64_t)part.near.size();
-        if ((int64_t)part.far.size() > capacity || (int64_t)part.near.size() > capacity)
-            throw Error{GACA_ERR_INVALID_ARG, "block list capacity too small"};
-        for (size_t b = 0; b < part.far.size(); ++b)
-            for (int k = 0; k < 4; ++k) far4[4 * b + k] = part.far[b][k];
-        for (size_t b = 0; b < part.near.size(); ++b)
-            for (int k = 0; k < 4; ++k) near4[4 * b + k] = part.near[b][k];
+        write_blocks(part, capacity, far4, n_far, near4, n_near);
+    });
+}
+
+gaca_status gaca_partition_host_p1(const double *xyz, int64_t nv, const int32_t *tri, int64_t M,
+                                   int32_t leaf_size, double eta, int64_t *perm,
+                                   int64_t capacity, int64_t *far4, int64_t *n_far,
+                                   int64_t *near4, int64_t *n_near) {
+    return guarded([&] {
+        REQUIRE(perm && n_far && n_near, "null output");
+        REQUIRE(eta > 0.0, "eta must be > 0");
+        HostMesh mesh, dofs;
+        mesh.init(xyz, nv, tri, M);
+        p1_dofs(mesh, dofs);
+        ClusterTree tree;
+        tree.build(dofs, leaf_size);
+        Partition part;
+        part.build(tree, eta);
+        std::copy(tree.perm.begin(), tree.perm.end(), perm);
+        write_blocks(part, capacity, far4, n_far, near4, n_near);
     });
 }
 
@@ -590,57 +649,11 @@ gaca_status gaca_quadrature_rule(int kind, int n, double *nodes, double *weights
     });
 }
 
-static void upload_problem(gaca_problem *p) {
+// Quadrature tables in device memory (every scheme).
+static void upload_quad(gaca_problem *p) {
     gaca_context *ctx = p->ctx;
-    const int64_t M = p->M;
-    // geometry SoA in tree order: 18 arrays of M + 24 arrays (6 points x 4) of M
-    const int nsoa = 18 + 24;
-    std::vector<double> geo((size_t)nsoa * M);
     double bary[6][3], w6[6];
     triangle6(bary, w6);
-    for (int64_t t = 0; t < M; ++t) {
-        const int64_t e = p->tree.perm[t];
-        const double *v = &p->mesh.vert[9 * e];
-        for (int k = 0; k < 9; ++k) geo[(size_t)k * M + t] = v[k];
-        for (int k = 0; k < 3; ++k) geo[(size_t)(9 + k) * M + t] = p->mesh.cen[3 * e + k];
-        for (int k = 0; k < 3; ++k) geo[(size_t)(12 + k) * M + t] = p->mesh.nrm[3 * e + k];
-        geo[(size_t)15 * M + t] = p->mesh.dpl[e];
-        geo[(size_t)16 * M + t] = p->mesh.hmax[e];
-        geo[(size_t)17 * M + t] = p->mesh.area[e];
-        for (int q = 0; q < 6; ++q) {
-            for (int k = 0; k < 3; ++k)
-                geo[(size_t)(18 + 6 * k + q) * M + t] =
-                    bary[q][0] * v[k] + bary[q][1] * v[3 + k] + bary[q][2] * v[6 + k];
-            geo[(size_t)(18 + 18 + q) * M + t] = w6[q] * p->mesh.area[e];
-        }
-    }
-    p->d_geo.upload(ctx, geo);
-    const double *G = p->d_geo.as<double>();
-    GeoDev &g = p->g;
-    g.M = M;
-    const double **fields[18] = {&g.ax, &g.ay, &g.az, &g.bx, &g.by, &g.bz, &g.cx, &g.cy, &g.cz,
-                                 &g.xx, &g.xy, &g.xz, &g.nx, &g.ny, &g.nz, &g.d, &g.h, &g.area};
-    for (int k = 0; k < 18; ++k) *fields[k] = G + (size_t)k * M;
-    g.q6x = G + (size_t)18 * M;
-    g.q6y = G + (size_t)24 * M;
-    g.q6z = G + (size_t)30 * M;
-    g.q6w = G + (size_t)36 * M;
-    // FP32 far-rule data for the mixed path: points relative to the centroid, weights
-    std::vector<float> geo32((size_t)24 * M);
-    for (int64_t t = 0; t < M; ++t)
-        for (int q = 0; q < 6; ++q) {
-            for (int k = 0; k < 3; ++k)
-                geo32[(size_t)(6 * k + q) * M + t] =
-                    (float)(geo[(size_t)(18 + 6 * k + q) * M + t] - geo[(size_t)(9 + k) * M + t]);
-            geo32[(size_t)(18 + q) * M + t] = (float)geo[(size_t)(36 + q) * M + t];
-        }
-    p->d_geo32.upload(ctx, geo32);
-    const float *G32 = p->d_geo32.as<float>();
-    g.q6dx = G32;
-    g.q6dy = G32 + (size_t)6 * M;
-    g.q6dz = G32 + (size_t)12 * M;
-    g.q6wf = G32 + (size_t)18 * M;
-    // quadrature tables
     Rule1D r4 = gauss_legendre01(p->opt.quad_mid), r8 = gauss_legendre01(p->opt.quad_near),
            rd = gauss_legendre01(p->opt.n_duffy), rg = gauss_legendre01(p->opt.n_galerkin),
            rs = gauss_legendre01(p->opt.n_touch);
@@ -678,6 +691,88 @@ static void upload_problem(gaca_problem *p) {
     p->q.r6 = Q + o6;
     p->q.nth = kGalerkinNTheta;
     p->q.gth = Q + oth;
+}
+
+// Leaves of the cluster tree in tree order (the row groups of the apply).
+static void set_leaves(gaca_problem *p) {
+    p->leaf_r0.clear();
+    p->leaf_m.clear();
+    for (const auto &nd : p->tree.nodes)
+        if (nd.child[0] < 0) {
+            p->leaf_r0.push_back((int32_t)nd.start);
+            p->leaf_m.push_back((int32_t)nd.size);
+        }
+    std::vector<size_t> order(p->leaf_r0.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(),
+              [&](size_t a, size_t b) { return p->leaf_r0[a] < p->leaf_r0[b]; });
+    std::vector<int32_t> r0s, ms;
+    for (size_t k : order) {
+        r0s.push_back(p->leaf_r0[k]);
+        ms.push_back(p->leaf_m[k]);
+    }
+    p->leaf_r0 = r0s;
+    p->leaf_m = ms;
+}
+
+static void upload_problem_p1(gaca_problem *p);
+
+static void upload_problem(gaca_problem *p) {
+    if (p->scheme == GACA_COLLOCATION_P1) {
+        upload_problem_p1(p);
+        return;
+    }
+    gaca_context *ctx = p->ctx;
+    const int64_t M = p->M;
+    // geometry SoA in tree order: 18 arrays of M + 24 arrays (6 points x 4) of M
+    const int nsoa = 18 + 24;
+    std::vector<double> geo((size_t)nsoa * M);
+    double bary[6][3], w6[6];
+    triangle6(bary, w6);
+    for (int64_t t = 0; t < M; ++t) {
+        const int64_t e = p->tree.perm[t];
+        const double *v = &p->mesh.vert[9 * e];
+        for (int k = 0; k < 9; ++k) geo[(size_t)k * M + t] = v[k];
+        for (int k = 0; k < 3; ++k) geo[(size_t)(9 + k) * M + t] = p->mesh.cen[3 * e + k];
+        for (int k = 0; k < 3; ++k) geo[(size_t)(12 + k) * M + t] = p->mesh.nrm[3 * e + k];
+        geo[(size_t)15 * M + t] = p->mesh.dpl[e];
+        geo[(size_t)16 * M + t] = p->mesh.hmax[e];
+        geo[(size_t)17 * M + t] = p->mesh.area[e];
+        for (int q = 0; q < 6; ++q) {
+            for (int k = 0; k < 3; ++k)
+                geo[(size_t)(18 + 6 * k + q) * M + t] =
+                    bary[q][0] * v[k] + bary[q][1] * v[3 + k] + bary[q][2] * v[6 + k];
+            geo[(size_t)(18 + 18 + q) * M + t] = w6[q] * p->mesh.area[e];
+        }
+    }
+    p->d_geo.upload(ctx, geo);
+    const double *G = p->d_geo.as<double>();
+    GeoDev &g = p->g;
+    g.M = M;
+    g.T = M;
+    const double **fields[18] = {&g.ax, &g.ay, &g.az, &g.bx, &g.by, &g.bz, &g.cx, &g.cy, &g.cz,
+                                 &g.xx, &g.xy, &g.xz, &g.nx, &g.ny, &g.nz, &g.d, &g.h, &g.area};
+    for (int k = 0; k < 18; ++k) *fields[k] = G + (size_t)k * M;
+    g.q6x = G + (size_t)18 * M;
+    g.q6y = G + (size_t)24 * M;
+    g.q6z = G + (size_t)30 * M;
+    g.q6w = G + (size_t)36 * M;
+    // FP32 far-rule data for the mixed path: points relative to the centroid, weights
+    std::vector<float> geo32((size_t)24 * M);
+    for (int64_t t = 0; t < M; ++t)
+        for (int q = 0; q < 6; ++q) {
+            for (int k = 0; k < 3; ++k)
+                geo32[(size_t)(6 * k + q) * M + t] =
+                    (float)(geo[(size_t)(18 + 6 * k + q) * M + t] - geo[(size_t)(9 + k) * M + t]);
+            geo32[(size_t)(18 + q) * M + t] = (float)geo[(size_t)(36 + q) * M + t];
+        }
+    p->d_geo32.upload(ctx, geo32);
+    const float *G32 = p->d_geo32.as<float>();
+    g.q6dx = G32;
+    g.q6dy = G32 + (size_t)6 * M;
+    g.q6dz = G32 + (size_t)12 * M;
+    g.q6wf = G32 + (size_t)18 * M;
+    upload_quad(p);
     // permutation
     p->d_perm.upload(ctx, p->tree.perm);
     // near blocks and tier pair lists
@@ -706,25 +801,142 @@ static void upload_problem(gaca_problem *p) {
         p->npairs[t] = (int64_t)pairs[t].size();
         p->d_pairs[t].upload(ctx, pairs[t]);
     }
-    // leaves in tree order
-    p->leaf_r0.clear();
-    p->leaf_m.clear();
-    for (const auto &nd : p->tree.nodes)
-        if (nd.child[0] < 0) {
-            p->leaf_r0.push_back((int32_t)nd.start);
-            p->leaf_m.push_back((int32_t)nd.size);
+    set_leaves(p);
+}
+
+// Geometry of the P1 double layer (layout in GeoDev): triangle arrays in the original
+// triangle order, vertex coordinates, patches and vertex ids in the tree order of the
+// vertices; one near pair list (the tier is chosen per triangle on the device).
+static void upload_problem_p1(gaca_problem *p) {
+    gaca_context *ctx = p->ctx;
+    const HostMesh &m = p->mesh;
+    const int64_t T = m.M, M = p->M;
+    double bary[6][3], w6[6];
+    triangle6(bary, w6);
+    // doubles: 18 triangle arrays + 3 centroids + 18 rule coordinates + 18 weights (per
+    // local vertex) of T, then the 3 vertex coordinates of M
+    const int ntri_arrays = 18 + 3 + 18 + 18;
+    std::vector<double> geo((size_t)ntri_arrays * T + 3 * (size_t)M);
+    for (int64_t t = 0; t < T; ++t) {
+        const double *v = &m.vert[9 * t];
+        for (int k = 0; k < 9; ++k) geo[(size_t)k * T + t] = v[k];
+        for (int k = 0; k < 3; ++k) geo[(size_t)(9 + k) * T + t] = m.cen[3 * t + k];
+        for (int k = 0; k < 3; ++k) geo[(size_t)(12 + k) * T + t] = m.nrm[3 * t + k];
+        geo[(size_t)15 * T + t] = m.dpl[t];
+        geo[(size_t)16 * T + t] = m.hmax[t];
+        geo[(size_t)17 * T + t] = m.area[t];
+        for (int k = 0; k < 3; ++k) geo[(size_t)(18 + k) * T + t] = m.cen[3 * t + k];
+        for (int q = 0; q < 6; ++q) {
+            for (int k = 0; k < 3; ++k)
+                geo[(size_t)(21 + 6 * k + q) * T + t] =
+                    bary[q][0] * v[k] + bary[q][1] * v[3 + k] + bary[q][2] * v[6 + k];
+            for (int loc = 0; loc < 3; ++loc)
+                geo[(size_t)(39 + 6 * loc + q) * T + t] = w6[q] * m.area[t] * bary[q][loc];
         }
-    std::vector<size_t> order(p->leaf_r0.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::sort(order.begin(), order.end(),
-              [&](size_t a, size_t b) { return p->leaf_r0[a] < p->leaf_r0[b]; });
-    std::vector<int32_t> r0s, ms;
-    for (size_t k : order) {
-        r0s.push_back(p->leaf_r0[k]);
-        ms.push_back(p->leaf_m[k]);
     }
-    p->leaf_r0 = r0s;
-    p->leaf_m = ms;
+    const size_t xo = (size_t)ntri_arrays * T;
+    for (int64_t i = 0; i < M; ++i) {
+        const int64_t v = p->tree.perm[i];
+        for (int k = 0; k < 3; ++k) geo[xo + (size_t)k * M + i] = m.xyz[3 * v + k];
+    }
+    p->d_geo.upload(ctx, geo);
+    const double *G = p->d_geo.as<double>();
+    GeoDev &g = p->g;
+    g = GeoDev{};
+    g.M = M;
+    g.T = T;
+    const double **fields[18] = {&g.ax, &g.ay, &g.az, &g.bx, &g.by, &g.bz, &g.cx, &g.cy, &g.cz,
+                                 &g.tcx, &g.tcy, &g.tcz, &g.nx, &g.ny, &g.nz, &g.d, &g.h, &g.area};
+    for (int k = 0; k < 18; ++k) *fields[k] = G + (size_t)k * T;
+    g.q6x = G + (size_t)21 * T;
+    g.q6y = G + (size_t)27 * T;
+    g.q6z = G + (size_t)33 * T;
+    g.q6wl = G + (size_t)39 * T;
+    g.xx = G + xo;
+    g.xy = G + xo + M;
+    g.xz = G + xo + 2 * (size_t)M;
+    // patches in tree order, triangle vertex ids, vertex id per tree position
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> pat(M);
+    for (int64_t t = 0; t < T; ++t)
+        for (int c = 0; c < 3; ++c) pat[p->inv_perm[m.tri[3 * t + c]]].push_back({(int32_t)t, c});
+    p->pptr.assign(M + 1, 0);
+    p->ptri.clear();
+    p->ploc.clear();
+    p->patch_prefix.assign(M + 1, 0.0);
+    for (int64_t i = 0; i < M; ++i) {
+        std::sort(pat[i].begin(), pat[i].end());
+        for (const auto &e : pat[i]) {
+            p->ptri.push_back(e.first);
+            p->ploc.push_back(e.second);
+        }
+        if (p->ptri.size() > (size_t)INT32_MAX) throw Error{GACA_ERR_UNSUPPORTED, "P1 patches too large"};
+        p->pptr[i + 1] = (int32_t)p->ptri.size();
+        p->patch_prefix[i + 1] = p->patch_prefix[i] + (double)pat[i].size();
+    }
+    const size_t np = p->ptri.size();
+    std::vector<int32_t> ints((size_t)(M + 1) + 2 * np + 3 * (size_t)T + (size_t)M);
+    size_t o = 0;
+    std::copy(p->pptr.begin(), p->pptr.end(), ints.begin());
+    o += M + 1;
+    std::copy(p->ptri.begin(), p->ptri.end(), ints.begin() + o);
+    o += np;
+    std::copy(p->ploc.begin(), p->ploc.end(), ints.begin() + o);
+    o += np;
+    for (int c = 0; c < 3; ++c)
+        for (int64_t t = 0; t < T; ++t) ints[o + (size_t)c * T + t] = m.tri[3 * t + c];
+    o += 3 * (size_t)T;
+    for (int64_t i = 0; i < M; ++i) ints[o + i] = (int32_t)p->tree.perm[i];
+    p->d_p1i.upload(ctx, ints);
+    const int32_t *I = p->d_p1i.as<int32_t>();
+    g.pptr = I;
+    g.ptri = I + (M + 1);
+    g.ploc = I + (M + 1) + np;
+    g.tv0 = I + (M + 1) + 2 * np;
+    g.tv1 = g.tv0 + T;
+    g.tv2 = g.tv1 + T;
+    g.dvid = g.tv2 + T;
+    upload_quad(p);
+    p->d_perm.upload(ctx, p->tree.perm);
+    // near blocks: one pair list; the host counts the quadrature points of every pair with
+    // the device's per-triangle rule (algorithmic work of the near field)
+    p->nblocks.clear();
+    int64_t off = 0;
+    std::vector<NearPair> pairs;
+    const double nm2 = (double)p->opt.quad_mid * p->opt.quad_mid;
+    const double nn2 = (double)p->opt.quad_near * p->opt.quad_near;
+    double pts = 0.0;
+    for (size_t b = 0; b < p->part.near.size(); ++b) {
+        const auto &nb = p->part.near[b];
+        NearBlockDev d{(int32_t)nb[0], (int32_t)nb[1], (int32_t)nb[2], (int32_t)nb[3], off};
+        p->nblocks.push_back(d);
+        off += nb[1] * nb[3] * (int64_t)p->L;
+        if (nb[1] > 32767 || nb[3] > 32767)
+            throw Error{GACA_ERR_UNSUPPORTED, "near block side above 32767"};
+        for (int64_t i = 0; i < nb[1]; ++i) {
+            const int64_t vi = p->tree.perm[nb[0] + i];
+            const double *x = &m.xyz[3 * vi];
+            for (int64_t j = 0; j < nb[3]; ++j) {
+                pairs.push_back(NearPair{(int32_t)b, (int16_t)i, (int16_t)j});
+                const int64_t tj = nb[2] + j;
+                for (int32_t e = p->pptr[tj]; e < p->pptr[tj + 1]; ++e) {
+                    const int64_t t = p->ptri[e];
+                    if (m.tri[3 * t] == vi || m.tri[3 * t + 1] == vi || m.tri[3 * t + 2] == vi) continue;
+                    double dv[3];
+                    for (int k = 0; k < 3; ++k) dv[k] = x[k] - m.cen[3 * t + k];
+                    const double qd = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]) / m.hmax[t];
+                    pts += qd >= 4.0 ? 6.0 : (qd >= 2.0 ? nm2 : nn2);
+                }
+            }
+        }
+    }
+    p->near_elems = off;
+    p->p1_near_points = pts;
+    p->d_nblocks.upload(ctx, p->nblocks);
+    for (int t = 0; t < kNumTiers; ++t) {
+        p->npairs[t] = t == 0 ? (int64_t)pairs.size() : 0;
+        if (t == 0) p->d_pairs[t].upload(ctx, pairs);
+    }
+    set_leaves(p);
 }
 
 static void upload_freq(gaca_problem *p) {
@@ -749,7 +961,8 @@ gaca_status gaca_problem_create(gaca_context *ctx, const double *xyz, int64_t nv
         REQUIRE(ctx && out, "null context or output");
         REQUIRE(s_re && s_im, "null frequencies");
         REQUIRE(L >= 1 && L <= 1024, "L must be in [1, 1024]");
-        REQUIRE(scheme == GACA_COLLOCATION_P0 || scheme == GACA_GALERKIN_P0, "bad scheme");
+        REQUIRE(scheme == GACA_COLLOCATION_P0 || scheme == GACA_GALERKIN_P0 ||
+                    scheme == GACA_COLLOCATION_P1, "bad scheme");
         auto p = std::make_unique<gaca_problem>();
         p->attach(ctx);
         if (opt) p->opt = *opt;
@@ -768,6 +981,12 @@ gaca_status gaca_problem_create(gaca_context *ctx, const double *xyz, int64_t nv
         p->scheme = scheme;
         p->mesh.init(xyz, nv, tri, M);
         p->M = M;
+        if (scheme == GACA_COLLOCATION_P1) {
+            if (p->opt.precision == GACA_MIXED)
+                throw Error{GACA_ERR_UNSUPPORTED, "the P1 double layer is built in FP64 only"};
+            p1_dofs(p->mesh, p->dofs);
+            p->M = nv;
+        }
         p->L = L;
         REQUIRE(p->opt.near_aca == 0 || p->opt.near_aca == 1, "near_aca must be 0 or 1");
         if (p->opt.near_aca && L > kNearAcaMaxFreq)
@@ -780,10 +999,10 @@ gaca_status gaca_problem_create(gaca_context *ctx, const double *xyz, int64_t nv
         for (int l = 0; l < L; ++l)
             if (!(s_re[L - 1 - l] == s_re[l] && s_im[L - 1 - l] == -s_im[l])) mir = false;
         p->mirror = mir;
-        p->tree.build(p->mesh, p->opt.leaf_size);
+        p->tree.build(scheme == GACA_COLLOCATION_P1 ? p->dofs : p->mesh, p->opt.leaf_size);
         p->part.build(p->tree, p->opt.eta);
-        p->inv_perm.assign(M, 0);
-        for (int64_t t = 0; t < M; ++t) p->inv_perm[p->tree.perm[t]] = t;
+        p->inv_perm.assign(p->M, 0);
+        for (int64_t t = 0; t < p->M; ++t) p->inv_perm[p->tree.perm[t]] = t;
         GACA_HIP_CHECK(hipSetDevice(ctx->device));
         upload_problem(p.get());
         upload_freq(p.get());
@@ -1100,8 +1319,14 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
     // algorithmic work model (flops; a complex multiply-add is 8): per quadrature point x
     // frequency the single layer costs 105 (distance 8, sqrt 13, exp 31, sincos 36,
     // 1/(4 pi r) 8, weight and accumulation 9), the double layer 113
-    auto f_eval_of = [&](int kern) { return dense ? 0.0 : (kern == 1 ? 113.0 : 105.0); };
-    const double qpe = h->kernel == 2 ? 36.0 : 6.0;
+    auto f_eval_of = [&](int kern) { return dense ? 0.0 : (kern == 1 || kern == 3 ? 113.0 : 105.0); };
+    // quadrature points per entry: 6 (collocation), 36 (Galerkin), 6 per triangle of the
+    // column vertex's patch (P1; the block's mean over its columns)
+    auto qpe_of = [&](const FarBlockDev &d) {
+        if (h->kernel == 3)
+            return 6.0 * (p->patch_prefix[d.c0 + d.n] - p->patch_prefix[d.c0]) / std::max(1, d.n);
+        return h->kernel == 2 ? 36.0 : 6.0;
+    };
     double ms_phase[4] = {0, 0, 0, 0}, ms_kind[4] = {0, 0, 0, 0}, fl_phase[4] = {0, 0, 0, 0};
     double by_phase[4] = {0, 0, 0, 0};   // algorithmic HBM bytes of the face and expand phases
     const double fe_bytes = mixed ? 8.0 : 16.0;   // one face element
@@ -1304,6 +1529,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                 ntile += A.ntile;
                 cnt[kd]++;
                 ha[a] = A;
+                const double qpe = qpe_of(d);
                 evals += (double)mn * qpe;
                 fl_face += (double)mn * (qpe * f_eval_of(d.kern) + 8.0 * ell_h[lb]);
                 // the previous faces read once, the new face written once
@@ -1468,6 +1694,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                         fl_phase[1] += f;
                         fl_kind[kd] += f;
                     }
+                    const double qpe = qpe_of(d);
                     fl_phase[3] += (double)L * qpe * f_eval_of(d.kern) + 16.0 * L * ell + 8.0 * (ell + 1.0) * (ell + 1.0);
                     evals += (double)L * qpe;
                 } else {
@@ -1813,6 +2040,8 @@ static bool build_ops(gaca_problem *p, const std::vector<gaca_kernel> &kernels,
         REQUIRE(kernel == GACA_SLP || kernel == GACA_DLP, "bad kernel");
         if (p->scheme == GACA_GALERKIN_P0 && kernel != GACA_SLP)
             throw Error{GACA_ERR_UNSUPPORTED, "Galerkin is available for the single layer only"};
+        if (p->scheme == GACA_COLLOCATION_P1 && kernel != GACA_DLP)
+            throw Error{GACA_ERR_UNSUPPORTED, "the P1 scheme has the double layer only"};
     }
     gaca_context *ctx = p->ctx;
     GACA_HIP_CHECK(hipSetDevice(ctx->device));
@@ -1855,7 +2084,10 @@ static bool build_ops(gaca_problem *p, const std::vector<gaca_kernel> &kernels,
             GACA_HIP_CHECK(hipEventRecord(ev[1 + 2 * w], st));
             double2 *n64 = mixed ? nullptr : h->d_near.as<double2>();
             float2 *n32 = mixed ? h->d_near.as<float2>() : nullptr;
-            for (int t = 0; t < kNumTiers; ++t) {
+            if (p->scheme == GACA_COLLOCATION_P1)
+                launch_near_p1(p->g, p->q, p->f, p->d_pairs[0].as<NearPair>(), p->npairs[0],
+                               p->d_nblocks.as<NearBlockDev>(), n64, st);
+            for (int t = 0; t < kNumTiers && p->scheme != GACA_COLLOCATION_P1; ++t) {
                 if (p->scheme == GACA_GALERKIN_P0)
                     launch_near_galerkin(t, p->g, p->q, p->f, p->d_pairs[t].as<NearPair>(),
                                          p->npairs[t], p->d_nblocks.as<NearBlockDev>(), n64, n32, st);
@@ -1896,6 +2128,7 @@ static bool build_ops(gaca_problem *p, const std::vector<gaca_kernel> &kernels,
         }
         double evn = 0.0;
         for (int t = 0; t < kNumTiers; ++t) evn += (double)p->npairs[t] * le * qp[t];
+        if (p->scheme == GACA_COLLOCATION_P1) evn = p->p1_near_points * le;
         h->st.near_kernel_evals = evn;
         h->st.ms_far = h->st.ms_far_kernel;
         h->st.ms_total = ms_total;
@@ -2038,6 +2271,8 @@ gaca_status gaca_build_both(gaca_problem *p, gaca_hmatrix **slp_out, gaca_hmatri
         REQUIRE(p && slp_out && dlp_out, "null argument");
         if (p->scheme == GACA_GALERKIN_P0)
             throw Error{GACA_ERR_UNSUPPORTED, "Galerkin is available for the single layer only"};
+        if (p->scheme == GACA_COLLOCATION_P1)
+            throw Error{GACA_ERR_UNSUPPORTED, "the P1 scheme has the double layer only"};
         std::vector<std::unique_ptr<gaca_hmatrix>> hs;
         capped = build_tuned(p, {GACA_SLP, GACA_DLP}, hs);
         *slp_out = hs[0].release();
@@ -2762,13 +2997,17 @@ gaca_status gaca_eval_entries(gaca_problem *p, gaca_kernel kernel, int64_t n, co
         REQUIRE(i && j && k && far && out, "null argument");
         REQUIRE(!p->synthetic, "entries need a mesh problem");
         std::vector<int32_t> rows(n), cols(n), ks(n), tiers(n);
+        if (p->scheme == GACA_COLLOCATION_P1 && kernel != GACA_DLP)
+            throw Error{GACA_ERR_UNSUPPORTED, "the P1 scheme has the double layer only"};
         for (int64_t t = 0; t < n; ++t) {
             REQUIRE(i[t] >= 0 && i[t] < p->M && j[t] >= 0 && j[t] < p->M, "element id out of range");
             REQUIRE(k[t] >= 0 && k[t] < p->L, "frequency index out of range");
             rows[t] = (int32_t)p->inv_perm[i[t]];
             cols[t] = (int32_t)p->inv_perm[j[t]];
             ks[t] = k[t];
-            if (p->scheme == GACA_GALERKIN_P0)
+            if (p->scheme == GACA_COLLOCATION_P1)
+                tiers[t] = far[t] ? 1 : 0;   // the far flag (tiers are chosen per triangle)
+            else if (p->scheme == GACA_GALERKIN_P0)
                 tiers[t] = i[t] == j[t] ? 5 : (far[t] ? 0 : galerkin_tier(p->mesh, i[t], j[t]));
             else
                 tiers[t] = far[t] ? (i[t] == j[t] ? TIER_SELF : TIER_FAR6)
@@ -2783,8 +3022,12 @@ gaca_status gaca_eval_entries(gaca_problem *p, gaca_kernel kernel, int64_t n, co
         dk.upload(ctx, ks);
         dt.upload(ctx, tiers);
         dout.alloc(ctx, n * sizeof(double2));
-        launch_eval(p->kid(kernel), p->g, p->q, p->f, n, dr.as<int32_t>(), dc.as<int32_t>(), dk.as<int32_t>(),
-                    dt.as<int32_t>(), dout.as<double2>(), ctx->stream);
+        if (p->scheme == GACA_COLLOCATION_P1)
+            launch_eval_p1(p->g, p->q, p->f, n, dr.as<int32_t>(), dc.as<int32_t>(), dk.as<int32_t>(),
+                           dt.as<int32_t>(), dout.as<double2>(), ctx->stream);
+        else
+            launch_eval(p->kid(kernel), p->g, p->q, p->f, n, dr.as<int32_t>(), dc.as<int32_t>(),
+                        dk.as<int32_t>(), dt.as<int32_t>(), dout.as<double2>(), ctx->stream);
         GACA_HIP_CHECK(hipGetLastError());
         GACA_HIP_CHECK(hipStreamSynchronize(ctx->stream));
         GACA_HIP_CHECK(hipMemcpy(out, dout.ptr, n * sizeof(double2), hipMemcpyDeviceToHost));
@@ -2804,6 +3047,8 @@ gaca_status gaca_eval_far_entries_mixed(gaca_problem *p, gaca_kernel kernel, int
         REQUIRE(il && jl && k && out, "null argument");
         if (p->scheme == GACA_GALERKIN_P0 && kernel != GACA_SLP)
             throw Error{GACA_ERR_UNSUPPORTED, "Galerkin is available for the single layer only"};
+        if (p->scheme == GACA_COLLOCATION_P1)
+            throw Error{GACA_ERR_UNSUPPORTED, "the P1 double layer has no mixed-precision path"};
         const auto &fb = p->part.far[far_block];
         FarBlockDev d{};
         d.r0 = (int32_t)fb[0];

@@ -17,11 +17,17 @@ SMALL = dict(name="cube768", mesh=("cube", 8), L=16, c0=10.0, rho=0.9, leaf=16, 
              eps=1e-4, scheme="collocation")
 SMALL_GAL = dict(name="lshape768", mesh=("lshape", 4), L=16, c0=10.0, rho=0.9, leaf=16,
                  eta=1.0, eps=1e-4, scheme="galerkin")
+# small P1 double layer workload: the same cube, its 386 vertices as degrees of freedom
+SMALL_P1 = dict(name="p1cube386", mesh=("cube", 8), L=16, c0=10.0, rho=0.9, leaf=16,
+                eta=1.0, eps=1e-4, scheme="p1")
 
 
 def workload(name):
     if name == "cube768":
         cfg = dict(SMALL)
+        xyz, tri = cube_mesh(8)
+    elif name == "p1cube386":
+        cfg = dict(SMALL_P1)
         xyz, tri = cube_mesh(8)
     elif name == "lshape768":
         # small Galerkin workload: reentrant-corner cube, 1/8 grid (768 triangles)

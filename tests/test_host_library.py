@@ -107,3 +107,19 @@ def test_invalid_meshes_rejected():
         gaca.partition_host(x2, tri, 8, 1.0)
     with pytest.raises(GacaError):
         gaca.partition_host(xyz, tri, 0, 1.0)
+
+
+@pytest.mark.parametrize("mesh,leaf", [("cube8", 16), ("sphere3", 16), ("lshape2", 8)])
+def test_p1_partition_matches_oracle(mesh, leaf):
+    """Vertex tree and partition of the P1 double layer: identical to the oracle's."""
+    from inputs import cube_mesh, icosphere_mesh, lshape_mesh
+    from oracle.tree import build_partition, build_tree_p1
+    import paper_2312_11219_amd as gaca
+    xyz, tri = {"cube8": lambda: cube_mesh(8), "sphere3": lambda: icosphere_mesh(3),
+                "lshape2": lambda: lshape_mesh(2)}[mesh]()
+    perm, far, near = gaca.partition_host(xyz, tri, leaf, 1.0, scheme="p1")
+    operm, root = build_tree_p1(xyz, tri, leaf)
+    ofar, onear = build_partition(root, 1.0)
+    assert np.array_equal(perm, operm)
+    assert np.array_equal(far, np.array(ofar, dtype=np.int64).reshape(-1, 4))
+    assert np.array_equal(near, np.array(onear, dtype=np.int64).reshape(-1, 4))
