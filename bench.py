@@ -335,7 +335,11 @@ def main():
     cfg = get_config(args.config)
     xyz, tri = mesh_for_config(args.config)
     s = circle_frequencies(cfg["L"], cfg["c0"], cfg["rho"])
-    M, L = tri.shape[0], cfg["L"]
+    p1 = cfg.get("scheme") == "p1"
+    # operator size: elements, or vertices for the P1 double layer (which has no mixed path)
+    M, L = (xyz.shape[0] if p1 else tri.shape[0]), cfg["L"]
+    if p1:
+        args.no_mixed = True
     kernels = cfg["kernels"]
     sample = desc = cpu = None
     if not args.no_cpu_baseline:
@@ -370,8 +374,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{cfg['name']}: {cfg['mesh'][0]} mesh ({M} triangles), "
-                               f"{cfg.get('scheme', 'collocation')} P0 {ops}, L={L} circle "
+        "config": {"workload": f"{cfg['name']}: {cfg['mesh'][0]} mesh ({tri.shape[0]} triangles"
+                               + (f", {M} vertices), collocation at the vertices, P1 {ops}" if p1 else
+                                  f"), {cfg.get('scheme', 'collocation')} P0 {ops}")
+                               + f", L={L} circle "
                                f"frequencies c0={cfg['c0']} rho={cfg['rho']}, leaf {cfg['leaf']}, "
                                f"eta {cfg['eta']}, eps {cfg['eps']}, eps_aca {cfg['eps_aca']}, "
                                f"FP64 build + apply with {args.nrhs} rhs per step",
