@@ -1221,7 +1221,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
         const double m = (double)far[b][1], n = (double)far[b][3], mn = m * n;
         const double rho_max = std::min(m, n);
         const double tiles = far_kind((int)m, (int)n, mixed) == 3 ? std::ceil(m / 32.0) * std::ceil(n / 32.0) : 1.0;
-        return rho_max * (m + n) * es + (rg + 1) * mn * es + rg * (double)(L + rcap) * 16 +
+        return 2.0 * rho_max * (m + n) * es + (rg + 1) * mn * es + rg * (double)(L + rcap) * 16 +
                tiles * PS * 8 + sizeof(FarStateDev) + sizeof(FarBlockDev) + rcap * 32.0 + L + 64;
     };
     double rguess = std::min(rcap, 24);
@@ -1383,7 +1383,10 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
         ensure(ctx, W.hs, (size_t)nb * rcap * sizeof(int64_t));
         ensure(ctx, W.fs, (size_t)nb * rcap * sizeof(int64_t));
         ensure(ctx, W.usedk, (size_t)nb * L);
-        ensure(ctx, W.uw, (size_t)std::max<int64_t>(uw_total, 1) * es);
+        // two slots of U, W scratch, alternating by iteration: the copy of the factors
+        // accepted in one iteration reads its slot while the next iteration's face ACAs
+        // write the other
+        ensure(ctx, W.uw, 2 * (size_t)std::max<int64_t>(uw_total, 1) * es);
         ensure(ctx, W.act, nb * sizeof(FarActive));
         ensure(ctx, W.status, nb * 2 * sizeof(int32_t));
         ensure(ctx, W.copies, nb * sizeof(FarCopy));
@@ -1402,7 +1405,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
         int64_t hused = 0, fused = 0;
         int iter = 0;
 
-        auto batch_dev = [&]() {
+        auto batch_dev = [&](int slot) {
             FarBatchDev bd{};
             bd.blk = W.blk.as<FarBlockDev>();
             bd.st = W.state.as<FarStateDev>();
@@ -1412,7 +1415,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             bd.usedk = W.usedk.as<unsigned char>();
             bd.hpool = W.hpool.ptr;
             bd.fgpool = W.fgpool.as<double2>();
-            bd.uw = W.uw.ptr;
+            bd.uw = static_cast<unsigned char *>(W.uw.ptr) + (size_t)slot * std::max<int64_t>(uw_total, 1) * es;
             bd.part = W.part.as<double>();
             bd.map_chunk = W.map_chunk.as<int32_t>();
             bd.map_tile = W.map_tile.as<int32_t>();
@@ -1446,7 +1449,8 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             GACA_HIP_CHECK(hipMemcpyAsync(W.copies.ptr, W.h_copies.ptr, chunks.size() * sizeof(FarCopy),
                                           hipMemcpyHostToDevice, cs));
             void *const arenas[2] = {h->d_arena.ptr, H[nh - 1]->d_arena.ptr};
-            launch_far_copy(batch_dev(), W.copies.as<FarCopy>(), (int)chunks.size(), arenas,
+            // the pending crosses were accepted in the previous iteration: its U, W slot
+            launch_far_copy(batch_dev((iter - 1) & 1), W.copies.as<FarCopy>(), (int)chunks.size(), arenas,
                             o_cross_off.as<int64_t>(), cs);
             GACA_HIP_CHECK(hipGetLastError());
             ++n_launch;
@@ -1544,11 +1548,12 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             ensure(ctx, W.part, (size_t)std::max<int64_t>(nparts, 1) * PS * sizeof(double));
             GACA_HIP_CHECK(hipMemcpyAsync(W.act.ptr, W.h_act.ptr, nact * sizeof(FarActive),
                                           hipMemcpyHostToDevice, s0));
-            // the copy reads the face factors that this iteration's ACA overwrites: it runs
-            // beside the map and face phases, and every ACA launch waits for it
-            const bool copied = flush_copies(ks[0]);
-            if (copied) GACA_HIP_CHECK(hipEventRecord(ev[EV_C], ks[0]));
-            const FarBatchDev bd = batch_dev();
+            // the copy reads the previous iteration's U, W slot beside the map and face phases;
+            // this iteration's ACAs write the other slot, so only the class-0 launches (same
+            // stream) run after it.  The copy of two iterations ago, which read the slot
+            // written now, completed before that iteration's status was read back.
+            flush_copies(ks[0]);
+            const FarBatchDev bd = batch_dev(iter & 1);
             const FarActive *dact = W.act.as<FarActive>();
             const int nlarge = recomp ? nact : cnt[3];
             // act is ordered kind 3, 2, 1, 0
@@ -1558,8 +1563,6 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             launch_far_face(fk, p->g, p->f, bd, dact, nchunk, s0);
             GACA_HIP_CHECK(hipEventRecord(ev[EV_F1], s0));
             for (int k = 0; k < 3; ++k) GACA_HIP_CHECK(hipStreamWaitEvent(ks[k], ev[EV_F1], 0));
-            if (copied)
-                for (int k = 1; k < 4; ++k) GACA_HIP_CHECK(hipStreamWaitEvent(ks[k], ev[EV_C], 0));
             // large faces: 512 threads and ~104 KB of LDS history, one face per CU (the
             // longest face bounds the phase); medium faces (sides <= kMediumSide) 256 threads
             // and 32 KB, several per CU, on the kind-2 stream, so that they do not hold whole
@@ -1728,7 +1731,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
         GACA_HIP_CHECK(hipMemcpyAsync(W.gathers.ptr, W.h_gathers.ptr, gth.size() * sizeof(FarGather),
                                       hipMemcpyHostToDevice, s0));
         double2 *const fibs[2] = {h->d_fib.as<double2>(), H[nh - 1]->d_fib.as<double2>()};
-        launch_far_gather(batch_dev(), W.gathers.as<FarGather>(), nb, fibs, o_fib_off.as<int64_t>(), s0);
+        launch_far_gather(batch_dev(0), W.gathers.as<FarGather>(), nb, fibs, o_fib_off.as<int64_t>(), s0);
         GACA_HIP_CHECK(hipGetLastError());
         ++n_launch;
         GACA_HIP_CHECK(hipStreamSynchronize(s0));
