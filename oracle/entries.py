@@ -15,7 +15,7 @@ from . import quadrature as Q
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "entries.c")
-_SRCS = [_SRC, os.path.join(_HERE, "galerkin.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "galerkin.c"), os.path.join(_HERE, "galerkin_p1.c")]
 _LIB = os.path.join(_HERE, "_oracle_entries.so")
 _lib = None
 
@@ -55,6 +55,16 @@ def _load():
             P, P, P, P, P, ctypes.c_int, P, P, ctypes.c_int64, P, P, P, P, ctypes.c_int, P,
             ctypes.c_int, P, ctypes.c_int, P, P]
         lib.oracle_p1_dlp_entries.restype = None
+        lib.oracle_p1_galerkin_entries.argtypes = [
+            ctypes.c_int, P, P, P, P, P, ctypes.c_int, P, P, ctypes.c_int64, P, P, P, P,
+            ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int, P, P]
+        lib.oracle_p1_galerkin_entries.restype = None
+        lib.oracle_p1_pair_local.argtypes = [
+            ctypes.c_int, P, P, ctypes.c_int, P, P, ctypes.c_int64, P, P, P, P, ctypes.c_int, P,
+            ctypes.c_int, P, ctypes.c_int, P, P]
+        lib.oracle_p1_pair_local.restype = None
+        lib.oracle_ss_monomial.argtypes = [ctypes.c_int] * 6 + [P]
+        lib.oracle_ss_monomial.restype = ctypes.c_double
         _lib = lib
     return _lib
 
