@@ -57,8 +57,19 @@ typedef enum {
  * kernel at vertex i weighted by the hat function of j).  For GACA_COLLOCATION_P1 the
  * operator's rows and columns are the nv vertices (original vertex ids, tree-permuted like
  * the elements of the other schemes), precision must be GACA_FP64 and only GACA_DLP builds. */
-typedef enum { GACA_COLLOCATION_P0 = 0, GACA_GALERKIN_P0 = 1, GACA_COLLOCATION_P1 = 2 } gaca_scheme;
-typedef enum { GACA_SLP = 0, GACA_DLP = 1 } gaca_kernel;
+/* GACA_GALERKIN_P1: the Galerkin operators of the Neumann problem (eq. bie_semi_neum) with
+ * linear continuous test and trial functions, rows and columns the nv vertices as for
+ * GACA_COLLOCATION_P1: the hypersingular operator GACA_HYP (in its form after integration by
+ * parts: G_s times curl phi_i . curl phi_j plus s^2 n_x . n_y G_s phi_i phi_j) and the adjoint
+ * double layer GACA_ADLP (dG/dn_x).  FP64 only.  Touching triangle pairs use the
+ * Sauter-Schwab maps with n_touch Gauss points in each of the four variables. */
+typedef enum {
+    GACA_COLLOCATION_P0 = 0,
+    GACA_GALERKIN_P0 = 1,
+    GACA_COLLOCATION_P1 = 2,
+    GACA_GALERKIN_P1 = 3
+} gaca_scheme;
+typedef enum { GACA_SLP = 0, GACA_DLP = 1, GACA_HYP = 2, GACA_ADLP = 3 } gaca_kernel;
 /* FP64: every step in FP64.  MIXED: far-field faces evaluated and stored in FP32 complex
  * with a per-(block, frequency) scale, FP64 fibres, norms and pivot bookkeeping; near
  * field computed in FP64 and stored in FP32. */

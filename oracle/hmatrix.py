@@ -21,14 +21,17 @@ from .entries import Geometry, collocation_entries
 
 
 class Problem:
-    """scheme: "collocation" (P0, centroids), "galerkin" (P0) or "p1" (the P1 double layer
-    collocated at the vertices: rows and columns are vertices)."""
+    """scheme: "collocation" (P0, centroids), "galerkin" (P0), "p1" (the P1 double layer
+    collocated at the vertices: rows and columns are vertices) or "galerkin_p1" (the
+    hypersingular operator and the adjoint double layer with P1 test and trial functions;
+    n_touch points per variable of the regularising maps)."""
 
-    def __init__(self, xyz, tri, s, leaf_size, eta, scheme="collocation"):
+    def __init__(self, xyz, tri, s, leaf_size, eta, scheme="collocation", n_touch=None):
         self.s = np.asarray(s, dtype=np.complex128)
         self.L = self.s.shape[0]
         self.scheme = scheme
-        if scheme == "p1":
+        self.n_touch = n_touch
+        if scheme in ("p1", "galerkin_p1"):
             from .entries import P1Geometry
             self.geom = P1Geometry(xyz, tri)
             self.perm, self.root = T.build_tree_p1(self.geom.xyz, self.geom.tri, leaf_size)
@@ -48,7 +51,13 @@ class Problem:
         ii = np.repeat(rows, n)
         jj = np.tile(cols, m)
         flag = np.full(ii.shape[0], 1 if far else 0, dtype=np.int32)
-        if self.scheme == "p1":
+        if self.scheme == "galerkin_p1":
+            from .galerkin_p1 import N_SS, p1_galerkin_entries
+            if kernel not in ("hyp", "adlp"):
+                raise ValueError("the Galerkin P1 scheme has the hypersingular operator and the adjoint double layer")
+            vals = p1_galerkin_entries(self.geom, kernel, self.s, ii, jj, flag,
+                                       n_ss=self.n_touch or N_SS)
+        elif self.scheme == "p1":
             from .entries import p1_dlp_entries
             if kernel != "dlp":
                 raise ValueError("the P1 scheme has the double layer only")

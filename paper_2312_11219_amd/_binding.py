@@ -16,8 +16,8 @@ I32, I64, F64, U64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_u
 ABI_VERSION = 3   # GACA_ABI_VERSION of include/gaca.h that these structures follow
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "STATE", -5: "NOT_CONVERGED",
           -6: "UNSUPPORTED"}
-SCHEMES = {"collocation": 0, "galerkin": 1, "p1": 2}
-KERNELS = {"slp": 0, "dlp": 1}
+SCHEMES = {"collocation": 0, "galerkin": 1, "p1": 2, "galerkin_p1": 3}
+KERNELS = {"slp": 0, "dlp": 1, "hyp": 2, "adlp": 3}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 MODES = {"sum": 0, "per_freq": 1}
 
@@ -238,7 +238,7 @@ class Problem:
         self.s = s
         self.L = s.shape[0]
         # operator size: elements, or vertices for the P1 double layer
-        self.M = self.xyz.shape[0] if scheme == "p1" else self.tri.shape[0]
+        self.M = self.xyz.shape[0] if scheme in ("p1", "galerkin_p1") else self.tri.shape[0]
         s_re = np.ascontiguousarray(s.real)
         s_im = np.ascontiguousarray(s.imag)
         self.opt = options_default(**options)

@@ -32,6 +32,7 @@
 #include "device_util.h"
 #include "entries_dev.h"
 #include "galerkin_dev.h"
+#include "galerkin_p1_dev.h"
 #include "kernels.h"
 
 namespace gaca {
@@ -58,6 +59,10 @@ __device__ __forceinline__ FT face_entry(const GeoDev &g, const FreqDev &f, cons
     if constexpr (KERNEL == 3) {   // P1 double layer (FP64 only)
         double er, ei;
         p1_far_entry(g, gi, gj, f.re[kk], f.im[kk], er, ei);
+        return from_d2<FT>(make_double2(er, ei));
+    } else if constexpr (KERNEL == 4 || KERNEL == 5) {   // Galerkin P1 D / K' (FP64 only)
+        double er, ei;
+        gp1_far_entry<KERNEL - 4>(g, QuadDev{}, gi, gj, f.re, f.im, kk, er, ei);
         return from_d2<FT>(make_double2(er, ei));
     } else if constexpr (KERNEL == 2) {
         if constexpr (sizeof(FT) == sizeof(double2)) {
@@ -104,6 +109,8 @@ __device__ __forceinline__ double2 fibre_entry(const GeoDev &g, const FreqDev &f
     double er, ei;
     if constexpr (KERNEL == 3)
         p1_far_entry(g, gi, gj, f.re[kk], f.im[kk], er, ei);
+    else if constexpr (KERNEL == 4 || KERNEL == 5)
+        gp1_far_entry<KERNEL - 4>(g, QuadDev{}, gi, gj, f.re, f.im, kk, er, ei);
     else if constexpr (KERNEL == 2)
         entry_gal36(g, gi, gj, f.re[kk], f.im[kk], er, ei);
     else
@@ -1885,6 +1892,8 @@ void launch_far_face(int kernel, const GeoDev &g, const FreqDev &f, const FarBat
         if (kernel == 0) face_dispatch<0, false, false>(g, f, bd, act, nchunk, st);
         else if (kernel == 1) face_dispatch<1, false, false>(g, f, bd, act, nchunk, st);
         else if (kernel == 3) face_dispatch<3, false, false>(g, f, bd, act, nchunk, st);
+        else if (kernel == 4) face_dispatch<4, false, false>(g, f, bd, act, nchunk, st);
+        else if (kernel == 5) face_dispatch<5, false, false>(g, f, bd, act, nchunk, st);
         else face_dispatch<2, false, false>(g, f, bd, act, nchunk, st);
     } else {
         if (kernel == 0) face_dispatch<0, false, true>(g, f, bd, act, nchunk, st);
@@ -1982,6 +1991,8 @@ void launch_far_tail(int kernel, const GeoDev &g, const FreqDev &f, const AcaPar
         if (kernel == 0) tail_dispatch<0, false, false>(g, f, P, bd, act, nact, nlarge, st);
         else if (kernel == 1) tail_dispatch<1, false, false>(g, f, P, bd, act, nact, nlarge, st);
         else if (kernel == 3) tail_dispatch<3, false, false>(g, f, P, bd, act, nact, nlarge, st);
+        else if (kernel == 4) tail_dispatch<4, false, false>(g, f, P, bd, act, nact, nlarge, st);
+        else if (kernel == 5) tail_dispatch<5, false, false>(g, f, P, bd, act, nact, nlarge, st);
         else tail_dispatch<2, false, false>(g, f, P, bd, act, nact, nlarge, st);
     } else {
         if (kernel == 0) tail_dispatch<0, false, true>(g, f, P, bd, act, nact, nlarge, st);

@@ -51,6 +51,15 @@ void launch_eval_p1(const GeoDev &g, const QuadDev &q, const FreqDev &f, int64_t
                     const int32_t *rows, const int32_t *cols, const int32_t *ks,
                     const int32_t *far, double2 *out, hipStream_t st);
 
+// Galerkin P1 operators (op 0 hypersingular, 1 adjoint double layer): near field and entry
+// hook, as for the P1 double layer.
+void launch_near_gp1(int op, const GeoDev &g, const QuadDev &q, const FreqDev &f,
+                     const NearPair *pairs, int64_t npairs, const NearBlockDev *blocks,
+                     double2 *out64, hipStream_t st);
+void launch_eval_gp1(int op, const GeoDev &g, const QuadDev &q, const FreqDev &f, int64_t n,
+                     const int32_t *rows, const int32_t *cols, const int32_t *ks,
+                     const int32_t *far, double2 *out, hipStream_t st);
+
 // Near field: every pair of one tier, all frequencies, FP64 compute, stored as double2
 // (out64) or float2 (out32).
 void launch_near(int kernel, int tier, const GeoDev &g, const QuadDev &q, const FreqDev &f,

@@ -437,8 +437,10 @@ struct gaca_problem {
     DevBuf d_pairs[kNumTiers];
     int64_t npairs[kNumTiers] = {0, 0, 0, 0, 0, 0};
     int kid(gaca_kernel k) const {
+        if (scheme == GACA_GALERKIN_P1) return k == GACA_HYP ? 4 : 5;
         return scheme == GACA_GALERKIN_P0 ? 2 : scheme == GACA_COLLOCATION_P1 ? 3 : (int)k;
     }
+    bool p1() const { return scheme == GACA_COLLOCATION_P1 || scheme == GACA_GALERKIN_P1; }
     // leaves for the apply
     std::vector<int32_t> leaf_r0, leaf_m;
     // far-field launch classes run concurrently on these streams (default priority)
@@ -718,7 +720,7 @@ static void set_leaves(gaca_problem *p) {
 static void upload_problem_p1(gaca_problem *p);
 
 static void upload_problem(gaca_problem *p) {
-    if (p->scheme == GACA_COLLOCATION_P1) {
+    if (p->p1()) {
         upload_problem_p1(p);
         return;
     }
@@ -918,6 +920,11 @@ static void upload_problem_p1(gaca_problem *p) {
             for (int64_t j = 0; j < nb[3]; ++j) {
                 pairs.push_back(NearPair{(int32_t)b, (int16_t)i, (int16_t)j});
                 const int64_t tj = nb[2] + j;
+                if (p->scheme == GACA_GALERKIN_P1) {
+                    // estimate: 36 points per triangle pair of the two patches
+                    pts += 36.0 * (p->pptr[nb[0] + i + 1] - p->pptr[nb[0] + i]) * (p->pptr[tj + 1] - p->pptr[tj]);
+                    continue;
+                }
                 for (int32_t e = p->pptr[tj]; e < p->pptr[tj + 1]; ++e) {
                     const int64_t t = p->ptri[e];
                     if (m.tri[3 * t] == vi || m.tri[3 * t + 1] == vi || m.tri[3 * t + 2] == vi) continue;
@@ -962,7 +969,7 @@ gaca_status gaca_problem_create(gaca_context *ctx, const double *xyz, int64_t nv
         REQUIRE(s_re && s_im, "null frequencies");
         REQUIRE(L >= 1 && L <= 1024, "L must be in [1, 1024]");
         REQUIRE(scheme == GACA_COLLOCATION_P0 || scheme == GACA_GALERKIN_P0 ||
-                    scheme == GACA_COLLOCATION_P1, "bad scheme");
+                    scheme == GACA_COLLOCATION_P1 || scheme == GACA_GALERKIN_P1, "bad scheme");
         auto p = std::make_unique<gaca_problem>();
         p->attach(ctx);
         if (opt) p->opt = *opt;
@@ -981,9 +988,9 @@ gaca_status gaca_problem_create(gaca_context *ctx, const double *xyz, int64_t nv
         p->scheme = scheme;
         p->mesh.init(xyz, nv, tri, M);
         p->M = M;
-        if (scheme == GACA_COLLOCATION_P1) {
+        if (scheme == GACA_COLLOCATION_P1 || scheme == GACA_GALERKIN_P1) {
             if (p->opt.precision == GACA_MIXED)
-                throw Error{GACA_ERR_UNSUPPORTED, "the P1 double layer is built in FP64 only"};
+                throw Error{GACA_ERR_UNSUPPORTED, "the P1 operators are built in FP64 only"};
             p1_dofs(p->mesh, p->dofs);
             p->M = nv;
         }
@@ -999,7 +1006,7 @@ gaca_status gaca_problem_create(gaca_context *ctx, const double *xyz, int64_t nv
         for (int l = 0; l < L; ++l)
             if (!(s_re[L - 1 - l] == s_re[l] && s_im[L - 1 - l] == -s_im[l])) mir = false;
         p->mirror = mir;
-        p->tree.build(scheme == GACA_COLLOCATION_P1 ? p->dofs : p->mesh, p->opt.leaf_size);
+        p->tree.build(p->p1() ? p->dofs : p->mesh, p->opt.leaf_size);
         p->part.build(p->tree, p->opt.eta);
         p->inv_perm.assign(p->M, 0);
         for (int64_t t = 0; t < p->M; ++t) p->inv_perm[p->tree.perm[t]] = t;
@@ -1319,12 +1326,17 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
     // algorithmic work model (flops; a complex multiply-add is 8): per quadrature point x
     // frequency the single layer costs 105 (distance 8, sqrt 13, exp 31, sincos 36,
     // 1/(4 pi r) 8, weight and accumulation 9), the double layer 113
-    auto f_eval_of = [&](int kern) { return dense ? 0.0 : (kern == 1 || kern == 3 ? 113.0 : 105.0); };
+    auto f_eval_of = [&](int kern) {
+        return dense ? 0.0 : (kern == 1 || kern == 3 || kern == 5 ? 113.0 : 105.0);
+    };
     // quadrature points per entry: 6 (collocation), 36 (Galerkin), 6 per triangle of the
     // column vertex's patch (P1; the block's mean over its columns)
     auto qpe_of = [&](const FarBlockDev &d) {
         if (h->kernel == 3)
             return 6.0 * (p->patch_prefix[d.c0 + d.n] - p->patch_prefix[d.c0]) / std::max(1, d.n);
+        if (h->kernel >= 4)   // 6 x 6 points per pair of triangles of the two patches
+            return 36.0 * (p->patch_prefix[d.r0 + d.m] - p->patch_prefix[d.r0]) / std::max(1, d.m) *
+                   (p->patch_prefix[d.c0 + d.n] - p->patch_prefix[d.c0]) / std::max(1, d.n);
         return h->kernel == 2 ? 36.0 : 6.0;
     };
     double ms_phase[4] = {0, 0, 0, 0}, ms_kind[4] = {0, 0, 0, 0}, fl_phase[4] = {0, 0, 0, 0};
@@ -2040,11 +2052,15 @@ static bool build_ops(gaca_problem *p, const std::vector<gaca_kernel> &kernels,
     REQUIRE(!p->synthetic, "build needs a mesh problem");
     REQUIRE(p->opt.precision == GACA_FP64 || p->opt.precision == GACA_MIXED, "bad precision");
     for (gaca_kernel kernel : kernels) {
-        REQUIRE(kernel == GACA_SLP || kernel == GACA_DLP, "bad kernel");
+        REQUIRE(kernel == GACA_SLP || kernel == GACA_DLP || kernel == GACA_HYP || kernel == GACA_ADLP,
+                "bad kernel");
         if (p->scheme == GACA_GALERKIN_P0 && kernel != GACA_SLP)
             throw Error{GACA_ERR_UNSUPPORTED, "Galerkin is available for the single layer only"};
         if (p->scheme == GACA_COLLOCATION_P1 && kernel != GACA_DLP)
             throw Error{GACA_ERR_UNSUPPORTED, "the P1 scheme has the double layer only"};
+        if ((p->scheme == GACA_GALERKIN_P1) != (kernel == GACA_HYP || kernel == GACA_ADLP))
+            throw Error{GACA_ERR_UNSUPPORTED,
+                        "the hypersingular operator and the adjoint double layer belong to the Galerkin P1 scheme"};
     }
     gaca_context *ctx = p->ctx;
     GACA_HIP_CHECK(hipSetDevice(ctx->device));
@@ -2090,7 +2106,10 @@ static bool build_ops(gaca_problem *p, const std::vector<gaca_kernel> &kernels,
             if (p->scheme == GACA_COLLOCATION_P1)
                 launch_near_p1(p->g, p->q, p->f, p->d_pairs[0].as<NearPair>(), p->npairs[0],
                                p->d_nblocks.as<NearBlockDev>(), n64, st);
-            for (int t = 0; t < kNumTiers && p->scheme != GACA_COLLOCATION_P1; ++t) {
+            if (p->scheme == GACA_GALERKIN_P1)
+                launch_near_gp1(kernels[w] == GACA_HYP ? 0 : 1, p->g, p->q, p->f, p->d_pairs[0].as<NearPair>(),
+                                p->npairs[0], p->d_nblocks.as<NearBlockDev>(), n64, st);
+            for (int t = 0; t < kNumTiers && !p->p1(); ++t) {
                 if (p->scheme == GACA_GALERKIN_P0)
                     launch_near_galerkin(t, p->g, p->q, p->f, p->d_pairs[t].as<NearPair>(),
                                          p->npairs[t], p->d_nblocks.as<NearBlockDev>(), n64, n32, st);
@@ -2131,7 +2150,7 @@ static bool build_ops(gaca_problem *p, const std::vector<gaca_kernel> &kernels,
         }
         double evn = 0.0;
         for (int t = 0; t < kNumTiers; ++t) evn += (double)p->npairs[t] * le * qp[t];
-        if (p->scheme == GACA_COLLOCATION_P1) evn = p->p1_near_points * le;
+        if (p->p1()) evn = p->p1_near_points * le;
         h->st.near_kernel_evals = evn;
         h->st.ms_far = h->st.ms_far_kernel;
         h->st.ms_total = ms_total;
@@ -2274,8 +2293,8 @@ gaca_status gaca_build_both(gaca_problem *p, gaca_hmatrix **slp_out, gaca_hmatri
         REQUIRE(p && slp_out && dlp_out, "null argument");
         if (p->scheme == GACA_GALERKIN_P0)
             throw Error{GACA_ERR_UNSUPPORTED, "Galerkin is available for the single layer only"};
-        if (p->scheme == GACA_COLLOCATION_P1)
-            throw Error{GACA_ERR_UNSUPPORTED, "the P1 scheme has the double layer only"};
+        if (p->p1())
+            throw Error{GACA_ERR_UNSUPPORTED, "joint builds are for the P0 collocation operators"};
         std::vector<std::unique_ptr<gaca_hmatrix>> hs;
         capped = build_tuned(p, {GACA_SLP, GACA_DLP}, hs);
         *slp_out = hs[0].release();
@@ -2994,7 +3013,8 @@ gaca_status gaca_eval_entries(gaca_problem *p, gaca_kernel kernel, int64_t n, co
                               double *out) {
     return guarded([&] {
         REQUIRE(p, "null problem");
-        REQUIRE(kernel == GACA_SLP || kernel == GACA_DLP, "bad kernel");
+        REQUIRE(kernel == GACA_SLP || kernel == GACA_DLP || kernel == GACA_HYP || kernel == GACA_ADLP,
+                "bad kernel");
         REQUIRE(n >= 0, "n must be >= 0");
         if (n == 0) return;
         REQUIRE(i && j && k && far && out, "null argument");
@@ -3002,13 +3022,16 @@ gaca_status gaca_eval_entries(gaca_problem *p, gaca_kernel kernel, int64_t n, co
         std::vector<int32_t> rows(n), cols(n), ks(n), tiers(n);
         if (p->scheme == GACA_COLLOCATION_P1 && kernel != GACA_DLP)
             throw Error{GACA_ERR_UNSUPPORTED, "the P1 scheme has the double layer only"};
+        if ((p->scheme == GACA_GALERKIN_P1) != (kernel == GACA_HYP || kernel == GACA_ADLP))
+            throw Error{GACA_ERR_UNSUPPORTED,
+                        "the hypersingular operator and the adjoint double layer belong to the Galerkin P1 scheme"};
         for (int64_t t = 0; t < n; ++t) {
             REQUIRE(i[t] >= 0 && i[t] < p->M && j[t] >= 0 && j[t] < p->M, "element id out of range");
             REQUIRE(k[t] >= 0 && k[t] < p->L, "frequency index out of range");
             rows[t] = (int32_t)p->inv_perm[i[t]];
             cols[t] = (int32_t)p->inv_perm[j[t]];
             ks[t] = k[t];
-            if (p->scheme == GACA_COLLOCATION_P1)
+            if (p->p1())
                 tiers[t] = far[t] ? 1 : 0;   // the far flag (tiers are chosen per triangle)
             else if (p->scheme == GACA_GALERKIN_P0)
                 tiers[t] = i[t] == j[t] ? 5 : (far[t] ? 0 : galerkin_tier(p->mesh, i[t], j[t]));
@@ -3028,6 +3051,9 @@ gaca_status gaca_eval_entries(gaca_problem *p, gaca_kernel kernel, int64_t n, co
         if (p->scheme == GACA_COLLOCATION_P1)
             launch_eval_p1(p->g, p->q, p->f, n, dr.as<int32_t>(), dc.as<int32_t>(), dk.as<int32_t>(),
                            dt.as<int32_t>(), dout.as<double2>(), ctx->stream);
+        else if (p->scheme == GACA_GALERKIN_P1)
+            launch_eval_gp1(kernel == GACA_HYP ? 0 : 1, p->g, p->q, p->f, n, dr.as<int32_t>(), dc.as<int32_t>(),
+                            dk.as<int32_t>(), dt.as<int32_t>(), dout.as<double2>(), ctx->stream);
         else
             launch_eval(p->kid(kernel), p->g, p->q, p->f, n, dr.as<int32_t>(), dc.as<int32_t>(),
                         dk.as<int32_t>(), dt.as<int32_t>(), dout.as<double2>(), ctx->stream);
@@ -3050,8 +3076,8 @@ gaca_status gaca_eval_far_entries_mixed(gaca_problem *p, gaca_kernel kernel, int
         REQUIRE(il && jl && k && out, "null argument");
         if (p->scheme == GACA_GALERKIN_P0 && kernel != GACA_SLP)
             throw Error{GACA_ERR_UNSUPPORTED, "Galerkin is available for the single layer only"};
-        if (p->scheme == GACA_COLLOCATION_P1)
-            throw Error{GACA_ERR_UNSUPPORTED, "the P1 double layer has no mixed-precision path"};
+        if (p->p1())
+            throw Error{GACA_ERR_UNSUPPORTED, "the P1 operators have no mixed-precision path"};
         const auto &fb = p->part.far[far_block];
         FarBlockDev d{};
         d.r0 = (int32_t)fb[0];

@@ -4,6 +4,7 @@
 #include "device_util.h"
 #include "entries_dev.h"
 #include "galerkin_dev.h"
+#include "galerkin_p1_dev.h"
 #include "kernels.h"
 
 namespace gaca {
@@ -194,6 +195,63 @@ void launch_eval_p1(const GeoDev &g, const QuadDev &q, const FreqDev &f, int64_t
                     const int32_t *far, double2 *out, hipStream_t st) {
     if (n <= 0) return;
     eval_p1_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(g, q, f, n, rows, cols, ks, far, out);
+}
+
+// Galerkin P1 operators of the Neumann problem (OP 0 hypersingular, 1 adjoint double layer):
+// one thread per (pair, NF frequencies), every triangle pair of the two patches.
+template <int OP, int NF>
+__global__ void __launch_bounds__(256)
+    near_gp1_kernel(GeoDev g, QuadDev q, FreqDev f, const NearPair *__restrict__ pairs,
+                    int64_t npairs, const NearBlockDev *__restrict__ blocks, double2 *out64) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npairs) return;
+    const int l0 = blockIdx.y * NF;
+    const int nl = min(NF, f.L_eval - l0);
+    NearPair pr = pairs[p];
+    NearBlockDev B = blocks[pr.blk];
+    const int64_t i = B.r0 + pr.i, j = B.c0 + pr.j;
+    double ar[NF], ai[NF];
+    gp1_entry<OP, NF>(g, q, f, i, j, false, l0, nl, ar, ai);
+    const int64_t base = B.off + (int64_t)pr.i * f.L * B.n + pr.j;
+#pragma unroll
+    for (int t = 0; t < NF; ++t) {
+        if (t < nl) {
+            const int l = l0 + t;
+            out64[base + (int64_t)l * B.n] = make_double2(ar[t], ai[t]);
+            if (f.mirror && f.L - 1 - l != l)
+                out64[base + (int64_t)(f.L - 1 - l) * B.n] = make_double2(ar[t], -ai[t]);
+        }
+    }
+}
+
+void launch_near_gp1(int op, const GeoDev &g, const QuadDev &q, const FreqDev &f,
+                     const NearPair *pairs, int64_t npairs, const NearBlockDev *blocks,
+                     double2 *out64, hipStream_t st) {
+    if (npairs <= 0) return;
+    constexpr int NF = 2;
+    dim3 grid((unsigned)((npairs + 255) / 256), (unsigned)((f.L_eval + NF - 1) / NF));
+    if (op == 0) near_gp1_kernel<0, NF><<<grid, 256, 0, st>>>(g, q, f, pairs, npairs, blocks, out64);
+    else near_gp1_kernel<1, NF><<<grid, 256, 0, st>>>(g, q, f, pairs, npairs, blocks, out64);
+}
+
+template <int OP>
+__global__ void eval_gp1_kernel(GeoDev g, QuadDev q, FreqDev f, int64_t n, const int32_t *rows,
+                                const int32_t *cols, const int32_t *ks, const int32_t *far,
+                                double2 *out) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    double ar[1], ai[1];
+    gp1_entry<OP, 1>(g, q, f, rows[p], cols[p], far[p] != 0, ks[p], 1, ar, ai);
+    out[p] = make_double2(ar[0], ai[0]);
+}
+
+void launch_eval_gp1(int op, const GeoDev &g, const QuadDev &q, const FreqDev &f, int64_t n,
+                     const int32_t *rows, const int32_t *cols, const int32_t *ks,
+                     const int32_t *far, double2 *out, hipStream_t st) {
+    if (n <= 0) return;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (op == 0) eval_gp1_kernel<0><<<nb, 256, 0, st>>>(g, q, f, n, rows, cols, ks, far, out);
+    else eval_gp1_kernel<1><<<nb, 256, 0, st>>>(g, q, f, n, rows, cols, ks, far, out);
 }
 
 template <int KERNEL>

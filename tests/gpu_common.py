@@ -20,6 +20,10 @@ SMALL_GAL = dict(name="lshape768", mesh=("lshape", 4), L=16, c0=10.0, rho=0.9, l
 # small P1 double layer workload: the same cube, its 386 vertices as degrees of freedom
 SMALL_P1 = dict(name="p1cube386", mesh=("cube", 8), L=16, c0=10.0, rho=0.9, leaf=16,
                 eta=1.0, eps=1e-4, scheme="p1")
+# small Galerkin P1 workload (hypersingular operator, adjoint double layer): the same cube,
+# 8 frequencies, touching pairs with 6 points per variable of the regularising maps
+SMALL_GP1 = dict(name="gp1cube386", mesh=("cube", 8), L=8, c0=10.0, rho=0.9, leaf=16,
+                 eta=1.0, eps=1e-4, scheme="galerkin_p1", n_touch=6)
 
 
 def workload(name):
@@ -28,6 +32,9 @@ def workload(name):
         xyz, tri = cube_mesh(8)
     elif name == "p1cube386":
         cfg = dict(SMALL_P1)
+        xyz, tri = cube_mesh(8)
+    elif name == "gp1cube386":
+        cfg = dict(SMALL_GP1)
         xyz, tri = cube_mesh(8)
     elif name == "lshape768":
         # small Galerkin workload: reentrant-corner cube, 1/8 grid (768 triangles)
@@ -52,6 +59,8 @@ def gpu_problem(name, **kw):
     import paper_2312_11219_amd as gaca
     cfg, xyz, tri, s = workload(name)
     opts = dict(leaf_size=cfg["leaf"], eta=cfg["eta"], eps3d=cfg["eps"], eps_aca=cfg["eps_aca"])
+    if "n_touch" in cfg:
+        opts["n_touch"] = cfg["n_touch"]
     opts.update(kw)
     scheme = cfg.get("scheme", "collocation")
     return cfg, gaca.Problem(context(), xyz, tri, s, scheme=scheme, **opts), (xyz, tri, s)
@@ -60,7 +69,8 @@ def gpu_problem(name, **kw):
 def oracle_problem(name):
     from oracle.hmatrix import Problem
     cfg, xyz, tri, s = workload(name)
-    return cfg, Problem(xyz, tri, s, cfg["leaf"], cfg["eta"], scheme=cfg.get("scheme", "collocation"))
+    return cfg, Problem(xyz, tri, s, cfg["leaf"], cfg["eta"], scheme=cfg.get("scheme", "collocation"),
+                        n_touch=cfg.get("n_touch"))
 
 
 def rel_fro(a, b):
