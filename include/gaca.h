@@ -100,8 +100,9 @@ typedef struct {
     int32_t max_rank3d;       /* cap on crosses per block (default min(L, 64)) */
     int32_t max_face_rank;    /* cap on a face's ACA rank (default min(m, n)) */
     uint64_t max_device_bytes;/* 0 = no limit; otherwise total library device memory cap */
-    uint64_t batch_bytes;     /* far-field scratch per batch of blocks (default 96 GiB; at most
-                                 half of the free device memory is used) */
+    uint64_t batch_bytes;     /* far-field scratch per batch of blocks (default 160 GiB; at most
+                                 60 % of the free device memory is used; the estimate takes the
+                                 faces per block of the problem's last build of the operator) */
     int32_t threads_small;    /* face-ACA workgroup size for faces with m n <= 1024: 128
                                  (default) or 64 (one wave per face) */
     int32_t threads_large;    /* face-ACA workgroup size for the large faces (256, 512 or
@@ -178,9 +179,11 @@ typedef struct {
                                      expand = U, W read + H_l written + the previous faces read
                                      for the Gram row; aca and tail 0 (not modelled) */
     /* aca phase by launch class (device time of the class's launches on its stream): 0 m n <= 1024 and sides <= 64 (registers, 128 or 64 threads),
-     * 1 m n <= 2304 and sides <= 96 (registers, 256 threads), 2 m n <= 4096 (FP64) or 8192
+     * 1 m n <= 2304 and sides <= 96 (registers, 256 threads) together with the faces whose
+     * sides are in (128, 256] when threads_large is above 256 (R in HBM, 256 threads, two
+     * faces per CU), 2 m n <= 4096 (FP64) or 8192
      * (mixed) and sides <= 128 (registers, 512 threads) together with the larger faces whose
-     * sides are <= 128 (R in HBM, 256 threads), 3 the faces with a side above 128 (R in HBM,
+     * sides are <= 128 (R in HBM, 256 threads), 3 the other faces with a side above 128 (R in HBM,
      * 512 threads by default) */
     double ms_far_by_kind[4];
     int32_t launches_by_kind[4];

@@ -1443,12 +1443,19 @@ __global__ void __launch_bounds__(NT)
 }
 
 // ---------------------------------------------------------------------------------------
-// Expand phase (kind 2): one 32 x 32 tile of H_l = U W^T per workgroup, written over R,
-// with the tile's max |H|^2, sum |H|^2 and Gram partials <H_l, H_p>.
+// Expand phase (kind 2): one 32 x 32 tile of H_l = U W^T per wave, written over R, with the
+// tile's max |H|^2, sum |H|^2 and Gram partials <H_l, H_p>.  Lane (rg, cg) = (lane / 8,
+// lane % 8) owns the sixteen entries (rg + 8 a, cg + 8 e), a, e < 4: each factor step
+// reads four U and four W values from LDS for sixteen complex products, and for each (a, e)
+// the wave touches eight rows of eight consecutive elements, so every load and store of the
+// face pool covers whole row segments.  The Gram row streams the previous faces with sixteen
+// loads in flight per lane and one wave reduction per face, with no barrier.
 template <bool MIXED>
-__global__ void __launch_bounds__(256) far_expand_kernel(FarBatchDev bd, const FarActive *act) {
+__global__ void __launch_bounds__(64) far_expand_kernel(FarBatchDev bd, const FarActive *act) {
     using FT = face_t<MIXED>;
     constexpr int T = kFarTile;
+    constexpr int QC = 8;   // factor steps staged in LDS per pass
+    static_assert(T == 32, "the lane layout covers 32 x 32 tiles");
     const int64_t c = blockIdx.x;
     const int a = bd.map_tile[c];
     const FarActive A = act[a];
@@ -1459,93 +1466,92 @@ __global__ void __launch_bounds__(256) far_expand_kernel(FarBatchDev bd, const F
     const int m = B.m, n = B.n;
     const int t = (int)(c - A.tile0), ntj = (n + T - 1) / T;
     const int i0 = (t / ntj) * T, j0 = (t % ntj) * T;
-    // thread (r, cg) owns columns cg, cg + 8, cg + 16, cg + 24 of tile row r: for each of its
-    // four entries the eight threads of a row touch eight consecutive elements, so every
-    // load and store of the face pool covers whole cache lines (with four consecutive
-    // entries per thread the pool reads of the Gram row were fetched 2.3 times over)
-    const int tid = threadIdx.x, r = tid >> 3, cg = tid & 7;
+    const int lane = threadIdx.x, rg = lane >> 3, cg = lane & 7;
     const FT *Ub = reinterpret_cast<const FT *>(bd.uw) + B.uw_off;
     const FT *Wb = Ub + (int64_t)B.rho_max * m;
-    FT *H = reinterpret_cast<FT *>(bd.hpool) + A.hslot;
-    const FT *hp = reinterpret_cast<const FT *>(bd.hpool);
+    // tile origin in the face (row-major m x n)
+    const int64_t org = (int64_t)i0 * n + j0;
+    FT *H = reinterpret_cast<FT *>(bd.hpool) + A.hslot + org;
+    const FT *hp = reinterpret_cast<const FT *>(bd.hpool) + org;
 
-    __shared__ FT Us[T][T + 1];
-    __shared__ FT Ws[T][T + 1];
-    __shared__ int64_t hsl[kMaxRcap];
-    __shared__ double red8[8][4];
-    for (int p = tid; p < ell; p += 256) hsl[p] = bd.hs[(int64_t)b * bd.rcap + p];
-    FT acc[4];
+    __shared__ FT Us[QC][T];
+    __shared__ FT Ws[QC][T];
+    FT acc[4][4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) acc[e] = czero<FT>();
-    for (int q0 = 0; q0 < rho; q0 += T) {
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[x][e] = czero<FT>();
+    for (int q0 = 0; q0 < rho; q0 += QC) {
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int id = tid + 256 * e, qq = id >> 5, ii = id & 31;
+        for (int e = 0; e < QC * T / 64; ++e) {
+            const int id = lane + 64 * e, qq = id >> 5, ii = id & 31;
             const bool qv = q0 + qq < rho;
             Us[qq][ii] = (qv && i0 + ii < m) ? Ub[(int64_t)(q0 + qq) * m + i0 + ii] : czero<FT>();
             Ws[qq][ii] = (qv && j0 + ii < n) ? Wb[(int64_t)(q0 + qq) * n + j0 + ii] : czero<FT>();
         }
         __syncthreads();
-        const int nq = min(T, rho - q0);
+        const int nq = min(QC, rho - q0);
         for (int qq = 0; qq < nq; ++qq) {
-            const FT u = Us[qq][r];
+            FT u[4], w[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[e] = cfma(u, Ws[qq][cg + 8 * e], acc[e]);
+            for (int x = 0; x < 4; ++x) u[x] = Us[qq][rg + 8 * x];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) w[e] = Ws[qq][cg + 8 * e];
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[x][e] = cfma(u[x], w[e], acc[x][e]);
         }
     }
-    const int i = i0 + r;
+    // entry offsets from the tile origin; entries outside the face are masked
+    bool ok[4][4];
+    int off[4][4];
     double mx = 0.0, s = 0.0;
-    int64_t gidx[4];
-    bool ok[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int j = j0 + cg + 8 * e;
-        ok[e] = i < m && j < n;
-        gidx[e] = (int64_t)i * n + j;
-        if (ok[e]) {
-            H[gidx[e]] = acc[e];
-            const double a2 = cabs2(acc[e]);
-            mx = fmax(mx, a2);
-            s += a2;
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = rg + 8 * x, cc = cg + 8 * e;
+            ok[x][e] = i0 + r < m && j0 + cc < n;
+            off[x][e] = r * n + cc;
+            if (ok[x][e]) {
+                H[off[x][e]] = acc[x][e];
+                const double a2 = cabs2(acc[x][e]);
+                mx = fmax(mx, a2);
+                s += a2;
+            }
         }
-    }
     double *out = bd.part + (A.tile0 + t) * (int64_t)far_part_stride(bd.rcap);
-    const int wave = tid >> 6, lane = tid & 63;
     mx = wave_max(mx);
     s = wave_sum(s);
     if (lane == 0) {
-        red8[0][wave] = mx;
-        red8[1][wave] = s;
+        out[0] = mx;
+        out[1] = s;
     }
-    __syncthreads();
-    if (tid == 0) {
-        out[0] = fmax(fmax(red8[0][0], red8[0][1]), fmax(red8[0][2], red8[0][3]));
-        out[1] = (red8[1][0] + red8[1][1]) + (red8[1][2] + red8[1][3]);
-    }
-    for (int p0 = 0; p0 < ell; p0 += 4) {
-        const int np = min(4, ell - p0);
-        double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t *hs = bd.hs + (int64_t)b * bd.rcap;
+    for (int p = 0; p < ell; ++p) {
+        const FT *hq = hp + hs[p];
+        FT v[4][4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-            if (ok[e]) {
-                const double2 h = to_d2(acc[e]);
+        for (int x = 0; x < 4; ++x)
 #pragma unroll
-                for (int tt = 0; tt < 4; ++tt)
-                    if (tt < np) {
-                        const double2 v = cmulc(h, to_d2(hp[hsl[p0 + tt] + gidx[e]]));
-                        g[2 * tt] += v.x;
-                        g[2 * tt + 1] += v.y;
-                    }
+            for (int e = 0; e < 4; ++e) v[x][e] = ok[x][e] ? hq[off[x][e]] : czero<FT>();
+        double gr = 0.0, gi = 0.0;
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double2 g = cmulc(to_d2(acc[x][e]), to_d2(v[x][e]));
+                gr += g.x;
+                gi += g.y;
             }
-#pragma unroll
-        for (int v = 0; v < 8; ++v) g[v] = wave_sum(g[v]);
-        __syncthreads();
-        if (lane == 0)
-#pragma unroll
-            for (int v = 0; v < 8; ++v) red8[v][wave] = g[v];
-        __syncthreads();
-        if (tid < 2 * np) out[2 + 2 * p0 + tid] = (red8[tid][0] + red8[tid][1]) + (red8[tid][2] + red8[tid][3]);
+        gr = wave_sum(gr);
+        gi = wave_sum(gi);
+        if (lane == 0) {
+            out[2 + 2 * p] = gr;
+            out[3 + 2 * p] = gi;
+        }
     }
 }
 
@@ -1963,8 +1969,8 @@ void launch_far_aca_small(int mnmax, int threads, const AcaParams &P, const FarB
 
 void launch_far_expand(const FarBatchDev &bd, const FarActive *act, int64_t ntile, hipStream_t st) {
     if (ntile <= 0) return;
-    if (bd.mixed) far_expand_kernel<true><<<(unsigned)ntile, 256, 0, st>>>(bd, act);
-    else far_expand_kernel<false><<<(unsigned)ntile, 256, 0, st>>>(bd, act);
+    if (bd.mixed) far_expand_kernel<true><<<(unsigned)ntile, 64, 0, st>>>(bd, act);
+    else far_expand_kernel<false><<<(unsigned)ntile, 64, 0, st>>>(bd, act);
 }
 
 void launch_far_gram_small(const FarBatchDev &bd, const FarActive *act, int nact, hipStream_t st) {

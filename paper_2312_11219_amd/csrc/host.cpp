@@ -33,7 +33,7 @@ void options_default(gaca_options *o) {
     o->max_rank3d = 64;
     o->max_face_rank = 0;
     o->max_device_bytes = 0;
-    o->batch_bytes = 96ull << 30;
+    o->batch_bytes = 160ull << 30;
     o->threads_small = 128;
     o->threads_large = 0;
     o->verbose = 0;

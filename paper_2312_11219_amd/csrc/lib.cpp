@@ -408,6 +408,9 @@ struct gaca_problem {
     std::string autotune_path;    // copy of opt.autotune_cache (opt points at it)
     int tuned_tl = 0, tuned_ts = 0;   // face-ACA workgroup sizes chosen by the autotuner
     int tune_state = 0;               // 0 none, 1 measured by this problem, 2 read from the cache
+    // faces per far block that the last build of each operator kind (slot 6: joint builds)
+    // stored, the start of the next build's batch estimate (0 = no build yet)
+    double faces_per_block[7] = {0, 0, 0, 0, 0, 0, 0};
     gaca_scheme scheme = GACA_COLLOCATION_P0;
     bool synthetic = false;       // dense-tensor problem of gaca_compress_tensor
     HostMesh mesh;
@@ -459,6 +462,13 @@ struct gaca_problem {
     DevBuf ws_spare[5];
     // near-field storage handed back by destroyed operators (slot kernel & 1)
     DevBuf near_spare[2];
+    // far-field result tables of destroyed operators (device: meta, cross meta, cross offsets,
+    // fibre offsets, block list; host: the same tables), by slot kernel & 1: taking them back
+    // spares the next build the allocation and first touch of tens of MB
+    DevBuf tab_spare[2][5];
+    std::vector<FarMeta> meta_spare[2];
+    std::vector<CrossMeta> cmeta_spare[2];
+    std::vector<int64_t> coff_spare[2], foff_spare[2];
     GrowBuf spare_arena[2], spare_fib[2];
     ~gaca_problem();
 };
@@ -1162,26 +1172,66 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
     const size_t es = mixed ? sizeof(float2) : sizeof(double2);
     const int PS = far_part_stride(rcap);
     const int fk = nh == 1 ? h->kernel : -1;   // face / tail launch kernel id
-    std::vector<int32_t> far4(4 * std::max<int64_t>(nfar, 1));
+    if (nfar == 0) {
+        for (gaca_hmatrix *hh : H) {
+            hh->nfar = 0;
+            hh->meta.clear();
+            hh->cmeta.clear();
+            hh->cross_off.clear();
+            hh->fib_off.clear();
+            hh->d_far4.alloc(ctx, 4 * sizeof(int32_t));
+        }
+        main_work();
+        return;
+    }
+    if (!p->far_streams_ready) {
+        {
+            std::lock_guard<std::mutex> lk(ctx->stream_mu);
+            if (!ctx->stream_pool.empty()) {
+                for (int k = 0; k < 4; ++k) p->far_streams[k] = ctx->stream_pool.back()[k];
+                ctx->stream_pool.pop_back();
+                p->far_streams_ready = true;
+            }
+        }
+        if (!p->far_streams_ready) {
+            for (int k = 0; k < 4; ++k)
+                GACA_HIP_CHECK(hipStreamCreateWithFlags(&p->far_streams[k], hipStreamNonBlocking));
+            p->far_streams_ready = true;
+        }
+    }
+    hipStream_t s0 = p->far_streams[0];
+    // the near field first, on the context stream: its kernels run while the host prepares
+    // the far field, whose copies and clears go to the far stream (non-blocking, so they do
+    // not wait for the near field)
+    main_work();
+    std::vector<int32_t> far4(4 * nfar);
     for (int64_t b = 0; b < nfar; ++b)
         for (int k = 0; k < 4; ++k) far4[4 * b + k] = (int32_t)far[b][k];
     for (gaca_hmatrix *hh : H) {
         hh->nfar = nfar;
-        hh->meta.assign(nfar, FarMeta{});
-        hh->cmeta.assign(nfar * rcap, CrossMeta{});
-        hh->cross_off.assign(nfar * rcap, -1);
-        hh->fib_off.assign(nfar, -1);
-        hh->d_far4.upload(ctx, far4);
-    }
-    if (nfar == 0) {
-        main_work();
-        return;
-    }
-    for (gaca_hmatrix *hh : H) {
-        hh->d_meta.alloc(ctx, nfar * sizeof(FarMeta));
-        hh->d_cmeta.alloc(ctx, nfar * rcap * sizeof(CrossMeta));
-        hh->d_cross_off.alloc(ctx, nfar * rcap * sizeof(int64_t));
-        hh->d_fib_off.alloc(ctx, nfar * sizeof(int64_t));
+        DevBuf *tabs[5] = {&hh->d_meta, &hh->d_cmeta, &hh->d_cross_off, &hh->d_fib_off, &hh->d_far4};
+        const size_t tb[5] = {nfar * sizeof(FarMeta), nfar * rcap * sizeof(CrossMeta),
+                              nfar * rcap * sizeof(int64_t), nfar * sizeof(int64_t),
+                              far4.size() * sizeof(int32_t)};
+        {
+            std::lock_guard<std::mutex> lk(p->spare_mu);
+            const int k = hh->kernel & 1;
+            for (int t = 0; t < 5; ++t)
+                if (p->tab_spare[k][t].ptr && p->tab_spare[k][t].bytes == tb[t]) tabs[t]->swap(p->tab_spare[k][t]);
+            hh->meta.swap(p->meta_spare[k]);
+            hh->cmeta.swap(p->cmeta_spare[k]);
+            hh->cross_off.swap(p->coff_spare[k]);
+            hh->fib_off.swap(p->foff_spare[k]);
+        }
+        for (int t = 0; t < 5; ++t)
+            if (!tabs[t]->ptr) tabs[t]->alloc(ctx, tb[t]);
+        // every entry is overwritten from the device tables when the far field completes
+        hh->meta.resize(nfar);
+        hh->cmeta.resize(nfar * rcap);
+        hh->cross_off.resize(nfar * rcap);
+        hh->fib_off.resize(nfar);
+        GACA_HIP_CHECK(hipMemcpyAsync(hh->d_far4.ptr, far4.data(), far4.size() * sizeof(int32_t),
+                                      hipMemcpyHostToDevice, s0));
     }
     // per-block outputs, indexed by FarBlockDev::out_idx = operator * nfar + far block: the
     // first operator's tables directly, or joint tables split at the end
@@ -1194,10 +1244,10 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
     }
     DevBuf &o_meta = nh > 1 ? j_meta : h->d_meta, &o_cmeta = nh > 1 ? j_cmeta : h->d_cmeta;
     DevBuf &o_cross_off = nh > 1 ? j_cross_off : h->d_cross_off, &o_fib_off = nh > 1 ? j_fib_off : h->d_fib_off;
-    GACA_HIP_CHECK(hipMemset(o_meta.ptr, 0, ntot * sizeof(FarMeta)));
-    GACA_HIP_CHECK(hipMemset(o_cmeta.ptr, 0, ntot * rcap * sizeof(CrossMeta)));
-    GACA_HIP_CHECK(hipMemset(o_cross_off.ptr, 0xff, ntot * rcap * sizeof(int64_t)));
-    GACA_HIP_CHECK(hipMemset(o_fib_off.ptr, 0xff, ntot * sizeof(int64_t)));
+    GACA_HIP_CHECK(hipMemsetAsync(o_meta.ptr, 0, ntot * sizeof(FarMeta), s0));
+    GACA_HIP_CHECK(hipMemsetAsync(o_cmeta.ptr, 0, ntot * rcap * sizeof(CrossMeta), s0));
+    GACA_HIP_CHECK(hipMemsetAsync(o_cross_off.ptr, 0xff, ntot * rcap * sizeof(int64_t), s0));
+    GACA_HIP_CHECK(hipMemsetAsync(o_fib_off.ptr, 0xff, ntot * sizeof(int64_t), s0));
     AcaParams P{};
     P.eps = p->opt.eps3d;
     P.eps_aca = p->opt.eps_aca;
@@ -1231,7 +1281,11 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
         return 2.0 * rho_max * (m + n) * es + (rg + 1) * mn * es + rg * (double)(L + rcap) * 16 +
                tiles * PS * 8 + sizeof(FarStateDev) + sizeof(FarBlockDev) + rcap * 32.0 + L + 64;
     };
-    double rguess = std::min(rcap, 24);
+    // faces per block of the memory estimate: what the last build of this operator kind
+    // stored (with a quarter added), else a generous first guess
+    const int fpb_slot = nh > 1 ? 6 : std::min(std::max(p->kid((gaca_kernel)h->kernel), 0), 5);
+    double rguess = p->faces_per_block[fpb_slot] > 0 ? std::min((double)rcap, p->faces_per_block[fpb_slot])
+                                                     : std::min(rcap, 24);
     double factor_guess = 0.0;
     for (int64_t b = 0; b < nfar; ++b) {
         const int m = (int)far[b][1], n = (int)far[b][3];
@@ -1265,23 +1319,6 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
         free_b = (size_t)p->opt.batch_bytes;
     }
 
-    main_work();   // near field on the context stream, concurrently with the far field
-    if (!p->far_streams_ready) {
-        {
-            std::lock_guard<std::mutex> lk(ctx->stream_mu);
-            if (!ctx->stream_pool.empty()) {
-                for (int k = 0; k < 4; ++k) p->far_streams[k] = ctx->stream_pool.back()[k];
-                ctx->stream_pool.pop_back();
-                p->far_streams_ready = true;
-            }
-        }
-        if (!p->far_streams_ready) {
-            for (int k = 0; k < 4; ++k)
-                GACA_HIP_CHECK(hipStreamCreateWithFlags(&p->far_streams[k], hipStreamNonBlocking));
-            p->far_streams_ready = true;
-        }
-    }
-    hipStream_t s0 = p->far_streams[0];
     // the aca phase of kind k runs on ks[k] (kind 3, the large faces, on the main far stream)
     const hipStream_t ks[4] = {p->far_streams[3], p->far_streams[2], p->far_streams[1], s0};
     enum { EV_BEGIN, EV_END, EV_F0, EV_F1, EV_K0, EV_K1, EV_K2, EV_K3, EV_S0, EV_S1, EV_S2, EV_S3, EV_J, EV_X,
@@ -1365,7 +1402,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             }
             // the pools held from the previous batch are reused
             fb += W.hpool.bytes + W.fgpool.bytes + W.uw.bytes + W.part.bytes;
-            budget = std::max(64.0 * (1 << 20), std::min((double)p->opt.batch_bytes, 0.5 * (double)fb));
+            budget = std::max(64.0 * (1 << 20), std::min((double)p->opt.batch_bytes, 0.6 * (double)fb));
         }
         int64_t blast = bnext;
         for (double acc = 0.0; blast < ntot;) {
@@ -1507,7 +1544,21 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                 if (side <= tlx) return 1;
                 return (tlx == 512 && side <= kFarMultiE * 512) ? 2 : 0;
             };
-            auto prank = [&](int x) { const int pth = path(x); return pth == 0 ? 0 : pth == 2 ? 1 : 2; };
+            // one-entry faces with sides <= 256 under a larger workgroup size run with 256
+            // threads (two faces per CU) on the class-1 stream, beside the larger faces
+            auto small_big = [&](int x) {
+                return tlx > 256 && path(x) == 1 && std::max(bdesc[x].m, bdesc[x].n) <= 256;
+            };
+            auto prank = [&](int x) {
+                const int pth = path(x);
+                return pth == 0 ? 0 : pth == 2 ? 1 : small_big(x) ? 3 : 2;
+            };
+            // launch class of a block's face ACA (the stream it runs on)
+            auto aca_class = [&](int x) {
+                const int kd = kind[base + x];
+                if (kd != 3) return kd;
+                return !big(x) ? 2 : small_big(x) ? 1 : 3;
+            };
             auto launch_order = [&](int x, int y) {
                 if (kind[base + x] != kind[base + y]) return kind[base + x] > kind[base + y];
                 if (kind[base + x] == 3 && big(x) != big(y)) return big(x);
@@ -1518,9 +1569,12 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             // first iteration the list is already in launch order
             if (!std::is_sorted(active.begin(), active.end(), launch_order))
                 std::stable_sort(active.begin(), active.end(), launch_order);
-            int nbig = 0, npath[3] = {0, 0, 0};
-            while (nbig < (int)active.size() && kind[base + active[nbig]] == 3 && big(active[nbig]))
-                ++npath[path(active[nbig++])];
+            int nbig = 0, nsb = 0, npath[3] = {0, 0, 0};
+            while (nbig < (int)active.size() && kind[base + active[nbig]] == 3 && big(active[nbig])) {
+                const int x = active[nbig++];
+                if (small_big(x)) ++nsb;
+                else ++npath[path(x)];
+            }
             const int nact = (int)active.size();
             ms_prep += wall_ms_since(t_it);
             const auto t_launch = std::chrono::steady_clock::now();
@@ -1595,8 +1649,9 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                     launch_far_aca(2, tl, P, bd, dact + npath[0], npath[2], ks[3]);
                     GACA_HIP_CHECK(hipEventRecord(ev[EV_P2], ks[3]));
                     launch_far_aca(1, tl, P, bd, dact + npath[0] + npath[2], npath[1], ks[3]);
+                    launch_far_aca(1, 256, P, bd, dact + npath[0] + npath[2] + npath[1], nsb, ks[1]);
                     launch_far_aca(1, 256, P, bd, dact + nbig, cnt[3] - nbig, ks[2]);
-                    nl += (npath[0] > 0) + (npath[2] > 0) + (npath[1] > 0) + (cnt[3] > nbig);
+                    nl += (npath[0] > 0) + (npath[2] > 0) + (npath[1] > 0) + (nsb > 0) + (cnt[3] > nbig);
                     continue;
                 }
                 if (k == 0 && ts <= 64) {
@@ -1649,15 +1704,16 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             ms_phase[1] += elapsed(EV_F1, EV_J);
             ms_phase[2] += elapsed(EV_J, EV_X);
             ms_phase[3] += elapsed(EV_X, EV_T);
-            // launch classes by stream: 0, 1, 2 (kind 2 and the medium large faces), 3 (the
-            // large faces with a side above kMediumSide)
-            const int ccls[4] = {cnt[0], cnt[1], cnt[2] + cnt[3] - nbig, nbig};
+            // launch classes by stream: 0, 1 (with the large faces of sides <= 256 when the
+            // large workgroup size is above 256), 2 (kind 2 and the medium large faces), 3 (the
+            // other large faces, sides above kMediumSide)
+            const int ccls[4] = {cnt[0], cnt[1] + nsb, cnt[2] + cnt[3] - nbig, nbig - nsb};
             for (int k = 0; k < 4; ++k)
                 if (ccls[k]) {
                     ms_kind[k] += elapsed(EV_S0 + k, EV_K0 + k);
                     launches_kind[k] += 1;
                 }
-            if (nbig > 0) {
+            if (nbig > nsb) {
                 // the path launches follow each other on ks[3]: path 0, path 2, path 1
                 if (npath[0]) { ms_path[0] += elapsed(EV_S0 + 3, EV_P0); launches_path[0] += 1; }
                 if (npath[2]) { ms_path[2] += elapsed(EV_P0, EV_P2); launches_path[2] += 1; }
@@ -1699,8 +1755,9 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                     if (kd == 3) {
                         const double f = 8.0 * (d.m + d.n) * (double)rho * (rho - 1.0);
                         fl_phase[1] += f;
-                        fl_kind[big(lb) ? 3 : 2] += f;
-                        if (big(lb)) fl_path[path(lb)] += f;
+                        const int ac = aca_class(lb);
+                        fl_kind[ac] += f;
+                        if (ac == 3) fl_path[path(lb)] += f;
                         fl_phase[2] += 8.0 * mn * (rho + ell);
                         // U, W read, H_l written, the previous faces read once (Gram row)
                         by_phase[2] += ((double)rho * (d.m + d.n) + mn * (ell + 1.0)) * fe_bytes;
@@ -1752,6 +1809,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             double mn_sum = 0.0;
             for (int lb = 0; lb < nb; ++lb) mn_sum += (double)bdesc[lb].m * bdesc[lb].n;
             rguess = std::min((double)rcap, std::max(4.0, 1.25 * (double)hused / std::max(mn_sum, 1.0)));
+            p->faces_per_block[fpb_slot] = rguess;
         }
         if (p->opt.verbose) {
             size_t fb = 0, tb = 0;
@@ -2343,6 +2401,25 @@ gaca_status gaca_hmatrix_destroy(gaca_hmatrix *h) {
                     synced = true;
                 }
                 sp.swap(h->d_near);
+            }
+        }
+        // far-field result tables (device and host) for the next build of the same size
+        {
+            const int k = h->kernel & 1;
+            DevBuf *tabs[5] = {&h->d_meta, &h->d_cmeta, &h->d_cross_off, &h->d_fib_off, &h->d_far4};
+            for (int t = 0; t < 5; ++t) {
+                if (!tabs[t]->ptr || p->tab_spare[k][t].ptr) continue;
+                if (!synced) {
+                    (void)hipDeviceSynchronize();   // no kernel may still read the table
+                    synced = true;
+                }
+                p->tab_spare[k][t].swap(*tabs[t]);
+            }
+            if (p->cmeta_spare[k].empty()) {
+                p->meta_spare[k].swap(h->meta);
+                p->cmeta_spare[k].swap(h->cmeta);
+                p->coff_spare[k].swap(h->cross_off);
+                p->foff_spare[k].swap(h->fib_off);
             }
         }
         // VALU apply workspace: kept when no larger buffer of its kind is kept already
