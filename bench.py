@@ -42,21 +42,88 @@ KID = {"slp": 0, "dlp": 1}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "far_traffic_icosphere20480.json")
 
 
+TRAFFIC_SOURCES = ["paper_2312_11219_amd/csrc/far_aca.hip", "paper_2312_11219_amd/csrc/device_util.h",
+                   "paper_2312_11219_amd/csrc/entries_dev.h", "paper_2312_11219_amd/csrc/fastmath_dev.h",
+                   "paper_2312_11219_amd/csrc/galerkin_dev.h", "paper_2312_11219_amd/csrc/kernels.h",
+                   "paper_2312_11219_amd/csrc/internal.h"]
+COPY_KERNEL = "MulFunctor<float>"   # the torch y = 1.0 * x pass of --copy-calibration
+
+
+def sources_sha256(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def write_traffic(fetch_db, write_db, copy_bytes, out_path):
+    """Traffic record from two rocprofv3 --pmc result databases of this bench (one with
+    FETCH_SIZE, one with WRITE_SIZE, both run with --copy-calibration copy_bytes): per far
+    kernel the mean KiB per dispatch, scaled so that the calibration copy reads and writes
+    copy_bytes, with the SHA-256 of the kernel sources."""
+    import re
+    import sqlite3
+
+    def per_kernel(db, counter):
+        con = sqlite3.connect(db)
+        rows = con.execute("select kernel_name, dispatch_id, sum(value), max(duration) from "
+                           "counters_collection where counter_name = ? group by kernel_name, "
+                           "dispatch_id order by dispatch_id", (counter,)).fetchall()
+        con.close()
+        out, copy = {}, None
+        for name, _, v, dur in rows:
+            if COPY_KERNEL in name and copy is None:
+                copy = v
+                continue
+            short = re.sub(r"\(.*\)$", "", name).replace("void ", "").replace("gaca::", "")
+            if not (short.startswith("far_") or short.startswith("near_")):
+                continue
+            e = out.setdefault(short, [0, 0.0, 0.0])
+            e[0] += 1
+            e[1] += v
+            e[2] += dur
+        if copy is None:
+            raise SystemExit(f"{db}: no calibration copy dispatch (run the bench with --copy-calibration)")
+        return out, copy
+
+    fk, fcopy = per_kernel(fetch_db, "FETCH_SIZE")
+    wk, wcopy = per_kernel(write_db, "WRITE_SIZE")
+    ff, wf = copy_bytes / (fcopy * 1024.0), copy_bytes / (wcopy * 1024.0)
+    kernels = {}
+    for name, (n, v, dur) in fk.items():
+        if name not in wk:
+            continue
+        wn, wv, _ = wk[name]
+        fb, wb = v / n * 1024.0 * ff, wv / wn * 1024.0 * wf
+        kernels[name] = {"dispatches": n, "fetch_kib_mean": v / n, "write_kib_mean": wv / wn,
+                         "mean_duration_ms_under_counters": dur / n / 1e6,
+                         "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                         "traffic_bytes_per_launch": fb + wb}
+    rec = {"workload": "icosphere 20480 triangles, collocation P0 single layer, L = 128 (bench.py "
+                       "default): FP64 and mixed legs, autotuning builds included",
+           "sources": TRAFFIC_SOURCES, "source_sha256": sources_sha256(TRAFFIC_SOURCES),
+           "copy_kernel": f"y = 1.0 * x, FP32, {copy_bytes} bytes read + written "
+                          f"(bench.py --copy-calibration {copy_bytes})",
+           "copy_fetch_kib": fcopy, "copy_write_kib": wcopy, "fetch_factor": ff, "write_factor": wf,
+           "kernels": kernels}
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(f"wrote {out_path}: {len(kernels)} kernels, fetch factor {ff:.4f}, write factor {wf:.4f}")
+
+
 def measured_traffic(kernel_name):
     """HBM bytes per launch of kernel_name from the stored counter runs, or None when there
     are none for it or its sources have changed since."""
-    import hashlib
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
-        h = hashlib.sha256()
-        for rel in rec["sources"]:
-            with open(os.path.join(ROOT, rel), "rb") as fh:
-                h.update(fh.read())
+        digest = sources_sha256(rec["sources"])
     except (OSError, ValueError, KeyError):
         return None
     k = rec.get("kernels", {}).get(kernel_name)
-    if rec.get("source_sha256") != h.hexdigest() or k is None:
+    if rec.get("source_sha256") != digest or k is None:
         return None
     return k.get("traffic_bytes_per_launch")
 
@@ -138,6 +205,10 @@ def parse():
     # counter calibration: one y = 1.0 * x pass over this many bytes of FP32 before the
     # warm-up (a kernel of known traffic for the FETCH_SIZE / WRITE_SIZE scale)
     ap.add_argument("--copy-calibration", type=int, default=0)
+    # no run: the traffic record from the FETCH_SIZE and WRITE_SIZE result databases of two
+    # counter runs of this bench with --copy-calibration (written to --traffic-out)
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"))
+    ap.add_argument("--traffic-out", default=TRAFFIC_FILE)
     return ap.parse_args()
 
 
@@ -318,6 +389,10 @@ def run_leg(gaca, ctx, xyz, tri, s, cfg, X, stream, args, precision, sample):
 
 def main():
     args = parse()
+    if args.write_traffic:
+        write_traffic(args.write_traffic[0], args.write_traffic[1], args.copy_calibration or (1 << 30),
+                      args.traffic_out)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the far blocks would shard by LPT across GPUs, see the design notes)",

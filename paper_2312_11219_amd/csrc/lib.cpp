@@ -1453,6 +1453,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
         std::vector<FarCopy> pending;
         int64_t hused = 0, fused = 0;
         int iter = 0;
+        bool copy_ev = false;   // ev[EV_C] marks the end of the last copy launched on ks[0]
 
         auto batch_dev = [&](int slot) {
             FarBatchDev bd{};
@@ -1482,6 +1483,8 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
         std::vector<FarCopy> chunks;
         auto flush_copies = [&](hipStream_t cs) {
             if (pending.empty()) return false;
+            // the copy list buffers are reused: the last copy (one iteration ago) has read them
+            if (copy_ev) GACA_HIP_CHECK(hipEventSynchronize(ev[EV_C]));
             chunks.clear();
             for (const FarCopy &c : pending) {
                 const int64_t tot = (int64_t)c.rho * (bdesc[c.b].m + bdesc[c.b].n);
@@ -1614,11 +1617,6 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             ensure(ctx, W.part, (size_t)std::max<int64_t>(nparts, 1) * PS * sizeof(double));
             GACA_HIP_CHECK(hipMemcpyAsync(W.act.ptr, W.h_act.ptr, nact * sizeof(FarActive),
                                           hipMemcpyHostToDevice, s0));
-            // the copy reads the previous iteration's U, W slot beside the map and face phases;
-            // this iteration's ACAs write the other slot, so only the class-0 launches (same
-            // stream) run after it.  The copy of two iterations ago, which read the slot
-            // written now, completed before that iteration's status was read back.
-            flush_copies(ks[0]);
             const FarBatchDev bd = batch_dev(iter & 1);
             const FarActive *dact = W.act.as<FarActive>();
             const int nlarge = recomp ? nact : cnt[3];
@@ -1629,6 +1627,10 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             launch_far_face(fk, p->g, p->f, bd, dact, nchunk, s0);
             GACA_HIP_CHECK(hipEventRecord(ev[EV_F1], s0));
             for (int k = 0; k < 3; ++k) GACA_HIP_CHECK(hipStreamWaitEvent(ks[k], ev[EV_F1], 0));
+            // this iteration's ACAs write the U, W slot that the previous iteration's copy
+            // reads (on ks[0], in order before the class-0 launches)
+            if (copy_ev)
+                for (int k = 1; k < 4; ++k) GACA_HIP_CHECK(hipStreamWaitEvent(ks[k], ev[EV_C], 0));
             // large faces: 512 threads and ~104 KB of LDS history, one face per CU (the
             // longest face bounds the phase); medium faces (sides <= kMediumSide) 256 threads
             // and 32 KB, several per CU, on the kind-2 stream, so that they do not hold whole
@@ -1677,6 +1679,13 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             for (int k = 0; k < 4; ++k) GACA_HIP_CHECK(hipEventRecord(ev[EV_K0 + k], ks[k]));
             for (int k = 0; k < 3; ++k) GACA_HIP_CHECK(hipStreamWaitEvent(s0, ev[EV_K0 + k], 0));
             GACA_HIP_CHECK(hipEventRecord(ev[EV_J], s0));
+            // the factors accepted in the previous iteration (its U, W slot) -> arena, on ks[0]
+            // after the class-0 ACAs: the copy runs beside the large-face ACAs (latency bound)
+            // instead of the face kernel, and nothing on s0 waits for it
+            if (flush_copies(ks[0])) {
+                GACA_HIP_CHECK(hipEventRecord(ev[EV_C], ks[0]));
+                copy_ev = true;
+            }
             if (recomp) {
                 launch_far_recompress(P, bd, dact, nact, W.rec_ws.as<double2>(), kRecSlots, s0);
                 ++n_launch;
@@ -1775,11 +1784,15 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                 if (!(code & 2)) next.push_back(lb);
             }
             for (int w = 0; w < nh; ++w)
-                if (arena_used[w] > H[w]->d_arena.bytes / es)
+                if (arena_used[w] > H[w]->d_arena.bytes / es) {
+                    // the copy on ks[0] may still write the arena
+                    if (copy_ev) GACA_HIP_CHECK(hipEventSynchronize(ev[EV_C]));
                     grow_keep(ctx, H[w]->d_arena, arena_used[w] * es, arena_before[w] * es, s0);
+                }
             active.swap(next);
             ++iter;
         }
+        if (copy_ev) GACA_HIP_CHECK(hipStreamWaitEvent(s0, ev[EV_C], 0));
         flush_copies(s0);
         // fibres of the batch -> fibre arena, contiguous per block
         std::vector<FarGather> gth;
