@@ -1510,6 +1510,46 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             return true;
         };
 
+        // kind 3 first (large faces with a side above kMediumSide before the medium ones),
+        // then 2, 1, 0; larger faces first within a class
+        auto big = [&](int x) { return std::max(bdesc[x].m, bdesc[x].n) > kMediumSide; };
+        // large-face kernel path of a big face: 0 general (several entries per thread
+        // beyond the register paths), 2 several entries per thread, 1 one entry per thread
+        const int tlx = p->opt.threads_large > 0 ? p->opt.threads_large : 512;
+        auto path = [&](int x) {
+            const int side = std::max(bdesc[x].m, bdesc[x].n);
+            if (side <= tlx) return 1;
+            return (tlx == 512 && side <= kFarMultiE * 512) ? 2 : 0;
+        };
+        // one-entry faces with sides <= 256 under a larger workgroup size run with 256
+        // threads (two faces per CU) on the class-1 stream, beside the larger faces
+        auto small_big = [&](int x) {
+            return tlx > 256 && path(x) == 1 && std::max(bdesc[x].m, bdesc[x].n) <= 256;
+        };
+        auto prank = [&](int x) {
+            const int pth = path(x);
+            return pth == 0 ? 0 : pth == 2 ? 1 : small_big(x) ? 3 : 2;
+        };
+        // launch class of a block's face ACA (the stream it runs on)
+        auto aca_class = [&](int x) {
+            const int kd = kind[base + x];
+            if (kd != 3) return kd;
+            return !big(x) ? 2 : small_big(x) ? 1 : 3;
+        };
+        {
+            // launch order as one key per block: class (3 first), then for kind 3 the big
+            // faces first and among them the path rank, then m n descending; a stable sort
+            // keeps the block order among equal keys
+            std::vector<int64_t> okey(nb);
+            for (int x = 0; x < nb; ++x) {
+                const int kd = kind[base + x];
+                const bool bg = kd == 3 && big(x);
+                const int64_t mn = (int64_t)bdesc[x].m * bdesc[x].n;
+                okey[x] = ((int64_t)(3 - kd) << 40) | ((int64_t)(kd == 3 && !bg) << 36) |
+                          ((int64_t)(bg ? prank(x) : 0) << 32) | ((int64_t)0xFFFFFFFF - mn);
+            }
+            std::stable_sort(active.begin(), active.end(), [&](int x, int y) { return okey[x] < okey[y]; });
+        }
         while (!active.empty()) {
             const auto t_it = std::chrono::steady_clock::now();
             // slots of this iteration's faces (a zero face keeps its slots for the next one)
@@ -1536,42 +1576,8 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             }
             grow_keep(ctx, W.hpool, (size_t)hused * es, (size_t)hprev * es, s0);
             grow_keep(ctx, W.fgpool, (size_t)fused * sizeof(double2), (size_t)fprev * sizeof(double2), s0);
-            // kind 3 first (large faces with a side above kMediumSide before the medium ones),
-            // then 2, 1, 0; larger faces first within a class
-            auto big = [&](int x) { return std::max(bdesc[x].m, bdesc[x].n) > kMediumSide; };
-            // large-face kernel path of a big face: 0 general (several entries per thread
-            // beyond the register paths), 2 several entries per thread, 1 one entry per thread
-            const int tlx = p->opt.threads_large > 0 ? p->opt.threads_large : 512;
-            auto path = [&](int x) {
-                const int side = std::max(bdesc[x].m, bdesc[x].n);
-                if (side <= tlx) return 1;
-                return (tlx == 512 && side <= kFarMultiE * 512) ? 2 : 0;
-            };
-            // one-entry faces with sides <= 256 under a larger workgroup size run with 256
-            // threads (two faces per CU) on the class-1 stream, beside the larger faces
-            auto small_big = [&](int x) {
-                return tlx > 256 && path(x) == 1 && std::max(bdesc[x].m, bdesc[x].n) <= 256;
-            };
-            auto prank = [&](int x) {
-                const int pth = path(x);
-                return pth == 0 ? 0 : pth == 2 ? 1 : small_big(x) ? 3 : 2;
-            };
-            // launch class of a block's face ACA (the stream it runs on)
-            auto aca_class = [&](int x) {
-                const int kd = kind[base + x];
-                if (kd != 3) return kd;
-                return !big(x) ? 2 : small_big(x) ? 1 : 3;
-            };
-            auto launch_order = [&](int x, int y) {
-                if (kind[base + x] != kind[base + y]) return kind[base + x] > kind[base + y];
-                if (kind[base + x] == 3 && big(x) != big(y)) return big(x);
-                if (kind[base + x] == 3 && big(x) && prank(x) != prank(y)) return prank(x) < prank(y);
-                return (int64_t)bdesc[x].m * bdesc[x].n > (int64_t)bdesc[y].m * bdesc[y].n;
-            };
-            // the keys are fixed per block and finished blocks leave in order, so after the
-            // first iteration the list is already in launch order
-            if (!std::is_sorted(active.begin(), active.end(), launch_order))
-                std::stable_sort(active.begin(), active.end(), launch_order);
+            // the list is in launch order (sorted once before the first iteration; finished
+            // blocks leave in order)
             int nbig = 0, nsb = 0, npath[3] = {0, 0, 0};
             while (nbig < (int)active.size() && kind[base + active[nbig]] == 3 && big(active[nbig])) {
                 const int x = active[nbig++];
@@ -1602,11 +1608,6 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                 ntile += A.ntile;
                 cnt[kd]++;
                 ha[a] = A;
-                const double qpe = qpe_of(d);
-                evals += (double)mn * qpe;
-                fl_face += (double)mn * (qpe * f_eval_of(d.kern) + 8.0 * ell_h[lb]);
-                // the previous faces read once, the new face written once
-                by_face += (double)mn * (ell_h[lb] + 1.0) * fe_bytes;
             }
             // small faces: one partial row each (their Gram row), after the expand tiles
             if (!recomp)
@@ -1626,6 +1627,16 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             GACA_HIP_CHECK(hipEventRecord(ev[EV_F0], s0));
             launch_far_face(fk, p->g, p->f, bd, dact, nchunk, s0);
             GACA_HIP_CHECK(hipEventRecord(ev[EV_F1], s0));
+            // work model of the face phase, while the face kernel runs
+            for (int a = 0; a < nact; ++a) {
+                const int lb = active[a];
+                const FarBlockDev &d = bdesc[lb];
+                const double mn = (double)d.m * d.n, qpe = qpe_of(d);
+                evals += mn * qpe;
+                fl_face += mn * (qpe * f_eval_of(d.kern) + 8.0 * ell_h[lb]);
+                // the previous faces read once, the new face written once
+                by_face += mn * (ell_h[lb] + 1.0) * fe_bytes;
+            }
             for (int k = 0; k < 3; ++k) GACA_HIP_CHECK(hipStreamWaitEvent(ks[k], ev[EV_F1], 0));
             // this iteration's ACAs write the U, W slot that the previous iteration's copy
             // reads (on ks[0], in order before the class-0 launches)
