@@ -376,6 +376,9 @@ def run_leg(gaca, ctx, xyz, tri, s, cfg, X, stream, args, precision, sample):
                             "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3),
                             "gbs": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)}
                         for k, v in kern.items()},
+        # every listed far-field kernel against its roofline (same model as "roofline")
+        "far_rooflines": {k: {f: r[f] for f in ("bound", "achieved", "unit", "frac")}
+                          for k, r in ((k, roofline(k, v)) for k, v in kern.items())},
         "dominant": (dom_name, dom),
     }
     if sample is not None:
