@@ -101,8 +101,9 @@ typedef struct {
     int32_t max_face_rank;    /* cap on a face's ACA rank (default min(m, n)) */
     uint64_t max_device_bytes;/* 0 = no limit; otherwise total library device memory cap */
     uint64_t batch_bytes;     /* far-field scratch per batch of blocks (default 160 GiB; at most
-                                 60 % of the free device memory is used; the estimate takes the
-                                 faces per block of the problem's last build of the operator) */
+                                 half of the free device memory, or 60 % when all remaining
+                                 blocks fit in one batch; the estimate takes the faces per block
+                                 of the problem's last build of the operator) */
     int32_t threads_small;    /* face-ACA workgroup size for faces with m n <= 1024: 128
                                  (default) or 64 (one wave per face) */
     int32_t threads_large;    /* face-ACA workgroup size for the large faces (256, 512 or

@@ -1402,7 +1402,13 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             }
             // the pools held from the previous batch are reused
             fb += W.hpool.bytes + W.fgpool.bytes + W.uw.bytes + W.part.bytes;
-            budget = std::max(64.0 * (1 << 20), std::min((double)p->opt.batch_bytes, 0.6 * (double)fb));
+            budget = std::max(64.0 * (1 << 20), std::min((double)p->opt.batch_bytes, 0.5 * (double)fb));
+            // the remaining blocks go as one batch when they fit in 60 % of the free memory:
+            // one batch saves the second batch's iterations, while several larger batches
+            // would leave too little memory between them to keep the pools mapped
+            double rest = 0.0;
+            for (int64_t gb = bnext; gb < ntot; ++gb) rest += est_of(gb, rguess);
+            if (rest <= std::min((double)p->opt.batch_bytes, 0.6 * (double)fb)) budget = std::max(budget, rest);
         }
         int64_t blast = bnext;
         for (double acc = 0.0; blast < ntot;) {
@@ -1849,10 +1855,11 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                          W.hpool.bytes / 1e9, fb / 1e9);
             std::fflush(stderr);
         }
-        // give the pools' pages back between batches when memory is short (the arena needs
-        // them; in-place pools regrow without copies).  Mapping fresh pages is slow (tens of
-        // ms per GiB when the driver has to clear recently released memory), so pools stay
-        // mapped while the free memory exceeds their size.
+        // give pool pages back between batches when memory is short (the arena needs them;
+        // in-place pools regrow without copies).  Mapping fresh pages is slow (tens of ms per
+        // GiB when the driver has to clear recently released memory), so pools stay mapped
+        // while the free memory exceeds their size, and otherwise give back only the part
+        // that leaves as much memory free as the face pool keeps
         if (bnext < ntot) {
             size_t fb = 0, tb = 0;
             if (hipMemGetInfo(&fb, &tb) != hipSuccess) {
@@ -1860,8 +1867,8 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                 fb = 0;
             }
             if (fb < W.hpool.bytes + W.fgpool.bytes) {
-                if (W.hpool.vmm) W.hpool.shrink(0);
                 if (W.fgpool.vmm) W.fgpool.shrink(0);
+                if (W.hpool.vmm) W.hpool.shrink((fb + W.hpool.bytes) / 2);
             }
         }
     }
