@@ -300,8 +300,10 @@ __global__ void __launch_bounds__(256) apply_near_t_kernel(ApplyDev a, const XT 
 // y_b of the covering far blocks.  One wave per row: a near block stores row ro as L n
 // contiguous entries ([m][L][n]), which the lanes read in order (entry t: frequency t / n,
 // column t % n); RC right-hand sides per pass, lane sums added by a fixed-order wave
-// reduction.  Grid (leaf, rows / 4).
-template <class NearT, class XT, int RC>
+// reduction.  Grid (leaf, rows / 4).  PART 0: near and far parts; 1: the near part only
+// (written to Yp); 2: the far part added to the near part in Yp (1 then 2 gives the values
+// of 0 bit for bit, with the far blocks' y computed in between or beside part 1).
+template <class NearT, class XT, int RC, int PART>
 __global__ void __launch_bounds__(256) apply_leaf_sum_kernel(ApplyDev a, const XT *Xp,
                                                              const XT *ybuf, const int64_t *y_off,
                                                              XT *Yp, const XT *tn) {
@@ -320,7 +322,7 @@ __global__ void __launch_bounds__(256) apply_leaf_sum_kernel(ApplyDev a, const X
         XT acc[RC];
 #pragma unroll
         for (int c = 0; c < RC; ++c) acc[c] = czero<XT>();
-        for (int e = np0; e < np1; ++e) {
+        for (int e = PART == 2 ? np1 : np0; e < np1; ++e) {
             const int ib = a.leaf_near_idx[e];
             const NearBlockDev nb = a.nblocks[ib];
             if (nb.comp) {
@@ -358,21 +360,25 @@ __global__ void __launch_bounds__(256) apply_leaf_sum_kernel(ApplyDev a, const X
                 }
             }
         }
+        if constexpr (PART != 2) {
 #pragma unroll
-        for (int c = 0; c < RC; ++c) {
-            const double sx = wave_sum((double)acc[c].x), sy = wave_sum((double)acc[c].y);
-            acc[c].x = sx;
-            acc[c].y = sy;
+            for (int c = 0; c < RC; ++c) {
+                const double sx = wave_sum((double)acc[c].x), sy = wave_sum((double)acc[c].y);
+                acc[c].x = sx;
+                acc[c].y = sy;
+            }
         }
         if (lane < RC && cr + lane < nr) {
             XT tot = acc[0];
 #pragma unroll
             for (int c = 1; c < RC; ++c)
                 if (lane == c) tot = acc[c];
-            for (int e = fp0; e < fp1; ++e) {
-                const int b = a.leaf_far_idx[e];
-                tot = cadd(tot, ybuf[y_off[b] + (int64_t)(row - a.far4[4 * b]) * nr + cr + lane]);
-            }
+            if constexpr (PART == 2) tot = Yp[(int64_t)row * nr + cr + lane];
+            if constexpr (PART != 1)
+                for (int e = fp0; e < fp1; ++e) {
+                    const int b = a.leaf_far_idx[e];
+                    tot = cadd(tot, ybuf[y_off[b] + (int64_t)(row - a.far4[4 * b]) * nr + cr + lane]);
+                }
             Yp[(int64_t)row * nr + cr + lane] = tot;
         }
     }
@@ -437,28 +443,50 @@ __global__ void __launch_bounds__(256) apply_leaf_freq_kernel(ApplyDev a, const 
     }
 }
 
+template <class FacT, class XT, int PART>
+static void leaf_sum(const ApplyDev &a, const XT *Xp, const XT *ybuf, const int64_t *y_off, XT *Yp,
+                     const XT *tnbuf, hipStream_t st) {
+    const dim3 grid(a.nleaf, (a.max_leaf_m + 3) / 4);
+    if (a.nrhs == 1)
+        apply_leaf_sum_kernel<FacT, XT, 1, PART><<<grid, 256, 0, st>>>(a, Xp, ybuf, y_off, Yp, tnbuf);
+    else if (a.nrhs == 2)
+        apply_leaf_sum_kernel<FacT, XT, 2, PART><<<grid, 256, 0, st>>>(a, Xp, ybuf, y_off, Yp, tnbuf);
+    else
+        apply_leaf_sum_kernel<FacT, XT, 4, PART><<<grid, 256, 0, st>>>(a, Xp, ybuf, y_off, Yp, tnbuf);
+}
+
 template <class FacT, class XT>
 static void apply_impl(const ApplyDev &a, int mode, const XT *X, XT *Y, XT *Xp, XT *Yp, XT *zbuf,
                        XT *tbuf, const int64_t *t_off, XT *ybuf, const int64_t *y_off,
-                       hipStream_t st, XT *tnbuf) {
+                       hipStream_t st, XT *tnbuf, const ApplySide *side) {
     const int64_t totx = (int64_t)a.L * a.M * a.nrhs;
     permute_x_kernel<XT><<<(unsigned)((totx + 255) / 256), 256, 0, st>>>(X, Xp, a.perm, a.L, a.M,
                                                                           a.nrhs);
-    if (a.nfar > 0)
-        apply_far_a_kernel<FacT, XT><<<a.nfar, 256, 0, st>>>(a, mode, Xp, zbuf, tbuf, t_off);
     const int nl = mode == 0 ? 1 : a.L;
-    if (mode == 0) {
-        if (a.nfar > 0) apply_far_y_kernel<FacT, XT><<<a.nfar, 256, 0, st>>>(a, zbuf, ybuf, y_off);
+    if (mode == 0 && side && a.nfar > 0) {
+        // far blocks (T, z, y) on the side stream beside the near part of the leaf sums (an
+        // L2-bound chain beside an HBM-bound pass), joined before the far parts are added
+        GACA_HIP_CHECK(hipEventRecord(side->fork, st));
+        GACA_HIP_CHECK(hipStreamWaitEvent(side->stream, side->fork, 0));
+        apply_far_a_kernel<FacT, XT><<<a.nfar, 256, 0, side->stream>>>(a, mode, Xp, zbuf, tbuf, t_off);
+        apply_far_y_kernel<FacT, XT><<<a.nfar, 256, 0, side->stream>>>(a, zbuf, ybuf, y_off);
+        GACA_HIP_CHECK(hipEventRecord(side->join, side->stream));
         if (a.near_faces && a.nnear > 0)
             apply_near_t_kernel<XT><<<a.nnear, 256, 0, st>>>(a, Xp, tnbuf);
-        const dim3 grid(a.nleaf, (a.max_leaf_m + 3) / 4);
-        if (a.nrhs == 1)
-            apply_leaf_sum_kernel<FacT, XT, 1><<<grid, 256, 0, st>>>(a, Xp, ybuf, y_off, Yp, tnbuf);
-        else if (a.nrhs == 2)
-            apply_leaf_sum_kernel<FacT, XT, 2><<<grid, 256, 0, st>>>(a, Xp, ybuf, y_off, Yp, tnbuf);
-        else
-            apply_leaf_sum_kernel<FacT, XT, 4><<<grid, 256, 0, st>>>(a, Xp, ybuf, y_off, Yp, tnbuf);
+        leaf_sum<FacT, XT, 1>(a, Xp, ybuf, y_off, Yp, tnbuf, st);
+        GACA_HIP_CHECK(hipStreamWaitEvent(st, side->join, 0));
+        leaf_sum<FacT, XT, 2>(a, Xp, ybuf, y_off, Yp, tnbuf, st);
+    } else if (mode == 0) {
+        if (a.nfar > 0) {
+            apply_far_a_kernel<FacT, XT><<<a.nfar, 256, 0, st>>>(a, mode, Xp, zbuf, tbuf, t_off);
+            apply_far_y_kernel<FacT, XT><<<a.nfar, 256, 0, st>>>(a, zbuf, ybuf, y_off);
+        }
+        if (a.near_faces && a.nnear > 0)
+            apply_near_t_kernel<XT><<<a.nnear, 256, 0, st>>>(a, Xp, tnbuf);
+        leaf_sum<FacT, XT, 0>(a, Xp, ybuf, y_off, Yp, tnbuf, st);
     } else {
+        if (a.nfar > 0)
+            apply_far_a_kernel<FacT, XT><<<a.nfar, 256, 0, st>>>(a, mode, Xp, zbuf, tbuf, t_off);
         apply_leaf_freq_kernel<FacT, FacT, XT><<<dim3(a.nleaf, nl), 256, 0, st>>>(a, Xp, zbuf, Yp);
     }
     const int64_t toty = (int64_t)nl * a.M * a.nrhs;
@@ -468,10 +496,10 @@ static void apply_impl(const ApplyDev &a, int mode, const XT *X, XT *Y, XT *Xp, 
 
 void launch_apply(const ApplyDev &a, int mode, int x_fp32, const void *X, void *Y, void *Xp,
                   void *Yp, void *zbuf, void *tbuf, const int64_t *t_off, void *ybuf,
-                  const int64_t *y_off, hipStream_t st, void *tnbuf) {
+                  const int64_t *y_off, hipStream_t st, void *tnbuf, const ApplySide *side) {
 #define GACA_APPLY(FT, XTT)                                                                  \
     apply_impl<FT, XTT>(a, mode, (const XTT *)X, (XTT *)Y, (XTT *)Xp, (XTT *)Yp, (XTT *)zbuf, \
-                        (XTT *)tbuf, t_off, (XTT *)ybuf, y_off, st, (XTT *)tnbuf)
+                        (XTT *)tbuf, t_off, (XTT *)ybuf, y_off, st, (XTT *)tnbuf, side)
     if (a.fac_fp32) {
         if (x_fp32) GACA_APPLY(float2, float2);
         else GACA_APPLY(float2, double2);

@@ -270,10 +270,18 @@ void launch_apply_far_z(const ApplyDev &a, const MfmaApplyDev &d, int nitems, co
 void launch_apply_leaf_mfma(const ApplyDev &a, const MfmaApplyDev &d, int row_tiles,
                             const float2 *X, const float2 *Z, float2 *Y, hipStream_t st);
 
+// Side stream of the SUM apply: the far blocks run on it beside the near part (fork is
+// recorded on the launch stream, join on the side stream; both created by the caller).
+struct ApplySide {
+    hipStream_t stream;
+    hipEvent_t fork, join;
+};
+
 // x_fp32: X, Y and the workspace are complex64 (FP32 arithmetic), else complex128.
-// Workspace pointers are in elements of that type.
+// Workspace pointers are in elements of that type.  side: null to launch everything on st.
 void launch_apply(const ApplyDev &a, int mode, int x_fp32, const void *X, void *Y, void *Xp,
                   void *Yp, void *zbuf, void *tbuf, const int64_t *t_off, void *ybuf,
-                  const int64_t *y_off, hipStream_t st, void *tnbuf = nullptr);
+                  const int64_t *y_off, hipStream_t st, void *tnbuf = nullptr,
+                  const ApplySide *side = nullptr);
 
 }  // namespace gaca

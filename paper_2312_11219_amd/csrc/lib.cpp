@@ -501,6 +501,7 @@ struct gaca_hmatrix {
     int32_t ws_nrhs = -1, ws_mode = -1, ws_dtype = -1, ws_cb = 1;
     DevBuf d_xp, d_yp, d_z, d_t, d_toff, d_zoff, d_yb, d_yoff;
     DevBuf d_tn, d_tnoff;   // T of the compressed near blocks (option near_aca, SUM mode)
+    hipEvent_t apply_ev[2] = {nullptr, nullptr};   // fork / join of the VALU SUM apply's side stream
     DevBuf d_mz, d_mt, d_mtitems, d_mttile0, d_mtrows, d_mzitems, d_mzoff, d_msumrho;   // matrix-core apply
 };
 
@@ -512,6 +513,8 @@ gaca_problem::~gaca_problem() {
 }
 
 gaca_hmatrix::~gaca_hmatrix() {
+    for (hipEvent_t e : apply_ev)
+        if (e) (void)hipEventDestroy(e);
     if (p && !owned_problem && --p->nops == 0 && p->destroy_requested) delete p;
 }
 
@@ -2970,9 +2973,20 @@ gaca_status gaca_apply(gaca_hmatrix *h, gaca_apply_mode mode, int32_t nrhs, cons
             apply_mfma(h, a, nrhs, reinterpret_cast<const float2 *>(X), reinterpret_cast<float2 *>(Y), st);
             return;
         }
+        // SUM mode: the far blocks on one of the problem's far-field streams (idle between
+        // builds) beside the near part of the leaf sums
+        ApplySide side{};
+        const bool use_side = mode == GACA_APPLY_SUM && p->far_streams_ready && h->nfar > 0;
+        if (use_side) {
+            for (hipEvent_t &e : h->apply_ev)
+                if (!e) GACA_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            side.stream = p->far_streams[1];
+            side.fork = h->apply_ev[0];
+            side.join = h->apply_ev[1];
+        }
         launch_apply(a, (int)mode, dtype == GACA_C64 ? 1 : 0, X, Y, h->d_xp.ptr, h->d_yp.ptr,
                      h->d_z.ptr, h->d_t.ptr, h->d_toff.as<int64_t>(), h->d_yb.ptr,
-                     h->d_yoff.as<int64_t>(), st, h->d_tn.ptr);
+                     h->d_yoff.as<int64_t>(), st, h->d_tn.ptr, use_side ? &side : nullptr);
         GACA_HIP_CHECK(hipGetLastError());
     });
 }
