@@ -169,9 +169,14 @@ __global__ void __launch_bounds__(256) apply_far_a_kernel(ApplyDev a, int mode, 
                 s_rho[cb] = rows;
             }
             // T_c for the crosses of the group ([c][j][rhs]); the fibres pass through LDS
-            // kApplyKF frequencies at a time
-            for (int t0 = 0; t0 < nt; t0 += blockDim.x) {
-                const int t = t0 + threadIdx.x;
+            // kApplyKF frequencies at a time.  Blocks with few columns split the frequencies
+            // over G adjacent lanes per (j, rhs) (G a power of two, G nt <= workgroup), whose
+            // sums are added by a fixed butterfly
+            int G = 1;
+            while (G < 16 && 2 * G * nt <= (int)blockDim.x) G *= 2;
+            const int tpp = (int)blockDim.x / G, gl = (int)threadIdx.x % G;
+            for (int t0 = 0; t0 < nt; t0 += tpp) {
+                const int t = t0 + (int)threadIdx.x / G;
                 const int j = t / nr, cc = t - j * nr;
                 const XT *xp = Xp + (int64_t)(c0 + min(j, n - 1)) * nr + cc;
                 XT acc[CB];
@@ -186,14 +191,20 @@ __global__ void __launch_bounds__(256) apply_far_a_kernel(ApplyDev a, int mode, 
                     }
                     __syncthreads();
 #pragma unroll 8
-                    for (int kk = 0; kk < nk; ++kk) {
+                    for (int kk = gl; kk < nk; kk += G) {
                         const XT x = xp[(int64_t)(k0 + kk) * M * nr];
 #pragma unroll
                         for (int c = 0; c < CB; ++c)
                             if (c < cb) acc[c] = cfma(s_f[c * kApplyKF + kk], x, acc[c]);
                     }
                 }
-                if (t < nt)
+                for (int o = G >> 1; o > 0; o >>= 1)
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) {
+                        acc[c].x += __shfl_xor(acc[c].x, o, 64);
+                        acc[c].y += __shfl_xor(acc[c].y, o, 64);
+                    }
+                if (gl == 0 && t < nt)
 #pragma unroll
                     for (int c = 0; c < CB; ++c)
                         if (c < cb) T[(int64_t)c * nt + t] = acc[c];
@@ -343,21 +354,43 @@ __global__ void __launch_bounds__(256) apply_leaf_sum_kernel(ApplyDev a, const X
             const int n = nb.n, E = L * n;
             const NearT *base = nearv + nb.off + (int64_t)(row - nb.r0) * E;
             const XT *xb = Xp + (int64_t)nb.c0 * nr + cr;
-            // (k, j) of entry t = lane + 64 i, advanced by 64 entries per step
+            // (k, j) of entry t = lane + 64 i, advanced by 64 entries per step; LU entries
+            // per round have their loads in flight together and are summed in order
             int k = lane / n, j = lane - k * n;
             const int dk = 64 / n, dj = 64 - dk * n;
-            for (int t = lane; t < E; t += 64) {
-                const XT nv = cast_c<XT>(base[t]);
-                const XT *xp = xb + ((int64_t)k * M + j) * nr;
-#pragma unroll
-                for (int c = 0; c < RC; ++c)
-                    if (cr + c < nr) acc[c] = cfma(nv, xp[c], acc[c]);
+            auto step = [&]() {
                 k += dk;
                 j += dj;
                 if (j >= n) {
                     j -= n;
                     ++k;
                 }
+            };
+            constexpr int LU = 8;
+            int t = lane;
+            for (; t + 64 * (LU - 1) < E; t += 64 * LU) {
+                XT nv[LU], xv[LU][RC];
+#pragma unroll
+                for (int u = 0; u < LU; ++u) {
+                    nv[u] = cast_c<XT>(base[t + 64 * u]);
+                    const XT *xp = xb + ((int64_t)k * M + j) * nr;
+#pragma unroll
+                    for (int c = 0; c < RC; ++c) xv[u][c] = cr + c < nr ? xp[c] : czero<XT>();
+                    step();
+                }
+#pragma unroll
+                for (int u = 0; u < LU; ++u)
+#pragma unroll
+                    for (int c = 0; c < RC; ++c)
+                        if (cr + c < nr) acc[c] = cfma(nv[u], xv[u][c], acc[c]);
+            }
+            for (; t < E; t += 64) {
+                const XT nv = cast_c<XT>(base[t]);
+                const XT *xp = xb + ((int64_t)k * M + j) * nr;
+#pragma unroll
+                for (int c = 0; c < RC; ++c)
+                    if (cr + c < nr) acc[c] = cfma(nv, xp[c], acc[c]);
+                step();
             }
         }
         if constexpr (PART != 2) {
