@@ -1286,7 +1286,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
     };
     // faces per block of the memory estimate: what the last build of this operator kind
     // stored (with a quarter added), else a generous first guess
-    const int fpb_slot = nh > 1 ? 6 : std::min(std::max(p->kid((gaca_kernel)h->kernel), 0), 5);
+    const int fpb_slot = nh > 1 ? 6 : std::min(std::max(h->kernel, 0), 5);   // kernel id 0-5
     double rguess = p->faces_per_block[fpb_slot] > 0 ? std::min((double)rcap, p->faces_per_block[fpb_slot])
                                                      : std::min(rcap, 24);
     double factor_guess = 0.0;
