@@ -1602,13 +1602,13 @@ __global__ void __launch_bounds__(256) far_gram_small_kernel(FarBatchDev bd, con
 }
 
 // ---------------------------------------------------------------------------------------
-// Tail phase: one workgroup per active block.
-template <int KERNEL, bool DENSE, bool MIXED>
-__global__ void __launch_bounds__(256)
+// Tail phase: one workgroup of NT threads per active block.
+template <int KERNEL, bool DENSE, bool MIXED, int NT>
+__global__ void __launch_bounds__(NT)
     far_tail_kernel(GeoDev g, FreqDev f, AcaParams P, FarBatchDev bd, const FarActive *act,
                     int nlarge) {
     using FT = face_t<MIXED>;
-    constexpr int NT = 256, NW = NT / 64;
+    constexpr int NW = NT / 64;
     const int a = blockIdx.x;
     const FarActive A = act[a];
     const int b = A.b;
@@ -1982,7 +1982,10 @@ template <int K, bool D, bool MX>
 static void tail_dispatch(const GeoDev &g, const FreqDev &f, const AcaParams &P,
                           const FarBatchDev &bd, const FarActive *act, int nact, int nlarge,
                           hipStream_t st) {
-    far_tail_kernel<K, D, MX><<<nact, 256, 0, st>>>(g, f, P, bd, act, nlarge);
+    // two waves per block: the fibre of L <= 128 frequencies is one entry per thread, and twice
+    // as many blocks share a CU as with four waves
+    constexpr int kTailThreads = 128;
+    far_tail_kernel<K, D, MX, kTailThreads><<<nact, kTailThreads, 0, st>>>(g, f, P, bd, act, nlarge);
 }
 
 void launch_far_tail(int kernel, const GeoDev &g, const FreqDev &f, const AcaParams &P,
