@@ -45,7 +45,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "far_traffic_icosphere20480.json")
 TRAFFIC_SOURCES = ["paper_2312_11219_amd/csrc/far_aca.hip", "paper_2312_11219_amd/csrc/device_util.h",
                    "paper_2312_11219_amd/csrc/entries_dev.h", "paper_2312_11219_amd/csrc/fastmath_dev.h",
                    "paper_2312_11219_amd/csrc/galerkin_dev.h", "paper_2312_11219_amd/csrc/kernels.h",
-                   "paper_2312_11219_amd/csrc/internal.h"]
+                   "paper_2312_11219_amd/csrc/internal.h",
+                   # the far-field driver: how many faces one launch covers (batches, classes)
+                   "paper_2312_11219_amd/csrc/lib.cpp"]
 COPY_KERNEL = "MulFunctor<float>"   # the torch y = 1.0 * x pass of --copy-calibration
 
 
@@ -61,8 +63,11 @@ def sources_sha256(paths):
 def write_traffic(fetch_db, write_db, copy_bytes, out_path):
     """Traffic record from two rocprofv3 --pmc result databases of this bench (one with
     FETCH_SIZE, one with WRITE_SIZE, both run with --copy-calibration copy_bytes): per far
-    kernel the mean KiB per dispatch, scaled so that the calibration copy reads and writes
-    copy_bytes, with the SHA-256 of the kernel sources."""
+    kernel the mean KiB per dispatch over the last build that launched it (a timed build:
+    the first build of a problem sizes its batches from a generous guess and may cut them
+    differently), scaled so that the calibration copy reads and writes copy_bytes, with the
+    SHA-256 of the kernel and driver sources.  A build starts with its near-field kernels,
+    so the near-field dispatches mark the build boundaries."""
     import re
     import sqlite3
 
@@ -72,20 +77,26 @@ def write_traffic(fetch_db, write_db, copy_bytes, out_path):
                            "counters_collection where counter_name = ? group by kernel_name, "
                            "dispatch_id order by dispatch_id", (counter,)).fetchall()
         con.close()
-        out, copy = {}, None
-        for name, _, v, dur in rows:
+        disp, copy, starts = {}, None, []
+        for name, did, v, dur in rows:
             if COPY_KERNEL in name and copy is None:
                 copy = v
                 continue
             short = re.sub(r"\(.*\)$", "", name).replace("void ", "").replace("gaca::", "")
+            if short.startswith("near_"):
+                starts.append(did)
             if not (short.startswith("far_") or short.startswith("near_")):
                 continue
-            e = out.setdefault(short, [0, 0.0, 0.0])
-            e[0] += 1
-            e[1] += v
-            e[2] += dur
+            disp.setdefault(short, []).append((did, v, dur))
         if copy is None:
             raise SystemExit(f"{db}: no calibration copy dispatch (run the bench with --copy-calibration)")
+        out = {}
+        for short, ds in disp.items():
+            if not short.startswith("near_"):
+                last = ds[-1][0]
+                b = max([d for d in starts if d < last], default=-1)
+                ds = [x for x in ds if x[0] > b]
+            out[short] = [len(ds), sum(x[1] for x in ds), sum(x[2] for x in ds)]
         return out, copy
 
     fk, fcopy = per_kernel(fetch_db, "FETCH_SIZE")
@@ -102,7 +113,8 @@ def write_traffic(fetch_db, write_db, copy_bytes, out_path):
                          "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
                          "traffic_bytes_per_launch": fb + wb}
     rec = {"workload": "icosphere 20480 triangles, collocation P0 single layer, L = 128 (bench.py "
-                       "default): FP64 and mixed legs, autotuning builds included",
+                       "default): FP64 and mixed legs; per kernel the dispatches of the last build "
+                       "that launched it",
            "sources": TRAFFIC_SOURCES, "source_sha256": sources_sha256(TRAFFIC_SOURCES),
            "copy_kernel": f"y = 1.0 * x, FP32, {copy_bytes} bytes read + written "
                           f"(bench.py --copy-calibration {copy_bytes})",

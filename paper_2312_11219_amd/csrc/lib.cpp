@@ -1396,7 +1396,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
     // batches of consecutive blocks whose estimate fits the memory free at their start; the
     // faces-per-block guess of the estimate follows what the previous batches used
     for (int64_t bnext = 0; bnext < ntot;) {
-        double budget = 0.0;
+        double budget = 0.0, rest = 0.0, fb_all = 0.0;
         {
             size_t fb = 0, tb = 0;
             if (hipMemGetInfo(&fb, &tb) != hipSuccess) {
@@ -1409,16 +1409,24 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             // the remaining blocks go as one batch when they fit in 60 % of the free memory:
             // one batch saves the second batch's iterations, while several larger batches
             // would leave too little memory between them to keep the pools mapped
-            double rest = 0.0;
             for (int64_t gb = bnext; gb < ntot; ++gb) rest += est_of(gb, rguess);
+            fb_all = (double)fb;
             if (rest <= std::min((double)p->opt.batch_bytes, 0.6 * (double)fb)) budget = std::max(budget, rest);
         }
         int64_t blast = bnext;
-        for (double acc = 0.0; blast < ntot;) {
+        double acc = 0.0;
+        while (blast < ntot) {
             const double e = est_of(blast, rguess);
             if (blast > bnext && acc + e > budget) break;
             acc += e;
             ++blast;
+        }
+        if (p->opt.verbose) {
+            std::fprintf(stderr, "gaca far field: batch of blocks %lld..%lld of %lld: estimate %.2f GB (all "
+                         "remaining blocks %.2f GB) at %.1f faces per block, budget %.2f GB of %.2f GB free\n",
+                         (long long)bnext, (long long)blast, (long long)ntot, acc / 1e9, rest / 1e9, rguess,
+                         budget / 1e9, fb_all / 1e9);
+            std::fflush(stderr);
         }
         const std::pair<int64_t, int64_t> bt{bnext, blast};
         bnext = blast;
@@ -2410,19 +2418,18 @@ gaca_status gaca_hmatrix_destroy(gaca_hmatrix *h) {
         }
         std::lock_guard<std::mutex> lk(p->spare_mu);
         bool synced = false;
+        // into the slot of the operator's kind only: a build takes one arena of its kind, so
+        // a second spare of that kind would stay mapped and idle, taking memory that the next
+        // build's far-field batch could use
         auto donate = [&](GrowBuf &src, GrowBuf *spare) {
             if (!src.vmm || !src.ptr || src.bytes > tb / 8) return;
-            for (int t = 0; t < 2; ++t) {
-                const int k = t == 0 ? (h->kernel & 1) : 1 - (h->kernel & 1);
-                if (!spare[k].ptr) {
-                    if (!synced) {
-                        (void)hipDeviceSynchronize();   // no kernel may still use the arena
-                        synced = true;
-                    }
-                    spare[k].swap(src);
-                    return;
-                }
+            const int k = h->kernel & 1;
+            if (spare[k].ptr) return;
+            if (!synced) {
+                (void)hipDeviceSynchronize();   // no kernel may still use the arena
+                synced = true;
             }
+            spare[k].swap(src);
         };
         donate(h->d_arena, p->spare_arena);
         donate(h->d_fib, p->spare_fib);
