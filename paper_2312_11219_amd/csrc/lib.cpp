@@ -1277,8 +1277,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
     // memory estimate of a block in a batch with rg faces per block (pool slots, fibres and
     // Gram rows, current factors, expand partials, state)
     auto est_of = [&](int64_t gb, double rg) {
-        const int64_t b = gb / nh;
-        const double m = (double)far[b][1], n = (double)far[b][3], mn = m * n;
+        const double m = (double)desc[gb].m, n = (double)desc[gb].n, mn = m * n;
         const double rho_max = std::min(m, n);
         const double tiles = far_kind((int)m, (int)n, mixed) == 3 ? std::ceil(m / 32.0) * std::ceil(n / 32.0) : 1.0;
         return 2.0 * rho_max * (m + n) * es + (rg + 1) * mn * es + rg * (double)(L + rcap) * 16 +
@@ -1315,6 +1314,27 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
         const double mn = (double)m * n;
         // first guess of the factor storage (the arena grows by half when it runs short)
         factor_guess += std::min(mn * L, (double)std::min(rcap, 8) * std::min(rho_max, 16) * (m + n));
+    }
+    // blocks enter the batches by size, the largest first (ties in partition order): a batch
+    // iterates until its block with the most crosses is done, and the large blocks, which
+    // take the most crosses and the longest face ACAs, then share a few batches instead of
+    // drawing out every batch.  The result tables are indexed by out_idx, so the order
+    // changes no result.
+    {
+        std::vector<int64_t> ord(nfar);
+        std::iota(ord.begin(), ord.end(), (int64_t)0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
+            return (int64_t)far[x][1] * far[x][3] > (int64_t)far[y][1] * far[y][3];
+        });
+        std::vector<FarBlockDev> dsort(ntot);
+        std::vector<int> ksort(ntot);
+        for (int64_t i = 0; i < nfar; ++i)
+            for (int w = 0; w < nh; ++w) {
+                dsort[nh * i + w] = desc[nh * ord[i] + w];
+                ksort[nh * i + w] = kind[nh * ord[i] + w];
+            }
+        desc.swap(dsort);
+        kind.swap(ksort);
     }
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
