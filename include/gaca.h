@@ -103,7 +103,9 @@ typedef struct {
     uint64_t batch_bytes;     /* far-field scratch per batch of blocks (default 160 GiB; at most
                                  half of the free device memory, or 60 % when all remaining
                                  blocks fit in one batch; the estimate takes the faces per block
-                                 of the problem's last build of the operator) */
+                                 of the problem's last build of the operator); blocks enter the
+                                 batches largest (m n) first; the result does not depend on the
+                                 batches */
     int32_t threads_small;    /* face-ACA workgroup size for faces with m n <= 1024: 128
                                  (default) or 64 (one wave per face) */
     int32_t threads_large;    /* face-ACA workgroup size for the large faces (256, 512 or

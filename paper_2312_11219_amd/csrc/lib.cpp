@@ -1413,8 +1413,9 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
     double evals = 0.0;
 
     if (recomp) ensure(ctx, W.rec_ws, (size_t)kRecSlots * kRecSlot * sizeof(double2));
-    // batches of consecutive blocks whose estimate fits the memory free at their start; the
-    // faces-per-block guess of the estimate follows what the previous batches used
+    // batches of consecutive blocks (in the size order above) whose estimate fits the memory
+    // free at their start; the faces-per-block guess of the estimate follows what the
+    // previous batches used
     for (int64_t bnext = 0; bnext < ntot;) {
         double budget = 0.0, rest = 0.0, fb_all = 0.0;
         {
