@@ -184,10 +184,9 @@ typedef struct {
     /* aca phase by launch class (device time of the class's launches on its stream): 0 m n <= 1024 and sides <= 64 (registers, 128 or 64 threads),
      * 1 m n <= 2304 and sides <= 96 (registers, 256 threads) together with the faces whose
      * sides are in (128, 256] when threads_large is above 256 (R in HBM, 256 threads, two
-     * faces per CU), 2 m n <= 4096 (FP64) or 8192
-     * (mixed) and sides <= 128 (registers, 512 threads) together with the larger faces whose
-     * sides are <= 128 (R in HBM, 256 threads), 3 the other faces with a side above 128 (R in HBM,
-     * 512 threads by default) */
+     * faces per CU), 2 m n <= 4096 and sides <= 128 (registers, 512 threads) together
+     * with the larger faces whose sides are <= 128 (R in HBM, 256 threads), 3 the other
+     * faces with a side above 128 (R in HBM, 512 threads by default) */
     double ms_far_by_kind[4];
     int32_t launches_by_kind[4];
     double far_flops_by_kind[4];  /* algorithmic flops of the class's face-ACA launches */

@@ -1936,7 +1936,6 @@ static void aca_dispatch(int path, int threads, const AcaParams &P, const FarBat
 template <bool MX>
 static void aca_small_dispatch(int mnmax, int threads, const AcaParams &P, const FarBatchDev &bd,
                                const FarActive *act, int nact, hipStream_t st) {
-    constexpr int K2 = MX ? 8192 : 4096;
     if (mnmax <= 576 && threads <= 64)
         far_aca_small_kernel<64, MX, 576, 64><<<nact, 64, 0, st>>>(P, bd, act);
     else if (mnmax <= 1024 && threads <= 64)
@@ -1950,7 +1949,7 @@ static void aca_small_dispatch(int mnmax, int threads, const AcaParams &P, const
     else if (mnmax <= 2304)
         far_aca_small_kernel<256, MX, 2304, 96><<<nact, 256, 0, st>>>(P, bd, act);
     else
-        far_aca_small_kernel<512, MX, K2, 128><<<nact, 512, 0, st>>>(P, bd, act);
+        far_aca_small_kernel<512, MX, 4096, 128><<<nact, 512, 0, st>>>(P, bd, act);
 }
 
 void launch_far_aca(int path, int threads, const AcaParams &P, const FarBatchDev &bd,

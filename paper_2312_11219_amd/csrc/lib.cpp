@@ -1071,11 +1071,13 @@ gaca_status gaca_problem_blocks(const gaca_problem *p, int64_t *far4, int64_t *n
 // Large faces with both sides at most this run as medium faces (see run_far).
 constexpr int kMediumSide = 128;
 
-static int far_kind(int m, int n, bool mixed) {
+// (The mixed build had FP32 faces of up to 8192 entries in registers too: the faces of 4097
+// to 8192 entries run faster on the one-entry-per-thread kernel, as in the FP64 build.)
+static int far_kind(int m, int n) {
     const int64_t mn = (int64_t)m * n;
     if (mn <= 1024 && m <= 64 && n <= 64) return 0;
     if (mn <= 2304 && m <= 96 && n <= 96) return 1;
-    if (mn <= (mixed ? 8192 : 4096) && m <= 128 && n <= 128) return 2;
+    if (mn <= 4096 && m <= 128 && n <= 128) return 2;
     return 3;
 }
 
@@ -1279,7 +1281,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
     auto est_of = [&](int64_t gb, double rg) {
         const double m = (double)desc[gb].m, n = (double)desc[gb].n, mn = m * n;
         const double rho_max = std::min(m, n);
-        const double tiles = far_kind((int)m, (int)n, mixed) == 3 ? std::ceil(m / 32.0) * std::ceil(n / 32.0) : 1.0;
+        const double tiles = far_kind((int)m, (int)n) == 3 ? std::ceil(m / 32.0) * std::ceil(n / 32.0) : 1.0;
         return 2.0 * rho_max * (m + n) * es + (rg + 1) * mn * es + rg * (double)(L + rcap) * 16 +
                tiles * PS * 8 + sizeof(FarStateDev) + sizeof(FarBlockDev) + rcap * 32.0 + L + 64;
     };
@@ -1309,7 +1311,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
             dw.kern = H[w]->kernel;
             dw.which = w;
             desc[nh * b + w] = dw;
-            kind[nh * b + w] = far_kind(m, n, mixed);
+            kind[nh * b + w] = far_kind(m, n);
         }
         const double mn = (double)m * n;
         // first guess of the factor storage (the arena grows by half when it runs short)
@@ -1714,7 +1716,7 @@ static void run_far(const std::vector<gaca_hmatrix *> &H, const double2 *dense,
                     launch_far_aca_small(576, 64, P, bd, dact + a, first[0] + cnt[0] - a, ks[0]);
                     nl += (a > first[0]) + (a < first[0] + cnt[0]);
                 } else {
-                    const int mnmax = k == 0 ? 1024 : k == 1 ? 2304 : (mixed ? 8192 : 4096);
+                    const int mnmax = k == 0 ? 1024 : k == 1 ? 2304 : 4096;
                     launch_far_aca_small(mnmax, k == 0 ? ts : k == 1 ? 256 : 512, P, bd, dact + first[k],
                                          cnt[k], ks[k]);
                     ++nl;
