@@ -409,8 +409,9 @@ def main():
                       args.traffic_out)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the far blocks would shard by LPT across GPUs, see the design notes)",
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the far blocks would be dealt to the GPUs longest estimated work first, each GPU "
+              "building and applying its share, with X gathered on every GPU)",
               file=sys.stderr)
         sys.exit(2)
     import torch
